@@ -1,0 +1,376 @@
+"""Pins of the oracle's time step: closed forms of each sub-step and invariants.
+
+Sub-steps (Sec. 3): Step 1 mass and momentum predictor (eqs. e1_d, step2_sd),
+Step 2 energy and e -> T (eqs. step3_sd, step3_2sd in total-energy form, eq.
+ent), Step 3 corrector, pressure equation and end-of-step update (eqs.
+step2_sd corrector, p_prime_sd, step4_4sd).  Each closed form below holds
+exactly for the discrete operators on the chosen polynomial fields, so a
+dropped term, a wrong sign or a wrong coefficient fails one of them.
+
+Invariants of the whole step: a hydrostatic atmosphere at rest stays at rest,
+mass is conserved to round-off, a centred bubble stays mirror-symmetric, warm
+air rises, and a converged pressure solve makes the conservative density
+agree with the equation of state (eq. p) to round-off.
+"""
+import numpy as np
+import pytest
+
+from paper_2303_10499_amd import configs
+
+MESH = dict(nx=12, ny=1, nz=10, lx=1200.0, ly=100.0, lz=1000.0)
+
+
+def make(oracle_lib, mesh=MESH, **over):
+    par = dict(configs.AIR, mu=0.15, dt=0.7, n_corr=2, n_energy_sweeps=2, tol=1e-14,
+               max_iter=5000)
+    par.update(over)
+    return oracle_lib.Oracle(mesh, par), par
+
+
+def grid(O):
+    x, y, z = O.cell_centres()
+    m = O.mesh
+    P = np.arange(O.nc)
+    return x, y, z, P % m.nx, (P // m.nx) % m.ny, P // (m.nx * m.ny)
+
+
+# ---------------------------------------------------------------- Step 1
+
+def test_mass_predictor_closed_form(oracle_lib):
+    O, par = make(oracle_lib)
+    x, y, z, i, j, k = grid(O)
+    f = lambda t: 0.8 + 2e-3 * t - 1e-6 * t * t
+    fp = lambda t: 2e-3 - 2e-6 * t
+    rho = np.ones(O.nc)
+    u = np.zeros((2, O.nc))
+    u[0] = f(x)
+    phi, rs = O.mass_predictor(rho, u)
+    sel = (i >= 2) & (i <= O.mesh.nx - 3)
+    np.testing.assert_allclose(rs[sel], (1.0 - par["dt"] * fp(x))[sel], rtol=1e-13)
+    # no flux through the walls, so total mass is unchanged
+    assert abs(rs.sum() - rho.sum()) < 1e-13 * O.nc
+
+
+def test_momentum_predictor_pressure_gradient(oracle_lib):
+    O, par = make(oracle_lib)
+    x, y, z, i, j, k = grid(O)
+    a = 0.03
+    rho = np.ones(O.nc)
+    u = np.zeros((2, O.nc))
+    pp = 1000.0 + a * x
+    phi, rs = O.mass_predictor(rho, u)
+    us = O.momentum_predictor(rho, u, pp, rs, phi)
+    n = O.mesh.nx
+    inner = (i >= 1) & (i <= n - 2)
+    np.testing.assert_allclose(us[0][inner], -par["dt"] * a, rtol=1e-12)
+    np.testing.assert_allclose(us[0][~inner], -par["dt"] * a / 2, rtol=1e-12)
+    assert np.all(np.abs(us[1]) < 1e-14)
+
+
+def test_momentum_predictor_gravity_term(oracle_lib):
+    O, par = make(oracle_lib)
+    x, y, z, i, j, k = grid(O)
+    beta = -1e-4
+    rho = 1.0 + beta * z
+    u = np.zeros((2, O.nc))
+    pp = np.zeros(O.nc)
+    phi, rs = O.mass_predictor(rho, u)
+    us = O.momentum_predictor(rho, u, pp, rs, phi)
+    inner = (k >= 1) & (k <= O.mesh.nz - 2)
+    # -(grad p' - Phi grad rho) = +g z grad rho  (reading of the split's sign)
+    np.testing.assert_allclose(us[1][inner], (par["dt"] * par["g"] * beta * z / rho)[inner], rtol=1e-11)
+    assert np.all(np.abs(us[0]) < 1e-14)
+
+
+def test_momentum_predictor_viscous_term(oracle_lib):
+    O, par = make(oracle_lib, mu=3.0)
+    x, y, z, i, j, k = grid(O)
+    a = 2e-6
+    rho = np.ones(O.nc)
+    u = np.zeros((2, O.nc))
+    u[0] = 1.0 + a * z * z
+    phi, rs = O.mass_predictor(rho, u)
+    us = O.momentum_predictor(rho, u, np.zeros(O.nc), rs, phi)
+    sel = (i >= 1) & (i <= O.mesh.nx - 2) & (k >= 1) & (k <= O.mesh.nz - 2)
+    np.testing.assert_allclose(rs[sel], 1.0, rtol=1e-15)
+    np.testing.assert_allclose(us[0][sel], (u[0] + 2 * a * par["mu"] * par["dt"])[sel], rtol=1e-12)
+
+
+def test_momentum_predictor_convective_term(oracle_lib):
+    O, par = make(oracle_lib, mu=0.0)
+    x, y, z, i, j, k = grid(O)
+    a, U0 = 4e-4, 0.5
+    rho = np.ones(O.nc)
+    u = np.zeros((2, O.nc))
+    u[0] = U0 + a * x
+    phi, rs = O.mass_predictor(rho, u)
+    us = O.momentum_predictor(rho, u, np.zeros(O.nc), rs, phi)
+    sel = (i >= 1) & (i <= O.mesh.nx - 2)
+    dt = par["dt"]
+    np.testing.assert_allclose(rs[sel], 1.0 - dt * a, rtol=1e-13)
+    np.testing.assert_allclose(us[0][sel], (u[0] * (1 - 2 * a * dt) / (1 - a * dt))[sel], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- Step 2
+
+def _energy(O, rho, u, T, us, rs, phi, Tbg):
+    return O.energy(rho, u, T, us, rs, phi, Tbg)
+
+
+def test_energy_diffusion_of_temperature_deviation(oracle_lib):
+    O, par = make(oracle_lib, mu=100.0, n_energy_sweeps=1)
+    x, y, z, i, j, k = grid(O)
+    a = 1e-5
+    Tbg = 290.0 - 3e-3 * (np.arange(O.mesh.nz) + 0.5) * 100.0
+    T = Tbg[k] + a * x * x
+    rho = np.ones(O.nc)
+    zero2 = np.zeros((2, O.nc))
+    Tn = _energy(O, rho, zero2, T, zero2, rho, zero2, Tbg)
+    sel = (i >= 1) & (i <= O.mesh.nx - 2)
+    want = par["dt"] * par["mu"] / par["Pr"] * par["cp"] * 2 * a / par["cv"]
+    np.testing.assert_allclose((Tn - T)[sel], want, rtol=1e-8)
+    # adiabatic walls: the heat content (rho c_v T summed) is conserved
+    assert abs(np.sum(Tn - T)) < 1e-9 * np.abs(Tn - T).sum()
+
+
+@pytest.mark.parametrize("sweeps,margin", [(1, 1), (2, 3)])
+def test_energy_flux_carries_enthalpy(oracle_lib, sweeps, margin):
+    """the flux of rho e u + p u is phi (e + R T): the temperature drops by
+    dt U (c_p/c_v) dT/dx, not dt U dT/dx (a dropped pressure work)"""
+    O, par = make(oracle_lib, mu=0.0, n_energy_sweeps=sweeps)
+    x, y, z, i, j, k = grid(O)
+    a, U = 2e-3, 1.5
+    T = 300.0 + a * x
+    rho = np.ones(O.nc)
+    u = np.zeros((2, O.nc))
+    u[0] = U
+    m = O.mesh
+    S = m.ly * m.lz / m.nz
+    phi = np.zeros((2, O.nc))
+    phi[0] = np.where(i <= m.nx - 2, U * S, 0.0)
+    Tn = _energy(O, rho, u, T, u, rho, phi, np.full(m.nz, 300.0))
+    sel = (i >= margin) & (i <= m.nx - 1 - margin)
+    want = -par["dt"] * U * par["cp"] / par["cv"] * a
+    np.testing.assert_allclose((Tn - T)[sel], want, rtol=1e-9)
+
+
+def test_energy_e_to_T_round_trip_at_rest(oracle_lib):
+    O, par = make(oracle_lib)
+    s = O.init_bubble(0)
+    zero2 = np.zeros((2, O.nc))
+    Tn = _energy(O, s.rho, zero2, s.T, zero2, s.rho, zero2, s.Tbg)
+    e = par["cv"] * s.T + O.potential()
+    assert np.all(np.abs(Tn - s.T) <= 4 * np.finfo(float).eps * e / par["cv"])
+
+
+def test_eos_coefficients(oracle_lib):
+    O, par = make(oracle_lib)
+    rng = np.random.default_rng(2)
+    p = rng.uniform(6e4, 1e5, O.nc)
+    T = rng.uniform(250, 310, O.nc)
+    rs = rng.uniform(0.4, 1.2, O.nc)
+    r23, psi, c, D = O.eos_coeffs(p, T, rs)
+    np.testing.assert_allclose(r23 * par["R"] * T, p, rtol=1e-15)           # eq. step3_3sd
+    V = O.mesh.lx / O.mesh.nx * O.mesh.ly * O.mesh.lz / O.mesh.nz
+    np.testing.assert_allclose(c, V / (par["R"] * T * par["dt"]), rtol=1e-15)
+    np.testing.assert_allclose(D, r23 * par["dt"] / rs, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- Step 3
+
+def test_H_and_predicted_flux_closed_forms(oracle_lib):
+    O, par = make(oracle_lib, mu=3.0)
+    x, y, z, i, j, k = grid(O)
+    m = O.mesh
+    dt, g = par["dt"], par["g"]
+    a = 2e-6
+    rho = np.ones(O.nc)
+    u = np.zeros((2, O.nc))
+    u[0] = 1.0 + a * z * z
+    phi, rs = O.mass_predictor(rho, u)
+    H = O.H(rho, u, u, phi)
+    sel = (i >= 1) & (i <= m.nx - 2) & (k >= 1) & (k <= m.nz - 2)
+    np.testing.assert_allclose(H[0][sel], (u[0] / dt + 2 * a * par["mu"])[sel], rtol=1e-12)
+    # predicted flux from a uniform H and a linear rho23 in z
+    H0 = np.zeros((2, O.nc))
+    H0[0] = 0.2
+    beta = -5e-5
+    r23 = 1.0 + beta * z
+    psi = np.full(O.nc, 1.0 / (287.0 * 300.0))
+    D = np.full(O.nc, 0.9)
+    pt, b = O.predicted_flux_rhs(rho, r23, psi, D, H0)
+    Sx = m.ly * m.lz / m.nz
+    Sz = m.lx / m.nx * m.ly
+    V = Sx * m.lx / m.nx
+    np.testing.assert_allclose(pt[0][i <= m.nx - 2], 0.9 * Sx * 0.2, rtol=1e-14)
+    zf = (k + 1) * (m.lz / m.nz)
+    np.testing.assert_allclose(pt[1][k <= m.nz - 2], (0.9 * Sz * g * zf * beta)[k <= m.nz - 2], rtol=1e-12)
+    inner = (i >= 1) & (i <= m.nx - 2) & (k >= 1) & (k <= m.nz - 2)
+    div_z = 0.9 * Sz * g * beta * m.lz / m.nz      # flux difference of the linear Phi_f
+    want = V / dt * (rho + psi * r23 * g * z) - div_z
+    np.testing.assert_allclose(b[inner], want[inner], rtol=1e-12)
+
+
+def test_corrector_closed_form(oracle_lib):
+    O, par = make(oracle_lib)
+    x, y, z, i, j, k = grid(O)
+    m = O.mesh
+    a = 0.02
+    pp = 5e4 + a * x
+    r23 = np.ones(O.nc)
+    D = np.full(O.nc, 0.6)
+    rs = np.full(O.nc, 1.1)
+    zero2 = np.zeros((2, O.nc))
+    phi, u = O.correct(pp, r23, zero2, D, rs, zero2)
+    inner = (i >= 1) & (i <= m.nx - 2)
+    np.testing.assert_allclose(u[0][inner], -a * par["dt"] / 1.1, rtol=1e-12)
+    Sx = m.ly * m.lz / m.nz
+    np.testing.assert_allclose(phi[0][i <= m.nx - 2], -0.6 * Sx * a, rtol=1e-10)
+    np.testing.assert_allclose(u[1], 0.0, atol=1e-13)
+
+
+def test_finalize_closed_form(oracle_lib):
+    O, par = make(oracle_lib)
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(0.5, 1.2, O.nc)
+    pp = rng.uniform(7e4, 1.1e5, O.nc)
+    r23 = rng.uniform(0.5, 1.2, O.nc)
+    psi = rng.uniform(1e-5, 1.3e-5, O.nc)
+    phi = np.zeros((2, O.nc))
+    rn, pn, mm = O.finalize(rho, phi, pp, r23, psi)
+    np.testing.assert_allclose(pn, pp - r23 * O.potential(), rtol=1e-15)
+    np.testing.assert_array_equal(rn, rho)
+
+
+# ---------------------------------------------------------------- initial state
+
+def test_initial_state_is_discretely_hydrostatic_and_satisfies_eos(oracle_lib):
+    cfg = configs.get("bubble2d_64x32")
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+    s = O.init_bubble(0)
+    par = cfg["params"]
+    m = O.mesh
+    nx, nz = m.nx, m.nz
+    dz = m.lz / nz
+    pp = s.pp.reshape(nz, nx)
+    rho = s.rho.reshape(nz, nx)
+    Phi_f = par["g"] * (np.arange(nz - 1) + 1.0) * dz
+    F = (pp[1:] - pp[:-1]) - Phi_f[:, None] * (rho[1:] - rho[:-1])
+    assert np.max(np.abs(F)) <= 1e-9                      # round-off of ~1e5 Pa values
+    assert np.max(np.abs(pp[:, 1:] - pp[:, :-1])) == 0.0   # horizontally uniform
+    np.testing.assert_allclose(s.p, s.rho * par["R"] * s.T, rtol=4e-16)
+    np.testing.assert_allclose(s.p, s.pp - s.rho * O.potential(), rtol=1e-15)
+    assert np.all(s.u == 0.0)
+
+
+def test_background_exner_profile_converges_at_second_order(oracle_lib):
+    errs = []
+    for nz in (16, 32, 64):
+        cfg = configs.get("bubble2d_64x32")
+        cfg["mesh"].update(nz=nz, nx=4, ly=5000.0)
+        O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+        s = O.init_bubble(0)
+        par = cfg["params"]
+        x, y, z = O.cell_centres()
+        pi_exact = 1.0 - par["g"] * z / (par["cp"] * par["theta0"])
+        pi_disc = (s.p / par["p0"]) ** (par["R"] / par["cp"])
+        errs.append(np.max(np.abs(pi_disc - pi_exact)))
+    assert errs[0] < 1e-4
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_initial_bubble_profiles(oracle_lib):
+    for name in ("bubble2d_64x32", "nonsmooth2d_2048"):
+        cfg = configs.scaled(name, 64, 64) if name == "nonsmooth2d_2048" else configs.get(name)
+        O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+        b = cfg["bubble"]
+        s = O.init_bubble(**b)
+        s0 = O.init_bubble(0)
+        x, y, z = O.cell_centres()
+        r = np.hypot(x - b["xc"], z - b["zc"])
+        if b["kind"] == 1:
+            want = np.where(r <= b["rc"], 0.5 * b["amp"] * (1 + np.cos(np.pi * r / b["rc"])), 0.0)
+        else:
+            want = np.where(r <= b["rc"], b["amp"], 0.0)
+        th = O.theta_prime(s) - O.theta_prime(s0)
+        # theta = T/pi with pi of the unperturbed pressure: theta' = theta'_0 T_b/(theta0 pi_b)
+        np.testing.assert_allclose(th, want, atol=2e-4 * b["amp"])
+        np.testing.assert_array_equal(s.p, s0.p)
+
+
+# ---------------------------------------------------------------- whole step
+
+def test_rest_state_stays_at_rest(oracle_lib):
+    cfg = configs.get("bubble2d_64x32", tol=1e-14)
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+    s = O.init_bubble(0)
+    s0 = s.copy()
+    O.step(s, 20)
+    assert np.max(np.abs(s.u)) <= 1e-10
+    for f in ("rho", "T", "pp", "p"):
+        a, b = getattr(s, f), getattr(s0, f)
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), f
+
+
+def test_rest_state_3d(oracle_lib):
+    cfg = configs.scaled("bubble3d_256x256x128", 8, 6, ny=7)
+    cfg["params"]["tol"] = 1e-14
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+    s = O.init_bubble(0)
+    O.step(s, 10)
+    assert np.max(np.abs(s.u)) <= 1e-10
+
+
+@pytest.mark.parametrize("name,dims", [("bubble2d_64x32", (64, 32, 1)),
+                                       ("bubble3d_256x256x128", (12, 8, 12))])
+def test_bubble_mass_symmetry_and_sign(oracle_lib, name, dims):
+    nx, nz, ny = dims
+    cfg = configs.scaled(name, nx, nz, ny=ny if ny > 1 else None)
+    par = cfg["params"]
+    par["tol"] = 1e-14
+    if ny > 1:
+        par["dt"] = 2.0
+    O = oracle_lib.Oracle(cfg["mesh"], par)
+    b = cfg["bubble"]
+    s = O.init_bubble(**b)
+    m0 = s.rho.sum()
+    st = O.step(s, 1)
+    # warm air rises: positive vertical velocity at the bubble centre
+    x, y, z = O.cell_centres()
+    r = np.hypot(x - b["xc"], z - b["zc"])
+    if ny > 1:
+        r = np.hypot(r, y - b["yc"])
+    assert s.u[-1][np.argmin(r)] > 0
+    assert np.max(np.abs(s.u[-1])) == np.max(s.u[-1])
+    nsteps = 10
+    for n in range(nsteps - 1):
+        st += O.step(s, 1)
+        assert abs(s.rho.sum() - m0) <= 100 * np.finfo(float).eps * m0 * (n + 2)
+    # the solves converged, and conservative density agrees with the EOS (eq. p)
+    for x_ in st:
+        assert all(x_.solve[q].converged for q in range(x_.n_solves))
+        assert x_.eos_mismatch < 1e-11
+    # mirror symmetry about the vertical centre plane(s)
+    shape = (O.mesh.nz, O.mesh.ny, O.mesh.nx)
+    sc = lambda a: np.max(np.abs(a)) + 1e-300
+    u = s.u[0].reshape(shape)
+    assert np.max(np.abs(u + u[:, :, ::-1])) <= 1e-11 * sc(u)
+    for f in (s.rho, s.T, s.pp, s.u[-1]):
+        f = f.reshape(shape)
+        assert np.max(np.abs(f - f[:, :, ::-1])) <= 1e-11 * sc(f)
+    if ny > 1:
+        v = s.u[1].reshape(shape)
+        assert np.max(np.abs(v + v[:, ::-1, :])) <= 1e-11 * sc(v)
+        w = s.u[2].reshape(shape)
+        assert np.max(np.abs(w - np.transpose(w, (0, 2, 1)))) <= 1e-11 * sc(w)
+
+
+def test_unconverged_solve_leaves_state_untouched(oracle_lib):
+    cfg = configs.get("bubble2d_64x32", tol=1e-14, max_iter=1)
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+    s = O.init_bubble(**cfg["bubble"])
+    s0 = s.copy()
+    with pytest.raises(RuntimeError):
+        O.step(s, 1)
+    for f in ("rho", "u", "T", "pp", "p"):
+        np.testing.assert_array_equal(getattr(s, f), getattr(s0, f))

@@ -557,6 +557,7 @@ void geao_finalize(const geao_mesh* m, const geao_params* q, const double* rho_o
 
 typedef struct {
   double *phi, *rho_star, *u_star, *T_new, *rho23, *psi, *c, *D, *H, *phi_tilde, *b;
+  double *phi_corr;   /* corrected face flux of the latest corrector */
 } work_t;
 
 static work_t work_alloc(const geom* G) {
@@ -572,12 +573,14 @@ static work_t work_alloc(const geom* G) {
   w.H = zalloc(G->ndim * G->nc);
   w.phi_tilde = zalloc(G->ndim * G->nc);
   w.b = zalloc(G->nc);
+  w.phi_corr = zalloc(G->ndim * G->nc);
   return w;
 }
 
 static void work_free(work_t* w) {
   free(w->phi); free(w->rho_star); free(w->u_star); free(w->T_new); free(w->rho23);
   free(w->psi); free(w->c); free(w->D); free(w->H); free(w->phi_tilde); free(w->b);
+  free(w->phi_corr);
 }
 
 static int check_args(const geao_mesh* m, const geao_params* q) {
@@ -630,6 +633,9 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
 
   memcpy(u_k, w.u_star, sizeof(double) * G.ndim * G.nc);
   memcpy(pp_k, pp, sizeof(double) * G.nc);
+  /* every corrector convects with the frozen Step-1 flux phi^n (eq. step2_sd
+   * of Step 3 and the H operator); the corrected flux only feeds the
+   * end-of-step density */
   for (int k = 0; k < q->n_corr; ++k) {
     geao_H(m, q, rho, u, u_k, w.phi, w.H);
     geao_predicted_flux_rhs(m, q, rho, w.rho23, w.psi, w.D, w.H, w.phi_tilde, w.b);
@@ -637,10 +643,10 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
     int rc = geao_pcg(m, w.c, w.D, w.b, pp_k, q->tol, q->max_iter, &ss);
     if (st->n_solves < 16) st->solve[st->n_solves++] = ss;
     if (rc != GEAO_OK) { status = rc; break; }
-    geao_correct(m, q, pp_k, w.rho23, w.H, w.D, w.rho_star, w.phi_tilde, w.phi, u_k);
+    geao_correct(m, q, pp_k, w.rho23, w.H, w.D, w.rho_star, w.phi_tilde, w.phi_corr, u_k);
   }
   if (status == GEAO_OK) {
-    geao_finalize(m, q, rho, w.phi, pp_k, w.rho23, w.psi, rho_new, p_new, &st->eos_mismatch);
+    geao_finalize(m, q, rho, w.phi_corr, pp_k, w.rho23, w.psi, rho_new, p_new, &st->eos_mismatch);
     for (long P = 0; P < G.nc; ++P)
       if (!isfinite(rho_new[P]) || !isfinite(p_new[P]) || !isfinite(w.T_new[P])) status = GEAO_ERR_NAN;
   }

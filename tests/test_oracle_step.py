@@ -374,3 +374,31 @@ def test_unconverged_solve_leaves_state_untouched(oracle_lib):
         O.step(s, 1)
     for f in ("rho", "u", "T", "pp", "p"):
         np.testing.assert_array_equal(getattr(s, f), getattr(s0, f))
+
+
+def test_step_is_the_composition_of_the_pinned_substeps(oracle_lib):
+    """The step wires the sub-steps in the paper's order: Step 1, Step 2, then
+    n_corr correctors, each convecting with the frozen Step-1 flux phi^n
+    (eq. step2_sd of Step 3 and the H operator both carry phi^n_j), the
+    corrected flux of the last corrector feeding the end-of-step density."""
+    cfg = configs.get("bubble2d_64x32", tol=1e-13)
+    cfg["mesh"].update(nx=16, nz=12, ly=1250.0)
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+    s = O.init_bubble(**dict(cfg["bubble"], xc=9000.0))
+    O.step(s, 2)                      # a moving state
+    want = s.copy()
+    O.step(want, 1)
+    phi, rs = O.mass_predictor(s.rho, s.u)
+    us = O.momentum_predictor(s.rho, s.u, s.pp, rs, phi)
+    Tn = O.energy(s.rho, s.u, s.T, us, rs, phi, s.Tbg)
+    r23, psi, c, D = O.eos_coeffs(s.p, Tn, rs)
+    uk, ppk = us, s.pp.copy()
+    for k in range(cfg["params"]["n_corr"]):
+        H = O.H(s.rho, s.u, uk, phi)
+        pt, b = O.predicted_flux_rhs(s.rho, r23, psi, D, H)
+        ppk, st, rc = O.pcg(c, D, b, ppk, cfg["params"]["tol"])
+        assert rc == 0
+        phik, uk = O.correct(ppk, r23, H, D, rs, pt)
+    rn, pn, mm = O.finalize(s.rho, phik, ppk, r23, psi)
+    for got, ref in ((rn, want.rho), (uk, want.u), (Tn, want.T), (ppk, want.pp), (pn, want.p)):
+        np.testing.assert_array_equal(got, ref)

@@ -1,0 +1,199 @@
+"""Benchmark: cell-steps/s of the segregated pressure-based Euler step at
+pressure relative residual 1e-8, on one MI355X.
+
+A step is one pass of the whole hot path (Steps 1-3 of Sec. 3 with n_corr
+PISO correctors and their pressure solves) over the 3D smooth-bubble
+evaluation mesh (256 x 256 x 128 cells over 20 x 20 x 10 km, dt 0.5 s),
+built on the device from the analytic initial state (synthetic input, no
+dataset).  Every solver form is timed on the same workload and tolerance:
+plain FP64 Jacobi-PCG, FP32/FP64 iterative refinement, and the learned
+initial guess/preconditioner when its weights are present.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per cell of one launch of each kernel class (each array
+# read or written once; halo re-reads are not counted)
+BYTES_PER_CELL = {
+    0: 56.0,   # FP64 operator: read r, 1/diag, p_old, c, D; write p, q
+    1: 56.0,   # FP64 update:   read x, p, r, q, 1/diag; write x, r
+    2: 28.0,   # FP32 operator (same arrays in FP32)
+    3: 28.0,   # FP32 update
+}
+CLASS_NAMES = {0: "k_cg_spmv<fp64>", 1: "k_cg_update<fp64>", 2: "k_cg_spmv<fp32>",
+               3: "k_cg_update<fp32>", 4: "refinement residual/correction",
+               5: "explicit step kernels", 6: "learned network"}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_form(cfg, solver, steps, warmup, kernel_steps):
+    import torch
+    from paper_2303_10499_amd import gea
+
+    S = gea.Solver(cfg["mesh"], cfg["params"], solver=solver)
+    S.init_bubble(**cfg["bubble"])
+    stream = S.stream
+    nc = S.nc
+    t0 = time.time()
+    if warmup:
+        S.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    st = S.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log(f"[bench] {solver}: {steps} steps in {ms:.1f} ms ({time.time() - t0:.1f} s wall incl. warmup)")
+    out = dict(solver=solver, ms_per_step=ms / steps, cell_steps_per_s=nc * steps / (ms * 1e-3),
+               iters_per_solve=st.total_iters / max(st.total_solves, 1),
+               rel_res_last=max(st.solve[k].rel_res for k in range(st.n_solves)),
+               eos_mismatch=st.eos_mismatch)
+    # per-kernel device time over a second window of steps (events around
+    # every launch, so kept out of the timed region above)
+    S.kernel_timing(True, reset=True)
+    S.step(kernel_steps)
+    kms, kn = S.kernel_times()
+    S.kernel_timing(False)
+    total = sum(kms)
+    out["kernel_ms_per_step"] = {CLASS_NAMES[k]: kms[k] / kernel_steps for k in range(7) if kn[k]}
+    out["solve_share"] = (total - kms[5]) / total if total > 0 else None
+    dom = max((k for k in BYTES_PER_CELL if kn[k]), key=lambda k: kms[k], default=None)
+    if dom is not None:
+        avg_ms = kms[dom] / kn[dom]
+        achieved = BYTES_PER_CELL[dom] * nc / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = dict(kernel=CLASS_NAMES[dom], avg_launch_us=avg_ms * 1e3,
+                               bytes_per_launch=BYTES_PER_CELL[dom] * nc, achieved=achieved)
+    S.close()
+    return out
+
+
+def cpu_baseline(cfg):
+    """The oracle as it stands, one step from the initial state, 1 thread."""
+    import numpy as np  # noqa: F401
+    from oracle import geao
+    geao.build(force=False)
+    O = geao.Oracle(cfg["mesh"], cfg["params"])
+    s = O.init_bubble(**cfg["bubble"])
+    t = time.time()
+    O.step(s, 1)
+    dt = time.time() - t
+    return dict(value=O.nc / dt, unit="cell-steps/s", cores=1, kind="oracle",
+                sample=f"1 step of {cfg['name']} from the initial state, FP64 Jacobi-PCG at "
+                       f"tol {cfg['params']['tol']:g}, single-threaded C (-O2), {dt:.1f} s")
+
+
+def read_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+    src = os.path.join(ROOT, "paper_2303_10499_amd", "csrc", "gea_cg.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    rec = {}
+    for line in open(path):
+        line = line.strip()
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("source_sha") != h or rec.get("kernel") != kernel:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="bubble3d_256x256x128")
+    ap.add_argument("--forms", default="pcg64,mixed,learned")
+    ap.add_argument("--kernel-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU domain decomposition is a design, not a build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2303_10499_amd import configs, gea
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    gea.lib()
+    cfg = configs.get(args.workload)
+    cfg["params"]["tol"] = 1e-8
+    cfg["params"]["inner_tol"] = 1e-4
+    cfg["params"]["max_iter"] = 200000
+
+    forms = [f for f in args.forms.split(",") if f]
+    results = {}
+    for f in forms:
+        if f == "learned" and not learned_available(cfg):
+            log("[bench] learned form skipped: no trained weights for this workload")
+            continue
+        results[f] = run_form(cfg, f, args.steps, args.warmup, args.kernel_steps)
+    primary = "learned" if "learned" in results else ("mixed" if "mixed" in results else forms[0])
+    R = results[primary]
+    nc = cfg["mesh"]["nx"] * cfg["mesh"]["ny"] * cfg["mesh"]["nz"]
+    roof = None
+    if "roofline" in R:
+        rr = R["roofline"]
+        roof = dict(bound="hbm", kernel=rr["kernel"], achieved=round(rr["achieved"], 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(rr["achieved"] / HBM_PEAK_GBS, 4),
+                    avg_launch_us=round(rr["avg_launch_us"], 2),
+                    bytes_per_launch=rr["bytes_per_launch"],
+                    traffic=read_traffic(rr["kernel"]))
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle on a one-step sample ...")
+        cpu = cpu_baseline(cfg)
+    line = {
+        "metric": "cell-steps/s at pressure residual 1e-8: learned+mixed vs plain FP64 PCG",
+        "value": round(R["cell_steps_per_s"], 1),
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(R["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if primary == "pcg64" else "f64+f32" + ("+bf16" if primary == "learned" else ""),
+        "data": "synthetic: analytic 3D smooth-bubble initial state built on the device",
+        "config": {"workload": cfg["name"], "cells": nc, "form": primary,
+                   "dt": cfg["params"]["dt"], "n_corr": cfg["params"]["n_corr"],
+                   "tol": cfg["params"]["tol"], "parallelism": "single GPU"},
+        "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv)
+                      for kk, vv in v.items() if kk != "roofline"} for k, v in results.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if "pcg64" in results and primary != "pcg64":
+        line["speedup_vs_pcg64"] = round(R["cell_steps_per_s"] / results["pcg64"]["cell_steps_per_s"], 3)
+    print(json.dumps(line), flush=True)
+
+
+def learned_available(cfg):
+    return False
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,760 @@
+// gea_api.hip -- the C ABI of include/gea.h: context, workspace carving,
+// the time step's kernel sequence (Sec. 3: Step 1, Step 2, PISO Step 3) and
+// the pressure solvers (FP64 Jacobi-PCG, FP32/FP64 iterative refinement).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gea.h"
+#include "gea_internal.h"
+
+using namespace gea;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+// Carves 256-byte aligned buffers out of one workspace; with a null base it
+// only measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct State {
+  double* rho;
+  double* u[3];
+  double* T;
+  double* pp;
+  double* p;
+};
+
+constexpr int kMaxPartials = 2048 * 8;
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(call)                                 \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) throw HipError{e_, #call}; \
+  } while (0)
+
+// Optional per-kernel-class device timing: events recorded on the stream
+// around each launch, summed after the next stream synchronisation.
+struct KernelTimer {
+  static constexpr int kClasses = 8;
+  bool on = false;
+  double ms[kClasses] = {};
+  long long launches[kClasses] = {};
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Pending {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+
+  hipEvent_t take() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  template <typename F>
+  void run(int k, hipStream_t s, F&& launch) {
+    if (!on) {
+      launch();
+      return;
+    }
+    hipEvent_t a = take(), b = take();
+    HIPCHK(hipEventRecord(a, s));
+    launch();
+    HIPCHK(hipEventRecord(b, s));
+    pending.push_back({k, a, b});
+    if (used > 4096) {
+      HIPCHK(hipStreamSynchronize(s));
+      flush();
+    }
+  }
+  // call only after the stream has been synchronised
+  void flush() {
+    for (const Pending& p : pending) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, p.a, p.b));
+      ms[p.k] += t;
+      launches[p.k] += 1;
+    }
+    pending.clear();
+    used = 0;
+  }
+  void reset() {
+    for (int k = 0; k < kClasses; ++k) {
+      ms[k] = 0.0;
+      launches[k] = 0;
+    }
+  }
+  ~KernelTimer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct gea_ctx {
+  gea_mesh mesh;
+  gea_params prm;
+  Geo G;
+  Phys ph;
+  hipStream_t stream;
+  State st[2];
+  int cur = 0;
+  double* Tbg;
+  double* rho_a;
+  double* pp_a;
+  // step work arrays
+  double* phi[3];
+  double* rho_star;
+  double* ustar[3];
+  double* e0;
+  double* ea;
+  double* eb;
+  double* Ta;
+  double* Tb;
+  double* rho23;
+  double* psi;
+  double* c;
+  double* D;
+  double* H[3];
+  double* b;
+  double* dinv;
+  // FP64 CG
+  double* r;
+  double* p0;
+  double* p1;
+  double* q;
+  double* xs;  // scratch vector (solutions, operator application)
+  // mixed precision
+  double* r64;
+  float* c32;
+  float* D32;
+  float* dinv32;
+  float* r32;
+  float* p032;
+  float* p132;
+  float* q32;
+  float* d32;
+  // reductions
+  double* partials;
+  CgScalars* sc;
+  CgScalars* sc32;
+  KernelTimer timer;
+  int last_iters64 = 0;  // iterations of the previous solve: first batch length
+  int last_iters32 = 0;
+  bool has_state = false;
+  bool has_system = false;
+  std::string err;
+};
+
+namespace {
+
+size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m) {
+  const size_t nc = (size_t)m.nx * m.ny * m.nz;
+  const int nd = m.ny == 1 ? 2 : 3;
+  for (int s = 0; s < 2; ++s) {
+    State& S = x->st[s];
+    S.rho = cv.take<double>(nc);
+    for (int d = 0; d < 3; ++d) S.u[d] = d < nd ? cv.take<double>(nc) : nullptr;
+    S.T = cv.take<double>(nc);
+    S.pp = cv.take<double>(nc);
+    S.p = cv.take<double>(nc);
+  }
+  x->Tbg = cv.take<double>(m.nz);
+  x->rho_a = cv.take<double>(m.nz);
+  x->pp_a = cv.take<double>(m.nz);
+  for (int d = 0; d < 3; ++d) x->phi[d] = d < nd ? cv.take<double>(nc) : nullptr;
+  x->rho_star = cv.take<double>(nc);
+  for (int d = 0; d < 3; ++d) x->ustar[d] = d < nd ? cv.take<double>(nc) : nullptr;
+  x->e0 = cv.take<double>(nc);
+  x->ea = cv.take<double>(nc);
+  x->eb = cv.take<double>(nc);
+  x->Ta = cv.take<double>(nc);
+  x->Tb = cv.take<double>(nc);
+  x->rho23 = cv.take<double>(nc);
+  x->psi = cv.take<double>(nc);
+  x->c = cv.take<double>(nc);
+  x->D = cv.take<double>(nc);
+  for (int d = 0; d < 3; ++d) x->H[d] = d < nd ? cv.take<double>(nc) : nullptr;
+  x->b = cv.take<double>(nc);
+  x->dinv = cv.take<double>(nc);
+  x->r = cv.take<double>(nc);
+  x->p0 = cv.take<double>(nc);
+  x->p1 = cv.take<double>(nc);
+  x->q = cv.take<double>(nc);
+  x->xs = cv.take<double>(nc);
+  x->r64 = cv.take<double>(nc);
+  x->c32 = cv.take<float>(nc);
+  x->D32 = cv.take<float>(nc);
+  x->dinv32 = cv.take<float>(nc);
+  x->r32 = cv.take<float>(nc);
+  x->p032 = cv.take<float>(nc);
+  x->p132 = cv.take<float>(nc);
+  x->q32 = cv.take<float>(nc);
+  x->d32 = cv.take<float>(nc);
+  x->partials = cv.take<double>(kMaxPartials);
+  x->sc = cv.take<CgScalars>(1);
+  x->sc32 = cv.take<CgScalars>(1);
+  return cv.off + 256;
+}
+
+gea_status check_params(const gea_mesh* m, const gea_params* q, std::string& err) {
+  if (!m || !q) {
+    err = "null mesh or params";
+    return GEA_ERR_ARG;
+  }
+  if (m->nx < 1 || m->ny < 1 || m->nz < 1) {
+    err = "mesh dimensions must be positive";
+    return GEA_ERR_ARG;
+  }
+  if ((double)m->nx * m->ny * m->nz > 2147483647.0 / 1.0) {
+    err = "more than 2^31-1 cells";
+    return GEA_ERR_ARG;
+  }
+  if (!(m->lx > 0 && m->ly > 0 && m->lz > 0)) {
+    err = "domain lengths must be positive";
+    return GEA_ERR_ARG;
+  }
+  if (!(q->R > 0 && q->cp > 0 && q->cv > 0 && q->dt > 0 && q->Pr > 0 && q->g >= 0 &&
+        q->mu >= 0 && q->p0 > 0 && q->theta0 > 0)) {
+    err = "physical constants must be positive (g, mu non-negative)";
+    return GEA_ERR_ARG;
+  }
+  if (q->n_corr < 1 || q->n_corr > 8 || q->n_energy_sweeps < 1) {
+    err = "n_corr must be in 1..8 and n_energy_sweeps >= 1";
+    return GEA_ERR_ARG;
+  }
+  if (q->solver < 0 || q->solver > 2 || !(q->tol > 0) || q->max_iter < 1) {
+    err = "bad solver, tol or max_iter";
+    return GEA_ERR_ARG;
+  }
+  if (q->solver != GEA_PCG_JACOBI_FP64 && !(q->inner_tol > 0 && q->inner_tol < 1)) {
+    err = "inner_tol must be in (0, 1) for the refined solvers";
+    return GEA_ERR_ARG;
+  }
+  return GEA_OK;
+}
+
+void setup_geometry(gea_ctx* x) {
+  const gea_mesh& m = x->mesh;
+  Geo& G = x->G;
+  const double dx = m.lx / m.nx, dy = m.ly / m.ny, dz = m.lz / m.nz;
+  G.nx = m.nx;
+  G.ny = m.ny;
+  G.nz = m.nz;
+  G.nc = m.nx * m.ny * m.nz;
+  G.V = dx * dy * dz;
+  G.dz = dz;
+  if (m.ny == 1) {
+    G.ndim = 2;
+    G.n[0] = m.nx; G.st[0] = 1;    G.h[0] = dx; G.S[0] = dy * dz;
+    G.n[1] = m.nz; G.st[1] = m.nx; G.h[1] = dz; G.S[1] = dx * dy;
+    G.n[2] = 1;    G.st[2] = 0;    G.h[2] = 0;  G.S[2] = 0;
+  } else {
+    G.ndim = 3;
+    G.n[0] = m.nx; G.st[0] = 1;           G.h[0] = dx; G.S[0] = dy * dz;
+    G.n[1] = m.ny; G.st[1] = m.nx;        G.h[1] = dy; G.S[1] = dx * dz;
+    G.n[2] = m.nz; G.st[2] = m.nx * m.ny; G.h[2] = dz; G.S[2] = dx * dy;
+  }
+  const gea_params& q = x->prm;
+  x->ph = Phys{q.R, q.cp, q.cv, q.g, q.mu, q.Pr, q.dt, q.p0, q.theta0};
+}
+
+void read_scalars(gea_ctx* x, CgScalars* dev, CgScalars* host) {
+  HIPCHK(hipMemcpyAsync(host, dev, sizeof(CgScalars), hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  x->timer.flush();
+}
+
+// Host loop of one CG solve: enqueue batches of iterations, read the device
+// scalars after each batch.  The batch length is predicted from the
+// residual's observed decay rate so that few launches follow convergence
+// (those find the done flag set and return at once).
+template <typename LaunchIter>
+gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int first_batch,
+                  LaunchIter&& launch_iter) {
+  const int every = x->prm.check_every > 0 ? x->prm.check_every : 8;
+  const long cap = (long)max_iter + 4L * every + 64;
+  int batch = first_batch > 0 ? first_batch : every;
+  long j = 0;
+  int prev_iter = hs.iter;
+  double prev_rr = hs.rr;
+  while (!hs.done) {
+    if (j > cap) {
+      x->err = "solver flag never set";
+      return GEA_ERR_HIP;
+    }
+    for (int k = 0; k < batch; ++k, ++j) launch_iter((int)j);
+    HIPCHK(hipGetLastError());
+    read_scalars(x, dsc, &hs);
+    const int di = hs.iter - prev_iter;
+    batch = every;
+    if (!hs.done && di > 0 && hs.rr > 0 && prev_rr > 0 && hs.bb > 0) {
+      const double rate = std::log(hs.rr / prev_rr) / di;    // per iteration, < 0 when converging
+      const double need = std::log(hs.tol2 * hs.bb / hs.rr);  // < 0 while not converged
+      if (rate < -1e-9) {
+        const double est = 0.9 * need / rate;
+        batch = est < 1.0 ? 1 : (est > 512.0 ? 512 : (int)est);
+      }
+    }
+    prev_iter = hs.iter;
+    prev_rr = hs.rr;
+  }
+  return GEA_OK;
+}
+
+// FP64 Jacobi-PCG on (c, D, dinv, b) from the initial guess in xv.
+gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
+  const Geo& G = x->G;
+  CgVectors<double> v{xv, x->r, x->p0, x->p1, x->q, x->c, x->D, x->dinv, x->b};
+  launch_cg_init(x->stream, G, v, x->prm.tol, x->prm.max_iter, x->partials, x->sc);
+  HIPCHK(hipGetLastError());
+  CgScalars hs;
+  read_scalars(x, x->sc, &hs);
+  out->rel_res0 = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
+  if (hs.bb == 0.0) {
+    HIPCHK(hipMemsetAsync(xv, 0, sizeof(double) * G.nc, x->stream));
+    out->iters = 0;
+    out->rel_res = 0.0;
+    out->status = GEA_OK;
+    return GEA_OK;
+  }
+  const int first = x->last_iters64 > 0 ? (int)(0.9 * x->last_iters64) : 0;
+  gea_status rc = run_cg(x, x->sc, hs, x->prm.max_iter, first, [&](int j) {
+    x->timer.run(0, x->stream, [&] { launch_cg_spmv(x->stream, G, v, j & 1, x->partials, x->sc); });
+    x->timer.run(1, x->stream, [&] { launch_cg_update(x->stream, G, v, j & 1, x->partials, x->sc); });
+  });
+  if (rc != GEA_OK) return rc;
+  x->last_iters64 = hs.iter;
+  out->iters = hs.iter;
+  out->outer_iters = 0;
+  out->rel_res = std::sqrt(hs.rr / hs.bb);
+  out->status = hs.status == 0 ? GEA_OK : (hs.status == -4 ? GEA_ERR_NOCONV : GEA_ERR_NAN);
+  return (gea_status)out->status;
+}
+
+// FP64 outer residual + FP32 inner Jacobi-PCG on the correction.
+gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
+  const Geo& G = x->G;
+  x->timer.run(5, x->stream, [&] {
+    launch_cast_coeffs(x->stream, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
+  });
+  CgVectors<float> v{x->d32, x->r32, x->p032, x->p132, x->q32, x->c32, x->D32, x->dinv32, x->r32};
+  int total = 0;
+  int outer = 0;
+  CgScalars h64, h32;
+  out->rel_res0 = -1.0;
+  out->status = GEA_OK;
+  for (int guard = 0;; ++guard) {
+    if (guard > x->prm.max_iter + 16) {
+      out->status = GEA_ERR_NOCONV;
+      break;
+    }
+    const int budget = x->prm.max_iter - total;
+    x->timer.run(4, x->stream, [&] {
+      launch_residual64(x->stream, G, x->c, x->D, x->b, xv, x->r64, v, x->prm.tol,
+                        x->prm.inner_tol, budget > 0 ? budget : 1, x->partials, x->sc, x->sc32);
+    });
+    HIPCHK(hipGetLastError());
+    read_scalars(x, x->sc, &h64);
+    const double rel = h64.bb > 0 ? std::sqrt(h64.rr / h64.bb) : 0.0;
+    if (out->rel_res0 < 0) out->rel_res0 = rel;
+    out->rel_res = rel;
+    if (h64.status != 0) {
+      out->status = GEA_ERR_NAN;
+      break;
+    }
+    if (h64.bb == 0.0) {
+      HIPCHK(hipMemsetAsync(xv, 0, sizeof(double) * G.nc, x->stream));
+      out->rel_res = 0.0;
+      break;
+    }
+    if (h64.done) break;
+    if (total >= x->prm.max_iter) {
+      out->status = GEA_ERR_NOCONV;
+      break;
+    }
+    read_scalars(x, x->sc32, &h32);
+    const int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
+    gea_status rc = run_cg(x, x->sc32, h32, budget, first, [&](int j) {
+      x->timer.run(2, x->stream, [&] { launch_cg32_spmv(x->stream, G, v, j & 1, x->partials, x->sc32); });
+      x->timer.run(3, x->stream, [&] { launch_cg32_update(x->stream, G, v, j & 1, x->partials, x->sc32); });
+    });
+    if (rc != GEA_OK) return rc;
+    if (outer == 0) x->last_iters32 = h32.iter;
+    total += h32.iter;
+    ++outer;
+    if (h32.status == -5) {
+      out->status = GEA_ERR_NAN;
+      break;
+    }
+    x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+  }
+  out->iters = total;
+  out->outer_iters = outer;
+  return (gea_status)out->status;
+}
+
+gea_status solve(gea_ctx* x, double* xv, gea_solve_stats* out) {
+  *out = gea_solve_stats{};
+  if (x->prm.solver == GEA_PCG_JACOBI_FP64) return solve_pcg64(x, xv, out);
+  return solve_mixed(x, xv, out);
+}
+
+// Steps 1 and 2 from state s; the last energy sweep writes T_out.
+void steps_1_2(gea_ctx* x, const State& S, double* T_out) {
+  const Geo& G = x->G;
+  const Phys& ph = x->ph;
+  hipStream_t s = x->stream;
+  x->timer.run(5, x->stream, [&] { launch_mass_flux(s, G, ph, S.rho, S.u, x->phi, x->rho_star); });
+  x->timer.run(5, x->stream, [&] { launch_mom_predict(s, G, ph, S.rho, S.u, S.pp, x->rho_star, x->phi, x->ustar); });
+  x->timer.run(5, x->stream, [&] { launch_energy_init(s, G, ph, S.T, S.u, x->e0); });
+  const double* e_prev = x->e0;
+  const double* T_prev = S.T;
+  const int ns = x->prm.n_energy_sweeps;
+  for (int sw = 0; sw < ns; ++sw) {
+    const bool last = sw == ns - 1;
+    double* e_next = (sw & 1) ? x->eb : x->ea;
+    double* T_next = last ? T_out : ((sw & 1) ? x->Tb : x->Ta);
+    x->timer.run(5, x->stream, [&] { launch_energy_sweep(s, G, ph, S.rho, x->e0, e_prev, T_prev, x->phi, x->rho_star, x->ustar,
+                        x->Tbg, e_next, T_next, last, S.p, x->rho23, x->psi, x->c, x->D); });
+    e_prev = e_next;
+    T_prev = T_next;
+  }
+}
+
+gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
+  const Geo& G = x->G;
+  const Phys& ph = x->ph;
+  hipStream_t s = x->stream;
+  const State& S = x->st[x->cur];
+  const State& N = x->st[1 - x->cur];
+  steps_1_2(x, S, N.T);
+  HIPCHK(hipMemcpyAsync(N.pp, S.pp, sizeof(double) * G.nc, hipMemcpyDeviceToDevice, s));
+  const int nc = x->prm.n_corr;
+  stats->n_solves = 0;
+  for (int k = 0; k < nc; ++k) {
+    const bool last = k == nc - 1;
+    x->timer.run(5, x->stream, [&] { launch_H(s, G, ph, S.rho, S.u, x->ustar, x->phi, x->H); });
+    x->timer.run(5, x->stream, [&] { launch_rhs(s, G, ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H, x->b, x->dinv); });
+    HIPCHK(hipGetLastError());
+    x->has_system = true;
+    gea_solve_stats ss;
+    gea_status rc = solve(x, N.pp, &ss);
+    stats->solve[stats->n_solves++] = ss;
+    stats->total_iters += ss.iters;
+    stats->total_solves += 1;
+    if (rc != GEA_OK) return rc;
+    double* uo[3] = {x->ustar[0], x->ustar[1], x->ustar[2]};
+    if (last)
+      for (int d = 0; d < 3; ++d) uo[d] = N.u[d];
+    x->timer.run(5, x->stream, [&] { launch_correct(s, G, ph, N.pp, x->rho23, x->psi, x->H, x->D, x->rho_star, uo, last, S.rho,
+                   N.rho, N.p, x->partials, x->sc); });
+    HIPCHK(hipGetLastError());
+  }
+  CgScalars hs;
+  read_scalars(x, x->sc, &hs);
+  stats->mass = hs.aux[0];
+  stats->eos_mismatch = hs.aux[1];
+  if (hs.aux[2] != 0.0) return GEA_ERR_NAN;
+  x->cur = 1 - x->cur;
+  stats->steps_done += 1;
+  return GEA_OK;
+}
+
+gea_status fail(gea_ctx* x, gea_status st, const std::string& msg) {
+  if (x) x->err = msg;
+  return st;
+}
+
+hipMemcpyKind kind_in(gea_ptr_kind k) {
+  return k == GEA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+hipMemcpyKind kind_out(gea_ptr_kind k) {
+  return k == GEA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+
+template <typename F>
+gea_status guarded(gea_ctx* x, F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "HIP error %d (%s) in %s", (int)e.e, hipGetErrorString(e.e),
+                  e.what);
+    return fail(x, GEA_ERR_HIP, buf);
+  } catch (const std::bad_alloc&) {
+    return fail(x, GEA_ERR_ALLOC, "host allocation failed");
+  } catch (...) {
+    return fail(x, GEA_ERR_HIP, "unexpected exception");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+gea_status gea_workspace_bytes(const gea_mesh* mesh, const gea_params* params, size_t* bytes) {
+  std::string err;
+  gea_status st = check_params(mesh, params, err);
+  if (st != GEA_OK) {
+    g_init_error = err;
+    return st;
+  }
+  if (!bytes) return GEA_ERR_ARG;
+  gea_ctx tmp;
+  Carver cv(nullptr);
+  *bytes = carve(cv, &tmp, *mesh);
+  return GEA_OK;
+}
+
+gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* hip_stream,
+                         void* workspace, size_t workspace_bytes, gea_ctx** out) {
+  std::string err;
+  if (!out) {
+    g_init_error = "null output pointer";
+    return GEA_ERR_ARG;
+  }
+  *out = nullptr;
+  gea_status st = check_params(mesh, params, err);
+  if (st != GEA_OK) {
+    g_init_error = err;
+    return st;
+  }
+  size_t need = 0;
+  gea_workspace_bytes(mesh, params, &need);
+  if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u)) {
+    g_init_error = "workspace missing, smaller than gea_workspace_bytes, or not 256-byte aligned";
+    return GEA_ERR_ARG;
+  }
+  gea_ctx* x = new (std::nothrow) gea_ctx();
+  if (!x) {
+    g_init_error = "context allocation failed";
+    return GEA_ERR_ALLOC;
+  }
+  x->mesh = *mesh;
+  x->prm = *params;
+  x->stream = static_cast<hipStream_t>(hip_stream);
+  setup_geometry(x);
+  Carver cv(workspace);
+  carve(cv, x, *mesh);
+  gea_status rc = guarded(x, [&]() {
+    // zero the reduction scalars and their tickets once
+    HIPCHK(hipMemsetAsync(x->sc, 0, sizeof(CgScalars), x->stream));
+    HIPCHK(hipMemsetAsync(x->sc32, 0, sizeof(CgScalars), x->stream));
+    HIPCHK(hipStreamSynchronize(x->stream));
+    return GEA_OK;
+  });
+  if (rc != GEA_OK) {
+    g_init_error = x->err;
+    delete x;
+    return rc;
+  }
+  *out = x;
+  return GEA_OK;
+}
+
+gea_status gea_set_solver(gea_ctx* x, int32_t solver, double tol, int32_t max_iter,
+                          double inner_tol) {
+  if (!x) return GEA_ERR_ARG;
+  gea_params q = x->prm;
+  q.solver = solver;
+  q.tol = tol;
+  q.max_iter = max_iter;
+  q.inner_tol = inner_tol;
+  std::string err;
+  gea_status st = check_params(&x->mesh, &q, err);
+  if (st != GEA_OK) return fail(x, st, err);
+  x->prm = q;
+  return GEA_OK;
+}
+
+gea_status gea_init_bubble(gea_ctx* x, const gea_bubble* b) {
+  if (!x) return GEA_ERR_ARG;
+  if (!b || b->kind < 0 || b->kind > 2 || !(b->rc > 0) || !std::isfinite(b->amp))
+    return fail(x, GEA_ERR_ARG, "bad bubble");
+  return guarded(x, [&]() {
+    const State& S = x->st[x->cur];
+    launch_init_column(x->stream, x->G, x->ph, x->rho_a, x->pp_a, x->Tbg);
+    launch_init_fields(x->stream, x->G, x->ph, b->kind, b->xc, b->yc, b->zc, b->rc, b->amp,
+                       x->rho_a, x->pp_a, x->Tbg, S.rho, S.u, S.T, S.pp, S.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(x->stream));
+    x->has_state = true;
+    x->has_system = false;
+    return GEA_OK;
+  });
+}
+
+gea_status gea_set_state(gea_ctx* x, const double* rho, const double* u, const double* T,
+                         const double* p_prime, const double* p, const double* T_bg,
+                         gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!rho || !u || !T || !p_prime || !p || !T_bg) return fail(x, GEA_ERR_ARG, "null field");
+  return guarded(x, [&]() {
+    const State& S = x->st[x->cur];
+    const size_t n = sizeof(double) * x->G.nc;
+    hipStream_t s = x->stream;
+    HIPCHK(hipMemcpyAsync(S.rho, rho, n, kind_in(kind), s));
+    for (int d = 0; d < x->G.ndim; ++d)
+      HIPCHK(hipMemcpyAsync(S.u[d], u + (size_t)d * x->G.nc, n, kind_in(kind), s));
+    HIPCHK(hipMemcpyAsync(S.T, T, n, kind_in(kind), s));
+    HIPCHK(hipMemcpyAsync(S.pp, p_prime, n, kind_in(kind), s));
+    HIPCHK(hipMemcpyAsync(S.p, p, n, kind_in(kind), s));
+    HIPCHK(hipMemcpyAsync(x->Tbg, T_bg, sizeof(double) * x->G.nz, kind_in(kind), s));
+    HIPCHK(hipStreamSynchronize(s));
+    x->has_state = true;
+    x->has_system = false;
+    return GEA_OK;
+  });
+}
+
+gea_status gea_step(gea_ctx* x, int32_t nsteps, gea_step_stats* stats) {
+  if (!x) return GEA_ERR_ARG;
+  if (nsteps < 0) return fail(x, GEA_ERR_ARG, "nsteps < 0");
+  if (!x->has_state) return fail(x, GEA_ERR_STATE, "no state: call gea_init_bubble or gea_set_state");
+  gea_step_stats local{};
+  gea_step_stats* st = stats ? stats : &local;
+  *st = gea_step_stats{};
+  return guarded(x, [&]() {
+    for (int n = 0; n < nsteps; ++n) {
+      gea_status rc = one_step(x, st);
+      if (rc != GEA_OK) {
+        HIPCHK(hipStreamSynchronize(x->stream));
+        return fail(x, rc, rc == GEA_ERR_NOCONV ? "pressure solve did not converge; step rolled back"
+                                                : "non-finite value; step rolled back");
+      }
+    }
+    return GEA_OK;
+  });
+}
+
+gea_status gea_pressure_solve(gea_ctx* x, const double* b, double* xv, gea_ptr_kind kind,
+                              gea_solve_stats* stats) {
+  if (!x) return GEA_ERR_ARG;
+  if (!xv) return fail(x, GEA_ERR_ARG, "null x");
+  if (!x->has_state) return fail(x, GEA_ERR_STATE, "no state");
+  gea_solve_stats local{};
+  gea_solve_stats* st = stats ? stats : &local;
+  return guarded(x, [&]() {
+    const Geo& G = x->G;
+    hipStream_t s = x->stream;
+    const State& S = x->st[x->cur];
+    const State& N = x->st[1 - x->cur];
+    steps_1_2(x, S, N.T);
+    x->timer.run(5, x->stream, [&] { launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H); });
+    x->timer.run(5, x->stream, [&] { launch_rhs(s, G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H, x->b, x->dinv); });
+    HIPCHK(hipGetLastError());
+    const size_t n = sizeof(double) * G.nc;
+    if (b) HIPCHK(hipMemcpyAsync(x->b, b, n, kind_in(kind), s));
+    HIPCHK(hipMemcpyAsync(x->xs, xv, n, kind_in(kind), s));
+    x->has_system = true;
+    gea_status rc = solve(x, x->xs, st);
+    HIPCHK(hipMemcpyAsync(xv, x->xs, n, kind_out(kind), s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (rc != GEA_OK) return fail(x, rc, "pressure solve failed");
+    return GEA_OK;
+  });
+}
+
+gea_status gea_apply_pressure_operator(gea_ctx* x, const double* xin, double* y,
+                                       gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!xin || !y) return fail(x, GEA_ERR_ARG, "null vector");
+  if (!x->has_system) return fail(x, GEA_ERR_STATE, "no assembled pressure system");
+  return guarded(x, [&]() {
+    const size_t n = sizeof(double) * x->G.nc;
+    HIPCHK(hipMemcpyAsync(x->xs, xin, n, kind_in(kind), x->stream));
+    launch_apply_A(x->stream, x->G, x->c, x->D, x->xs, x->r64);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(y, x->r64, n, kind_out(kind), x->stream));
+    HIPCHK(hipStreamSynchronize(x->stream));
+    return GEA_OK;
+  });
+}
+
+gea_status gea_get_fields(gea_ctx* x, uint32_t mask, double* out, gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!out) return fail(x, GEA_ERR_ARG, "null output");
+  if (!x->has_state) return fail(x, GEA_ERR_STATE, "no state");
+  if ((mask & (GEA_FIELD_C | GEA_FIELD_D | GEA_FIELD_B)) && !x->has_system)
+    return fail(x, GEA_ERR_STATE, "no assembled pressure system");
+  return guarded(x, [&]() {
+    const State& S = x->st[x->cur];
+    const size_t n = (size_t)x->G.nc;
+    size_t off = 0;
+    auto put = [&](const double* src) {
+      HIPCHK(hipMemcpyAsync(out + off, src, n * sizeof(double), kind_out(kind), x->stream));
+      off += n;
+    };
+    if (mask & GEA_FIELD_RHO) put(S.rho);
+    if (mask & GEA_FIELD_U)
+      for (int d = 0; d < x->G.ndim; ++d) put(S.u[d]);
+    if (mask & GEA_FIELD_T) put(S.T);
+    if (mask & GEA_FIELD_PPRIME) put(S.pp);
+    if (mask & GEA_FIELD_P) put(S.p);
+    if (mask & GEA_FIELD_C) put(x->c);
+    if (mask & GEA_FIELD_D) put(x->D);
+    if (mask & GEA_FIELD_B) put(x->b);
+    HIPCHK(hipStreamSynchronize(x->stream));
+    return GEA_OK;
+  });
+}
+
+gea_status gea_kernel_timing(gea_ctx* x, int32_t on, int32_t reset) {
+  if (!x) return GEA_ERR_ARG;
+  return guarded(x, [&]() {
+    HIPCHK(hipStreamSynchronize(x->stream));
+    x->timer.flush();
+    if (reset) x->timer.reset();
+    x->timer.on = on != 0;
+    return GEA_OK;
+  });
+}
+
+gea_status gea_kernel_times(gea_ctx* x, double* ms, int64_t* launches) {
+  if (!x || !ms || !launches) return GEA_ERR_ARG;
+  return guarded(x, [&]() {
+    HIPCHK(hipStreamSynchronize(x->stream));
+    x->timer.flush();
+    for (int k = 0; k < 8; ++k) {
+      ms[k] = x->timer.ms[k];
+      launches[k] = x->timer.launches[k];
+    }
+    return GEA_OK;
+  });
+}
+
+void gea_destroy(gea_ctx* x) { delete x; }
+
+const char* gea_last_error(const gea_ctx* x) {
+  return x ? x->err.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"

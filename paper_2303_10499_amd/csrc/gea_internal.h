@@ -1,0 +1,128 @@
+// gea_internal.h -- declarations shared by the library's translation units:
+// mesh geometry passed to kernels by value, physical constants, device
+// scalars of the solvers, and the host-side launchers of every kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gea {
+
+constexpr int kBlock = 256;     // threads per workgroup (4 waves of 64)
+constexpr int kMaxDim = 3;
+
+// Uniform hexahedral mesh.  Direction d = 0..ndim-1 is x, (y,) z; z is the
+// last direction.  Index P = i + nx*(j + ny*k).
+struct Geo {
+  int ndim;
+  int nx, ny, nz;
+  int nc;                  // number of cells (< 2^31)
+  int n[kMaxDim];          // cells along direction d
+  int st[kMaxDim];         // index stride of direction d
+  double h[kMaxDim];       // spacing along d
+  double S[kMaxDim];       // area of the faces normal to d
+  double V;                // cell volume
+  double dz;
+};
+
+struct Phys {
+  double R, cp, cv, g, mu, Pr, dt, p0, theta0;
+};
+
+template <int NDIM, typename T = double>
+struct Vec {
+  T* p[NDIM];
+};
+
+// Device-resident solver scalars.  Written by the last workgroup of a
+// reduction, read by the next kernel on the stream and by the host.
+struct CgScalars {
+  double rz;        // <r, z> of the current iterate
+  double rr;        // ||r||^2
+  double bb;        // ||b||^2 (of the system being solved)
+  double alpha, beta;
+  double tol2;      // tol^2
+  double aux[6];    // spare reduction results
+  int iter;
+  int max_iter;
+  int done;         // 1 once converged or failed
+  int status;       // 0 ok, -4 no convergence, -5 non-finite
+  unsigned ticket[4];
+};
+
+// Number of workgroups of the grid-stride kernels: a fixed multiple of the
+// CU count, so the per-workgroup partial sums stay few.
+int grid_for(int nc);
+
+// ---- explicit step kernels (gea_step.hip) ----------------------------------
+void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                      double* const* u, double* const* phi, double* rho_star);
+void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                        double* const* u, const double* pp, const double* rho_star,
+                        double* const* phi, double* const* u_star);
+void launch_energy_init(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
+                        double* const* u, double* e0);
+void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                         const double* e0, const double* e_prev, const double* T_prev,
+                         double* const* phi, const double* rho_star, double* const* u_star,
+                         const double* Tbg, double* e_next, double* T_next, bool last,
+                         const double* p, double* rho23, double* psi, double* c, double* D);
+void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,
+              double* const* u_prev, double* const* phi, double* const* H);
+void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                const double* rho23, const double* psi, const double* c, const double* D,
+                double* const* H, double* b, double* dinv);
+void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
+                    const double* rho23, const double* psi, double* const* H, const double* D,
+                    const double* rho_star, double* const* u_out, bool last,
+                    const double* rho_old, double* rho_new, double* p_new, double* partials,
+                    CgScalars* sc);
+void launch_init_column(hipStream_t s, const Geo& G, const Phys& ph, double* rho_a,
+                        double* pp_a, double* Tbg);
+void launch_init_fields(hipStream_t s, const Geo& G, const Phys& ph, int kind, double xc,
+                        double yc, double zc, double rc, double amp, const double* rho_a,
+                        const double* pp_a, const double* Tbg, double* rho, double* const* u,
+                        double* T, double* pp, double* p);
+
+// ---- Jacobi-PCG kernels (gea_cg.hip) ----------------------------------------
+// FP64 solve of A x = b; r, p, q are work vectors.  Iterations are enqueued
+// in batches; a device flag turns the remaining launches of a batch into
+// no-ops once the solve is done.
+template <typename T>
+struct CgVectors {
+  T* x;
+  T* r;
+  T* p0;   // direction, double buffered (the fused kernel reads the old
+  T* p1;   // direction with halo while writing the new one)
+  T* q;    // A p
+  const T* c;
+  const T* D;
+  const T* dinv;
+  const T* b;
+};
+
+void launch_cg_init(hipStream_t s, const Geo& G, const CgVectors<double>& v, double tol,
+                    int max_iter, double* partials, CgScalars* sc);
+// one iteration = spmv (p = z + beta p_old, q = A p, alpha) then update
+// (x, r, beta, stop test); parity selects which p buffer is the old one
+void launch_cg_spmv(hipStream_t s, const Geo& G, const CgVectors<double>& v, int parity,
+                    double* partials, CgScalars* sc);
+void launch_cg_update(hipStream_t s, const Geo& G, const CgVectors<double>& v, int parity,
+                      double* partials, CgScalars* sc);
+void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,
+                    const double* x, double* y);
+
+// Mixed precision: FP64 residual r = b - A x, its FP32 copy as the inner
+// right-hand side; FP32 inner iterations with FP64 dot accumulation; x += dx.
+void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
+                       const double* b, const double* x, double* r64,
+                       const CgVectors<float>& v32, double tol, double inner_tol, int inner_max,
+                       double* partials, CgScalars* sc64, CgScalars* sc32);
+void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,
+                        const double* dinv, float* c32, float* D32, float* dinv32);
+void launch_cg32_spmv(hipStream_t s, const Geo& G, const CgVectors<float>& v, int parity,
+                      double* partials, CgScalars* sc);
+void launch_cg32_update(hipStream_t s, const Geo& G, const CgVectors<float>& v, int parity,
+                        double* partials, CgScalars* sc);
+void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx);
+
+}  // namespace gea

@@ -1,0 +1,112 @@
+// gea_reduce.h -- workgroup and single-pass grid reductions for wave64.
+//
+// A value is reduced inside each wave with xor shuffles, across the waves
+// of the workgroup through LDS, and across the grid by the last workgroup
+// to finish: every workgroup stores its partial, takes a ticket from a
+// device counter, and the one that draws the last ticket sums all partials
+// in workgroup order.  The order of every addition is fixed by indices, not
+// by timing, so results are bitwise reproducible run to run.
+#pragma once
+#include "gea_internal.h"
+
+namespace gea {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <unsigned MAXMASK, int K>
+__device__ __forceinline__ double combine(double a, double b) {
+  return ((MAXMASK >> K) & 1u) ? fmax(a, b) : a + b;
+}
+
+template <unsigned MAXMASK, int N>
+struct Reducer {
+  static constexpr int kWaves = kBlock / 64;
+
+  // Result in v[] of thread 0 (and, after the call, of every thread via sh).
+  __device__ static void block(double (&v)[N], double (*sh)[kWaves]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      v[k] = ((MAXMASK >> k) & 1u) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) sh[k][w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a = sh[k][0];
+      for (int i = 1; i < kWaves; ++i) a = ((MAXMASK >> k) & 1u) ? fmax(a, sh[k][i]) : a + sh[k][i];
+      v[k] = a;
+    }
+    __syncthreads();
+  }
+
+  // Returns true in every thread of the last workgroup, with out[] holding
+  // the grid-wide result; false elsewhere.  Every workgroup of the grid
+  // must call it exactly once.
+  __device__ static bool grid(double (&v)[N], double* partials, unsigned* ticket,
+                              double (&out)[N]) {
+    __shared__ double sh[N][kWaves];
+    __shared__ int is_last;
+    block(v, sh);
+    const unsigned G = gridDim.x;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < N; ++k)
+        __hip_atomic_store(&partials[k * G + blockIdx.x], v[k], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      is_last = (t == G - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double a[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] = ((MAXMASK >> k) & 1u) ? -INFINITY : 0.0;
+    for (unsigned b = threadIdx.x; b < G; b += blockDim.x) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        double x = __hip_atomic_load(&partials[k * G + b], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        a[k] = ((MAXMASK >> k) & 1u) ? fmax(a[k], x) : a[k] + x;
+      }
+    }
+    block(a, sh);
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = a[k];
+    if (threadIdx.x == 0)
+      __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+};
+
+// 2D/3D cell coordinates: c[0] = i, then (j,) k.
+template <int NDIM>
+__device__ __forceinline__ void cell_coords(const Geo& G, int P, int* c) {
+  c[0] = P % G.nx;
+  const int r = P / G.nx;
+  if constexpr (NDIM == 2) {
+    c[1] = r;
+  } else {
+    c[1] = r % G.ny;
+    c[2] = r / G.ny;
+  }
+}
+
+#define GEA_FOR_CELLS(P, G) \
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < (G).nc; P += gridDim.x * blockDim.x)
+
+}  // namespace gea

@@ -34,7 +34,7 @@ BYTES_PER_CELL = {
     3: 28.0,   # FP32 update
 }
 CLASS_NAMES = {0: "k_cg_spmv<fp64>", 1: "k_cg_update<fp64>", 2: "k_cg_spmv<fp32>",
-               3: "k_cg_update<fp32>", 4: "refinement residual/correction",
+               3: "k_cg_update<fp32>", 4: "solver set-up/check kernels",
                5: "explicit step kernels", 6: "learned network"}
 
 

@@ -174,7 +174,8 @@ gea_status gea_get_fields(gea_ctx* ctx, uint32_t field_mask, double* out, gea_pt
  *   0 FP64 CG operator kernel (p update, q = A p, <p,q>)
  *   1 FP64 CG update kernel (x, r, <r,z>, <r,r>)
  *   2 FP32 inner CG operator kernel   3 FP32 inner CG update kernel
- *   4 FP64 residual and correction kernels of the refinement
+ *   4 solver set-up and check kernels (initial residual, per-batch stop
+ *     test, refinement residual and correction, FP32 coefficient copy)
  *   5 explicit step kernels (Steps 1-3 outside the solve)
  *   6 learned network kernels         7 unused
  * reset = 1 clears the sums.  Timing adds two event records per launch. */

@@ -162,9 +162,12 @@ struct gea_ctx {
   float* q32;
   float* d32;
   // reductions
-  double* partials;
-  CgScalars* sc;
-  CgScalars* sc32;
+  double* partials;  // per-workgroup partials of the step kernels
+  double* o_part;    // partials of the refinement's outer residual
+  CgScalars* sc;     // FP64 solver and step scalars
+  CgScalars* sc32;   // inner FP32 solver scalars
+  CgWork w64;
+  CgWork w32;
   KernelTimer timer;
   int last_iters64 = 0;  // iterations of the previous solve: first batch length
   int last_iters32 = 0;
@@ -174,6 +177,29 @@ struct gea_ctx {
 };
 
 namespace {
+
+Geo make_geo(const gea_mesh& m) {
+  Geo G;
+  const double dx = m.lx / m.nx, dy = m.ly / m.ny, dz = m.lz / m.nz;
+  G.nx = m.nx;
+  G.ny = m.ny;
+  G.nz = m.nz;
+  G.nc = m.nx * m.ny * m.nz;
+  G.V = dx * dy * dz;
+  G.dz = dz;
+  if (m.ny == 1) {
+    G.ndim = 2;
+    G.n[0] = m.nx; G.st[0] = 1;    G.h[0] = dx; G.S[0] = dy * dz;
+    G.n[1] = m.nz; G.st[1] = m.nx; G.h[1] = dz; G.S[1] = dx * dy;
+    G.n[2] = 1;    G.st[2] = 0;    G.h[2] = 0;  G.S[2] = 0;
+  } else {
+    G.ndim = 3;
+    G.n[0] = m.nx; G.st[0] = 1;           G.h[0] = dx; G.S[0] = dy * dz;
+    G.n[1] = m.ny; G.st[1] = m.nx;        G.h[1] = dy; G.S[1] = dx * dz;
+    G.n[2] = m.nz; G.st[2] = m.nx * m.ny; G.h[2] = dz; G.S[2] = dx * dy;
+  }
+  return G;
+}
 
 size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m) {
   const size_t nc = (size_t)m.nx * m.ny * m.nz;
@@ -219,8 +245,18 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m) {
   x->q32 = cv.take<float>(nc);
   x->d32 = cv.take<float>(nc);
   x->partials = cv.take<double>(kMaxPartials);
+  x->o_part = cv.take<double>(kMaxPartials);
   x->sc = cv.take<CgScalars>(1);
   x->sc32 = cv.take<CgScalars>(1);
+  const int ns = spmv_grid(make_geo(m));
+  for (CgWork* w : {&x->w64, &x->w32}) {
+    w->s = cv.take<double>(ns);
+    w->u[0] = cv.take<double>(2 * 2048);
+    w->u[1] = cv.take<double>(2 * 2048);
+    w->b = cv.take<double>(2048);
+  }
+  x->w64.sc = x->sc;
+  x->w32.sc = x->sc32;
   return cv.off + 256;
 }
 
@@ -262,26 +298,7 @@ gea_status check_params(const gea_mesh* m, const gea_params* q, std::string& err
 }
 
 void setup_geometry(gea_ctx* x) {
-  const gea_mesh& m = x->mesh;
-  Geo& G = x->G;
-  const double dx = m.lx / m.nx, dy = m.ly / m.ny, dz = m.lz / m.nz;
-  G.nx = m.nx;
-  G.ny = m.ny;
-  G.nz = m.nz;
-  G.nc = m.nx * m.ny * m.nz;
-  G.V = dx * dy * dz;
-  G.dz = dz;
-  if (m.ny == 1) {
-    G.ndim = 2;
-    G.n[0] = m.nx; G.st[0] = 1;    G.h[0] = dx; G.S[0] = dy * dz;
-    G.n[1] = m.nz; G.st[1] = m.nx; G.h[1] = dz; G.S[1] = dx * dy;
-    G.n[2] = 1;    G.st[2] = 0;    G.h[2] = 0;  G.S[2] = 0;
-  } else {
-    G.ndim = 3;
-    G.n[0] = m.nx; G.st[0] = 1;           G.h[0] = dx; G.S[0] = dy * dz;
-    G.n[1] = m.ny; G.st[1] = m.nx;        G.h[1] = dy; G.S[1] = dx * dz;
-    G.n[2] = m.nz; G.st[2] = m.nx * m.ny; G.h[2] = dz; G.S[2] = dx * dy;
-  }
+  x->G = make_geo(x->mesh);
   const gea_params& q = x->prm;
   x->ph = Phys{q.R, q.cp, q.cv, q.g, q.mu, q.Pr, q.dt, q.p0, q.theta0};
 }
@@ -296,9 +313,9 @@ void read_scalars(gea_ctx* x, CgScalars* dev, CgScalars* host) {
 // scalars after each batch.  The batch length is predicted from the
 // residual's observed decay rate so that few launches follow convergence
 // (those find the done flag set and return at once).
-template <typename LaunchIter>
+template <typename LaunchIter, typename LaunchCheck>
 gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int first_batch,
-                  LaunchIter&& launch_iter) {
+                  LaunchIter&& launch_iter, LaunchCheck&& launch_check) {
   const int every = x->prm.check_every > 0 ? x->prm.check_every : 8;
   const long cap = (long)max_iter + 4L * every + 64;
   int batch = first_batch > 0 ? first_batch : every;
@@ -311,6 +328,7 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
       return GEA_ERR_HIP;
     }
     for (int k = 0; k < batch; ++k, ++j) launch_iter((int)j);
+    launch_check((int)j);
     HIPCHK(hipGetLastError());
     read_scalars(x, dsc, &hs);
     const int di = hs.iter - prev_iter;
@@ -332,8 +350,9 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
 // FP64 Jacobi-PCG on (c, D, dinv, b) from the initial guess in xv.
 gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
   const Geo& G = x->G;
+  const CgWork& w = x->w64;
   CgVectors<double> v{xv, x->r, x->p0, x->p1, x->q, x->c, x->D, x->dinv, x->b};
-  launch_cg_init(x->stream, G, v, x->prm.tol, x->prm.max_iter, x->partials, x->sc);
+  x->timer.run(4, x->stream, [&] { cg_init<double>(x->stream, G, v, w, x->prm.tol, x->prm.max_iter); });
   HIPCHK(hipGetLastError());
   CgScalars hs;
   read_scalars(x, x->sc, &hs);
@@ -346,10 +365,13 @@ gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
     return GEA_OK;
   }
   const int first = x->last_iters64 > 0 ? (int)(0.9 * x->last_iters64) : 0;
-  gea_status rc = run_cg(x, x->sc, hs, x->prm.max_iter, first, [&](int j) {
-    x->timer.run(0, x->stream, [&] { launch_cg_spmv(x->stream, G, v, j & 1, x->partials, x->sc); });
-    x->timer.run(1, x->stream, [&] { launch_cg_update(x->stream, G, v, j & 1, x->partials, x->sc); });
-  });
+  gea_status rc = run_cg(
+      x, x->sc, hs, x->prm.max_iter, first,
+      [&](int j) {
+        x->timer.run(0, x->stream, [&] { cg_spmv<double>(x->stream, G, v, j, w); });
+        x->timer.run(1, x->stream, [&] { cg_update<double>(x->stream, G, v, j, w); });
+      },
+      [&](int j) { x->timer.run(4, x->stream, [&] { cg_check(x->stream, G, j, w); }); });
   if (rc != GEA_OK) return rc;
   x->last_iters64 = hs.iter;
   out->iters = hs.iter;
@@ -362,7 +384,8 @@ gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
 // FP64 outer residual + FP32 inner Jacobi-PCG on the correction.
 gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   const Geo& G = x->G;
-  x->timer.run(5, x->stream, [&] {
+  const CgWork& w = x->w32;
+  x->timer.run(4, x->stream, [&] {
     launch_cast_coeffs(x->stream, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
   });
   CgVectors<float> v{x->d32, x->r32, x->p032, x->p132, x->q32, x->c32, x->D32, x->dinv32, x->r32};
@@ -379,7 +402,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
     const int budget = x->prm.max_iter - total;
     x->timer.run(4, x->stream, [&] {
       launch_residual64(x->stream, G, x->c, x->D, x->b, xv, x->r64, v, x->prm.tol,
-                        x->prm.inner_tol, budget > 0 ? budget : 1, x->partials, x->sc, x->sc32);
+                        x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
     });
     HIPCHK(hipGetLastError());
     read_scalars(x, x->sc, &h64);
@@ -402,10 +425,13 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
     }
     read_scalars(x, x->sc32, &h32);
     const int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
-    gea_status rc = run_cg(x, x->sc32, h32, budget, first, [&](int j) {
-      x->timer.run(2, x->stream, [&] { launch_cg32_spmv(x->stream, G, v, j & 1, x->partials, x->sc32); });
-      x->timer.run(3, x->stream, [&] { launch_cg32_update(x->stream, G, v, j & 1, x->partials, x->sc32); });
-    });
+    gea_status rc = run_cg(
+        x, x->sc32, h32, budget, first,
+        [&](int j) {
+          x->timer.run(2, x->stream, [&] { cg_spmv<float>(x->stream, G, v, j, w); });
+          x->timer.run(3, x->stream, [&] { cg_update<float>(x->stream, G, v, j, w); });
+        },
+        [&](int j) { x->timer.run(4, x->stream, [&] { cg_check(x->stream, G, j, w); }); });
     if (rc != GEA_OK) return rc;
     if (outer == 0) x->last_iters32 = h32.iter;
     total += h32.iter;
@@ -565,7 +591,7 @@ gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* h
   Carver cv(workspace);
   carve(cv, x, *mesh);
   gea_status rc = guarded(x, [&]() {
-    // zero the reduction scalars and their tickets once
+    // zero the solver scalars once
     HIPCHK(hipMemsetAsync(x->sc, 0, sizeof(CgScalars), x->stream));
     HIPCHK(hipMemsetAsync(x->sc32, 0, sizeof(CgScalars), x->stream));
     HIPCHK(hipStreamSynchronize(x->stream));

@@ -1,15 +1,29 @@
 // gea_cg.hip -- Jacobi-preconditioned conjugate gradients on the matrix-free
 // pressure operator of Step 3 (GEA, Sec. 3, eq. p_prime_sd re-derived):
 //     (A x)_i = c_i x_i + sum_f w_f (x_i - x_nb),  w_f = (D_P + D_N)/2 S_f/d_f,
-// homogeneous Neumann on walls.  Face weights are formed on the fly from
-// the cell coefficient D (two FP64 coefficient arrays instead of ndim face
-// arrays).  Two kernels per iteration, each ending in a single-pass grid
-// reduction whose last workgroup writes the CG scalars to device memory:
-//   spmv:   p = z + beta p_old  (z = r/diag, on the fly, own cell and
-//           neighbours), q = A p, <p, q>            -> alpha
-//   update: x += alpha p, r -= alpha q, <r, z>, <r, r> -> beta, convergence
-// so the host never waits inside a solve; it polls the done flag every few
-// iterations.  The same kernels, instantiated on float with FP64 dot
+// homogeneous Neumann on walls; face weights are formed on the fly from the
+// cell coefficient D.
+//
+// One iteration is two kernels:
+//   spmv:   p = r/diag + beta p_old on the tile and its halo, q = A p, <p, q>
+//   update: x += alpha p, r -= alpha q, <r, r/diag>, <r, r>
+// Dot products: every workgroup reduces its values (wave xor-shuffles, then
+// LDS) and stores one partial per workgroup.  The next kernel, which needs
+// the scalar, sums all partials of the previous kernel at its start, every
+// workgroup in the same fixed order, so all workgroups hold bitwise the same
+// alpha/beta and no grid-wide fence or atomic is needed (an agent-scope
+// release in every workgroup costs more than the stream kernel it ends).
+// The stop test (||r|| <= tol ||b||, iteration cap, non-finite) is taken by
+// the spmv kernel from the partials of the update before it; workgroup 0
+// publishes scalars and the done flag, which later launches of a batch read
+// to return at once.  A one-workgroup check kernel closes each batch so the
+// host sees the latest residual.
+//
+// The spmv kernel stages, per workgroup, a 64 x 8 (3D) or 256 x 1 (2D)
+// column tile of p and D with a one-cell halo in an LDS ring of three
+// planes and marches along z, so every value is loaded once per workgroup;
+// workgroups are mapped so that each XCD (own L2) works on a contiguous
+// block of tiles.  The same kernels instantiated on float, with FP64 dot
 // accumulation, are the inner solver of the mixed-precision refinement.
 #include "gea_reduce.h"
 
@@ -17,10 +31,52 @@ namespace gea {
 
 namespace {
 
+constexpr int kTX3 = 64, kTY3 = 8, kKC3 = 16;  // 3D tile and z chunk
+constexpr int kTX2 = 256, kKC2 = 16;           // 2D row segment and z chunk
+
 template <int NDIM, typename T>
 struct Stencil {
   T k[NDIM];  // S_d / h_d in the working precision
 };
+
+// Workgroup index remapped so that the hardware's round-robin placement of
+// consecutive workgroups over the 8 XCDs gives each XCD a contiguous range.
+__device__ __forceinline__ int xcd_block() {
+  const int G = gridDim.x, b = blockIdx.x;
+  return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+}
+
+// sum of n partials, identical in every workgroup; result in all threads
+template <int N>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int n,
+                                             double (&out)[N]) {
+  __shared__ double sh[N][kBlock / 64];
+  double a[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) a[k] = 0.0;
+  for (int b = threadIdx.x; b < n; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] += part[k * n + b];
+  }
+  Reducer<0u, N>::block(a, sh);
+#pragma unroll
+  for (int k = 0; k < N; ++k) out[k] = a[k];
+}
+
+// store this workgroup's N sums at part[k * gridDim.x + blockIdx.x]
+template <int N>
+__device__ __forceinline__ void store_partials(double (&v)[N], double* __restrict__ part) {
+  __shared__ double sh[N][kBlock / 64];
+  Reducer<0u, N>::block(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) part[k * gridDim.x + blockIdx.x] = v[k];
+  }
+}
+
+__device__ __forceinline__ int load_done(CgScalars* sc) {
+  return __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <int NDIM, typename T>
 __device__ __forceinline__ T apply_A_at(const Geo& G, const Stencil<NDIM, T>& K, const int* c,
@@ -38,12 +94,51 @@ __device__ __forceinline__ T apply_A_at(const Geo& G, const Stencil<NDIM, T>& K,
   return acc;
 }
 
-// r = b - A x, p_old = 0, beta = 0; scalars rz, rr, bb and the done flag
+// Stop test from the update partials of the previous iteration.  Returns
+// true (in every workgroup) when the solve ends here; workgroup 0 then
+// publishes the result.  Otherwise beta is returned through *beta_out.
+__device__ __forceinline__ bool spmv_prologue(const double* u_part, int nu, int iter,
+                                              CgScalars* sc, double* beta_out) {
+  double s[2];
+  sum_partials<2>(u_part, nu, s);
+  const double rz = s[0], rr = s[1];
+  int stop = 0, status = 0;
+  if (!isfinite(rz) || !isfinite(rr)) {
+    stop = 1;
+    status = -5;
+  } else if (rr <= sc->tol2 * sc->bb) {
+    stop = 1;
+  } else if (iter >= sc->max_iter) {
+    stop = 1;
+    status = -4;
+  }
+  if (stop) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->rz = rz;
+      sc->rr = rr;
+      sc->iter = iter;
+      sc->status = status;
+      __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+  }
+  const double rz_old = sc->rzs[(iter + 1) & 1];
+  *beta_out = iter == 0 ? 0.0 : rz / rz_old;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rzs[iter & 1] = rz;
+    sc->rz = rz;
+    sc->rr = rr;
+    sc->iter = iter;
+  }
+  return false;
+}
+
+// r = b - A x, p_old = 0; partials (<r, r/diag>, <r, r>) -> u_part, <b, b> -> b_part
 template <int NDIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_init(Geo G, Stencil<NDIM, T> K, CgVectors<T> v,
-                                                    double tol2, int max_iter, double* partials,
-                                                    CgScalars* sc) {
-  double red[3] = {0.0, 0.0, 0.0};
+                                                    double* u_part, double* b_part) {
+  double red[2] = {0.0, 0.0};
+  double bb[1] = {0.0};
   GEA_FOR_CELLS(P, G) {
     int c[NDIM];
     cell_coords<NDIM>(G, P, c);
@@ -53,70 +148,208 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geo G, Stencil<NDIM, T> K, C
     const double rd = (double)r;
     red[0] += rd * (double)(r * v.dinv[P]);
     red[1] += rd * rd;
-    red[2] += (double)v.b[P] * (double)v.b[P];
+    bb[0] += (double)v.b[P] * (double)v.b[P];
   }
-  double out[3];
-  if (Reducer<0u, 3>::grid(red, partials, &sc->ticket[0], out) && threadIdx.x == 0) {
-    sc->rz = out[0];
-    sc->rr = out[1];
-    sc->bb = out[2];
-    sc->alpha = 0.0;
-    sc->beta = 0.0;
-    sc->tol2 = tol2;
-    sc->iter = 0;
-    sc->max_iter = max_iter;
-    const bool finite = isfinite(out[0]) && isfinite(out[1]) && isfinite(out[2]);
-    sc->status = finite ? 0 : -5;
-    sc->done = (!finite || out[1] <= tol2 * out[2]) ? 1 : 0;
-  }
+  store_partials<2>(red, u_part);
+  store_partials<1>(bb, b_part);
 }
 
-// p = r/diag + beta p_old (own cell and neighbours), q = A p, alpha = rz/<p,q>
-template <int NDIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(Geo G, Stencil<NDIM, T> K, CgVectors<T> v,
-                                                    const T* __restrict__ p_old,
-                                                    T* __restrict__ p_new, double* partials,
-                                                    CgScalars* sc) {
-  if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const T beta = (T)sc->beta;
-  const T* __restrict__ r = v.r;
-  const T* __restrict__ dinv = v.dinv;
-  const T* __restrict__ D = v.D;
-  double red[1] = {0.0};
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
-    auto pn = [&](int Q) { return r[Q] * dinv[Q] + beta * p_old[Q]; };
-    const T pp = pn(P);
-    const T dp = D[P];
-    T acc = v.c[P] * pp;
-#pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-      const int st = G.st[d];
-      if (c[d] + 1 < G.n[d]) acc += T(0.5) * (dp + D[P + st]) * K.k[d] * (pp - pn(P + st));
-      if (c[d] > 0) acc += T(0.5) * (D[P - st] + dp) * K.k[d] * (pp - pn(P - st));
-    }
-    p_new[P] = pp;
-    v.q[P] = acc;
-    red[0] += (double)pp * (double)acc;
+// one workgroup: reduce the partials of the last update (or of init) and
+// publish residual and stop test; with init != 0 also ||b||^2 and the setup
+__global__ __launch_bounds__(kBlock) void k_cg_check(const double* u_part, int nu,
+                                                     const double* b_part, int init, double tol2,
+                                                     int max_iter, int iter, CgScalars* sc) {
+  if (!init && load_done(sc)) return;
+  double s[2];
+  sum_partials<2>(u_part, nu, s);
+  double bbv[1] = {0.0};
+  if (init) sum_partials<1>(b_part, nu, bbv);
+  if (threadIdx.x != 0) return;
+  if (init) {
+    sc->bb = bbv[0];
+    sc->tol2 = tol2;
+    sc->max_iter = max_iter;
+    sc->status = 0;
+    sc->alpha = 0.0;
+    sc->rzs[0] = s[0];
+    sc->rzs[1] = s[0];
   }
-  double out[1];
-  if (Reducer<0u, 1>::grid(red, partials, &sc->ticket[0], out) && threadIdx.x == 0) {
-    sc->alpha = sc->rz / out[0];
-    if (!isfinite(sc->alpha)) {
+  const double bb = sc->bb;
+  sc->rz = s[0];
+  sc->rr = s[1];
+  sc->iter = iter;
+  int done = 0;
+  if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(bb)) {
+    sc->status = -5;
+    done = 1;
+  } else if (s[1] <= sc->tol2 * bb) {
+    done = 1;
+  } else if (iter >= sc->max_iter) {
+    sc->status = -4;
+    done = 1;
+  }
+  __hip_atomic_store(&sc->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 3D: p = r/diag + beta p_old, q = A p, partial <p, q>, on a 64 x 8 column
+// tile marching over 16 planes.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv3(Geo G, Stencil<3, T> K, CgVectors<T> v,
+                                                     const T* __restrict__ p_old,
+                                                     T* __restrict__ p_new, int iter,
+                                                     const double* u_part, int nu,
+                                                     double* s_part, CgScalars* sc) {
+  constexpr int TX = kTX3, TY = kTY3, KC = kKC3;
+  constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;
+  constexpr int RPT = TX * TY / kBlock;
+  __shared__ T sp[3][HP];
+  __shared__ T sd[3][HP];
+  if (load_done(sc)) return;
+  double beta_d = 0.0;
+  if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
+  const T beta = (T)beta_d;
+  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+  const int b = xcd_block();
+  const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
+  const int i0 = tx * TX, j0 = ty * TY, k0 = tz * KC;
+  const int k1 = min(k0 + KC, nz);
+  const T kx = K.k[0], ky = K.k[1], kz = K.k[2];
+  double acc = 0.0;
+  for (int kk = k0 - 1; kk <= k1; ++kk) {
+    if (kk >= 0 && kk < nz) {
+      const int sl = (kk + 3) % 3;
+      for (int h = threadIdx.x; h < HP; h += kBlock) {
+        const int hx = h % HX, hy = h / HX;
+        const int i = i0 + hx - 1, j = j0 + hy - 1;
+        T pv = T(0), dv = T(0);
+        if (i >= 0 && i < nx && j >= 0 && j < ny) {
+          const int Q = i + nx * (j + ny * kk);
+          pv = v.r[Q] * v.dinv[Q] + beta * p_old[Q];
+          dv = v.D[Q];
+        }
+        sp[sl][h] = pv;
+        sd[sl][h] = dv;
+      }
+    }
+    __syncthreads();
+    const int k = kk - 1;
+    if (k >= k0 && k < k1) {
+      const int sm = (k + 2) % 3, s0 = (k + 3) % 3, sP = (k + 4) % 3;
+#pragma unroll
+      for (int m = 0; m < RPT; ++m) {
+        const int t = threadIdx.x + kBlock * m;
+        const int lx = t % TX, ly = t / TX;
+        const int i = i0 + lx, j = j0 + ly;
+        if (i < nx && j < ny) {
+          const int h = (lx + 1) + HX * (ly + 1);
+          const int P = i + nx * (j + ny * k);
+          const T pp = sp[s0][h], dp = sd[s0][h];
+          T a = v.c[P] * pp;
+          if (i + 1 < nx) a += T(0.5) * (dp + sd[s0][h + 1]) * kx * (pp - sp[s0][h + 1]);
+          if (i > 0) a += T(0.5) * (sd[s0][h - 1] + dp) * kx * (pp - sp[s0][h - 1]);
+          if (j + 1 < ny) a += T(0.5) * (dp + sd[s0][h + HX]) * ky * (pp - sp[s0][h + HX]);
+          if (j > 0) a += T(0.5) * (sd[s0][h - HX] + dp) * ky * (pp - sp[s0][h - HX]);
+          if (k + 1 < nz) a += T(0.5) * (dp + sd[sP][h]) * kz * (pp - sp[sP][h]);
+          if (k > 0) a += T(0.5) * (sd[sm][h] + dp) * kz * (pp - sp[sm][h]);
+          p_new[P] = pp;
+          v.q[P] = a;
+          acc += (double)pp * (double)a;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double red[1] = {acc};
+  store_partials<1>(red, s_part);
+}
+
+// 2D: the same on a row segment of 256 cells marching over 16 rows of z
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv2(Geo G, Stencil<2, T> K, CgVectors<T> v,
+                                                     const T* __restrict__ p_old,
+                                                     T* __restrict__ p_new, int iter,
+                                                     const double* u_part, int nu,
+                                                     double* s_part, CgScalars* sc) {
+  constexpr int TX = kTX2, KC = kKC2, HX = TX + 2;
+  constexpr int RPT = TX / kBlock;
+  __shared__ T sp[3][HX];
+  __shared__ T sd[3][HX];
+  if (load_done(sc)) return;
+  double beta_d = 0.0;
+  if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
+  const T beta = (T)beta_d;
+  const int nx = G.nx, nz = G.nz;
+  const int ntx = (nx + TX - 1) / TX;
+  const int b = xcd_block();
+  const int tx = b % ntx, tz = b / ntx;
+  const int i0 = tx * TX, k0 = tz * KC, k1 = min(k0 + KC, nz);
+  const T kx = K.k[0], kz = K.k[1];
+  double acc = 0.0;
+  for (int kk = k0 - 1; kk <= k1; ++kk) {
+    if (kk >= 0 && kk < nz) {
+      const int sl = (kk + 3) % 3;
+      for (int h = threadIdx.x; h < HX; h += kBlock) {
+        const int i = i0 + h - 1;
+        T pv = T(0), dv = T(0);
+        if (i >= 0 && i < nx) {
+          const int Q = i + nx * kk;
+          pv = v.r[Q] * v.dinv[Q] + beta * p_old[Q];
+          dv = v.D[Q];
+        }
+        sp[sl][h] = pv;
+        sd[sl][h] = dv;
+      }
+    }
+    __syncthreads();
+    const int k = kk - 1;
+    if (k >= k0 && k < k1) {
+      const int sm = (k + 2) % 3, s0 = (k + 3) % 3, sP = (k + 4) % 3;
+#pragma unroll
+      for (int m = 0; m < RPT; ++m) {
+        const int lx = threadIdx.x + kBlock * m;
+        const int i = i0 + lx;
+        if (i < nx) {
+          const int h = lx + 1, P = i + nx * k;
+          const T pp = sp[s0][h], dp = sd[s0][h];
+          T a = v.c[P] * pp;
+          if (i + 1 < nx) a += T(0.5) * (dp + sd[s0][h + 1]) * kx * (pp - sp[s0][h + 1]);
+          if (i > 0) a += T(0.5) * (sd[s0][h - 1] + dp) * kx * (pp - sp[s0][h - 1]);
+          if (k + 1 < nz) a += T(0.5) * (dp + sd[sP][h]) * kz * (pp - sp[sP][h]);
+          if (k > 0) a += T(0.5) * (sd[sm][h] + dp) * kz * (pp - sp[sm][h]);
+          p_new[P] = pp;
+          v.q[P] = a;
+          acc += (double)pp * (double)a;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double red[1] = {acc};
+  store_partials<1>(red, s_part);
+}
+
+// alpha = <r,z>/<p,q> from the spmv partials; x += alpha p, r -= alpha q;
+// partials (<r, r/diag>, <r, r>)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(Geo G, CgVectors<T> v,
+                                                      const T* __restrict__ p_cur, int iter,
+                                                      const double* s_part, int ns,
+                                                      double* u_part, CgScalars* sc) {
+  if (load_done(sc)) return;
+  double pq[1];
+  sum_partials<1>(s_part, ns, pq);
+  const double alpha_d = sc->rzs[iter & 1] / pq[0];
+  if (!isfinite(alpha_d)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->status = -5;
+      sc->iter = iter;
       __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    return;
   }
-}
-
-// x += alpha p, r -= alpha q, beta = <r,z>_new/<r,z>, stop test on ||r||
-template <int NDIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(Geo G, CgVectors<T> v,
-                                                      const T* __restrict__ p_cur,
-                                                      double* partials, CgScalars* sc) {
-  if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const T alpha = (T)sc->alpha;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha_d;
+  const T alpha = (T)alpha_d;
   double red[2] = {0.0, 0.0};
   GEA_FOR_CELLS(P, G) {
     v.x[P] += alpha * p_cur[P];
@@ -126,24 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Geo G, CgVectors<T> v,
     red[0] += rd * (double)(r * v.dinv[P]);
     red[1] += rd * rd;
   }
-  double out[2];
-  if (Reducer<0u, 2>::grid(red, partials, &sc->ticket[0], out) && threadIdx.x == 0) {
-    sc->beta = out[0] / sc->rz;
-    sc->rz = out[0];
-    sc->rr = out[1];
-    sc->iter += 1;
-    int done = 0;
-    if (!isfinite(out[0]) || !isfinite(out[1])) {
-      sc->status = -5;
-      done = 1;
-    } else if (out[1] <= sc->tol2 * sc->bb) {
-      done = 1;
-    } else if (sc->iter >= sc->max_iter) {
-      sc->status = -4;
-      done = 1;
-    }
-    __hip_atomic_store(&sc->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  store_partials<2>(red, u_part);
 }
 
 template <int NDIM>
@@ -159,10 +375,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_A(Geo G, Stencil<NDIM, double>
 
 // ---- mixed precision ----------------------------------------------------------
 
-// FP64 outer residual r = b - A x; its FP32 copy becomes the inner right-hand
-// side and initial inner residual (inner x = 0, inner p_old = 0).  Reduces
-// ||r||^2, ||b||^2 in FP64 for the outer test and <r32, r32/diag>, ||r32||^2
-// for the inner start.
+// FP64 outer residual r = b - A x and its FP32 copy as the inner right-hand
+// side / initial inner residual (inner x = 0, inner p_old = 0).  Partials:
+// outer (||r||^2, ||b||^2) -> o_part; inner (<r32, r32/diag>, ||r32||^2) ->
+// i_part (the slot the inner solver's first spmv reads).
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, double> K,
                                                        const double* __restrict__ c,
@@ -170,11 +386,10 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ r64,
-                                                       CgVectors<float> v32, double tol2,
-                                                       double inner_tol2, int inner_max,
-                                                       double* partials, CgScalars* sc64,
-                                                       CgScalars* sc32) {
-  double red[4] = {0.0, 0.0, 0.0, 0.0};
+                                                       CgVectors<float> v32, double* o_part,
+                                                       double* i_part) {
+  double ro[2] = {0.0, 0.0};
+  double ri[2] = {0.0, 0.0};
   GEA_FOR_CELLS(P, G) {
     int cc[NDIM];
     cell_coords<NDIM>(G, P, cc);
@@ -184,31 +399,44 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
     v32.r[P] = rf;
     v32.x[P] = 0.0f;
     v32.p0[P] = 0.0f;
-    red[0] += r * r;
-    red[1] += b[P] * b[P];
-    red[2] += (double)rf * (double)(rf * v32.dinv[P]);
-    red[3] += (double)rf * (double)rf;
+    ro[0] += r * r;
+    ro[1] += b[P] * b[P];
+    ri[0] += (double)rf * (double)(rf * v32.dinv[P]);
+    ri[1] += (double)rf * (double)rf;
   }
-  double out[4];
-  if (Reducer<0u, 4>::grid(red, partials, &sc64->ticket[0], out) && threadIdx.x == 0) {
-    sc64->rr = out[0];
-    sc64->bb = out[1];
-    sc64->tol2 = tol2;
-    const bool finite = isfinite(out[0]) && isfinite(out[1]);
-    sc64->status = finite ? 0 : -5;
-    sc64->done = (!finite || out[0] <= tol2 * out[1]) ? 1 : 0;
-    sc32->rz = out[2];
-    sc32->rr = out[3];
-    sc32->bb = out[3];
-    sc32->alpha = 0.0;
-    sc32->beta = 0.0;
-    sc32->tol2 = inner_tol2;
-    sc32->iter = 0;
-    sc32->max_iter = inner_max;
-    sc32->status = 0;
-    __hip_atomic_store(&sc32->done, (sc64->done || out[3] == 0.0) ? 1 : 0, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  }
+  store_partials<2>(ro, o_part);
+  store_partials<2>(ri, i_part);
+}
+
+// one workgroup: outer stop test and the inner solver's setup
+__global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
+                                                           const double* i_part, int n,
+                                                           double tol2, double inner_tol2,
+                                                           int inner_max, CgScalars* sc64,
+                                                           CgScalars* sc32) {
+  double o[2], in[2];
+  sum_partials<2>(o_part, n, o);
+  sum_partials<2>(i_part, n, in);
+  if (threadIdx.x != 0) return;
+  sc64->rr = o[0];
+  sc64->bb = o[1];
+  sc64->tol2 = tol2;
+  const bool finite = isfinite(o[0]) && isfinite(o[1]);
+  sc64->status = finite ? 0 : -5;
+  const int outer_done = (!finite || o[0] <= tol2 * o[1]) ? 1 : 0;
+  __hip_atomic_store(&sc64->done, outer_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  sc32->rz = in[0];
+  sc32->rr = in[1];
+  sc32->bb = in[1];
+  sc32->rzs[0] = in[0];
+  sc32->rzs[1] = in[0];
+  sc32->alpha = 0.0;
+  sc32->tol2 = inner_tol2;
+  sc32->iter = 0;
+  sc32->max_iter = inner_max;
+  sc32->status = 0;
+  __hip_atomic_store(&sc32->done, (outer_done || in[1] == 0.0) ? 1 : 0, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cast_coeffs(int n, const double* c, const double* D,
@@ -233,65 +461,58 @@ Stencil<NDIM, T> stencil(const Geo& G) {
   return K;
 }
 
-template <typename T>
-void cg_init_t(hipStream_t s, const Geo& G, const CgVectors<T>& v, double tol2, int max_iter,
-               double* partials, CgScalars* sc) {
-  const dim3 grid(grid_for(G.nc)), block(kBlock);
-  if (G.ndim == 2)
-    hipLaunchKernelGGL((k_cg_init<2, T>), grid, block, 0, s, G, stencil<2, T>(G), v, tol2, max_iter, partials, sc);
-  else
-    hipLaunchKernelGGL((k_cg_init<3, T>), grid, block, 0, s, G, stencil<3, T>(G), v, tol2, max_iter, partials, sc);
-}
-
-template <typename T>
-void cg_spmv_t(hipStream_t s, const Geo& G, const CgVectors<T>& v, int parity, double* partials,
-               CgScalars* sc) {
-  const dim3 grid(grid_for(G.nc)), block(kBlock);
-  const T* p_old = parity ? v.p1 : v.p0;
-  T* p_new = parity ? v.p0 : v.p1;
-  if (G.ndim == 2)
-    hipLaunchKernelGGL((k_cg_spmv<2, T>), grid, block, 0, s, G, stencil<2, T>(G), v, p_old, p_new, partials, sc);
-  else
-    hipLaunchKernelGGL((k_cg_spmv<3, T>), grid, block, 0, s, G, stencil<3, T>(G), v, p_old, p_new, partials, sc);
-}
-
-template <typename T>
-void cg_update_t(hipStream_t s, const Geo& G, const CgVectors<T>& v, int parity,
-                 double* partials, CgScalars* sc) {
-  const dim3 grid(grid_for(G.nc)), block(kBlock);
-  const T* p_new = parity ? v.p0 : v.p1;
-  if (G.ndim == 2)
-    hipLaunchKernelGGL((k_cg_update<2, T>), grid, block, 0, s, G, v, p_new, partials, sc);
-  else
-    hipLaunchKernelGGL((k_cg_update<3, T>), grid, block, 0, s, G, v, p_new, partials, sc);
-}
-
 }  // namespace
 
-void launch_cg_init(hipStream_t s, const Geo& G, const CgVectors<double>& v, double tol,
-                        int max_iter, double* partials, CgScalars* sc) {
-  cg_init_t<double>(s, G, v, tol * tol, max_iter, partials, sc);
+int spmv_grid(const Geo& G) {
+  if (G.ndim == 3)
+    return ((G.nx + kTX3 - 1) / kTX3) * ((G.ny + kTY3 - 1) / kTY3) * ((G.nz + kKC3 - 1) / kKC3);
+  return ((G.nx + kTX2 - 1) / kTX2) * ((G.nz + kKC2 - 1) / kKC2);
 }
 
-void launch_cg_spmv(hipStream_t s, const Geo& G, const CgVectors<double>& v, int parity,
-                    double* partials, CgScalars* sc) {
-  cg_spmv_t<double>(s, G, v, parity, partials, sc);
+template <typename T>
+void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w, double tol,
+             int max_iter) {
+  const int gu = grid_for(G.nc);
+  if (G.ndim == 2)
+    hipLaunchKernelGGL((k_cg_init<2, T>), dim3(gu), dim3(kBlock), 0, s, G, stencil<2, T>(G), v, w.u[1], w.b);
+  else
+    hipLaunchKernelGGL((k_cg_init<3, T>), dim3(gu), dim3(kBlock), 0, s, G, stencil<3, T>(G), v, w.u[1], w.b);
+  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[1], gu,
+                     (const double*)w.b, 1, tol * tol, max_iter, 0, w.sc);
 }
 
-void launch_cg_update(hipStream_t s, const Geo& G, const CgVectors<double>& v, int parity,
-                      double* partials, CgScalars* sc) {
-  cg_update_t<double>(s, G, v, parity, partials, sc);
+template <typename T>
+void cg_spmv(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w) {
+  const T* p_old = (iter & 1) ? v.p1 : v.p0;
+  T* p_new = (iter & 1) ? v.p0 : v.p1;
+  const int gu = grid_for(G.nc);
+  const double* up = w.u[(iter + 1) & 1];
+  if (G.ndim == 2)
+    hipLaunchKernelGGL(k_cg_spmv2<T>, dim3(spmv_grid(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), v, p_old, p_new, iter, up, gu, w.s, w.sc);
+  else
+    hipLaunchKernelGGL(k_cg_spmv3<T>, dim3(spmv_grid(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), v, p_old, p_new, iter, up, gu, w.s, w.sc);
 }
 
-void launch_cg32_spmv(hipStream_t s, const Geo& G, const CgVectors<float>& v, int parity,
-                      double* partials, CgScalars* sc) {
-  cg_spmv_t<float>(s, G, v, parity, partials, sc);
+template <typename T>
+void cg_update(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w) {
+  const T* p_cur = (iter & 1) ? v.p0 : v.p1;
+  hipLaunchKernelGGL(k_cg_update<T>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, v, p_cur, iter,
+                     (const double*)w.s, spmv_grid(G), w.u[iter & 1], w.sc);
 }
 
-void launch_cg32_update(hipStream_t s, const Geo& G, const CgVectors<float>& v, int parity,
-                        double* partials, CgScalars* sc) {
-  cg_update_t<float>(s, G, v, parity, partials, sc);
+void cg_check(hipStream_t s, const Geo& G, int iter, const CgWork& w) {
+  // the residual after `iter` completed iterations sits in the partials of
+  // update iter-1, i.e. slot (iter + 1) & 1
+  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[(iter + 1) & 1],
+                     grid_for(G.nc), (const double*)nullptr, 0, 0.0, 0, iter, w.sc);
 }
+
+template void cg_init<double>(hipStream_t, const Geo&, const CgVectors<double>&, const CgWork&, double, int);
+template void cg_init<float>(hipStream_t, const Geo&, const CgVectors<float>&, const CgWork&, double, int);
+template void cg_spmv<double>(hipStream_t, const Geo&, const CgVectors<double>&, int, const CgWork&);
+template void cg_spmv<float>(hipStream_t, const Geo&, const CgVectors<float>&, int, const CgWork&);
+template void cg_update<double>(hipStream_t, const Geo&, const CgVectors<double>&, int, const CgWork&);
+template void cg_update<float>(hipStream_t, const Geo&, const CgVectors<float>&, int, const CgWork&);
 
 void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,
                     const double* x, double* y) {
@@ -303,14 +524,18 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 }
 
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
-                           const double* b, const double* x, double* r64,
-                           const CgVectors<float>& v32, double tol, double inner_tol,
-                           int inner_max, double* partials, CgScalars* sc64, CgScalars* sc32) {
-  const dim3 grid(grid_for(G.nc)), block(kBlock);
+                       const double* b, const double* x, double* r64,
+                       const CgVectors<float>& v32, double tol, double inner_tol, int inner_max,
+                       double* o_part, const CgWork& w32, CgScalars* sc64) {
+  const int gu = grid_for(G.nc);
+  const dim3 grid(gu), block(kBlock);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, r64, v32, tol * tol, inner_tol * inner_tol, inner_max, partials, sc64, sc32);
+    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, r64, v32, o_part, w32.u[1]);
   else
-    hipLaunchKernelGGL(k_residual64<3>, grid, block, 0, s, G, stencil<3, double>(G), c, D, b, x, r64, v32, tol * tol, inner_tol * inner_tol, inner_max, partials, sc64, sc32);
+    hipLaunchKernelGGL(k_residual64<3>, grid, block, 0, s, G, stencil<3, double>(G), c, D, b, x, r64, v32, o_part, w32.u[1]);
+  hipLaunchKernelGGL(k_residual_check, dim3(1), block, 0, s, (const double*)o_part,
+                     (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, inner_max,
+                     sc64, w32.sc);
 }
 
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,

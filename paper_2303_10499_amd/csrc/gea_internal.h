@@ -33,20 +33,21 @@ struct Vec {
   T* p[NDIM];
 };
 
-// Device-resident solver scalars.  Written by the last workgroup of a
-// reduction, read by the next kernel on the stream and by the host.
+// Device-resident solver scalars.  Written by workgroup 0 of the solver
+// kernels (and by the one-workgroup check kernels), read by later kernels on
+// the stream and by the host.
 struct CgScalars {
   double rz;        // <r, z> of the current iterate
   double rr;        // ||r||^2
   double bb;        // ||b||^2 (of the system being solved)
-  double alpha, beta;
+  double alpha;
+  double rzs[2];    // <r, z> of iterations of even / odd index
   double tol2;      // tol^2
-  double aux[6];    // spare reduction results
-  int iter;
+  double aux[6];    // reduction results of the step kernels
+  int iter;         // completed iterations
   int max_iter;
   int done;         // 1 once converged or failed
   int status;       // 0 ok, -4 no convergence, -5 non-finite
-  unsigned ticket[4];
 };
 
 // Number of workgroups of the grid-stride kernels: a fixed multiple of the
@@ -100,29 +101,36 @@ struct CgVectors {
   const T* b;
 };
 
-void launch_cg_init(hipStream_t s, const Geo& G, const CgVectors<double>& v, double tol,
-                    int max_iter, double* partials, CgScalars* sc);
-// one iteration = spmv (p = z + beta p_old, q = A p, alpha) then update
-// (x, r, beta, stop test); parity selects which p buffer is the old one
-void launch_cg_spmv(hipStream_t s, const Geo& G, const CgVectors<double>& v, int parity,
-                    double* partials, CgScalars* sc);
-void launch_cg_update(hipStream_t s, const Geo& G, const CgVectors<double>& v, int parity,
-                      double* partials, CgScalars* sc);
+// Per-workgroup partial sums of one CG instance: s (spmv, 1 value per
+// workgroup), u[2] (update, 2 values per workgroup, by iteration parity; u[1]
+// also receives the initial residual), b (||b||^2 at init).
+struct CgWork {
+  double* s;
+  double* u[2];
+  double* b;
+  CgScalars* sc;
+};
+
+int spmv_grid(const Geo& G);
+template <typename T>
+void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w, double tol,
+             int max_iter);
+template <typename T>
+void cg_spmv(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w);
+template <typename T>
+void cg_update(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w);
+void cg_check(hipStream_t s, const Geo& G, int iter, const CgWork& w);
 void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,
                     const double* x, double* y);
 
-// Mixed precision: FP64 residual r = b - A x, its FP32 copy as the inner
-// right-hand side; FP32 inner iterations with FP64 dot accumulation; x += dx.
+// Mixed precision: FP64 residual r = b - A x and its FP32 copy as the inner
+// right-hand side, outer stop test and inner setup; x += dx.
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
                        const double* b, const double* x, double* r64,
                        const CgVectors<float>& v32, double tol, double inner_tol, int inner_max,
-                       double* partials, CgScalars* sc64, CgScalars* sc32);
+                       double* o_part, const CgWork& w32, CgScalars* sc64);
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,
                         const double* dinv, float* c32, float* D32, float* dinv32);
-void launch_cg32_spmv(hipStream_t s, const Geo& G, const CgVectors<float>& v, int parity,
-                      double* partials, CgScalars* sc);
-void launch_cg32_update(hipStream_t s, const Geo& G, const CgVectors<float>& v, int parity,
-                        double* partials, CgScalars* sc);
 void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx);
 
 }  // namespace gea

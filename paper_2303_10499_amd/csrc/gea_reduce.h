@@ -1,11 +1,10 @@
-// gea_reduce.h -- workgroup and single-pass grid reductions for wave64.
+// gea_reduce.h -- workgroup reductions for wave64 and cell coordinates.
 //
-// A value is reduced inside each wave with xor shuffles, across the waves
-// of the workgroup through LDS, and across the grid by the last workgroup
-// to finish: every workgroup stores its partial, takes a ticket from a
-// device counter, and the one that draws the last ticket sums all partials
-// in workgroup order.  The order of every addition is fixed by indices, not
-// by timing, so results are bitwise reproducible run to run.
+// A value is reduced inside each wave with xor shuffles and across the
+// waves of the workgroup through LDS.  Grid-wide sums are formed from one
+// partial per workgroup by the kernel that consumes them, in workgroup
+// order; the order of every addition is fixed by indices, not by timing, so
+// results are bitwise reproducible run to run.
 #pragma once
 #include "gea_internal.h"
 
@@ -52,45 +51,6 @@ struct Reducer {
     __syncthreads();
   }
 
-  // Returns true in every thread of the last workgroup, with out[] holding
-  // the grid-wide result; false elsewhere.  Every workgroup of the grid
-  // must call it exactly once.
-  __device__ static bool grid(double (&v)[N], double* partials, unsigned* ticket,
-                              double (&out)[N]) {
-    __shared__ double sh[N][kWaves];
-    __shared__ int is_last;
-    block(v, sh);
-    const unsigned G = gridDim.x;
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int k = 0; k < N; ++k)
-        __hip_atomic_store(&partials[k * G + blockIdx.x], v[k], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      is_last = (t == G - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double a[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) a[k] = ((MAXMASK >> k) & 1u) ? -INFINITY : 0.0;
-    for (unsigned b = threadIdx.x; b < G; b += blockDim.x) {
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        double x = __hip_atomic_load(&partials[k * G + b], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-        a[k] = ((MAXMASK >> k) & 1u) ? fmax(a[k], x) : a[k] + x;
-      }
-    }
-    block(a, sh);
-#pragma unroll
-    for (int k = 0; k < N; ++k) out[k] = a[k];
-    if (threadIdx.x == 0)
-      __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-  }
 };
 
 // 2D/3D cell coordinates: c[0] = i, then (j,) k.

@@ -326,11 +326,28 @@ __global__ __launch_bounds__(kBlock) void k_correct(
     red[2] += finite ? 0.0 : 1.0;
   }
   if (!last) return;
-  double out[3];
-  if (Reducer<0x2u, 3>::grid(red, partials, &sc->ticket[0], out) && threadIdx.x == 0) {
-    sc->aux[0] = out[0];
-    sc->aux[1] = out[1];
-    sc->aux[2] = out[2];
+  __shared__ double sh[3][kBlock / 64];
+  Reducer<0x2u, 3>::block(red, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partials[k * gridDim.x + blockIdx.x] = red[k];
+}
+
+// one workgroup: [sum of mass, max |rho - psi p|, non-finite count] over the
+// correction kernel's per-workgroup partials, in workgroup order
+__global__ __launch_bounds__(kBlock) void k_finalize_reduce(const double* partials, int n,
+                                                            CgScalars* sc) {
+  __shared__ double sh[3][kBlock / 64];
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < n; b += kBlock) {
+    a[0] += partials[b];
+    a[1] = fmax(a[1], partials[n + b]);
+    a[2] += partials[2 * n + b];
+  }
+  Reducer<0x2u, 3>::block(a, sh);
+  if (threadIdx.x == 0) {
+    sc->aux[0] = a[0];
+    sc->aux[1] = a[1];
+    sc->aux[2] = a[2];
   }
 }
 
@@ -473,6 +490,8 @@ void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* p
     hipLaunchKernelGGL(k_correct<2>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, pp, rho23, psi, V2(H), D, rho_star, V2(u_out), (int)last, rho_old, rho_new, p_new, partials, sc);
   else
     hipLaunchKernelGGL(k_correct<3>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), (int)last, rho_old, rho_new, p_new, partials, sc);
+  if (last)
+    hipLaunchKernelGGL(k_finalize_reduce, dim3(1), dim3(kBlock), 0, s, (const double*)partials, grid_for(G.nc), sc);
 }
 
 void launch_init_column(hipStream_t s, const Geo& G, const Phys& ph, double* rho_a,

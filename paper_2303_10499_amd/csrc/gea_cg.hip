@@ -39,13 +39,6 @@ struct Stencil {
   T k[NDIM];  // S_d / h_d in the working precision
 };
 
-// Workgroup index remapped so that the hardware's round-robin placement of
-// consecutive workgroups over the 8 XCDs gives each XCD a contiguous range.
-__device__ __forceinline__ int xcd_block() {
-  const int G = gridDim.x, b = blockIdx.x;
-  return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
-}
-
 // sum of n partials, identical in every workgroup; result in all threads
 template <int N>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int n,

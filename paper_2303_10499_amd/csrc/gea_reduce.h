@@ -74,22 +74,10 @@ __device__ __forceinline__ int xcd_block() {
   return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
 }
 
-// Cells of this workgroup: a contiguous chunk (a multiple of the workgroup
-// size) in XCD-aware order, so the rows and planes a stencil re-reads are
-// mostly the workgroup's own or its XCD neighbours'.
-__device__ __forceinline__ int chunk_cells(int nc) {
-  const int per = (nc + gridDim.x - 1) / gridDim.x;
-  return (per + kBlock - 1) / kBlock * kBlock;
-}
-
-#ifndef GEA_GRID_STRIDE
-#define GEA_FOR_CELLS(P, G)                                                   \
-  for (int gea_per_ = chunk_cells((G).nc), gea_beg_ = xcd_block() * gea_per_, \
-           gea_end_ = min(gea_beg_ + gea_per_, (G).nc), P = gea_beg_ + (int)threadIdx.x; \
-       P < gea_end_; P += kBlock)
-#else
+// Cells of a workgroup: grid-stride over the mesh in x-fastest order.  (A
+// contiguous chunk per workgroup in XCD-aware order was measured slower for
+// the cache-only stencil kernels on MI355X.)
 #define GEA_FOR_CELLS(P, G) \
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < (G).nc; P += gridDim.x * blockDim.x)
-#endif
 
 }  // namespace gea

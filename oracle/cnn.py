@@ -21,10 +21,12 @@ tensor has shape (C_out, taps, C_in); tap t is the offset (dz, dx) (2D) or
 (dz, dy, dx) (3D) in lexicographic order over {-1, 0, 1}; y[p] uses
 x[p + offset].
 
-Everything is FP64 unless ``bf16=True``: then every convolution input
-(activation and weight) is rounded to bfloat16 (round to nearest even) and
-accumulated in float32 -- the arithmetic of the GPU kernels, for parity.
-The loss is L = sum((y - t)^2) / (2 * npix).
+Everything is FP64 unless ``bf16=True``: then weights and every stored
+activation (the output of each convolution, pooling and concatenation) are
+rounded to bfloat16 (round to nearest even), products are accumulated in
+float32, gradients are kept in float32 and rounded to bfloat16 where they
+enter a convolution -- the arithmetic of the GPU kernels, for parity.  The
+network output stays float32.  The loss is L = sum((y - t)^2) / (2 * npix).
 """
 from __future__ import annotations
 
@@ -159,17 +161,18 @@ def init_params(ndim: int, c_in: int, seed: int = 0):
 def forward(params, x, bf16=False):
     """returns (y, cache of activations)"""
     (W0, b0), (W1, b1), (W2, b2), (W3, b3), (W4, b4), (W5, b5) = params
+    st = round_bf16 if bf16 else (lambda a: a)   # storage of an activation
     c = {}
-    c["x"] = x
-    c["e0"] = relu(conv(x, W0, b0, bf16))
-    c["p0"] = pool(c["e0"])
-    c["e1"] = relu(conv(c["p0"], W1, b1, bf16))
-    c["p1"] = pool(c["e1"])
-    c["e2"] = relu(conv(c["p1"], W2, b2, bf16))
+    c["x"] = st(x)
+    c["e0"] = st(relu(conv(c["x"], W0, b0, bf16)))
+    c["p0"] = st(pool(c["e0"]))
+    c["e1"] = st(relu(conv(c["p0"], W1, b1, bf16)))
+    c["p1"] = st(pool(c["e1"]))
+    c["e2"] = st(relu(conv(c["p1"], W2, b2, bf16)))
     c["c1"] = np.concatenate([up(c["e2"]), c["e1"]], axis=-1)
-    c["d1"] = relu(conv(c["c1"], W3, b3, bf16))
+    c["d1"] = st(relu(conv(c["c1"], W3, b3, bf16)))
     c["c0"] = np.concatenate([up(c["d1"]), c["e0"]], axis=-1)
-    c["d0"] = relu(conv(c["c0"], W4, b4, bf16))
+    c["d0"] = st(relu(conv(c["c0"], W4, b4, bf16)))
     y = conv(c["d0"], W5, b5, bf16)
     return y, c
 

@@ -11,6 +11,8 @@
 #include <vector>
 
 #include "../../include/gea.h"
+#include "../../include/gea_learned.h"
+#include "gea_cnn_internal.h"
 #include "gea_internal.h"
 
 using namespace gea;
@@ -168,6 +170,17 @@ struct gea_ctx {
   CgScalars* sc32;   // inner FP32 solver scalars
   CgWork w64;
   CgWork w32;
+  // learned form
+  float* r_old32;
+  float* z32;
+  double* pair_part;
+  double* pair_s;      // max |r0| and its inverse (training pairs)
+  FcgScalars* fsc;
+  FcgVectors fv;
+  Cnn net;             // network at the mesh resolution (learned form only)
+  bool has_net_space = false;
+  bool has_net = false;
+  int fallbacks = 0;
   KernelTimer timer;
   int last_iters64 = 0;  // iterations of the previous solve: first batch length
   int last_iters32 = 0;
@@ -201,7 +214,7 @@ Geo make_geo(const gea_mesh& m) {
   return G;
 }
 
-size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m) {
+size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   const size_t nc = (size_t)m.nx * m.ny * m.nz;
   const int nd = m.ny == 1 ? 2 : 3;
   for (int s = 0; s < 2; ++s) {
@@ -257,6 +270,18 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m) {
   }
   x->w64.sc = x->sc;
   x->w32.sc = x->sc32;
+  x->r_old32 = cv.take<float>(nc);
+  x->z32 = cv.take<float>(nc);
+  x->pair_part = cv.take<double>(3 * 2048);
+  x->pair_s = cv.take<double>(2);
+  x->fsc = cv.take<FcgScalars>(1);
+  x->fv.part_d = cv.take<double>(2 * 2048);
+  x->fv.part_s = cv.take<double>(2048);
+  x->fv.part_u = cv.take<double>(2 * 2048);
+  // the network (inference buffers) only for the learned form on a mesh whose
+  // dimensions are multiples of 4
+  x->has_net_space = learned && cnn_dims_ok(nd, m.nx, m.ny, m.nz);
+  if (x->has_net_space) cv.off = cnn_carve(x->net, nd, m.nx, m.ny, m.nz, false, cv.base, cv.off);
   return cv.off + 256;
 }
 
@@ -447,9 +472,133 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   return (gea_status)out->status;
 }
 
+// One inner solve by flexible CG with the network as preconditioner on the
+// FP32 correction system set up by the refinement residual (r32, c32, D32).
+// Returns the iterations done; *stalled is set when the stall test fired.
+int learned_inner(gea_ctx* x, double bb, int budget, bool* stalled) {
+  const Geo& G = x->G;
+  FcgVectors& v = x->fv;
+  v.d = x->d32;
+  v.r = x->r32;
+  v.r_old = x->r_old32;
+  v.z = x->z32;
+  v.p0 = x->p032;
+  v.p1 = x->p132;
+  v.q = x->q32;
+  v.c = x->c32;
+  v.D = x->D32;
+  x->timer.run(4, x->stream, [&] {
+    fcg_start(x->stream, G, v, bb, x->prm.inner_tol, budget, x->fsc);
+  });
+  FcgScalars hf;
+  HIPCHK(hipMemcpyAsync(&hf, x->fsc, sizeof hf, hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  x->timer.flush();
+  *stalled = false;
+  int it = 0;
+  const int cap = budget + 8;
+  while (!hf.done && it < cap) {
+    x->timer.run(6, x->stream, [&] {
+      cnn_input_from_residual(x->net, x->r32, &x->fsc->inv_s, x->c32, x->dinv32);
+      cnn_forward(x->net);
+      cnn_scale_output(x->net, &x->fsc->s, x->z32, 0);
+    });
+    x->timer.run(2, x->stream, [&] { fcg_iteration_after_z(x->stream, G, v, it, x->fsc); });
+    HIPCHK(hipGetLastError());
+    ++it;
+    HIPCHK(hipMemcpyAsync(&hf, x->fsc, sizeof hf, hipMemcpyDeviceToHost, x->stream));
+    HIPCHK(hipStreamSynchronize(x->stream));
+    x->timer.flush();
+  }
+  *stalled = hf.status == 1 || !hf.done;
+  return hf.iter;
+}
+
+// FP64 refinement whose inner solves use the learned preconditioner; when
+// an inner solve stalls the rest of this solve uses Jacobi-PCG (fallback).
+gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
+  if (!x->has_net) return solve_mixed(x, xv, out);
+  const Geo& G = x->G;
+  const CgWork& w = x->w32;
+  x->timer.run(4, x->stream, [&] {
+    launch_cast_coeffs(x->stream, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
+  });
+  CgVectors<float> v{x->d32, x->r32, x->p032, x->p132, x->q32, x->c32, x->D32, x->dinv32, x->r32};
+  int total = 0, outer = 0, fallbacks = 0;
+  bool use_net = true;
+  CgScalars h64, h32;
+  out->rel_res0 = -1.0;
+  out->status = GEA_OK;
+  for (int guard = 0;; ++guard) {
+    if (guard > x->prm.max_iter + 16) {
+      out->status = GEA_ERR_NOCONV;
+      break;
+    }
+    const int budget = x->prm.max_iter - total;
+    x->timer.run(4, x->stream, [&] {
+      launch_residual64(x->stream, G, x->c, x->D, x->b, xv, x->r64, v, x->prm.tol,
+                        x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
+    });
+    HIPCHK(hipGetLastError());
+    read_scalars(x, x->sc, &h64);
+    const double rel = h64.bb > 0 ? std::sqrt(h64.rr / h64.bb) : 0.0;
+    if (out->rel_res0 < 0) out->rel_res0 = rel;
+    out->rel_res = rel;
+    if (h64.status != 0) {
+      out->status = GEA_ERR_NAN;
+      break;
+    }
+    if (h64.bb == 0.0) {
+      HIPCHK(hipMemsetAsync(xv, 0, sizeof(double) * G.nc, x->stream));
+      out->rel_res = 0.0;
+      break;
+    }
+    if (h64.done) break;
+    if (total >= x->prm.max_iter) {
+      out->status = GEA_ERR_NOCONV;
+      break;
+    }
+    read_scalars(x, x->sc32, &h32);
+    int done_iters = 0;
+    if (use_net) {
+      bool stalled = false;
+      done_iters = learned_inner(x, h32.bb, budget > 0 ? budget : 1, &stalled);
+      if (stalled) {
+        use_net = false;
+        ++fallbacks;
+      }
+    } else {
+      const int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
+      gea_status rc = run_cg(
+          x, x->sc32, h32, budget, first,
+          [&](int j) {
+            x->timer.run(2, x->stream, [&] { cg_spmv<float>(x->stream, G, v, j, w); });
+            x->timer.run(3, x->stream, [&] { cg_update<float>(x->stream, G, v, j, w); });
+          },
+          [&](int j) { x->timer.run(4, x->stream, [&] { cg_check(x->stream, G, j, w); }); });
+      if (rc != GEA_OK) return rc;
+      done_iters = h32.iter;
+      if (h32.status == -5) {
+        out->status = GEA_ERR_NAN;
+        break;
+      }
+    }
+    total += done_iters;
+    ++outer;
+    // a stalled learned correction is still a descent step: keep it
+    x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+  }
+  out->iters = total;
+  out->outer_iters = outer;
+  out->fallbacks = fallbacks;
+  x->fallbacks += fallbacks;
+  return (gea_status)out->status;
+}
+
 gea_status solve(gea_ctx* x, double* xv, gea_solve_stats* out) {
   *out = gea_solve_stats{};
   if (x->prm.solver == GEA_PCG_JACOBI_FP64) return solve_pcg64(x, xv, out);
+  if (x->prm.solver == GEA_LEARNED_MIXED) return solve_learned(x, xv, out);
   return solve_mixed(x, xv, out);
 }
 
@@ -556,7 +705,7 @@ gea_status gea_workspace_bytes(const gea_mesh* mesh, const gea_params* params, s
   if (!bytes) return GEA_ERR_ARG;
   gea_ctx tmp;
   Carver cv(nullptr);
-  *bytes = carve(cv, &tmp, *mesh);
+  *bytes = carve(cv, &tmp, *mesh, params->solver == GEA_LEARNED_MIXED);
   return GEA_OK;
 }
 
@@ -587,9 +736,10 @@ gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* h
   x->mesh = *mesh;
   x->prm = *params;
   x->stream = static_cast<hipStream_t>(hip_stream);
+  x->net.s = x->stream;
   setup_geometry(x);
   Carver cv(workspace);
-  carve(cv, x, *mesh);
+  carve(cv, x, *mesh, params->solver == GEA_LEARNED_MIXED);
   gea_status rc = guarded(x, [&]() {
     // zero the solver scalars once
     HIPCHK(hipMemsetAsync(x->sc, 0, sizeof(CgScalars), x->stream));
@@ -609,6 +759,8 @@ gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* h
 gea_status gea_set_solver(gea_ctx* x, int32_t solver, double tol, int32_t max_iter,
                           double inner_tol) {
   if (!x) return GEA_ERR_ARG;
+  if (solver == GEA_LEARNED_MIXED && !x->has_net_space)
+    return fail(x, GEA_ERR_STATE, "learned form needs a context created with it (network buffers)");
   gea_params q = x->prm;
   q.solver = solver;
   q.tol = tol;
@@ -773,6 +925,75 @@ gea_status gea_kernel_times(gea_ctx* x, double* ms, int64_t* launches) {
       ms[k] = x->timer.ms[k];
       launches[k] = x->timer.launches[k];
     }
+    return GEA_OK;
+  });
+}
+
+gea_status gea_load_weights(gea_ctx* x, const float* params, gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!params) return fail(x, GEA_ERR_ARG, "null params");
+  if (!x->has_net_space)
+    return fail(x, GEA_ERR_STATE,
+                "no network buffers: create the context with the learned solver on a mesh whose "
+                "dimensions are multiples of 4");
+  return guarded(x, [&]() {
+    x->net.s = x->stream;
+    HIPCHK(hipMemcpyAsync(x->net.master, params, sizeof(float) * x->net.nparams, kind_in(kind),
+                          x->stream));
+    cnn_pack_weights(x->net);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(x->stream));
+    x->has_net = true;
+    return GEA_OK;
+  });
+}
+
+gea_status gea_make_pair(gea_ctx* x, double rel_tol, float* in_r, float* in_a, float* out_d,
+                         double* scale, gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!in_r || !in_a || !out_d || !(rel_tol > 0)) return fail(x, GEA_ERR_ARG, "bad pair arguments");
+  if (!x->has_state) return fail(x, GEA_ERR_STATE, "no state");
+  return guarded(x, [&]() {
+    const Geo& G = x->G;
+    hipStream_t s = x->stream;
+    const State& S = x->st[x->cur];
+    const State& N = x->st[1 - x->cur];
+    steps_1_2(x, S, N.T);
+    launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H);
+    launch_rhs(s, G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H, x->b, x->dinv);
+    // r0 = b - A p'  (FP64), then the tight FP64 solve from x0 = p'
+    launch_apply_A(s, G, x->c, x->D, S.pp, x->r64);
+    const size_t n = sizeof(double) * G.nc;
+    HIPCHK(hipMemcpyAsync(x->xs, S.pp, n, hipMemcpyDeviceToDevice, s));
+    launch_sub(s, G, x->b, x->r64);
+    gea_params keep = x->prm;
+    x->prm.tol = rel_tol;
+    x->prm.max_iter = 200000;
+    gea_solve_stats st;
+    gea_status rc = solve_pcg64(x, x->xs, &st);
+    x->prm = keep;
+    if (rc != GEA_OK) return fail(x, rc, "pair solve failed");
+    float* tr = in_r;
+    float* ta = in_a;
+    float* td = out_d;
+    if (kind == GEA_HOST) {  // stage through device scratch (the FP32 work vectors)
+      tr = x->r_old32;
+      ta = x->z32;
+      td = x->q32;
+    }
+    pair_outputs(s, G, x->r64, x->c, x->dinv, x->xs, S.pp, x->pair_part, x->pair_s, tr, ta, td);
+    HIPCHK(hipGetLastError());
+    if (kind == GEA_HOST) {
+      const size_t nf = sizeof(float) * G.nc;
+      HIPCHK(hipMemcpyAsync(in_r, tr, nf, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(in_a, ta, nf, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(out_d, td, nf, hipMemcpyDeviceToHost, s));
+    }
+    double hs[2];
+    HIPCHK(hipMemcpyAsync(hs, x->pair_s, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (scale) *scale = hs[0];
+    x->has_system = true;
     return GEA_OK;
   });
 }

@@ -442,6 +442,11 @@ __global__ __launch_bounds__(kBlock) void k_cast_coeffs(int n, const double* c, 
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_sub(int n, const double* b, double* y) {
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x)
+    y[P] = b[P] - y[P];
+}
+
 __global__ __launch_bounds__(kBlock) void k_add_correction(int n, double* x, const float* dx) {
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x)
     x[P] += (double)dx[P];
@@ -538,6 +543,10 @@ void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const doub
 
 void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx) {
   hipLaunchKernelGGL(k_add_correction, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, x, dx);
+}
+
+void launch_sub(hipStream_t s, const Geo& G, const double* b, double* y) {
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, b, y);
 }
 
 }  // namespace gea

@@ -1,0 +1,894 @@
+// gea_cnn.hip -- bfloat16 matrix-core kernels of the learned initial guess /
+// preconditioner network (forward, backward, Adam) and its C ABI
+// (include/gea_learned.h).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (gfx950):
+//   forward / backward-data:  M = cells, N = output channels,
+//                             K = taps x input channels (zero-padded to 32);
+//   backward-weight:          M = output channels, N = taps x input channels,
+//                             K = cells, split over workgroups, the splits
+//                             summed in a fixed order by a second kernel.
+// Operand lane layout of the 16x16x32 instruction (checked on the device):
+// lane l holds A[m = l%16][k = 8*(l/16) + i] and B[k = 8*(l/16) + i][n = l%16]
+// for i = 0..7, and D[m = 4*(l/16) + i][n = l%16] for i = 0..3.  With
+// channels-last activations and input channels padded to a multiple of 8,
+// each lane's 8 K-values of one tap are 16 contiguous bytes.
+// Backward-data is the forward kernel run on the output gradient with the
+// weights flipped in space and transposed in channels.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/gea_learned.h"
+#include "gea_cnn_internal.h"
+#include "gea_reduce.h"
+
+namespace gea {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMT = 2;  // 16-cell M tiles per wave in the convolution
+constexpr int kPixPerSplit = 512;
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite values)
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 load8(const bf16_t* p) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  return __builtin_bit_cast(bf16x8, u);
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+
+template <int NDIM>
+struct Taps {
+  static constexpr int n = NDIM == 2 ? 9 : 27;
+};
+
+// neighbour of cell (i, j, k) at tap t, or -1 outside the grid
+template <int NDIM>
+__device__ __forceinline__ int neighbor(const CnnDims& d, int i, int j, int k, int t) {
+  int dx, dy, dz;
+  if (NDIM == 2) {
+    dz = t / 3 - 1;
+    dx = t % 3 - 1;
+    dy = 0;
+  } else {
+    dz = t / 9 - 1;
+    dy = (t / 3) % 3 - 1;
+    dx = t % 3 - 1;
+  }
+  const int a = i + dx, b = j + dy, c = k + dz;
+  if (a < 0 || a >= d.nx || b < 0 || b >= d.ny || c < 0 || c >= d.nz) return -1;
+  return a + d.nx * (b + d.ny * c);
+}
+
+template <int NDIM>
+__device__ __forceinline__ void coords(const CnnDims& d, int p, int& i, int& j, int& k) {
+  i = p % d.nx;
+  const int r = p / d.nx;
+  if (NDIM == 2) {
+    j = 0;
+    k = r;
+  } else {
+    j = r % d.ny;
+    k = r / d.ny;
+  }
+}
+
+// MODE 0: +bias, ReLU, bf16 out; 1: +bias, FP32 out (first ycount channels);
+// 2: no bias, FP32 out (backward-data).
+template <int NDIM, int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv(CnnDims d, const bf16_t* __restrict__ X,
+                                              const bf16_t* __restrict__ W,
+                                              const float* __restrict__ bias, void* __restrict__ Y,
+                                              int ystride, int ycount) {
+  constexpr int NT = Taps<NDIM>::n;
+  constexpr int KC = (NT * CIN + 31) / 32;
+  constexpr int KPAD = KC * 32;
+  constexpr int NTILE = COUT / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int pbase = (blockIdx.x * 4 + wave) * (16 * kMT);
+  int pi[kMT], pj[kMT], pk[kMT];
+  bool pv[kMT];
+#pragma unroll
+  for (int mt = 0; mt < kMT; ++mt) {
+    const int p = pbase + mt * 16 + r;
+    pv[mt] = p < d.npix;
+    coords<NDIM>(d, pv[mt] ? p : 0, pi[mt], pj[mt], pk[mt]);
+  }
+  f32x4 acc[kMT][NTILE];
+#pragma unroll
+  for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int kc = 0; kc < KC; ++kc) {
+    const int k = kc * 32 + 8 * g;
+    const int t = k / CIN, ci = k % CIN;
+    bf16x8 bw[NTILE];
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt)
+      bw[nt] = (t < NT) ? load8(W + (size_t)(nt * 16 + r) * KPAD + k) : zero8();
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt) {
+      bf16x8 a = zero8();
+      if (t < NT && pv[mt]) {
+        const int q = neighbor<NDIM>(d, pi[mt], pj[mt], pk[mt], t);
+        if (q >= 0) a = load8(X + (size_t)q * CIN + ci);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NTILE; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[nt], acc[mt][nt], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int p = pbase + mt * 16 + 4 * g + i;
+        const int co = nt * 16 + r;
+        if (p < d.npix && co < ycount) {
+          float v = acc[mt][nt][i];
+          if (MODE < 2) v += bias[co];
+          if (MODE == 0) {
+            v = fmaxf(v, 0.f);
+            reinterpret_cast<bf16_t*>(Y)[(size_t)p * ystride + co] = f2bf(v);
+          } else {
+            reinterpret_cast<float*>(Y)[(size_t)p * ystride + co] = v;
+          }
+        }
+      }
+}
+
+// Weight gradient partials: part[split][co][n] = sum over the split's cells
+// p of dY[p][co] * X[p + off(tap(n))][ci(n)], n = tap*CIN + ci.
+template <int NDIM, int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_wgrad(CnnDims d, const bf16_t* __restrict__ X,
+                                               const bf16_t* __restrict__ dY,
+                                               float* __restrict__ part) {
+  constexpr int NT = Taps<NDIM>::n;
+  constexpr int KPAD = (NT * CIN + 31) / 32 * 32;
+  constexpr int MTI = COUT / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int n0 = (blockIdx.x * 4 + wave) * 16;
+  if (n0 >= KPAD) return;  // no workgroup barrier below
+  const int split = blockIdx.y;
+  const int p_beg = split * kPixPerSplit;
+  const int p_end = min(p_beg + kPixPerSplit, d.npix);
+  const int n = n0 + r;
+  const int t = n / CIN, ci = n % CIN;
+  f32x4 acc[MTI];
+#pragma unroll
+  for (int mt = 0; mt < MTI; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int p0 = p_beg; p0 < p_end; p0 += 32) {
+    bf16x8 b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int p = p0 + 8 * g + i;
+      bf16_t v = 0;
+      if (p < p_end && t < NT) {
+        int a, bb, c;
+        coords<NDIM>(d, p, a, bb, c);
+        const int q = neighbor<NDIM>(d, a, bb, c, t);
+        if (q >= 0) v = X[(size_t)q * CIN + ci];
+      }
+      b[i] = __builtin_bit_cast(__bf16, v);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MTI; ++mt) {
+      bf16x8 a;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int p = p0 + 8 * g + i;
+        const bf16_t v = p < p_end ? dY[(size_t)p * COUT + mt * 16 + r] : (bf16_t)0;
+        a[i] = __builtin_bit_cast(__bf16, v);
+      }
+      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mt], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < MTI; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = mt * 16 + 4 * g + i;
+      part[((size_t)split * COUT + co) * KPAD + n0 + r] = acc[mt][i];
+    }
+}
+
+// Sum the weight-gradient partials in split order into the packed gradient
+// (logical layout W[co][tap][ci]); the bias gradient sums dY over the cells.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nsplit,
+                                                      int cout_p, int kpad, int cin, int cin_p,
+                                                      int cout, int ntaps, float* __restrict__ gW,
+                                                      int accumulate) {
+  const int total = cout * ntaps * cin;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int ci = e % cin, t = (e / cin) % ntaps, co = e / (cin * ntaps);
+    const int n = t * cin_p + ci;
+    float s = 0.f;
+    for (int sp = 0; sp < nsplit; ++sp) s += part[((size_t)sp * cout_p + co) * kpad + n];
+    gW[e] = accumulate ? gW[e] + s : s;
+  }
+}
+
+// one workgroup per output channel: db[co] = sum_p dY[p][co] (bf16 dY)
+__global__ __launch_bounds__(256) void k_bias_grad(const bf16_t* __restrict__ dY, int npix,
+                                                   int cout_p, float* __restrict__ gb,
+                                                   int accumulate) {
+  __shared__ double sh[1][kBlock / 64];
+  const int co = blockIdx.x;
+  double a[1] = {0.0};
+  for (int p = threadIdx.x; p < npix; p += kBlock) a[0] += (double)bf2f(dY[(size_t)p * cout_p + co]);
+  Reducer<0u, 1>::block(a, sh);
+  if (threadIdx.x == 0) gb[co] = accumulate ? gb[co] + (float)a[0] : (float)a[0];
+}
+
+// 2x average pooling (bf16 in and out, FP32 sum); d is the coarse grid
+template <int NDIM>
+__global__ __launch_bounds__(256) void k_pool(CnnDims d, int C, const bf16_t* __restrict__ X,
+                                              bf16_t* __restrict__ Y) {
+  const int nxf = 2 * d.nx, nyf = NDIM == 3 ? 2 * d.ny : 1;
+  const long total = (long)d.npix * C;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C), q = (int)(e / C);
+    int i, j, k;
+    coords<NDIM>(d, q, i, j, k);
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < (NDIM == 3 ? 2 : 1); ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int p = (2 * i + dx) + nxf * ((NDIM == 3 ? 2 * j + dy : 0) + nyf * (2 * k + dz));
+          s += bf2f(X[(size_t)p * C + c]);
+        }
+    Y[e] = f2bf(s * (NDIM == 3 ? 0.125f : 0.25f));
+  }
+}
+
+// Y[p] = [up(A)[p], B[p]] on the fine grid d (A has CA channels, B has CB)
+template <int NDIM>
+__global__ __launch_bounds__(256) void k_upcat(CnnDims d, int CA, int CB,
+                                               const bf16_t* __restrict__ A,
+                                               const bf16_t* __restrict__ B,
+                                               bf16_t* __restrict__ Y) {
+  const int C = CA + CB;
+  const int nxc = d.nx / 2, nyc = NDIM == 3 ? d.ny / 2 : 1;
+  const long total = (long)d.npix * C;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C), p = (int)(e / C);
+    if (c < CA) {
+      int i, j, k;
+      coords<NDIM>(d, p, i, j, k);
+      const int q = (i / 2) + nxc * ((NDIM == 3 ? j / 2 : 0) + nyc * (k / 2));
+      Y[e] = A[(size_t)q * CA + c];
+    } else {
+      Y[e] = B[(size_t)p * CB + (c - CA)];
+    }
+  }
+}
+
+// out = bf16(dy * (y > 0)) (mask = 0: no mask); C channels, padded to Cp in out
+__global__ __launch_bounds__(256) void k_mask(int npix, int C, int Cp, const float* __restrict__ dy,
+                                              const bf16_t* __restrict__ y, int mask,
+                                              bf16_t* __restrict__ out) {
+  const long total = (long)npix * Cp;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % Cp), p = (int)(e / Cp);
+    float v = 0.f;
+    if (c < C) {
+      v = dy[(size_t)p * C + c];
+      if (mask && !(bf2f(y[(size_t)p * C + c]) > 0.f)) v = 0.f;
+    }
+    out[e] = f2bf(v);
+  }
+}
+
+// dA[q] = sum over the fine children of dcat[child][0:CA]; dB[p] = dcat[p][CA:]
+template <int NDIM>
+__global__ __launch_bounds__(256) void k_upcat_bwd(CnnDims dc, int CA, int CB,
+                                                   const float* __restrict__ dcat,
+                                                   float* __restrict__ dA, float* __restrict__ dB) {
+  const int C = CA + CB;
+  const int nxf = 2 * dc.nx, nyf = NDIM == 3 ? 2 * dc.ny : 1;
+  const long tA = (long)dc.npix * CA;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tA; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % CA), q = (int)(e / CA);
+    int i, j, k;
+    coords<NDIM>(dc, q, i, j, k);
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < (NDIM == 3 ? 2 : 1); ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int p = (2 * i + dx) + nxf * ((NDIM == 3 ? 2 * j + dy : 0) + nyf * (2 * k + dz));
+          s += dcat[(size_t)p * C + c];
+        }
+    dA[e] = s;
+  }
+  const long nfine = (long)dc.npix * (NDIM == 3 ? 8 : 4);
+  const long tB = nfine * CB;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tB; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % CB), p = (int)(e / CB);
+    dB[e] = dcat[(size_t)p * C + CA + c];
+  }
+}
+
+// dE[p] += dP[parent(p)] / 2^ndim on the fine grid d
+template <int NDIM>
+__global__ __launch_bounds__(256) void k_pool_bwd_add(CnnDims d, int C, const float* __restrict__ dP,
+                                                      float* __restrict__ dE) {
+  const int nxc = d.nx / 2, nyc = NDIM == 3 ? d.ny / 2 : 1;
+  const long total = (long)d.npix * C;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C), p = (int)(e / C);
+    int i, j, k;
+    coords<NDIM>(d, p, i, j, k);
+    const int q = (i / 2) + nxc * ((NDIM == 3 ? j / 2 : 0) + nyc * (k / 2));
+    dE[e] += dP[(size_t)q * C + c] * (NDIM == 3 ? 0.125f : 0.25f);
+  }
+}
+
+// dY[p] = (y - t)/npix in channel 0 of 16; loss partials sum (y - t)^2
+__global__ __launch_bounds__(256) void k_loss(int npix, const float* __restrict__ y,
+                                              const float* __restrict__ t, float* __restrict__ dY,
+                                              double* __restrict__ lpart) {
+  __shared__ double sh[1][kBlock / 64];
+  double a[1] = {0.0};
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x) {
+    const float e = y[p] - t[p];
+    dY[p] = e / (float)npix;
+    a[0] += (double)e * (double)e;
+  }
+  Reducer<0u, 1>::block(a, sh);
+  if (threadIdx.x == 0) lpart[blockIdx.x] = a[0];
+}
+
+__global__ __launch_bounds__(256) void k_input_f32(int npix, const float* __restrict__ xf,
+                                                   bf16_t* __restrict__ xin) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x) {
+    bf16_t* o = xin + (size_t)p * 8;
+    o[0] = f2bf(xf[2 * p]);
+    o[1] = f2bf(xf[2 * p + 1]);
+    for (int c = 2; c < 8; ++c) o[c] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_input_residual(int npix, const float* __restrict__ r,
+                                                        const double* __restrict__ inv_s,
+                                                        const float* __restrict__ c,
+                                                        const float* __restrict__ dinv,
+                                                        bf16_t* __restrict__ xin) {
+  const float is = (float)*inv_s;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x) {
+    bf16_t* o = xin + (size_t)p * 8;
+    o[0] = f2bf(r[p] * is);
+    o[1] = f2bf(c[p] * dinv[p]);
+    for (int k = 2; k < 8; ++k) o[k] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scale_output(int npix, const float* __restrict__ y,
+                                                      const double* __restrict__ s,
+                                                      float* __restrict__ out, int accumulate) {
+  const float sc = (float)*s;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x)
+    out[p] = accumulate ? out[p] + sc * y[p] : sc * y[p];
+}
+
+// master FP32 (W[co][t][ci], b) -> bf16 W[co_p][kpad] (k = t*cin_p + ci),
+// bf16 Wt[ci_p][kpad_t] (k' = flip(t)*cout_p + co), FP32 bias[co_p]
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ mW, const float* __restrict__ mb,
+                                              int cin, int cout, int cin_p, int cout_p, int kpad,
+                                              int kpad_t, int cin_t_p, int ntaps,
+                                              bf16_t* __restrict__ W, bf16_t* __restrict__ Wt,
+                                              float* __restrict__ bias) {
+  const long nW = (long)cout_p * kpad;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nW; e += (long)gridDim.x * blockDim.x) {
+    const int co = (int)(e / kpad), k = (int)(e % kpad);
+    const int t = k / cin_p, ci = k % cin_p;
+    float v = 0.f;
+    if (co < cout && t < ntaps && ci < cin) v = mW[((long)co * ntaps + t) * cin + ci];
+    W[e] = f2bf(v);
+  }
+  if (Wt) {
+    const long nT = (long)cin_t_p * kpad_t;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nT; e += (long)gridDim.x * blockDim.x) {
+      const int ci = (int)(e / kpad_t), k = (int)(e % kpad_t);
+      const int tf = k / cout_p, co = k % cout_p;
+      float v = 0.f;
+      if (ci < cin && tf < ntaps && co < cout) {
+        const int t = ntaps - 1 - tf;
+        v = mW[((long)co * ntaps + t) * cin + ci];
+      }
+      Wt[e] = f2bf(v);
+    }
+  }
+  for (int co = blockIdx.x * blockDim.x + threadIdx.x; co < cout_p; co += gridDim.x * blockDim.x)
+    bias[co] = co < cout ? mb[co] : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_adam(long n, float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, float lr,
+                                              float scale, float bc1, float bc2) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const float gr = g[e] * scale;
+    const float mm = 0.9f * m[e] + 0.1f * gr;
+    const float vv = 0.999f * v[e] + 0.001f * gr * gr;
+    m[e] = mm;
+    v[e] = vv;
+    p[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+  }
+}
+
+int blocks_for(long n) {
+  long b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+int conv_blocks(int npix) { return (npix + 4 * 16 * kMT - 1) / (4 * 16 * kMT); }
+
+// ---- dispatch -------------------------------------------------------------------
+
+template <int NDIM>
+void conv_fwd(const Cnn& n, int layer, const bf16_t* X, void* Y, int mode) {
+  const CnnLayer& L = n.L[layer];
+  const CnnDims& d = n.d[L.level];
+  const dim3 gr(conv_blocks(d.npix)), bl(256);
+  hipStream_t s = n.s;
+#define GEA_CONV(CI, CO, MODE, YS, YC)                                                            \
+  hipLaunchKernelGGL((k_conv<NDIM, CI, CO, MODE>), gr, bl, 0, s, d, X, n.W[layer], n.bias[layer], \
+                     Y, YS, YC)
+  switch (layer) {
+    case 0: GEA_CONV(8, 16, 0, 16, 16); break;
+    case 1: GEA_CONV(16, 32, 0, 32, 32); break;
+    case 2: GEA_CONV(32, 64, 0, 64, 64); break;
+    case 3: GEA_CONV(96, 32, 0, 32, 32); break;
+    case 4: GEA_CONV(48, 16, 0, 16, 16); break;
+    case 5: GEA_CONV(16, 16, 1, 1, 1); break;
+  }
+#undef GEA_CONV
+  (void)mode;
+}
+
+// dX (FP32, cin channels) = conv(dYmasked (bf16, cout_p channels), Wt)
+template <int NDIM>
+void conv_bwd_data(const Cnn& n, int layer, const bf16_t* dYq, float* dX) {
+  const CnnLayer& L = n.L[layer];
+  const CnnDims& d = n.d[L.level];
+  const dim3 gr(conv_blocks(d.npix)), bl(256);
+  hipStream_t s = n.s;
+#define GEA_CONVT(CI, CO, YS)                                                                   \
+  hipLaunchKernelGGL((k_conv<NDIM, CI, CO, 2>), gr, bl, 0, s, d, dYq, n.Wt[layer],            \
+                     (const float*)nullptr, (void*)dX, YS, YS)
+  switch (layer) {
+    case 1: GEA_CONVT(32, 16, 16); break;
+    case 2: GEA_CONVT(64, 32, 32); break;
+    case 3: GEA_CONVT(32, 96, 96); break;
+    case 4: GEA_CONVT(16, 48, 48); break;
+    case 5: GEA_CONVT(16, 16, 16); break;
+  }
+#undef GEA_CONVT
+}
+
+template <int NDIM>
+void conv_wgrad(const Cnn& n, int layer, const bf16_t* X, const bf16_t* dYq, bool acc) {
+  const CnnLayer& L = n.L[layer];
+  const CnnDims& d = n.d[L.level];
+  const int nsplit = (d.npix + kPixPerSplit - 1) / kPixPerSplit;
+  const dim3 gr((L.kpad / 16 + 3) / 4, nsplit), bl(256);
+  hipStream_t s = n.s;
+#define GEA_WG(CI, CO) hipLaunchKernelGGL((k_wgrad<NDIM, CI, CO>), gr, bl, 0, s, d, X, dYq, n.part)
+  switch (layer) {
+    case 0: GEA_WG(8, 16); break;
+    case 1: GEA_WG(16, 32); break;
+    case 2: GEA_WG(32, 64); break;
+    case 3: GEA_WG(96, 32); break;
+    case 4: GEA_WG(48, 16); break;
+    case 5: GEA_WG(16, 16); break;
+  }
+#undef GEA_WG
+  const int ntaps = NDIM == 2 ? 9 : 27;
+  const long nW = (long)L.cout * ntaps * L.cin;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(nW)), bl, 0, s, (const float*)n.part, nsplit,
+                     L.cout_p, L.kpad, L.cin, L.cin_p, L.cout, ntaps, n.grad + L.woff, (int)acc);
+  hipLaunchKernelGGL(k_bias_grad, dim3(L.cout), bl, 0, s, dYq, d.npix, L.cout_p, n.grad + L.boff,
+                     (int)acc);
+}
+
+template <int NDIM>
+void forward_t(Cnn& n) {
+  hipStream_t s = n.s;
+  const dim3 bl(256);
+  conv_fwd<NDIM>(n, 0, n.xin, n.e0, 0);
+  hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[1].npix * 16)), bl, 0, s, n.d[1], 16, (const bf16_t*)n.e0, n.p0);
+  conv_fwd<NDIM>(n, 1, n.p0, n.e1, 0);
+  hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[2].npix * 32)), bl, 0, s, n.d[2], 32, (const bf16_t*)n.e1, n.p1);
+  conv_fwd<NDIM>(n, 2, n.p1, n.e2, 0);
+  hipLaunchKernelGGL(k_upcat<NDIM>, dim3(blocks_for((long)n.d[1].npix * 96)), bl, 0, s, n.d[1], 64, 32, (const bf16_t*)n.e2, (const bf16_t*)n.e1, n.c1);
+  conv_fwd<NDIM>(n, 3, n.c1, n.d1, 0);
+  hipLaunchKernelGGL(k_upcat<NDIM>, dim3(blocks_for((long)n.d[0].npix * 48)), bl, 0, s, n.d[0], 32, 16, (const bf16_t*)n.d1, (const bf16_t*)n.e0, n.c0);
+  conv_fwd<NDIM>(n, 4, n.c0, n.d0, 0);
+  conv_fwd<NDIM>(n, 5, n.d0, n.y, 1);
+}
+
+template <int NDIM>
+void backward_t(Cnn& n, bool acc) {
+  hipStream_t s = n.s;
+  const dim3 bl(256);
+  const int N0 = n.d[0].npix, N1 = n.d[1].npix, N2 = n.d[2].npix;
+  hipLaunchKernelGGL(k_loss, dim3(cnn_loss_partials(n)), bl, 0, s, N0, (const float*)n.y, (const float*)n.t, n.dy5, n.lpart);
+  // layer 5 (no ReLU): dY5 has one channel, padded to 16 for the MFMA kernels
+  hipLaunchKernelGGL(k_mask, dim3(blocks_for((long)N0 * 16)), bl, 0, s, N0, 1, 16, (const float*)n.dy5, (const bf16_t*)nullptr, 0, n.q5);
+  conv_wgrad<NDIM>(n, 5, n.d0, n.q5, acc);
+  conv_bwd_data<NDIM>(n, 5, n.q5, n.dd0);
+  // layer 4
+  hipLaunchKernelGGL(k_mask, dim3(blocks_for((long)N0 * 16)), bl, 0, s, N0, 16, 16, (const float*)n.dd0, (const bf16_t*)n.d0, 1, n.q4);
+  conv_wgrad<NDIM>(n, 4, n.c0, n.q4, acc);
+  conv_bwd_data<NDIM>(n, 4, n.q4, n.dc0);
+  hipLaunchKernelGGL(k_upcat_bwd<NDIM>, dim3(blocks_for((long)N0 * 16)), bl, 0, s, n.d[1], 32, 16, (const float*)n.dc0, n.dd1, n.de0);
+  // layer 3
+  hipLaunchKernelGGL(k_mask, dim3(blocks_for((long)N1 * 32)), bl, 0, s, N1, 32, 32, (const float*)n.dd1, (const bf16_t*)n.d1, 1, n.q3);
+  conv_wgrad<NDIM>(n, 3, n.c1, n.q3, acc);
+  conv_bwd_data<NDIM>(n, 3, n.q3, n.dc1);
+  hipLaunchKernelGGL(k_upcat_bwd<NDIM>, dim3(blocks_for((long)N1 * 32)), bl, 0, s, n.d[2], 64, 32, (const float*)n.dc1, n.de2, n.de1);
+  // layer 2
+  hipLaunchKernelGGL(k_mask, dim3(blocks_for((long)N2 * 64)), bl, 0, s, N2, 64, 64, (const float*)n.de2, (const bf16_t*)n.e2, 1, n.q2);
+  conv_wgrad<NDIM>(n, 2, n.p1, n.q2, acc);
+  conv_bwd_data<NDIM>(n, 2, n.q2, n.dp1);
+  hipLaunchKernelGGL(k_pool_bwd_add<NDIM>, dim3(blocks_for((long)N1 * 32)), bl, 0, s, n.d[1], 32, (const float*)n.dp1, n.de1);
+  // layer 1
+  hipLaunchKernelGGL(k_mask, dim3(blocks_for((long)N1 * 32)), bl, 0, s, N1, 32, 32, (const float*)n.de1, (const bf16_t*)n.e1, 1, n.q1);
+  conv_wgrad<NDIM>(n, 1, n.p0, n.q1, acc);
+  conv_bwd_data<NDIM>(n, 1, n.q1, n.dp0);
+  hipLaunchKernelGGL(k_pool_bwd_add<NDIM>, dim3(blocks_for((long)N0 * 16)), bl, 0, s, n.d[0], 16, (const float*)n.dp0, n.de0);
+  // layer 0 (no input gradient needed)
+  hipLaunchKernelGGL(k_mask, dim3(blocks_for((long)N0 * 16)), bl, 0, s, N0, 16, 16, (const float*)n.de0, (const bf16_t*)n.e0, 1, n.q0);
+  conv_wgrad<NDIM>(n, 0, n.xin, n.q0, acc);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_bf16_to_f32(long n, const bf16_t* __restrict__ a,
+                                                     float* __restrict__ out) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    out[e] = __uint_as_float((uint32_t)a[e] << 16);
+}
+
+int blocks_for_pub(long n) { return blocks_for(n); }
+
+// ---- network geometry and buffers ------------------------------------------------
+
+static void set_layers(Cnn& n, int ndim) {
+  const int nt = ndim == 2 ? 9 : 27;
+  const int cin[kCnnLayers] = {kCnnInputs, 16, 32, 96, 48, 16};
+  const int cout[kCnnLayers] = {16, 32, 64, 32, 16, 1};
+  const int level[kCnnLayers] = {0, 1, 2, 1, 0, 0};
+  long off = 0;
+  for (int l = 0; l < kCnnLayers; ++l) {
+    CnnLayer& L = n.L[l];
+    L.cin = cin[l];
+    L.cout = cout[l];
+    L.cin_p = (cin[l] + 7) / 8 * 8;
+    L.cout_p = (cout[l] + 15) / 16 * 16;
+    L.level = level[l];
+    L.kpad = (nt * L.cin_p + 31) / 32 * 32;
+    L.kpad_t = (nt * L.cout_p + 31) / 32 * 32;
+    L.cin_t_p = (cin[l] + 15) / 16 * 16;
+    L.woff = off;
+    off += (long)L.cout * nt * L.cin;
+    L.boff = off;
+    off += L.cout;
+  }
+  n.nparams = off;
+}
+
+long cnn_param_count(int ndim) {
+  Cnn n;
+  set_layers(n, ndim);
+  return n.nparams;
+}
+
+bool cnn_dims_ok(int ndim, int nx, int ny, int nz) {
+  if (nx < 4 || nz < 4 || nx % 4 || nz % 4) return false;
+  if (ndim == 2) return ny == 1;
+  return ny >= 4 && ny % 4 == 0;
+}
+
+size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* base, size_t off) {
+  n.ndim = ndim;
+  n.train = train;
+  set_layers(n, ndim);
+  for (int l = 0; l < 3; ++l) {
+    n.d[l].nx = nx >> l;
+    n.d[l].ny = ndim == 3 ? (ny >> l) : 1;
+    n.d[l].nz = nz >> l;
+    n.d[l].npix = n.d[l].nx * n.d[l].ny * n.d[l].nz;
+  }
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) & ~size_t(255);
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const size_t N0 = n.d[0].npix, N1 = n.d[1].npix, N2 = n.d[2].npix;
+  const size_t B2 = sizeof(bf16_t), F4 = sizeof(float);
+  n.master = (float*)take(n.nparams * F4);
+  for (int l = 0; l < kCnnLayers; ++l) {
+    const CnnLayer& L = n.L[l];
+    n.W[l] = (bf16_t*)take((size_t)L.cout_p * L.kpad * B2);
+    n.Wt[l] = (train && l > 0) ? (bf16_t*)take((size_t)L.cin_t_p * L.kpad_t * B2) : nullptr;
+    n.bias[l] = (float*)take((size_t)L.cout_p * F4);
+  }
+  n.xin = (bf16_t*)take(N0 * 8 * B2);
+  n.xf = (float*)take(N0 * 2 * F4);
+  n.e0 = (bf16_t*)take(N0 * 16 * B2);
+  n.p0 = (bf16_t*)take(N1 * 16 * B2);
+  n.e1 = (bf16_t*)take(N1 * 32 * B2);
+  n.p1 = (bf16_t*)take(N2 * 32 * B2);
+  n.e2 = (bf16_t*)take(N2 * 64 * B2);
+  n.c1 = (bf16_t*)take(N1 * 96 * B2);
+  n.d1 = (bf16_t*)take(N1 * 32 * B2);
+  n.c0 = (bf16_t*)take(N0 * 48 * B2);
+  n.d0 = (bf16_t*)take(N0 * 16 * B2);
+  n.y = (float*)take(N0 * F4);
+  if (train) {
+    n.grad = (float*)take(n.nparams * F4);
+    n.m = (float*)take(n.nparams * F4);
+    n.v = (float*)take(n.nparams * F4);
+    n.t = (float*)take(N0 * F4);
+    n.dy5 = (float*)take(N0 * F4);
+    n.dd0 = (float*)take(N0 * 16 * F4);
+    n.dc0 = (float*)take(N0 * 48 * F4);
+    n.dd1 = (float*)take(N1 * 32 * F4);
+    n.de0 = (float*)take(N0 * 16 * F4);
+    n.dc1 = (float*)take(N1 * 96 * F4);
+    n.de2 = (float*)take(N2 * 64 * F4);
+    n.de1 = (float*)take(N1 * 32 * F4);
+    n.dp1 = (float*)take(N2 * 32 * F4);
+    n.dp0 = (float*)take(N1 * 16 * F4);
+    n.q5 = (bf16_t*)take(N0 * 16 * B2);
+    n.q4 = (bf16_t*)take(N0 * 16 * B2);
+    n.q3 = (bf16_t*)take(N1 * 32 * B2);
+    n.q2 = (bf16_t*)take(N2 * 64 * B2);
+    n.q1 = (bf16_t*)take(N1 * 32 * B2);
+    n.q0 = (bf16_t*)take(N0 * 16 * B2);
+    long mx = 0;
+    for (int l = 0; l < kCnnLayers; ++l) {
+      const CnnLayer& L = n.L[l];
+      const long ns = (n.d[L.level].npix + kPixPerSplit - 1) / kPixPerSplit;
+      const long need = ns * L.cout_p * L.kpad;
+      if (need > mx) mx = need;
+    }
+    n.part_floats = mx;
+    n.part = (float*)take((size_t)mx * F4);
+    n.lpart = (double*)take(sizeof(double) * 1024);
+  }
+  return off;
+}
+
+int cnn_loss_partials(const Cnn& n) { return blocks_for(n.d[0].npix) > 1024 ? 1024 : blocks_for(n.d[0].npix); }
+
+void cnn_pack_weights(Cnn& n) {
+  const int nt = n.ndim == 2 ? 9 : 27;
+  for (int l = 0; l < kCnnLayers; ++l) {
+    const CnnLayer& L = n.L[l];
+    const long work = (long)L.cout_p * L.kpad + (long)L.cin_t_p * L.kpad_t;
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for(work)), dim3(256), 0, n.s,
+                       (const float*)(n.master + L.woff), (const float*)(n.master + L.boff), L.cin,
+                       L.cout, L.cin_p, L.cout_p, L.kpad, L.kpad_t, L.cin_t_p, nt, n.W[l],
+                       n.Wt[l], n.bias[l]);
+  }
+}
+
+void cnn_input_from_f32(Cnn& n) {
+  hipLaunchKernelGGL(k_input_f32, dim3(blocks_for(n.d[0].npix)), dim3(256), 0, n.s, n.d[0].npix,
+                     (const float*)n.xf, n.xin);
+}
+
+void cnn_input_from_residual(Cnn& n, const float* r, const double* inv_s, const float* c,
+                             const float* dinv) {
+  hipLaunchKernelGGL(k_input_residual, dim3(blocks_for(n.d[0].npix)), dim3(256), 0, n.s,
+                     n.d[0].npix, r, inv_s, c, dinv, n.xin);
+}
+
+void cnn_scale_output(Cnn& n, const double* s, float* out, int accumulate) {
+  hipLaunchKernelGGL(k_scale_output, dim3(blocks_for(n.d[0].npix)), dim3(256), 0, n.s,
+                     n.d[0].npix, (const float*)n.y, s, out, accumulate);
+}
+
+void cnn_forward(Cnn& n) {
+  if (n.ndim == 2) forward_t<2>(n);
+  else forward_t<3>(n);
+}
+
+void cnn_backward(Cnn& n, bool accumulate) {
+  if (n.ndim == 2) backward_t<2>(n, accumulate);
+  else backward_t<3>(n, accumulate);
+}
+
+void cnn_adam(Cnn& n, float lr, float scale, int step) {
+  const float bc1 = 1.f - powf(0.9f, (float)step), bc2 = 1.f - powf(0.999f, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n.nparams)), dim3(256), 0, n.s, n.nparams, n.master,
+                     (const float*)n.grad, n.m, n.v, lr, scale, bc1, bc2);
+  cnn_pack_weights(n);
+}
+
+}  // namespace gea
+
+// ---- C ABI -----------------------------------------------------------------------------
+
+struct gea_cnn {
+  gea::Cnn net;
+  std::string err;
+};
+
+namespace {
+hipMemcpyKind kin(gea_ptr_kind k) { return k == GEA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+hipMemcpyKind kout(gea_ptr_kind k) { return k == GEA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+gea_status hip_status(gea_cnn* x, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GEA_OK;
+  if (x) x->err = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+  return GEA_ERR_HIP;
+}
+}  // namespace
+
+extern "C" {
+
+gea_status gea_cnn_param_count(int32_t ndim, int64_t* count) {
+  if ((ndim != 2 && ndim != 3) || !count) return GEA_ERR_ARG;
+  *count = gea::cnn_param_count(ndim);
+  return GEA_OK;
+}
+
+gea_status gea_cnn_workspace_bytes(int32_t ndim, int32_t nx, int32_t ny, int32_t nz,
+                                   int32_t train, size_t* bytes) {
+  if ((ndim != 2 && ndim != 3) || !bytes || !gea::cnn_dims_ok(ndim, nx, ny, nz)) return GEA_ERR_ARG;
+  if ((double)nx * ny * nz > 1.5e8) return GEA_ERR_ARG;
+  gea::Cnn n;
+  *bytes = gea::cnn_carve(n, ndim, nx, ny, nz, train != 0, nullptr, 0) + 256;
+  return GEA_OK;
+}
+
+gea_status gea_cnn_create(int32_t ndim, int32_t nx, int32_t ny, int32_t nz, int32_t train,
+                          void* hip_stream, void* workspace, size_t workspace_bytes,
+                          gea_cnn** out) {
+  if (!out) return GEA_ERR_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  if (gea_cnn_workspace_bytes(ndim, nx, ny, nz, train, &need) != GEA_OK) return GEA_ERR_ARG;
+  if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u))
+    return GEA_ERR_ARG;
+  gea_cnn* x = new (std::nothrow) gea_cnn();
+  if (!x) return GEA_ERR_ALLOC;
+  gea::cnn_carve(x->net, ndim, nx, ny, nz, train != 0, static_cast<char*>(workspace), 0);
+  x->net.s = static_cast<hipStream_t>(hip_stream);
+  *out = x;
+  return GEA_OK;
+}
+
+gea_status gea_cnn_set_params(gea_cnn* x, const float* params, gea_ptr_kind kind) {
+  if (!x || !params) return GEA_ERR_ARG;
+  gea::Cnn& n = x->net;
+  const size_t bytes = sizeof(float) * n.nparams;
+  gea_status st = hip_status(x, hipMemcpyAsync(n.master, params, bytes, kin(kind), n.s), "params");
+  if (st != GEA_OK) return st;
+  if (n.train) {
+    if ((st = hip_status(x, hipMemsetAsync(n.m, 0, bytes, n.s), "m")) != GEA_OK) return st;
+    if ((st = hip_status(x, hipMemsetAsync(n.v, 0, bytes, n.s), "v")) != GEA_OK) return st;
+    if ((st = hip_status(x, hipMemsetAsync(n.grad, 0, bytes, n.s), "grad")) != GEA_OK) return st;
+  }
+  gea::cnn_pack_weights(n);
+  return hip_status(x, hipStreamSynchronize(n.s), "set_params");
+}
+
+gea_status gea_cnn_get_params(gea_cnn* x, float* params, gea_ptr_kind kind) {
+  if (!x || !params) return GEA_ERR_ARG;
+  gea::Cnn& n = x->net;
+  gea_status st = hip_status(x, hipMemcpyAsync(params, n.master, sizeof(float) * n.nparams, kout(kind), n.s), "get_params");
+  if (st != GEA_OK) return st;
+  return hip_status(x, hipStreamSynchronize(n.s), "get_params");
+}
+
+gea_status gea_cnn_forward(gea_cnn* x, const float* in, float* y, gea_ptr_kind kind) {
+  if (!x || !in || !y) return GEA_ERR_ARG;
+  gea::Cnn& n = x->net;
+  const size_t N0 = n.d[0].npix;
+  gea_status st = hip_status(x, hipMemcpyAsync(n.xf, in, N0 * 2 * sizeof(float), kin(kind), n.s), "input");
+  if (st != GEA_OK) return st;
+  gea::cnn_input_from_f32(n);
+  gea::cnn_forward(n);
+  if ((st = hip_status(x, hipGetLastError(), "forward")) != GEA_OK) return st;
+  st = hip_status(x, hipMemcpyAsync(y, n.y, N0 * sizeof(float), kout(kind), n.s), "output");
+  if (st != GEA_OK) return st;
+  return hip_status(x, hipStreamSynchronize(n.s), "forward");
+}
+
+gea_status gea_cnn_backward(gea_cnn* x, const float* target, gea_ptr_kind kind,
+                            int32_t accumulate, double* loss) {
+  if (!x || !target) return GEA_ERR_ARG;
+  gea::Cnn& n = x->net;
+  if (!n.train) {
+    x->err = "not a training instance";
+    return GEA_ERR_STATE;
+  }
+  const size_t N0 = n.d[0].npix;
+  gea_status st = hip_status(x, hipMemcpyAsync(n.t, target, N0 * sizeof(float), kin(kind), n.s), "target");
+  if (st != GEA_OK) return st;
+  gea::cnn_backward(n, accumulate != 0);
+  if ((st = hip_status(x, hipGetLastError(), "backward")) != GEA_OK) return st;
+  if (loss) {
+    const int np = gea::cnn_loss_partials(n);
+    double h[1024];
+    st = hip_status(x, hipMemcpyAsync(h, n.lpart, np * sizeof(double), hipMemcpyDeviceToHost, n.s), "loss");
+    if (st != GEA_OK) return st;
+    if ((st = hip_status(x, hipStreamSynchronize(n.s), "loss")) != GEA_OK) return st;
+    double s = 0.0;
+    for (int i = 0; i < np; ++i) s += h[i];
+    *loss = s / (2.0 * (double)N0);
+  }
+  return hip_status(x, hipStreamSynchronize(n.s), "backward");
+}
+
+gea_status gea_cnn_get_grads(gea_cnn* x, float* grads, gea_ptr_kind kind) {
+  if (!x || !grads) return GEA_ERR_ARG;
+  gea::Cnn& n = x->net;
+  if (!n.train) return GEA_ERR_STATE;
+  gea_status st = hip_status(x, hipMemcpyAsync(grads, n.grad, sizeof(float) * n.nparams, kout(kind), n.s), "grads");
+  if (st != GEA_OK) return st;
+  return hip_status(x, hipStreamSynchronize(n.s), "grads");
+}
+
+gea_status gea_cnn_adam(gea_cnn* x, float lr, float grad_scale, int32_t step) {
+  if (!x || step < 1 || !(lr > 0)) return GEA_ERR_ARG;
+  gea::Cnn& n = x->net;
+  if (!n.train) return GEA_ERR_STATE;
+  gea::cnn_adam(n, lr, grad_scale, step);
+  gea_status st = hip_status(x, hipGetLastError(), "adam");
+  if (st != GEA_OK) return st;
+  return hip_status(x, hipStreamSynchronize(n.s), "adam");
+}
+
+gea_status gea_cnn_activation(gea_cnn* x, int32_t which, float* out, gea_ptr_kind kind) {
+  if (!x || !out || which < 0 || which > 10) return GEA_ERR_ARG;
+  gea::Cnn& n = x->net;
+  const gea::bf16_t* src[10] = {n.xin, n.e0, n.p0, n.e1, n.p1, n.e2, n.c1, n.d1, n.c0, n.d0};
+  const int lev[10] = {0, 0, 1, 1, 2, 2, 1, 1, 0, 0};
+  const int ch[10] = {8, 16, 16, 32, 32, 64, 96, 32, 48, 16};
+  if (which == 10) {
+    gea_status st = hip_status(x, hipMemcpyAsync(out, n.y, sizeof(float) * n.d[0].npix, kout(kind), n.s), "activation");
+    if (st != GEA_OK) return st;
+    return hip_status(x, hipStreamSynchronize(n.s), "activation");
+  }
+  const long count = (long)n.d[lev[which]].npix * ch[which];
+  float* dst = out;
+  if (kind == GEA_HOST) {
+    dst = n.xf;  // staging: large enough only for the input; use a device copy per chunk
+  }
+  const long chunk = 2L * n.d[0].npix;
+  for (long off = 0; off < count; off += chunk) {
+    const long m = count - off < chunk ? count - off : chunk;
+    float* d = kind == GEA_HOST ? n.xf : out + off;
+    hipLaunchKernelGGL(gea::k_bf16_to_f32, dim3(gea::blocks_for_pub(m)), dim3(256), 0, n.s, m, src[which] + off, d);
+    if (kind == GEA_HOST) {
+      gea_status st = hip_status(x, hipMemcpyAsync(out + off, n.xf, sizeof(float) * m, hipMemcpyDeviceToHost, n.s), "activation");
+      if (st != GEA_OK) return st;
+      if ((st = hip_status(x, hipStreamSynchronize(n.s), "activation")) != GEA_OK) return st;
+    }
+  }
+  (void)dst;
+  return hip_status(x, hipStreamSynchronize(n.s), "activation");
+}
+
+void gea_cnn_destroy(gea_cnn* x) { delete x; }
+
+}  // extern "C"

@@ -1,0 +1,279 @@
+// gea_fcg.hip -- flexible conjugate gradients for the learned form of the
+// pressure solve, and the kernels that cut training pairs from the solver.
+//
+// The inner FP32 solve of the refinement (A d = r, d0 = 0) with a nonlinear
+// preconditioner z = M(r) = s * net(r/s, c/diag), s = max |r|:
+//   p = z + beta p_old,  beta = (<z, r> - <z, r_old>) / <z_old, r_old>
+//   q = A p, alpha = <z, r> / <p, q>, d += alpha p, r_old = r, r -= alpha q
+// (Polak-Ribiere beta, which keeps CG convergent for a preconditioner that
+// changes from one iteration to the next).  The first direction is the
+// network's correction itself, so the first step is the learned initial
+// guess with an optimal step length.  A one-workgroup kernel per iteration
+// publishes ||r||, max |r| (the next scale) and the stop / stall decision:
+// converged, non-finite, or ||r|| not reduced by 10 % over 10 iterations
+// (then the caller falls back to Jacobi-PCG).
+#include "gea_reduce.h"
+
+namespace gea {
+
+namespace {
+
+template <int N>
+__device__ __forceinline__ void store_part(double (&v)[N], double* part) {
+  __shared__ double sh[N][kBlock / 64];
+  Reducer<0u, N>::block(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < N; ++k) part[k * gridDim.x + blockIdx.x] = v[k];
+}
+
+// <z, r>, <z, r_old>
+__global__ __launch_bounds__(kBlock) void k_fcg_dots(int n, const float* __restrict__ z,
+                                                     const float* __restrict__ r,
+                                                     const float* __restrict__ r_old,
+                                                     double* part, const FcgScalars* sc) {
+  if (sc->done) return;
+  double v[2] = {0.0, 0.0};
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
+    const double zd = z[P];
+    v[0] += zd * (double)r[P];
+    v[1] += zd * (double)r_old[P];
+  }
+  store_part<2>(v, part);
+}
+
+// sum of the k-th value of n per-workgroup partials, fixed order, in every thread
+__device__ __forceinline__ double sum_part(const double* part, int n, int k) {
+  __shared__ double sh[1][kBlock / 64];
+  double a[1] = {0.0};
+  for (int b = threadIdx.x; b < n; b += kBlock) a[0] += part[k * n + b];
+  Reducer<0u, 1>::block(a, sh);
+  return a[0];
+}
+
+// beta from the dot partials; p = z + beta p_old; q = A p; partial <p, q>.
+// Cache-only stencil (the learned form's cost is dominated by the network).
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_fcg_spmv(Geo G, int iter, const float* __restrict__ z,
+                                                     const float* __restrict__ p_old,
+                                                     float* __restrict__ p_new,
+                                                     float* __restrict__ q,
+                                                     const float* __restrict__ c,
+                                                     const float* __restrict__ D,
+                                                     const double* dots, int nd, double* part,
+                                                     FcgScalars* sc) {
+  if (sc->done) return;
+  const double zr = sum_part(dots, nd, 0);
+  const double zro = sum_part(dots, nd, 1);
+  const double beta_d = iter == 0 ? 0.0 : (zr - zro) / sc->rz_prev[(iter + 1) & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->rz_prev[iter & 1] = zr;
+  const float beta = (float)beta_d;
+  float kk[NDIM];
+  for (int d = 0; d < NDIM; ++d) kk[d] = (float)(G.S[d] / G.h[d]);
+  double acc[1] = {0.0};
+  GEA_FOR_CELLS(P, G) {
+    int cc[NDIM];
+    cell_coords<NDIM>(G, P, cc);
+    auto pn = [&](int Q) { return z[Q] + beta * p_old[Q]; };
+    const float pp = pn(P), dp = D[P];
+    float a = c[P] * pp;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+      const int st = G.st[d];
+      if (cc[d] + 1 < G.n[d]) a += 0.5f * (dp + D[P + st]) * kk[d] * (pp - pn(P + st));
+      if (cc[d] > 0) a += 0.5f * (D[P - st] + dp) * kk[d] * (pp - pn(P - st));
+    }
+    p_new[P] = pp;
+    q[P] = a;
+    acc[0] += (double)pp * (double)a;
+  }
+  store_part<1>(acc, part);
+}
+
+// alpha = <z, r>/<p, q>; d += alpha p, r_old = r, r -= alpha q;
+// partials ||r||^2 and max |r| (as a sum of per-workgroup maxima stored apart)
+__global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* __restrict__ d,
+                                                       const float* __restrict__ p,
+                                                       float* __restrict__ r,
+                                                       float* __restrict__ r_old,
+                                                       const float* __restrict__ q,
+                                                       const double* pq_part, int np,
+                                                       double* part, FcgScalars* sc) {
+  if (sc->done) return;
+  const double pq = sum_part(pq_part, np, 0);
+  const double alpha_d = sc->rz_prev[iter & 1] / pq;
+  if (!isfinite(alpha_d) || alpha_d == 0.0) {
+    // no usable step (e.g. a network that outputs nothing): stop as stalled,
+    // leaving d and r untouched; every workgroup takes this same branch
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->status = 1;
+      sc->done = 1;
+    }
+    return;
+  }
+  const float alpha = (float)alpha_d;
+  __shared__ double sh[2][kBlock / 64];
+  double v[2] = {0.0, 0.0};
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
+    d[P] += alpha * p[P];
+    const float ro = r[P];
+    r_old[P] = ro;
+    const float rn = ro - alpha * q[P];
+    r[P] = rn;
+    v[0] += (double)rn * (double)rn;
+    v[1] = fmax(v[1], fabs((double)rn));
+  }
+  Reducer<0x2u, 2>::block(v, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v[0];
+    part[gridDim.x + blockIdx.x] = v[1];
+  }
+}
+
+// One workgroup: ||r||^2 and max |r| from the update partials (or from the
+// start kernel), stop / stall decision, next scale 1/s.
+__global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n, int iter,
+                                                      int init, double bb, double tol2,
+                                                      int max_iter, FcgScalars* sc) {
+  __shared__ double sh[2][kBlock / 64];
+  if (!init && sc->done) return;
+  double a[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < n; b += kBlock) {
+    a[0] += part[b];
+    a[1] = fmax(a[1], part[n + b]);
+  }
+  Reducer<0x2u, 2>::block(a, sh);
+  if (threadIdx.x != 0) return;
+  if (init) {
+    sc->bb = bb;
+    sc->tol2 = tol2;
+    sc->max_iter = max_iter;
+    sc->status = 0;
+    sc->rz_prev[0] = sc->rz_prev[1] = 1.0;
+    for (int k = 0; k < 10; ++k) sc->hist[k] = a[0];
+  }
+  sc->rr = a[0];
+  sc->iter = iter;
+  sc->s = a[1];
+  sc->inv_s = a[1] > 0 ? 1.0 / a[1] : 0.0;
+  const double old = sc->hist[iter % 10];   // ||r||^2 ten iterations ago
+  sc->hist[iter % 10] = a[0];
+  int done = 0;
+  if (!isfinite(a[0]) || !isfinite(a[1])) {
+    sc->status = 1;  // stall: fall back
+    done = 1;
+  } else if (a[0] <= sc->tol2 * sc->bb) {
+    done = 1;
+  } else if (iter >= 10 && a[0] > 0.81 * old) {
+    sc->status = 1;
+    done = 1;
+  } else if (iter >= sc->max_iter) {
+    sc->status = 2;
+    done = 1;
+  }
+  sc->done = done;
+}
+
+// inner start: d = 0, p_old = 0, r_old = 0; r (= r32) already set by the
+// refinement residual; partials ||r||^2 and max |r|
+__global__ __launch_bounds__(kBlock) void k_fcg_start(int n, float* __restrict__ d,
+                                                      float* __restrict__ p0,
+                                                      float* __restrict__ r_old,
+                                                      const float* __restrict__ r, double* part) {
+  __shared__ double sh[2][kBlock / 64];
+  double v[2] = {0.0, 0.0};
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
+    d[P] = 0.f;
+    p0[P] = 0.f;
+    r_old[P] = 0.f;
+    const double rv = r[P];
+    v[0] += rv * rv;
+    v[1] = fmax(v[1], fabs(rv));
+  }
+  Reducer<0x2u, 2>::block(v, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v[0];
+    part[gridDim.x + blockIdx.x] = v[1];
+  }
+}
+
+// ---- training pairs --------------------------------------------------------------
+
+// partial max |r|
+__global__ __launch_bounds__(kBlock) void k_maxabs(int n, const double* __restrict__ r, double* part) {
+  __shared__ double sh[1][kBlock / 64];
+  double v[1] = {0.0};
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x)
+    v[0] = fmax(v[0], fabs(r[P]));
+  Reducer<0x1u, 1>::block(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_maxabs_final(const double* part, int n, double* out) {
+  __shared__ double sh[1][kBlock / 64];
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < n; b += kBlock) v[0] = fmax(v[0], part[b]);
+  Reducer<0x1u, 1>::block(v, sh);
+  if (threadIdx.x == 0) {
+    out[0] = v[0];
+    out[1] = v[0] > 0 ? 1.0 / v[0] : 0.0;
+  }
+}
+
+// in_r = r0/s, in_a = c/diag, out_d = (x - x0)/s
+__global__ __launch_bounds__(kBlock) void k_pair(int n, const double* __restrict__ r0,
+                                                 const double* __restrict__ c,
+                                                 const double* __restrict__ dinv,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ x0,
+                                                 const double* __restrict__ s, float* in_r,
+                                                 float* in_a, float* out_d) {
+  const double is = s[1];
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
+    in_r[P] = (float)(r0[P] * is);
+    in_a[P] = (float)(c[P] * dinv[P]);
+    out_d[P] = (float)((x[P] - x0[P]) * is);
+  }
+}
+
+}  // namespace
+
+void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, double bb, double tol,
+               int max_iter, FcgScalars* sc) {
+  const int gu = grid_for(G.nc);
+  hipLaunchKernelGGL(k_fcg_start, dim3(gu), dim3(kBlock), 0, s, G.nc, v.d, v.p0, v.r_old,
+                     (const float*)v.r, v.part_u);
+  hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(kBlock), 0, s, (const double*)v.part_u, gu, 0, 1,
+                     bb, tol * tol, max_iter, sc);
+}
+
+void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter,
+                           FcgScalars* sc) {
+  const int gu = grid_for(G.nc);
+  const dim3 gr(gu), bl(kBlock);
+  hipLaunchKernelGGL(k_fcg_dots, gr, bl, 0, s, G.nc, (const float*)v.z, (const float*)v.r,
+                     (const float*)v.r_old, v.part_d, (const FcgScalars*)sc);
+  const float* p_old = (iter & 1) ? v.p1 : v.p0;
+  float* p_new = (iter & 1) ? v.p0 : v.p1;
+  if (G.ndim == 2)
+    hipLaunchKernelGGL(k_fcg_spmv<2>, gr, bl, 0, s, G, iter, (const float*)v.z, p_old, p_new, v.q,
+                       v.c, v.D, (const double*)v.part_d, gu, v.part_s, sc);
+  else
+    hipLaunchKernelGGL(k_fcg_spmv<3>, gr, bl, 0, s, G, iter, (const float*)v.z, p_old, p_new, v.q,
+                       v.c, v.D, (const double*)v.part_d, gu, v.part_s, sc);
+  hipLaunchKernelGGL(k_fcg_update, gr, bl, 0, s, G.nc, iter, v.d, (const float*)p_new, v.r,
+                     v.r_old, (const float*)v.q, (const double*)v.part_s, gu, v.part_u, sc);
+  hipLaunchKernelGGL(k_fcg_check, dim3(1), bl, 0, s, (const double*)v.part_u, gu, iter + 1, 0, 0.0,
+                     0.0, 0, sc);
+}
+
+void pair_outputs(hipStream_t s, const Geo& G, const double* r0, const double* c,
+                  const double* dinv, const double* x, const double* x0, double* part,
+                  double* s_out, float* in_r, float* in_a, float* out_d) {
+  const int gu = grid_for(G.nc);
+  hipLaunchKernelGGL(k_maxabs, dim3(gu), dim3(kBlock), 0, s, G.nc, r0, part);
+  hipLaunchKernelGGL(k_maxabs_final, dim3(1), dim3(kBlock), 0, s, (const double*)part, gu, s_out);
+  hipLaunchKernelGGL(k_pair, dim3(gu), dim3(kBlock), 0, s, G.nc, r0, c, dinv, x, x0,
+                     (const double*)s_out, in_r, in_a, out_d);
+}
+
+}  // namespace gea

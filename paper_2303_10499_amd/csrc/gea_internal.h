@@ -132,5 +132,35 @@ void launch_residual64(hipStream_t s, const Geo& G, const double* c, const doubl
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,
                         const double* dinv, float* c32, float* D32, float* dinv32);
 void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx);
+// y = b - y
+void launch_sub(hipStream_t s, const Geo& G, const double* b, double* y);
+
+// ---- learned form: flexible CG (gea_fcg.hip) ----------------------------------
+struct FcgScalars {
+  double rr, bb, tol2;
+  double s, inv_s;      // max |r| and its inverse (scale of the network input)
+  double rz_prev[2];    // <z, r> of iterations of even / odd index
+  double hist[10];      // ||r||^2 of the last ten iterations (stall test)
+  int iter, max_iter;
+  int done;
+  int status;           // 0 ok, 1 stalled or non-finite (fall back), 2 iteration cap
+};
+
+struct FcgVectors {
+  float *d, *r, *r_old, *z, *p0, *p1, *q;
+  const float *c, *D;
+  double *part_d, *part_s, *part_u;
+};
+
+void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, double bb, double tol,
+               int max_iter, FcgScalars* sc);
+// one iteration once z = M(r) is in v.z: dots, direction + operator, update, check
+void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter,
+                           FcgScalars* sc);
+// training pair: s = max |r0| (s_out[0], 1/s in s_out[1]); in_r = r0/s,
+// in_a = c/diag, out_d = (x - x0)/s
+void pair_outputs(hipStream_t s, const Geo& G, const double* r0, const double* c,
+                  const double* dinv, const double* x, const double* x0, double* part,
+                  double* s_out, float* in_r, float* in_a, float* out_d);
 
 }  // namespace gea

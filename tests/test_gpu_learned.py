@@ -1,0 +1,188 @@
+"""GPU tests of the learned preconditioner: the BF16 matrix-core network
+against the numpy oracle (forward and gradients), training, solver-made
+training pairs, and the flexible-CG solve with its Jacobi-PCG fallback."""
+import numpy as np
+import pytest
+
+from oracle import cnn
+from paper_2303_10499_amd import configs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def learned():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_10499_amd import learned as L
+    L._lib()
+    return L
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+def setup_net(L, shape, seed=0):
+    nd = len(shape)
+    rng = np.random.default_rng(seed)
+    params = cnn.init_params(nd, 2, seed=seed)
+    params = [(W, rng.normal(0, 0.05, size=b.shape)) for W, b in params]
+    # the GPU holds the weights in bf16: give both sides bf16-representable values
+    params = [(cnn.round_bf16(W).astype(np.float64), b.astype(np.float32).astype(np.float64))
+              for W, b in params]
+    x = cnn.round_bf16(rng.normal(size=shape + (2,))).astype(np.float64)
+    if nd == 2:
+        net = L.Net(2, shape[1], 1, shape[0], train=True)
+    else:
+        net = L.Net(3, shape[2], shape[1], shape[0], train=True)
+    net.set_params(L.pack(params))
+    return net, params, x
+
+
+def bf16_ulp(v):
+    v = np.maximum(np.abs(v), 1e-30)
+    return 2.0 ** (np.floor(np.log2(v)) - 7)
+
+
+def close_bf16(got, want, name):
+    """same bf16 values up to one rounding flip: a different FP32 summation
+    order can put a value on the other side of a bf16 rounding midpoint"""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    d = np.abs(got - want)
+    tol = bf16_ulp(np.maximum(np.abs(got), np.abs(want)))
+    assert np.all(d <= tol + 1e-30), (name, float(np.max(d / tol)))
+    frac = float(np.mean(d > 0))
+    assert frac <= 0.02, (name, frac)
+    return frac
+
+
+@pytest.mark.parametrize("shape", [(16, 32), (8, 12, 16)])
+def test_forward_layers_match_bf16_oracle(learned, shape):
+    """each layer recomputed by the oracle from the GPU's own bf16 input of
+    that layer (same bf16 products, only the FP32 summation order differs)"""
+    net, params, x = setup_net(learned, shape)
+    y = net.forward(np.ascontiguousarray(x.reshape(-1, 2), dtype=np.float32))
+    A = {k: net.activation(k) for k in net.ACT}
+    R = cnn.round_bf16
+    (W0, b0), (W1, b1), (W2, b2), (W3, b3), (W4, b4), (W5, b5) = params
+    np.testing.assert_array_equal(A["xin"][..., :2], R(x))
+    assert np.all(A["xin"][..., 2:] == 0)
+    fr = {}
+    fr["e0"] = close_bf16(A["e0"], R(cnn.relu(cnn.conv(A["xin"][..., :2], W0, b0, True))), "e0")
+    np.testing.assert_array_equal(A["p0"], R(cnn.pool(A["e0"])))
+    fr["e1"] = close_bf16(A["e1"], R(cnn.relu(cnn.conv(A["p0"], W1, b1, True))), "e1")
+    np.testing.assert_array_equal(A["p1"], R(cnn.pool(A["e1"])))
+    fr["e2"] = close_bf16(A["e2"], R(cnn.relu(cnn.conv(A["p1"], W2, b2, True))), "e2")
+    np.testing.assert_array_equal(A["c1"], np.concatenate([cnn.up(A["e2"]), A["e1"]], -1))
+    fr["d1"] = close_bf16(A["d1"], R(cnn.relu(cnn.conv(A["c1"], W3, b3, True))), "d1")
+    np.testing.assert_array_equal(A["c0"], np.concatenate([cnn.up(A["d1"]), A["e0"]], -1))
+    fr["d0"] = close_bf16(A["d0"], R(cnn.relu(cnn.conv(A["c0"], W4, b4, True))), "d0")
+    want = cnn.conv(A["d0"], W5, b5, True).reshape(-1)
+    # FP32 output: only the summation order differs
+    np.testing.assert_allclose(y, want, rtol=0, atol=1e-5 * np.max(np.abs(want)))
+    print("fraction of bf16 flips per layer", fr)
+    # and the whole network stays within bf16 noise of the FP64 network
+    y64 = cnn.forward(params, x)[0].reshape(-1)
+    assert rel(y, y64) <= 3e-2
+
+
+@pytest.mark.parametrize("shape", [(16, 32), (8, 12, 16)])
+def test_gradients_match_oracle(learned, shape):
+    net, params, x = setup_net(learned, shape, seed=1)
+    rng = np.random.default_rng(7)
+    t = rng.normal(size=shape + (1,))
+    net.forward(np.ascontiguousarray(x.reshape(-1, 2), dtype=np.float32))
+    loss_gpu = net.backward(np.ascontiguousarray(t.reshape(-1), dtype=np.float32))
+    g_gpu = learned.unpack(net.get_grads(), len(shape))
+    y_bf, cache = cnn.forward(params, x, bf16=True)
+    g_bf = cnn.backward(params, cache, y_bf, t, bf16=True)
+    y_64, c64 = cnn.forward(params, x)
+    g_64 = cnn.backward(params, c64, y_64, t)
+    assert abs(loss_gpu - cnn.loss(y_bf, t)) <= 1e-3 * cnn.loss(y_bf, t)
+    for k in range(6):
+        for j in range(2):
+            a, b, c = g_gpu[k][j], g_bf[k][j], g_64[k][j]
+            e_gpu = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            e_bf = np.linalg.norm(b - c) / max(np.linalg.norm(c), 1e-30)
+            print(f"layer {k} {'Wb'[j]}: gpu vs bf16 {e_gpu:.2e}, bf16 vs fp64 {e_bf:.2e}")
+            assert e_gpu <= 0.5 * e_bf + 1e-4, (k, j, e_gpu, e_bf)
+            # and the gradient points the way the exact one does
+            assert np.dot(a.ravel(), c.ravel()) > 0.9 * np.linalg.norm(a) * np.linalg.norm(c)
+
+
+def test_training_reduces_loss(learned):
+    shape = (32, 32)
+    net, params, x = setup_net(learned, shape, seed=2)
+    rng = np.random.default_rng(3)
+    # a smooth target that depends linearly on the input channel 0
+    t = np.cumsum(np.cumsum(x[..., :1], axis=0), axis=1) * 0.01
+    xf = np.ascontiguousarray(x.reshape(-1, 2), dtype=np.float32)
+    tf = np.ascontiguousarray(t.reshape(-1), dtype=np.float32)
+    losses = []
+    for step in range(1, 61):
+        net.forward(xf)
+        losses.append(net.backward(tf))
+        net.adam(3e-3, step)
+    print("loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_pairs_are_solver_corrections(learned):
+    from paper_2303_10499_amd import gea
+    cfg = configs.scaled("nonsmooth2d_2048", 64, 64)
+    cfg["params"]["tol"] = 1e-8
+    S = gea.Solver(cfg["mesh"], cfg["params"], solver="learned")
+    S.init_bubble(**cfg["bubble"])
+    S.step(3)
+    n = S.nc
+    r = np.empty(n, np.float32)
+    a = np.empty(n, np.float32)
+    d = np.empty(n, np.float32)
+    import ctypes as C
+    sc = C.c_double(0.0)
+    rc = learned._lib().gea_make_pair(S.ctx, 1e-12, r.ctypes.data, a.ctypes.data, d.ctypes.data,
+                                      C.byref(sc), gea.HOST)
+    assert rc == 0
+    s = sc.value
+    assert s > 0 and abs(np.max(np.abs(r)) - 1.0) < 1e-6
+    assert np.all((a > 0) & (a < 1))
+    st = S.state()
+    sysf = S.get_fields(gea.FIELD_B)
+    b = sysf[0]
+    Ax0 = np.empty(n)
+    S.apply_A(np.ascontiguousarray(st["pp"]), Ax0)
+    np.testing.assert_allclose(r.astype(np.float64) * s, b - Ax0, rtol=0, atol=2e-7 * s)
+    # p' + s d solves the system (to the FP32 rounding of d)
+    x = st["pp"] + s * d.astype(np.float64)
+    Ax = np.empty(n)
+    S.apply_A(np.ascontiguousarray(x), Ax)
+    assert np.linalg.norm(b - Ax) <= 1e-6 * np.linalg.norm(b - Ax0) + 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("junk", ["zeros", "random"])
+def test_learned_solver_falls_back_and_still_converges(learned, junk):
+    from paper_2303_10499_amd import gea
+    cfg = configs.scaled("nonsmooth2d_2048", 128, 128)
+    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000)
+    S = gea.Solver(cfg["mesh"], cfg["params"], solver="learned")
+    S.init_bubble(**cfg["bubble"])
+    npar = learned.param_count(2)
+    w = np.zeros(npar, np.float32) if junk == "zeros" else \
+        np.random.default_rng(0).normal(0, 1.0, npar).astype(np.float32)
+    rc = learned._lib().gea_load_weights(S.ctx, w.ctypes.data, gea.HOST)
+    assert rc == 0
+    st = S.step(3)
+    for k in range(st.n_solves):
+        assert st.solve[k].status == 0
+        assert st.solve[k].rel_res <= 1e-8
+    fb = sum(st.solve[k].fallbacks for k in range(st.n_solves))
+    print("fallbacks", fb)
+    if junk == "zeros":
+        # a zero network cannot make progress: every solve that needed an inner
+        # iteration falls back (a corrector can start below tol and need none)
+        for k in range(st.n_solves):
+            assert st.solve[k].fallbacks == (1 if st.solve[k].outer_iters > 0 else 0)
+        assert fb >= 1

@@ -108,7 +108,8 @@ def test_gradients_match_oracle(learned, shape):
             e_gpu = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
             e_bf = np.linalg.norm(b - c) / max(np.linalg.norm(c), 1e-30)
             print(f"layer {k} {'Wb'[j]}: gpu vs bf16 {e_gpu:.2e}, bf16 vs fp64 {e_bf:.2e}")
-            assert e_gpu <= 0.5 * e_bf + 1e-4, (k, j, e_gpu, e_bf)
+            # identical bf16 operands; only FP32 summation order differs
+            assert e_gpu <= 1e-5, (k, j, e_gpu, e_bf)
             # and the gradient points the way the exact one does
             assert np.dot(a.ravel(), c.ravel()) > 0.9 * np.linalg.norm(a) * np.linalg.norm(c)
 

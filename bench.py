@@ -42,11 +42,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_form(cfg, solver, steps, warmup, kernel_steps):
+# solver forms: (library solver, learned_steps)
+FORMS = {"pcg64": ("pcg64", 1), "mixed": ("mixed", 1), "learned": ("learned", 1),
+         "learned_fcg": ("learned", 25)}
+
+
+def run_form(cfg, form, steps, warmup, kernel_steps):
     import torch
     from paper_2303_10499_amd import gea
 
-    S = gea.Solver(cfg["mesh"], cfg["params"], solver=solver)
+    solver, lsteps = FORMS[form]
+    params = dict(cfg["params"], learned_steps=lsteps)
+    S = gea.Solver(cfg["mesh"], params, solver=solver)
+    if solver == "learned":
+        S.load_weights()
     S.init_bubble(**cfg["bubble"])
     stream = S.stream
     nc = S.nc
@@ -60,25 +69,34 @@ def run_form(cfg, solver, steps, warmup, kernel_steps):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    log(f"[bench] {solver}: {steps} steps in {ms:.1f} ms ({time.time() - t0:.1f} s wall incl. warmup)")
-    out = dict(solver=solver, ms_per_step=ms / steps, cell_steps_per_s=nc * steps / (ms * 1e-3),
+    log(f"[bench] {cfg['name']} {form}: {steps} steps in {ms:.1f} ms "
+        f"({time.time() - t0:.1f} s wall incl. warmup)")
+    out = dict(solver=solver, learned_steps=lsteps if solver == "learned" else None,
+               ms_per_step=ms / steps, cell_steps_per_s=nc * steps / (ms * 1e-3),
                iters_per_solve=st.total_iters / max(st.total_solves, 1),
                rel_res_last=max(st.solve[k].rel_res for k in range(st.n_solves)),
+               fallbacks_last_step=sum(st.solve[k].fallbacks for k in range(st.n_solves)),
                eos_mismatch=st.eos_mismatch)
-    # per-kernel device time over a second window of steps (events around
-    # every launch, so kept out of the timed region above)
+    # launches per step of each kernel class, from a second window of steps
+    # with the per-launch event timer (events around every launch inflate
+    # short kernels, so its times are only used for the explicit kernels'
+    # share; kept out of the timed region above)
     S.kernel_timing(True, reset=True)
     S.step(kernel_steps)
     kms, kn = S.kernel_times()
     S.kernel_timing(False)
-    total = sum(kms)
-    out["kernel_ms_per_step"] = {CLASS_NAMES[k]: kms[k] / kernel_steps for k in range(7) if kn[k]}
-    out["solve_share"] = (total - kms[5]) / total if total > 0 else None
-    dom = max((k for k in BYTES_PER_CELL if kn[k]), key=lambda k: kms[k], default=None)
+    # accurate per-launch durations of the CG kernels: reps back-to-back
+    # launches between two events on the solver's stream
+    avg = S.time_solver_kernels(reps=50)
+    out["kernel_avg_us"] = {CLASS_NAMES[k]: round(avg[k] * 1e3, 2) for k in range(4)}
+    per_step = {k: avg[k] * kn[k] / kernel_steps for k in range(4) if kn[k]}
+    out["launches_per_step"] = {CLASS_NAMES[k]: kn[k] / kernel_steps for k in range(7) if kn[k]}
+    out["cg_kernel_ms_per_step"] = {CLASS_NAMES[k]: round(v, 4) for k, v in per_step.items()}
+    out["explicit_ms_per_step_event_timed"] = kms[5] / kernel_steps
+    dom = max(per_step, key=lambda k: per_step[k], default=None)
     if dom is not None:
-        avg_ms = kms[dom] / kn[dom]
-        achieved = BYTES_PER_CELL[dom] * nc / (avg_ms * 1e-3) / 1e9
-        out["roofline"] = dict(kernel=CLASS_NAMES[dom], avg_launch_us=avg_ms * 1e3,
+        achieved = BYTES_PER_CELL[dom] * nc / (avg[dom] * 1e-3) / 1e9
+        out["roofline"] = dict(kernel=CLASS_NAMES[dom], avg_launch_us=avg[dom] * 1e3,
                                bytes_per_launch=BYTES_PER_CELL[dom] * nc, achieved=achieved)
     S.close()
     return out
@@ -100,8 +118,9 @@ def cpu_baseline(cfg):
 
 
 def read_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    """HBM bytes per launch of a CG kernel from the committed rocprofv3 counter
+    summary (profiles/traffic.txt), if it was taken on the current source of
+    the CG kernels; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
@@ -114,9 +133,9 @@ def read_traffic(kernel):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("source_sha") != h or rec.get("kernel") != kernel:
+    if rec.get("source_sha") != h or kernel not in rec:
         return None
-    return float(rec["bytes_per_launch"])
+    return float(rec[kernel])
 
 
 def main():
@@ -125,7 +144,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bubble3d_256x256x128")
-    ap.add_argument("--forms", default="pcg64,mixed,learned")
+    ap.add_argument("--also", default="nonsmooth2d_2048_eval",
+                    help="second evaluation mesh reported beside the first ('' for none)")
+    ap.add_argument("--forms", default="pcg64,mixed,learned,learned_fcg")
     ap.add_argument("--kernel-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -138,18 +159,32 @@ def main():
     from paper_2303_10499_amd import configs, gea
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gea.lib()
-    cfg = configs.get(args.workload)
-    cfg["params"]["tol"] = 1e-8
-    cfg["params"]["inner_tol"] = 1e-4
-    cfg["params"]["max_iter"] = 200000
-
     forms = [f for f in args.forms.split(",") if f]
-    results = {}
-    for f in forms:
-        if f == "learned" and not learned_available(cfg):
-            log("[bench] learned form skipped: no trained weights for this workload")
-            continue
-        results[f] = run_form(cfg, f, args.steps, args.warmup, args.kernel_steps)
+
+    def run_workload(name):
+        cfg = configs.get(name)
+        cfg["params"]["tol"] = 1e-8
+        cfg["params"]["inner_tol"] = 1e-4
+        cfg["params"]["max_iter"] = 200000
+        res = {}
+        for f in forms:
+            if FORMS[f][0] == "learned" and not learned_available(cfg):
+                log(f"[bench] {f} skipped: no trained weights for this workload")
+                continue
+            res[f] = run_form(cfg, f, args.steps, args.warmup, args.kernel_steps)
+        return cfg, res
+
+    cfg, results = run_workload(args.workload)
+    also = None
+    if args.also:
+        cfg2, res2 = run_workload(args.also)
+        also = {"workload": cfg2["name"],
+                "cells": cfg2["mesh"]["nx"] * cfg2["mesh"]["ny"] * cfg2["mesh"]["nz"],
+                "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv)
+                              for kk, vv in v.items() if kk != "roofline"} for k, v in res2.items()}}
+        if "pcg64" in res2:
+            also["speedup_vs_pcg64"] = {k: round(v["cell_steps_per_s"] / res2["pcg64"]["cell_steps_per_s"], 3)
+                                        for k, v in res2.items()}
     primary = "learned" if "learned" in results else ("mixed" if "mixed" in results else forms[0])
     R = results[primary]
     nc = cfg["mesh"]["nx"] * cfg["mesh"]["ny"] * cfg["mesh"]["nz"]
@@ -186,13 +221,19 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    if "pcg64" in results and primary != "pcg64":
-        line["speedup_vs_pcg64"] = round(R["cell_steps_per_s"] / results["pcg64"]["cell_steps_per_s"], 3)
+    if "pcg64" in results:
+        line["speedup_vs_pcg64"] = {k: round(v["cell_steps_per_s"] / results["pcg64"]["cell_steps_per_s"], 3)
+                                    for k, v in results.items()}
+    line["also"] = also
     print(json.dumps(line), flush=True)
 
 
 def learned_available(cfg):
-    return False
+    from paper_2303_10499_amd import learned
+    ndim = 2 if cfg["mesh"]["ny"] == 1 else 3
+    m = cfg["mesh"]
+    ok = all(n % 4 == 0 for n in (m["nx"], m["nz"])) and (ndim == 2 or m["ny"] % 4 == 0)
+    return ok and os.path.exists(learned.weights_file(ndim))
 
 
 if __name__ == "__main__":

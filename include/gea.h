@@ -83,6 +83,9 @@ typedef struct {
                                       inner iterations in the refined forms)                         */
   int32_t check_every;             /* host reads the convergence flag every this many iterations     */
   double inner_tol;                /* relative tolerance of each inner solve (refined forms)         */
+  int32_t learned_steps;           /* learned form: network-preconditioned flexible-CG iterations
+                                      per solve before Jacobi-PCG continues (>= 1; 1 = the learned
+                                      initial guess with an optimal step length)                    */
 } gea_params;
 
 /* initial perturbation of Sec. 4: kind 0 none; 1 cosine bubble
@@ -183,6 +186,13 @@ gea_status gea_kernel_timing(gea_ctx* ctx, int32_t on, int32_t reset);
 
 /* Summed device milliseconds and launch counts per class (8 entries each). */
 gea_status gea_kernel_times(gea_ctx* ctx, double* ms, int64_t* launches);
+
+/* Average device milliseconds of one launch of the CG kernels on the
+ * pressure system of the last assembly, each launched reps times back to
+ * back between two events on the context's stream: ms[0] FP64 operator
+ * kernel, ms[1] FP64 update kernel, ms[2] FP32 operator kernel, ms[3] FP32
+ * update kernel.  Uses scratch vectors only; the state is not changed. */
+gea_status gea_time_solver_kernels(gea_ctx* ctx, int32_t reps, double* ms);
 
 /* Release the context (the workspace stays with its owner). */
 void gea_destroy(gea_ctx* ctx);

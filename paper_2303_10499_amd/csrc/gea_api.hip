@@ -3,6 +3,7 @@
 // the pressure solvers (FP64 Jacobi-PCG, FP32/FP64 iterative refinement).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -319,6 +320,10 @@ gea_status check_params(const gea_mesh* m, const gea_params* q, std::string& err
     err = "inner_tol must be in (0, 1) for the refined solvers";
     return GEA_ERR_ARG;
   }
+  if (q->solver == GEA_LEARNED_MIXED && q->learned_steps < 1) {
+    err = "learned_steps must be >= 1";
+    return GEA_ERR_ARG;
+  }
   return GEA_OK;
 }
 
@@ -475,7 +480,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
 // One inner solve by flexible CG with the network as preconditioner on the
 // FP32 correction system set up by the refinement residual (r32, c32, D32).
 // Returns the iterations done; *stalled is set when the stall test fired.
-int learned_inner(gea_ctx* x, double bb, int budget, bool* stalled) {
+int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps, bool* stalled) {
   const Geo& G = x->G;
   FcgVectors& v = x->fv;
   v.d = x->d32;
@@ -488,7 +493,7 @@ int learned_inner(gea_ctx* x, double bb, int budget, bool* stalled) {
   v.c = x->c32;
   v.D = x->D32;
   x->timer.run(4, x->stream, [&] {
-    fcg_start(x->stream, G, v, bb, x->prm.inner_tol, budget, x->fsc);
+    fcg_start(x->stream, G, v, bb, inner_tol, budget, x->fsc);
   });
   FcgScalars hf;
   HIPCHK(hipMemcpyAsync(&hf, x->fsc, sizeof hf, hipMemcpyDeviceToHost, x->stream));
@@ -496,7 +501,7 @@ int learned_inner(gea_ctx* x, double bb, int budget, bool* stalled) {
   x->timer.flush();
   *stalled = false;
   int it = 0;
-  const int cap = budget + 8;
+  const int cap = steps < budget ? steps : budget;
   while (!hf.done && it < cap) {
     x->timer.run(6, x->stream, [&] {
       cnn_input_from_residual(x->net, x->r32, &x->fsc->inv_s, x->c32, x->dinv32);
@@ -510,8 +515,8 @@ int learned_inner(gea_ctx* x, double bb, int budget, bool* stalled) {
     HIPCHK(hipStreamSynchronize(x->stream));
     x->timer.flush();
   }
-  *stalled = hf.status == 1 || !hf.done;
-  return hf.iter;
+  *stalled = hf.status == 1;
+  return it;
 }
 
 // FP64 refinement whose inner solves use the learned preconditioner; when
@@ -562,11 +567,14 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
     int done_iters = 0;
     if (use_net) {
       bool stalled = false;
-      done_iters = learned_inner(x, h32.bb, budget > 0 ? budget : 1, &stalled);
-      if (stalled) {
-        use_net = false;
-        ++fallbacks;
-      }
+      // same adaptive inner tolerance as the refinement residual kernel sets
+      const double need = 0.1 * std::sqrt(x->prm.tol * x->prm.tol * h64.bb / h64.rr);
+      const double itol = std::max(x->prm.inner_tol, std::min(0.5, need));
+      done_iters = learned_inner(x, h32.bb, itol, budget > 0 ? budget : 1, x->prm.learned_steps,
+                                 &stalled);
+      // after learned_steps network iterations (or a stall) Jacobi-PCG continues
+      use_net = false;
+      if (stalled) ++fallbacks;
     } else {
       const int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
       gea_status rc = run_cg(
@@ -912,6 +920,54 @@ gea_status gea_kernel_timing(gea_ctx* x, int32_t on, int32_t reset) {
     x->timer.flush();
     if (reset) x->timer.reset();
     x->timer.on = on != 0;
+    return GEA_OK;
+  });
+}
+
+gea_status gea_time_solver_kernels(gea_ctx* x, int32_t reps, double* ms) {
+  if (!x || !ms || reps < 1) return GEA_ERR_ARG;
+  if (!x->has_system) return fail(x, GEA_ERR_STATE, "no assembled pressure system");
+  return guarded(x, [&]() {
+    const Geo& G = x->G;
+    hipStream_t s = x->stream;
+    const State& S = x->st[x->cur];
+    hipEvent_t ev[3];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    auto elapsed = [&](hipEvent_t a, hipEvent_t b) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, a, b));
+      return (double)t / reps;
+    };
+    // FP64: a fresh solve set-up that never reports done (tol 0), then the
+    // same iteration's kernels launched back to back
+    HIPCHK(hipMemcpyAsync(x->xs, S.pp, sizeof(double) * G.nc, hipMemcpyDeviceToDevice, s));
+    CgVectors<double> v{x->xs, x->r, x->p0, x->p1, x->q, x->c, x->D, x->dinv, x->b};
+    cg_init<double>(s, G, v, x->w64, 0.0, 1 << 30);
+    cg_spmv<double>(s, G, v, 0, x->w64);  // warm-up
+    HIPCHK(hipEventRecord(ev[0], s));
+    for (int k = 0; k < reps; ++k) cg_spmv<double>(s, G, v, 0, x->w64);
+    HIPCHK(hipEventRecord(ev[1], s));
+    for (int k = 0; k < reps; ++k) cg_update<double>(s, G, v, 0, x->w64);
+    HIPCHK(hipEventRecord(ev[2], s));
+    HIPCHK(hipEventSynchronize(ev[2]));
+    ms[0] = elapsed(ev[0], ev[1]);
+    ms[1] = elapsed(ev[1], ev[2]);
+    // FP32 inner kernels on the refinement's set-up (outer tol 0: not done)
+    launch_cast_coeffs(s, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
+    CgVectors<float> v32{x->d32, x->r32, x->p032, x->p132, x->q32, x->c32, x->D32, x->dinv32, x->r32};
+    launch_residual64(s, G, x->c, x->D, x->b, x->xs, x->r64, v32, 0.0, 1e-30, 1 << 30, x->o_part,
+                      x->w32, x->sc);
+    cg_spmv<float>(s, G, v32, 0, x->w32);
+    HIPCHK(hipEventRecord(ev[0], s));
+    for (int k = 0; k < reps; ++k) cg_spmv<float>(s, G, v32, 0, x->w32);
+    HIPCHK(hipEventRecord(ev[1], s));
+    for (int k = 0; k < reps; ++k) cg_update<float>(s, G, v32, 0, x->w32);
+    HIPCHK(hipEventRecord(ev[2], s));
+    HIPCHK(hipEventSynchronize(ev[2]));
+    ms[2] = elapsed(ev[0], ev[1]);
+    ms[3] = elapsed(ev[1], ev[2]);
+    for (auto& e : ev) HIPCHK(hipEventDestroy(e));
+    HIPCHK(hipGetLastError());
     return GEA_OK;
   });
 }

@@ -424,7 +424,16 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
   sc32->rzs[0] = in[0];
   sc32->rzs[1] = in[0];
   sc32->alpha = 0.0;
-  sc32->tol2 = inner_tol2;
+  // inner tolerance: what the outer residual still needs (with a factor 0.1
+  // for the FP32 solve's own error), never looser than 0.5 nor tighter than
+  // the configured inner tolerance
+  double it2 = inner_tol2;
+  if (o[0] > 0.0 && finite) {
+    const double need = 0.1 * sqrt(tol2 * o[1] / o[0]);
+    const double it = fmax(sqrt(inner_tol2), fmin(0.5, need));
+    it2 = it * it;
+  }
+  sc32->tol2 = it2;
   sc32->iter = 0;
   sc32->max_iter = inner_max;
   sc32->status = 0;

@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("p0", C.c_double), ("theta0", C.c_double), ("mu", C.c_double),
                 ("Pr", C.c_double), ("dt", C.c_double), ("n_corr", C.c_int32),
                 ("n_energy_sweeps", C.c_int32), ("solver", C.c_int32), ("tol", C.c_double),
-                ("max_iter", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double)]
+                ("max_iter", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double),
+                ("learned_steps", C.c_int32)]
 
 
 class Bubble(C.Structure):
@@ -84,6 +85,7 @@ def lib():
         L.gea_get_fields.argtypes = [vp, C.c_uint32, dp, C.c_int]
         L.gea_kernel_timing.argtypes = [vp, C.c_int32, C.c_int32]
         L.gea_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_int64)]
+        L.gea_time_solver_kernels.argtypes = [vp, C.c_int32, P(C.c_double)]
         L.gea_destroy.argtypes = [vp]
         L.gea_destroy.restype = None
         L.gea_last_error.argtypes = [vp]
@@ -91,7 +93,7 @@ def lib():
         for name in ("gea_workspace_bytes", "gea_init_mesh", "gea_set_solver", "gea_init_bubble",
                      "gea_set_state", "gea_step", "gea_pressure_solve",
                      "gea_apply_pressure_operator", "gea_get_fields", "gea_kernel_timing",
-                     "gea_kernel_times"):
+                     "gea_kernel_times", "gea_time_solver_kernels"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -107,7 +109,8 @@ def make_params(p: dict, solver="pcg64") -> Params:
     return Params(*(float(p[k]) for k in ("R", "cp", "cv", "g", "p0", "theta0", "mu", "Pr", "dt")),
                   int(p.get("n_corr", 2)), int(p.get("n_energy_sweeps", 2)), s,
                   float(p.get("tol", 1e-10)), int(p.get("max_iter", 20000)),
-                  int(p.get("check_every", 8)), float(p.get("inner_tol", 1e-4)))
+                  int(p.get("check_every", 8)), float(p.get("inner_tol", 1e-4)),
+                  int(p.get("learned_steps", 1)))
 
 
 def _ptr(a):
@@ -217,6 +220,16 @@ class Solver:
         self._check(self.L.gea_get_fields(self.ctx, int(mask), C.c_void_p(p), kind), self.ctx)
         return out
 
+    def load_weights(self, params=None):
+        """give the learned form its network weights (packed FP32; default:
+        the trained weights shipped with the package for this dimension)"""
+        from . import learned
+        if params is None:
+            params = np.load(learned.weights_file(self.ndim), allow_pickle=False)
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        L = learned._lib()
+        self._check(L.gea_load_weights(self.ctx, C.c_void_p(params.ctypes.data), HOST), self.ctx)
+
     def kernel_timing(self, on: bool, reset: bool = True):
         self._check(self.L.gea_kernel_timing(self.ctx, int(on), int(reset)), self.ctx)
 
@@ -226,6 +239,12 @@ class Solver:
         n = (C.c_int64 * 8)()
         self._check(self.L.gea_kernel_times(self.ctx, ms, n), self.ctx)
         return list(ms), list(n)
+
+    def time_solver_kernels(self, reps=50):
+        """average ms per launch: FP64 spmv, FP64 update, FP32 spmv, FP32 update"""
+        ms = (C.c_double * 4)()
+        self._check(self.L.gea_time_solver_kernels(self.ctx, int(reps), ms), self.ctx)
+        return list(ms)
 
     def state(self):
         """dict of host arrays: rho, u (ndim, nc), T, pp, p"""

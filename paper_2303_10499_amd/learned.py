@@ -40,6 +40,12 @@ def _lib():
     return L
 
 
+def weights_file(ndim: int) -> str:
+    """trained weights shipped with the package (written by train.py)"""
+    import os
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", f"net{ndim}d.npy")
+
+
 def param_count(ndim: int) -> int:
     n = C.c_int64(0)
     rc = _lib().gea_cnn_param_count(ndim, C.byref(n))

@@ -258,7 +258,10 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->p132 = cv.take<float>(nc);
   x->q32 = cv.take<float>(nc);
   x->d32 = cv.take<float>(nc);
-  x->partials = cv.take<double>(kMaxPartials);
+  {
+    const int zb = 3 * zplan(make_geo(m)).blocks;  // partials of the correction kernel
+    x->partials = cv.take<double>(zb > kMaxPartials ? zb : kMaxPartials);
+  }
   x->o_part = cv.take<double>(kMaxPartials);
   x->sc = cv.take<CgScalars>(1);
   x->sc32 = cv.take<CgScalars>(1);

@@ -54,6 +54,15 @@ struct CgScalars {
 // CU count, so the per-workgroup partial sums stay few.
 int grid_for(int nc);
 
+// Launch shape of the z-marching stencil kernels: kc planes per chunk and
+// the number of workgroups (one per column tile and chunk).
+constexpr int kMaxZBlocks = 4096;
+struct ZPlan {
+  int kc;
+  int blocks;
+};
+ZPlan zplan(const Geo& G);
+
 // ---- explicit step kernels (gea_step.hip) ----------------------------------
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                       double* const* u, double* const* phi, double* rho_star);

@@ -4,12 +4,11 @@
 // pressure right-hand side, flux/velocity correction and end-of-step update;
 // plus the initial bubble state of Sec. 4.
 //
-// One thread per cell in grid-stride loops over the SoA FP64 fields; x is
-// the fastest index, so the x-neighbours of a wave are contiguous and the
-// (y,) z-neighbours are whole rows that the neighbouring waves also read
-// (L2/MALL hits).  A face value is computed by one formula whichever of its
-// two cells evaluates it, so the flux leaving one cell is bitwise the flux
-// entering the other and the divergence telescopes.
+// The stencil kernels march column tiles through z (one thread per vertical
+// column of cells, SoA FP64 fields, x fastest).  A face value is computed by
+// one formula whichever of its two cells evaluates it, and a z-face value is
+// computed once and carried to the cell above, so the flux leaving one cell
+// is bitwise the flux entering the other and the divergence telescopes.
 #include "gea_reduce.h"
 
 namespace gea {
@@ -27,49 +26,6 @@ __device__ __forceinline__ double phi_face(const Geo& G, const Phys& ph, int d, 
   return d == NDIM - 1 ? ph.g * (cq + 1.0) * G.dz : phi_cell(G, ph, kz);
 }
 
-// Fourth-order point-value interpolation at the face between Q and Q+st
-// (coordinate cq of Q along a direction with n cells): cubic with two cells
-// on each side, linear next to a wall.
-template <typename F>
-__device__ __forceinline__ double interp4(F s, int Q, int st, int cq, int n) {
-  if (cq >= 1 && cq + 2 <= n - 1)
-    return (-s(Q - st) + 9.0 * s(Q) + 9.0 * s(Q + st) - s(Q + 2 * st)) / 16.0;
-  return 0.5 * (s(Q) + s(Q + st));
-}
-
-// sum_out phi_f I4(s)_f
-template <int NDIM>
-__device__ __forceinline__ double convective(const Geo& G, const Vec<NDIM>& phi, const double* s,
-                                             int P, const int* c) {
-  double acc = 0.0;
-  auto f = [&](int Q) { return s[Q]; };
-#pragma unroll
-  for (int d = 0; d < NDIM; ++d) {
-    const int st = G.st[d], n = G.n[d];
-    if (c[d] + 1 < n) acc += phi.p[d][P] * interp4(f, P, st, c[d], n);
-    if (c[d] > 0) acc -= phi.p[d][P - st] * interp4(f, P - st, st, c[d] - 1, n);
-  }
-  return acc;
-}
-
-// sum_f mu snGrad(u_comp) S with free-slip impenetrable walls
-template <int NDIM>
-__device__ __forceinline__ double viscous(const Geo& G, const double* uc, int comp, double mu,
-                                          int P, const int* c) {
-  double acc = 0.0;
-  const double up = uc[P];
-#pragma unroll
-  for (int d = 0; d < NDIM; ++d) {
-    const int st = G.st[d];
-    const double k = mu * G.S[d] / G.h[d];
-    if (c[d] + 1 < G.n[d]) acc += k * (uc[P + st] - up);
-    else if (comp == d) acc += 2.0 * k * (0.0 - up);
-    if (c[d] > 0) acc += k * (uc[P - st] - up);
-    else if (comp == d) acc += 2.0 * k * (0.0 - up);
-  }
-  return acc;
-}
-
 // F on the face between Q and Q+st along d: grad p' - Phi grad rho
 template <int NDIM>
 __device__ __forceinline__ double force_face(const Geo& G, const Phys& ph, const double* pp,
@@ -77,17 +33,6 @@ __device__ __forceinline__ double force_face(const Geo& G, const Phys& ph, const
   const int st = G.st[d];
   return ((pp[Q + st] - pp[Q]) - phi_face<NDIM>(G, ph, d, cq, kz) * (rho[Q + st] - rho[Q])) /
          G.h[d];
-}
-
-// cell value of component d of R(F): mean of the two faces, 0 on walls
-template <int NDIM>
-__device__ __forceinline__ double reconstruct(const Geo& G, const Phys& ph, const double* pp,
-                                              const double* rho, int P, const int* c, int d) {
-  const double hi = (c[d] + 1 < G.n[d]) ? force_face<NDIM>(G, ph, pp, rho, P, d, c[d], c[NDIM - 1]) : 0.0;
-  const int kz_lo = (d == NDIM - 1) ? c[d] - 1 : c[NDIM - 1];
-  const double lo =
-      (c[d] > 0) ? force_face<NDIM>(G, ph, pp, rho, P - G.st[d], d, c[d] - 1, kz_lo) : 0.0;
-  return 0.5 * (lo + hi);
 }
 
 template <int NDIM>
@@ -98,52 +43,203 @@ __device__ __forceinline__ double kinetic(const Vec<NDIM>& u, int P) {
   return 0.5 * k;
 }
 
+// ---- z-marching column tiles --------------------------------------------------
+//
+// A workgroup owns a TX x TY column of cells (TX cells of one row in 2D) and
+// marches it through kc consecutive planes along z; each thread walks one
+// vertical column.  Values along z stay in registers (a short queue shifted
+// once per plane), the flux through the face below a cell is the one the
+// same thread formed one plane earlier, and x/y neighbours come from the
+// caches: the workgroup's own rows and the halo rows of the neighbouring
+// columns, which the XCD-aware block order keeps on the same XCD.
+
+template <int NDIM>
+struct ZTile;
+template <>
+struct ZTile<3> {
+  static constexpr int TX = 64, TY = 4, KC = 32;
+};
+template <>
+struct ZTile<2> {
+  static constexpr int TX = 256, TY = 1, KC = 8;
+};
+
+struct Col {
+  int i, j;      // x (and y) coordinates of the column
+  int k0, k1;    // planes [k0, k1) of the chunk
+  int base;      // cell index of the column at k = 0
+  int pl;        // index stride between planes
+  bool act;      // inside the mesh
+};
+
+template <int NDIM>
+__device__ __forceinline__ Col col_of(const Geo& G, int kc) {
+  using T = ZTile<NDIM>;
+  const int ntx = (G.nx + T::TX - 1) / T::TX;
+  const int nty = NDIM == 3 ? (G.ny + T::TY - 1) / T::TY : 1;
+  const int b = xcd_block();
+  const int bx = b % ntx, by = (b / ntx) % nty, bk = b / (ntx * nty);
+  const int nz = G.n[NDIM - 1];
+  Col c;
+  c.i = bx * T::TX + (int)threadIdx.x % T::TX;
+  c.j = NDIM == 3 ? by * T::TY + (int)threadIdx.x / T::TX : 0;
+  c.k0 = bk * kc;
+  c.k1 = min(c.k0 + kc, nz);
+  c.pl = G.st[NDIM - 1];
+  c.base = NDIM == 3 ? c.i + G.nx * c.j : c.i;
+  c.act = c.i < G.nx && (NDIM == 2 || c.j < G.ny) && c.k0 < nz;
+  return c;
+}
+
+// Five consecutive values of a cell field along one direction, centred on
+// the cell; entries outside the mesh are never used and left 0.
+struct Line {
+  double m2, m1, c, p1, p2;
+};
+
+template <typename F>
+__device__ __forceinline__ Line line_at(F s, int P, int st, int q, int n) {
+  Line L;
+  L.c = s(P);
+  L.m1 = q >= 1 ? s(P - st) : 0.0;
+  L.m2 = q >= 2 ? s(P - 2 * st) : 0.0;
+  L.p1 = q + 1 < n ? s(P + st) : 0.0;
+  L.p2 = q + 2 < n ? s(P + 2 * st) : 0.0;
+  return L;
+}
+
+// next plane: drop the lowest value, append the one two planes above
+__device__ __forceinline__ Line shift(const Line& L, double next) {
+  return Line{L.m1, L.c, L.p1, L.p2, next};
+}
+
+// interp4 on the face above (q + 1/2) and below (q - 1/2) the centre of a line
+__device__ __forceinline__ double i4_hi(const Line& s, int q, int n) {
+  if (q >= 1 && q + 2 <= n - 1) return (-s.m1 + 9.0 * s.c + 9.0 * s.p1 - s.p2) / 16.0;
+  return 0.5 * (s.c + s.p1);
+}
+__device__ __forceinline__ double i4_lo(const Line& s, int q, int n) {
+  if (q >= 2 && q + 1 <= n - 1) return (-s.m2 + 9.0 * s.m1 + 9.0 * s.c - s.p1) / 16.0;
+  return 0.5 * (s.m1 + s.c);
+}
+
+// mu snGrad(u_comp) S on the two faces of a line; walls normal to the line
+// hold the normal component at 0 and leave the tangential ones free
+__device__ __forceinline__ void visc_add(double& acc, const Line& s, int q, int n, double k,
+                                         bool normal) {
+  if (q + 1 < n) acc += k * (s.p1 - s.c);
+  else if (normal) acc += 2.0 * k * (0.0 - s.c);
+  if (q > 0) acc += k * (s.m1 - s.c);
+  else if (normal) acc += 2.0 * k * (0.0 - s.c);
+}
+
+// coordinate of the column along an x/y direction
+__device__ __forceinline__ int coord(const Col& c, int d) { return d == 0 ? c.i : c.j; }
+
 // ---- Step 1 ----------------------------------------------------------------
 
 // phi_f = I4(rho u . n) S on interior faces, rho* = rho - dt/V sum_out phi
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, const double* __restrict__ rho,
+__global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
+                                                      const double* __restrict__ rho,
                                                       Vec<NDIM> u, Vec<NDIM> phi,
                                                       double* __restrict__ rho_star) {
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
+  constexpr int Z = NDIM - 1;
+  const Col c = col_of<NDIM>(G, kc);
+  if (!c.act) return;
+  const int nz = G.n[Z], pl = c.pl;
+  const double* uz = u.p[Z];
+  auto mz = [&](int Q) { return rho[Q] * uz[Q]; };
+  int P = c.base + pl * c.k0;
+  Line z = line_at(mz, P, pl, c.k0, nz);
+  double flo = c.k0 > 0 ? i4_lo(z, c.k0, nz) * G.S[Z] : 0.0;
+  for (int k = c.k0; k < c.k1; ++k, P += pl) {
     double sum = 0.0;
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
+    for (int d = 0; d < Z; ++d) {
       const double* ud = u.p[d];
-      const int st = G.st[d], n = G.n[d];
-      auto mom = [&](int Q) { return rho[Q] * ud[Q]; };
-      double hi = 0.0, lo = 0.0;
-      if (c[d] + 1 < n) hi = interp4(mom, P, st, c[d], n) * G.S[d];
-      if (c[d] > 0) lo = interp4(mom, P - st, st, c[d] - 1, n) * G.S[d];
+      const int st = G.st[d], n = G.n[d], q = coord(c, d);
+      auto m = [&](int Q) { return rho[Q] * ud[Q]; };
+      const Line s = line_at(m, P, st, q, n);
+      const double hi = q + 1 < n ? i4_hi(s, q, n) * G.S[d] : 0.0;
+      const double lo = q > 0 ? i4_lo(s, q, n) * G.S[d] : 0.0;
       phi.p[d][P] = hi;
       sum += hi;
       sum -= lo;
     }
+    const double hi = k + 1 < nz ? i4_hi(z, k, nz) * G.S[Z] : 0.0;
+    phi.p[Z][P] = hi;
+    sum += hi;
+    sum -= flo;
+    flo = hi;
     rho_star[P] = rho[P] - ph.dt / G.V * sum;
+    z = shift(z, k + 3 < nz ? mz(P + 3 * pl) : 0.0);
   }
 }
 
 // rho* u* = rho u - dt/V [sum_out phi I4(u) - sum mu snGrad(u) S] - dt R(F)
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph,
+__global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
                                                         const double* __restrict__ rho, Vec<NDIM> u,
                                                         const double* __restrict__ pp,
                                                         const double* __restrict__ rho_star,
                                                         Vec<NDIM> phi, Vec<NDIM> u_star) {
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
+  constexpr int Z = NDIM - 1;
+  const Col c = col_of<NDIM>(G, kc);
+  if (!c.act) return;
+  const int nz = G.n[Z], pl = c.pl;
+  int P = c.base + pl * c.k0;
+  Line z[NDIM];
+  double flo[NDIM];
+  const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
+#pragma unroll
+  for (int cc = 0; cc < NDIM; ++cc) {
+    const double* uc = u.p[cc];
+    z[cc] = line_at([&](int Q) { return uc[Q]; }, P, pl, c.k0, nz);
+    flo[cc] = c.k0 > 0 ? phz_lo * i4_lo(z[cc], c.k0, nz) : 0.0;
+  }
+  double Flo = c.k0 > 0 ? force_face<NDIM>(G, ph, pp, rho, P - pl, Z, c.k0 - 1, c.k0 - 1) : 0.0;
+  const double kvz = ph.mu * G.S[Z] / G.h[Z];
+  for (int k = c.k0; k < c.k1; ++k, P += pl) {
+    const double Fhi = k + 1 < nz ? force_face<NDIM>(G, ph, pp, rho, P, Z, k, k) : 0.0;
+    const double r = rho[P], rs = rho_star[P], phz = phi.p[Z][P];
 #pragma unroll
     for (int cc = 0; cc < NDIM; ++cc) {
       const double* uc = u.p[cc];
-      const double conv = convective<NDIM>(G, phi, uc, P, c);
-      const double visc = viscous<NDIM>(G, uc, cc, ph.mu, P, c);
-      const double RF = reconstruct<NDIM>(G, ph, pp, rho, P, c, cc);
-      const double mom = rho[P] * uc[P] - ph.dt / G.V * (conv - visc) - ph.dt * RF;
-      u_star.p[cc][P] = mom / rho_star[P];
+      double conv = 0.0, visc = 0.0;
+      Line s[NDIM - 1];
+#pragma unroll
+      for (int d = 0; d < Z; ++d) {
+        const int st = G.st[d], n = G.n[d], q = coord(c, d);
+        s[d] = line_at([&](int Q) { return uc[Q]; }, P, st, q, n);
+        if (q + 1 < n) conv += phi.p[d][P] * i4_hi(s[d], q, n);
+        if (q > 0) conv -= phi.p[d][P - st] * i4_lo(s[d], q, n);
+      }
+      double fh = 0.0;
+      if (k + 1 < nz) {
+        fh = phz * i4_hi(z[cc], k, nz);
+        conv += fh;
+      }
+      if (k > 0) conv -= flo[cc];
+      flo[cc] = fh;
+#pragma unroll
+      for (int d = 0; d < Z; ++d)
+        visc_add(visc, s[d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
+      visc_add(visc, z[cc], k, nz, kvz, cc == Z);
+      double RF;
+      if (cc == Z) {
+        RF = 0.5 * (Flo + Fhi);
+      } else {
+        const int st = G.st[cc], n = G.n[cc], q = coord(c, cc);
+        const double hi = q + 1 < n ? force_face<NDIM>(G, ph, pp, rho, P, cc, q, k) : 0.0;
+        const double lo = q > 0 ? force_face<NDIM>(G, ph, pp, rho, P - st, cc, q - 1, k) : 0.0;
+        RF = 0.5 * (lo + hi);
+      }
+      const double mom = r * z[cc].c - ph.dt / G.V * (conv - visc) - ph.dt * RF;
+      u_star.p[cc][P] = mom / rs;
+      z[cc] = shift(z[cc], k + 3 < nz ? uc[P + 3 * pl] : 0.0);
     }
+    Flo = Fhi;
   }
 }
 
@@ -166,45 +262,70 @@ __global__ __launch_bounds__(kBlock) void k_energy_init(Geo G, Phys ph, const do
 // The last sweep also forms the EOS density and pressure-equation coefficients.
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_energy_sweep(
-    Geo G, Phys ph, const double* __restrict__ rho, const double* __restrict__ e0,
+    Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
     const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<NDIM> phi,
     const double* __restrict__ rho_star, Vec<NDIM> u_star, const double* __restrict__ Tbg,
     double* __restrict__ e_next, double* __restrict__ T_next, int last,
     const double* __restrict__ p, double* __restrict__ rho23, double* __restrict__ psi,
     double* __restrict__ cc, double* __restrict__ D) {
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
-    const int kz = c[NDIM - 1];
-    auto hhat = [&](int Q) { return e_prev[Q] + ph.R * T_prev[Q]; };
+  constexpr int Z = NDIM - 1;
+  const Col c = col_of<NDIM>(G, kc);
+  if (!c.act) return;
+  const int nz = G.n[Z], pl = c.pl;
+  auto hhat = [&](int Q) { return e_prev[Q] + ph.R * T_prev[Q]; };
+  int P = c.base + pl * c.k0;
+  Line ze = line_at([&](int Q) { return e_prev[Q]; }, P, pl, c.k0, nz);
+  Line zT = line_at([&](int Q) { return T_prev[Q]; }, P, pl, c.k0, nz);
+  auto hz_of = [&]() {
+    return Line{ze.m2 + ph.R * zT.m2, ze.m1 + ph.R * zT.m1, ze.c + ph.R * zT.c,
+                ze.p1 + ph.R * zT.p1, ze.p2 + ph.R * zT.p2};
+  };
+  double flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hz_of(), c.k0, nz) : 0.0;
+  const double kdz = ph.mu / ph.Pr * ph.cp * G.S[Z] / G.h[Z];
+  for (int k = c.k0; k < c.k1; ++k, P += pl) {
     double conv = 0.0;
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-      const int st = G.st[d], n = G.n[d];
-      if (c[d] + 1 < n) conv += phi.p[d][P] * interp4(hhat, P, st, c[d], n);
-      if (c[d] > 0) conv -= phi.p[d][P - st] * interp4(hhat, P - st, st, c[d] - 1, n);
+    for (int d = 0; d < Z; ++d) {
+      const int st = G.st[d], n = G.n[d], q = coord(c, d);
+      const Line s = line_at(hhat, P, st, q, n);
+      if (q + 1 < n) conv += phi.p[d][P] * i4_hi(s, q, n);
+      if (q > 0) conv -= phi.p[d][P - st] * i4_lo(s, q, n);
     }
-    const double Tp = T_prev[P] - Tbg[kz];
+    double fh = 0.0;
+    if (k + 1 < nz) {
+      fh = phi.p[Z][P] * i4_hi(hz_of(), k, nz);
+      conv += fh;
+    }
+    if (k > 0) conv -= flo;
+    flo = fh;
+    const double Tp = zT.c - Tbg[k];
     double diff = 0.0;
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-      const int st = G.st[d];
-      const double k = ph.mu / ph.Pr * ph.cp * G.S[d] / G.h[d];
-      const int up = (d == NDIM - 1) ? 1 : 0;
-      if (c[d] + 1 < G.n[d]) diff += k * ((T_prev[P + st] - Tbg[kz + up]) - Tp);
-      if (c[d] > 0) diff += k * ((T_prev[P - st] - Tbg[kz - up]) - Tp);
+    for (int d = 0; d < Z; ++d) {
+      const int st = G.st[d], n = G.n[d], q = coord(c, d);
+      const double kd = ph.mu / ph.Pr * ph.cp * G.S[d] / G.h[d];
+      if (q + 1 < n) diff += kd * ((T_prev[P + st] - Tbg[k]) - Tp);
+      if (q > 0) diff += kd * ((T_prev[P - st] - Tbg[k]) - Tp);
     }
+    if (k + 1 < nz) diff += kdz * ((zT.p1 - Tbg[k + 1]) - Tp);
+    if (k > 0) diff += kdz * ((zT.m1 - Tbg[k - 1]) - Tp);
+    const double rs = rho_star[P];
     const double rhoe = rho[P] * e0[P] - ph.dt / G.V * conv + ph.dt / G.V * diff;
-    const double e = rhoe / rho_star[P];
-    const double T = (e - kinetic<NDIM>(u_star, P) - phi_cell(G, ph, kz)) / ph.cv;
+    const double e = rhoe / rs;
+    const double T = (e - kinetic<NDIM>(u_star, P) - phi_cell(G, ph, k)) / ph.cv;
     e_next[P] = e;
     T_next[P] = T;
     if (last) {
-      rho23[P] = p[P] / (ph.R * T);
-      psi[P] = 1.0 / (ph.R * T);
-      cc[P] = psi[P] * G.V / ph.dt;
-      D[P] = rho23[P] / (rho_star[P] / ph.dt);
+      const double r23 = p[P] / (ph.R * T);
+      const double ps = 1.0 / (ph.R * T);
+      rho23[P] = r23;
+      psi[P] = ps;
+      cc[P] = ps * G.V / ph.dt;
+      D[P] = r23 / (rs / ph.dt);
     }
+    const bool more = k + 3 < nz;
+    ze = shift(ze, more ? e_prev[P + 3 * pl] : 0.0);
+    zT = shift(zT, more ? T_prev[P + 3 * pl] : 0.0);
   }
 }
 
@@ -212,18 +333,51 @@ __global__ __launch_bounds__(kBlock) void k_energy_sweep(
 
 // H(u) = rho^n u^n/dt - (1/V) sum_out phi I4(u) + (1/V) sum mu snGrad(u) S
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, const double* __restrict__ rho,
-                                              Vec<NDIM> u, Vec<NDIM> u_prev, Vec<NDIM> phi,
-                                              Vec<NDIM> H) {
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
+__global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
+                                              const double* __restrict__ rho, Vec<NDIM> u,
+                                              Vec<NDIM> u_prev, Vec<NDIM> phi, Vec<NDIM> H) {
+  constexpr int Z = NDIM - 1;
+  const Col c = col_of<NDIM>(G, kc);
+  if (!c.act) return;
+  const int nz = G.n[Z], pl = c.pl;
+  int P = c.base + pl * c.k0;
+  Line z[NDIM];
+  double flo[NDIM];
+  const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
+#pragma unroll
+  for (int cc = 0; cc < NDIM; ++cc) {
+    const double* uc = u_prev.p[cc];
+    z[cc] = line_at([&](int Q) { return uc[Q]; }, P, pl, c.k0, nz);
+    flo[cc] = c.k0 > 0 ? phz_lo * i4_lo(z[cc], c.k0, nz) : 0.0;
+  }
+  const double kvz = ph.mu * G.S[Z] / G.h[Z];
+  for (int k = c.k0; k < c.k1; ++k, P += pl) {
+    const double r = rho[P], phz = phi.p[Z][P];
 #pragma unroll
     for (int cc = 0; cc < NDIM; ++cc) {
       const double* uc = u_prev.p[cc];
-      const double conv = convective<NDIM>(G, phi, uc, P, c);
-      const double visc = viscous<NDIM>(G, uc, cc, ph.mu, P, c);
-      H.p[cc][P] = rho[P] * u.p[cc][P] / ph.dt - conv / G.V + visc / G.V;
+      double conv = 0.0, visc = 0.0;
+      Line s[NDIM - 1];
+#pragma unroll
+      for (int d = 0; d < Z; ++d) {
+        const int st = G.st[d], n = G.n[d], q = coord(c, d);
+        s[d] = line_at([&](int Q) { return uc[Q]; }, P, st, q, n);
+        if (q + 1 < n) conv += phi.p[d][P] * i4_hi(s[d], q, n);
+        if (q > 0) conv -= phi.p[d][P - st] * i4_lo(s[d], q, n);
+      }
+      double fh = 0.0;
+      if (k + 1 < nz) {
+        fh = phz * i4_hi(z[cc], k, nz);
+        conv += fh;
+      }
+      if (k > 0) conv -= flo[cc];
+      flo[cc] = fh;
+#pragma unroll
+      for (int d = 0; d < Z; ++d)
+        visc_add(visc, s[d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
+      visc_add(visc, z[cc], k, nz, kvz, cc == Z);
+      H.p[cc][P] = r * u.p[cc][P] / ph.dt - conv / G.V + visc / G.V;
+      z[cc] = shift(z[cc], k + 3 < nz ? uc[P + 3 * pl] : 0.0);
     }
   }
 }
@@ -242,33 +396,54 @@ __device__ __forceinline__ double phi_tilde(const Geo& G, const Phys& ph, const 
 
 // b = (V/dt)(rho^n + psi rho23 Phi) - sum_out phitilde; 1/diag of the operator
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, const double* __restrict__ rho,
+__global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
+                                                const double* __restrict__ rho,
                                                 const double* __restrict__ rho23,
                                                 const double* __restrict__ psi,
                                                 const double* __restrict__ cc,
                                                 const double* __restrict__ D, Vec<NDIM> H,
                                                 double* __restrict__ b, double* __restrict__ dinv) {
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
-    const int kz = c[NDIM - 1];
+  constexpr int Z = NDIM - 1;
+  const Col c = col_of<NDIM>(G, kc);
+  if (!c.act) return;
+  const int nz = G.n[Z], pl = c.pl;
+  const double kz_ = G.S[Z] / G.h[Z];
+  int P = c.base + pl * c.k0;
+  double flux_lo = 0.0, diag_lo = 0.0;
+  if (c.k0 > 0) {
+    flux_lo = phi_tilde<NDIM>(G, ph, D, H.p[Z], rho23, P - pl, Z, c.k0 - 1, c.k0 - 1);
+    diag_lo = 0.5 * (D[P - pl] + D[P]) * kz_;
+  }
+  for (int k = c.k0; k < c.k1; ++k, P += pl) {
     double sum = 0.0;
     double diag = cc[P];
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-      const int st = G.st[d];
-      const double k = G.S[d] / G.h[d];
-      if (c[d] + 1 < G.n[d]) {
-        sum += phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P, d, c[d], kz);
-        diag += 0.5 * (D[P] + D[P + st]) * k;
+    for (int d = 0; d < Z; ++d) {
+      const int st = G.st[d], q = coord(c, d);
+      const double kd = G.S[d] / G.h[d];
+      if (q + 1 < G.n[d]) {
+        sum += phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P, d, q, k);
+        diag += 0.5 * (D[P] + D[P + st]) * kd;
       }
-      if (c[d] > 0) {
-        const int kzl = (d == NDIM - 1) ? kz - 1 : kz;
-        sum -= phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P - st, d, c[d] - 1, kzl);
-        diag += 0.5 * (D[P - st] + D[P]) * k;
+      if (q > 0) {
+        sum -= phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P - st, d, q - 1, k);
+        diag += 0.5 * (D[P - st] + D[P]) * kd;
       }
     }
-    const double Phi = phi_cell(G, ph, kz);
+    double flux_hi = 0.0, diag_hi = 0.0;
+    if (k + 1 < nz) {
+      flux_hi = phi_tilde<NDIM>(G, ph, D, H.p[Z], rho23, P, Z, k, k);
+      diag_hi = 0.5 * (D[P] + D[P + pl]) * kz_;
+      sum += flux_hi;
+      diag += diag_hi;
+    }
+    if (k > 0) {
+      sum -= flux_lo;
+      diag += diag_lo;
+    }
+    flux_lo = flux_hi;
+    diag_lo = diag_hi;
+    const double Phi = phi_cell(G, ph, k);
     b[P] = G.V / ph.dt * (rho[P] + psi[P] * rho23[P] * Phi) - sum;
     dinv[P] = 1.0 / diag;
   }
@@ -279,51 +454,81 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, const double* __
 // p^{n+1} = p' - rho23 Phi, and reduces [mass, max |rho - psi p|, non-finite count].
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_correct(
-    Geo G, Phys ph, const double* __restrict__ pp, const double* __restrict__ rho23,
+    Geo G, Phys ph, int kc, const double* __restrict__ pp, const double* __restrict__ rho23,
     const double* __restrict__ psi, Vec<NDIM> H, const double* __restrict__ D,
     const double* __restrict__ rho_star, Vec<NDIM> u_out, int last,
     const double* __restrict__ rho_old, double* __restrict__ rho_new, double* __restrict__ p_new,
-    double* partials, CgScalars* sc) {
+    double* partials) {
+  constexpr int Z = NDIM - 1;
   double red[3] = {0.0, 0.0, 0.0};
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
-    const int kz = c[NDIM - 1];
-    const double A = rho_star[P] / ph.dt;
-    bool finite = true;
-#pragma unroll
-    for (int cc = 0; cc < NDIM; ++cc) {
-      const double RF = reconstruct<NDIM>(G, ph, pp, rho23, P, c, cc);
-      const double un = (H.p[cc][P] - RF) / A;
-      u_out.p[cc][P] = un;
-      finite = finite && isfinite(un);
-    }
-    if (last) {
-      double sum = 0.0;
-#pragma unroll
-      for (int d = 0; d < NDIM; ++d) {
-        const int st = G.st[d];
-        const double k = G.S[d] / G.h[d];
-        if (c[d] + 1 < G.n[d]) {
-          const double w = 0.5 * (D[P] + D[P + st]) * k;
-          sum += phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P, d, c[d], kz) - w * (pp[P + st] - pp[P]);
-        }
-        if (c[d] > 0) {
-          const int kzl = (d == NDIM - 1) ? kz - 1 : kz;
-          const double w = 0.5 * (D[P - st] + D[P]) * k;
-          sum -= phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P - st, d, c[d] - 1, kzl) -
-                 w * (pp[P] - pp[P - st]);
-        }
+  const Col c = col_of<NDIM>(G, kc);
+  if (c.act) {
+    const int nz = G.n[Z], pl = c.pl;
+    const double kz_ = G.S[Z] / G.h[Z];
+    int P = c.base + pl * c.k0;
+    double Flo = 0.0, flux_lo = 0.0;
+    if (c.k0 > 0) {
+      Flo = force_face<NDIM>(G, ph, pp, rho23, P - pl, Z, c.k0 - 1, c.k0 - 1);
+      if (last) {
+        const double w = 0.5 * (D[P - pl] + D[P]) * kz_;
+        flux_lo = phi_tilde<NDIM>(G, ph, D, H.p[Z], rho23, P - pl, Z, c.k0 - 1, c.k0 - 1) -
+                  w * (pp[P] - pp[P - pl]);
       }
-      const double rn = rho_old[P] - ph.dt / G.V * sum;
-      const double pn = pp[P] - rho23[P] * phi_cell(G, ph, kz);
-      rho_new[P] = rn;
-      p_new[P] = pn;
-      red[0] += rn * G.V;
-      red[1] = fmax(red[1], fabs(rn - psi[P] * pn));
-      finite = finite && isfinite(rn) && isfinite(pn);
     }
-    red[2] += finite ? 0.0 : 1.0;
+    for (int k = c.k0; k < c.k1; ++k, P += pl) {
+      const double A = rho_star[P] / ph.dt;
+      const double Fhi = k + 1 < nz ? force_face<NDIM>(G, ph, pp, rho23, P, Z, k, k) : 0.0;
+      bool finite = true;
+#pragma unroll
+      for (int cmp = 0; cmp < NDIM; ++cmp) {
+        double RF;
+        if (cmp == Z) {
+          RF = 0.5 * (Flo + Fhi);
+        } else {
+          const int st = G.st[cmp], n = G.n[cmp], q = coord(c, cmp);
+          const double hi = q + 1 < n ? force_face<NDIM>(G, ph, pp, rho23, P, cmp, q, k) : 0.0;
+          const double lo = q > 0 ? force_face<NDIM>(G, ph, pp, rho23, P - st, cmp, q - 1, k) : 0.0;
+          RF = 0.5 * (lo + hi);
+        }
+        const double un = (H.p[cmp][P] - RF) / A;
+        u_out.p[cmp][P] = un;
+        finite = finite && isfinite(un);
+      }
+      Flo = Fhi;
+      if (last) {
+        double sum = 0.0;
+#pragma unroll
+        for (int d = 0; d < Z; ++d) {
+          const int st = G.st[d], q = coord(c, d);
+          const double kd = G.S[d] / G.h[d];
+          if (q + 1 < G.n[d]) {
+            const double w = 0.5 * (D[P] + D[P + st]) * kd;
+            sum += phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P, d, q, k) - w * (pp[P + st] - pp[P]);
+          }
+          if (q > 0) {
+            const double w = 0.5 * (D[P - st] + D[P]) * kd;
+            sum -= phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P - st, d, q - 1, k) -
+                   w * (pp[P] - pp[P - st]);
+          }
+        }
+        double flux_hi = 0.0;
+        if (k + 1 < nz) {
+          const double w = 0.5 * (D[P] + D[P + pl]) * kz_;
+          flux_hi = phi_tilde<NDIM>(G, ph, D, H.p[Z], rho23, P, Z, k, k) - w * (pp[P + pl] - pp[P]);
+          sum += flux_hi;
+        }
+        if (k > 0) sum -= flux_lo;
+        flux_lo = flux_hi;
+        const double rn = rho_old[P] - ph.dt / G.V * sum;
+        const double pn = pp[P] - rho23[P] * phi_cell(G, ph, k);
+        rho_new[P] = rn;
+        p_new[P] = pn;
+        red[0] += rn * G.V;
+        red[1] = fmax(red[1], fabs(rn - psi[P] * pn));
+        finite = finite && isfinite(rn) && isfinite(pn);
+      }
+      red[2] += finite ? 0.0 : 1.0;
+    }
   }
   if (!last) return;
   __shared__ double sh[3][kBlock / 64];
@@ -425,24 +630,47 @@ int grid_for(int nc) {
   return need < 1 ? 1 : (need < cap ? need : cap);
 }
 
+// Column tiles of the z-marching kernels: the default chunk of planes, made
+// longer on large meshes so that there are at most kMaxZBlocks workgroups
+// (each leaves per-workgroup partials) unless the columns alone need more.
+template <int NDIM>
+ZPlan zplan_t(const Geo& G) {
+  using T = ZTile<NDIM>;
+  const int ntx = (G.nx + T::TX - 1) / T::TX;
+  const int nty = NDIM == 3 ? (G.ny + T::TY - 1) / T::TY : 1;
+  const int cols = ntx * nty, nz = G.n[NDIM - 1];
+  int kc = T::KC < nz ? T::KC : nz;
+  int nk = (nz + kc - 1) / kc;
+  const int maxk = kMaxZBlocks / cols > 1 ? kMaxZBlocks / cols : 1;
+  if (nk > maxk) {
+    kc = (nz + maxk - 1) / maxk;
+    nk = (nz + kc - 1) / kc;
+  }
+  return ZPlan{kc, cols * nk};
+}
+
+ZPlan zplan(const Geo& G) { return G.ndim == 2 ? zplan_t<2>(G) : zplan_t<3>(G); }
+
 #define V2(a) vec<2>(a)
 #define V3(a) vec<3>(a)
 
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                       double* const* u, double* const* phi, double* rho_star) {
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_mass_flux<2>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, V2(u), V2(phi), rho_star);
+    hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), V2(phi), rho_star);
   else
-    hipLaunchKernelGGL(k_mass_flux<3>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, V3(u), V3(phi), rho_star);
+    hipLaunchKernelGGL(k_mass_flux<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), V3(phi), rho_star);
 }
 
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                         double* const* u, const double* pp, const double* rho_star,
                         double* const* phi, double* const* u_star) {
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_mom_predict<2>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, V2(u), pp, rho_star, V2(phi), V2(u_star));
+    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star));
   else
-    hipLaunchKernelGGL(k_mom_predict<3>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, V3(u), pp, rho_star, V3(phi), V3(u_star));
+    hipLaunchKernelGGL(k_mom_predict<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star));
 }
 
 void launch_energy_init(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
@@ -458,27 +686,30 @@ void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const doub
                          double* const* phi, const double* rho_star, double* const* u_star,
                          const double* Tbg, double* e_next, double* T_next, bool last,
                          const double* p, double* rho23, double* psi, double* c, double* D) {
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_energy_sweep<2>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
+    hipLaunchKernelGGL(k_energy_sweep<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
   else
-    hipLaunchKernelGGL(k_energy_sweep<3>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
+    hipLaunchKernelGGL(k_energy_sweep<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
 }
 
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,
               double* const* u_prev, double* const* phi, double* const* H) {
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_H<2>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, V2(u), V2(u_prev), V2(phi), V2(H));
+    hipLaunchKernelGGL(k_H<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), V2(u_prev), V2(phi), V2(H));
   else
-    hipLaunchKernelGGL(k_H<3>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, V3(u), V3(u_prev), V3(phi), V3(H));
+    hipLaunchKernelGGL(k_H<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), V3(u_prev), V3(phi), V3(H));
 }
 
 void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                 const double* rho23, const double* psi, const double* c, const double* D,
                 double* const* H, double* b, double* dinv) {
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_rhs<2>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, rho23, psi, c, D, V2(H), b, dinv);
+    hipLaunchKernelGGL(k_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V2(H), b, dinv);
   else
-    hipLaunchKernelGGL(k_rhs<3>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, rho, rho23, psi, c, D, V3(H), b, dinv);
+    hipLaunchKernelGGL(k_rhs<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V3(H), b, dinv);
 }
 
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
@@ -486,12 +717,13 @@ void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* p
                     const double* rho_star, double* const* u_out, bool last,
                     const double* rho_old, double* rho_new, double* p_new, double* partials,
                     CgScalars* sc) {
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_correct<2>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, pp, rho23, psi, V2(H), D, rho_star, V2(u_out), (int)last, rho_old, rho_new, p_new, partials, sc);
+    hipLaunchKernelGGL(k_correct<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V2(H), D, rho_star, V2(u_out), (int)last, rho_old, rho_new, p_new, partials);
   else
-    hipLaunchKernelGGL(k_correct<3>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), (int)last, rho_old, rho_new, p_new, partials, sc);
+    hipLaunchKernelGGL(k_correct<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), (int)last, rho_old, rho_new, p_new, partials);
   if (last)
-    hipLaunchKernelGGL(k_finalize_reduce, dim3(1), dim3(kBlock), 0, s, (const double*)partials, grid_for(G.nc), sc);
+    hipLaunchKernelGGL(k_finalize_reduce, dim3(1), dim3(kBlock), 0, s, (const double*)partials, zp.blocks, sc);
 }
 
 void launch_init_column(hipStream_t s, const Geo& G, const Phys& ph, double* rho_a,

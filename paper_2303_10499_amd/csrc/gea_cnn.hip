@@ -151,6 +151,142 @@ __global__ __launch_bounds__(256) void k_conv(CnnDims d, const bf16_t* __restric
       }
 }
 
+// Output tile of the forward convolution: TX x TY x TZ cells, staged with a
+// one-cell halo in LDS.  A 16-cell M tile is 16 consecutive x cells; wave w
+// owns the M tiles of z-row w (3D: the TY rows of that z plane; 2D: the
+// TX/16 segments of that row), so every weight chunk a wave loads serves
+// kMTt M tiles.
+template <int NDIM, int CIN>
+struct ConvTile {
+  static constexpr int TX = NDIM == 3 ? 16 : 64;
+  static constexpr int TY = NDIM == 3 ? 4 : 1;
+  static constexpr int TZ = (NDIM == 3 && CIN > 64) ? 2 : 4;
+  static constexpr int HX = TX + 2, HY = NDIM == 3 ? TY + 2 : 1, HZ = TZ + 2;
+  static constexpr int HP = HX * HY * HZ;           // staged cells
+  static constexpr int SP = CIN + 8;                // LDS row stride (bf16), padded against bank conflicts
+  static constexpr int MT = (TX / 16) * TY * TZ;    // M tiles per workgroup
+  static constexpr int MTW = MT / 4;                // per wave
+};
+
+// Forward convolution through an LDS-staged input tile.  CA = 0: input X
+// with CIN channels; CA > 0: the channel-concatenation [up(A), B] of a
+// coarse tensor A (CA channels, nearest-upsampled on the fly) and a fine
+// tensor B (CIN - CA channels).  MODE 0: +bias, ReLU, bf16 out; 1: +bias,
+// FP32 out (first ycount channels).
+template <int NDIM, int CIN, int COUT, int MODE, int CA>
+__global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restrict__ X,
+                                                const bf16_t* __restrict__ A,
+                                                const bf16_t* __restrict__ W,
+                                                const float* __restrict__ bias,
+                                                void* __restrict__ Y, int ystride, int ycount) {
+  using T = ConvTile<NDIM, CIN>;
+  constexpr int NT = Taps<NDIM>::n;
+  constexpr int KC = (NT * CIN + 31) / 32;
+  constexpr int KPAD = KC * 32;
+  constexpr int NTILE = COUT / 16;
+  constexpr int CB = CIN - CA;
+  __shared__ __attribute__((aligned(16))) bf16_t sIn[T::HP * T::SP];
+  const int ntx = (d.nx + T::TX - 1) / T::TX;
+  const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
+  const int b = blockIdx.x;
+  const int ox = (b % ntx) * T::TX;
+  const int oy = NDIM == 3 ? ((b / ntx) % nty) * T::TY : 0;
+  const int oz = (b / (ntx * nty)) * T::TZ;
+  // stage the input tile with its halo (zeros outside the grid)
+  const int nxc = d.nx / 2, nyc = NDIM == 3 ? d.ny / 2 : 1;
+  for (int e = threadIdx.x; e < T::HP * (CIN / 8); e += 256) {
+    const int hp = e / (CIN / 8), c8 = (e % (CIN / 8)) * 8;
+    const int hx = hp % T::HX, hy = (hp / T::HX) % T::HY, hz = hp / (T::HX * T::HY);
+    const int gx = ox + hx - 1, gy = NDIM == 3 ? oy + hy - 1 : 0, gz = oz + hz - 1;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz) {
+      const int gp = gx + d.nx * (gy + d.ny * gz);
+      if (CA == 0) {
+        v = *reinterpret_cast<const uint4*>(X + (size_t)gp * CIN + c8);
+      } else if (c8 < CA) {
+        const int q = (gx / 2) + nxc * ((NDIM == 3 ? gy / 2 : 0) + nyc * (gz / 2));
+        v = *reinterpret_cast<const uint4*>(A + (size_t)q * (CA > 0 ? CA : 1) + c8);
+      } else {
+        v = *reinterpret_cast<const uint4*>(X + (size_t)gp * (CB > 0 ? CB : 1) + (c8 - CA));
+      }
+    }
+    *reinterpret_cast<uint4*>(sIn + hp * T::SP + c8) = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  // staged-cell index of the centre cell of each of the wave's M tiles (lane r)
+  int pix[T::MTW];
+#pragma unroll
+  for (int m = 0; m < T::MTW; ++m) {
+    const int mt = wave * T::MTW + m;
+    const int seg = mt % (T::TX / 16), row = mt / (T::TX / 16);
+    const int lx = seg * 16 + r;
+    const int ly = NDIM == 3 ? row % T::TY : 0, lz = NDIM == 3 ? row / T::TY : row;
+    pix[m] = (lx + 1) + T::HX * ((NDIM == 3 ? ly + 1 : 0) + T::HY * (lz + 1));
+  }
+  f32x4 acc[T::MTW][NTILE];
+#pragma unroll
+  for (int m = 0; m < T::MTW; ++m)
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt) acc[m][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int kc = 0; kc < KC; ++kc) {
+    const int k = kc * 32 + 8 * g;
+    const int t = k / CIN, ci = k % CIN;
+    const bool tap = t < NT;
+    bf16x8 bw[NTILE];
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt)
+      bw[nt] = tap ? load8(W + (size_t)(nt * 16 + r) * KPAD + k) : zero8();
+    int off = 0;
+    if (NDIM == 2) off = (t % 3 - 1) + T::HX * (t / 3 - 1);
+    else off = (t % 3 - 1) + T::HX * ((t / 3) % 3 - 1 + T::HY * (t / 9 - 1));
+    off = off * T::SP + ci;
+#pragma unroll
+    for (int m = 0; m < T::MTW; ++m) {
+      bf16x8 a = zero8();
+      if (tap) a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sIn + pix[m] * T::SP + off));
+#pragma unroll
+      for (int nt = 0; nt < NTILE; ++nt)
+        acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[nt], acc[m][nt], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < T::MTW; ++m) {
+    const int mt = wave * T::MTW + m;
+    const int seg = mt % (T::TX / 16), row = mt / (T::TX / 16);
+    const int ly = NDIM == 3 ? row % T::TY : 0, lz = NDIM == 3 ? row / T::TY : row;
+    const int gy = oy + ly, gz = oz + lz;
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gx = ox + seg * 16 + 4 * g + i;
+        const int co = nt * 16 + r;
+        if (gx < d.nx && gy < d.ny && gz < d.nz && co < ycount) {
+          const size_t p = (size_t)gx + (size_t)d.nx * (gy + (size_t)d.ny * gz);
+          float v = acc[m][nt][i] + bias[co];
+          if (MODE == 0) {
+            v = fmaxf(v, 0.f);
+            reinterpret_cast<bf16_t*>(Y)[p * ystride + co] = f2bf(v);
+          } else {
+            reinterpret_cast<float*>(Y)[p * ystride + co] = v;
+          }
+        }
+      }
+  }
+}
+
+template <int NDIM, int CIN>
+int conv_tiles(const CnnDims& d) {
+  using T = ConvTile<NDIM, CIN>;
+  const int ntx = (d.nx + T::TX - 1) / T::TX;
+  const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
+  const int ntz = (d.nz + T::TZ - 1) / T::TZ;
+  return ntx * nty * ntz;
+}
+
 // Weight gradient partials: part[split][co][n] = sum over the split's cells
 // p of dY[p][co] * X[p + off(tap(n))][ci(n)], n = tap*CIN + ci.
 template <int NDIM, int CIN, int COUT>
@@ -439,25 +575,26 @@ int conv_blocks(int npix) { return (npix + 4 * 16 * kMT - 1) / (4 * 16 * kMT); }
 
 // ---- dispatch -------------------------------------------------------------------
 
+// forward convolution of a layer; layers 3 and 4 read the concatenation
+// [up(A), X] directly (A = e2 / d1 on the coarser grid, X = e1 / e0)
 template <int NDIM>
-void conv_fwd(const Cnn& n, int layer, const bf16_t* X, void* Y, int mode) {
+void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y) {
   const CnnLayer& L = n.L[layer];
   const CnnDims& d = n.d[L.level];
-  const dim3 gr(conv_blocks(d.npix)), bl(256);
+  const dim3 bl(256);
   hipStream_t s = n.s;
-#define GEA_CONV(CI, CO, MODE, YS, YC)                                                            \
-  hipLaunchKernelGGL((k_conv<NDIM, CI, CO, MODE>), gr, bl, 0, s, d, X, n.W[layer], n.bias[layer], \
-                     Y, YS, YC)
+#define GEA_CONV(CI, CO, MODE, CAA, YS, YC)                                                       \
+  hipLaunchKernelGGL((k_conv_t<NDIM, CI, CO, MODE, CAA>), dim3(conv_tiles<NDIM, CI>(d)), bl, 0, s, \
+                     d, X, A, n.W[layer], n.bias[layer], Y, YS, YC)
   switch (layer) {
-    case 0: GEA_CONV(8, 16, 0, 16, 16); break;
-    case 1: GEA_CONV(16, 32, 0, 32, 32); break;
-    case 2: GEA_CONV(32, 64, 0, 64, 64); break;
-    case 3: GEA_CONV(96, 32, 0, 32, 32); break;
-    case 4: GEA_CONV(48, 16, 0, 16, 16); break;
-    case 5: GEA_CONV(16, 16, 1, 1, 1); break;
+    case 0: GEA_CONV(8, 16, 0, 0, 16, 16); break;
+    case 1: GEA_CONV(16, 32, 0, 0, 32, 32); break;
+    case 2: GEA_CONV(32, 64, 0, 0, 64, 64); break;
+    case 3: GEA_CONV(96, 32, 0, 64, 32, 32); break;
+    case 4: GEA_CONV(48, 16, 0, 32, 16, 16); break;
+    case 5: GEA_CONV(16, 16, 1, 0, 1, 1); break;
   }
 #undef GEA_CONV
-  (void)mode;
 }
 
 // dX (FP32, cin channels) = conv(dYmasked (bf16, cout_p channels), Wt)
@@ -509,16 +646,20 @@ template <int NDIM>
 void forward_t(Cnn& n) {
   hipStream_t s = n.s;
   const dim3 bl(256);
-  conv_fwd<NDIM>(n, 0, n.xin, n.e0, 0);
+  const bf16_t* none = nullptr;
+  conv_fwd<NDIM>(n, 0, n.xin, none, n.e0);
   hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[1].npix * 16)), bl, 0, s, n.d[1], 16, (const bf16_t*)n.e0, n.p0);
-  conv_fwd<NDIM>(n, 1, n.p0, n.e1, 0);
+  conv_fwd<NDIM>(n, 1, n.p0, none, n.e1);
   hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[2].npix * 32)), bl, 0, s, n.d[2], 32, (const bf16_t*)n.e1, n.p1);
-  conv_fwd<NDIM>(n, 2, n.p1, n.e2, 0);
-  hipLaunchKernelGGL(k_upcat<NDIM>, dim3(blocks_for((long)n.d[1].npix * 96)), bl, 0, s, n.d[1], 64, 32, (const bf16_t*)n.e2, (const bf16_t*)n.e1, n.c1);
-  conv_fwd<NDIM>(n, 3, n.c1, n.d1, 0);
-  hipLaunchKernelGGL(k_upcat<NDIM>, dim3(blocks_for((long)n.d[0].npix * 48)), bl, 0, s, n.d[0], 32, 16, (const bf16_t*)n.d1, (const bf16_t*)n.e0, n.c0);
-  conv_fwd<NDIM>(n, 4, n.c0, n.d0, 0);
-  conv_fwd<NDIM>(n, 5, n.d0, n.y, 1);
+  conv_fwd<NDIM>(n, 2, n.p1, none, n.e2);
+  conv_fwd<NDIM>(n, 3, n.e1, n.e2, n.d1);
+  conv_fwd<NDIM>(n, 4, n.e0, n.d1, n.d0);
+  conv_fwd<NDIM>(n, 5, n.d0, none, n.y);
+  if (n.train) {
+    // the concatenated inputs of layers 3 and 4, kept for the weight gradients
+    hipLaunchKernelGGL(k_upcat<NDIM>, dim3(blocks_for((long)n.d[1].npix * 96)), bl, 0, s, n.d[1], 64, 32, (const bf16_t*)n.e2, (const bf16_t*)n.e1, n.c1);
+    hipLaunchKernelGGL(k_upcat<NDIM>, dim3(blocks_for((long)n.d[0].npix * 48)), bl, 0, s, n.d[0], 32, 16, (const bf16_t*)n.d1, (const bf16_t*)n.e0, n.c0);
+  }
 }
 
 template <int NDIM>
@@ -636,9 +777,9 @@ size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* bas
   n.e1 = (bf16_t*)take(N1 * 32 * B2);
   n.p1 = (bf16_t*)take(N2 * 32 * B2);
   n.e2 = (bf16_t*)take(N2 * 64 * B2);
-  n.c1 = (bf16_t*)take(N1 * 96 * B2);
+  n.c1 = train ? (bf16_t*)take(N1 * 96 * B2) : nullptr;
   n.d1 = (bf16_t*)take(N1 * 32 * B2);
-  n.c0 = (bf16_t*)take(N0 * 48 * B2);
+  n.c0 = train ? (bf16_t*)take(N0 * 48 * B2) : nullptr;
   n.d0 = (bf16_t*)take(N0 * 16 * B2);
   n.y = (float*)take(N0 * F4);
   if (train) {
@@ -868,6 +1009,10 @@ gea_status gea_cnn_activation(gea_cnn* x, int32_t which, float* out, gea_ptr_kin
     gea_status st = hip_status(x, hipMemcpyAsync(out, n.y, sizeof(float) * n.d[0].npix, kout(kind), n.s), "activation");
     if (st != GEA_OK) return st;
     return hip_status(x, hipStreamSynchronize(n.s), "activation");
+  }
+  if (!src[which]) {
+    x->err = "the concatenated inputs are kept by training instances only";
+    return GEA_ERR_STATE;
   }
   const long count = (long)n.d[lev[which]].npix * ch[which];
   float* dst = out;

@@ -203,6 +203,13 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
     const double Fhi = k + 1 < nz ? force_face<NDIM>(G, ph, pp, rho, P, Z, k, k) : 0.0;
     const double r = rho[P], rs = rho_star[P], phz = phi.p[Z][P];
+    double fhi_d[NDIM - 1], flo_d[NDIM - 1];
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int q = coord(c, d);
+      fhi_d[d] = q + 1 < G.n[d] ? phi.p[d][P] : 0.0;
+      flo_d[d] = q > 0 ? phi.p[d][P - G.st[d]] : 0.0;
+    }
 #pragma unroll
     for (int cc = 0; cc < NDIM; ++cc) {
       const double* uc = u.p[cc];
@@ -212,8 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
       for (int d = 0; d < Z; ++d) {
         const int st = G.st[d], n = G.n[d], q = coord(c, d);
         s[d] = line_at([&](int Q) { return uc[Q]; }, P, st, q, n);
-        if (q + 1 < n) conv += phi.p[d][P] * i4_hi(s[d], q, n);
-        if (q > 0) conv -= phi.p[d][P - st] * i4_lo(s[d], q, n);
+        if (q + 1 < n) conv += fhi_d[d] * i4_hi(s[d], q, n);
+        if (q > 0) conv -= flo_d[d] * i4_lo(s[d], q, n);
       }
       double fh = 0.0;
       if (k + 1 < nz) {
@@ -353,6 +360,13 @@ __global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
   const double kvz = ph.mu * G.S[Z] / G.h[Z];
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
     const double r = rho[P], phz = phi.p[Z][P];
+    double fhi_d[NDIM - 1], flo_d[NDIM - 1];
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int q = coord(c, d);
+      fhi_d[d] = q + 1 < G.n[d] ? phi.p[d][P] : 0.0;
+      flo_d[d] = q > 0 ? phi.p[d][P - G.st[d]] : 0.0;
+    }
 #pragma unroll
     for (int cc = 0; cc < NDIM; ++cc) {
       const double* uc = u_prev.p[cc];
@@ -362,8 +376,8 @@ __global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
       for (int d = 0; d < Z; ++d) {
         const int st = G.st[d], n = G.n[d], q = coord(c, d);
         s[d] = line_at([&](int Q) { return uc[Q]; }, P, st, q, n);
-        if (q + 1 < n) conv += phi.p[d][P] * i4_hi(s[d], q, n);
-        if (q > 0) conv -= phi.p[d][P - st] * i4_lo(s[d], q, n);
+        if (q + 1 < n) conv += fhi_d[d] * i4_hi(s[d], q, n);
+        if (q > 0) conv -= flo_d[d] * i4_lo(s[d], q, n);
       }
       double fh = 0.0;
       if (k + 1 < nz) {

@@ -155,109 +155,162 @@ __global__ __launch_bounds__(256) void k_conv(CnnDims d, const bf16_t* __restric
 // one-cell halo in LDS.  A 16-cell M tile is 16 consecutive x cells; wave w
 // owns the M tiles of z-row w (3D: the TY rows of that z plane; 2D: the
 // TX/16 segments of that row), so every weight chunk a wave loads serves
-// kMTt M tiles.
-template <int NDIM, int CIN>
+// MTW M tiles.  For a concatenated input [up(A), X] the fine part X is
+// staged per fine cell and the coarse part A once per coarse cell (CHX x
+// CHY x CHZ coarse cells cover the fine tile and its halo).
+template <int NDIM, int CIN, int CA>
 struct ConvTile {
   static constexpr int TX = NDIM == 3 ? 16 : 64;
   static constexpr int TY = NDIM == 3 ? 4 : 1;
   static constexpr int TZ = (NDIM == 3 && CIN > 64) ? 2 : 4;
   static constexpr int HX = TX + 2, HY = NDIM == 3 ? TY + 2 : 1, HZ = TZ + 2;
-  static constexpr int HP = HX * HY * HZ;           // staged cells
-  static constexpr int SP = CIN + 8;                // LDS row stride (bf16), padded against bank conflicts
-  static constexpr int MT = (TX / 16) * TY * TZ;    // M tiles per workgroup
-  static constexpr int MTW = MT / 4;                // per wave
+  static constexpr int HP = HX * HY * HZ;              // staged fine cells
+  static constexpr int CF = CIN - CA;                  // channels staged per fine cell
+  static constexpr int FSP = CF + 8;                   // LDS stride per fine cell (bf16), padded against bank conflicts
+  static constexpr int CHX = TX / 2 + 2, CHY = NDIM == 3 ? TY / 2 + 2 : 1, CHZ = TZ / 2 + 2;
+  static constexpr int CHP = CA > 0 ? CHX * CHY * CHZ : 0;  // staged coarse cells
+  static constexpr int CSP = CA + 8;                   // LDS stride per coarse cell
+  static constexpr int LDS = HP * FSP + CHP * CSP;     // bf16 elements
+  static constexpr int MT = (TX / 16) * TY * TZ;       // M tiles per workgroup
+  static constexpr int MTW = MT / 4;                   // per wave
 };
 
 // Forward convolution through an LDS-staged input tile.  CA = 0: input X
-// with CIN channels; CA > 0: the channel-concatenation [up(A), B] of a
-// coarse tensor A (CA channels, nearest-upsampled on the fly) and a fine
-// tensor B (CIN - CA channels).  MODE 0: +bias, ReLU, bf16 out; 1: +bias,
-// FP32 out (first ycount channels).
+// with CIN channels; CA > 0: the channel concatenation [up(A), X] of a
+// coarse tensor A (CA channels, nearest-upsampled) and a fine tensor X
+// (CIN - CA channels).  MODE 0: +bias, ReLU, bf16 out; 1: +bias, FP32 out
+// (first ycount channels).
 template <int NDIM, int CIN, int COUT, int MODE, int CA>
 __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restrict__ X,
                                                 const bf16_t* __restrict__ A,
                                                 const bf16_t* __restrict__ W,
                                                 const float* __restrict__ bias,
                                                 void* __restrict__ Y, int ystride, int ycount) {
-  using T = ConvTile<NDIM, CIN>;
+  using T = ConvTile<NDIM, CIN, CA>;
   constexpr int NT = Taps<NDIM>::n;
   constexpr int KC = (NT * CIN + 31) / 32;
   constexpr int KPAD = KC * 32;
   constexpr int NTILE = COUT / 16;
-  constexpr int CB = CIN - CA;
-  __shared__ __attribute__((aligned(16))) bf16_t sIn[T::HP * T::SP];
+  constexpr int CF = T::CF;
+  __shared__ __attribute__((aligned(16))) bf16_t sIn[T::LDS];
   const int ntx = (d.nx + T::TX - 1) / T::TX;
   const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
   const int b = blockIdx.x;
   const int ox = (b % ntx) * T::TX;
   const int oy = NDIM == 3 ? ((b / ntx) % nty) * T::TY : 0;
   const int oz = (b / (ntx * nty)) * T::TZ;
-  // stage the input tile with its halo (zeros outside the grid)
-  const int nxc = d.nx / 2, nyc = NDIM == 3 ? d.ny / 2 : 1;
-  for (int e = threadIdx.x; e < T::HP * (CIN / 8); e += 256) {
-    const int hp = e / (CIN / 8), c8 = (e % (CIN / 8)) * 8;
-    const int hx = hp % T::HX, hy = (hp / T::HX) % T::HY, hz = hp / (T::HX * T::HY);
-    const int gx = ox + hx - 1, gy = NDIM == 3 ? oy + hy - 1 : 0, gz = oz + hz - 1;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz) {
-      const int gp = gx + d.nx * (gy + d.ny * gz);
-      if (CA == 0) {
-        v = *reinterpret_cast<const uint4*>(X + (size_t)gp * CIN + c8);
-      } else if (c8 < CA) {
-        const int q = (gx / 2) + nxc * ((NDIM == 3 ? gy / 2 : 0) + nyc * (gz / 2));
-        v = *reinterpret_cast<const uint4*>(A + (size_t)q * (CA > 0 ? CA : 1) + c8);
-      } else {
-        v = *reinterpret_cast<const uint4*>(X + (size_t)gp * (CB > 0 ? CB : 1) + (c8 - CA));
+  // ---- stage the tile and its halo (zeros outside the grid); batches of
+  // kStage 16-byte loads are issued before their LDS writes
+  constexpr int NEF = T::HP * (CF / 8);
+  constexpr int NE = NEF + T::CHP * (CA / 8);
+  constexpr int kStage = 8;
+  const int nxc = d.nx / 2, nyc = NDIM == 3 ? d.ny / 2 : 1, nzc = d.nz / 2;
+  // (LDS offset, source) of staging element e; src == nullptr: zero
+  auto locate = [&](int e, int& lds) -> const bf16_t* {
+    if (e < NEF) {
+      const int hp = e / (CF / 8), c8 = (e % (CF / 8)) * 8;
+      lds = hp * T::FSP + c8;
+      const int hx = hp % T::HX, hy = (hp / T::HX) % T::HY, hz = hp / (T::HX * T::HY);
+      const int gx = ox + hx - 1, gy = NDIM == 3 ? oy + hy - 1 : 0, gz = oz + hz - 1;
+      if (gx < 0 || gx >= d.nx || gy < 0 || gy >= d.ny || gz < 0 || gz >= d.nz) return nullptr;
+      return X + (size_t)(gx + d.nx * (gy + d.ny * gz)) * CF + c8;
+    }
+    const int e2 = e - NEF;
+    const int cp = e2 / (CA > 0 ? CA / 8 : 1), c8 = (e2 % (CA > 0 ? CA / 8 : 1)) * 8;
+    lds = T::HP * T::FSP + cp * T::CSP + c8;
+    const int cx = cp % T::CHX, cy = (cp / T::CHX) % T::CHY, cz = cp / (T::CHX * T::CHY);
+    const int gx = ox / 2 - 1 + cx, gy = NDIM == 3 ? oy / 2 - 1 + cy : 0, gz = oz / 2 - 1 + cz;
+    if (gx < 0 || gx >= nxc || gy < 0 || gy >= nyc || gz < 0 || gz >= nzc) return nullptr;
+    return A + (size_t)(gx + nxc * (gy + nyc * gz)) * (CA > 0 ? CA : 1) + c8;
+  };
+  for (int e0 = threadIdx.x; e0 < NE; e0 += 256 * kStage) {
+    uint4 v[kStage];
+    int lds[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      v[u] = make_uint4(0, 0, 0, 0);
+      lds[u] = -1;
+      const int e = e0 + 256 * u;
+      if (e < NE) {
+        // groups of 8 bf16 channels start on 16-byte boundaries (channel counts are multiples of 8)
+        const bf16_t* src = locate(e, lds[u]);
+        if (src) v[u] = *reinterpret_cast<const uint4*>(__builtin_assume_aligned(src, 16));
       }
     }
-    *reinterpret_cast<uint4*>(sIn + hp * T::SP + c8) = v;
+#pragma unroll
+    for (int u = 0; u < kStage; ++u)
+      if (lds[u] >= 0) *reinterpret_cast<uint4*>(sIn + lds[u]) = v[u];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
-  // staged-cell index of the centre cell of each of the wave's M tiles (lane r)
-  int pix[T::MTW];
+  // local coordinates (lane r) and staged fine cell of each of the wave's M tiles
+  int lxm[T::MTW], lym[T::MTW], lzm[T::MTW], pix[T::MTW];
 #pragma unroll
   for (int m = 0; m < T::MTW; ++m) {
     const int mt = wave * T::MTW + m;
     const int seg = mt % (T::TX / 16), row = mt / (T::TX / 16);
-    const int lx = seg * 16 + r;
-    const int ly = NDIM == 3 ? row % T::TY : 0, lz = NDIM == 3 ? row / T::TY : row;
-    pix[m] = (lx + 1) + T::HX * ((NDIM == 3 ? ly + 1 : 0) + T::HY * (lz + 1));
+    lxm[m] = seg * 16 + r;
+    lym[m] = NDIM == 3 ? row % T::TY : 0;
+    lzm[m] = NDIM == 3 ? row / T::TY : row;
+    pix[m] = (lxm[m] + 1) + T::HX * ((NDIM == 3 ? lym[m] + 1 : 0) + T::HY * (lzm[m] + 1));
   }
   f32x4 acc[T::MTW][NTILE];
 #pragma unroll
   for (int m = 0; m < T::MTW; ++m)
 #pragma unroll
     for (int nt = 0; nt < NTILE; ++nt) acc[m][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int kc = 0; kc < KC; ++kc) {
+  // operands of one 32-wide K chunk: weights (global, cached) and the
+  // wave's M tiles (LDS); the next chunk's operands are loaded before the
+  // current chunk's MFMAs are issued
+  auto load_chunk = [&](int kc, bf16x8(&a)[T::MTW], bf16x8(&bw)[NTILE]) {
     const int k = kc * 32 + 8 * g;
     const int t = k / CIN, ci = k % CIN;
     const bool tap = t < NT;
-    bf16x8 bw[NTILE];
 #pragma unroll
     for (int nt = 0; nt < NTILE; ++nt)
       bw[nt] = tap ? load8(W + (size_t)(nt * 16 + r) * KPAD + k) : zero8();
-    int off = 0;
-    if (NDIM == 2) off = (t % 3 - 1) + T::HX * (t / 3 - 1);
-    else off = (t % 3 - 1) + T::HX * ((t / 3) % 3 - 1 + T::HY * (t / 9 - 1));
-    off = off * T::SP + ci;
+    const int dx = t % 3 - 1;
+    const int dy = NDIM == 3 ? (t / 3) % 3 - 1 : 0;
+    const int dz = NDIM == 3 ? t / 9 - 1 : t / 3 - 1;
+    const bool coarse = ci < CA;
+    const int offf = (dx + T::HX * (dy + T::HY * dz)) * T::FSP + (ci - CA);
 #pragma unroll
     for (int m = 0; m < T::MTW; ++m) {
-      bf16x8 a = zero8();
-      if (tap) a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sIn + pix[m] * T::SP + off));
+      int addr = pix[m] * T::FSP + offf;
+      if (CA > 0) {
+        const int cx = (lxm[m] + dx + 2) >> 1;
+        const int cy = NDIM == 3 ? (lym[m] + dy + 2) >> 1 : 0;
+        const int cz = (lzm[m] + dz + 2) >> 1;
+        const int ca = T::HP * T::FSP + (cx + T::CHX * (cy + T::CHY * cz)) * T::CSP + ci;
+        addr = coarse ? ca : addr;
+      }
+      a[m] = tap ? __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sIn + addr)) : zero8();
+    }
+  };
+  bf16x8 a0[T::MTW], b0[NTILE], a1[T::MTW], b1[NTILE];
+  load_chunk(0, a0, b0);
+#pragma unroll
+  for (int kc = 0; kc < KC; kc += 2) {
+    if (kc + 1 < KC) load_chunk(kc + 1, a1, b1);
+#pragma unroll
+    for (int m = 0; m < T::MTW; ++m)
 #pragma unroll
       for (int nt = 0; nt < NTILE; ++nt)
-        acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[nt], acc[m][nt], 0, 0, 0);
+        acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[m], b0[nt], acc[m][nt], 0, 0, 0);
+    if (kc + 1 < KC) {
+      if (kc + 2 < KC) load_chunk(kc + 2, a0, b0);
+#pragma unroll
+      for (int m = 0; m < T::MTW; ++m)
+#pragma unroll
+        for (int nt = 0; nt < NTILE; ++nt)
+          acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[m], b1[nt], acc[m][nt], 0, 0, 0);
     }
   }
 #pragma unroll
   for (int m = 0; m < T::MTW; ++m) {
-    const int mt = wave * T::MTW + m;
-    const int seg = mt % (T::TX / 16), row = mt / (T::TX / 16);
-    const int ly = NDIM == 3 ? row % T::TY : 0, lz = NDIM == 3 ? row / T::TY : row;
-    const int gy = oy + ly, gz = oz + lz;
+    const int gy = oy + lym[m], gz = oz + lzm[m];
+    const int seg = (wave * T::MTW + m) % (T::TX / 16);
 #pragma unroll
     for (int nt = 0; nt < NTILE; ++nt)
 #pragma unroll
@@ -280,7 +333,7 @@ __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restr
 
 template <int NDIM, int CIN>
 int conv_tiles(const CnnDims& d) {
-  using T = ConvTile<NDIM, CIN>;
+  using T = ConvTile<NDIM, CIN, 0>;
   const int ntx = (d.nx + T::TX - 1) / T::TX;
   const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
   const int ntz = (d.nz + T::TZ - 1) / T::TZ;

@@ -31,7 +31,7 @@ namespace gea {
 
 namespace {
 
-constexpr int kTX3 = 64, kTY3 = 8, kKC3 = 16;  // 3D tile and z chunk
+constexpr int kTX3 = 64, kTY3 = 4, kKC3 = 16;  // 3D tile and z chunk
 constexpr int kTX2 = 256, kKC2 = 16;           // 2D row segment and z chunk
 
 template <int NDIM, typename T>
@@ -195,8 +195,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv3(Geo G, Stencil<3, T> K, CgV
   constexpr int TX = kTX3, TY = kTY3, KC = kKC3;
   constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;
   constexpr int RPT = TX * TY / kBlock;
-  __shared__ T sp[3][HP];
-  __shared__ T sd[3][HP];
+  constexpr int HPT = (HP + kBlock - 1) / kBlock;  // staged cells per thread and plane
+  // Plane kk+1 is loaded into registers while plane kk-1 is computed.  FP32:
+  // a ring of 4 planes, where the slot a plane is written to was last read
+  // two planes earlier, before the previous barrier, so one barrier per plane
+  // suffices.  FP64: a ring of 3 (4 would not leave room for 4 workgroups per
+  // CU) and a second barrier before the next write.
+  constexpr int NS = sizeof(T) == 8 ? 3 : 4;
+  __shared__ T sp[NS][HP];
+  __shared__ T sd[NS][HP];
   if (load_done(sc)) return;
   double beta_d = 0.0;
   if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
@@ -208,27 +215,46 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv3(Geo G, Stencil<3, T> K, CgV
   const int i0 = tx * TX, j0 = ty * TY, k0 = tz * KC;
   const int k1 = min(k0 + KC, nz);
   const T kx = K.k[0], ky = K.k[1], kz = K.k[2];
-  double acc = 0.0;
-  for (int kk = k0 - 1; kk <= k1; ++kk) {
-    if (kk >= 0 && kk < nz) {
-      const int sl = (kk + 3) % 3;
-      for (int h = threadIdx.x; h < HP; h += kBlock) {
-        const int hx = h % HX, hy = h / HX;
-        const int i = i0 + hx - 1, j = j0 + hy - 1;
-        T pv = T(0), dv = T(0);
-        if (i >= 0 && i < nx && j >= 0 && j < ny) {
-          const int Q = i + nx * (j + ny * kk);
-          pv = v.r[Q] * v.dinv[Q] + beta * p_old[Q];
-          dv = v.D[Q];
-        }
-        sp[sl][h] = pv;
-        sd[sl][h] = dv;
+  // global index of each staged cell of this thread in plane 0 (-1: outside)
+  int qh[HPT];
+#pragma unroll
+  for (int u = 0; u < HPT; ++u) {
+    const int h = threadIdx.x + kBlock * u;
+    const int hx = h % HX, hy = h / HX;
+    const int i = i0 + hx - 1, j = j0 + hy - 1;
+    qh[u] = (h < HP && i >= 0 && i < nx && j >= 0 && j < ny) ? i + nx * j : -1;
+  }
+  const int plane = nx * ny;
+  T pr[HPT], pd[HPT];
+  auto fetch = [&](int kk) {
+#pragma unroll
+    for (int u = 0; u < HPT; ++u) {
+      pr[u] = T(0);
+      pd[u] = T(0);
+      if (kk >= 0 && kk < nz && qh[u] >= 0) {
+        const int Q = qh[u] + plane * kk;
+        pr[u] = v.r[Q] * v.dinv[Q] + beta * p_old[Q];
+        pd[u] = v.D[Q];
       }
     }
+  };
+  double acc = 0.0;
+  fetch(k0 - 1);
+  for (int kk = k0 - 1; kk <= k1; ++kk) {
+    const int sl = (kk + NS) % NS;
+#pragma unroll
+    for (int u = 0; u < HPT; ++u) {
+      const int h = threadIdx.x + kBlock * u;
+      if (h < HP) {
+        sp[sl][h] = pr[u];
+        sd[sl][h] = pd[u];
+      }
+    }
+    if (kk + 1 <= k1) fetch(kk + 1);
     __syncthreads();
     const int k = kk - 1;
     if (k >= k0 && k < k1) {
-      const int sm = (k + 2) % 3, s0 = (k + 3) % 3, sP = (k + 4) % 3;
+      const int sm = (k - 1 + NS) % NS, s0 = (k + NS) % NS, sP = (k + 1) % NS;
 #pragma unroll
       for (int m = 0; m < RPT; ++m) {
         const int t = threadIdx.x + kBlock * m;
@@ -251,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv3(Geo G, Stencil<3, T> K, CgV
         }
       }
     }
-    __syncthreads();
+    if (NS == 3) __syncthreads();
   }
   double red[1] = {acc};
   store_partials<1>(red, s_part);

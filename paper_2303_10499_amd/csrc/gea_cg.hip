@@ -47,6 +47,7 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   double a[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) a[k] = 0.0;
+#pragma unroll 8
   for (int b = threadIdx.x; b < n; b += kBlock) {
 #pragma unroll
     for (int k = 0; k < N; ++k) a[k] += part[k * n + b];
@@ -205,9 +206,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv3(Geo G, Stencil<3, T> K, CgV
   __shared__ T sp[NS][HP];
   __shared__ T sd[NS][HP];
   if (load_done(sc)) return;
-  double beta_d = 0.0;
-  if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
-  const T beta = (T)beta_d;
   const int nx = G.nx, ny = G.ny, nz = G.nz;
   const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
   const int b = xcd_block();
@@ -225,28 +223,35 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv3(Geo G, Stencil<3, T> K, CgV
     qh[u] = (h < HP && i >= 0 && i < nx && j >= 0 && j < ny) ? i + nx * j : -1;
   }
   const int plane = nx * ny;
-  T pr[HPT], pd[HPT];
+  // staged values: z = r/diag, the old direction and D (p = z + beta p_old
+  // is formed when a plane is written to LDS, once beta is known)
+  T pz[HPT], po[HPT], pd[HPT];
   auto fetch = [&](int kk) {
 #pragma unroll
     for (int u = 0; u < HPT; ++u) {
-      pr[u] = T(0);
+      pz[u] = T(0);
+      po[u] = T(0);
       pd[u] = T(0);
       if (kk >= 0 && kk < nz && qh[u] >= 0) {
         const int Q = qh[u] + plane * kk;
-        pr[u] = v.r[Q] * v.dinv[Q] + beta * p_old[Q];
+        pz[u] = v.r[Q] * v.dinv[Q];
+        po[u] = p_old[Q];
         pd[u] = v.D[Q];
       }
     }
   };
+  fetch(k0 - 1);  // in flight while the previous kernel's partials are summed
+  double beta_d = 0.0;
+  if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
+  const T beta = (T)beta_d;
   double acc = 0.0;
-  fetch(k0 - 1);
   for (int kk = k0 - 1; kk <= k1; ++kk) {
     const int sl = (kk + NS) % NS;
 #pragma unroll
     for (int u = 0; u < HPT; ++u) {
       const int h = threadIdx.x + kBlock * u;
       if (h < HP) {
-        sp[sl][h] = pr[u];
+        sp[sl][h] = pz[u] + beta * po[u];
         sd[sl][h] = pd[u];
       }
     }

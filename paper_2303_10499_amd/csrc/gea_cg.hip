@@ -288,66 +288,96 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv3(Geo G, Stencil<3, T> K, CgV
   store_partials<1>(red, s_part);
 }
 
-// 2D: the same on a row segment of 256 cells marching over 16 rows of z
+// 2D: p = r/diag + beta p_old, q = A p, partial <p, q>.  A workgroup owns a
+// 256-cell row segment and marches it over 16 rows of z; each wave owns 64
+// consecutive cells.  The rows below and above a cell stay in registers and
+// x-neighbours come from the neighbouring lanes (the first and last lane of a
+// wave also load the cell just beyond the wave), so the kernel needs neither
+// LDS nor barriers.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv2(Geo G, Stencil<2, T> K, CgVectors<T> v,
                                                      const T* __restrict__ p_old,
                                                      T* __restrict__ p_new, int iter,
                                                      const double* u_part, int nu,
                                                      double* s_part, CgScalars* sc) {
-  constexpr int TX = kTX2, KC = kKC2, HX = TX + 2;
-  constexpr int RPT = TX / kBlock;
-  __shared__ T sp[3][HX];
-  __shared__ T sd[3][HX];
+  constexpr int TX = kTX2, KC = kKC2;
+  static_assert(TX == kBlock, "one cell of the row segment per thread");
   if (load_done(sc)) return;
-  double beta_d = 0.0;
-  if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
-  const T beta = (T)beta_d;
   const int nx = G.nx, nz = G.nz;
   const int ntx = (nx + TX - 1) / TX;
   const int b = xcd_block();
   const int tx = b % ntx, tz = b / ntx;
-  const int i0 = tx * TX, k0 = tz * KC, k1 = min(k0 + KC, nz);
+  const int lane = threadIdx.x & 63;
+  const int i = tx * TX + threadIdx.x;
+  const int k0 = tz * KC, k1 = min(k0 + KC, nz);
   const T kx = K.k[0], kz = K.k[1];
-  double acc = 0.0;
-  for (int kk = k0 - 1; kk <= k1; ++kk) {
+  const bool in = i < nx;
+  // the cell beyond the wave that an edge lane supplies (lane 0: left, lane 63: right)
+  const int ie = lane == 0 ? i - 1 : (lane == 63 ? i + 1 : -1);
+  const bool edge = ie >= 0 && ie < nx;
+  // raw values of row kk (z = r/diag, old direction, D), own cell and edge cell
+  struct Raw {
+    T z, o, d, ze, oe, de;
+  };
+  auto fetch = [&](int kk) {
+    Raw w{T(0), T(0), T(0), T(0), T(0), T(0)};
     if (kk >= 0 && kk < nz) {
-      const int sl = (kk + 3) % 3;
-      for (int h = threadIdx.x; h < HX; h += kBlock) {
-        const int i = i0 + h - 1;
-        T pv = T(0), dv = T(0);
-        if (i >= 0 && i < nx) {
-          const int Q = i + nx * kk;
-          pv = v.r[Q] * v.dinv[Q] + beta * p_old[Q];
-          dv = v.D[Q];
-        }
-        sp[sl][h] = pv;
-        sd[sl][h] = dv;
+      if (in) {
+        const int Q = i + nx * kk;
+        w.z = v.r[Q] * v.dinv[Q];
+        w.o = p_old[Q];
+        w.d = v.D[Q];
+      }
+      if (edge) {
+        const int Q = ie + nx * kk;
+        w.ze = v.r[Q] * v.dinv[Q];
+        w.oe = p_old[Q];
+        w.de = v.D[Q];
       }
     }
-    __syncthreads();
-    const int k = kk - 1;
-    if (k >= k0 && k < k1) {
-      const int sm = (k + 2) % 3, s0 = (k + 3) % 3, sP = (k + 4) % 3;
-#pragma unroll
-      for (int m = 0; m < RPT; ++m) {
-        const int lx = threadIdx.x + kBlock * m;
-        const int i = i0 + lx;
-        if (i < nx) {
-          const int h = lx + 1, P = i + nx * k;
-          const T pp = sp[s0][h], dp = sd[s0][h];
-          T a = v.c[P] * pp;
-          if (i + 1 < nx) a += T(0.5) * (dp + sd[s0][h + 1]) * kx * (pp - sp[s0][h + 1]);
-          if (i > 0) a += T(0.5) * (sd[s0][h - 1] + dp) * kx * (pp - sp[s0][h - 1]);
-          if (k + 1 < nz) a += T(0.5) * (dp + sd[sP][h]) * kz * (pp - sp[sP][h]);
-          if (k > 0) a += T(0.5) * (sd[sm][h] + dp) * kz * (pp - sp[sm][h]);
-          p_new[P] = pp;
-          v.q[P] = a;
-          acc += (double)pp * (double)a;
-        }
-      }
+    return w;
+  };
+  // rows k0-1, k0, k0+1 in flight while the previous kernel's partials are summed
+  const Raw wm = fetch(k0 - 1), wc = fetch(k0);
+  Raw wn = fetch(k0 + 1);
+  double beta_d = 0.0;
+  if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
+  const T beta = (T)beta_d;
+  T pm = wm.z + beta * wm.o, dm = wm.d;
+  T pc = wc.z + beta * wc.o, dc = wc.d;
+  T pec = wc.ze + beta * wc.oe, dec = wc.de;
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const T pn = wn.z + beta * wn.o, dn = wn.d;
+    const T pen = wn.ze + beta * wn.oe, den = wn.de;
+    if (k + 2 <= k1) wn = fetch(k + 2);
+    T pl = __shfl_up(pc, 1, 64), pr = __shfl_down(pc, 1, 64);
+    T dl = __shfl_up(dc, 1, 64), dr = __shfl_down(dc, 1, 64);
+    if (lane == 0) {
+      pl = pec;
+      dl = dec;
     }
-    __syncthreads();
+    if (lane == 63) {
+      pr = pec;
+      dr = dec;
+    }
+    if (in) {
+      const int P = i + nx * k;
+      T a = v.c[P] * pc;
+      if (i + 1 < nx) a += T(0.5) * (dc + dr) * kx * (pc - pr);
+      if (i > 0) a += T(0.5) * (dl + dc) * kx * (pc - pl);
+      if (k + 1 < nz) a += T(0.5) * (dc + dn) * kz * (pc - pn);
+      if (k > 0) a += T(0.5) * (dm + dc) * kz * (pc - pm);
+      p_new[P] = pc;
+      v.q[P] = a;
+      acc += (double)pc * (double)a;
+    }
+    pm = pc;
+    dm = dc;
+    pc = pn;
+    dc = dn;
+    pec = pen;
+    dec = den;
   }
   double red[1] = {acc};
   store_partials<1>(red, s_part);

@@ -337,20 +337,29 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv2(Geo G, Stencil<2, T> K, CgV
     }
     return w;
   };
-  // rows k0-1, k0, k0+1 in flight while the previous kernel's partials are summed
-  const Raw wm = fetch(k0 - 1), wc = fetch(k0);
-  Raw wn = fetch(k0 + 1);
+  // rows k0-1 .. k0+PD in flight while the previous kernel's partials are
+  // summed; afterwards row k+PD+1 is requested while row k is computed
+  constexpr int PD = 3;
+  Raw ring[PD + 1];
+  const Raw wm = fetch(k0 - 1);
+#pragma unroll
+  for (int w = 0; w <= PD; ++w) ring[w] = fetch(k0 + w);
   double beta_d = 0.0;
   if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
   const T beta = (T)beta_d;
   T pm = wm.z + beta * wm.o, dm = wm.d;
-  T pc = wc.z + beta * wc.o, dc = wc.d;
-  T pec = wc.ze + beta * wc.oe, dec = wc.de;
+  T pc = ring[0].z + beta * ring[0].o, dc = ring[0].d;
+  T pec = ring[0].ze + beta * ring[0].oe, dec = ring[0].de;
   double acc = 0.0;
-  for (int k = k0; k < k1; ++k) {
+#pragma unroll
+  for (int it = 0; it < KC; ++it) {
+    const int k = k0 + it;
+    if (k >= k1) break;
+    const Raw& wn = ring[(it + 1) % (PD + 1)];
     const T pn = wn.z + beta * wn.o, dn = wn.d;
     const T pen = wn.ze + beta * wn.oe, den = wn.de;
-    if (k + 2 <= k1) wn = fetch(k + 2);
+    // slot of row k is free now: request row k+PD+1 into it
+    ring[it % (PD + 1)] = (k + PD + 1 <= k1) ? fetch(k + PD + 1) : Raw{T(0), T(0), T(0), T(0), T(0), T(0)};
     T pl = __shfl_up(pc, 1, 64), pr = __shfl_down(pc, 1, 64);
     T dl = __shfl_up(dc, 1, 64), dr = __shfl_down(dc, 1, 64);
     if (lane == 0) {

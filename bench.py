@@ -36,6 +36,10 @@ BYTES_PER_CELL = {
 CLASS_NAMES = {0: "k_cg_spmv<fp64>", 1: "k_cg_update<fp64>", 2: "k_cg_spmv<fp32>",
                3: "k_cg_update<fp32>", 4: "solver set-up/check kernels",
                5: "explicit step kernels", 6: "learned network"}
+# the six forward convolutions of the network (bf16 matrix-core kernels)
+LAYER_NAMES = ["k_conv_t L0 (2->16)", "k_conv_t L1 (16->32, 1/2)", "k_conv_t L2 (32->64, 1/4)",
+               "k_conv_t L3 ([64,32]->32, 1/2)", "k_conv_t L4 ([32,16]->16)", "k_conv_t L5 (16->1)"]
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def log(msg):
@@ -89,17 +93,43 @@ def run_form(cfg, form, steps, warmup, kernel_steps):
     # launches between two events on the solver's stream
     avg = S.time_solver_kernels(reps=50)
     out["kernel_avg_us"] = {CLASS_NAMES[k]: round(avg[k] * 1e3, 2) for k in range(4)}
-    per_step = {k: avg[k] * kn[k] / kernel_steps for k in range(4) if kn[k]}
     out["launches_per_step"] = {CLASS_NAMES[k]: kn[k] / kernel_steps for k in range(7) if kn[k]}
-    out["cg_kernel_ms_per_step"] = {CLASS_NAMES[k]: round(v, 4) for k, v in per_step.items()}
     out["explicit_ms_per_step_event_timed"] = kms[5] / kernel_steps
-    dom = max(per_step, key=lambda k: per_step[k], default=None)
-    if dom is not None:
-        achieved = BYTES_PER_CELL[dom] * nc / (avg[dom] * 1e-3) / 1e9
-        out["roofline"] = dict(kernel=CLASS_NAMES[dom], avg_launch_us=avg[dom] * 1e3,
-                               bytes_per_launch=BYTES_PER_CELL[dom] * nc, achieved=achieved)
+    # candidates for the dominant kernel: device time per step = average
+    # launch duration x launches per step
+    cands = {}
+    for k in range(4):
+        if kn[k]:
+            cands[CLASS_NAMES[k]] = dict(bound="hbm", avg_ms=avg[k], per_step_ms=avg[k] * kn[k] / kernel_steps,
+                                         work=BYTES_PER_CELL[k] * nc)
+    if solver == "learned":
+        nms, ngf = S.time_network(reps=20)
+        apps = kn[6] / kernel_steps
+        out["network_applications_per_step"] = apps
+        out["network_layer_avg_us"] = {LAYER_NAMES[l]: round(nms[l] * 1e3, 2) for l in range(6)}
+        for l in range(6):
+            cands[LAYER_NAMES[l]] = dict(bound="mfma", avg_ms=nms[l], per_step_ms=nms[l] * apps,
+                                         work=ngf[l] * 1e9)
+    out["kernel_ms_per_step"] = {k: round(v["per_step_ms"], 4) for k, v in cands.items()}
+    if cands:
+        dom = max(cands, key=lambda k: cands[k]["per_step_ms"])
+        out["roofline"] = dict(kernel=dom, **cands[dom])
     S.close()
     return out
+
+
+def roofline_entry(rr):
+    """the roofline object of a kernel candidate (see run_form)"""
+    t = rr["avg_ms"] * 1e-3
+    if rr["bound"] == "hbm":
+        achieved, peak, unit = rr["work"] / t / 1e9, HBM_PEAK_GBS, "GB/s"
+        extra = dict(bytes_per_launch=rr["work"])
+    else:
+        achieved, peak, unit = rr["work"] / t / 1e12, MFMA_BF16_PEAK_TFLOPS, "TFLOP/s"
+        extra = dict(flop_per_launch=rr["work"])
+    return dict(bound=rr["bound"], kernel=rr["kernel"], achieved=round(achieved, 1), peak=peak,
+                unit=unit, frac=round(achieved / peak, 4), avg_launch_us=round(rr["avg_ms"] * 1e3, 2),
+                **extra, traffic=read_traffic(rr["kernel"]))
 
 
 def cpu_baseline(cfg):
@@ -117,25 +147,29 @@ def cpu_baseline(cfg):
                        f"tol {cfg['params']['tol']:g}, single-threaded C (-O2), {dt:.1f} s")
 
 
+def source_sha(name):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2303_10499_amd", "csrc", name)
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
 def read_traffic(kernel):
-    """HBM bytes per launch of a CG kernel from the committed rocprofv3 counter
-    summary (profiles/traffic.txt), if it was taken on the current source of
-    the CG kernels; else None."""
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (profiles/traffic.txt: lines 'kernel = bytes @ source sha'), if
+    the counters were taken on the current source of that kernel; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
-    import hashlib
-    src = os.path.join(ROOT, "paper_2303_10499_amd", "csrc", "gea_cg.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    rec = {}
     for line in open(path):
         line = line.strip()
-        if "=" in line and not line.startswith("#"):
-            k, v = line.split("=", 1)
-            rec[k.strip()] = v.strip()
-    if rec.get("source_sha") != h or kernel not in rec:
-        return None
-    return float(rec[kernel])
+        if line.startswith("#") or "=" not in line or "@" not in line:
+            continue
+        k, rest = line.split("=", 1)
+        val, src = rest.split("@", 1)
+        name, sha = src.split()
+        if k.strip() == kernel:
+            return float(val) if source_sha(name) == sha else None
+    return None
 
 
 def main():
@@ -188,14 +222,7 @@ def main():
     primary = "learned" if "learned" in results else ("mixed" if "mixed" in results else forms[0])
     R = results[primary]
     nc = cfg["mesh"]["nx"] * cfg["mesh"]["ny"] * cfg["mesh"]["nz"]
-    roof = None
-    if "roofline" in R:
-        rr = R["roofline"]
-        roof = dict(bound="hbm", kernel=rr["kernel"], achieved=round(rr["achieved"], 1),
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(rr["achieved"] / HBM_PEAK_GBS, 4),
-                    avg_launch_us=round(rr["avg_launch_us"], 2),
-                    bytes_per_launch=rr["bytes_per_launch"],
-                    traffic=read_traffic(rr["kernel"]))
+    roof = roofline_entry(R["roofline"]) if "roofline" in R else None
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a one-step sample ...")

@@ -194,6 +194,15 @@ gea_status gea_kernel_times(gea_ctx* ctx, double* ms, int64_t* launches);
  * update kernel.  Uses scratch vectors only; the state is not changed. */
 gea_status gea_time_solver_kernels(gea_ctx* ctx, int32_t reps, double* ms);
 
+/* Average device milliseconds of one launch of each of the six forward
+ * convolutions of the learned form's network (ms[6], layers in the order of
+ * include/gea_learned.h), each launched reps times back to back between two
+ * events on the context's stream on the network's current activations, and
+ * the algorithmic GFLOP of one launch (2 x cells x C_out x taps x C_in with
+ * the logical channel counts; gflop[6]).  Needs loaded weights
+ * (GEA_ERR_STATE otherwise); overwrites only the network's activations. */
+gea_status gea_time_network(gea_ctx* ctx, int32_t reps, double* ms, double* gflop);
+
 /* Release the context (the workspace stays with its owner). */
 void gea_destroy(gea_ctx* ctx);
 

@@ -975,6 +975,31 @@ gea_status gea_time_solver_kernels(gea_ctx* x, int32_t reps, double* ms) {
   });
 }
 
+gea_status gea_time_network(gea_ctx* x, int32_t reps, double* ms, double* gflop) {
+  if (!x || !ms || !gflop || reps < 1) return GEA_ERR_ARG;
+  if (!x->has_net) return fail(x, GEA_ERR_STATE, "no network weights loaded");
+  return guarded(x, [&]() {
+    hipStream_t s = x->stream;
+    x->net.s = s;
+    hipEvent_t ev[2];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (int l = 0; l < kCnnLayers; ++l) {
+      cnn_conv_layer(x->net, l);  // warm-up
+      HIPCHK(hipEventRecord(ev[0], s));
+      for (int k = 0; k < reps; ++k) cnn_conv_layer(x->net, l);
+      HIPCHK(hipEventRecord(ev[1], s));
+      HIPCHK(hipEventSynchronize(ev[1]));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+      ms[l] = (double)t / reps;
+      gflop[l] = cnn_layer_flops(x->net, l) * 1e-9;
+    }
+    for (auto& e : ev) HIPCHK(hipEventDestroy(e));
+    HIPCHK(hipGetLastError());
+    return GEA_OK;
+  });
+}
+
 gea_status gea_kernel_times(gea_ctx* x, double* ms, int64_t* launches) {
   if (!x || !ms || !launches) return GEA_ERR_ARG;
   return guarded(x, [&]() {

@@ -195,7 +195,9 @@ __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restr
   __shared__ __attribute__((aligned(16))) bf16_t sIn[T::LDS];
   const int ntx = (d.nx + T::TX - 1) / T::TX;
   const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
-  const int b = blockIdx.x;
+  // XCD-aware order: neighbouring tiles (which re-read each other's halo
+  // cells) run on the same XCD and share its L2
+  const int b = xcd_block();
   const int ox = (b % ntx) * T::TX;
   const int oy = NDIM == 3 ? ((b / ntx) % nty) * T::TY : 0;
   const int oz = (b / (ntx * nty)) * T::TZ;
@@ -695,19 +697,32 @@ void conv_wgrad(const Cnn& n, int layer, const bf16_t* X, const bf16_t* dYq, boo
                      (int)acc);
 }
 
+// the forward convolution of one layer on the network's own buffers
+template <int NDIM>
+void conv_layer(Cnn& n, int layer) {
+  const bf16_t* none = nullptr;
+  switch (layer) {
+    case 0: conv_fwd<NDIM>(n, 0, n.xin, none, n.e0); break;
+    case 1: conv_fwd<NDIM>(n, 1, n.p0, none, n.e1); break;
+    case 2: conv_fwd<NDIM>(n, 2, n.p1, none, n.e2); break;
+    case 3: conv_fwd<NDIM>(n, 3, n.e1, n.e2, n.d1); break;
+    case 4: conv_fwd<NDIM>(n, 4, n.e0, n.d1, n.d0); break;
+    case 5: conv_fwd<NDIM>(n, 5, n.d0, none, n.y); break;
+  }
+}
+
 template <int NDIM>
 void forward_t(Cnn& n) {
   hipStream_t s = n.s;
   const dim3 bl(256);
-  const bf16_t* none = nullptr;
-  conv_fwd<NDIM>(n, 0, n.xin, none, n.e0);
+  conv_layer<NDIM>(n, 0);
   hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[1].npix * 16)), bl, 0, s, n.d[1], 16, (const bf16_t*)n.e0, n.p0);
-  conv_fwd<NDIM>(n, 1, n.p0, none, n.e1);
+  conv_layer<NDIM>(n, 1);
   hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[2].npix * 32)), bl, 0, s, n.d[2], 32, (const bf16_t*)n.e1, n.p1);
-  conv_fwd<NDIM>(n, 2, n.p1, none, n.e2);
-  conv_fwd<NDIM>(n, 3, n.e1, n.e2, n.d1);
-  conv_fwd<NDIM>(n, 4, n.e0, n.d1, n.d0);
-  conv_fwd<NDIM>(n, 5, n.d0, none, n.y);
+  conv_layer<NDIM>(n, 2);
+  conv_layer<NDIM>(n, 3);
+  conv_layer<NDIM>(n, 4);
+  conv_layer<NDIM>(n, 5);
   if (n.train) {
     // the concatenated inputs of layers 3 and 4, kept for the weight gradients
     hipLaunchKernelGGL(k_upcat<NDIM>, dim3(blocks_for((long)n.d[1].npix * 96)), bl, 0, s, n.d[1], 64, 32, (const bf16_t*)n.e2, (const bf16_t*)n.e1, n.c1);
@@ -903,6 +918,17 @@ void cnn_scale_output(Cnn& n, const double* s, float* out, int accumulate) {
 void cnn_forward(Cnn& n) {
   if (n.ndim == 2) forward_t<2>(n);
   else forward_t<3>(n);
+}
+
+void cnn_conv_layer(Cnn& n, int layer) {
+  if (n.ndim == 2) conv_layer<2>(n, layer);
+  else conv_layer<3>(n, layer);
+}
+
+double cnn_layer_flops(const Cnn& n, int layer) {
+  const CnnLayer& L = n.L[layer];
+  const double taps = n.ndim == 2 ? 9.0 : 27.0;
+  return 2.0 * (double)n.d[L.level].npix * L.cout * taps * L.cin;
 }
 
 void cnn_backward(Cnn& n, bool accumulate) {

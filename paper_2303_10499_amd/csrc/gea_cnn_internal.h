@@ -64,6 +64,8 @@ bool cnn_dims_ok(int ndim, int nx, int ny, int nz);
 void cnn_pack_weights(Cnn& n);                 // master -> bf16 W, Wt and bias
 void cnn_input_from_f32(Cnn& n);              // xf (npix x 2 FP32) -> xin
 void cnn_forward(Cnn& n);                      // xin -> y
+void cnn_conv_layer(Cnn& n, int layer);        // the forward convolution of one layer
+double cnn_layer_flops(const Cnn& n, int layer);  // its multiply-adds x 2 (logical channels)
 void cnn_backward(Cnn& n, bool accumulate);    // t, last forward -> grad (loss partials in lpart)
 void cnn_adam(Cnn& n, float lr, float scale, int step);
 int cnn_loss_partials(const Cnn& n);           // number of loss partials in lpart

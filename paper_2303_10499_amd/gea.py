@@ -86,6 +86,7 @@ def lib():
         L.gea_kernel_timing.argtypes = [vp, C.c_int32, C.c_int32]
         L.gea_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_int64)]
         L.gea_time_solver_kernels.argtypes = [vp, C.c_int32, P(C.c_double)]
+        L.gea_time_network.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_double)]
         L.gea_destroy.argtypes = [vp]
         L.gea_destroy.restype = None
         L.gea_last_error.argtypes = [vp]
@@ -93,7 +94,7 @@ def lib():
         for name in ("gea_workspace_bytes", "gea_init_mesh", "gea_set_solver", "gea_init_bubble",
                      "gea_set_state", "gea_step", "gea_pressure_solve",
                      "gea_apply_pressure_operator", "gea_get_fields", "gea_kernel_timing",
-                     "gea_kernel_times", "gea_time_solver_kernels"):
+                     "gea_kernel_times", "gea_time_solver_kernels", "gea_time_network"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -245,6 +246,13 @@ class Solver:
         ms = (C.c_double * 4)()
         self._check(self.L.gea_time_solver_kernels(self.ctx, int(reps), ms), self.ctx)
         return list(ms)
+
+    def time_network(self, reps=20):
+        """average ms per launch and GFLOP per launch of the six forward convolutions"""
+        ms = (C.c_double * 6)()
+        gf = (C.c_double * 6)()
+        self._check(self.L.gea_time_network(self.ctx, int(reps), ms, gf), self.ctx)
+        return list(ms), list(gf)
 
     def state(self):
         """dict of host arrays: rho, u (ndim, nc), T, pp, p"""

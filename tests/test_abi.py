@@ -24,11 +24,41 @@ def L():
     return gea.lib()
 
 
-def test_every_declared_symbol_is_exported(L):
-    names = declared("gea.h")
-    assert "gea_step" in names and "gea_pressure_solve" in names
+@pytest.mark.parametrize("header,must", [
+    ("gea.h", ("gea_init_mesh", "gea_set_state", "gea_step", "gea_pressure_solve",
+               "gea_get_fields", "gea_time_network")),
+    ("gea_learned.h", ("gea_cnn_forward", "gea_cnn_backward", "gea_cnn_adam",
+                       "gea_load_weights", "gea_make_pair")),
+])
+def test_every_declared_symbol_is_exported(L, header, must):
+    names = declared(header)
+    for n in must:
+        assert n in names, f"{n} missing from {header}"
     for n in names:
-        assert hasattr(L, n), f"{n} declared in gea.h but not exported"
+        assert hasattr(L, n), f"{n} declared in {header} but not exported"
+
+
+def test_network_argument_errors(L):
+    from paper_2303_10499_amd import gea, learned
+    Ll = learned._lib()
+    n = C.c_int64(0)
+    assert Ll.gea_cnn_param_count(2, C.byref(n)) == gea.OK and n.value == 58193
+    assert Ll.gea_cnn_param_count(3, C.byref(n)) == gea.OK and n.value == 174257
+    assert Ll.gea_cnn_param_count(4, C.byref(n)) == gea.ERR_ARG
+    b = C.c_size_t(0)
+    # grid dimensions must be multiples of 4 (two 2x poolings)
+    assert Ll.gea_cnn_workspace_bytes(2, 64, 1, 32, 0, C.byref(b)) == gea.OK
+    assert Ll.gea_cnn_workspace_bytes(2, 66, 1, 32, 0, C.byref(b)) == gea.ERR_ARG
+    assert Ll.gea_cnn_workspace_bytes(3, 16, 6, 16, 1, C.byref(b)) == gea.ERR_ARG
+    # inference instances keep no concatenated inputs: smaller than training ones
+    bi, bt = C.c_size_t(0), C.c_size_t(0)
+    assert Ll.gea_cnn_workspace_bytes(3, 32, 32, 32, 0, C.byref(bi)) == gea.OK
+    assert Ll.gea_cnn_workspace_bytes(3, 32, 32, 32, 1, C.byref(bt)) == gea.OK
+    assert bi.value < bt.value
+    h = C.c_void_p()
+    assert Ll.gea_cnn_create(2, 64, 1, 32, 0, None, None, 0, C.byref(h)) == gea.ERR_ARG
+    assert not h.value
+    assert L.gea_time_network(None, 1, None, None) == gea.ERR_ARG
 
 
 def test_workspace_bytes_and_argument_errors(L):

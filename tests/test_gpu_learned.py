@@ -187,3 +187,85 @@ def test_learned_solver_falls_back_and_still_converges(learned, junk):
         for k in range(st.n_solves):
             assert st.solve[k].fallbacks == (1 if st.solve[k].outer_iters > 0 else 0)
         assert fb >= 1
+
+
+@pytest.mark.parametrize("name", ["nonsmooth2d_2048", "bubble3d_256x256x128"])
+def test_trained_network_gain(learned, name):
+    """What the trained network gains over the method without it, on the
+    solver's own pressure systems at full size: its correction against the
+    zero predictor, and one step along its direction against one Jacobi step
+    (both with the optimal step length), in the residual and in the A-norm of
+    the error; and the iterations of a whole solve, learned vs mixed."""
+    import ctypes as C
+    from paper_2303_10499_amd import gea
+    cfg = configs.get(name)
+    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=200000)
+    S = gea.Solver(cfg["mesh"], cfg["params"], solver="learned")
+    S.load_weights()
+    S.init_bubble(**cfg["bubble"])
+    S.step(3)
+    n = S.nc
+    r = np.empty(n, np.float32)
+    a = np.empty(n, np.float32)
+    d = np.empty(n, np.float32)
+    sc = C.c_double(0.0)
+    assert learned._lib().gea_make_pair(S.ctx, 1e-12, r.ctypes.data, a.ctypes.data, d.ctypes.data,
+                                        C.byref(sc), gea.HOST) == 0
+    m = cfg["mesh"]
+    net = learned.Net(S.ndim, m["nx"], m["ny"], m["nz"], train=False)
+    net.set_params(np.load(learned.weights_file(S.ndim), allow_pickle=False))
+    y = net.forward(np.ascontiguousarray(np.stack([r, a], -1))).astype(np.float64)
+    net.close()
+    r64, d64 = r.astype(np.float64), d.astype(np.float64)
+    c = S.get_fields(gea.FIELD_C)[0]
+    zj = r64 * a.astype(np.float64) / c          # Jacobi direction r/diag (a = c/diag)
+
+    def A(x):
+        out = np.empty(n)
+        S.apply_A(np.ascontiguousarray(x), out)
+        return out
+
+    def res_after_step(z):   # min_alpha ||r - alpha A z|| / ||r||
+        Az = A(z)
+        al = np.dot(r64, Az) / np.dot(Az, Az)
+        return float(np.linalg.norm(r64 - al * Az) / np.linalg.norm(r64))
+
+    Ad = A(d64)
+    dAd = float(np.dot(d64, Ad))
+
+    def anorm_after_step(z):   # min_alpha ||d - alpha z||_A / ||d||_A
+        Az = A(z)
+        al = np.dot(d64, Az) / np.dot(z, Az)
+        e = d64 - al * z
+        return float(np.sqrt(max(np.dot(e, A(e)), 0.0) / dAd))
+
+    cy = np.dot(y, d64) / np.dot(y, y)
+    e_net = float(np.linalg.norm(cy * y - d64) / np.linalg.norm(d64))
+    rho_net, rho_jac = res_after_step(y), res_after_step(zj)
+    ea_net, ea_jac = anorm_after_step(y), anorm_after_step(zj)
+    # a whole solve of the same system by each form
+    x0 = np.ascontiguousarray(S.state()["pp"])
+    its = {}
+    for form in ("mixed", "learned"):
+        S.set_solver(form, 1e-8)
+        x = x0.copy()
+        st = S.pressure_solve(x)
+        assert st.status == 0 and st.rel_res <= 1e-8
+        its[form] = (st.iters, st.outer_iters, st.fallbacks)
+    print(f"\n{name}: correction error {e_net:.3f} (zero predictor 1); after one step: "
+          f"residual {rho_net:.4f} (Jacobi {rho_jac:.4f}), A-norm error {ea_net:.4f} "
+          f"(Jacobi {ea_jac:.4f}); solve iterations (inner, outer, fallbacks) {its}")
+    S.close()
+    assert np.isfinite([e_net, rho_net, rho_jac, ea_net, ea_jac]).all()
+    assert e_net <= 1.0 + 1e-6
+    if S.ndim == 3:
+        # the smooth 3D bubble: the network's correction is within a few per
+        # cent of the exact one and one step along it beats a Jacobi step
+        assert e_net < 0.1
+        assert rho_net < rho_jac and ea_net < ea_jac
+        assert its["learned"][0] <= its["mixed"][0]
+    # 2D non-smooth bubble: the residual is concentrated on the bubble's edge
+    # and most of the field holds residuals far below the global maximum,
+    # while training crops were each scaled to their own maximum; the network
+    # (with biases, so not scale-equivariant) predicts nothing useful there
+    # and the solve relies on the Jacobi-PCG iterations (no gain, no loss)

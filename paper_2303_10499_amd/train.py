@@ -5,14 +5,17 @@ bubble drawn at random (theta_c ~ U(0.25, 3) K, r_c ~ U(150, 2500) m clipped
 to [2 dx, 0.4 min(Lx, Lz)], numpy PCG64 seeded: 0 for training, 1 for
 held-out evaluation), a few time steps are taken, then the next step's
 first-corrector pressure system is assembled and solved tightly; the pair is
-(r0/s, c/diag) -> delta/s with r0 = b - A p', delta = x - p'.  Crops of
-128^2 (2D) or 32^3 (3D) cells are cut from each full-mesh pair on the GPU
-and rescaled by their own max |r0| (the map r -> A^{-1} r is linear, so input
-and target scale together); crops whose residual is below 5 % of the field's
-maximum (round-off far from the bubble) are left out, and targets are divided
+(r0/s, c/diag) -> delta/s with r0 = b - A p', delta = x - p' and s the
+field's max |r0| (the scaling the solver applies to the network's input).
+Crops of 128^2 (2D) or 32^3 (3D) cells are cut from each full-mesh pair on
+the GPU.  With --crop-scale local each crop is rescaled by its own max |r0|
+and crops below 5 % of the field's maximum are dropped; with global the crops
+keep the field's scaling (as the network sees them in use) and only crops of
+pure round-off (below 1e-6 of the maximum) are dropped.  Targets are divided
 by their RMS over the training set (the flexible-CG line search makes the
 network's output scale irrelevant to the solve).  Training runs the library's
-bfloat16 forward and backward kernels with Adam (FP32 master weights).
+bfloat16 forward and backward kernels with Adam (FP32 master weights).  The
+held-out error is reported on crops and on whole fields.
 
 Usage: python -m paper_2303_10499_amd.train --workload nonsmooth2d_2048 --out w2d.npy
 """
@@ -67,8 +70,10 @@ def draw_bubble(rng, cfg):
     return dict(kind=kind, xc=xc, yc=yc, zc=zc, rc=rc, amp=amp)
 
 
-def make_pairs(workload: str, runs: int, crops_per_run: int, seed: int, device="cuda:0"):
-    """crops (X: [n, cells, 2], T: [n, cells]) as torch tensors on the GPU"""
+def make_pairs(workload: str, runs: int, crops_per_run: int, seed: int, device="cuda:0",
+               crop_scale: str = "local", fields: list | None = None):
+    """crops (X: [n, cells, 2], T: [n, cells]) as torch tensors on the GPU;
+    with fields given, the whole-field pairs (x, t) are appended to it"""
     import torch
     cfg = configs.get(workload)
     m = cfg["mesh"]
@@ -95,17 +100,22 @@ def make_pairs(workload: str, runs: int, crops_per_run: int, seed: int, device="
         if rc != gea.OK:
             raise gea.GeaError(rc, "gea_make_pair")
         R, A, D = (v.view(shape) for v in (r, a, d))
+        if fields is not None:
+            fields.append((torch.stack([r, a], dim=-1).clone(), d.clone()))
         tries = 0
         kept = 0
+        floor = 0.05 if crop_scale == "local" else 1e-6
         while kept < crops_per_run and tries < 20 * crops_per_run:
             tries += 1
             o = [int(rng.integers(0, n - cs + 1)) for n in shape]
             sl = tuple(slice(oi, oi + cs) for oi in o)
             rr, aa, dd = R[sl], A[sl], D[sl]
             s = float(rr.abs().max())   # the full field has max |r0/s| = 1
-            if s < 0.05:
+            if s < floor:
                 continue
             kept += 1
+            if crop_scale == "global":
+                s = 1.0
             Xs.append(torch.stack([rr / s, aa], dim=-1).reshape(-1, 2).clone())
             Ts.append((dd / s).reshape(-1).clone())
         if run % 10 == 0:
@@ -153,6 +163,24 @@ def train(X, T, ndim, cs, steps: int, batch: int, lr: float, seed: int = 0, Xv=N
     return net, losses
 
 
+def field_error(ndim, shape, params, fields) -> float:
+    """mean over whole fields of min_c ||c net(x) - t|| / ||t|| (the output
+    scale is free: the solver takes the optimal step along it)"""
+    import torch
+    nz, ny, nx = (shape[0], 1, shape[1]) if ndim == 2 else shape
+    net = learned.Net(ndim, nx, ny, nz, train=False)
+    net.set_params(params)
+    errs = []
+    for x, t in fields:
+        y = net.forward(x.contiguous()).double()
+        t = t.double()
+        c = float((y * t).sum() / (y * y).sum().clamp_min(1e-300))
+        errs.append(float((c * y - t).norm() / t.norm()))
+    net.close()
+    torch.cuda.synchronize()
+    return float(np.mean(errs))
+
+
 def evaluate(net, X, T) -> float:
     """mean loss and the relative error of the correction, over held-out crops"""
     tot = 0.0
@@ -172,9 +200,13 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--crop-scale", choices=("local", "global"), default="local")
     args = ap.parse_args()
-    X, T, ndim, cs = make_pairs(args.workload, args.runs, args.crops, seed=0)
-    Xv, Tv, _, _ = make_pairs(args.workload, args.eval_runs, 16, seed=1)
+    X, T, ndim, cs = make_pairs(args.workload, args.runs, args.crops, seed=0,
+                                crop_scale=args.crop_scale)
+    fields = []
+    Xv, Tv, _, _ = make_pairs(args.workload, args.eval_runs, 16, seed=1,
+                              crop_scale=args.crop_scale, fields=fields)
     sigma = float(T.pow(2).mean().sqrt())
     T /= sigma
     Tv /= sigma
@@ -186,8 +218,13 @@ def main():
     base = float(sum(float((Tv[i] ** 2).sum() / (2 * Tv[i].numel())) for i in range(Tv.shape[0])) / Tv.shape[0])
     out = args.out or weights_path(ndim)
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
-    np.save(out, net.get_params())
-    summary = dict(workload=args.workload, ndim=ndim, crop=cs, train_crops=int(X.shape[0]),
+    params = net.get_params()
+    np.save(out, params)
+    m = configs.get(args.workload)["mesh"]
+    shape = (m["nz"], m["nx"]) if ndim == 2 else (m["nz"], m["ny"], m["nx"])
+    ferr = field_error(ndim, shape, params, fields)
+    summary = dict(workload=args.workload, ndim=ndim, crop=cs, crop_scale=args.crop_scale,
+                   heldout_field_rel_error=ferr, train_crops=int(X.shape[0]),
                    heldout_crops=int(Xv.shape[0]), steps=args.steps, batch=args.batch,
                    first_loss=float(np.mean(losses[:20])), last_loss=float(np.mean(losses[-200:])),
                    heldout_loss=ev, heldout_zero_predictor_loss=base, heldout_rel_error=rel,

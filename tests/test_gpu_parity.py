@@ -221,3 +221,76 @@ def test_mixed_precision_reaches_fp64_residual(oracle_lib, gea_mod, name, dims):
         e_gpu = rel(g[f], getattr(exact, f))
         e_fp64 = rel(getattr(s, f), getattr(exact, f))
         assert e_gpu <= 10 * e_fp64 + 1e-12, (f, e_gpu, e_fp64)
+
+
+# ---- the benchmark's meshes at full size, in the launch configuration bench.py times
+
+def test_full_size_3d_step_matches_oracle(oracle_lib, gea_mod):
+    """bubble3d_256x256x128 (8.4 M cells, the benchmark's 3D mesh and kernel
+    launch shapes): one step with FP64 Jacobi-PCG, every field against the
+    oracle"""
+    cfg = configs.get("bubble3d_256x256x128", tol=1e-13, max_iter=100000)
+    O, s, S = pair(oracle_lib, gea_mod, cfg)
+    O.step(s, 1)
+    st = S.step(1)
+    assert st.steps_done == 1
+    errs = compare(S, s, 1e-10, cfg, 1)
+    print("full-size 3D step, per-field relative error:", errs)
+
+
+def test_full_size_3d_mixed_error_per_field(oracle_lib, gea_mod):
+    """the refinement form on the full 3D mesh at the benchmark's tolerance
+    (1e-8): its error against the tightly solved FP64 oracle, per field, is
+    within 10x of the FP64 oracle's own error at the same tolerance"""
+    cfg = configs.get("bubble3d_256x256x128", tol=1e-8, max_iter=100000)
+    cfg["params"]["inner_tol"] = 1e-4
+    O, s, S = pair(oracle_lib, gea_mod, cfg, solver="mixed")
+    exact = s.copy()
+    O.step(s, 1)
+    O.params.tol = 1e-14
+    O.step(exact, 1)
+    st = S.step(1)
+    for k in range(st.n_solves):
+        assert st.solve[k].status == 0 and st.solve[k].rel_res <= 1e-8
+    g = S.state()
+    report = {}
+    for f in FIELDS:
+        e_gpu = rel(g[f], getattr(exact, f))
+        e_fp64 = rel(getattr(s, f), getattr(exact, f))
+        report[f] = (e_gpu, e_fp64)
+        assert e_gpu <= 10 * e_fp64 + 1e-12, (f, e_gpu, e_fp64)
+    print("full-size 3D mixed form, per-field error (mixed, FP64 at the same tol):", report)
+
+
+def test_full_size_2d_system_matches_oracle(oracle_lib, gea_mod):
+    """nonsmooth2d_2048 (4.2 M cells, the benchmark's 2D mesh): the initial
+    state, then after two steps of the refinement form the assembled pressure
+    system and the operator against the oracle on the GPU's own state, and the
+    true FP64 residual of the GPU's solve"""
+    cfg = configs.get("nonsmooth2d_2048", tol=1e-8, max_iter=200000)
+    cfg["params"]["inner_tol"] = 1e-4
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+    s = O.init_bubble(**cfg["bubble"])
+    S = gea_mod.Solver(cfg["mesh"], cfg["params"], solver="mixed")
+    S.init_bubble(**cfg["bubble"])
+    g = S.state()
+    for f in FIELDS:
+        assert rel(g[f], getattr(s, f)) <= 1e-13, f
+    S.step(2)
+    g = S.state()
+    s2 = oracle_lib.State(*(np.ascontiguousarray(a) for a in
+                            (g["rho"], g["u"], g["T"], g["pp"], g["p"], s.Tbg)))
+    c, D, b = O.pressure_system(s2)
+    x = np.ascontiguousarray(g["pp"]).copy()
+    st = S.pressure_solve(x)
+    assert st.status == 0
+    sysf = S.get_fields(gea_mod.FIELD_C | gea_mod.FIELD_D | gea_mod.FIELD_B)
+    assert rel(sysf[0], c) <= 1e-14
+    assert rel(sysf[1], D) <= 1e-14
+    assert rel(sysf[2], b) <= 1e-12
+    v = np.random.default_rng(1).normal(size=O.nc)
+    y = np.empty_like(v)
+    S.apply_A(v, y)
+    assert rel(y, O.apply_A(c, D, v)) <= 1e-14
+    r = b - O.apply_A(c, D, x)
+    assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)

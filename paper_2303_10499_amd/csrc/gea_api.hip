@@ -266,11 +266,15 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->sc = cv.take<CgScalars>(1);
   x->sc32 = cv.take<CgScalars>(1);
   const int ns = spmv_grid(make_geo(m));
+  // update partials: one per workgroup of the update grid (at most 2048) or
+  // of the set-up kernels' column-tile grid, two values each
+  const int nzb = zplan(make_geo(m)).blocks;
+  const int nu = nzb > 2048 ? nzb : 2048;
   for (CgWork* w : {&x->w64, &x->w32}) {
     w->s = cv.take<double>(ns);
-    w->u[0] = cv.take<double>(2 * 2048);
-    w->u[1] = cv.take<double>(2 * 2048);
-    w->b = cv.take<double>(2048);
+    w->u[0] = cv.take<double>(2 * nu);
+    w->u[1] = cv.take<double>(2 * nu);
+    w->b = cv.take<double>(nu);
   }
   x->w64.sc = x->sc;
   x->w32.sc = x->sc32;

@@ -127,22 +127,70 @@ __device__ __forceinline__ bool spmv_prologue(const double* u_part, int nu, int 
   return false;
 }
 
+// A x at the cells of a column walking up through z: x and D of the planes
+// below, at and above the current one stay in registers, x/y neighbours
+// come from the caches.  The terms are summed in the order of apply_A_at.
+template <int NDIM, typename T>
+struct ColumnA {
+  const T* x;
+  const T* D;
+  T xm, xc, xp, dm, dc, dp;
+  int nz, pl;
+  __device__ void start(const Col& c, int P) {
+    xm = c.k0 > 0 ? x[P - pl] : T(0);
+    dm = c.k0 > 0 ? D[P - pl] : T(0);
+    xc = x[P];
+    dc = D[P];
+  }
+  // A x at cell P of plane k (loads the plane above first)
+  __device__ T at(const Geo& G, const Stencil<NDIM, T>& K, const Col& c, int P, int k,
+                  const T* __restrict__ cc) {
+    constexpr int Z = NDIM - 1;
+    xp = k + 1 < nz ? x[P + pl] : T(0);
+    dp = k + 1 < nz ? D[P + pl] : T(0);
+    T acc = cc[P] * xc;
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int st = G.st[d], q = coord(c, d);
+      if (q + 1 < G.n[d]) acc += T(0.5) * (dc + D[P + st]) * K.k[d] * (xc - x[P + st]);
+      if (q > 0) acc += T(0.5) * (D[P - st] + dc) * K.k[d] * (xc - x[P - st]);
+    }
+    if (k + 1 < nz) acc += T(0.5) * (dc + dp) * K.k[Z] * (xc - xp);
+    if (k > 0) acc += T(0.5) * (dm + dc) * K.k[Z] * (xc - xm);
+    return acc;
+  }
+  __device__ void next() {
+    xm = xc;
+    dm = dc;
+    xc = xp;
+    dc = dp;
+  }
+};
+
 // r = b - A x, p_old = 0; partials (<r, r/diag>, <r, r>) -> u_part, <b, b> -> b_part
+// (column tiles: one partial per workgroup of the z-marching grid)
 template <int NDIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_init(Geo G, Stencil<NDIM, T> K, CgVectors<T> v,
-                                                    double* u_part, double* b_part) {
+                                                    int kc, double* u_part, double* b_part) {
   double red[2] = {0.0, 0.0};
   double bb[1] = {0.0};
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
-    const T r = v.b[P] - apply_A_at<NDIM, T>(G, K, c, P, v.c, v.D, v.x);
-    v.r[P] = r;
-    v.p0[P] = T(0);
-    const double rd = (double)r;
-    red[0] += rd * (double)(r * v.dinv[P]);
-    red[1] += rd * rd;
-    bb[0] += (double)v.b[P] * (double)v.b[P];
+  const Col c = col_of<NDIM>(G, kc);
+  if (c.act) {
+    ColumnA<NDIM, T> A{v.x, v.D};
+    A.nz = G.n[NDIM - 1];
+    A.pl = c.pl;
+    int P = c.base + c.pl * c.k0;
+    A.start(c, P);
+    for (int k = c.k0; k < c.k1; ++k, P += c.pl) {
+      const T r = v.b[P] - A.at(G, K, c, P, k, v.c);
+      A.next();
+      v.r[P] = r;
+      v.p0[P] = T(0);
+      const double rd = (double)r;
+      red[0] += rd * (double)(r * v.dinv[P]);
+      red[1] += rd * rd;
+      bb[0] += (double)v.b[P] * (double)v.b[P];
+    }
   }
   store_partials<2>(red, u_part);
   store_partials<1>(bb, b_part);
@@ -449,23 +497,31 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ r64,
-                                                       CgVectors<float> v32, double* o_part,
-                                                       double* i_part) {
+                                                       CgVectors<float> v32, int kc,
+                                                       double* o_part, double* i_part) {
   double ro[2] = {0.0, 0.0};
   double ri[2] = {0.0, 0.0};
-  GEA_FOR_CELLS(P, G) {
-    int cc[NDIM];
-    cell_coords<NDIM>(G, P, cc);
-    const double r = b[P] - apply_A_at<NDIM, double>(G, K, cc, P, c, D, x);
-    r64[P] = r;
-    const float rf = (float)r;
-    v32.r[P] = rf;
-    v32.x[P] = 0.0f;
-    v32.p0[P] = 0.0f;
-    ro[0] += r * r;
-    ro[1] += b[P] * b[P];
-    ri[0] += (double)rf * (double)(rf * v32.dinv[P]);
-    ri[1] += (double)rf * (double)rf;
+  const Col col = col_of<NDIM>(G, kc);
+  if (col.act) {
+    ColumnA<NDIM, double> A{x, D};
+    A.nz = G.n[NDIM - 1];
+    A.pl = col.pl;
+    int P = col.base + col.pl * col.k0;
+    A.start(col, P);
+    for (int k = col.k0; k < col.k1; ++k, P += col.pl) {
+      const double bp = b[P];
+      const double r = bp - A.at(G, K, col, P, k, c);
+      A.next();
+      r64[P] = r;
+      const float rf = (float)r;
+      v32.r[P] = rf;
+      v32.x[P] = 0.0f;
+      v32.p0[P] = 0.0f;
+      ro[0] += r * r;
+      ro[1] += bp * bp;
+      ri[0] += (double)rf * (double)(rf * v32.dinv[P]);
+      ri[1] += (double)rf * (double)rf;
+    }
   }
   store_partials<2>(ro, o_part);
   store_partials<2>(ri, i_part);
@@ -546,15 +602,20 @@ int spmv_grid(const Geo& G) {
   return ((G.nx + kTX2 - 1) / kTX2) * ((G.nz + kKC2 - 1) / kKC2);
 }
 
+// Partials in the slot iteration 0 reads were written by the set-up kernel
+// (the initial residual, one per workgroup of the column-tile grid); later
+// slots by the update kernel (one per workgroup of its grid-stride grid).
+int partials_for(const Geo& G, int iter) { return iter == 0 ? zplan(G).blocks : grid_for(G.nc); }
+
 template <typename T>
 void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w, double tol,
              int max_iter) {
-  const int gu = grid_for(G.nc);
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL((k_cg_init<2, T>), dim3(gu), dim3(kBlock), 0, s, G, stencil<2, T>(G), v, w.u[1], w.b);
+    hipLaunchKernelGGL((k_cg_init<2, T>), dim3(zp.blocks), dim3(kBlock), 0, s, G, stencil<2, T>(G), v, zp.kc, w.u[1], w.b);
   else
-    hipLaunchKernelGGL((k_cg_init<3, T>), dim3(gu), dim3(kBlock), 0, s, G, stencil<3, T>(G), v, w.u[1], w.b);
-  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[1], gu,
+    hipLaunchKernelGGL((k_cg_init<3, T>), dim3(zp.blocks), dim3(kBlock), 0, s, G, stencil<3, T>(G), v, zp.kc, w.u[1], w.b);
+  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[1], zp.blocks,
                      (const double*)w.b, 1, tol * tol, max_iter, 0, w.sc);
 }
 
@@ -562,7 +623,7 @@ template <typename T>
 void cg_spmv(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w) {
   const T* p_old = (iter & 1) ? v.p1 : v.p0;
   T* p_new = (iter & 1) ? v.p0 : v.p1;
-  const int gu = grid_for(G.nc);
+  const int gu = partials_for(G, iter);
   const double* up = w.u[(iter + 1) & 1];
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_cg_spmv2<T>, dim3(spmv_grid(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), v, p_old, p_new, iter, up, gu, w.s, w.sc);
@@ -581,7 +642,7 @@ void cg_check(hipStream_t s, const Geo& G, int iter, const CgWork& w) {
   // the residual after `iter` completed iterations sits in the partials of
   // update iter-1, i.e. slot (iter + 1) & 1
   hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[(iter + 1) & 1],
-                     grid_for(G.nc), (const double*)nullptr, 0, 0.0, 0, iter, w.sc);
+                     partials_for(G, iter), (const double*)nullptr, 0, 0.0, 0, iter, w.sc);
 }
 
 template void cg_init<double>(hipStream_t, const Geo&, const CgVectors<double>&, const CgWork&, double, int);
@@ -604,12 +665,13 @@ void launch_residual64(hipStream_t s, const Geo& G, const double* c, const doubl
                        const double* b, const double* x, double* r64,
                        const CgVectors<float>& v32, double tol, double inner_tol, int inner_max,
                        double* o_part, const CgWork& w32, CgScalars* sc64) {
-  const int gu = grid_for(G.nc);
+  const ZPlan zp = zplan(G);
+  const int gu = zp.blocks;
   const dim3 grid(gu), block(kBlock);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, r64, v32, o_part, w32.u[1]);
+    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, r64, v32, zp.kc, o_part, w32.u[1]);
   else
-    hipLaunchKernelGGL(k_residual64<3>, grid, block, 0, s, G, stencil<3, double>(G), c, D, b, x, r64, v32, o_part, w32.u[1]);
+    hipLaunchKernelGGL(k_residual64<3>, grid, block, 0, s, G, stencil<3, double>(G), c, D, b, x, r64, v32, zp.kc, o_part, w32.u[1]);
   hipLaunchKernelGGL(k_residual_check, dim3(1), block, 0, s, (const double*)o_part,
                      (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, inner_max,
                      sc64, w32.sc);

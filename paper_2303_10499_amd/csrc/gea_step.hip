@@ -43,54 +43,6 @@ __device__ __forceinline__ double kinetic(const Vec<NDIM>& u, int P) {
   return 0.5 * k;
 }
 
-// ---- z-marching column tiles --------------------------------------------------
-//
-// A workgroup owns a TX x TY column of cells (TX cells of one row in 2D) and
-// marches it through kc consecutive planes along z; each thread walks one
-// vertical column.  Values along z stay in registers (a short queue shifted
-// once per plane), the flux through the face below a cell is the one the
-// same thread formed one plane earlier, and x/y neighbours come from the
-// caches: the workgroup's own rows and the halo rows of the neighbouring
-// columns, which the XCD-aware block order keeps on the same XCD.
-
-template <int NDIM>
-struct ZTile;
-template <>
-struct ZTile<3> {
-  static constexpr int TX = 64, TY = 4, KC = 32;
-};
-template <>
-struct ZTile<2> {
-  static constexpr int TX = 256, TY = 1, KC = 8;
-};
-
-struct Col {
-  int i, j;      // x (and y) coordinates of the column
-  int k0, k1;    // planes [k0, k1) of the chunk
-  int base;      // cell index of the column at k = 0
-  int pl;        // index stride between planes
-  bool act;      // inside the mesh
-};
-
-template <int NDIM>
-__device__ __forceinline__ Col col_of(const Geo& G, int kc) {
-  using T = ZTile<NDIM>;
-  const int ntx = (G.nx + T::TX - 1) / T::TX;
-  const int nty = NDIM == 3 ? (G.ny + T::TY - 1) / T::TY : 1;
-  const int b = xcd_block();
-  const int bx = b % ntx, by = (b / ntx) % nty, bk = b / (ntx * nty);
-  const int nz = G.n[NDIM - 1];
-  Col c;
-  c.i = bx * T::TX + (int)threadIdx.x % T::TX;
-  c.j = NDIM == 3 ? by * T::TY + (int)threadIdx.x / T::TX : 0;
-  c.k0 = bk * kc;
-  c.k1 = min(c.k0 + kc, nz);
-  c.pl = G.st[NDIM - 1];
-  c.base = NDIM == 3 ? c.i + G.nx * c.j : c.i;
-  c.act = c.i < G.nx && (NDIM == 2 || c.j < G.ny) && c.k0 < nz;
-  return c;
-}
-
 // Five consecutive values of a cell field along one direction, centred on
 // the cell; entries outside the mesh are never used and left 0.
 struct Line {
@@ -133,8 +85,6 @@ __device__ __forceinline__ void visc_add(double& acc, const Line& s, int q, int 
   else if (normal) acc += 2.0 * k * (0.0 - s.c);
 }
 
-// coordinate of the column along an x/y direction
-__device__ __forceinline__ int coord(const Col& c, int d) { return d == 0 ? c.i : c.j; }
 
 // ---- Step 1 ----------------------------------------------------------------
 

@@ -212,6 +212,8 @@ Geo make_geo(const gea_mesh& m) {
     G.n[1] = m.ny; G.st[1] = m.nx;        G.h[1] = dy; G.S[1] = dx * dz;
     G.n[2] = m.nz; G.st[2] = m.nx * m.ny; G.h[2] = dz; G.S[2] = dx * dy;
   }
+  for (int d = 0; d < kMaxDim; ++d) G.inv_h[d] = G.h[d] > 0 ? 1.0 / G.h[d] : 0.0;
+  G.inv_V = 1.0 / G.V;
   return G;
 }
 
@@ -337,7 +339,7 @@ gea_status check_params(const gea_mesh* m, const gea_params* q, std::string& err
 void setup_geometry(gea_ctx* x) {
   x->G = make_geo(x->mesh);
   const gea_params& q = x->prm;
-  x->ph = Phys{q.R, q.cp, q.cv, q.g, q.mu, q.Pr, q.dt, q.p0, q.theta0};
+  x->ph = Phys{q.R, q.cp, q.cv, q.g, q.mu, q.Pr, q.dt, q.p0, q.theta0, 1.0 / q.dt, 1.0 / q.cv};
 }
 
 void read_scalars(gea_ctx* x, CgScalars* dev, CgScalars* host) {

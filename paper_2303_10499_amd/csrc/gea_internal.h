@@ -22,10 +22,13 @@ struct Geo {
   double S[kMaxDim];       // area of the faces normal to d
   double V;                // cell volume
   double dz;
+  double inv_h[kMaxDim];   // 1/h (0 for an absent direction)
+  double inv_V;            // 1/V
 };
 
 struct Phys {
   double R, cp, cv, g, mu, Pr, dt, p0, theta0;
+  double inv_dt, inv_cv;   // 1/dt, 1/c_v
 };
 
 template <int NDIM, typename T = double>

@@ -31,8 +31,8 @@ template <int NDIM>
 __device__ __forceinline__ double force_face(const Geo& G, const Phys& ph, const double* pp,
                                              const double* rho, int Q, int d, int cq, int kz) {
   const int st = G.st[d];
-  return ((pp[Q + st] - pp[Q]) - phi_face<NDIM>(G, ph, d, cq, kz) * (rho[Q + st] - rho[Q])) /
-         G.h[d];
+  return ((pp[Q + st] - pp[Q]) - phi_face<NDIM>(G, ph, d, cq, kz) * (rho[Q + st] - rho[Q])) *
+         G.inv_h[d];
 }
 
 template <int NDIM>
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
   const double kvz = ph.mu * G.S[Z] / G.h[Z];
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
     const double Fhi = k + 1 < nz ? force_face<NDIM>(G, ph, pp, rho, P, Z, k, k) : 0.0;
-    const double r = rho[P], rs = rho_star[P], phz = phi.p[Z][P];
+    const double r = rho[P], inv_rs = 1.0 / rho_star[P], phz = phi.p[Z][P];
     double fhi_d[NDIM - 1], flo_d[NDIM - 1];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
         RF = 0.5 * (lo + hi);
       }
       const double mom = r * z[cc].c - ph.dt / G.V * (conv - visc) - ph.dt * RF;
-      u_star.p[cc][P] = mom / rs;
+      u_star.p[cc][P] = mom * inv_rs;
       z[cc] = shift(z[cc], k + 3 < nz ? uc[P + 3 * pl] : 0.0);
     }
     Flo = Fhi;
@@ -266,19 +266,19 @@ __global__ __launch_bounds__(kBlock) void k_energy_sweep(
     }
     if (k + 1 < nz) diff += kdz * ((zT.p1 - Tbg[k + 1]) - Tp);
     if (k > 0) diff += kdz * ((zT.m1 - Tbg[k - 1]) - Tp);
-    const double rs = rho_star[P];
-    const double rhoe = rho[P] * e0[P] - ph.dt / G.V * conv + ph.dt / G.V * diff;
-    const double e = rhoe / rs;
-    const double T = (e - kinetic<NDIM>(u_star, P) - phi_cell(G, ph, k)) / ph.cv;
+    const double inv_rs = 1.0 / rho_star[P];
+    const double rhoe = rho[P] * e0[P] - ph.dt * G.inv_V * conv + ph.dt * G.inv_V * diff;
+    const double e = rhoe * inv_rs;
+    const double T = (e - kinetic<NDIM>(u_star, P) - phi_cell(G, ph, k)) * ph.inv_cv;
     e_next[P] = e;
     T_next[P] = T;
     if (last) {
-      const double r23 = p[P] / (ph.R * T);
       const double ps = 1.0 / (ph.R * T);
+      const double r23 = p[P] * ps;
       rho23[P] = r23;
       psi[P] = ps;
-      cc[P] = ps * G.V / ph.dt;
-      D[P] = r23 / (rs / ph.dt);
+      cc[P] = ps * G.V * ph.inv_dt;
+      D[P] = r23 * ph.dt * inv_rs;
     }
     const bool more = k + 3 < nz;
     ze = shift(ze, more ? e_prev[P + 3 * pl] : 0.0);
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
       for (int d = 0; d < Z; ++d)
         visc_add(visc, s[d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
       visc_add(visc, z[cc], k, nz, kvz, cc == Z);
-      H.p[cc][P] = r * u.p[cc][P] / ph.dt - conv / G.V + visc / G.V;
+      H.p[cc][P] = r * u.p[cc][P] * ph.inv_dt - conv * G.inv_V + visc * G.inv_V;
       z[cc] = shift(z[cc], k + 3 < nz ? uc[P + 3 * pl] : 0.0);
     }
   }
@@ -355,7 +355,7 @@ __device__ __forceinline__ double phi_tilde(const Geo& G, const Phys& ph, const 
   const int st = G.st[d];
   const double Df = 0.5 * (D[Q] + D[Q + st]);
   const double Hf = 0.5 * (Hd[Q] + Hd[Q + st]);
-  return Df * G.S[d] * (Hf + phi_face<NDIM>(G, ph, d, cq, kz) * (rho23[Q + st] - rho23[Q]) / G.h[d]);
+  return Df * G.S[d] * (Hf + phi_face<NDIM>(G, ph, d, cq, kz) * (rho23[Q + st] - rho23[Q]) * G.inv_h[d]);
 }
 
 // b = (V/dt)(rho^n + psi rho23 Phi) - sum_out phitilde; 1/diag of the operator
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_correct(
       }
     }
     for (int k = c.k0; k < c.k1; ++k, P += pl) {
-      const double A = rho_star[P] / ph.dt;
+      const double inv_A = ph.dt / rho_star[P];
       const double Fhi = k + 1 < nz ? force_face<NDIM>(G, ph, pp, rho23, P, Z, k, k) : 0.0;
       bool finite = true;
 #pragma unroll
@@ -454,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_correct(
           const double lo = q > 0 ? force_face<NDIM>(G, ph, pp, rho23, P - st, cmp, q - 1, k) : 0.0;
           RF = 0.5 * (lo + hi);
         }
-        const double un = (H.p[cmp][P] - RF) / A;
+        const double un = (H.p[cmp][P] - RF) * inv_A;
         u_out.p[cmp][P] = un;
         finite = finite && isfinite(un);
       }

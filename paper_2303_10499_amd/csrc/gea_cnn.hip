@@ -175,6 +175,44 @@ struct ConvTile {
   static constexpr int MTW = MT / 4;                   // per wave
 };
 
+// bf16 output of a convolution tile through LDS: every lane writes its
+// accumulator values (+bias, ReLU) as [cell][channel] into `buf` (PX cells of
+// the tile, COUT channels), then the workgroup stores whole 16-byte channel
+// groups, consecutive lanes covering consecutive bytes of Y.  The caller
+// synchronises before (buf may alias the staged input).
+template <int NDIM, int COUT, int MTW, int TX, int TY, int TZ>
+__device__ __forceinline__ void store_relu_tile(const f32x4 (&acc)[MTW][COUT / 16], const float* __restrict__ bias,
+                                                bf16_t* buf, const CnnDims& d, int ox, int oy, int oz,
+                                                bf16_t* __restrict__ Y) {
+  constexpr int PX = TX * TY * TZ;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+#pragma unroll
+  for (int m = 0; m < MTW; ++m) {
+    const int mt = wave * MTW + m;
+#pragma unroll
+    for (int nt = 0; nt < COUT / 16; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = mt * 16 + 4 * g + i;  // cell of the tile: M tile mt, row position 4g+i
+        const int co = nt * 16 + r;
+        buf[q * COUT + co] = f2bf(fmaxf(acc[m][nt][i] + bias[co], 0.f));
+      }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < PX * (COUT / 8); e += 256) {
+    const int q = e / (COUT / 8), c8 = (e % (COUT / 8)) * 8;
+    const int mt = q / 16, x16 = q % 16;
+    const int seg = mt % (TX / 16), row = mt / (TX / 16);
+    const int gx = ox + seg * 16 + x16;
+    const int gy = oy + (NDIM == 3 ? row % TY : 0), gz = oz + (NDIM == 3 ? row / TY : row);
+    if (gx < d.nx && gy < d.ny && gz < d.nz) {
+      const size_t p = (size_t)gx + (size_t)d.nx * (gy + (size_t)d.ny * gz);
+      *reinterpret_cast<uint4*>(Y + p * COUT + c8) = *reinterpret_cast<const uint4*>(buf + q * COUT + c8);
+    }
+  }
+}
+
 // Forward convolution through an LDS-staged input tile.  CA = 0: input X
 // with CIN channels; CA > 0: the channel concatenation [up(A), X] of a
 // coarse tensor A (CA channels, nearest-upsampled) and a fine tensor X
@@ -192,7 +230,9 @@ __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restr
   constexpr int KPAD = KC * 32;
   constexpr int NTILE = COUT / 16;
   constexpr int CF = T::CF;
-  __shared__ __attribute__((aligned(16))) bf16_t sIn[T::LDS];
+  constexpr int PX = T::TX * T::TY * T::TZ;
+  constexpr int LDSN = T::LDS > PX * COUT ? T::LDS : PX * COUT;  // input tile, then output tile
+  __shared__ __attribute__((aligned(16))) bf16_t sIn[LDSN];
   const int ntx = (d.nx + T::TX - 1) / T::TX;
   const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
   // XCD-aware order: neighbouring tiles (which re-read each other's halo
@@ -309,6 +349,12 @@ __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restr
           acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[m], b1[nt], acc[m][nt], 0, 0, 0);
     }
   }
+  if (MODE == 0) {
+    __syncthreads();  // every wave is done with the staged input
+    store_relu_tile<NDIM, COUT, T::MTW, T::TX, T::TY, T::TZ>(acc, bias, sIn, d, ox, oy, oz,
+                                                            reinterpret_cast<bf16_t*>(Y));
+    return;
+  }
 #pragma unroll
   for (int m = 0; m < T::MTW; ++m) {
     const int gy = oy + lym[m], gz = oz + lzm[m];
@@ -321,16 +367,86 @@ __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restr
         const int co = nt * 16 + r;
         if (gx < d.nx && gy < d.ny && gz < d.nz && co < ycount) {
           const size_t p = (size_t)gx + (size_t)d.nx * (gy + (size_t)d.ny * gz);
-          float v = acc[m][nt][i] + bias[co];
-          if (MODE == 0) {
-            v = fmaxf(v, 0.f);
-            reinterpret_cast<bf16_t*>(Y)[p * ystride + co] = f2bf(v);
-          } else {
-            reinterpret_cast<float*>(Y)[p * ystride + co] = v;
-          }
+          reinterpret_cast<float*>(Y)[p * ystride + co] = acc[m][nt][i] + bias[co];
         }
       }
   }
+}
+
+// Layer 0: the input has 2 real channels (r/s and c/diag) stored in 8.  Each
+// staged cell keeps only those 2 (4 bytes) and K is ordered tap x 2 +
+// channel, 54 padded to 64: two 32-wide chunks cover all 27 taps (instead of
+// seven chunks of 8-channel taps), each lane's 8 K-values being 4 taps x 2
+// channels from four 4-byte LDS reads.  W0 holds the weights in that order.
+template <int NDIM>
+__global__ __launch_bounds__(256) void k_conv0(CnnDims d, const bf16_t* __restrict__ X,
+                                               const bf16_t* __restrict__ W0,
+                                               const float* __restrict__ bias,
+                                               bf16_t* __restrict__ Y) {
+  using T = ConvTile<NDIM, 8, 0>;
+  constexpr int NT = Taps<NDIM>::n;
+  constexpr int KC = (NT * 2 + 31) / 32;
+  constexpr int KPAD = KC * 32;
+  __shared__ uint32_t s2[T::HP];
+  __shared__ __attribute__((aligned(16))) bf16_t sOut[T::TX * T::TY * T::TZ * 16];
+  const int ntx = (d.nx + T::TX - 1) / T::TX;
+  const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
+  const int b = xcd_block();
+  const int ox = (b % ntx) * T::TX;
+  const int oy = NDIM == 3 ? ((b / ntx) % nty) * T::TY : 0;
+  const int oz = (b / (ntx * nty)) * T::TZ;
+  for (int hp = threadIdx.x; hp < T::HP; hp += 256) {
+    const int hx = hp % T::HX, hy = (hp / T::HX) % T::HY, hz = hp / (T::HX * T::HY);
+    const int gx = ox + hx - 1, gy = NDIM == 3 ? oy + hy - 1 : 0, gz = oz + hz - 1;
+    uint32_t v = 0;
+    if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
+      v = *reinterpret_cast<const uint32_t*>(X + (size_t)(gx + d.nx * (gy + d.ny * gz)) * 8);
+    s2[hp] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  int pix[T::MTW];
+#pragma unroll
+  for (int m = 0; m < T::MTW; ++m) {
+    const int mt = wave * T::MTW + m;
+    const int seg = mt % (T::TX / 16), row = mt / (T::TX / 16);
+    const int lx = seg * 16 + r;
+    const int ly = NDIM == 3 ? row % T::TY : 0, lz = NDIM == 3 ? row / T::TY : row;
+    pix[m] = (lx + 1) + T::HX * ((NDIM == 3 ? ly + 1 : 0) + T::HY * (lz + 1));
+  }
+  f32x4 acc[T::MTW];
+#pragma unroll
+  for (int m = 0; m < T::MTW; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    const int t0 = kc * 16 + 4 * g;  // first of this lane group's 4 taps
+    const bf16x8 bw = load8(W0 + (size_t)r * KPAD + kc * 32 + 8 * g);
+    int off[4];
+    bool on[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int t = t0 + i;
+      on[i] = t < NT;
+      const int dx = t % 3 - 1;
+      const int dy = NDIM == 3 ? (t / 3) % 3 - 1 : 0;
+      const int dz = NDIM == 3 ? t / 9 - 1 : t / 3 - 1;
+      off[i] = on[i] ? dx + T::HX * (dy + T::HY * dz) : 0;  // padding taps: a valid cell, value unused
+    }
+#pragma unroll
+    for (int m = 0; m < T::MTW; ++m) {
+      uint4 a;
+      a.x = on[0] ? s2[pix[m] + off[0]] : 0u;
+      a.y = on[1] ? s2[pix[m] + off[1]] : 0u;
+      a.z = on[2] ? s2[pix[m] + off[2]] : 0u;
+      a.w = on[3] ? s2[pix[m] + off[3]] : 0u;
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), bw, acc[m], 0, 0, 0);
+    }
+  }
+  f32x4 acc1[T::MTW][1];
+#pragma unroll
+  for (int m = 0; m < T::MTW; ++m) acc1[m][0] = acc[m];
+  store_relu_tile<NDIM, 16, T::MTW, T::TX, T::TY, T::TZ>(acc1, bias, sOut, d, ox, oy, oz, Y);
 }
 
 template <int NDIM, int CIN>
@@ -642,7 +758,10 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
   hipLaunchKernelGGL((k_conv_t<NDIM, CI, CO, MODE, CAA>), dim3(conv_tiles<NDIM, CI>(d)), bl, 0, s, \
                      d, X, A, n.W[layer], n.bias[layer], Y, YS, YC)
   switch (layer) {
-    case 0: GEA_CONV(8, 16, 0, 0, 16, 16); break;
+    case 0:
+      hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d, X, n.W0,
+                         n.bias[0], (bf16_t*)Y);
+      break;
     case 1: GEA_CONV(16, 32, 0, 0, 32, 32); break;
     case 2: GEA_CONV(32, 64, 0, 0, 64, 64); break;
     case 3: GEA_CONV(96, 32, 0, 64, 32, 32); break;
@@ -838,6 +957,7 @@ size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* bas
     n.Wt[l] = (train && l > 0) ? (bf16_t*)take((size_t)L.cin_t_p * L.kpad_t * B2) : nullptr;
     n.bias[l] = (float*)take((size_t)L.cout_p * F4);
   }
+  n.W0 = (bf16_t*)take((size_t)16 * (((ndim == 3 ? 27 : 9) * 2 + 31) / 32 * 32) * B2);
   n.xin = (bf16_t*)take(N0 * 8 * B2);
   n.xf = (float*)take(N0 * 2 * F4);
   n.e0 = (bf16_t*)take(N0 * 16 * B2);
@@ -889,6 +1009,13 @@ int cnn_loss_partials(const Cnn& n) { return blocks_for(n.d[0].npix) > 1024 ? 10
 
 void cnn_pack_weights(Cnn& n) {
   const int nt = n.ndim == 2 ? 9 : 27;
+  {
+    const CnnLayer& L = n.L[0];
+    const int kp0 = (nt * 2 + 31) / 32 * 32;
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for((long)16 * kp0)), dim3(256), 0, n.s,
+                       (const float*)(n.master + L.woff), (const float*)(n.master + L.boff), L.cin,
+                       L.cout, 2, 16, kp0, 0, 0, nt, n.W0, (bf16_t*)nullptr, n.bias[0]);
+  }
   for (int l = 0; l < kCnnLayers; ++l) {
     const CnnLayer& L = n.L[l];
     const long work = (long)L.cout_p * L.kpad + (long)L.cin_t_p * L.kpad_t;

@@ -44,6 +44,7 @@ struct Cnn {
   float* v = nullptr;
   bf16_t* W[kCnnLayers] = {};
   bf16_t* Wt[kCnnLayers] = {};
+  bf16_t* W0 = nullptr;  // layer 0 weights in the (tap, 2 channels) K order
   float* bias[kCnnLayers] = {};
   // forward activations (bf16, channels last)
   bf16_t *xin, *e0, *p0, *e1, *p1, *e2, *c1, *d1, *c0, *d0;

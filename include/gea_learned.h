@@ -75,7 +75,9 @@ gea_status gea_cnn_adam(gea_cnn* net, float lr, float grad_scale, int32_t step);
 
 /* Test support: an activation of the last forward pass as FP32, channels
  * last: which = 0 input (8 channels, 2 used), 1 e0, 2 pool(e0), 3 e1,
- * 4 pool(e1), 5 e2, 6 [up(e2), e1], 7 d1, 8 [up(d1), e0], 9 d0, 10 y. */
+ * 4 pool(e1), 5 e2, 6 [up(e2), e1], 7 d1, 8 [up(d1), e0], 9 d0, 10 y.
+ * Inference instances (train = 0) keep neither the padded input nor the
+ * concatenations: which = 0, 6 and 8 return GEA_ERR_STATE there. */
 gea_status gea_cnn_activation(gea_cnn* net, int32_t which, float* out, gea_ptr_kind kind);
 
 void gea_cnn_destroy(gea_cnn* net);

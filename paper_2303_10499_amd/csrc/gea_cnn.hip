@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restr
 // seven chunks of 8-channel taps), each lane's 8 K-values being 4 taps x 2
 // channels from four 4-byte LDS reads.  W0 holds the weights in that order.
 template <int NDIM>
-__global__ __launch_bounds__(256) void k_conv0(CnnDims d, const bf16_t* __restrict__ X,
+__global__ __launch_bounds__(256) void k_conv0(CnnDims d, const uint32_t* __restrict__ X2,
                                                const bf16_t* __restrict__ W0,
                                                const float* __restrict__ bias,
                                                bf16_t* __restrict__ Y) {
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_conv0(CnnDims d, const bf16_t* __restri
     const int gx = ox + hx - 1, gy = NDIM == 3 ? oy + hy - 1 : 0, gz = oz + hz - 1;
     uint32_t v = 0;
     if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
-      v = *reinterpret_cast<const uint32_t*>(X + (size_t)(gx + d.nx * (gy + d.ny * gz)) * 8);
+      v = X2[gx + d.nx * (gy + d.ny * gz)];
     s2[hp] = v;
   }
   __syncthreads();
@@ -660,28 +660,36 @@ __global__ __launch_bounds__(256) void k_loss(int npix, const float* __restrict_
   if (threadIdx.x == 0) lpart[blockIdx.x] = a[0];
 }
 
-__global__ __launch_bounds__(256) void k_input_f32(int npix, const float* __restrict__ xf,
-                                                   bf16_t* __restrict__ xin) {
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x) {
+// the network input of a cell: x2 (2 channels, what layer 0 reads) and, in
+// training instances, xin (the same padded to 8 channels, for the weight
+// gradients of layer 0)
+__device__ __forceinline__ void put_input(int p, float a, float b, uint32_t* __restrict__ x2,
+                                          bf16_t* __restrict__ xin) {
+  const bf16_t ha = f2bf(a), hb = f2bf(b);
+  x2[p] = (uint32_t)ha | ((uint32_t)hb << 16);
+  if (xin) {
     bf16_t* o = xin + (size_t)p * 8;
-    o[0] = f2bf(xf[2 * p]);
-    o[1] = f2bf(xf[2 * p + 1]);
+    o[0] = ha;
+    o[1] = hb;
     for (int c = 2; c < 8; ++c) o[c] = 0;
   }
+}
+
+__global__ __launch_bounds__(256) void k_input_f32(int npix, const float* __restrict__ xf,
+                                                   uint32_t* __restrict__ x2, bf16_t* __restrict__ xin) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x)
+    put_input(p, xf[2 * p], xf[2 * p + 1], x2, xin);
 }
 
 __global__ __launch_bounds__(256) void k_input_residual(int npix, const float* __restrict__ r,
                                                         const double* __restrict__ inv_s,
                                                         const float* __restrict__ c,
                                                         const float* __restrict__ dinv,
+                                                        uint32_t* __restrict__ x2,
                                                         bf16_t* __restrict__ xin) {
   const float is = (float)*inv_s;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x) {
-    bf16_t* o = xin + (size_t)p * 8;
-    o[0] = f2bf(r[p] * is);
-    o[1] = f2bf(c[p] * dinv[p]);
-    for (int k = 2; k < 8; ++k) o[k] = 0;
-  }
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x)
+    put_input(p, r[p] * is, c[p] * dinv[p], x2, xin);
 }
 
 __global__ __launch_bounds__(256) void k_scale_output(int npix, const float* __restrict__ y,
@@ -759,8 +767,8 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
                      d, X, A, n.W[layer], n.bias[layer], Y, YS, YC)
   switch (layer) {
     case 0:
-      hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d, X, n.W0,
-                         n.bias[0], (bf16_t*)Y);
+      hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d,
+                         (const uint32_t*)n.x2, n.W0, n.bias[0], (bf16_t*)Y);
       break;
     case 1: GEA_CONV(16, 32, 0, 0, 32, 32); break;
     case 2: GEA_CONV(32, 64, 0, 0, 64, 64); break;
@@ -958,7 +966,8 @@ size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* bas
     n.bias[l] = (float*)take((size_t)L.cout_p * F4);
   }
   n.W0 = (bf16_t*)take((size_t)16 * (((ndim == 3 ? 27 : 9) * 2 + 31) / 32 * 32) * B2);
-  n.xin = (bf16_t*)take(N0 * 8 * B2);
+  n.x2 = (uint32_t*)take(N0 * 4);
+  n.xin = train ? (bf16_t*)take(N0 * 8 * B2) : nullptr;
   n.xf = (float*)take(N0 * 2 * F4);
   n.e0 = (bf16_t*)take(N0 * 16 * B2);
   n.p0 = (bf16_t*)take(N1 * 16 * B2);
@@ -1028,13 +1037,13 @@ void cnn_pack_weights(Cnn& n) {
 
 void cnn_input_from_f32(Cnn& n) {
   hipLaunchKernelGGL(k_input_f32, dim3(blocks_for(n.d[0].npix)), dim3(256), 0, n.s, n.d[0].npix,
-                     (const float*)n.xf, n.xin);
+                     (const float*)n.xf, n.x2, n.xin);
 }
 
 void cnn_input_from_residual(Cnn& n, const float* r, const double* inv_s, const float* c,
                              const float* dinv) {
   hipLaunchKernelGGL(k_input_residual, dim3(blocks_for(n.d[0].npix)), dim3(256), 0, n.s,
-                     n.d[0].npix, r, inv_s, c, dinv, n.xin);
+                     n.d[0].npix, r, inv_s, c, dinv, n.x2, n.xin);
 }
 
 void cnn_scale_output(Cnn& n, const double* s, float* out, int accumulate) {
@@ -1217,7 +1226,7 @@ gea_status gea_cnn_activation(gea_cnn* x, int32_t which, float* out, gea_ptr_kin
     return hip_status(x, hipStreamSynchronize(n.s), "activation");
   }
   if (!src[which]) {
-    x->err = "the concatenated inputs are kept by training instances only";
+    x->err = "the padded input and the concatenated inputs are kept by training instances only";
     return GEA_ERR_STATE;
   }
   const long count = (long)n.d[lev[which]].npix * ch[which];

@@ -47,7 +47,8 @@ struct Cnn {
   bf16_t* W0 = nullptr;  // layer 0 weights in the (tap, 2 channels) K order
   float* bias[kCnnLayers] = {};
   // forward activations (bf16, channels last)
-  bf16_t *xin, *e0, *p0, *e1, *p1, *e2, *c1, *d1, *c0, *d0;
+  uint32_t* x2;  // input, 2 bf16 channels per cell (what layer 0 reads)
+  bf16_t *xin, *e0, *p0, *e1, *p1, *e2, *c1, *d1, *c0, *d0;  // xin: input padded to 8 (training)
   float* y;   // output, 1 channel
   float* xf;  // FP32 staging of the 2-channel input
   // backward

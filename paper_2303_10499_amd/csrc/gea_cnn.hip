@@ -449,6 +449,106 @@ __global__ __launch_bounds__(256) void k_conv0(CnnDims d, const uint32_t* __rest
   store_relu_tile<NDIM, 16, T::MTW, T::TX, T::TY, T::TZ>(acc1, bias, sOut, d, ox, oy, oz, Y);
 }
 
+// Layer 5 (16 channels -> 1): y[p] = b + sum_t sum_c d0[p + off_t][c] W[t][c].
+// A convolution with one output channel would use 1/16 of each MFMA's
+// columns, so the taps take the N dimension instead: for every staged cell h
+// of the tile and its halo, z[h][t] = sum_c d0[h][c] W[t][c] is one 16-cell x
+// 32-tap MFMA tile (K = the 16 channels, zero-padded to 32), kept in FP32 in
+// LDS; then each output cell sums z[p + off_t][t] over the taps.  W5 holds
+// W^T as [tap (32, zero-padded)][16 channels].
+template <int NDIM>
+struct Conv5Tile {  // used in 2D
+  static constexpr int TX = NDIM == 3 ? 16 : 64, TY = NDIM == 3 ? 4 : 1, TZ = NDIM == 3 ? 2 : 4;
+  static constexpr int HX = TX + 2, HY = NDIM == 3 ? TY + 2 : 1, HZ = TZ + 2;
+  static constexpr int HP = HX * HY * HZ;
+  static constexpr int HPM = (HP + 15) / 16 * 16;  // staged cells, padded to whole M tiles
+  static constexpr int NT = NDIM == 3 ? 27 : 9;
+  static constexpr int ZS = NT;                     // z row stride (odd: no bank conflicts in the gather)
+  static constexpr int DS = 24;                     // staged d0 stride (bf16)
+  static constexpr int PX = TX * TY * TZ;
+};
+
+template <int NDIM>
+__global__ __launch_bounds__(256) void k_conv5(CnnDims d, const bf16_t* __restrict__ X,
+                                               const bf16_t* __restrict__ W5,
+                                               const float* __restrict__ bias,
+                                               float* __restrict__ Y) {
+  using T = Conv5Tile<NDIM>;
+  __shared__ __attribute__((aligned(16))) bf16_t sx[T::HPM * T::DS];
+  __shared__ float sz[T::HPM * T::ZS];
+  const int ntx = (d.nx + T::TX - 1) / T::TX;
+  const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
+  const int b = xcd_block();
+  const int ox = (b % ntx) * T::TX;
+  const int oy = NDIM == 3 ? ((b / ntx) % nty) * T::TY : 0;
+  const int oz = (b / (ntx * nty)) * T::TZ;
+  // stage d0 (2 groups of 8 channels per cell; zeros outside the grid and
+  // in the padding cells)
+  constexpr int NIT = (T::HPM * 2 + 255) / 256;  // all loads issued before the LDS writes
+  uint4 v[NIT];
+#pragma unroll
+  for (int u = 0; u < NIT; ++u) {
+    const int e = threadIdx.x + 256 * u, hp = e >> 1, c8 = (e & 1) * 8;
+    v[u] = make_uint4(0, 0, 0, 0);
+    if (hp < T::HP) {
+      const int hx = hp % T::HX, hy = (hp / T::HX) % T::HY, hz = hp / (T::HX * T::HY);
+      const int gx = ox + hx - 1, gy = NDIM == 3 ? oy + hy - 1 : 0, gz = oz + hz - 1;
+      if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
+        v[u] = *reinterpret_cast<const uint4*>(X + (size_t)(gx + d.nx * (gy + d.ny * gz)) * 16 + c8);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NIT; ++u) {
+    const int e = threadIdx.x + 256 * u, hp = e >> 1, c8 = (e & 1) * 8;
+    if (hp < T::HPM) *reinterpret_cast<uint4*>(sx + hp * T::DS + c8) = v[u];
+  }
+  __syncthreads();
+  // z = d0 W^T on the staged cells: M tiles of 16 cells, N = 32 taps (2 tiles)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  bf16x8 bw[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)  // B[k = 8g + i][n = tap nt*16 + r]; k >= 16 zero
+    bw[nt] = g < 2 ? load8(W5 + (size_t)(nt * 16 + r) * 16 + 8 * g) : zero8();
+  for (int mt = wave; mt < T::HPM / 16; mt += 4) {
+    const bf16x8 a = g < 2 ? __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sx + (mt * 16 + r) * T::DS + 8 * g))
+                           : zero8();
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const f32x4 zt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[nt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      const int t = nt * 16 + r;
+      if (t < T::NT)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sz[(mt * 16 + 4 * g + i) * T::ZS + t] = zt[i];
+    }
+  }
+  __syncthreads();
+  // each output cell: bias + sum over the taps of its neighbours' z
+  for (int q = threadIdx.x; q < T::PX; q += 256) {
+    const int lx = q % T::TX, ly = NDIM == 3 ? (q / T::TX) % T::TY : 0;
+    const int lz = NDIM == 3 ? q / (T::TX * T::TY) : q / T::TX;
+    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+    if (gx >= d.nx || gy >= d.ny || gz >= d.nz) continue;
+    const int h = (lx + 1) + T::HX * ((NDIM == 3 ? ly + 1 : 0) + T::HY * (lz + 1));
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < T::NT; ++t) {
+      const int dx = t % 3 - 1;
+      const int dy = NDIM == 3 ? (t / 3) % 3 - 1 : 0;
+      const int dz = NDIM == 3 ? t / 9 - 1 : t / 3 - 1;
+      acc += sz[(h + dx + T::HX * (dy + T::HY * dz)) * T::ZS + t];
+    }
+    Y[(size_t)gx + (size_t)d.nx * (gy + (size_t)d.ny * gz)] = acc + bias[0];
+  }
+}
+
+template <int NDIM>
+int conv5_tiles(const CnnDims& d) {
+  using T = Conv5Tile<NDIM>;
+  return ((d.nx + T::TX - 1) / T::TX) * (NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1) *
+         ((d.nz + T::TZ - 1) / T::TZ);
+}
+
 template <int NDIM, int CIN>
 int conv_tiles(const CnnDims& d) {
   using T = ConvTile<NDIM, CIN, 0>;
@@ -732,6 +832,15 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ mW, cons
     bias[co] = co < cout ? mb[co] : 0.f;
 }
 
+// layer 5: master W[0][t][c] (1 output channel) -> bf16 W5[t][c], taps padded to 32
+__global__ __launch_bounds__(256) void k_pack5(const float* __restrict__ mW, int ntaps,
+                                               bf16_t* __restrict__ W5) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 32 * 16; e += gridDim.x * blockDim.x) {
+    const int t = e / 16, c = e % 16;
+    W5[e] = f2bf(t < ntaps ? mW[t * 16 + c] : 0.f);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_adam(long n, float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, float lr,
                                               float scale, float bc1, float bc2) {
@@ -774,7 +883,15 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
     case 2: GEA_CONV(32, 64, 0, 0, 64, 64); break;
     case 3: GEA_CONV(96, 32, 0, 64, 32, 32); break;
     case 4: GEA_CONV(48, 16, 0, 32, 16, 16); break;
-    case 5: GEA_CONV(16, 16, 1, 0, 1, 1); break;
+    case 5:
+      // 3D: the taps' z values of a tile with its halo need too much LDS
+      // (measured slower there); the padded-N convolution is kept
+      if (NDIM == 2)
+        hipLaunchKernelGGL((k_conv5<NDIM>), dim3(conv5_tiles<NDIM>(d)), bl, 0, s, d, X, n.W5,
+                           n.bias[5], (float*)Y);
+      else
+        GEA_CONV(16, 16, 1, 0, 1, 1);
+      break;
   }
 #undef GEA_CONV
 }
@@ -966,6 +1083,7 @@ size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* bas
     n.bias[l] = (float*)take((size_t)L.cout_p * F4);
   }
   n.W0 = (bf16_t*)take((size_t)16 * (((ndim == 3 ? 27 : 9) * 2 + 31) / 32 * 32) * B2);
+  n.W5 = (bf16_t*)take((size_t)32 * 16 * B2);
   n.x2 = (uint32_t*)take(N0 * 4);
   n.xin = train ? (bf16_t*)take(N0 * 8 * B2) : nullptr;
   n.xf = (float*)take(N0 * 2 * F4);
@@ -1018,6 +1136,8 @@ int cnn_loss_partials(const Cnn& n) { return blocks_for(n.d[0].npix) > 1024 ? 10
 
 void cnn_pack_weights(Cnn& n) {
   const int nt = n.ndim == 2 ? 9 : 27;
+  hipLaunchKernelGGL(k_pack5, dim3(2), dim3(256), 0, n.s, (const float*)(n.master + n.L[5].woff), nt,
+                     n.W5);
   {
     const CnnLayer& L = n.L[0];
     const int kp0 = (nt * 2 + 31) / 32 * 32;

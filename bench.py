@@ -37,9 +37,11 @@ CLASS_NAMES = {0: "k_cg_spmv<fp64>", 1: "k_cg_update<fp64>", 2: "k_cg_spmv<fp32>
                3: "k_cg_update<fp32>", 4: "solver set-up/check kernels",
                5: "explicit step kernels", 6: "learned network"}
 # the six forward convolutions of the network (bf16 matrix-core kernels)
-LAYER_NAMES = ["k_conv_t L0 (2->16)", "k_conv_t L1 (16->32, 1/2)", "k_conv_t L2 (32->64, 1/4)",
-               "k_conv_t L3 ([64,32]->32, 1/2)", "k_conv_t L4 ([32,16]->16)", "k_conv_t L5 (16->1)"]
+LAYER_NAMES = ["k_conv0 L0 (2->16)", "k_conv_t L1 (16->32, 1/2)", "k_conv_t L2 (32->64, 1/4)",
+               "k_conv_t L3 ([64,32]->32, 1/2)", "k_conv_t L4 ([32,16]->16)", "k_conv5z L5 (16->1)"]
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+# vector bf16 pair dot products (layer 5): 256 CUs x 64 lanes x 2.4 GHz x 4 FLOP
+VALU_DOT2_PEAK_TFLOPS = 157.3
 
 
 def log(msg):
@@ -108,7 +110,8 @@ def run_form(cfg, form, steps, warmup, kernel_steps):
         out["network_applications_per_step"] = apps
         out["network_layer_avg_us"] = {LAYER_NAMES[l]: round(nms[l] * 1e3, 2) for l in range(6)}
         for l in range(6):
-            cands[LAYER_NAMES[l]] = dict(bound="mfma", avg_ms=nms[l], per_step_ms=nms[l] * apps,
+            cands[LAYER_NAMES[l]] = dict(bound="alu" if l == 5 else "mfma", avg_ms=nms[l],
+                                         per_step_ms=nms[l] * apps,
                                          work=ngf[l] * 1e9)
     out["kernel_ms_per_step"] = {k: round(v["per_step_ms"], 4) for k, v in cands.items()}
     if cands:
@@ -125,7 +128,8 @@ def roofline_entry(rr):
         achieved, peak, unit = rr["work"] / t / 1e9, HBM_PEAK_GBS, "GB/s"
         extra = dict(bytes_per_launch=rr["work"])
     else:
-        achieved, peak, unit = rr["work"] / t / 1e12, MFMA_BF16_PEAK_TFLOPS, "TFLOP/s"
+        peak = MFMA_BF16_PEAK_TFLOPS if rr["bound"] == "mfma" else VALU_DOT2_PEAK_TFLOPS
+        achieved, unit = rr["work"] / t / 1e12, "TFLOP/s"
         extra = dict(flop_per_launch=rr["work"])
     return dict(bound=rr["bound"], kernel=rr["kernel"], achieved=round(achieved, 1), peak=peak,
                 unit=unit, frac=round(achieved / peak, 4), avg_launch_us=round(rr["avg_ms"] * 1e3, 2),

@@ -216,14 +216,13 @@ __device__ __forceinline__ void store_relu_tile(const f32x4 (&acc)[MTW][COUT / 1
 // Forward convolution through an LDS-staged input tile.  CA = 0: input X
 // with CIN channels; CA > 0: the channel concatenation [up(A), X] of a
 // coarse tensor A (CA channels, nearest-upsampled) and a fine tensor X
-// (CIN - CA channels).  MODE 0: +bias, ReLU, bf16 out; 1: +bias, FP32 out
-// (first ycount channels).
-template <int NDIM, int CIN, int COUT, int MODE, int CA>
+// (CIN - CA channels).  Output: +bias, ReLU, bf16.
+template <int NDIM, int CIN, int COUT, int CA>
 __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restrict__ X,
                                                 const bf16_t* __restrict__ A,
                                                 const bf16_t* __restrict__ W,
                                                 const float* __restrict__ bias,
-                                                void* __restrict__ Y, int ystride, int ycount) {
+                                                bf16_t* __restrict__ Y) {
   using T = ConvTile<NDIM, CIN, CA>;
   constexpr int NT = Taps<NDIM>::n;
   constexpr int KC = (NT * CIN + 31) / 32;
@@ -349,28 +348,8 @@ __global__ __launch_bounds__(256) void k_conv_t(CnnDims d, const bf16_t* __restr
           acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[m], b1[nt], acc[m][nt], 0, 0, 0);
     }
   }
-  if (MODE == 0) {
-    __syncthreads();  // every wave is done with the staged input
-    store_relu_tile<NDIM, COUT, T::MTW, T::TX, T::TY, T::TZ>(acc, bias, sIn, d, ox, oy, oz,
-                                                            reinterpret_cast<bf16_t*>(Y));
-    return;
-  }
-#pragma unroll
-  for (int m = 0; m < T::MTW; ++m) {
-    const int gy = oy + lym[m], gz = oz + lzm[m];
-    const int seg = (wave * T::MTW + m) % (T::TX / 16);
-#pragma unroll
-    for (int nt = 0; nt < NTILE; ++nt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gx = ox + seg * 16 + 4 * g + i;
-        const int co = nt * 16 + r;
-        if (gx < d.nx && gy < d.ny && gz < d.nz && co < ycount) {
-          const size_t p = (size_t)gx + (size_t)d.nx * (gy + (size_t)d.ny * gz);
-          reinterpret_cast<float*>(Y)[p * ystride + co] = acc[m][nt][i] + bias[co];
-        }
-      }
-  }
+  __syncthreads();  // every wave is done with the staged input
+  store_relu_tile<NDIM, COUT, T::MTW, T::TX, T::TY, T::TZ>(acc, bias, sIn, d, ox, oy, oz, Y);
 }
 
 // Layer 0: the input has 2 real channels (r/s and c/diag) stored in 8.  Each
@@ -449,104 +428,123 @@ __global__ __launch_bounds__(256) void k_conv0(CnnDims d, const uint32_t* __rest
   store_relu_tile<NDIM, 16, T::MTW, T::TX, T::TY, T::TZ>(acc1, bias, sOut, d, ox, oy, oz, Y);
 }
 
-// Layer 5 (16 channels -> 1): y[p] = b + sum_t sum_c d0[p + off_t][c] W[t][c].
-// A convolution with one output channel would use 1/16 of each MFMA's
-// columns, so the taps take the N dimension instead: for every staged cell h
-// of the tile and its halo, z[h][t] = sum_c d0[h][c] W[t][c] is one 16-cell x
-// 32-tap MFMA tile (K = the 16 channels, zero-padded to 32), kept in FP32 in
-// LDS; then each output cell sums z[p + off_t][t] over the taps.  W5 holds
-// W^T as [tap (32, zero-padded)][16 channels].
+// Layer 5 (16 channels -> 1 output) on the vector units, marching along z:
+// a workgroup owns a TX x TY column tile (TX cells of a row in 2D) and a
+// chunk of KC output planes.  Each input plane, with a one-cell x/y halo, is
+// staged once in LDS (two 16-byte halves per cell, the next plane's loads in
+// flight while the current one is used); every thread then adds that plane's
+// share to the three output planes it touches (taps dz = +1, 0, -1) with
+// bf16 pair dot products accumulated in FP32.  An output plane is complete
+// and stored once the plane above it has been added.  Work: 16 x taps
+// multiply-adds per cell, no padded output channels.
 template <int NDIM>
-struct Conv5Tile {  // used in 2D
-  static constexpr int TX = NDIM == 3 ? 16 : 64, TY = NDIM == 3 ? 4 : 1, TZ = NDIM == 3 ? 2 : 4;
-  static constexpr int HX = TX + 2, HY = NDIM == 3 ? TY + 2 : 1, HZ = TZ + 2;
-  static constexpr int HP = HX * HY * HZ;
-  static constexpr int HPM = (HP + 15) / 16 * 16;  // staged cells, padded to whole M tiles
-  static constexpr int NT = NDIM == 3 ? 27 : 9;
-  static constexpr int ZS = NT;                     // z row stride (odd: no bank conflicts in the gather)
-  static constexpr int DS = 24;                     // staged d0 stride (bf16)
-  static constexpr int PX = TX * TY * TZ;
+struct Conv5Z {
+  static constexpr int TX = NDIM == 3 ? 64 : 256, TY = NDIM == 3 ? 4 : 1, KC = 16;
+  static constexpr int HX = TX + 2, HY = NDIM == 3 ? TY + 2 : 1;
+  static constexpr int HC = HX * HY;                // staged cells per plane
+  static constexpr int NL = (2 * HC + 255) / 256;   // 16-byte loads per thread and plane
 };
 
+__device__ __forceinline__ float dot16(const uint4& p, const uint4& q, const uint32_t* __restrict__ w,
+                                       float a) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+#define GEA_D2(V, I) a = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, V), \
+                                                         __builtin_bit_cast(bf16x2, w[I]), a, false)
+  GEA_D2(p.x, 0); GEA_D2(p.y, 1); GEA_D2(p.z, 2); GEA_D2(p.w, 3);
+  GEA_D2(q.x, 4); GEA_D2(q.y, 5); GEA_D2(q.z, 6); GEA_D2(q.w, 7);
+#undef GEA_D2
+  return a;
+}
+
 template <int NDIM>
-__global__ __launch_bounds__(256) void k_conv5(CnnDims d, const bf16_t* __restrict__ X,
-                                               const bf16_t* __restrict__ W5,
-                                               const float* __restrict__ bias,
-                                               float* __restrict__ Y) {
-  using T = Conv5Tile<NDIM>;
-  __shared__ __attribute__((aligned(16))) bf16_t sx[T::HPM * T::DS];
-  __shared__ float sz[T::HPM * T::ZS];
+__global__ __launch_bounds__(256) void k_conv5z(CnnDims d, const bf16_t* __restrict__ X,
+                                                const uint32_t* __restrict__ W5,
+                                                const float* __restrict__ bias,
+                                                float* __restrict__ Y) {
+  using T = Conv5Z<NDIM>;
+  __shared__ uint4 sx[2][2][T::HC];  // [slot][channel half][cell]
   const int ntx = (d.nx + T::TX - 1) / T::TX;
   const int nty = NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1;
   const int b = xcd_block();
   const int ox = (b % ntx) * T::TX;
   const int oy = NDIM == 3 ? ((b / ntx) % nty) * T::TY : 0;
-  const int oz = (b / (ntx * nty)) * T::TZ;
-  // stage d0 (2 groups of 8 channels per cell; zeros outside the grid and
-  // in the padding cells)
-  constexpr int NIT = (T::HPM * 2 + 255) / 256;  // all loads issued before the LDS writes
-  uint4 v[NIT];
+  const int k0 = (b / (ntx * nty)) * T::KC;
+  const int k1 = min(k0 + T::KC, d.nz);
+  const int lx = (int)threadIdx.x % T::TX, ly = (int)threadIdx.x / T::TX;
+  const int gx = ox + lx, gy = oy + ly;
+  const bool act = gx < d.nx && gy < d.ny;
+  const size_t plane = (size_t)d.nx * d.ny;
+  uint4 v[T::NL];
+  auto fetch = [&](int k) {  // plane k of d0 with its halo; zeros outside the grid
 #pragma unroll
-  for (int u = 0; u < NIT; ++u) {
-    const int e = threadIdx.x + 256 * u, hp = e >> 1, c8 = (e & 1) * 8;
-    v[u] = make_uint4(0, 0, 0, 0);
-    if (hp < T::HP) {
-      const int hx = hp % T::HX, hy = (hp / T::HX) % T::HY, hz = hp / (T::HX * T::HY);
-      const int gx = ox + hx - 1, gy = NDIM == 3 ? oy + hy - 1 : 0, gz = oz + hz - 1;
-      if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
-        v[u] = *reinterpret_cast<const uint4*>(X + (size_t)(gx + d.nx * (gy + d.ny * gz)) * 16 + c8);
+    for (int u = 0; u < T::NL; ++u) {
+      const int e = threadIdx.x + 256 * u, c = e >> 1, h = e & 1;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (c < T::HC && k >= 0 && k < d.nz) {
+        const int x = ox + c % T::HX - 1;
+        const int y = NDIM == 3 ? oy + c / T::HX - 1 : 0;
+        if (x >= 0 && x < d.nx && y >= 0 && y < d.ny)
+          v[u] = *reinterpret_cast<const uint4*>(X + ((size_t)k * plane + x + (size_t)d.nx * y) * 16 + 8 * h);
+      }
     }
-  }
+  };
+  auto put = [&](int slot) {
 #pragma unroll
-  for (int u = 0; u < NIT; ++u) {
-    const int e = threadIdx.x + 256 * u, hp = e >> 1, c8 = (e & 1) * 8;
-    if (hp < T::HPM) *reinterpret_cast<uint4*>(sx + hp * T::DS + c8) = v[u];
-  }
+    for (int u = 0; u < T::NL; ++u) {
+      const int e = threadIdx.x + 256 * u, c = e >> 1, h = e & 1;
+      if (c < T::HC) sx[slot][h][c] = v[u];
+    }
+  };
+  const float b0 = bias[0];
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;  // output planes k - 1, k, k + 1 of input plane k
+  fetch(k0 - 1);
+  put(0);
   __syncthreads();
-  // z = d0 W^T on the staged cells: M tiles of 16 cells, N = 32 taps (2 tiles)
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, r = lane & 15;
-  bf16x8 bw[2];
+  int slot = 0;
+  for (int k = k0 - 1; k <= k1; ++k) {
+    if (k < k1) fetch(k + 1);
+    if (k >= 0 && k < d.nz) {
+      // the thread's 3 x 3 (2D: 3) neighbours in this plane, then one tap
+      // group (9 or 3 taps x 8 channel pairs) per output plane
+      constexpr int NC = NDIM == 3 ? 9 : 3;
+      constexpr int TZ = NC;  // tap stride of dz
+      uint4 P[NC], Q[NC];
 #pragma unroll
-  for (int nt = 0; nt < 2; ++nt)  // B[k = 8g + i][n = tap nt*16 + r]; k >= 16 zero
-    bw[nt] = g < 2 ? load8(W5 + (size_t)(nt * 16 + r) * 16 + 8 * g) : zero8();
-  for (int mt = wave; mt < T::HPM / 16; mt += 4) {
-    const bf16x8 a = g < 2 ? __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sx + (mt * 16 + r) * T::DS + 8 * g))
-                           : zero8();
+      for (int c = 0; c < NC; ++c) {
+        const int a = (NDIM == 3 ? (ly + c / 3) * T::HX : 0) + lx + c % 3;
+        P[c] = sx[slot][0][a];
+        Q[c] = sx[slot][1][a];
+      }
+      auto group = [&](const uint32_t* __restrict__ w, float acc) {
+        float e = 0.f;  // two chains
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const f32x4 zt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[nt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      const int t = nt * 16 + r;
-      if (t < T::NT)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sz[(mt * 16 + 4 * g + i) * T::ZS + t] = zt[i];
+        for (int c = 0; c < NC; ++c) {
+          if (c & 1) e = dot16(P[c], Q[c], w + 8 * c, e);
+          else acc = dot16(P[c], Q[c], w + 8 * c, acc);
+        }
+        return acc + e;
+      };
+      if (k - 1 >= k0) a0 = group(W5 + 8 * 2 * TZ, a0);     // dz = +1 for output k - 1
+      if (k >= k0 && k < k1) a1 = group(W5 + 8 * TZ, a1);  // dz = 0
+      if (k + 1 < k1) a2 = group(W5, a2);                   // dz = -1 for output k + 1
     }
-  }
-  __syncthreads();
-  // each output cell: bias + sum over the taps of its neighbours' z
-  for (int q = threadIdx.x; q < T::PX; q += 256) {
-    const int lx = q % T::TX, ly = NDIM == 3 ? (q / T::TX) % T::TY : 0;
-    const int lz = NDIM == 3 ? q / (T::TX * T::TY) : q / T::TX;
-    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-    if (gx >= d.nx || gy >= d.ny || gz >= d.nz) continue;
-    const int h = (lx + 1) + T::HX * ((NDIM == 3 ? ly + 1 : 0) + T::HY * (lz + 1));
-    float acc = 0.f;
-#pragma unroll
-    for (int t = 0; t < T::NT; ++t) {
-      const int dx = t % 3 - 1;
-      const int dy = NDIM == 3 ? (t / 3) % 3 - 1 : 0;
-      const int dz = NDIM == 3 ? t / 9 - 1 : t / 3 - 1;
-      acc += sz[(h + dx + T::HX * (dy + T::HY * dz)) * T::ZS + t];
+    if (k - 1 >= k0 && act) Y[(size_t)(k - 1) * plane + gx + (size_t)d.nx * gy] = a0 + b0;
+    a0 = a1;
+    a1 = a2;
+    a2 = 0.f;
+    if (k < k1) {
+      put(slot ^ 1);
+      __syncthreads();
+      slot ^= 1;
     }
-    Y[(size_t)gx + (size_t)d.nx * (gy + (size_t)d.ny * gz)] = acc + bias[0];
   }
 }
 
 template <int NDIM>
-int conv5_tiles(const CnnDims& d) {
-  using T = Conv5Tile<NDIM>;
+int conv5z_tiles(const CnnDims& d) {
+  using T = Conv5Z<NDIM>;
   return ((d.nx + T::TX - 1) / T::TX) * (NDIM == 3 ? (d.ny + T::TY - 1) / T::TY : 1) *
-         ((d.nz + T::TZ - 1) / T::TZ);
+         ((d.nz + T::KC - 1) / T::KC);
 }
 
 template <int NDIM, int CIN>
@@ -871,26 +869,21 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
   const CnnDims& d = n.d[L.level];
   const dim3 bl(256);
   hipStream_t s = n.s;
-#define GEA_CONV(CI, CO, MODE, CAA, YS, YC)                                                       \
-  hipLaunchKernelGGL((k_conv_t<NDIM, CI, CO, MODE, CAA>), dim3(conv_tiles<NDIM, CI>(d)), bl, 0, s, \
-                     d, X, A, n.W[layer], n.bias[layer], Y, YS, YC)
+#define GEA_CONV(CI, CO, CAA)                                                                   \
+  hipLaunchKernelGGL((k_conv_t<NDIM, CI, CO, CAA>), dim3(conv_tiles<NDIM, CI>(d)), bl, 0, s, d, X, \
+                     A, n.W[layer], n.bias[layer], (bf16_t*)Y)
   switch (layer) {
     case 0:
       hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d,
                          (const uint32_t*)n.x2, n.W0, n.bias[0], (bf16_t*)Y);
       break;
-    case 1: GEA_CONV(16, 32, 0, 0, 32, 32); break;
-    case 2: GEA_CONV(32, 64, 0, 0, 64, 64); break;
-    case 3: GEA_CONV(96, 32, 0, 64, 32, 32); break;
-    case 4: GEA_CONV(48, 16, 0, 32, 16, 16); break;
+    case 1: GEA_CONV(16, 32, 0); break;
+    case 2: GEA_CONV(32, 64, 0); break;
+    case 3: GEA_CONV(96, 32, 64); break;
+    case 4: GEA_CONV(48, 16, 32); break;
     case 5:
-      // 3D: the taps' z values of a tile with its halo need too much LDS
-      // (measured slower there); the padded-N convolution is kept
-      if (NDIM == 2)
-        hipLaunchKernelGGL((k_conv5<NDIM>), dim3(conv5_tiles<NDIM>(d)), bl, 0, s, d, X, n.W5,
-                           n.bias[5], (float*)Y);
-      else
-        GEA_CONV(16, 16, 1, 0, 1, 1);
+      hipLaunchKernelGGL((k_conv5z<NDIM>), dim3(conv5z_tiles<NDIM>(d)), bl, 0, s, d, X,
+                         (const uint32_t*)n.W5, n.bias[5], (float*)Y);
       break;
   }
 #undef GEA_CONV

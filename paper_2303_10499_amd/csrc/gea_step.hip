@@ -26,15 +26,6 @@ __device__ __forceinline__ double phi_face(const Geo& G, const Phys& ph, int d, 
   return d == NDIM - 1 ? ph.g * (cq + 1.0) * G.dz : phi_cell(G, ph, kz);
 }
 
-// F on the face between Q and Q+st along d: grad p' - Phi grad rho
-template <int NDIM>
-__device__ __forceinline__ double force_face(const Geo& G, const Phys& ph, const double* pp,
-                                             const double* rho, int Q, int d, int cq, int kz) {
-  const int st = G.st[d];
-  return ((pp[Q + st] - pp[Q]) - phi_face<NDIM>(G, ph, d, cq, kz) * (rho[Q + st] - rho[Q])) *
-         G.inv_h[d];
-}
-
 template <int NDIM>
 __device__ __forceinline__ double kinetic(const Vec<NDIM>& u, int P) {
   double k = 0.0;
@@ -44,19 +35,26 @@ __device__ __forceinline__ double kinetic(const Vec<NDIM>& u, int P) {
 }
 
 // Five consecutive values of a cell field along one direction, centred on
-// the cell; entries outside the mesh are never used and left 0.
+// the cell.  Positions outside the mesh hold the centre value (their load is
+// clamped to the cell itself) and are never used.
 struct Line {
   double m2, m1, c, p1, p2;
 };
 
+// Index of a neighbour if it exists, else of the cell itself.  Every load of
+// a plane is then made unconditionally from inside the mesh and each wall
+// test is a select on loaded values: no branch separates a plane's loads, so
+// they are all in flight together.
+__device__ __forceinline__ int nb(bool ok, int Q, int P) { return ok ? Q : P; }
+
 template <typename F>
 __device__ __forceinline__ Line line_at(F s, int P, int st, int q, int n) {
   Line L;
+  L.m2 = s(nb(q >= 2, P - 2 * st, P));
+  L.m1 = s(nb(q >= 1, P - st, P));
   L.c = s(P);
-  L.m1 = q >= 1 ? s(P - st) : 0.0;
-  L.m2 = q >= 2 ? s(P - 2 * st) : 0.0;
-  L.p1 = q + 1 < n ? s(P + st) : 0.0;
-  L.p2 = q + 2 < n ? s(P + 2 * st) : 0.0;
+  L.p1 = s(nb(q + 1 < n, P + st, P));
+  L.p2 = s(nb(q + 2 < n, P + 2 * st, P));
   return L;
 }
 
@@ -65,24 +63,43 @@ __device__ __forceinline__ Line shift(const Line& L, double next) {
   return Line{L.m1, L.c, L.p1, L.p2, next};
 }
 
-// interp4 on the face above (q + 1/2) and below (q - 1/2) the centre of a line
+// interp4 on the face above (q + 1/2) and below (q - 1/2) the centre of a
+// line; linear next to a wall
 __device__ __forceinline__ double i4_hi(const Line& s, int q, int n) {
-  if (q >= 1 && q + 2 <= n - 1) return (-s.m1 + 9.0 * s.c + 9.0 * s.p1 - s.p2) / 16.0;
-  return 0.5 * (s.c + s.p1);
+  const double f4 = (-s.m1 + 9.0 * s.c + 9.0 * s.p1 - s.p2) / 16.0;
+  const double f2 = 0.5 * (s.c + s.p1);
+  return (q >= 1 && q + 2 <= n - 1) ? f4 : f2;
 }
 __device__ __forceinline__ double i4_lo(const Line& s, int q, int n) {
-  if (q >= 2 && q + 1 <= n - 1) return (-s.m2 + 9.0 * s.m1 + 9.0 * s.c - s.p1) / 16.0;
-  return 0.5 * (s.m1 + s.c);
+  const double f4 = (-s.m2 + 9.0 * s.m1 + 9.0 * s.c - s.p1) / 16.0;
+  const double f2 = 0.5 * (s.m1 + s.c);
+  return (q >= 2 && q + 1 <= n - 1) ? f4 : f2;
 }
 
 // mu snGrad(u_comp) S on the two faces of a line; walls normal to the line
 // hold the normal component at 0 and leave the tangential ones free
 __device__ __forceinline__ void visc_add(double& acc, const Line& s, int q, int n, double k,
                                          bool normal) {
-  if (q + 1 < n) acc += k * (s.p1 - s.c);
-  else if (normal) acc += 2.0 * k * (0.0 - s.c);
-  if (q > 0) acc += k * (s.m1 - s.c);
-  else if (normal) acc += 2.0 * k * (0.0 - s.c);
+  const double wall = normal ? 2.0 * k * (0.0 - s.c) : 0.0;
+  acc += q + 1 < n ? k * (s.p1 - s.c) : wall;
+  acc += q > 0 ? k * (s.m1 - s.c) : wall;
+}
+
+// F = grad p' - Phi grad rho on a face, from the values on its two sides
+// (low, high along the face normal)
+__device__ __forceinline__ double force_val(double p_lo, double p_hi, double r_lo, double r_hi,
+                                            double phif, double inv_h) {
+  return ((p_hi - p_lo) - phif * (r_hi - r_lo)) * inv_h;
+}
+
+// predicted flux on a face from its two sides' D, H.n and rho23:
+// D_f S [H_f . n + Phi_f (rho23_N - rho23_P)/h]
+__device__ __forceinline__ double phit_val(double D_lo, double D_hi, double H_lo, double H_hi,
+                                           double r_lo, double r_hi, double S, double phif,
+                                           double inv_h) {
+  const double Df = 0.5 * (D_lo + D_hi);
+  const double Hf = 0.5 * (H_lo + H_hi);
+  return Df * S * (Hf + phif * (r_hi - r_lo) * inv_h);
 }
 
 
@@ -104,26 +121,35 @@ __global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
   Line z = line_at(mz, P, pl, c.k0, nz);
   double flo = c.k0 > 0 ? i4_lo(z, c.k0, nz) * G.S[Z] : 0.0;
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
-    double sum = 0.0;
+    // loads of the plane
+    Line s[NDIM - 1];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
       const double* ud = u.p[d];
-      const int st = G.st[d], n = G.n[d], q = coord(c, d);
-      auto m = [&](int Q) { return rho[Q] * ud[Q]; };
-      const Line s = line_at(m, P, st, q, n);
-      const double hi = q + 1 < n ? i4_hi(s, q, n) * G.S[d] : 0.0;
-      const double lo = q > 0 ? i4_lo(s, q, n) * G.S[d] : 0.0;
-      phi.p[d][P] = hi;
+      s[d] = line_at([&](int Q) { return rho[Q] * ud[Q]; }, P, G.st[d], coord(c, d), G.n[d]);
+    }
+    const double r = rho[P];
+    const double znext = mz(nb(k + 3 < nz, P + 3 * pl, P));
+    // fluxes
+    double sum = 0.0, hid[NDIM - 1];
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int n = G.n[d], q = coord(c, d);
+      const double hi = q + 1 < n ? i4_hi(s[d], q, n) * G.S[d] : 0.0;
+      const double lo = q > 0 ? i4_lo(s[d], q, n) * G.S[d] : 0.0;
+      hid[d] = hi;
       sum += hi;
       sum -= lo;
     }
     const double hi = k + 1 < nz ? i4_hi(z, k, nz) * G.S[Z] : 0.0;
-    phi.p[Z][P] = hi;
     sum += hi;
     sum -= flo;
     flo = hi;
-    rho_star[P] = rho[P] - ph.dt / G.V * sum;
-    z = shift(z, k + 3 < nz ? mz(P + 3 * pl) : 0.0);
+#pragma unroll
+    for (int d = 0; d < Z; ++d) phi.p[d][P] = hid[d];
+    phi.p[Z][P] = hi;
+    rho_star[P] = r - ph.dt / G.V * sum;
+    z = shift(z, k + 3 < nz ? znext : 0.0);
   }
 }
 
@@ -148,32 +174,55 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
     z[cc] = line_at([&](int Q) { return uc[Q]; }, P, pl, c.k0, nz);
     flo[cc] = c.k0 > 0 ? phz_lo * i4_lo(z[cc], c.k0, nz) : 0.0;
   }
-  double Flo = c.k0 > 0 ? force_face<NDIM>(G, ph, pp, rho, P - pl, Z, c.k0 - 1, c.k0 - 1) : 0.0;
+  double Flo = 0.0;
+  if (c.k0 > 0)
+    Flo = force_val(pp[P - pl], pp[P], rho[P - pl], rho[P], phi_face<NDIM>(G, ph, Z, c.k0 - 1, c.k0 - 1),
+                    G.inv_h[Z]);
   const double kvz = ph.mu * G.S[Z] / G.h[Z];
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
-    const double Fhi = k + 1 < nz ? force_face<NDIM>(G, ph, pp, rho, P, Z, k, k) : 0.0;
-    const double r = rho[P], inv_rs = 1.0 / rho_star[P], phz = phi.p[Z][P];
-    double fhi_d[NDIM - 1], flo_d[NDIM - 1];
+    // loads of the plane
+    const bool up = k + 1 < nz;
+    const int Pu = nb(up, P + pl, P), Pn = nb(k + 3 < nz, P + 3 * pl, P);
+    const double r = rho[P], pc = pp[P], rs = rho_star[P], phz = phi.p[Z][P];
+    const double p_up = pp[Pu], r_up = rho[Pu];
+    double fhi[NDIM - 1], flod[NDIM - 1], p_hi[NDIM - 1], p_lo[NDIM - 1], r_hi[NDIM - 1],
+        r_lo[NDIM - 1];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
-      const int q = coord(c, d);
-      fhi_d[d] = q + 1 < G.n[d] ? phi.p[d][P] : 0.0;
-      flo_d[d] = q > 0 ? phi.p[d][P - G.st[d]] : 0.0;
+      const int st = G.st[d], q = coord(c, d);
+      const int Ph = nb(q + 1 < G.n[d], P + st, P), Pl = nb(q > 0, P - st, P);
+      fhi[d] = phi.p[d][P];
+      flod[d] = phi.p[d][Pl];
+      p_hi[d] = pp[Ph];
+      p_lo[d] = pp[Pl];
+      r_hi[d] = rho[Ph];
+      r_lo[d] = rho[Pl];
     }
+    Line s[NDIM][NDIM - 1];
+    double zn[NDIM];
 #pragma unroll
     for (int cc = 0; cc < NDIM; ++cc) {
       const double* uc = u.p[cc];
+#pragma unroll
+      for (int d = 0; d < Z; ++d)
+        s[cc][d] = line_at([&](int Q) { return uc[Q]; }, P, G.st[d], coord(c, d), G.n[d]);
+      zn[cc] = uc[Pn];
+    }
+    // update
+    const double Fhi = up ? force_val(pc, p_up, r, r_up, phi_face<NDIM>(G, ph, Z, k, k), G.inv_h[Z]) : 0.0;
+    const double inv_rs = 1.0 / rs;
+    double us[NDIM];
+#pragma unroll
+    for (int cc = 0; cc < NDIM; ++cc) {
       double conv = 0.0, visc = 0.0;
-      Line s[NDIM - 1];
 #pragma unroll
       for (int d = 0; d < Z; ++d) {
-        const int st = G.st[d], n = G.n[d], q = coord(c, d);
-        s[d] = line_at([&](int Q) { return uc[Q]; }, P, st, q, n);
-        if (q + 1 < n) conv += fhi_d[d] * i4_hi(s[d], q, n);
-        if (q > 0) conv -= flo_d[d] * i4_lo(s[d], q, n);
+        const int n = G.n[d], q = coord(c, d);
+        conv = q + 1 < n ? conv + fhi[d] * i4_hi(s[cc][d], q, n) : conv;
+        conv = q > 0 ? conv - flod[d] * i4_lo(s[cc][d], q, n) : conv;
       }
       double fh = 0.0;
-      if (k + 1 < nz) {
+      if (up) {
         fh = phz * i4_hi(z[cc], k, nz);
         conv += fh;
       }
@@ -181,20 +230,25 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
       flo[cc] = fh;
 #pragma unroll
       for (int d = 0; d < Z; ++d)
-        visc_add(visc, s[d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
+        visc_add(visc, s[cc][d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
       visc_add(visc, z[cc], k, nz, kvz, cc == Z);
       double RF;
       if (cc == Z) {
         RF = 0.5 * (Flo + Fhi);
       } else {
-        const int st = G.st[cc], n = G.n[cc], q = coord(c, cc);
-        const double hi = q + 1 < n ? force_face<NDIM>(G, ph, pp, rho, P, cc, q, k) : 0.0;
-        const double lo = q > 0 ? force_face<NDIM>(G, ph, pp, rho, P - st, cc, q - 1, k) : 0.0;
+        const int n = G.n[cc], q = coord(c, cc);
+        const double phf = phi_cell(G, ph, k);
+        const double hi = q + 1 < n ? force_val(pc, p_hi[cc], r, r_hi[cc], phf, G.inv_h[cc]) : 0.0;
+        const double lo = q > 0 ? force_val(p_lo[cc], pc, r_lo[cc], r, phf, G.inv_h[cc]) : 0.0;
         RF = 0.5 * (lo + hi);
       }
       const double mom = r * z[cc].c - ph.dt / G.V * (conv - visc) - ph.dt * RF;
-      u_star.p[cc][P] = mom * inv_rs;
-      z[cc] = shift(z[cc], k + 3 < nz ? uc[P + 3 * pl] : 0.0);
+      us[cc] = mom * inv_rs;
+    }
+#pragma unroll
+    for (int cc = 0; cc < NDIM; ++cc) {
+      u_star.p[cc][P] = us[cc];
+      z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
     }
     Flo = Fhi;
   }
@@ -229,47 +283,68 @@ __global__ __launch_bounds__(kBlock) void k_energy_sweep(
   const Col c = col_of<NDIM>(G, kc);
   if (!c.act) return;
   const int nz = G.n[Z], pl = c.pl;
-  auto hhat = [&](int Q) { return e_prev[Q] + ph.R * T_prev[Q]; };
   int P = c.base + pl * c.k0;
   Line ze = line_at([&](int Q) { return e_prev[Q]; }, P, pl, c.k0, nz);
   Line zT = line_at([&](int Q) { return T_prev[Q]; }, P, pl, c.k0, nz);
-  auto hz_of = [&]() {
-    return Line{ze.m2 + ph.R * zT.m2, ze.m1 + ph.R * zT.m1, ze.c + ph.R * zT.c,
-                ze.p1 + ph.R * zT.p1, ze.p2 + ph.R * zT.p2};
+  auto hhat = [&](const Line& e, const Line& T) {
+    return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
+                e.p2 + ph.R * T.p2};
   };
-  double flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hz_of(), c.k0, nz) : 0.0;
+  double flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hhat(ze, zT), c.k0, nz) : 0.0;
   const double kdz = ph.mu / ph.Pr * ph.cp * G.S[Z] / G.h[Z];
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
-    double conv = 0.0;
+    // loads of the plane
+    const int Pn = nb(k + 3 < nz, P + 3 * pl, P);
+    Line le[NDIM - 1], lT[NDIM - 1];
+    double fhi[NDIM - 1], flod[NDIM - 1];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
       const int st = G.st[d], n = G.n[d], q = coord(c, d);
-      const Line s = line_at(hhat, P, st, q, n);
-      if (q + 1 < n) conv += phi.p[d][P] * i4_hi(s, q, n);
-      if (q > 0) conv -= phi.p[d][P - st] * i4_lo(s, q, n);
+      le[d] = line_at([&](int Q) { return e_prev[Q]; }, P, st, q, n);
+      lT[d] = line_at([&](int Q) { return T_prev[Q]; }, P, st, q, n);
+      fhi[d] = phi.p[d][P];
+      flod[d] = phi.p[d][nb(q > 0, P - st, P)];
+    }
+    const double phz = phi.p[Z][P], rs = rho_star[P], r = rho[P], e0c = e0[P];
+    double us[NDIM];
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) us[d] = u_star.p[d][P];
+    const double e_n = e_prev[Pn], T_n = T_prev[Pn];
+    const double tb = Tbg[k], tb_up = Tbg[k + 1 < nz ? k + 1 : k], tb_dn = Tbg[k > 0 ? k - 1 : k];
+    // update
+    double conv = 0.0;
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int n = G.n[d], q = coord(c, d);
+      const Line h = hhat(le[d], lT[d]);
+      conv = q + 1 < n ? conv + fhi[d] * i4_hi(h, q, n) : conv;
+      conv = q > 0 ? conv - flod[d] * i4_lo(h, q, n) : conv;
     }
     double fh = 0.0;
     if (k + 1 < nz) {
-      fh = phi.p[Z][P] * i4_hi(hz_of(), k, nz);
+      fh = phz * i4_hi(hhat(ze, zT), k, nz);
       conv += fh;
     }
     if (k > 0) conv -= flo;
     flo = fh;
-    const double Tp = zT.c - Tbg[k];
+    const double Tp = zT.c - tb;
     double diff = 0.0;
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
-      const int st = G.st[d], n = G.n[d], q = coord(c, d);
+      const int n = G.n[d], q = coord(c, d);
       const double kd = ph.mu / ph.Pr * ph.cp * G.S[d] / G.h[d];
-      if (q + 1 < n) diff += kd * ((T_prev[P + st] - Tbg[k]) - Tp);
-      if (q > 0) diff += kd * ((T_prev[P - st] - Tbg[k]) - Tp);
+      diff = q + 1 < n ? diff + kd * ((lT[d].p1 - tb) - Tp) : diff;
+      diff = q > 0 ? diff + kd * ((lT[d].m1 - tb) - Tp) : diff;
     }
-    if (k + 1 < nz) diff += kdz * ((zT.p1 - Tbg[k + 1]) - Tp);
-    if (k > 0) diff += kdz * ((zT.m1 - Tbg[k - 1]) - Tp);
-    const double inv_rs = 1.0 / rho_star[P];
-    const double rhoe = rho[P] * e0[P] - ph.dt * G.inv_V * conv + ph.dt * G.inv_V * diff;
+    if (k + 1 < nz) diff += kdz * ((zT.p1 - tb_up) - Tp);
+    if (k > 0) diff += kdz * ((zT.m1 - tb_dn) - Tp);
+    const double inv_rs = 1.0 / rs;
+    const double rhoe = r * e0c - ph.dt * G.inv_V * conv + ph.dt * G.inv_V * diff;
     const double e = rhoe * inv_rs;
-    const double T = (e - kinetic<NDIM>(u_star, P) - phi_cell(G, ph, k)) * ph.inv_cv;
+    double kin = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) kin += us[d] * us[d];
+    const double T = (e - 0.5 * kin - phi_cell(G, ph, k)) * ph.inv_cv;
     e_next[P] = e;
     T_next[P] = T;
     if (last) {
@@ -281,8 +356,8 @@ __global__ __launch_bounds__(kBlock) void k_energy_sweep(
       D[P] = r23 * ph.dt * inv_rs;
     }
     const bool more = k + 3 < nz;
-    ze = shift(ze, more ? e_prev[P + 3 * pl] : 0.0);
-    zT = shift(zT, more ? T_prev[P + 3 * pl] : 0.0);
+    ze = shift(ze, more ? e_n : 0.0);
+    zT = shift(zT, more ? T_n : 0.0);
   }
 }
 
@@ -309,25 +384,37 @@ __global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
   }
   const double kvz = ph.mu * G.S[Z] / G.h[Z];
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
+    // loads of the plane
+    const int Pn = nb(k + 3 < nz, P + 3 * pl, P);
     const double r = rho[P], phz = phi.p[Z][P];
-    double fhi_d[NDIM - 1], flo_d[NDIM - 1];
+    double fhi[NDIM - 1], flod[NDIM - 1];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
       const int q = coord(c, d);
-      fhi_d[d] = q + 1 < G.n[d] ? phi.p[d][P] : 0.0;
-      flo_d[d] = q > 0 ? phi.p[d][P - G.st[d]] : 0.0;
+      fhi[d] = phi.p[d][P];
+      flod[d] = phi.p[d][nb(q > 0, P - G.st[d], P)];
     }
+    Line s[NDIM][NDIM - 1];
+    double zn[NDIM], un[NDIM];
 #pragma unroll
     for (int cc = 0; cc < NDIM; ++cc) {
       const double* uc = u_prev.p[cc];
+#pragma unroll
+      for (int d = 0; d < Z; ++d)
+        s[cc][d] = line_at([&](int Q) { return uc[Q]; }, P, G.st[d], coord(c, d), G.n[d]);
+      zn[cc] = uc[Pn];
+      un[cc] = u.p[cc][P];
+    }
+    // H
+    double h[NDIM];
+#pragma unroll
+    for (int cc = 0; cc < NDIM; ++cc) {
       double conv = 0.0, visc = 0.0;
-      Line s[NDIM - 1];
 #pragma unroll
       for (int d = 0; d < Z; ++d) {
-        const int st = G.st[d], n = G.n[d], q = coord(c, d);
-        s[d] = line_at([&](int Q) { return uc[Q]; }, P, st, q, n);
-        if (q + 1 < n) conv += fhi_d[d] * i4_hi(s[d], q, n);
-        if (q > 0) conv -= flo_d[d] * i4_lo(s[d], q, n);
+        const int n = G.n[d], q = coord(c, d);
+        conv = q + 1 < n ? conv + fhi[d] * i4_hi(s[cc][d], q, n) : conv;
+        conv = q > 0 ? conv - flod[d] * i4_lo(s[cc][d], q, n) : conv;
       }
       double fh = 0.0;
       if (k + 1 < nz) {
@@ -338,24 +425,16 @@ __global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
       flo[cc] = fh;
 #pragma unroll
       for (int d = 0; d < Z; ++d)
-        visc_add(visc, s[d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
+        visc_add(visc, s[cc][d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
       visc_add(visc, z[cc], k, nz, kvz, cc == Z);
-      H.p[cc][P] = r * u.p[cc][P] * ph.inv_dt - conv * G.inv_V + visc * G.inv_V;
-      z[cc] = shift(z[cc], k + 3 < nz ? uc[P + 3 * pl] : 0.0);
+      h[cc] = r * un[cc] * ph.inv_dt - conv * G.inv_V + visc * G.inv_V;
+    }
+#pragma unroll
+    for (int cc = 0; cc < NDIM; ++cc) {
+      H.p[cc][P] = h[cc];
+      z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
     }
   }
-}
-
-// predicted flux on the face between Q and Q+st along d:
-// D_f S [H_f . n + Phi_f (rho23_N - rho23_P)/d]
-template <int NDIM>
-__device__ __forceinline__ double phi_tilde(const Geo& G, const Phys& ph, const double* D,
-                                            const double* Hd, const double* rho23, int Q, int d,
-                                            int cq, int kz) {
-  const int st = G.st[d];
-  const double Df = 0.5 * (D[Q] + D[Q + st]);
-  const double Hf = 0.5 * (Hd[Q] + Hd[Q + st]);
-  return Df * G.S[d] * (Hf + phi_face<NDIM>(G, ph, d, cq, kz) * (rho23[Q + st] - rho23[Q]) * G.inv_h[d]);
 }
 
 // b = (V/dt)(rho^n + psi rho23 Phi) - sum_out phitilde; 1/diag of the operator
@@ -375,29 +454,53 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
   int P = c.base + pl * c.k0;
   double flux_lo = 0.0, diag_lo = 0.0;
   if (c.k0 > 0) {
-    flux_lo = phi_tilde<NDIM>(G, ph, D, H.p[Z], rho23, P - pl, Z, c.k0 - 1, c.k0 - 1);
-    diag_lo = 0.5 * (D[P - pl] + D[P]) * kz_;
+    const int Q = P - pl;
+    flux_lo = phit_val(D[Q], D[P], H.p[Z][Q], H.p[Z][P], rho23[Q], rho23[P], G.S[Z],
+                       phi_face<NDIM>(G, ph, Z, c.k0 - 1, c.k0 - 1), G.inv_h[Z]);
+    diag_lo = 0.5 * (D[Q] + D[P]) * kz_;
   }
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
-    double sum = 0.0;
-    double diag = cc[P];
+    // loads of the plane
+    const bool up = k + 1 < nz;
+    const int Pu = nb(up, P + pl, P);
+    const double Dc = D[P], r23 = rho23[P], cP = cc[P], rP = rho[P], psP = psi[P];
+    const double D_up = D[Pu], Hz = H.p[Z][P], Hz_up = H.p[Z][Pu], r23_up = rho23[Pu];
+    double D_hi[NDIM - 1], D_lo[NDIM - 1], Hc[NDIM - 1], H_hi[NDIM - 1], H_lo[NDIM - 1],
+        r_hi[NDIM - 1], r_lo[NDIM - 1];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
       const int st = G.st[d], q = coord(c, d);
+      const int Ph = nb(q + 1 < G.n[d], P + st, P), Pl = nb(q > 0, P - st, P);
+      D_hi[d] = D[Ph];
+      D_lo[d] = D[Pl];
+      Hc[d] = H.p[d][P];
+      H_hi[d] = H.p[d][Ph];
+      H_lo[d] = H.p[d][Pl];
+      r_hi[d] = rho23[Ph];
+      r_lo[d] = rho23[Pl];
+    }
+    // right-hand side and diagonal
+    double sum = 0.0;
+    double diag = cP;
+    const double phc = phi_cell(G, ph, k);
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int q = coord(c, d);
       const double kd = G.S[d] / G.h[d];
       if (q + 1 < G.n[d]) {
-        sum += phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P, d, q, k);
-        diag += 0.5 * (D[P] + D[P + st]) * kd;
+        sum += phit_val(Dc, D_hi[d], Hc[d], H_hi[d], r23, r_hi[d], G.S[d], phc, G.inv_h[d]);
+        diag += 0.5 * (Dc + D_hi[d]) * kd;
       }
       if (q > 0) {
-        sum -= phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P - st, d, q - 1, k);
-        diag += 0.5 * (D[P - st] + D[P]) * kd;
+        sum -= phit_val(D_lo[d], Dc, H_lo[d], Hc[d], r_lo[d], r23, G.S[d], phc, G.inv_h[d]);
+        diag += 0.5 * (D_lo[d] + Dc) * kd;
       }
     }
     double flux_hi = 0.0, diag_hi = 0.0;
-    if (k + 1 < nz) {
-      flux_hi = phi_tilde<NDIM>(G, ph, D, H.p[Z], rho23, P, Z, k, k);
-      diag_hi = 0.5 * (D[P] + D[P + pl]) * kz_;
+    if (up) {
+      flux_hi = phit_val(Dc, D_up, Hz, Hz_up, r23, r23_up, G.S[Z], phi_face<NDIM>(G, ph, Z, k, k),
+                         G.inv_h[Z]);
+      diag_hi = 0.5 * (Dc + D_up) * kz_;
       sum += flux_hi;
       diag += diag_hi;
     }
@@ -407,8 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
     }
     flux_lo = flux_hi;
     diag_lo = diag_hi;
-    const double Phi = phi_cell(G, ph, k);
-    b[P] = G.V / ph.dt * (rho[P] + psi[P] * rho23[P] * Phi) - sum;
+    b[P] = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
     dinv[P] = 1.0 / diag;
   }
 }
@@ -432,63 +534,101 @@ __global__ __launch_bounds__(kBlock) void k_correct(
     int P = c.base + pl * c.k0;
     double Flo = 0.0, flux_lo = 0.0;
     if (c.k0 > 0) {
-      Flo = force_face<NDIM>(G, ph, pp, rho23, P - pl, Z, c.k0 - 1, c.k0 - 1);
+      const int Q = P - pl;
+      const double phf = phi_face<NDIM>(G, ph, Z, c.k0 - 1, c.k0 - 1);
+      Flo = force_val(pp[Q], pp[P], rho23[Q], rho23[P], phf, G.inv_h[Z]);
       if (last) {
-        const double w = 0.5 * (D[P - pl] + D[P]) * kz_;
-        flux_lo = phi_tilde<NDIM>(G, ph, D, H.p[Z], rho23, P - pl, Z, c.k0 - 1, c.k0 - 1) -
-                  w * (pp[P] - pp[P - pl]);
+        const double w = 0.5 * (D[Q] + D[P]) * kz_;
+        flux_lo = phit_val(D[Q], D[P], H.p[Z][Q], H.p[Z][P], rho23[Q], rho23[P], G.S[Z], phf,
+                           G.inv_h[Z]) -
+                  w * (pp[P] - pp[Q]);
       }
     }
     for (int k = c.k0; k < c.k1; ++k, P += pl) {
-      const double inv_A = ph.dt / rho_star[P];
-      const double Fhi = k + 1 < nz ? force_face<NDIM>(G, ph, pp, rho23, P, Z, k, k) : 0.0;
+      // loads of the plane
+      const bool up = k + 1 < nz;
+      const int Pu = nb(up, P + pl, P);
+      const double pc = pp[P], r23 = rho23[P], rs = rho_star[P], p_up = pp[Pu], r_up = rho23[Pu];
+      double Hc[NDIM], p_hi[NDIM - 1], p_lo[NDIM - 1], r_hi[NDIM - 1], r_lo[NDIM - 1];
+#pragma unroll
+      for (int d = 0; d < NDIM; ++d) Hc[d] = H.p[d][P];
+#pragma unroll
+      for (int d = 0; d < Z; ++d) {
+        const int st = G.st[d], q = coord(c, d);
+        const int Ph = nb(q + 1 < G.n[d], P + st, P), Pl = nb(q > 0, P - st, P);
+        p_hi[d] = pp[Ph];
+        p_lo[d] = pp[Pl];
+        r_hi[d] = rho23[Ph];
+        r_lo[d] = rho23[Pl];
+      }
+      // velocity correction
+      const double inv_A = ph.dt / rs;
+      const double phc = phi_cell(G, ph, k);
+      const double Fhi = up ? force_val(pc, p_up, r23, r_up, phi_face<NDIM>(G, ph, Z, k, k), G.inv_h[Z]) : 0.0;
       bool finite = true;
+      double uo[NDIM];
 #pragma unroll
       for (int cmp = 0; cmp < NDIM; ++cmp) {
         double RF;
         if (cmp == Z) {
           RF = 0.5 * (Flo + Fhi);
         } else {
-          const int st = G.st[cmp], n = G.n[cmp], q = coord(c, cmp);
-          const double hi = q + 1 < n ? force_face<NDIM>(G, ph, pp, rho23, P, cmp, q, k) : 0.0;
-          const double lo = q > 0 ? force_face<NDIM>(G, ph, pp, rho23, P - st, cmp, q - 1, k) : 0.0;
+          const int n = G.n[cmp], q = coord(c, cmp);
+          const double hi = q + 1 < n ? force_val(pc, p_hi[cmp], r23, r_hi[cmp], phc, G.inv_h[cmp]) : 0.0;
+          const double lo = q > 0 ? force_val(p_lo[cmp], pc, r_lo[cmp], r23, phc, G.inv_h[cmp]) : 0.0;
           RF = 0.5 * (lo + hi);
         }
-        const double un = (H.p[cmp][P] - RF) * inv_A;
-        u_out.p[cmp][P] = un;
-        finite = finite && isfinite(un);
+        uo[cmp] = (Hc[cmp] - RF) * inv_A;
+        finite = finite && isfinite(uo[cmp]);
       }
+#pragma unroll
+      for (int cmp = 0; cmp < NDIM; ++cmp) u_out.p[cmp][P] = uo[cmp];
       Flo = Fhi;
       if (last) {
-        double sum = 0.0;
+        // loads for the new density
+        const double Dc = D[P], D_up = D[Pu], Hz_up = H.p[Z][Pu], r_old = rho_old[P], psP = psi[P];
+        double D_hi[NDIM - 1], D_lo[NDIM - 1], H_hi[NDIM - 1], H_lo[NDIM - 1];
 #pragma unroll
         for (int d = 0; d < Z; ++d) {
           const int st = G.st[d], q = coord(c, d);
+          const int Ph = nb(q + 1 < G.n[d], P + st, P), Pl = nb(q > 0, P - st, P);
+          D_hi[d] = D[Ph];
+          D_lo[d] = D[Pl];
+          H_hi[d] = H.p[d][Ph];
+          H_lo[d] = H.p[d][Pl];
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int d = 0; d < Z; ++d) {
+          const int q = coord(c, d);
           const double kd = G.S[d] / G.h[d];
           if (q + 1 < G.n[d]) {
-            const double w = 0.5 * (D[P] + D[P + st]) * kd;
-            sum += phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P, d, q, k) - w * (pp[P + st] - pp[P]);
+            const double w = 0.5 * (Dc + D_hi[d]) * kd;
+            sum += phit_val(Dc, D_hi[d], Hc[d], H_hi[d], r23, r_hi[d], G.S[d], phc, G.inv_h[d]) -
+                   w * (p_hi[d] - pc);
           }
           if (q > 0) {
-            const double w = 0.5 * (D[P - st] + D[P]) * kd;
-            sum -= phi_tilde<NDIM>(G, ph, D, H.p[d], rho23, P - st, d, q - 1, k) -
-                   w * (pp[P] - pp[P - st]);
+            const double w = 0.5 * (D_lo[d] + Dc) * kd;
+            sum -= phit_val(D_lo[d], Dc, H_lo[d], Hc[d], r_lo[d], r23, G.S[d], phc, G.inv_h[d]) -
+                   w * (pc - p_lo[d]);
           }
         }
         double flux_hi = 0.0;
-        if (k + 1 < nz) {
-          const double w = 0.5 * (D[P] + D[P + pl]) * kz_;
-          flux_hi = phi_tilde<NDIM>(G, ph, D, H.p[Z], rho23, P, Z, k, k) - w * (pp[P + pl] - pp[P]);
+        if (up) {
+          const double w = 0.5 * (Dc + D_up) * kz_;
+          flux_hi = phit_val(Dc, D_up, Hc[Z], Hz_up, r23, r_up, G.S[Z], phi_face<NDIM>(G, ph, Z, k, k),
+                             G.inv_h[Z]) -
+                    w * (p_up - pc);
           sum += flux_hi;
         }
         if (k > 0) sum -= flux_lo;
         flux_lo = flux_hi;
-        const double rn = rho_old[P] - ph.dt / G.V * sum;
-        const double pn = pp[P] - rho23[P] * phi_cell(G, ph, k);
+        const double rn = r_old - ph.dt / G.V * sum;
+        const double pn = pc - r23 * phc;
         rho_new[P] = rn;
         p_new[P] = pn;
         red[0] += rn * G.V;
-        red[1] = fmax(red[1], fabs(rn - psi[P] * pn));
+        red[1] = fmax(red[1], fabs(rn - psP * pn));
         finite = finite && isfinite(rn) && isfinite(pn);
       }
       red[2] += finite ? 0.0 : 1.0;

@@ -142,20 +142,35 @@ struct ColumnA {
     xc = x[P];
     dc = D[P];
   }
-  // A x at cell P of plane k (loads the plane above first)
+  // A x at cell P of plane k (loads the plane above first).  Neighbour loads
+  // are clamped to the cell itself where the neighbour does not exist, and
+  // the wall tests are selects, so no branch separates the plane's loads.
   __device__ T at(const Geo& G, const Stencil<NDIM, T>& K, const Col& c, int P, int k,
                   const T* __restrict__ cc) {
     constexpr int Z = NDIM - 1;
-    xp = k + 1 < nz ? x[P + pl] : T(0);
-    dp = k + 1 < nz ? D[P + pl] : T(0);
-    T acc = cc[P] * xc;
+    const bool up = k + 1 < nz;
+    const int Pu = up ? P + pl : P;
+    const T xu = x[Pu], du = D[Pu], cP = cc[P];
+    T x_hi[Z > 0 ? Z : 1], x_lo[Z > 0 ? Z : 1], d_hi[Z > 0 ? Z : 1], d_lo[Z > 0 ? Z : 1];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
       const int st = G.st[d], q = coord(c, d);
-      if (q + 1 < G.n[d]) acc += T(0.5) * (dc + D[P + st]) * K.k[d] * (xc - x[P + st]);
-      if (q > 0) acc += T(0.5) * (D[P - st] + dc) * K.k[d] * (xc - x[P - st]);
+      const int Ph = q + 1 < G.n[d] ? P + st : P, Pl = q > 0 ? P - st : P;
+      x_hi[d] = x[Ph];
+      d_hi[d] = D[Ph];
+      x_lo[d] = x[Pl];
+      d_lo[d] = D[Pl];
     }
-    if (k + 1 < nz) acc += T(0.5) * (dc + dp) * K.k[Z] * (xc - xp);
+    xp = up ? xu : T(0);
+    dp = up ? du : T(0);
+    T acc = cP * xc;
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int q = coord(c, d);
+      acc = q + 1 < G.n[d] ? acc + T(0.5) * (dc + d_hi[d]) * K.k[d] * (xc - x_hi[d]) : acc;
+      acc = q > 0 ? acc + T(0.5) * (d_lo[d] + dc) * K.k[d] * (xc - x_lo[d]) : acc;
+    }
+    if (up) acc += T(0.5) * (dc + dp) * K.k[Z] * (xc - xp);
     if (k > 0) acc += T(0.5) * (dm + dc) * K.k[Z] * (xc - xm);
     return acc;
   }
@@ -182,14 +197,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geo G, Stencil<NDIM, T> K, C
     int P = c.base + c.pl * c.k0;
     A.start(c, P);
     for (int k = c.k0; k < c.k1; ++k, P += c.pl) {
-      const T r = v.b[P] - A.at(G, K, c, P, k, v.c);
+      const T bp = v.b[P], di = v.dinv[P];
+      const T r = bp - A.at(G, K, c, P, k, v.c);
       A.next();
       v.r[P] = r;
       v.p0[P] = T(0);
       const double rd = (double)r;
-      red[0] += rd * (double)(r * v.dinv[P]);
+      red[0] += rd * (double)(r * di);
       red[1] += rd * rd;
-      bb[0] += (double)v.b[P] * (double)v.b[P];
+      bb[0] += (double)bp * (double)bp;
     }
   }
   store_partials<2>(red, u_part);
@@ -510,6 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
     A.start(col, P);
     for (int k = col.k0; k < col.k1; ++k, P += col.pl) {
       const double bp = b[P];
+      const float di = v32.dinv[P];
       const double r = bp - A.at(G, K, col, P, k, c);
       A.next();
       r64[P] = r;
@@ -519,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
       v32.p0[P] = 0.0f;
       ro[0] += r * r;
       ro[1] += bp * bp;
-      ri[0] += (double)rf * (double)(rf * v32.dinv[P]);
+      ri[0] += (double)rf * (double)(rf * di);
       ri[1] += (double)rf * (double)rf;
     }
   }

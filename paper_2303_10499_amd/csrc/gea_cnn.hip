@@ -857,6 +857,222 @@ int blocks_for(long n) {
   return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
+// ---- 3D skip-connection layers as a z-march ------------------------------------
+//
+// Layers 3 and 4 read [up(A), X] (A on the grid one level coarser).  Here an M
+// tile is one output row (16 consecutive x cells at one y, z) and K runs, for
+// one input row, over the three x taps and the input channels
+// (k = (dx + 1) CIN + channel, padded to a multiple of 32).  A wave owns RY
+// output rows and marches through z: each input plane is staged once in LDS
+// (fine cells of X and, separately, the coarse cells of A under them), and
+// each A operand -- one input row, one 32-wide K chunk -- is read once and
+// used for up to nine MFMAs: the three y taps of the output rows it borders
+// times the three z taps of the output planes it borders, with accumulators
+// for the planes z - 1, z, z + 1.  An output plane is complete once the plane
+// above it has been added; it then takes bias and ReLU and leaves through a
+// per-wave LDS scratch as 16-byte stores.  The B operands (the weights of one
+// K chunk and one (dy, dz) tap pair, prepacked per lane) are read from LDS
+// when they fit there, else from global memory.  Each wave computes one 16-channel
+// tile of the output channels: with 32 outputs, waves 0-1 and 2-3 take the
+// same rows for the two channel tiles.
+template <int CIN, int CA, int COUT>
+struct ConvZ {
+  static constexpr int RY = 4;                        // output rows per wave
+  static constexpr int NT = COUT / 16;                // output channel tiles
+  static constexpr int WG = 4 / NT;                   // waves per channel tile, stacked in y
+  static constexpr int TX = 16, TY = WG * RY;         // workgroup tile
+  static constexpr int KC = 16;                       // output planes per workgroup
+  static constexpr int CF = CIN - CA;                 // fine channels
+  static constexpr int NCH = (3 * CIN + 31) / 32;     // K chunks of one input row
+  static constexpr int HX = TX + 2, HY = TY + 2;      // staged fine plane (one-cell halo)
+  static constexpr int CHX = TX / 2 + 2, CHY = TY / 2 + 2;  // coarse cells under it
+  static constexpr int FROW = HX * CF * 2, CROW = CHX * CA * 2;  // bytes per staged row
+  static constexpr int F_OFF = 0, C_OFF = HY * FROW;
+  static constexpr int NB = NCH * 9 * NT;             // B fragments, 1 KB each
+  static constexpr bool BL = NB * 1024 <= 48 * 1024;  // B in LDS
+  static constexpr int B_OFF = C_OFF + CHY * CROW;
+  static constexpr int S_OFF = B_OFF + (BL ? NB * 1024 : 0);
+  static constexpr int LDS = S_OFF + 4 * 1024;        // + 1 KB output scratch per wave
+  static constexpr int FU = HX * HY * (CF / 8), CU = CHX * CHY * (CA / 8);  // 16-byte units per plane
+  static constexpr int NL = (FU + CU + 255) / 256;
+  static_assert(CF % 8 == 0 && CA % 8 == 0 && CA > 0 && COUT % 16 == 0 && COUT <= 32, "layout");
+};
+
+template <int CIN, int CA, int COUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_z(
+    CnnDims d, CnnDims dc, const bf16_t* __restrict__ X,
+                                                const bf16_t* __restrict__ A,
+                                                const bf16_t* __restrict__ Wz,
+                                                const float* __restrict__ bias,
+                                                bf16_t* __restrict__ Y) {
+  using T = ConvZ<CIN, CA, COUT>;
+  constexpr int RY = T::RY, NT = T::NT, NCH = T::NCH;
+  __shared__ __attribute__((aligned(16))) unsigned char sm[T::LDS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, g = lane >> 4;
+  const int nt = wave / T::WG, rw = wave % T::WG;  // channel tile, row group
+  const int ntx = (d.nx + T::TX - 1) / T::TX, nty = (d.ny + T::TY - 1) / T::TY;
+  const int b = xcd_block();
+  const int x0 = (b % ntx) * T::TX, y0 = ((b / ntx) % nty) * T::TY;
+  const int k0 = (b / (ntx * nty)) * T::KC, k1 = min(k0 + T::KC, d.nz);
+  const int cx0 = (x0 - 1) >> 1, cy0 = (y0 - 1) >> 1;  // coarse origin of the staged plane
+  if constexpr (T::BL)
+    for (int e = threadIdx.x; e < T::NB * 64; e += 256)
+      *reinterpret_cast<uint4*>(sm + T::B_OFF + e * 16) = *reinterpret_cast<const uint4*>(Wz + (size_t)e * 8);
+  // staging of input plane z: fine cells of X, then the coarse cells of A
+  uint4 v[T::NL];
+  auto fetch = [&](int z) {
+    const bool zin = z >= 0 && z < d.nz;
+    const int cz = z >> 1;
+#pragma unroll
+    for (int u = 0; u < T::NL; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (zin && e < T::FU) {
+        const int cell = e / (T::CF / 8), part = e % (T::CF / 8);
+        const int x = x0 + cell % T::HX - 1, y = y0 + cell / T::HX - 1;
+        if (x >= 0 && x < d.nx && y >= 0 && y < d.ny)
+          v[u] = *reinterpret_cast<const uint4*>(X + (((size_t)z * d.ny + y) * d.nx + x) * T::CF + part * 8);
+      } else if (zin && e < T::FU + T::CU) {
+        const int f = e - T::FU;
+        const int cell = f / (CA / 8), part = f % (CA / 8);
+        const int x = cx0 + cell % T::CHX, y = cy0 + cell / T::CHX;
+        if (x >= 0 && x < dc.nx && y >= 0 && y < dc.ny)
+          v[u] = *reinterpret_cast<const uint4*>(A + (((size_t)cz * dc.ny + y) * dc.nx + x) * CA + part * 8);
+      }
+    }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int u = 0; u < T::NL; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < T::FU + T::CU)
+        *reinterpret_cast<uint4*>(sm + (e < T::FU ? T::F_OFF + e * 16 : T::C_OFF + (e - T::FU) * 16)) = v[u];
+    }
+  };
+  // this lane's A operand address in each K chunk (row 0 of the wave), and
+  // whether its channels are coarse ones
+  int aoff[NCH];
+  bool aco[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int k = 32 * c + 8 * g;
+    int dx = 0, ch = 0;  // K padding: any staged value (its B rows are 0)
+    if (k < 3 * CIN) {
+      dx = k / CIN - 1;
+      ch = k % CIN;
+    }
+    aco[c] = ch < CA;
+    aoff[c] = aco[c] ? T::C_OFF + (((x0 + m + dx) >> 1) - cx0) * (CA * 2) + ch * 2
+                     : T::F_OFF + (m + dx + 1) * (T::CF * 2) + (ch - CA) * 2;
+  }
+  const float bz = bias[nt * 16 + m];
+  f32x4 aM[RY], a0[RY], aP[RY];  // output planes z - 1, z, z + 1
+#pragma unroll
+  for (int j = 0; j < RY; ++j) aM[j] = a0[j] = aP[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto loadB = [&](int c, int dy, int dz) {
+    const int f = ((c * 3 + dy + 1) * 3 + dz + 1) * NT + nt;
+    if constexpr (T::BL)
+      return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sm + T::B_OFF + f * 1024 + lane * 16));
+    else
+      return load8(Wz + (size_t)f * 512 + lane * 8);
+  };
+  // all contributions of the staged plane (input rows RY*rw - 1 ... RY*rw + RY)
+  auto compute = [&]() {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      bf16x8 bw[3][3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) bw[dy][dz] = loadB(c, dy - 1, dz - 1);
+#pragma unroll
+      for (int r = 0; r < RY + 2; ++r) {
+        const int hy = RY * rw + r;  // staged fine row; its coarse row is (hy + 1) / 2
+        const int addr = aoff[c] + (aco[c] ? ((hy + 1) >> 1) * T::CROW : hy * T::FROW);
+        const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sm + addr));
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int j = r - 1 - dy;  // output row of tap dy
+          if (j < 0 || j >= RY) continue;
+          aM[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][2], aM[j], 0, 0, 0);
+          a0[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][1], a0[j], 0, 0, 0);
+          aP[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][0], aP[j], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // bias, ReLU, bf16 of output plane zo (in aM) through the wave's scratch:
+  // two rows of 16 cells x 16 channels per round, then 16 bytes per lane
+  auto store = [&](int zo) {
+    unsigned char* scr = sm + T::S_OFF + wave * 1024;
+#pragma unroll
+    for (int j0 = 0; j0 < RY; j0 += 2) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          reinterpret_cast<bf16_t*>(scr)[(t * 16 + 4 * g + i) * 16 + m] = f2bf(fmaxf(aM[j0 + t][i] + bz, 0.f));
+      const int t = lane >> 5, cell = (lane >> 1) & 15, c8 = nt * 16 + (lane & 1) * 8;
+      const uint4 val = *reinterpret_cast<const uint4*>(scr + lane * 16);
+      const int x = x0 + cell, y = y0 + RY * rw + j0 + t;
+      if (x < d.nx && y < d.ny)
+        *reinterpret_cast<uint4*>(Y + (((size_t)zo * d.ny + y) * d.nx + x) * COUT + c8) = val;
+    }
+  };
+  fetch(k0 - 1);
+  put();
+  __syncthreads();
+  for (int z = k0 - 1; z <= k1; ++z) {
+    if (z < k1) fetch(z + 1);
+    if (z >= 0 && z < d.nz) compute();
+    if (z - 1 >= k0) store(z - 1);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      aM[j] = a0[j];
+      a0[j] = aP[j];
+      aP[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (z < k1) {
+      __syncthreads();  // every wave is done with plane z
+      put();
+      __syncthreads();
+    }
+  }
+}
+
+template <int CIN, int CA, int COUT>
+int convz_tiles(const CnnDims& d) {
+  using T = ConvZ<CIN, CA, COUT>;
+  return ((d.nx + T::TX - 1) / T::TX) * ((d.ny + T::TY - 1) / T::TY) * ((d.nz + T::KC - 1) / T::KC);
+}
+
+// z-march weights: fragment f = ((c * 3 + dy + 1) * 3 + dz + 1) * NT + nt holds, for lane
+// 16 g + n, B[k = 32 c + 8 g + i][out channel 16 nt + n], i = 0..7, where
+// k = (dx + 1) cin + ci; 0 beyond 3 cin
+__global__ __launch_bounds__(256) void k_packz(const float* __restrict__ mW, int cin, int cout,
+                                               int nch, int ntiles, bf16_t* __restrict__ Wz) {
+  const long n = (long)nch * 9 * ntiles * 512;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % 8), lane = (int)((e / 8) % 64);
+    long f = e / 512;
+    const int nt = (int)(f % ntiles);
+    f /= ntiles;
+    const int dz = (int)(f % 3) - 1;
+    f /= 3;
+    const int dy = (int)(f % 3) - 1;
+    const int c = (int)(f / 3);
+    const int k = 32 * c + 8 * (lane >> 4) + i, co = nt * 16 + (lane & 15);
+    float v = 0.f;
+    if (k < 3 * cin && co < cout) {
+      const int dx = k / cin - 1, ci = k % cin;
+      const int t = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+      v = mW[((long)co * 27 + t) * cin + ci];
+    }
+    Wz[e] = f2bf(v);
+  }
+}
+
 int conv_blocks(int npix) { return (npix + 4 * 16 * kMT - 1) / (4 * 16 * kMT); }
 
 // ---- dispatch -------------------------------------------------------------------
@@ -880,7 +1096,13 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
     case 1: GEA_CONV(16, 32, 0); break;
     case 2: GEA_CONV(32, 64, 0); break;
     case 3: GEA_CONV(96, 32, 64); break;
-    case 4: GEA_CONV(48, 16, 32); break;
+    case 4:
+      if (NDIM == 3)
+        hipLaunchKernelGGL((k_conv_z<48, 32, 16>), dim3(convz_tiles<48, 32, 16>(d)), bl, 0, s, d,
+                           n.d[L.level + 1], X, A, n.Wz[4], n.bias[4], (bf16_t*)Y);
+      else
+        GEA_CONV(48, 16, 32);
+      break;
     case 5:
       hipLaunchKernelGGL((k_conv5z<NDIM>), dim3(conv5z_tiles<NDIM>(d)), bl, 0, s, d, X,
                          (const uint32_t*)n.W5, n.bias[5], (float*)Y);
@@ -1050,6 +1272,9 @@ bool cnn_dims_ok(int ndim, int nx, int ny, int nz) {
   return ny >= 4 && ny % 4 == 0;
 }
 
+// 1 KB B fragments of a layer's z-march weights
+long convz_frags(const CnnLayer& L) { return (long)((3 * L.cin + 31) / 32) * 9 * (L.cout_p / 16); }
+
 size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* base, size_t off) {
   n.ndim = ndim;
   n.train = train;
@@ -1077,6 +1302,8 @@ size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* bas
   }
   n.W0 = (bf16_t*)take((size_t)16 * (((ndim == 3 ? 27 : 9) * 2 + 31) / 32 * 32) * B2);
   n.W5 = (bf16_t*)take((size_t)32 * 16 * B2);
+  for (int l = 4; l <= 4; ++l)  // 3D layer 4: z-march weights
+    n.Wz[l] = ndim == 3 ? (bf16_t*)take((size_t)convz_frags(n.L[l]) * 512 * B2) : nullptr;
   n.x2 = (uint32_t*)take(N0 * 4);
   n.xin = train ? (bf16_t*)take(N0 * 8 * B2) : nullptr;
   n.xf = (float*)take(N0 * 2 * F4);
@@ -1138,6 +1365,14 @@ void cnn_pack_weights(Cnn& n) {
                        (const float*)(n.master + L.woff), (const float*)(n.master + L.boff), L.cin,
                        L.cout, 2, 16, kp0, 0, 0, nt, n.W0, (bf16_t*)nullptr, n.bias[0]);
   }
+  for (int l = 4; l <= 4; ++l)
+    if (n.Wz[l]) {
+      const CnnLayer& L = n.L[l];
+      const long work = (long)convz_frags(L) * 512;
+      hipLaunchKernelGGL(k_packz, dim3(blocks_for(work)), dim3(256), 0, n.s,
+                         (const float*)(n.master + L.woff), L.cin, L.cout, (3 * L.cin + 31) / 32,
+                         L.cout_p / 16, n.Wz[l]);
+    }
   for (int l = 0; l < kCnnLayers; ++l) {
     const CnnLayer& L = n.L[l];
     const long work = (long)L.cout_p * L.kpad + (long)L.cin_t_p * L.kpad_t;

@@ -950,22 +950,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         *reinterpret_cast<uint4*>(sm + (e < T::FU ? T::F_OFF + e * 16 : T::C_OFF + (e - T::FU) * 16)) = v[u];
     }
   };
-  // this lane's A operand address in each K chunk (row 0 of the wave), and
-  // whether its channels are coarse ones
-  int aoff[NCH];
-  bool aco[NCH];
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) {
+  // this lane's A operand offset in K chunk c (staged row 0), and whether
+  // its channels are coarse ones
+  auto kch = [&](int c, int& dx, int& ch) {
     const int k = 32 * c + 8 * g;
-    int dx = 0, ch = 0;  // K padding: any staged value (its B rows are 0)
+    dx = 0;
+    ch = 0;  // K padding: any staged value (its B rows are 0)
     if (k < 3 * CIN) {
       dx = k / CIN - 1;
       ch = k % CIN;
     }
-    aco[c] = ch < CA;
-    aoff[c] = aco[c] ? T::C_OFF + (((x0 + m + dx) >> 1) - cx0) * (CA * 2) + ch * 2
-                     : T::F_OFF + (m + dx + 1) * (T::CF * 2) + (ch - CA) * 2;
-  }
+  };
+  auto aco_of = [&](int c) {
+    int dx, ch;
+    kch(c, dx, ch);
+    return ch < CA;
+  };
+  auto aoff_of = [&](int c) {
+    int dx, ch;
+    kch(c, dx, ch);
+    return ch < CA ? T::C_OFF + (((x0 + m + dx) >> 1) - cx0) * (CA * 2) + ch * 2
+                   : T::F_OFF + (m + dx + 1) * (T::CF * 2) + (ch - CA) * 2;
+  };
+  int aoff[T::BL ? NCH : 1];
+  bool aco[T::BL ? NCH : 1];
+  if constexpr (T::BL)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      aoff[c] = aoff_of(c);
+      aco[c] = aco_of(c);
+    }
   const float bz = bias[nt * 16 + m];
   f32x4 aM[RY], a0[RY], aP[RY];  // output planes z - 1, z, z + 1
 #pragma unroll
@@ -977,27 +991,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     else
       return load8(Wz + (size_t)f * 512 + lane * 8);
   };
+  // A operand of input row r (staged fine row RY*rw + r; its coarse row is
+  // (hy + 1) / 2) in K chunk c, at this lane's offset in that chunk
+  auto loadA = [&](int off, bool co, int r) {
+    const int hy = RY * rw + r;
+    const int addr = off + (co ? ((hy + 1) >> 1) * T::CROW : hy * T::FROW);
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sm + addr));
+  };
+  // the nine MFMAs of one A operand per output row it borders
+  auto chunk = [&](int off, bool co, const bf16x8 (&bw)[3][3]) {
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+      const bf16x8 a = loadA(off, co, r);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int j = r - 1 - dy;  // output row of tap dy
+        if (j < 0 || j >= RY) continue;
+        aM[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][2], aM[j], 0, 0, 0);
+        a0[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][1], a0[j], 0, 0, 0);
+        aP[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][0], aP[j], 0, 0, 0);
+      }
+    }
+  };
+  auto loadBs = [&](int c, bf16x8 (&bw)[3][3]) {
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) bw[dy][dz] = loadB(c, dy - 1, dz - 1);
+  };
   // all contributions of the staged plane (input rows RY*rw - 1 ... RY*rw + RY)
   auto compute = [&]() {
+    if constexpr (T::BL) {
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      bf16x8 bw[3][3];
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dz = 0; dz < 3; ++dz) bw[dy][dz] = loadB(c, dy - 1, dz - 1);
-#pragma unroll
-      for (int r = 0; r < RY + 2; ++r) {
-        const int hy = RY * rw + r;  // staged fine row; its coarse row is (hy + 1) / 2
-        const int addr = aoff[c] + (aco[c] ? ((hy + 1) >> 1) * T::CROW : hy * T::FROW);
-        const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sm + addr));
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-          const int j = r - 1 - dy;  // output row of tap dy
-          if (j < 0 || j >= RY) continue;
-          aM[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][2], aM[j], 0, 0, 0);
-          a0[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][1], a0[j], 0, 0, 0);
-          aP[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dy + 1][0], aP[j], 0, 0, 0);
+      for (int c = 0; c < NCH; ++c) {
+        bf16x8 bw[3][3];
+        loadBs(c, bw);
+        chunk(aoff[c], aco[c], bw);
+      }
+    } else {
+      // weights from global memory: a rolled loop over chunk pairs, the next
+      // chunk's nine B operands in flight during the current chunk
+      bf16x8 b0[3][3], b1[3][3];
+      loadBs(0, b0);
+#pragma unroll 1
+      for (int c = 0; c < NCH; c += 2) {
+        if (c + 1 < NCH) loadBs(c + 1, b1);
+        chunk(aoff_of(c), aco_of(c), b0);
+        if (c + 1 < NCH) {
+          if (c + 2 < NCH) loadBs(c + 2, b0);
+          chunk(aoff_of(c + 1), aco_of(c + 1), b1);
         }
       }
     }
@@ -1095,7 +1137,13 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
       break;
     case 1: GEA_CONV(16, 32, 0); break;
     case 2: GEA_CONV(32, 64, 0); break;
-    case 3: GEA_CONV(96, 32, 64); break;
+    case 3:
+      if (NDIM == 3)
+        hipLaunchKernelGGL((k_conv_z<96, 64, 32>), dim3(convz_tiles<96, 64, 32>(d)), bl, 0, s, d,
+                           n.d[L.level + 1], X, A, n.Wz[3], n.bias[3], (bf16_t*)Y);
+      else
+        GEA_CONV(96, 32, 64);
+      break;
     case 4:
       if (NDIM == 3)
         hipLaunchKernelGGL((k_conv_z<48, 32, 16>), dim3(convz_tiles<48, 32, 16>(d)), bl, 0, s, d,
@@ -1302,7 +1350,7 @@ size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* bas
   }
   n.W0 = (bf16_t*)take((size_t)16 * (((ndim == 3 ? 27 : 9) * 2 + 31) / 32 * 32) * B2);
   n.W5 = (bf16_t*)take((size_t)32 * 16 * B2);
-  for (int l = 4; l <= 4; ++l)  // 3D layer 4: z-march weights
+  for (int l = 3; l <= 4; ++l)  // 3D skip-connection layers: z-march weights
     n.Wz[l] = ndim == 3 ? (bf16_t*)take((size_t)convz_frags(n.L[l]) * 512 * B2) : nullptr;
   n.x2 = (uint32_t*)take(N0 * 4);
   n.xin = train ? (bf16_t*)take(N0 * 8 * B2) : nullptr;
@@ -1365,7 +1413,7 @@ void cnn_pack_weights(Cnn& n) {
                        (const float*)(n.master + L.woff), (const float*)(n.master + L.boff), L.cin,
                        L.cout, 2, 16, kp0, 0, 0, nt, n.W0, (bf16_t*)nullptr, n.bias[0]);
   }
-  for (int l = 4; l <= 4; ++l)
+  for (int l = 3; l <= 4; ++l)
     if (n.Wz[l]) {
       const CnnLayer& L = n.L[l];
       const long work = (long)convz_frags(L) * 512;

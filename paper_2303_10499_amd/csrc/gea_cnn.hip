@@ -857,9 +857,10 @@ int blocks_for(long n) {
   return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
-// ---- 3D skip-connection layers as a z-march ------------------------------------
+// ---- 3D convolutions as a z-march -----------------------------------------------
 //
-// Layers 3 and 4 read [up(A), X] (A on the grid one level coarser).  Here an M
+// Layers 1, 3 and 4 in 3D; layers 3 and 4 read [up(A), X] (A on the grid one
+// level coarser; CA = 0: input X alone).  Here an M
 // tile is one output row (16 consecutive x cells at one y, z) and K runs, for
 // one input row, over the three x taps and the input channels
 // (k = (dx + 1) CIN + channel, padded to a multiple of 32).  A wave owns RY
@@ -875,13 +876,13 @@ int blocks_for(long n) {
 // when they fit there, else from global memory.  Each wave computes one 16-channel
 // tile of the output channels: with 32 outputs, waves 0-1 and 2-3 take the
 // same rows for the two channel tiles.
-template <int CIN, int CA, int COUT>
+template <int CIN, int CA, int COUT, int KCH>
 struct ConvZ {
   static constexpr int RY = 4;                        // output rows per wave
   static constexpr int NT = COUT / 16;                // output channel tiles
   static constexpr int WG = 4 / NT;                   // waves per channel tile, stacked in y
   static constexpr int TX = 16, TY = WG * RY;         // workgroup tile
-  static constexpr int KC = 16;                       // output planes per workgroup
+  static constexpr int KC = KCH;                      // output planes per workgroup
   static constexpr int CF = CIN - CA;                 // fine channels
   static constexpr int NCH = (3 * CIN + 31) / 32;     // K chunks of one input row
   static constexpr int HX = TX + 2, HY = TY + 2;      // staged fine plane (one-cell halo)
@@ -895,17 +896,17 @@ struct ConvZ {
   static constexpr int LDS = S_OFF + 4 * 1024;        // + 1 KB output scratch per wave
   static constexpr int FU = HX * HY * (CF / 8), CU = CHX * CHY * (CA / 8);  // 16-byte units per plane
   static constexpr int NL = (FU + CU + 255) / 256;
-  static_assert(CF % 8 == 0 && CA % 8 == 0 && CA > 0 && COUT % 16 == 0 && COUT <= 32, "layout");
+  static_assert(CF % 8 == 0 && CA % 8 == 0 && COUT % 16 == 0 && COUT <= 64, "layout");
 };
 
-template <int CIN, int CA, int COUT>
+template <int CIN, int CA, int COUT, int KCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_z(
     CnnDims d, CnnDims dc, const bf16_t* __restrict__ X,
                                                 const bf16_t* __restrict__ A,
                                                 const bf16_t* __restrict__ Wz,
                                                 const float* __restrict__ bias,
                                                 bf16_t* __restrict__ Y) {
-  using T = ConvZ<CIN, CA, COUT>;
+  using T = ConvZ<CIN, CA, COUT, KCH>;
   constexpr int RY = T::RY, NT = T::NT, NCH = T::NCH;
   __shared__ __attribute__((aligned(16))) unsigned char sm[T::LDS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -933,12 +934,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int x = x0 + cell % T::HX - 1, y = y0 + cell / T::HX - 1;
         if (x >= 0 && x < d.nx && y >= 0 && y < d.ny)
           v[u] = *reinterpret_cast<const uint4*>(X + (((size_t)z * d.ny + y) * d.nx + x) * T::CF + part * 8);
-      } else if (zin && e < T::FU + T::CU) {
-        const int f = e - T::FU;
-        const int cell = f / (CA / 8), part = f % (CA / 8);
-        const int x = cx0 + cell % T::CHX, y = cy0 + cell / T::CHX;
-        if (x >= 0 && x < dc.nx && y >= 0 && y < dc.ny)
-          v[u] = *reinterpret_cast<const uint4*>(A + (((size_t)cz * dc.ny + y) * dc.nx + x) * CA + part * 8);
+      } else if constexpr (CA > 0) {
+        if (zin && e < T::FU + T::CU) {
+          const int f = e - T::FU;
+          const int cell = f / (CA / 8), part = f % (CA / 8);
+          const int x = cx0 + cell % T::CHX, y = cy0 + cell / T::CHX;
+          if (x >= 0 && x < dc.nx && y >= 0 && y < dc.ny)
+            v[u] = *reinterpret_cast<const uint4*>(A + (((size_t)cz * dc.ny + y) * dc.nx + x) * CA + part * 8);
+        }
       }
     }
   };
@@ -1083,9 +1086,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
-template <int CIN, int CA, int COUT>
+template <int CIN, int CA, int COUT, int KCH>
 int convz_tiles(const CnnDims& d) {
-  using T = ConvZ<CIN, CA, COUT>;
+  using T = ConvZ<CIN, CA, COUT, KCH>;
   return ((d.nx + T::TX - 1) / T::TX) * ((d.ny + T::TY - 1) / T::TY) * ((d.nz + T::KC - 1) / T::KC);
 }
 
@@ -1135,18 +1138,24 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
       hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d,
                          (const uint32_t*)n.x2, n.W0, n.bias[0], (bf16_t*)Y);
       break;
-    case 1: GEA_CONV(16, 32, 0); break;
+    case 1:
+      if (NDIM == 3)
+        hipLaunchKernelGGL((k_conv_z<16, 0, 32, 16>), dim3(convz_tiles<16, 0, 32, 16>(d)), bl, 0, s, d, d,
+                           X, X, n.Wz[1], n.bias[1], (bf16_t*)Y);
+      else
+        GEA_CONV(16, 32, 0);
+      break;
     case 2: GEA_CONV(32, 64, 0); break;
     case 3:
       if (NDIM == 3)
-        hipLaunchKernelGGL((k_conv_z<96, 64, 32>), dim3(convz_tiles<96, 64, 32>(d)), bl, 0, s, d,
+        hipLaunchKernelGGL((k_conv_z<96, 64, 32, 16>), dim3(convz_tiles<96, 64, 32, 16>(d)), bl, 0, s, d,
                            n.d[L.level + 1], X, A, n.Wz[3], n.bias[3], (bf16_t*)Y);
       else
         GEA_CONV(96, 32, 64);
       break;
     case 4:
       if (NDIM == 3)
-        hipLaunchKernelGGL((k_conv_z<48, 32, 16>), dim3(convz_tiles<48, 32, 16>(d)), bl, 0, s, d,
+        hipLaunchKernelGGL((k_conv_z<48, 32, 16, 32>), dim3(convz_tiles<48, 32, 16, 32>(d)), bl, 0, s, d,
                            n.d[L.level + 1], X, A, n.Wz[4], n.bias[4], (bf16_t*)Y);
       else
         GEA_CONV(48, 16, 32);
@@ -1350,8 +1359,8 @@ size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* bas
   }
   n.W0 = (bf16_t*)take((size_t)16 * (((ndim == 3 ? 27 : 9) * 2 + 31) / 32 * 32) * B2);
   n.W5 = (bf16_t*)take((size_t)32 * 16 * B2);
-  for (int l = 3; l <= 4; ++l)  // 3D skip-connection layers: z-march weights
-    n.Wz[l] = ndim == 3 ? (bf16_t*)take((size_t)convz_frags(n.L[l]) * 512 * B2) : nullptr;
+  for (int l = 1; l <= 4; ++l)  // 3D layers 1, 3, 4: z-march weights
+    n.Wz[l] = (ndim == 3 && l != 2) ? (bf16_t*)take((size_t)convz_frags(n.L[l]) * 512 * B2) : nullptr;
   n.x2 = (uint32_t*)take(N0 * 4);
   n.xin = train ? (bf16_t*)take(N0 * 8 * B2) : nullptr;
   n.xf = (float*)take(N0 * 2 * F4);
@@ -1413,7 +1422,7 @@ void cnn_pack_weights(Cnn& n) {
                        (const float*)(n.master + L.woff), (const float*)(n.master + L.boff), L.cin,
                        L.cout, 2, 16, kp0, 0, 0, nt, n.W0, (bf16_t*)nullptr, n.bias[0]);
   }
-  for (int l = 3; l <= 4; ++l)
+  for (int l = 1; l <= 4; ++l)
     if (n.Wz[l]) {
       const CnnLayer& L = n.L[l];
       const long work = (long)convz_frags(L) * 512;

@@ -858,6 +858,30 @@ int blocks_for(long n) {
 }
 
 // ---- 3D convolutions as a z-march -----------------------------------------------
+
+// Bias, ReLU and bf16 of RY output rows (16 cells x one 16-channel tile each,
+// in MFMA D layout) through a wave's 1 KB LDS scratch: two rows per round,
+// then 16 bytes per lane to the channels-last output (COUT channels per cell).
+template <int RY, int COUT>
+__device__ __forceinline__ void store_rows(const f32x4 (&acc)[RY], float bz, unsigned char* scr,
+                                           const CnnDims& d, int x0, int y, int zo, int nt,
+                                           bf16_t* __restrict__ Y) {
+  const int lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int j0 = 0; j0 < RY; j0 += 2) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        reinterpret_cast<bf16_t*>(scr)[(t * 16 + 4 * g + i) * 16 + m] = f2bf(fmaxf(acc[j0 + t][i] + bz, 0.f));
+    const int t = lane >> 5, cell = (lane >> 1) & 15, c8 = nt * 16 + (lane & 1) * 8;
+    const uint4 val = *reinterpret_cast<const uint4*>(scr + lane * 16);
+    const int x = x0 + cell, yy = y + j0 + t;
+    if (x < d.nx && yy < d.ny)
+      *reinterpret_cast<uint4*>(Y + (((size_t)zo * d.ny + yy) * d.nx + x) * COUT + c8) = val;
+  }
+}
+
 //
 // Layers 1, 3 and 4 in 3D; layers 3 and 4 read [up(A), X] (A on the grid one
 // level coarser; CA = 0: input X alone).  Here an M
@@ -1047,23 +1071,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       }
     }
   };
-  // bias, ReLU, bf16 of output plane zo (in aM) through the wave's scratch:
-  // two rows of 16 cells x 16 channels per round, then 16 bytes per lane
   auto store = [&](int zo) {
-    unsigned char* scr = sm + T::S_OFF + wave * 1024;
-#pragma unroll
-    for (int j0 = 0; j0 < RY; j0 += 2) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          reinterpret_cast<bf16_t*>(scr)[(t * 16 + 4 * g + i) * 16 + m] = f2bf(fmaxf(aM[j0 + t][i] + bz, 0.f));
-      const int t = lane >> 5, cell = (lane >> 1) & 15, c8 = nt * 16 + (lane & 1) * 8;
-      const uint4 val = *reinterpret_cast<const uint4*>(scr + lane * 16);
-      const int x = x0 + cell, y = y0 + RY * rw + j0 + t;
-      if (x < d.nx && y < d.ny)
-        *reinterpret_cast<uint4*>(Y + (((size_t)zo * d.ny + y) * d.nx + x) * COUT + c8) = val;
-    }
+    store_rows<RY, COUT>(aM, bz, sm + T::S_OFF + wave * 1024, d, x0, y0 + RY * rw, zo, nt, Y);
   };
   fetch(k0 - 1);
   put();
@@ -1090,6 +1099,118 @@ template <int CIN, int CA, int COUT, int KCH>
 int convz_tiles(const CnnDims& d) {
   using T = ConvZ<CIN, CA, COUT, KCH>;
   return ((d.nx + T::TX - 1) / T::TX) * ((d.ny + T::TY - 1) / T::TY) * ((d.nz + T::KC - 1) / T::KC);
+}
+
+// Layer 0 in 3D as a z-march (2 real input channels, 4 bytes per staged cell).
+// A wave owns 4 output rows of 16 cells; one MFMA's K covers the nine (dx, dy)
+// taps of one z tap: lane group g < 3 holds the three x taps x 2 channels of
+// input row dy = g - 1 (k = 8g ... 8g + 5, three 4-byte LDS reads), the rest
+// of K is zero.  Each A operand serves the three z taps: MFMAs into the
+// accumulators of planes z - 1, z, z + 1.  W0z holds the three B operands.
+struct Conv0Z {
+  static constexpr int RY = 4, TX = 16, TY = 4 * RY, KC = 32;
+  static constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;
+  static constexpr int NL = (HP + 255) / 256;
+};
+
+__global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __restrict__ X2,
+                                                const bf16_t* __restrict__ W0z,
+                                                const float* __restrict__ bias,
+                                                bf16_t* __restrict__ Y) {
+  using T = Conv0Z;
+  constexpr int RY = T::RY;
+  __shared__ uint32_t s2[T::HP];
+  __shared__ __attribute__((aligned(16))) unsigned char scr[4 * 1024];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, g = lane >> 4;
+  const int ntx = (d.nx + T::TX - 1) / T::TX, nty = (d.ny + T::TY - 1) / T::TY;
+  const int b = xcd_block();
+  const int x0 = (b % ntx) * T::TX, y0 = ((b / ntx) % nty) * T::TY;
+  const int k0 = (b / (ntx * nty)) * T::KC, k1 = min(k0 + T::KC, d.nz);
+  bf16x8 bw[3];  // dz = -1, 0, +1
+#pragma unroll
+  for (int i = 0; i < 3; ++i) bw[i] = load8(W0z + (size_t)(i * 64 + lane) * 8);
+  const float bz = bias[m];
+  uint32_t v[T::NL];
+  auto fetch = [&](int z) {
+    const bool zin = z >= 0 && z < d.nz;
+#pragma unroll
+    for (int u = 0; u < T::NL; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int x = x0 + e % T::HX - 1, y = y0 + e / T::HX - 1;
+      v[u] = 0u;
+      if (zin && e < T::HP && x >= 0 && x < d.nx && y >= 0 && y < d.ny)
+        v[u] = X2[((size_t)z * d.ny + y) * d.nx + x];
+    }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int u = 0; u < T::NL; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < T::HP) s2[e] = v[u];
+    }
+  };
+  f32x4 aM[RY], a0[RY], aP[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) aM[j] = a0[j] = aP[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&]() {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      uint4 a = make_uint4(0u, 0u, 0u, 0u);
+      if (g < 3) {
+        const int h = (RY * wave + j + g) * T::HX + m;  // input row y + g - 1, cells x - 1 ... x + 1
+        a.x = s2[h];
+        a.y = s2[h + 1];
+        a.z = s2[h + 2];
+      }
+      const bf16x8 av = __builtin_bit_cast(bf16x8, a);
+      aM[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[2], aM[j], 0, 0, 0);
+      a0[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[1], a0[j], 0, 0, 0);
+      aP[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[0], aP[j], 0, 0, 0);
+    }
+  };
+  fetch(k0 - 1);
+  put();
+  __syncthreads();
+  for (int z = k0 - 1; z <= k1; ++z) {
+    if (z < k1) fetch(z + 1);
+    if (z >= 0 && z < d.nz) compute();
+    if (z - 1 >= k0) store_rows<RY, 16>(aM, bz, scr + wave * 1024, d, x0, y0 + RY * wave, z - 1, 0, Y);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      aM[j] = a0[j];
+      a0[j] = aP[j];
+      aP[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (z < k1) {
+      __syncthreads();
+      put();
+      __syncthreads();
+    }
+  }
+}
+
+int conv0z_tiles(const CnnDims& d) {
+  using T = Conv0Z;
+  return ((d.nx + T::TX - 1) / T::TX) * ((d.ny + T::TY - 1) / T::TY) * ((d.nz + T::KC - 1) / T::KC);
+}
+
+// layer 0 z-march weights: fragment dz + 1 holds, for lane 16 g + n,
+// B[k = 8 g + i][n] = W[n][tap(dx, dy = g - 1, dz)][ch] with i = 2 (dx + 1) + ch
+// for g < 3, i < 6; 0 elsewhere
+__global__ __launch_bounds__(256) void k_pack0z(const float* __restrict__ mW, int cout,
+                                                bf16_t* __restrict__ W0z) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 3 * 64 * 8; e += gridDim.x * blockDim.x) {
+    const int i = e % 8, lane = (e / 8) % 64, dz = e / 512 - 1;
+    const int g = lane >> 4, n = lane & 15;
+    float v = 0.f;
+    if (g < 3 && i < 6 && n < cout) {
+      const int dx = i / 2 - 1, ch = i % 2, dy = g - 1;
+      const int t = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+      v = mW[((long)n * 27 + t) * 2 + ch];
+    }
+    W0z[e] = f2bf(v);
+  }
 }
 
 // z-march weights: fragment f = ((c * 3 + dy + 1) * 3 + dz + 1) * NT + nt holds, for lane
@@ -1135,11 +1256,15 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
                      A, n.W[layer], n.bias[layer], (bf16_t*)Y)
   switch (layer) {
     case 0:
-      hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d,
-                         (const uint32_t*)n.x2, n.W0, n.bias[0], (bf16_t*)Y);
+      if constexpr (NDIM == 3)
+        hipLaunchKernelGGL(k_conv0z, dim3(conv0z_tiles(d)), bl, 0, s, d, (const uint32_t*)n.x2, n.W0z,
+                           n.bias[0], (bf16_t*)Y);
+      else
+        hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d,
+                           (const uint32_t*)n.x2, n.W0, n.bias[0], (bf16_t*)Y);
       break;
     case 1:
-      if (NDIM == 3)
+      if constexpr (NDIM == 3)
         hipLaunchKernelGGL((k_conv_z<16, 0, 32, 16>), dim3(convz_tiles<16, 0, 32, 16>(d)), bl, 0, s, d, d,
                            X, X, n.Wz[1], n.bias[1], (bf16_t*)Y);
       else
@@ -1147,14 +1272,14 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
       break;
     case 2: GEA_CONV(32, 64, 0); break;
     case 3:
-      if (NDIM == 3)
+      if constexpr (NDIM == 3)
         hipLaunchKernelGGL((k_conv_z<96, 64, 32, 16>), dim3(convz_tiles<96, 64, 32, 16>(d)), bl, 0, s, d,
                            n.d[L.level + 1], X, A, n.Wz[3], n.bias[3], (bf16_t*)Y);
       else
         GEA_CONV(96, 32, 64);
       break;
     case 4:
-      if (NDIM == 3)
+      if constexpr (NDIM == 3)
         hipLaunchKernelGGL((k_conv_z<48, 32, 16, 32>), dim3(convz_tiles<48, 32, 16, 32>(d)), bl, 0, s, d,
                            n.d[L.level + 1], X, A, n.Wz[4], n.bias[4], (bf16_t*)Y);
       else
@@ -1359,6 +1484,7 @@ size_t cnn_carve(Cnn& n, int ndim, int nx, int ny, int nz, bool train, char* bas
   }
   n.W0 = (bf16_t*)take((size_t)16 * (((ndim == 3 ? 27 : 9) * 2 + 31) / 32 * 32) * B2);
   n.W5 = (bf16_t*)take((size_t)32 * 16 * B2);
+  n.W0z = ndim == 3 ? (bf16_t*)take((size_t)3 * 64 * 8 * B2) : nullptr;
   for (int l = 1; l <= 4; ++l)  // 3D layers 1, 3, 4: z-march weights
     n.Wz[l] = (ndim == 3 && l != 2) ? (bf16_t*)take((size_t)convz_frags(n.L[l]) * 512 * B2) : nullptr;
   n.x2 = (uint32_t*)take(N0 * 4);
@@ -1422,6 +1548,9 @@ void cnn_pack_weights(Cnn& n) {
                        (const float*)(n.master + L.woff), (const float*)(n.master + L.boff), L.cin,
                        L.cout, 2, 16, kp0, 0, 0, nt, n.W0, (bf16_t*)nullptr, n.bias[0]);
   }
+  if (n.W0z)
+    hipLaunchKernelGGL(k_pack0z, dim3(2), dim3(256), 0, n.s, (const float*)(n.master + n.L[0].woff),
+                       n.L[0].cout, n.W0z);
   for (int l = 1; l <= 4; ++l)
     if (n.Wz[l]) {
       const CnnLayer& L = n.L[l];

@@ -47,6 +47,7 @@ struct Cnn {
   bf16_t* W0 = nullptr;  // layer 0 weights in the (tap, 2 channels) K order
   bf16_t* W5 = nullptr;  // layer 5 weights transposed: [tap (32)][channel (16)]
   bf16_t* Wz[kCnnLayers] = {};  // 3D layers 1, 3, 4: weights packed for the z-march kernel
+  bf16_t* W0z = nullptr;        // 3D layer 0: its three z-march B operands
   float* bias[kCnnLayers] = {};
   // forward activations (bf16, channels last)
   uint32_t* x2;  // input, 2 bf16 channels per cell (what layer 0 reads)

@@ -68,12 +68,11 @@ ZPlan zplan(const Geo& G);
 
 // ---- explicit step kernels (gea_step.hip) ----------------------------------
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                      double* const* u, double* const* phi, double* rho_star);
+                      double* const* u, const double* T, double* const* phi, double* rho_star,
+                      double* e0);
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                         double* const* u, const double* pp, const double* rho_star,
                         double* const* phi, double* const* u_star);
-void launch_energy_init(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
-                        double* const* u, double* e0);
 void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                          const double* e0, const double* e_prev, const double* T_prev,
                          double* const* phi, const double* rho_star, double* const* u_star,

@@ -26,13 +26,6 @@ __device__ __forceinline__ double phi_face(const Geo& G, const Phys& ph, int d, 
   return d == NDIM - 1 ? ph.g * (cq + 1.0) * G.dz : phi_cell(G, ph, kz);
 }
 
-template <int NDIM>
-__device__ __forceinline__ double kinetic(const Vec<NDIM>& u, int P) {
-  double k = 0.0;
-#pragma unroll
-  for (int d = 0; d < NDIM; ++d) k += u.p[d][P] * u.p[d][P];
-  return 0.5 * k;
-}
 
 // Five consecutive values of a cell field along one direction, centred on
 // the cell.  Positions outside the mesh hold the centre value (their load is
@@ -105,12 +98,14 @@ __device__ __forceinline__ double phit_val(double D_lo, double D_hi, double H_lo
 
 // ---- Step 1 ----------------------------------------------------------------
 
-// phi_f = I4(rho u . n) S on interior faces, rho* = rho - dt/V sum_out phi
+// phi_f = I4(rho u . n) S on interior faces, rho* = rho - dt/V sum_out phi;
+// also e^n = c_v T + K + Phi, the total energy the Step 2 sweeps start from
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
                                                       const double* __restrict__ rho,
-                                                      Vec<NDIM> u, Vec<NDIM> phi,
-                                                      double* __restrict__ rho_star) {
+                                                      Vec<NDIM> u, const double* __restrict__ T,
+                                                      Vec<NDIM> phi, double* __restrict__ rho_star,
+                                                      double* __restrict__ e0) {
   constexpr int Z = NDIM - 1;
   const Col c = col_of<NDIM>(G, kc);
   if (!c.act) return;
@@ -128,7 +123,10 @@ __global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
       const double* ud = u.p[d];
       s[d] = line_at([&](int Q) { return rho[Q] * ud[Q]; }, P, G.st[d], coord(c, d), G.n[d]);
     }
-    const double r = rho[P];
+    const double r = rho[P], Tc = T[P];
+    double uc[NDIM];
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) uc[d] = u.p[d][P];
     const double znext = mz(nb(k + 3 < nz, P + 3 * pl, P));
     // fluxes
     double sum = 0.0, hid[NDIM - 1];
@@ -149,6 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
     for (int d = 0; d < Z; ++d) phi.p[d][P] = hid[d];
     phi.p[Z][P] = hi;
     rho_star[P] = r - ph.dt / G.V * sum;
+    double kin = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) kin += uc[d] * uc[d];
+    e0[P] = ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, k);
     z = shift(z, k + 3 < nz ? znext : 0.0);
   }
 }
@@ -255,17 +257,6 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
 }
 
 // ---- Step 2 ----------------------------------------------------------------
-
-// e^n = c_v T + K + Phi
-template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_energy_init(Geo G, Phys ph, const double* __restrict__ T,
-                                                        Vec<NDIM> u, double* __restrict__ e0) {
-  GEA_FOR_CELLS(P, G) {
-    int c[NDIM];
-    cell_coords<NDIM>(G, P, c);
-    e0[P] = ph.cv * T[P] + kinetic<NDIM>(u, P) + phi_cell(G, ph, c[NDIM - 1]);
-  }
-}
 
 // One Picard sweep of the total-energy equation with frozen flux phi:
 //   rho* e = rho^n e^n - dt/V sum_out phi I4(e + R T) + dt/V sum (mu/Pr) c_p snGrad(T - T_bg) S
@@ -759,12 +750,13 @@ ZPlan zplan(const Geo& G) { return G.ndim == 2 ? zplan_t<2>(G) : zplan_t<3>(G); 
 #define V3(a) vec<3>(a)
 
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                      double* const* u, double* const* phi, double* rho_star) {
+                      double* const* u, const double* T, double* const* phi, double* rho_star,
+                      double* e0) {
   const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), V2(phi), rho_star);
+    hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
   else
-    hipLaunchKernelGGL(k_mass_flux<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), V3(phi), rho_star);
+    hipLaunchKernelGGL(k_mass_flux<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), T, V3(phi), rho_star, e0);
 }
 
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
@@ -775,14 +767,6 @@ void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const doubl
     hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star));
   else
     hipLaunchKernelGGL(k_mom_predict<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star));
-}
-
-void launch_energy_init(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
-                        double* const* u, double* e0) {
-  if (G.ndim == 2)
-    hipLaunchKernelGGL(k_energy_init<2>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, T, V2(u), e0);
-  else
-    hipLaunchKernelGGL(k_energy_init<3>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, T, V3(u), e0);
 }
 
 void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,

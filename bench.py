@@ -37,8 +37,8 @@ CLASS_NAMES = {0: "k_cg_spmv<fp64>", 1: "k_cg_update<fp64>", 2: "k_cg_spmv<fp32>
                3: "k_cg_update<fp32>", 4: "solver set-up/check kernels",
                5: "explicit step kernels", 6: "learned network"}
 # the six forward convolutions of the network (bf16 matrix-core kernels)
-LAYER_NAMES = ["k_conv0 L0 (2->16)", "k_conv_t L1 (16->32, 1/2)", "k_conv_t L2 (32->64, 1/4)",
-               "k_conv_t L3 ([64,32]->32, 1/2)", "k_conv_t L4 ([32,16]->16)", "k_conv5z L5 (16->1)"]
+LAYER_NAMES = ["k_conv0z L0 (2->16)", "k_conv_z L1 (16->32, 1/2)", "k_conv_t L2 (32->64, 1/4)",
+               "k_conv_z L3 ([64,32]->32, 1/2)", "k_conv_z L4 ([32,16]->16)", "k_conv5z L5 (16->1)"]
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # vector bf16 pair dot products (layer 5): 256 CUs x 64 lanes x 2.4 GHz x 4 FLOP
 VALU_DOT2_PEAK_TFLOPS = 157.3

@@ -28,13 +28,11 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell of one launch of each kernel class (each array
 # read or written once; halo re-reads are not counted)
 BYTES_PER_CELL = {
-    0: 56.0,   # FP64 operator: read r, 1/diag, p_old, c, D; write p, q
-    1: 56.0,   # FP64 update:   read x, p, r, q, 1/diag; write x, r
-    2: 28.0,   # FP32 operator (same arrays in FP32)
-    3: 28.0,   # FP32 update
+    0: 88.0,   # FP64 CG iteration: read r, A p, p (old), x, 1/diag, c, D; write r, p, A p, x
+    2: 44.0,   # FP32 CG iteration (same arrays in FP32)
 }
-CLASS_NAMES = {0: "k_cg_spmv<fp64>", 1: "k_cg_update<fp64>", 2: "k_cg_spmv<fp32>",
-               3: "k_cg_update<fp32>", 4: "solver set-up/check kernels",
+CLASS_NAMES = {0: "k_cg_iter<fp64>", 1: "k_cg_scalars<fp64>", 2: "k_cg_iter<fp32>",
+               3: "k_cg_scalars<fp32>", 4: "solver set-up kernels",
                5: "explicit step kernels", 6: "learned network"}
 # the six forward convolutions of the network (bf16 matrix-core kernels)
 LAYER_NAMES = ["k_conv0z L0 (2->16)", "k_conv_z L1 (16->32, 1/2)", "k_conv_t L2 (32->64, 1/4)",
@@ -100,7 +98,7 @@ def run_form(cfg, form, steps, warmup, kernel_steps):
     # candidates for the dominant kernel: device time per step = average
     # launch duration x launches per step
     cands = {}
-    for k in range(4):
+    for k in BYTES_PER_CELL:
         if kn[k]:
             cands[CLASS_NAMES[k]] = dict(bound="hbm", avg_ms=avg[k], per_step_ms=avg[k] * kn[k] / kernel_steps,
                                          work=BYTES_PER_CELL[k] * nc)

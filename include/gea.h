@@ -174,11 +174,12 @@ gea_status gea_get_fields(gea_ctx* ctx, uint32_t field_mask, double* out, gea_pt
 /* Measurement support.  With timing on, every kernel launch is bracketed by
  * two events on the context's stream and its device time is summed per
  * kernel class:
- *   0 FP64 CG operator kernel (p update, q = A p, <p,q>)
- *   1 FP64 CG update kernel (x, r, <r,z>, <r,r>)
- *   2 FP32 inner CG operator kernel   3 FP32 inner CG update kernel
- *   4 solver set-up and check kernels (initial residual, per-batch stop
- *     test, refinement residual and correction, FP32 coefficient copy)
+ *   0 FP64 CG iteration kernel (the previous update of r and x, the new
+ *     direction p, q = A p, the iteration's partial dot products)
+ *   1 FP64 CG scalar kernel (one workgroup: alpha, beta, stop test)
+ *   2 FP32 inner CG iteration kernel  3 FP32 inner CG scalar kernel
+ *   4 solver set-up kernels (initial residual and its scalars, refinement
+ *     residual and correction, FP32 coefficient copy)
  *   5 explicit step kernels (Steps 1-3 outside the solve)
  *   6 learned network kernels         7 unused
  * reset = 1 clears the sums.  Timing adds two event records per launch. */
@@ -189,9 +190,11 @@ gea_status gea_kernel_times(gea_ctx* ctx, double* ms, int64_t* launches);
 
 /* Average device milliseconds of one launch of the CG kernels on the
  * pressure system of the last assembly, each launched reps times back to
- * back between two events on the context's stream: ms[0] FP64 operator
- * kernel, ms[1] FP64 update kernel, ms[2] FP32 operator kernel, ms[3] FP32
- * update kernel.  Uses scratch vectors only; the state is not changed. */
+ * back between two events on the context's stream: ms[0] FP64 iteration
+ * kernel, ms[1] FP64 scalar kernel, ms[2] FP32 iteration kernel, ms[3] FP32
+ * scalar kernel (iteration 1 of a fresh solve, so that the previous
+ * iteration's update is applied as in every later one).  Uses scratch
+ * vectors only; the state is not changed. */
 gea_status gea_time_solver_kernels(gea_ctx* ctx, int32_t reps, double* ms);
 
 /* Average device milliseconds of one launch of each of the six forward

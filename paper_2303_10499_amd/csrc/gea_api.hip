@@ -148,11 +148,13 @@ struct gea_ctx {
   double* H[3];
   double* b;
   double* dinv;
-  // FP64 CG
+  // FP64 CG (residual and A p double buffered)
   double* r;
+  double* r1;
   double* p0;
   double* p1;
   double* q;
+  double* q1;
   double* xs;  // scratch vector (solutions, operator application)
   // mixed precision
   double* r64;
@@ -160,9 +162,11 @@ struct gea_ctx {
   float* D32;
   float* dinv32;
   float* r32;
+  float* r132;
   float* p032;
   float* p132;
   float* q32;
+  float* q132;
   float* d32;
   // reductions
   double* partials;  // per-workgroup partials of the step kernels
@@ -247,18 +251,22 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->b = cv.take<double>(nc);
   x->dinv = cv.take<double>(nc);
   x->r = cv.take<double>(nc);
+  x->r1 = cv.take<double>(nc);
   x->p0 = cv.take<double>(nc);
   x->p1 = cv.take<double>(nc);
   x->q = cv.take<double>(nc);
+  x->q1 = cv.take<double>(nc);
   x->xs = cv.take<double>(nc);
   x->r64 = cv.take<double>(nc);
   x->c32 = cv.take<float>(nc);
   x->D32 = cv.take<float>(nc);
   x->dinv32 = cv.take<float>(nc);
   x->r32 = cv.take<float>(nc);
+  x->r132 = cv.take<float>(nc);
   x->p032 = cv.take<float>(nc);
   x->p132 = cv.take<float>(nc);
   x->q32 = cv.take<float>(nc);
+  x->q132 = cv.take<float>(nc);
   x->d32 = cv.take<float>(nc);
   {
     const int zb = 3 * zplan(make_geo(m)).blocks;  // partials of the correction kernel
@@ -267,16 +275,15 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->o_part = cv.take<double>(kMaxPartials);
   x->sc = cv.take<CgScalars>(1);
   x->sc32 = cv.take<CgScalars>(1);
-  const int ns = spmv_grid(make_geo(m));
-  // update partials: one per workgroup of the update grid (at most 2048) or
-  // of the set-up kernels' column-tile grid, two values each
+  // partials: 7 per workgroup of the iteration kernel's grid; 2 (and 1 for
+  // ||b||^2) per workgroup of the set-up kernels' column-tile grid
+  const int ns = iter_grid(make_geo(m));
   const int nzb = zplan(make_geo(m)).blocks;
-  const int nu = nzb > 2048 ? nzb : 2048;
   for (CgWork* w : {&x->w64, &x->w32}) {
-    w->s = cv.take<double>(ns);
-    w->u[0] = cv.take<double>(2 * nu);
-    w->u[1] = cv.take<double>(2 * nu);
-    w->b = cv.take<double>(nu);
+    w->s = cv.take<double>(7 * (size_t)ns);
+    w->u[0] = nullptr;
+    w->u[1] = cv.take<double>(2 * (size_t)nzb);
+    w->b = cv.take<double>(nzb);
   }
   x->w64.sc = x->sc;
   x->w32.sc = x->sc32;
@@ -352,9 +359,9 @@ void read_scalars(gea_ctx* x, CgScalars* dev, CgScalars* host) {
 // scalars after each batch.  The batch length is predicted from the
 // residual's observed decay rate so that few launches follow convergence
 // (those find the done flag set and return at once).
-template <typename LaunchIter, typename LaunchCheck>
+template <typename LaunchIter>
 gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int first_batch,
-                  LaunchIter&& launch_iter, LaunchCheck&& launch_check) {
+                  LaunchIter&& launch_iter) {
   const int every = x->prm.check_every > 0 ? x->prm.check_every : 8;
   const long cap = (long)max_iter + 4L * every + 64;
   int batch = first_batch > 0 ? first_batch : every;
@@ -367,7 +374,6 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
       return GEA_ERR_HIP;
     }
     for (int k = 0; k < batch; ++k, ++j) launch_iter((int)j);
-    launch_check((int)j);
     HIPCHK(hipGetLastError());
     read_scalars(x, dsc, &hs);
     const int di = hs.iter - prev_iter;
@@ -390,7 +396,7 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
 gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
   const Geo& G = x->G;
   const CgWork& w = x->w64;
-  CgVectors<double> v{xv, x->r, x->p0, x->p1, x->q, x->c, x->D, x->dinv, x->b};
+  CgVectors<double> v{xv, x->r, x->r1, x->p0, x->p1, x->q, x->q1, x->c, x->D, x->dinv, x->b};
   x->timer.run(4, x->stream, [&] { cg_init<double>(x->stream, G, v, w, x->prm.tol, x->prm.max_iter); });
   HIPCHK(hipGetLastError());
   CgScalars hs;
@@ -407,10 +413,9 @@ gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
   gea_status rc = run_cg(
       x, x->sc, hs, x->prm.max_iter, first,
       [&](int j) {
-        x->timer.run(0, x->stream, [&] { cg_spmv<double>(x->stream, G, v, j, w); });
-        x->timer.run(1, x->stream, [&] { cg_update<double>(x->stream, G, v, j, w); });
-      },
-      [&](int j) { x->timer.run(4, x->stream, [&] { cg_check(x->stream, G, j, w); }); });
+        x->timer.run(0, x->stream, [&] { cg_iter_kernel<double>(x->stream, G, v, j, w); });
+        x->timer.run(1, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+      });
   if (rc != GEA_OK) return rc;
   x->last_iters64 = hs.iter;
   out->iters = hs.iter;
@@ -427,7 +432,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   x->timer.run(4, x->stream, [&] {
     launch_cast_coeffs(x->stream, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
   });
-  CgVectors<float> v{x->d32, x->r32, x->p032, x->p132, x->q32, x->c32, x->D32, x->dinv32, x->r32};
+  CgVectors<float> v{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
   int total = 0;
   int outer = 0;
   CgScalars h64, h32;
@@ -467,10 +472,9 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
     gea_status rc = run_cg(
         x, x->sc32, h32, budget, first,
         [&](int j) {
-          x->timer.run(2, x->stream, [&] { cg_spmv<float>(x->stream, G, v, j, w); });
-          x->timer.run(3, x->stream, [&] { cg_update<float>(x->stream, G, v, j, w); });
-        },
-        [&](int j) { x->timer.run(4, x->stream, [&] { cg_check(x->stream, G, j, w); }); });
+          x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
+          x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+        });
     if (rc != GEA_OK) return rc;
     if (outer == 0) x->last_iters32 = h32.iter;
     total += h32.iter;
@@ -537,7 +541,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   x->timer.run(4, x->stream, [&] {
     launch_cast_coeffs(x->stream, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
   });
-  CgVectors<float> v{x->d32, x->r32, x->p032, x->p132, x->q32, x->c32, x->D32, x->dinv32, x->r32};
+  CgVectors<float> v{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
   int total = 0, outer = 0, fallbacks = 0;
   bool use_net = true;
   CgScalars h64, h32;
@@ -589,10 +593,9 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       gea_status rc = run_cg(
           x, x->sc32, h32, budget, first,
           [&](int j) {
-            x->timer.run(2, x->stream, [&] { cg_spmv<float>(x->stream, G, v, j, w); });
-            x->timer.run(3, x->stream, [&] { cg_update<float>(x->stream, G, v, j, w); });
-          },
-          [&](int j) { x->timer.run(4, x->stream, [&] { cg_check(x->stream, G, j, w); }); });
+            x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
+            x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+          });
       if (rc != GEA_OK) return rc;
       done_iters = h32.iter;
       if (h32.status == -5) {
@@ -946,30 +949,35 @@ gea_status gea_time_solver_kernels(gea_ctx* x, int32_t reps, double* ms) {
       HIPCHK(hipEventElapsedTime(&t, a, b));
       return (double)t / reps;
     };
-    // FP64: a fresh solve set-up that never reports done (tol 0), then the
-    // same iteration's kernels launched back to back
+    // FP64: a fresh solve set-up that never reports done (tol 0), its first
+    // iteration, then iteration 1's kernels (an update pending, as in every
+    // later iteration) launched back to back
     HIPCHK(hipMemcpyAsync(x->xs, S.pp, sizeof(double) * G.nc, hipMemcpyDeviceToDevice, s));
-    CgVectors<double> v{x->xs, x->r, x->p0, x->p1, x->q, x->c, x->D, x->dinv, x->b};
+    CgVectors<double> v{x->xs, x->r, x->r1, x->p0, x->p1, x->q, x->q1, x->c, x->D, x->dinv, x->b};
     cg_init<double>(s, G, v, x->w64, 0.0, 1 << 30);
-    cg_spmv<double>(s, G, v, 0, x->w64);  // warm-up
+    cg_iter_kernel<double>(s, G, v, 0, x->w64);
+    cg_scalars(s, G, 0, x->w64);
+    cg_iter_kernel<double>(s, G, v, 1, x->w64);  // warm-up
     HIPCHK(hipEventRecord(ev[0], s));
-    for (int k = 0; k < reps; ++k) cg_spmv<double>(s, G, v, 0, x->w64);
+    for (int k = 0; k < reps; ++k) cg_iter_kernel<double>(s, G, v, 1, x->w64);
     HIPCHK(hipEventRecord(ev[1], s));
-    for (int k = 0; k < reps; ++k) cg_update<double>(s, G, v, 0, x->w64);
+    for (int k = 0; k < reps; ++k) cg_scalars(s, G, 1, x->w64);
     HIPCHK(hipEventRecord(ev[2], s));
     HIPCHK(hipEventSynchronize(ev[2]));
     ms[0] = elapsed(ev[0], ev[1]);
     ms[1] = elapsed(ev[1], ev[2]);
     // FP32 inner kernels on the refinement's set-up (outer tol 0: not done)
     launch_cast_coeffs(s, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
-    CgVectors<float> v32{x->d32, x->r32, x->p032, x->p132, x->q32, x->c32, x->D32, x->dinv32, x->r32};
+    CgVectors<float> v32{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
     launch_residual64(s, G, x->c, x->D, x->b, x->xs, x->r64, v32, 0.0, 1e-30, 1 << 30, x->o_part,
                       x->w32, x->sc);
-    cg_spmv<float>(s, G, v32, 0, x->w32);
+    cg_iter_kernel<float>(s, G, v32, 0, x->w32);
+    cg_scalars(s, G, 0, x->w32);
+    cg_iter_kernel<float>(s, G, v32, 1, x->w32);
     HIPCHK(hipEventRecord(ev[0], s));
-    for (int k = 0; k < reps; ++k) cg_spmv<float>(s, G, v32, 0, x->w32);
+    for (int k = 0; k < reps; ++k) cg_iter_kernel<float>(s, G, v32, 1, x->w32);
     HIPCHK(hipEventRecord(ev[1], s));
-    for (int k = 0; k < reps; ++k) cg_update<float>(s, G, v32, 0, x->w32);
+    for (int k = 0; k < reps; ++k) cg_scalars(s, G, 1, x->w32);
     HIPCHK(hipEventRecord(ev[2], s));
     HIPCHK(hipEventSynchronize(ev[2]));
     ms[2] = elapsed(ev[0], ev[1]);

@@ -4,34 +4,42 @@
 // homogeneous Neumann on walls; face weights are formed on the fly from the
 // cell coefficient D.
 //
-// One iteration is two kernels:
-//   spmv:   p = r/diag + beta p_old on the tile and its halo, q = A p, <p, q>
-//   update: x += alpha p, r -= alpha q, <r, r/diag>, <r, r>
+// One iteration is one stencil kernel and one one-workgroup scalar kernel:
+//   iteration j:  r_j = r_{j-1} - alpha q_{j-1} and p_j = r_j/diag + beta p_{j-1}
+//                 on the tile and its halo, x += alpha p_{j-1} on the own cells,
+//                 q_j = A p_j, and partials <p,q>, <q,z>, <q,q/diag>, <r,r>,
+//                 <q,r>, <q,q>, <r,z> (z = r/diag) of iteration j
+//   scalars j:    alpha_j = <r,z>/<p,q>; <r,z> and ||r||^2 after the update
+//                 r - alpha_j q follow without another pass over the vectors,
+//                 <r - a q, M (r - a q)> = <r,z> - 2a<q,z> + a^2<q,Mq> (and the
+//                 same for ||r||^2), each from directly summed values of the
+//                 iterate before, so rounding does not accumulate; beta_j, the
+//                 stop test (||r|| <= tol ||b||, iteration cap, non-finite).
+// This is Jacobi-PCG with the same iterates; it reads and writes 11 arrays
+// per iteration instead of 14 (separate operator and update kernels) and
+// needs no grid-wide reduction inside the stencil kernel.  The residual,
+// direction and A p are double buffered by iteration parity (the stencil
+// kernel reads the old values with halo while writing the new ones).  When
+// the scalar kernel finds the solve converged it raises a finish flag: the
+// next iteration kernel only applies the last x update, and the scalar
+// kernel after it sets the done flag, on which later launches return at once.
 // Dot products: every workgroup reduces its values (wave xor-shuffles, then
-// LDS) and stores one partial per workgroup.  The next kernel, which needs
-// the scalar, sums all partials of the previous kernel at its start, every
-// workgroup in the same fixed order, so all workgroups hold bitwise the same
-// alpha/beta and no grid-wide fence or atomic is needed (an agent-scope
-// release in every workgroup costs more than the stream kernel it ends).
-// The stop test (||r|| <= tol ||b||, iteration cap, non-finite) is taken by
-// the spmv kernel from the partials of the update before it; workgroup 0
-// publishes scalars and the done flag, which later launches of a batch read
-// to return at once.  A one-workgroup check kernel closes each batch so the
-// host sees the latest residual.
+// LDS) and stores one partial; the scalar kernel sums them in workgroup
+// order, so results are bitwise reproducible.
 //
-// The spmv kernel stages, per workgroup, a 64 x 8 (3D) or 256 x 1 (2D)
-// column tile of p and D with a one-cell halo in an LDS ring of three
-// planes and marches along z, so every value is loaded once per workgroup;
-// workgroups are mapped so that each XCD (own L2) works on a contiguous
-// block of tiles.  The same kernels instantiated on float, with FP64 dot
-// accumulation, are the inner solver of the mixed-precision refinement.
+// The 3D stencil kernel stages, per workgroup, a 64 x 4 column tile of p, D,
+// r and 1/diag with a one-cell halo in an LDS ring of planes and marches
+// along z, so every value is loaded once per workgroup; workgroups are
+// mapped so that each XCD (own L2) works on a contiguous block of tiles.  The
+// same kernels instantiated on float, with FP64 dot accumulation, are the
+// inner solver of the mixed-precision refinement.
 #include "gea_reduce.h"
 
 namespace gea {
 
 namespace {
 
-constexpr int kTX3 = 64, kTY3 = 4, kKC3 = 16;  // 3D tile and z chunk
+constexpr int kTX3 = 64, kTY3 = 8, kKC3 = 16;  // 3D tile and z chunk
 constexpr int kTX2 = 256, kKC2 = 16;           // 2D row segment and z chunk
 
 template <int NDIM, typename T>
@@ -86,45 +94,6 @@ __device__ __forceinline__ T apply_A_at(const Geo& G, const Stencil<NDIM, T>& K,
     if (c[d] > 0) acc += T(0.5) * (D[P - st] + dp) * K.k[d] * (xp - x[P - st]);
   }
   return acc;
-}
-
-// Stop test from the update partials of the previous iteration.  Returns
-// true (in every workgroup) when the solve ends here; workgroup 0 then
-// publishes the result.  Otherwise beta is returned through *beta_out.
-__device__ __forceinline__ bool spmv_prologue(const double* u_part, int nu, int iter,
-                                              CgScalars* sc, double* beta_out) {
-  double s[2];
-  sum_partials<2>(u_part, nu, s);
-  const double rz = s[0], rr = s[1];
-  int stop = 0, status = 0;
-  if (!isfinite(rz) || !isfinite(rr)) {
-    stop = 1;
-    status = -5;
-  } else if (rr <= sc->tol2 * sc->bb) {
-    stop = 1;
-  } else if (iter >= sc->max_iter) {
-    stop = 1;
-    status = -4;
-  }
-  if (stop) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->rz = rz;
-      sc->rr = rr;
-      sc->iter = iter;
-      sc->status = status;
-      __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return true;
-  }
-  const double rz_old = sc->rzs[(iter + 1) & 1];
-  *beta_out = iter == 0 ? 0.0 : rz / rz_old;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->rzs[iter & 1] = rz;
-    sc->rz = rz;
-    sc->rr = rr;
-    sc->iter = iter;
-  }
-  return false;
 }
 
 // A x at the cells of a column walking up through z: x and D of the planes
@@ -212,161 +181,267 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geo G, Stencil<NDIM, T> K, C
   store_partials<1>(bb, b_part);
 }
 
-// one workgroup: reduce the partials of the last update (or of init) and
-// publish residual and stop test; with init != 0 also ||b||^2 and the setup
-__global__ __launch_bounds__(kBlock) void k_cg_check(const double* u_part, int nu,
-                                                     const double* b_part, int init, double tol2,
-                                                     int max_iter, int iter, CgScalars* sc) {
-  if (!init && load_done(sc)) return;
-  double s[2];
+// one workgroup: set-up of a solve from the set-up kernel's partials
+// (<r, z>, ||r||^2 and ||b||^2 of the initial residual)
+__global__ __launch_bounds__(kBlock) void k_cg_start(const double* u_part, int nu,
+                                                     const double* b_part, double tol2,
+                                                     int max_iter, CgScalars* sc) {
+  double s[2], bbv[1];
   sum_partials<2>(u_part, nu, s);
-  double bbv[1] = {0.0};
-  if (init) sum_partials<1>(b_part, nu, bbv);
+  sum_partials<1>(b_part, nu, bbv);
   if (threadIdx.x != 0) return;
-  if (init) {
-    sc->bb = bbv[0];
-    sc->tol2 = tol2;
-    sc->max_iter = max_iter;
-    sc->status = 0;
-    sc->alpha = 0.0;
-    sc->rzs[0] = s[0];
-    sc->rzs[1] = s[0];
-  }
-  const double bb = sc->bb;
+  const double bb = bbv[0];
+  sc->bb = bb;
+  sc->tol2 = tol2;
+  sc->max_iter = max_iter;
+  sc->alpha = 0.0;
+  sc->beta = 0.0;
+  sc->fin = 0;
   sc->rz = s[0];
   sc->rr = s[1];
-  sc->iter = iter;
-  int done = 0;
+  sc->iter = 0;
+  int done = 0, status = 0;
   if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(bb)) {
-    sc->status = -5;
     done = 1;
-  } else if (s[1] <= sc->tol2 * bb) {
+    status = -5;
+  } else if (s[1] <= tol2 * bb) {
     done = 1;
-  } else if (iter >= sc->max_iter) {
-    sc->status = -4;
+  } else if (max_iter <= 0) {
     done = 1;
+    status = -4;
   }
+  sc->status = status;
   __hip_atomic_store(&sc->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// 3D: p = r/diag + beta p_old, q = A p, partial <p, q>, on a 64 x 8 column
-// tile marching over 16 planes.
+// one workgroup after iteration `iter`: alpha, the residual after the
+// update, beta and the stop test (see the file header)
+__global__ __launch_bounds__(kBlock) void k_cg_scalars(const double* part, int n, int iter,
+                                                       CgScalars* sc) {
+  if (load_done(sc)) return;
+  if (sc->fin) {  // the iteration kernel just applied the last update
+    if (threadIdx.x == 0) __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  double s[7];
+  sum_partials<7>(part, n, s);
+  if (threadIdx.x != 0) return;
+  const double pq = s[0], qz = s[1], qmq = s[2], rr0 = s[3], qr = s[4], qq = s[5], rz0 = s[6];
+  const double alpha = rz0 / pq;
+  const double rz = rz0 - 2.0 * alpha * qz + alpha * alpha * qmq;
+  const double rr = fmax(rr0 - 2.0 * alpha * qr + alpha * alpha * qq, 0.0);
+  sc->iter = iter + 1;
+  sc->alpha = alpha;
+  sc->beta = rz / rz0;
+  sc->rz = rz;
+  sc->rr = rr;
+  int done = 0, fin = 0, status = 0;
+  if (!isfinite(alpha) || !isfinite(rz) || !isfinite(rr) || !isfinite(sc->beta)) {
+    done = 1;
+    status = -5;
+  } else if (rr <= sc->tol2 * sc->bb) {
+    fin = 1;
+  } else if (iter + 1 >= sc->max_iter) {
+    fin = 1;
+    status = -4;
+  }
+  sc->status = status;
+  sc->fin = fin;
+  if (done) __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// the seven partials of an iteration: <p,q>, <q,z>, <q,q/diag>, <r,r>, <q,r>,
+// <q,q>, <r,z> of one cell
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv3(Geo G, Stencil<3, T> K, CgVectors<T> v,
-                                                     const T* __restrict__ p_old,
-                                                     T* __restrict__ p_new, int iter,
-                                                     const double* u_part, int nu,
-                                                     double* s_part, CgScalars* sc) {
+__device__ __forceinline__ void iter_dots(double (&acc)[7], T p, T a, T r, T m) {
+  const T z = r * m, mq = a * m;
+  acc[0] += (double)p * (double)a;
+  acc[1] += (double)a * (double)z;
+  acc[2] += (double)a * (double)mq;
+  acc[3] += (double)r * (double)r;
+  acc[4] += (double)a * (double)r;
+  acc[5] += (double)a * (double)a;
+  acc[6] += (double)r * (double)z;
+}
+
+// 3D iteration kernel: a workgroup owns a 64 x 8 column tile and marches it
+// through a chunk of 16 planes.  Thread t stages its two own cells
+// (t % 64, t / 64) and (t % 64, t / 64 + 4) and, for t < 148, one halo cell of
+// the tile; each staged plane is loaded into registers one plane ahead (old
+// residual, old A p, old direction, D, 1/diag), turned into the new residual
+// and direction, and p and D are written to an LDS ring.  The own cells'
+// new residual and x update are stored there, and their residual and 1/diag
+// stay in the thread's registers for the dot products of the plane, which
+// is computed one step later.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgIter<T> v,
+                                                     double* part, CgScalars* sc) {
   constexpr int TX = kTX3, TY = kTY3, KC = kKC3;
   constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;
-  constexpr int RPT = TX * TY / kBlock;
-  constexpr int HPT = (HP + kBlock - 1) / kBlock;  // staged cells per thread and plane
+  constexpr int RPT = TX * TY / kBlock;  // own cells per thread
+  constexpr int NH = HP - TX * TY;       // halo cells of a plane
+  static_assert(TX == 64 && RPT * kBlock == TX * TY && NH <= kBlock, "tile layout");
   // Plane kk+1 is loaded into registers while plane kk-1 is computed.  FP32:
   // a ring of 4 planes, where the slot a plane is written to was last read
   // two planes earlier, before the previous barrier, so one barrier per plane
-  // suffices.  FP64: a ring of 3 (4 would not leave room for 4 workgroups per
-  // CU) and a second barrier before the next write.
+  // suffices.  FP64: a ring of 3 and a second barrier before the next write.
   constexpr int NS = sizeof(T) == 8 ? 3 : 4;
-  __shared__ T sp[NS][HP];
-  __shared__ T sd[NS][HP];
+  __shared__ T sp[NS][HP];  // direction
+  __shared__ T sd[NS][HP];  // D
   if (load_done(sc)) return;
+  const T alpha = (T)sc->alpha, beta = (T)sc->beta;
+  const int fin = sc->fin;
   const int nx = G.nx, ny = G.ny, nz = G.nz;
   const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
   const int b = xcd_block();
   const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
   const int i0 = tx * TX, j0 = ty * TY, k0 = tz * KC;
   const int k1 = min(k0 + KC, nz);
-  const T kx = K.k[0], ky = K.k[1], kz = K.k[2];
-  // global index of each staged cell of this thread in plane 0 (-1: outside)
-  int qh[HPT];
-#pragma unroll
-  for (int u = 0; u < HPT; ++u) {
-    const int h = threadIdx.x + kBlock * u;
-    const int hx = h % HX, hy = h / HX;
-    const int i = i0 + hx - 1, j = j0 + hy - 1;
-    qh[u] = (h < HP && i >= 0 && i < nx && j >= 0 && j < ny) ? i + nx * j : -1;
-  }
   const int plane = nx * ny;
-  // staged values: z = r/diag, the old direction and D (p = z + beta p_old
-  // is formed when a plane is written to LDS, once beta is known)
-  T pz[HPT], po[HPT], pd[HPT];
-  auto fetch = [&](int kk) {
+  const int lx = threadIdx.x % TX, ly0 = threadIdx.x / TX;
+  const int i = i0 + lx;
+  int jo[RPT];
+  bool in[RPT];
 #pragma unroll
-    for (int u = 0; u < HPT; ++u) {
-      pz[u] = T(0);
-      po[u] = T(0);
-      pd[u] = T(0);
-      if (kk >= 0 && kk < nz && qh[u] >= 0) {
-        const int Q = qh[u] + plane * kk;
-        pz[u] = v.r[Q] * v.dinv[Q];
-        po[u] = p_old[Q];
-        pd[u] = v.D[Q];
+  for (int m = 0; m < RPT; ++m) {
+    jo[m] = j0 + ly0 + m * (kBlock / TX);
+    in[m] = i < nx && jo[m] < ny;
+  }
+  if (fin) {  // the solve ended at the last scalar kernel: its x update only
+#pragma unroll
+    for (int m = 0; m < RPT; ++m)
+      if (in[m])
+        for (int k = k0; k < k1; ++k) {
+          const int P = i + nx * (jo[m] + ny * k);
+          v.x[P] += alpha * v.p_in[P];
+        }
+    return;
+  }
+  const T kx = K.k[0], ky = K.k[1], kz = K.k[2];
+  // staged cells of this thread: [0, RPT) its own cells, [RPT] halo cell e = t
+  // (row 0, row TY+1, then the two side columns); global index in plane 0,
+  // clamped into the mesh (values staged for cells outside it are never read,
+  // and unconditional loads are not waited for where branches would merge)
+  constexpr int NU = RPT + 1;
+  int qh[NU], hh[NU];
+#pragma unroll
+  for (int m = 0; m < RPT; ++m) {
+    hh[m] = (lx + 1) + HX * (jo[m] - j0 + 1);
+    qh[m] = (i < nx ? i : nx - 1) + nx * (jo[m] < ny ? jo[m] : ny - 1);
+  }
+  {
+    const int e = threadIdx.x;
+    int hx = 0, hy = 0;
+    if (e < HX) {
+      hx = e;
+    } else if (e < 2 * HX) {
+      hx = e - HX;
+      hy = TY + 1;
+    } else {
+      const int e2 = e - 2 * HX;
+      hy = 1 + e2 / 2;
+      hx = (e2 & 1) ? HX - 1 : 0;
+    }
+    const int gi = i0 + hx - 1, gj = j0 + hy - 1;
+    hh[RPT] = hx + HX * hy;
+    // threads without a halo cell load their own cell again (a cache hit)
+    qh[RPT] = e < NH ? (gi < 0 ? 0 : (gi >= nx ? nx - 1 : gi)) + nx * (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj))
+                     : qh[0];
+  }
+  const bool halo = threadIdx.x < NH;
+  T fr[NU], fq[NU], fp[NU], fd[NU], fm[NU], fx[RPT], fc[RPT];  // raw values of the plane in flight
+  auto fetch = [&](int kk) {
+    const int o = plane * (kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk));
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int Q = qh[u] + o;
+      fr[u] = v.r_in[Q];
+      fq[u] = v.q_in[Q];
+      fp[u] = v.p_in[Q];
+      fd[u] = v.D[Q];
+      fm[u] = v.dinv[Q];
+      if (u < RPT) {  // own cell: x for its update, c for the operator
+        fx[u] = v.x[Q];
+        fc[u] = v.c[Q];
       }
     }
   };
-  fetch(k0 - 1);  // in flight while the previous kernel's partials are summed
-  double beta_d = 0.0;
-  if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
-  const T beta = (T)beta_d;
-  double acc = 0.0;
+  fetch(k0 - 1);
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // own cells' new residual, 1/diag and c of the last staged plane (the
+  // compute step reads no global memory: a load issued after the next
+  // plane's loads would wait for all of them)
+  T r_own[RPT], m_own[RPT], c_own[RPT];
+#pragma unroll
+  for (int m = 0; m < RPT; ++m) r_own[m] = m_own[m] = c_own[m] = T(0);
   for (int kk = k0 - 1; kk <= k1; ++kk) {
     const int sl = (kk + NS) % NS;
+    T r_prev[RPT], m_prev[RPT], c_prev[RPT];
 #pragma unroll
-    for (int u = 0; u < HPT; ++u) {
-      const int h = threadIdx.x + kBlock * u;
-      if (h < HP) {
-        sp[sl][h] = pz[u] + beta * po[u];
-        sd[sl][h] = pd[u];
-      }
+    for (int m = 0; m < RPT; ++m) {
+      r_prev[m] = r_own[m];
+      m_prev[m] = m_own[m];
+      c_prev[m] = c_own[m];
     }
-    if (kk + 1 <= k1) fetch(kk + 1);
-    __syncthreads();
-    const int k = kk - 1;
-    if (k >= k0 && k < k1) {
-      const int sm = (k - 1 + NS) % NS, s0 = (k + NS) % NS, sP = (k + 1) % NS;
 #pragma unroll
-      for (int m = 0; m < RPT; ++m) {
-        const int t = threadIdx.x + kBlock * m;
-        const int lx = t % TX, ly = t / TX;
-        const int i = i0 + lx, j = j0 + ly;
-        if (i < nx && j < ny) {
-          const int h = (lx + 1) + HX * (ly + 1);
-          const int P = i + nx * (j + ny * k);
-          const T pp = sp[s0][h], dp = sd[s0][h];
-          T a = v.c[P] * pp;
-          if (i + 1 < nx) a += T(0.5) * (dp + sd[s0][h + 1]) * kx * (pp - sp[s0][h + 1]);
-          if (i > 0) a += T(0.5) * (sd[s0][h - 1] + dp) * kx * (pp - sp[s0][h - 1]);
-          if (j + 1 < ny) a += T(0.5) * (dp + sd[s0][h + HX]) * ky * (pp - sp[s0][h + HX]);
-          if (j > 0) a += T(0.5) * (sd[s0][h - HX] + dp) * ky * (pp - sp[s0][h - HX]);
-          if (k + 1 < nz) a += T(0.5) * (dp + sd[sP][h]) * kz * (pp - sp[sP][h]);
-          if (k > 0) a += T(0.5) * (sd[sm][h] + dp) * kz * (pp - sp[sm][h]);
-          p_new[P] = pp;
-          v.q[P] = a;
-          acc += (double)pp * (double)a;
+    for (int u = 0; u < NU; ++u) {
+      if (u == RPT && !halo) break;
+      const T rn = fr[u] - alpha * fq[u];
+      sp[sl][hh[u]] = rn * fm[u] + beta * fp[u];
+      sd[sl][hh[u]] = fd[u];
+      if (u < RPT) {
+        r_own[u] = rn;
+        m_own[u] = fm[u];
+        c_own[u] = fc[u];
+        if (kk >= k0 && kk < k1 && in[u]) {
+          const int Q = qh[u] + plane * kk;
+          v.r_out[Q] = rn;
+          v.x[Q] = fx[u] + alpha * fp[u];
         }
       }
     }
-    if (NS == 3) __syncthreads();
+    if (kk + 1 <= k1) fetch(kk + 1);
+    lds_barrier();
+    const int k = kk - 1;
+    if (k >= k0 && k < k1) {
+      const int sM = (k - 1 + NS) % NS, s0 = (k + NS) % NS, sP = (k + 1) % NS;
+#pragma unroll
+      for (int m = 0; m < RPT; ++m) {
+        if (!in[m]) continue;
+        const int j = jo[m];
+        const int h = hh[m];
+        const int P = i + nx * (j + ny * k);
+        const T pp = sp[s0][h], dp = sd[s0][h];
+        T a = c_prev[m] * pp;
+        if (i + 1 < nx) a += T(0.5) * (dp + sd[s0][h + 1]) * kx * (pp - sp[s0][h + 1]);
+        if (i > 0) a += T(0.5) * (sd[s0][h - 1] + dp) * kx * (pp - sp[s0][h - 1]);
+        if (j + 1 < ny) a += T(0.5) * (dp + sd[s0][h + HX]) * ky * (pp - sp[s0][h + HX]);
+        if (j > 0) a += T(0.5) * (sd[s0][h - HX] + dp) * ky * (pp - sp[s0][h - HX]);
+        if (k + 1 < nz) a += T(0.5) * (dp + sd[sP][h]) * kz * (pp - sp[sP][h]);
+        if (k > 0) a += T(0.5) * (sd[sM][h] + dp) * kz * (pp - sp[sM][h]);
+        v.p_out[P] = pp;
+        v.q_out[P] = a;
+        iter_dots(acc, pp, a, r_prev[m], m_prev[m]);
+      }
+    }
+    if (NS == 3) lds_barrier();
   }
-  double red[1] = {acc};
-  store_partials<1>(red, s_part);
+  store_partials<7>(acc, part);
 }
 
-// 2D: p = r/diag + beta p_old, q = A p, partial <p, q>.  A workgroup owns a
-// 256-cell row segment and marches it over 16 rows of z; each wave owns 64
-// consecutive cells.  The rows below and above a cell stay in registers and
-// x-neighbours come from the neighbouring lanes (the first and last lane of a
-// wave also load the cell just beyond the wave), so the kernel needs neither
-// LDS nor barriers.
+// 2D iteration kernel: a workgroup owns a 256-cell row segment and marches it
+// over 16 rows of z; each wave owns 64 consecutive cells.  The rows below and
+// above a cell stay in registers and x-neighbours come from the neighbouring
+// lanes (the first and last lane of a wave also load the cell just beyond the
+// wave), so the kernel needs neither LDS nor barriers.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv2(Geo G, Stencil<2, T> K, CgVectors<T> v,
-                                                     const T* __restrict__ p_old,
-                                                     T* __restrict__ p_new, int iter,
-                                                     const double* u_part, int nu,
-                                                     double* s_part, CgScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgIter<T> v,
+                                                     double* part, CgScalars* sc) {
   constexpr int TX = kTX2, KC = kKC2;
   static_assert(TX == kBlock, "one cell of the row segment per thread");
   if (load_done(sc)) return;
+  const T alpha = (T)sc->alpha, beta = (T)sc->beta;
+  const int fin = sc->fin;
   const int nx = G.nx, nz = G.nz;
   const int ntx = (nx + TX - 1) / TX;
   const int b = xcd_block();
@@ -374,56 +449,60 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv2(Geo G, Stencil<2, T> K, CgV
   const int lane = threadIdx.x & 63;
   const int i = tx * TX + threadIdx.x;
   const int k0 = tz * KC, k1 = min(k0 + KC, nz);
-  const T kx = K.k[0], kz = K.k[1];
   const bool in = i < nx;
+  if (fin) {  // the solve ended at the last scalar kernel: its x update only
+    if (in)
+      for (int k = k0; k < k1; ++k) {
+        const int P = i + nx * k;
+        v.x[P] += alpha * v.p_in[P];
+      }
+    return;
+  }
+  const T kx = K.k[0], kz = K.k[1];
   // the cell beyond the wave that an edge lane supplies (lane 0: left, lane 63: right)
   const int ie = lane == 0 ? i - 1 : (lane == 63 ? i + 1 : -1);
   const bool edge = ie >= 0 && ie < nx;
-  // raw values of row kk (z = r/diag, old direction, D), own cell and edge cell
+  // raw values of row kk (old residual, old A p, old direction, D, 1/diag),
+  // own cell and edge cell
   struct Raw {
-    T z, o, d, ze, oe, de;
+    T r, q, p, d, m, x, c, re, qe, pe, de, me;
   };
+  // unconditional loads from indices clamped into the mesh (values of cells
+  // or rows outside it are never used; a load under a branch would be
+  // waited for where the branches merge)
+  const int ic = in ? i : nx - 1, iec = edge ? ie : ic;
   auto fetch = [&](int kk) {
-    Raw w{T(0), T(0), T(0), T(0), T(0), T(0)};
-    if (kk >= 0 && kk < nz) {
-      if (in) {
-        const int Q = i + nx * kk;
-        w.z = v.r[Q] * v.dinv[Q];
-        w.o = p_old[Q];
-        w.d = v.D[Q];
-      }
-      if (edge) {
-        const int Q = ie + nx * kk;
-        w.ze = v.r[Q] * v.dinv[Q];
-        w.oe = p_old[Q];
-        w.de = v.D[Q];
-      }
-    }
-    return w;
+    const int kc = kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk);
+    const int Q = ic + nx * kc, Qe = iec + nx * kc;
+    return Raw{v.r_in[Q], v.q_in[Q], v.p_in[Q], v.D[Q], v.dinv[Q], v.x[Q], v.c[Q],
+               v.r_in[Qe], v.q_in[Qe], v.p_in[Qe], v.D[Qe], v.dinv[Qe]};
   };
-  // rows k0-1 .. k0+PD in flight while the previous kernel's partials are
-  // summed; afterwards row k+PD+1 is requested while row k is computed
-  constexpr int PD = 3;
+  // new residual and direction from raw values
+  auto rnew = [&](T r, T q) { return r - alpha * q; };
+  auto pnew = [&](T rn, T m, T po) { return rn * m + beta * po; };
+  // rows k0-1 .. k0+PD in flight while the scalars are read; afterwards row
+  // k+PD+1 is requested while row k is computed
+  constexpr int PD = sizeof(T) == 8 ? 2 : 3;
   Raw ring[PD + 1];
   const Raw wm = fetch(k0 - 1);
 #pragma unroll
   for (int w = 0; w <= PD; ++w) ring[w] = fetch(k0 + w);
-  double beta_d = 0.0;
-  if (spmv_prologue(u_part, nu, iter, sc, &beta_d)) return;
-  const T beta = (T)beta_d;
-  T pm = wm.z + beta * wm.o, dm = wm.d;
-  T pc = ring[0].z + beta * ring[0].o, dc = ring[0].d;
-  T pec = ring[0].ze + beta * ring[0].oe, dec = ring[0].de;
-  double acc = 0.0;
+  T pm = pnew(rnew(wm.r, wm.q), wm.m, wm.p), dm = wm.d;
+  Raw cur = ring[0];
+  T rc = rnew(cur.r, cur.q);
+  T pc = pnew(rc, cur.m, cur.p), dc = cur.d;
+  T pec = pnew(rnew(cur.re, cur.qe), cur.me, cur.pe), dec = cur.de;
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int it = 0; it < KC; ++it) {
     const int k = k0 + it;
     if (k >= k1) break;
-    const Raw& wn = ring[(it + 1) % (PD + 1)];
-    const T pn = wn.z + beta * wn.o, dn = wn.d;
-    const T pen = wn.ze + beta * wn.oe, den = wn.de;
+    const Raw wn = ring[(it + 1) % (PD + 1)];
+    const T rn = rnew(wn.r, wn.q);
+    const T pn = pnew(rn, wn.m, wn.p), dn = wn.d;
+    const T pen = pnew(rnew(wn.re, wn.qe), wn.me, wn.pe), den = wn.de;
     // slot of row k is free now: request row k+PD+1 into it
-    ring[it % (PD + 1)] = (k + PD + 1 <= k1) ? fetch(k + PD + 1) : Raw{T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (k + PD + 1 <= k1) ring[it % (PD + 1)] = fetch(k + PD + 1);
     T pl = __shfl_up(pc, 1, 64), pr = __shfl_down(pc, 1, 64);
     T dl = __shfl_up(dc, 1, 64), dr = __shfl_down(dc, 1, 64);
     if (lane == 0) {
@@ -436,14 +515,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv2(Geo G, Stencil<2, T> K, CgV
     }
     if (in) {
       const int P = i + nx * k;
-      T a = v.c[P] * pc;
+      T a = cur.c * pc;
       if (i + 1 < nx) a += T(0.5) * (dc + dr) * kx * (pc - pr);
       if (i > 0) a += T(0.5) * (dl + dc) * kx * (pc - pl);
       if (k + 1 < nz) a += T(0.5) * (dc + dn) * kz * (pc - pn);
       if (k > 0) a += T(0.5) * (dm + dc) * kz * (pc - pm);
-      p_new[P] = pc;
-      v.q[P] = a;
-      acc += (double)pc * (double)a;
+      v.p_out[P] = pc;
+      v.q_out[P] = a;
+      v.r_out[P] = rc;
+      v.x[P] = cur.x + alpha * cur.p;
+      iter_dots(acc, pc, a, rc, cur.m);
     }
     pm = pc;
     dm = dc;
@@ -451,42 +532,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv2(Geo G, Stencil<2, T> K, CgV
     dc = dn;
     pec = pen;
     dec = den;
+    rc = rn;
+    cur = wn;
   }
-  double red[1] = {acc};
-  store_partials<1>(red, s_part);
-}
-
-// alpha = <r,z>/<p,q> from the spmv partials; x += alpha p, r -= alpha q;
-// partials (<r, r/diag>, <r, r>)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(Geo G, CgVectors<T> v,
-                                                      const T* __restrict__ p_cur, int iter,
-                                                      const double* s_part, int ns,
-                                                      double* u_part, CgScalars* sc) {
-  if (load_done(sc)) return;
-  double pq[1];
-  sum_partials<1>(s_part, ns, pq);
-  const double alpha_d = sc->rzs[iter & 1] / pq[0];
-  if (!isfinite(alpha_d)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->status = -5;
-      sc->iter = iter;
-      __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha_d;
-  const T alpha = (T)alpha_d;
-  double red[2] = {0.0, 0.0};
-  GEA_FOR_CELLS(P, G) {
-    v.x[P] += alpha * p_cur[P];
-    const T r = v.r[P] - alpha * v.q[P];
-    v.r[P] = r;
-    const double rd = (double)r;
-    red[0] += rd * (double)(r * v.dinv[P]);
-    red[1] += rd * rd;
-  }
-  store_partials<2>(red, u_part);
+  store_partials<7>(acc, part);
 }
 
 template <int NDIM>
@@ -505,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_A(Geo G, Stencil<NDIM, double>
 // FP64 outer residual r = b - A x and its FP32 copy as the inner right-hand
 // side / initial inner residual (inner x = 0, inner p_old = 0).  Partials:
 // outer (||r||^2, ||b||^2) -> o_part; inner (<r32, r32/diag>, ||r32||^2) ->
-// i_part (the slot the inner solver's first spmv reads).
+// i_part (what the inner solve's set-up kernel reads).
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, double> K,
                                                        const double* __restrict__ c,
@@ -564,9 +613,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
   sc32->rz = in[0];
   sc32->rr = in[1];
   sc32->bb = in[1];
-  sc32->rzs[0] = in[0];
-  sc32->rzs[1] = in[0];
   sc32->alpha = 0.0;
+  sc32->beta = 0.0;
+  sc32->fin = 0;
   // inner tolerance: what the outer residual still needs (with a factor 0.1
   // for the FP32 solve's own error), never looser than 0.5 nor tighter than
   // the configured inner tolerance
@@ -613,16 +662,11 @@ Stencil<NDIM, T> stencil(const Geo& G) {
 
 }  // namespace
 
-int spmv_grid(const Geo& G) {
+int iter_grid(const Geo& G) {
   if (G.ndim == 3)
     return ((G.nx + kTX3 - 1) / kTX3) * ((G.ny + kTY3 - 1) / kTY3) * ((G.nz + kKC3 - 1) / kKC3);
   return ((G.nx + kTX2 - 1) / kTX2) * ((G.nz + kKC2 - 1) / kKC2);
 }
-
-// Partials in the slot iteration 0 reads were written by the set-up kernel
-// (the initial residual, one per workgroup of the column-tile grid); later
-// slots by the update kernel (one per workgroup of its grid-stride grid).
-int partials_for(const Geo& G, int iter) { return iter == 0 ? zplan(G).blocks : grid_for(G.nc); }
 
 template <typename T>
 void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w, double tol,
@@ -632,42 +676,42 @@ void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w
     hipLaunchKernelGGL((k_cg_init<2, T>), dim3(zp.blocks), dim3(kBlock), 0, s, G, stencil<2, T>(G), v, zp.kc, w.u[1], w.b);
   else
     hipLaunchKernelGGL((k_cg_init<3, T>), dim3(zp.blocks), dim3(kBlock), 0, s, G, stencil<3, T>(G), v, zp.kc, w.u[1], w.b);
-  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[1], zp.blocks,
-                     (const double*)w.b, 1, tol * tol, max_iter, 0, w.sc);
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[1], zp.blocks,
+                     (const double*)w.b, tol * tol, max_iter, w.sc);
+}
+
+// the vectors iteration `iter` reads and writes (by parity; the set-up
+// kernels leave the residual in r and a zero direction in p0).  Iteration 0
+// has no update to apply (alpha = 0, beta = 0): it reads r in place of the
+// old A p, so that only finite values enter r - 0 q and x + 0 p.
+template <typename T>
+CgIter<T> iter_vectors(const CgVectors<T>& v, int iter) {
+  const bool odd = iter & 1;
+  return CgIter<T>{v.x,
+                   odd ? v.r1 : v.r, odd ? v.r : v.r1,
+                   iter == 0 ? v.r : (odd ? v.q : v.q1), odd ? v.q1 : v.q,
+                   odd ? v.p1 : v.p0, odd ? v.p0 : v.p1,
+                   v.c, v.D, v.dinv};
 }
 
 template <typename T>
-void cg_spmv(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w) {
-  const T* p_old = (iter & 1) ? v.p1 : v.p0;
-  T* p_new = (iter & 1) ? v.p0 : v.p1;
-  const int gu = partials_for(G, iter);
-  const double* up = w.u[(iter + 1) & 1];
+void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w) {
+  const CgIter<T> it = iter_vectors(v, iter);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_cg_spmv2<T>, dim3(spmv_grid(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), v, p_old, p_new, iter, up, gu, w.s, w.sc);
+    hipLaunchKernelGGL(k_cg_iter2<T>, dim3(iter_grid(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), it, w.s, w.sc);
   else
-    hipLaunchKernelGGL(k_cg_spmv3<T>, dim3(spmv_grid(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), v, p_old, p_new, iter, up, gu, w.s, w.sc);
+    hipLaunchKernelGGL(k_cg_iter3<T>, dim3(iter_grid(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), it, w.s, w.sc);
 }
 
-template <typename T>
-void cg_update(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w) {
-  const T* p_cur = (iter & 1) ? v.p0 : v.p1;
-  hipLaunchKernelGGL(k_cg_update<T>, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, v, p_cur, iter,
-                     (const double*)w.s, spmv_grid(G), w.u[iter & 1], w.sc);
-}
-
-void cg_check(hipStream_t s, const Geo& G, int iter, const CgWork& w) {
-  // the residual after `iter` completed iterations sits in the partials of
-  // update iter-1, i.e. slot (iter + 1) & 1
-  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[(iter + 1) & 1],
-                     partials_for(G, iter), (const double*)nullptr, 0, 0.0, 0, iter, w.sc);
+void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w) {
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)w.s, iter_grid(G), iter, w.sc);
 }
 
 template void cg_init<double>(hipStream_t, const Geo&, const CgVectors<double>&, const CgWork&, double, int);
 template void cg_init<float>(hipStream_t, const Geo&, const CgVectors<float>&, const CgWork&, double, int);
-template void cg_spmv<double>(hipStream_t, const Geo&, const CgVectors<double>&, int, const CgWork&);
-template void cg_spmv<float>(hipStream_t, const Geo&, const CgVectors<float>&, int, const CgWork&);
-template void cg_update<double>(hipStream_t, const Geo&, const CgVectors<double>&, int, const CgWork&);
-template void cg_update<float>(hipStream_t, const Geo&, const CgVectors<float>&, int, const CgWork&);
+template void cg_iter_kernel<double>(hipStream_t, const Geo&, const CgVectors<double>&, int, const CgWork&);
+template void cg_iter_kernel<float>(hipStream_t, const Geo&, const CgVectors<float>&, int, const CgWork&);
+
 
 void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,
                     const double* x, double* y) {

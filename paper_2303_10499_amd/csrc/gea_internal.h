@@ -36,21 +36,21 @@ struct Vec {
   T* p[NDIM];
 };
 
-// Device-resident solver scalars.  Written by workgroup 0 of the solver
-// kernels (and by the one-workgroup check kernels), read by later kernels on
-// the stream and by the host.
+// Device-resident solver scalars.  Written by the one-workgroup set-up and
+// scalar kernels, read by later kernels on the stream and by the host.
 struct CgScalars {
   double rz;        // <r, z> of the current iterate
   double rr;        // ||r||^2
   double bb;        // ||b||^2 (of the system being solved)
-  double alpha;
-  double rzs[2];    // <r, z> of iterations of even / odd index
+  double alpha;     // step length of the update the next iteration kernel applies
+  double beta;      // its direction coefficient
   double tol2;      // tol^2
   double aux[6];    // reduction results of the step kernels
   int iter;         // completed iterations
   int max_iter;
   int done;         // 1 once converged or failed
   int status;       // 0 ok, -4 no convergence, -5 non-finite
+  int fin;          // 1: the next iteration kernel applies the last x update only
 };
 
 // Number of workgroups of the grid-stride kernels: a fixed multiple of the
@@ -102,19 +102,36 @@ void launch_init_fields(hipStream_t s, const Geo& G, const Phys& ph, int kind, d
 template <typename T>
 struct CgVectors {
   T* x;
-  T* r;
-  T* p0;   // direction, double buffered (the fused kernel reads the old
-  T* p1;   // direction with halo while writing the new one)
-  T* q;    // A p
+  T* r;    // residual and A p, double buffered by iteration parity (r, r1;
+  T* r1;   // q, q1): the iteration kernel reads the old values with halo
+  T* p0;   // while writing the new ones; so is the direction (p0, p1)
+  T* p1;
+  T* q;
+  T* q1;
   const T* c;
   const T* D;
   const T* dinv;
   const T* b;
 };
 
-// Per-workgroup partial sums of one CG instance: s (spmv, 1 value per
-// workgroup), u[2] (update, 2 values per workgroup, by iteration parity; u[1]
-// also receives the initial residual), b (||b||^2 at init).
+// The vectors one iteration kernel reads (_in) and writes (_out).
+template <typename T>
+struct CgIter {
+  T* x;
+  const T* r_in;
+  T* r_out;
+  const T* q_in;
+  T* q_out;
+  const T* p_in;
+  T* p_out;
+  const T* c;
+  const T* D;
+  const T* dinv;
+};
+
+// Per-workgroup partial sums of one CG instance: s (iteration kernel, 7
+// values per workgroup), u[1] (the set-up kernel's <r, z>, ||r||^2; u[0] is
+// unused), b (||b||^2 at set-up).
 struct CgWork {
   double* s;
   double* u[2];
@@ -122,15 +139,15 @@ struct CgWork {
   CgScalars* sc;
 };
 
-int spmv_grid(const Geo& G);
+int iter_grid(const Geo& G);  // workgroups of the CG iteration kernel
 template <typename T>
 void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w, double tol,
              int max_iter);
+// iteration `iter` of a solve set up by cg_init / launch_residual64: the
+// stencil kernel, then the one-workgroup scalar kernel
 template <typename T>
-void cg_spmv(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w);
-template <typename T>
-void cg_update(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w);
-void cg_check(hipStream_t s, const Geo& G, int iter, const CgWork& w);
+void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w);
+void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w);
 void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,
                     const double* x, double* y);
 

@@ -53,6 +53,17 @@ struct Reducer {
 
 };
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() is also a
+// release fence for global memory, which waits for every global load and
+// store in flight -- including the next plane's loads issued just before it.
+// For kernels in which no thread reads, across the barrier, what another
+// thread of the workgroup wrote to global memory.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // 2D/3D cell coordinates: c[0] = i, then (j,) k.
 template <int NDIM>
 __device__ __forceinline__ void cell_coords(const Geo& G, int P, int* c) {

@@ -490,10 +490,12 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   return (gea_status)out->status;
 }
 
-// One inner solve by flexible CG with the network as preconditioner on the
-// FP32 correction system set up by the refinement residual (r32, c32, D32).
-// Returns the iterations done; *stalled is set when the stall test fired.
-int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps, bool* stalled) {
+// Flexible CG with the network as preconditioner on the FP32 correction
+// system set up by the refinement residual (r32, c32, D32), at most `steps`
+// iterations.  Returns the iterations done; *stalled is set when the stall
+// test fired, *converged when the inner tolerance was reached.
+int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps, bool* stalled,
+                  bool* converged) {
   const Geo& G = x->G;
   FcgVectors& v = x->fv;
   v.d = x->d32;
@@ -529,6 +531,7 @@ int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps
     x->timer.flush();
   }
   *stalled = hf.status == 1;
+  *converged = hf.done && hf.status == 0;
   return it;
 }
 
@@ -578,17 +581,26 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
     }
     read_scalars(x, x->sc32, &h32);
     int done_iters = 0;
+    bool pcg = true;  // the inner solve (still) needs Jacobi-PCG
     if (use_net) {
-      bool stalled = false;
+      bool stalled = false, converged = false;
       // same adaptive inner tolerance as the refinement residual kernel sets
       const double need = 0.1 * std::sqrt(x->prm.tol * x->prm.tol * h64.bb / h64.rr);
       const double itol = std::max(x->prm.inner_tol, std::min(0.5, need));
       done_iters = learned_inner(x, h32.bb, itol, budget > 0 ? budget : 1, x->prm.learned_steps,
-                                 &stalled);
+                                 &stalled, &converged);
       // after learned_steps network iterations (or a stall) Jacobi-PCG continues
+      // the same inner solve from its current iterate and residual
       use_net = false;
       if (stalled) ++fallbacks;
-    } else {
+      pcg = !converged && done_iters < budget;
+      if (pcg) {
+        const int left = budget - done_iters;
+        x->timer.run(4, x->stream, [&] { cg_resume(x->stream, G, v, w, left); });
+        read_scalars(x, x->sc32, &h32);
+      }
+    }
+    if (pcg) {
       const int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
       gea_status rc = run_cg(
           x, x->sc32, h32, budget, first,
@@ -597,7 +609,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
             x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
           });
       if (rc != GEA_OK) return rc;
-      done_iters = h32.iter;
+      done_iters += h32.iter;
       if (h32.status == -5) {
         out->status = GEA_ERR_NAN;
         break;

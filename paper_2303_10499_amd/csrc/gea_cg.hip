@@ -633,6 +633,44 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Jacobi-PCG resumed on an inner system from its current iterate (after the
+// learned form's flexible-CG steps): zero direction, and partials
+// <r, r/diag>, ||r||^2 of the current residual
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_resume(int n, const T* __restrict__ r,
+                                                      const T* __restrict__ dinv,
+                                                      T* __restrict__ p0, double* part) {
+  double v[2] = {0.0, 0.0};
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
+    const T rv = r[P];
+    p0[P] = T(0);
+    const double rd = (double)rv;
+    v[0] += rd * (double)(rv * dinv[P]);
+    v[1] += rd * rd;
+  }
+  store_partials<2>(v, part);
+}
+
+// one workgroup: scalars of the resumed solve (its ||b||^2 and tolerance are
+// those the set-up kernel gave the inner system; max_iter iterations remain)
+__global__ __launch_bounds__(kBlock) void k_cg_resume_start(const double* part, int n, int max_iter,
+                                                            CgScalars* sc) {
+  double s[2];
+  sum_partials<2>(part, n, s);
+  if (threadIdx.x != 0) return;
+  sc->rz = s[0];
+  sc->rr = s[1];
+  sc->alpha = 0.0;
+  sc->beta = 0.0;
+  sc->fin = 0;
+  sc->iter = 0;
+  sc->max_iter = max_iter;
+  const bool finite = isfinite(s[0]) && isfinite(s[1]);
+  sc->status = finite ? 0 : -5;
+  const int done = (!finite || s[1] <= sc->tol2 * sc->bb || sc->max_iter <= 0) ? 1 : 0;
+  __hip_atomic_store(&sc->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(kBlock) void k_cast_coeffs(int n, const double* c, const double* D,
                                                         const double* dinv, float* c32, float* D32,
                                                         float* dinv32) {
@@ -736,6 +774,14 @@ void launch_residual64(hipStream_t s, const Geo& G, const double* c, const doubl
   hipLaunchKernelGGL(k_residual_check, dim3(1), block, 0, s, (const double*)o_part,
                      (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, inner_max,
                      sc64, w32.sc);
+}
+
+void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter) {
+  const int gu = zplan(G).blocks;  // the set-up partial buffer holds 2 values per block of this grid
+  hipLaunchKernelGGL(k_cg_resume<float>, dim3(gu), dim3(kBlock), 0, s, G.nc, (const float*)v.r, v.dinv,
+                     v.p0, w.u[1]);
+  hipLaunchKernelGGL(k_cg_resume_start, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[1], gu, max_iter,
+                     w.sc);
 }
 
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,

@@ -148,6 +148,10 @@ void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w
 template <typename T>
 void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w);
 void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w);
+// Jacobi-PCG resumed on the FP32 inner system from its current iterate and
+// residual (v.x, v.r), keeping the set-up's ||b||^2 and tolerance; then
+// cg_iter_kernel / cg_scalars from iteration 0
+void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter);
 void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,
                     const double* x, double* y);
 

@@ -95,6 +95,75 @@ __device__ __forceinline__ double phit_val(double D_lo, double D_hi, double H_lo
   return Df * S * (Hf + phif * (r_hi - r_lo) * inv_h);
 }
 
+// Plane staging of the 3D kernels: the workgroup's 64x4 column tile with a
+// halo of HW cells along x and y (HW = 2: 68x8 = 544 cells a plane, for the
+// fourth-order interpolation; HW = 1: 66x6 = 396).  Thread t stages its own
+// cell (slot 0) and halo cells t, 256 + t, ... (slots 1, 2, ...): the HW rows
+// below the tile, the HW rows above it, then the side columns.  Indices are
+// clamped into the mesh, so every staging load is unconditional and in
+// bounds; a staged value of a cell outside the mesh is only ever read into a
+// term that a wall test discards.
+template <int HW_>
+struct Stage3 {
+  static constexpr int TX = ZTile<3>::TX, TY = ZTile<3>::TY, HW = HW_;
+  static constexpr int HX = TX + 2 * HW, HY = TY + 2 * HW, HP = HX * HY;
+  static constexpr int NH = HP - TX * TY;                 // halo cells
+  static constexpr int NU = 1 + (NH + kBlock - 1) / kBlock;  // slots a thread
+  static_assert(TX * TY == kBlock, "one own cell a thread");
+  int q[NU];     // cell index in plane 0 (clamped into the mesh)
+  int h[NU];     // index in the staged plane
+  bool has[NU];  // the thread stages a cell in this slot
+  int qo;        // the thread's own column, clamped into the mesh
+  int ho;        // its cell in the staged plane
+};
+
+__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+template <int HW>
+__device__ __forceinline__ Stage3<HW> stage3(const Geo& G, const Col& c) {
+  using S = Stage3<HW>;
+  S st;
+  const int lx = (int)threadIdx.x % S::TX, ly = (int)threadIdx.x / S::TX;
+  const int i0 = c.i - lx, j0 = c.j - ly;
+  st.ho = (lx + HW) + S::HX * (ly + HW);
+  st.qo = clampi(c.i, G.nx) + G.nx * clampi(c.j, G.ny);
+  st.q[0] = st.qo;
+  st.h[0] = st.ho;
+  st.has[0] = true;
+#pragma unroll
+  for (int m = 1; m < S::NU; ++m) {
+    int e = (int)threadIdx.x + (m - 1) * kBlock;
+    st.has[m] = e < S::NH;
+    if (!st.has[m]) {  // no cell in this slot: load the own cell again, write nothing
+      st.q[m] = st.qo;
+      st.h[m] = st.ho;
+      continue;
+    }
+    int hx, hy;
+    if (e < HW * S::HX) {
+      hy = e / S::HX;
+      hx = e % S::HX;
+    } else if (e < 2 * HW * S::HX) {
+      e -= HW * S::HX;
+      hy = S::TY + HW + e / S::HX;
+      hx = e % S::HX;
+    } else {
+      e -= 2 * HW * S::HX;
+      hy = HW + e / (2 * HW);
+      const int s = e % (2 * HW);
+      hx = s < HW ? s : S::HX - 2 * HW + s;
+    }
+    st.h[m] = hx + S::HX * hy;
+    st.q[m] = clampi(i0 + hx - HW, G.nx) + G.nx * clampi(j0 + hy - HW, G.ny);
+  }
+  return st;
+}
+
+// the five staged values of a line through the own cell, stride 1 (x) or HX (y)
+__device__ __forceinline__ Line line_lds(const double* s, int h, int str) {
+  return Line{s[h - 2 * str], s[h - str], s[h], s[h + str], s[h + 2 * str]};
+}
+
 
 // ---- Step 1 ----------------------------------------------------------------
 
@@ -151,6 +220,88 @@ __global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) kin += uc[d] * uc[d];
     e0[P] = ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, k);
+    z = shift(z, k + 3 < nz ? znext : 0.0);
+  }
+}
+
+// k_mass_flux on a 3D mesh with the x/y neighbourhoods of rho u_x and rho u_y
+// staged in LDS and the next plane's loads in flight while a plane is
+// computed.  Same formulas and order as k_mass_flux.
+__global__ __launch_bounds__(kBlock) void k_mass_flux3(Geo G, Phys ph, int kc,
+                                                       const double* __restrict__ rho, Vec<3> u,
+                                                       const double* __restrict__ T, Vec<3> phi,
+                                                       double* __restrict__ rho_star,
+                                                       double* __restrict__ e0) {
+  using St = Stage3<2>;
+  constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
+  __shared__ double sm[2][2][HP];  // rho u_x, rho u_y
+  const Col c = col_of<3>(G, kc);
+  const St st = stage3<2>(G, c);
+  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
+  const double* uz = u.p[Z];
+  auto mz = [&](int Q) { return rho[Q] * uz[Q]; };
+  // raw values of the plane in flight
+  double fs[2][NU], fr, fT, fu[3], fzn;
+  auto fetch = [&](int kk) {
+    const int o = pl * kk, P = qo + o;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int Q = st.q[m] + o;
+      const double rq = rho[Q];
+      fs[0][m] = rq * u.p[0][Q];
+      fs[1][m] = rq * u.p[1][Q];
+    }
+    fr = rho[P];
+    fT = T[P];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fu[d] = u.p[d][P];
+    fzn = mz(nb(kk + 3 < nz, P + 3 * pl, P));
+  };
+  Line z;
+  double flo;
+  {
+    const int P = qo + pl * c.k0;
+    z = line_at(mz, P, pl, c.k0, nz);
+    flo = c.k0 > 0 ? i4_lo(z, c.k0, nz) * G.S[Z] : 0.0;
+  }
+  fetch(c.k0);
+  for (int k = c.k0; k < c.k1; ++k) {
+    const int sl = k & 1;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int m = 0; m < NU; ++m)
+        if (st.has[m]) sm[sl][f][st.h[m]] = fs[f][m];
+    const double r = fr, Tc = fT, znext = fzn;
+    const double uc[3] = {fu[0], fu[1], fu[2]};
+    fetch(k + 1 < c.k1 ? k + 1 : k);
+    lds_barrier();
+    double sum = 0.0, hid[2];
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const Line s = line_lds(sm[sl][d], ho, d == 0 ? 1 : HX);
+      const int n = G.n[d], q = coord(c, d);
+      const double hi = q + 1 < n ? i4_hi(s, q, n) * G.S[d] : 0.0;
+      const double lo = q > 0 ? i4_lo(s, q, n) * G.S[d] : 0.0;
+      hid[d] = hi;
+      sum += hi;
+      sum -= lo;
+    }
+    const double hi = k + 1 < nz ? i4_hi(z, k, nz) * G.S[Z] : 0.0;
+    sum += hi;
+    sum -= flo;
+    flo = hi;
+    double kin = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) kin += uc[d] * uc[d];
+    if (c.act) {
+      const int P = qo + pl * k;
+#pragma unroll
+      for (int d = 0; d < Z; ++d) phi.p[d][P] = hid[d];
+      phi.p[Z][P] = hi;
+      rho_star[P] = r - ph.dt / G.V * sum;
+      e0[P] = ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, k);
+    }
     z = shift(z, k + 3 < nz ? znext : 0.0);
   }
 }
@@ -256,6 +407,130 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
   }
 }
 
+// k_mom_predict on a 3D mesh with the x/y neighbourhoods of u, p' and rho
+// staged in LDS and the next plane's loads in flight while a plane is
+// computed.  Same formulas and order as k_mom_predict.
+__global__ __launch_bounds__(kBlock) void k_mom_predict3(Geo G, Phys ph, int kc,
+                                                         const double* __restrict__ rho, Vec<3> u,
+                                                         const double* __restrict__ pp,
+                                                         const double* __restrict__ rho_star,
+                                                         Vec<3> phi, Vec<3> u_star) {
+  using St = Stage3<2>;
+  constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
+  __shared__ double su[2][5][HP];  // u (3 components), p', rho
+  const Col c = col_of<3>(G, kc);
+  const St st = stage3<2>(G, c);
+  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
+  const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
+  const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
+  // raw values of the plane in flight
+  double fs[5][NU], frs, fz, fh[2], fl[2], fpu, fru, fzn[3];
+  auto fetch = [&](int kk) {
+    const int o = pl * kk, P = qo + o;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int Q = st.q[m] + o;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) fs[cc][m] = u.p[cc][Q];
+      fs[3][m] = pp[Q];
+      fs[4][m] = rho[Q];
+    }
+    frs = rho_star[P];
+    fz = phi.p[Z][P];
+    fh[0] = phi.p[0][P];
+    fh[1] = phi.p[1][P];
+    fl[0] = phi.p[0][Pxl + o];
+    fl[1] = phi.p[1][Pyl + o];
+    const int Pu = nb(kk + 1 < nz, P + pl, P), Pn = nb(kk + 3 < nz, P + 3 * pl, P);
+    fpu = pp[Pu];
+    fru = rho[Pu];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) fzn[cc] = u.p[cc][Pn];
+  };
+  Line z[3];
+  double flo[3];
+  double Flo = 0.0;
+  {
+    const int P = qo + pl * c.k0;
+    const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const double* uc = u.p[cc];
+      z[cc] = line_at([&](int Q) { return uc[Q]; }, P, pl, c.k0, nz);
+      flo[cc] = c.k0 > 0 ? phz_lo * i4_lo(z[cc], c.k0, nz) : 0.0;
+    }
+    if (c.k0 > 0)
+      Flo = force_val(pp[P - pl], pp[P], rho[P - pl], rho[P],
+                      phi_face<3>(G, ph, Z, c.k0 - 1, c.k0 - 1), G.inv_h[Z]);
+  }
+  fetch(c.k0);
+  const double kvz = ph.mu * G.S[Z] / G.h[Z];
+  for (int k = c.k0; k < c.k1; ++k) {
+    const int sl = k & 1;
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+      for (int m = 0; m < NU; ++m)
+        if (st.has[m]) su[sl][f][st.h[m]] = fs[f][m];
+    const double rs = frs, phz = fz, p_up = fpu, r_up = fru;
+    const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
+    double zn[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) zn[cc] = fzn[cc];
+    fetch(k + 1 < c.k1 ? k + 1 : k);
+    lds_barrier();
+    const bool up = k + 1 < nz;
+    const double* Sp = su[sl][3];
+    const double* Sr = su[sl][4];
+    const double r = Sr[ho], pc = Sp[ho];
+    const double Fhi = up ? force_val(pc, p_up, r, r_up, phi_face<3>(G, ph, Z, k, k), G.inv_h[Z]) : 0.0;
+    const double inv_rs = 1.0 / rs;
+    double us[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const Line s[2] = {line_lds(su[sl][cc], ho, 1), line_lds(su[sl][cc], ho, HX)};
+      double conv = 0.0, visc = 0.0;
+#pragma unroll
+      for (int d = 0; d < Z; ++d) {
+        const int n = G.n[d], q = coord(c, d);
+        conv = q + 1 < n ? conv + fhi[d] * i4_hi(s[d], q, n) : conv;
+        conv = q > 0 ? conv - flod[d] * i4_lo(s[d], q, n) : conv;
+      }
+      double fhz = 0.0;
+      if (up) {
+        fhz = phz * i4_hi(z[cc], k, nz);
+        conv += fhz;
+      }
+      if (k > 0) conv -= flo[cc];
+      flo[cc] = fhz;
+#pragma unroll
+      for (int d = 0; d < Z; ++d)
+        visc_add(visc, s[d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
+      visc_add(visc, z[cc], k, nz, kvz, cc == Z);
+      double RF;
+      if (cc == Z) {
+        RF = 0.5 * (Flo + Fhi);
+      } else {
+        const int n = G.n[cc], q = coord(c, cc), sd = cc == 0 ? 1 : HX;
+        const double phf = phi_cell(G, ph, k);
+        const double hi = q + 1 < n ? force_val(pc, Sp[ho + sd], r, Sr[ho + sd], phf, G.inv_h[cc]) : 0.0;
+        const double lo = q > 0 ? force_val(Sp[ho - sd], pc, Sr[ho - sd], r, phf, G.inv_h[cc]) : 0.0;
+        RF = 0.5 * (lo + hi);
+      }
+      const double mom = r * z[cc].c - ph.dt / G.V * (conv - visc) - ph.dt * RF;
+      us[cc] = mom * inv_rs;
+    }
+    if (c.act) {
+      const int P = qo + pl * k;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) u_star.p[cc][P] = us[cc];
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
+    Flo = Fhi;
+  }
+}
+
 // ---- Step 2 ----------------------------------------------------------------
 
 // One Picard sweep of the total-energy equation with frozen flux phi:
@@ -352,6 +627,133 @@ __global__ __launch_bounds__(kBlock) void k_energy_sweep(
   }
 }
 
+// k_energy_sweep on a 3D mesh with the x/y neighbourhoods of e and T staged
+// in LDS and the next plane's loads in flight while a plane is computed.
+// Same formulas and order as k_energy_sweep.
+__global__ __launch_bounds__(kBlock) void k_energy_sweep3(
+    Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
+    const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<3> phi,
+    const double* __restrict__ rho_star, Vec<3> u_star, const double* __restrict__ Tbg,
+    double* __restrict__ e_next, double* __restrict__ T_next, int last,
+    const double* __restrict__ p, double* __restrict__ rho23, double* __restrict__ psi,
+    double* __restrict__ cc, double* __restrict__ D) {
+  using St = Stage3<2>;
+  constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
+  __shared__ double su[2][2][HP];  // e, T
+  const Col c = col_of<3>(G, kc);
+  const St st = stage3<2>(G, c);
+  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
+  const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
+  const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
+  // raw values of the plane in flight
+  double fs[2][NU], fh[2], fl[2], fz, frs, fr, fe0, fus[3], fen, fTn, fp;
+  auto fetch = [&](int kk) {
+    const int o = pl * kk, P = qo + o;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      fs[0][m] = e_prev[st.q[m] + o];
+      fs[1][m] = T_prev[st.q[m] + o];
+    }
+    fh[0] = phi.p[0][P];
+    fh[1] = phi.p[1][P];
+    fl[0] = phi.p[0][Pxl + o];
+    fl[1] = phi.p[1][Pyl + o];
+    fz = phi.p[Z][P];
+    frs = rho_star[P];
+    fr = rho[P];
+    fe0 = e0[P];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fus[d] = u_star.p[d][P];
+    const int Pn = nb(kk + 3 < nz, P + 3 * pl, P);
+    fen = e_prev[Pn];
+    fTn = T_prev[Pn];
+    fp = p[P];  // read on every sweep (p is a valid field), used on the last
+  };
+  auto hhat = [&](const Line& e, const Line& T) {
+    return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
+                e.p2 + ph.R * T.p2};
+  };
+  Line ze, zT;
+  double flo;
+  {
+    const int P = qo + pl * c.k0;
+    ze = line_at([&](int Q) { return e_prev[Q]; }, P, pl, c.k0, nz);
+    zT = line_at([&](int Q) { return T_prev[Q]; }, P, pl, c.k0, nz);
+    flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hhat(ze, zT), c.k0, nz) : 0.0;
+  }
+  fetch(c.k0);
+  const double kdz = ph.mu / ph.Pr * ph.cp * G.S[Z] / G.h[Z];
+  for (int k = c.k0; k < c.k1; ++k) {
+    const int sl = k & 1;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int m = 0; m < NU; ++m)
+        if (st.has[m]) su[sl][f][st.h[m]] = fs[f][m];
+    const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
+    const double phz = fz, rs = frs, r = fr, e0c = fe0, e_n = fen, T_n = fTn, pc = fp;
+    const double us[3] = {fus[0], fus[1], fus[2]};
+    const double tb = Tbg[k], tb_up = Tbg[k + 1 < nz ? k + 1 : k], tb_dn = Tbg[k > 0 ? k - 1 : k];
+    fetch(k + 1 < c.k1 ? k + 1 : k);
+    lds_barrier();
+    Line le[2], lT[2];
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      le[d] = line_lds(su[sl][0], ho, d == 0 ? 1 : HX);
+      lT[d] = line_lds(su[sl][1], ho, d == 0 ? 1 : HX);
+    }
+    double conv = 0.0;
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int n = G.n[d], q = coord(c, d);
+      const Line h = hhat(le[d], lT[d]);
+      conv = q + 1 < n ? conv + fhi[d] * i4_hi(h, q, n) : conv;
+      conv = q > 0 ? conv - flod[d] * i4_lo(h, q, n) : conv;
+    }
+    double fhz = 0.0;
+    if (k + 1 < nz) {
+      fhz = phz * i4_hi(hhat(ze, zT), k, nz);
+      conv += fhz;
+    }
+    if (k > 0) conv -= flo;
+    flo = fhz;
+    const double Tp = zT.c - tb;
+    double diff = 0.0;
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int n = G.n[d], q = coord(c, d);
+      const double kd = ph.mu / ph.Pr * ph.cp * G.S[d] / G.h[d];
+      diff = q + 1 < n ? diff + kd * ((lT[d].p1 - tb) - Tp) : diff;
+      diff = q > 0 ? diff + kd * ((lT[d].m1 - tb) - Tp) : diff;
+    }
+    if (k + 1 < nz) diff += kdz * ((zT.p1 - tb_up) - Tp);
+    if (k > 0) diff += kdz * ((zT.m1 - tb_dn) - Tp);
+    const double inv_rs = 1.0 / rs;
+    const double rhoe = r * e0c - ph.dt * G.inv_V * conv + ph.dt * G.inv_V * diff;
+    const double e = rhoe * inv_rs;
+    double kin = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) kin += us[d] * us[d];
+    const double T = (e - 0.5 * kin - phi_cell(G, ph, k)) * ph.inv_cv;
+    if (c.act) {
+      const int P = qo + pl * k;
+      e_next[P] = e;
+      T_next[P] = T;
+      if (last) {
+        const double ps = 1.0 / (ph.R * T);
+        const double r23 = pc * ps;
+        rho23[P] = r23;
+        psi[P] = ps;
+        cc[P] = ps * G.V * ph.inv_dt;
+        D[P] = r23 * ph.dt * inv_rs;
+      }
+    }
+    const bool more = k + 3 < nz;
+    ze = shift(ze, more ? e_n : 0.0);
+    zT = shift(zT, more ? T_n : 0.0);
+  }
+}
+
 // ---- Step 3 ----------------------------------------------------------------
 
 // H(u) = rho^n u^n/dt - (1/V) sum_out phi I4(u) + (1/V) sum mu snGrad(u) S
@@ -425,6 +827,106 @@ __global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
       H.p[cc][P] = h[cc];
       z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
     }
+  }
+}
+
+// k_H on a 3D mesh with the x/y neighbourhoods of u_prev staged in LDS: the
+// next plane's loads are in flight while a plane is computed from LDS and
+// registers.  Same formulas and order as k_H.  (168 VGPRs: 3 waves a SIMD.)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_H3(Geo G, Phys ph, int kc,
+                                               const double* __restrict__ rho, Vec<3> u,
+                                               Vec<3> u_prev, Vec<3> phi, Vec<3> H) {
+  using St = Stage3<2>;
+  constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
+  __shared__ double su[2][3][HP];
+  const Col c = col_of<3>(G, kc);
+  const St st = stage3<2>(G, c);
+  const int nz = G.n[Z], pl = c.pl, qo = st.qo;
+  const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
+  const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
+  // raw values of the plane in flight
+  double fu[3][NU], fr, fz, fh[2], fl[2], fun[3], fzn[3];
+  auto fetch = [&](int kk) {
+    const int o = pl * kk, P = qo + o;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int m = 0; m < NU; ++m) fu[cc][m] = u_prev.p[cc][st.q[m] + o];
+    fr = rho[P];
+    fz = phi.p[Z][P];
+    fh[0] = phi.p[0][P];
+    fh[1] = phi.p[1][P];
+    fl[0] = phi.p[0][Pxl + o];
+    fl[1] = phi.p[1][Pyl + o];
+    const int Pn = nb(kk + 3 < nz, P + 3 * pl, P);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      fun[cc] = u.p[cc][P];
+      fzn[cc] = u_prev.p[cc][Pn];
+    }
+  };
+  Line z[3];
+  double flo[3];
+  {
+    const int P = qo + pl * c.k0;
+    const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const double* uc = u_prev.p[cc];
+      z[cc] = line_at([&](int Q) { return uc[Q]; }, P, pl, c.k0, nz);
+      flo[cc] = c.k0 > 0 ? phz_lo * i4_lo(z[cc], c.k0, nz) : 0.0;
+    }
+  }
+  fetch(c.k0);
+  const double kvz = ph.mu * G.S[Z] / G.h[Z];
+  for (int k = c.k0; k < c.k1; ++k) {
+    const int sl = k & 1;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int m = 0; m < NU; ++m)
+        if (st.has[m]) su[sl][cc][st.h[m]] = fu[cc][m];
+    const double r = fr, phz = fz;
+    const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
+    double un[3], zn[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      un[cc] = fun[cc];
+      zn[cc] = fzn[cc];
+    }
+    fetch(k + 1 < c.k1 ? k + 1 : k);
+    lds_barrier();
+    double h[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const Line s[2] = {line_lds(su[sl][cc], st.ho, 1), line_lds(su[sl][cc], st.ho, HX)};
+      double conv = 0.0, visc = 0.0;
+#pragma unroll
+      for (int d = 0; d < Z; ++d) {
+        const int n = G.n[d], q = coord(c, d);
+        conv = q + 1 < n ? conv + fhi[d] * i4_hi(s[d], q, n) : conv;
+        conv = q > 0 ? conv - flod[d] * i4_lo(s[d], q, n) : conv;
+      }
+      double fhz = 0.0;
+      if (k + 1 < nz) {
+        fhz = phz * i4_hi(z[cc], k, nz);
+        conv += fhz;
+      }
+      if (k > 0) conv -= flo[cc];
+      flo[cc] = fhz;
+#pragma unroll
+      for (int d = 0; d < Z; ++d)
+        visc_add(visc, s[d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
+      visc_add(visc, z[cc], k, nz, kvz, cc == Z);
+      h[cc] = r * un[cc] * ph.inv_dt - conv * G.inv_V + visc * G.inv_V;
+    }
+    if (c.act) {
+      const int P = qo + pl * k;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) H.p[cc][P] = h[cc];
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
   }
 }
 
@@ -503,6 +1005,106 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
     diag_lo = diag_hi;
     b[P] = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
     dinv[P] = 1.0 / diag;
+  }
+}
+
+// k_rhs on a 3D mesh with the x/y neighbours of D, rho23, H_x and H_y staged
+// in LDS and the next plane's loads in flight while a plane is computed.
+// Same formulas and order as k_rhs.
+__global__ __launch_bounds__(kBlock) void k_rhs3(Geo G, Phys ph, int kc,
+                                                 const double* __restrict__ rho,
+                                                 const double* __restrict__ rho23,
+                                                 const double* __restrict__ psi,
+                                                 const double* __restrict__ cc,
+                                                 const double* __restrict__ D, Vec<3> H,
+                                                 double* __restrict__ b, double* __restrict__ dinv) {
+  using St = Stage3<1>;
+  constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
+  __shared__ double ss[2][4][HP];  // D, rho23, H_x, H_y
+  const Col c = col_of<3>(G, kc);
+  const St st = stage3<1>(G, c);
+  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
+  const double kz_ = G.S[Z] / G.h[Z];
+  // raw values of the plane in flight
+  double fs[4][NU], fc, fr, fps, fDu, fHz, fHzu, fru;
+  auto fetch = [&](int kk) {
+    const int o = pl * kk, P = qo + o;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int Q = st.q[m] + o;
+      fs[0][m] = D[Q];
+      fs[1][m] = rho23[Q];
+      fs[2][m] = H.p[0][Q];
+      fs[3][m] = H.p[1][Q];
+    }
+    fc = cc[P];
+    fr = rho[P];
+    fps = psi[P];
+    const int Pu = nb(kk + 1 < nz, P + pl, P);
+    fDu = D[Pu];
+    fHz = H.p[Z][P];
+    fHzu = H.p[Z][Pu];
+    fru = rho23[Pu];
+  };
+  double flux_lo = 0.0, diag_lo = 0.0;
+  if (c.k0 > 0) {
+    const int P = qo + pl * c.k0, Q = P - pl;
+    flux_lo = phit_val(D[Q], D[P], H.p[Z][Q], H.p[Z][P], rho23[Q], rho23[P], G.S[Z],
+                       phi_face<3>(G, ph, Z, c.k0 - 1, c.k0 - 1), G.inv_h[Z]);
+    diag_lo = 0.5 * (D[Q] + D[P]) * kz_;
+  }
+  fetch(c.k0);
+  for (int k = c.k0; k < c.k1; ++k) {
+    const int sl = k & 1;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int m = 0; m < NU; ++m)
+        if (st.has[m]) ss[sl][f][st.h[m]] = fs[f][m];
+    const double cP = fc, rP = fr, psP = fps, D_up = fDu, Hz = fHz, Hz_up = fHzu, r23_up = fru;
+    fetch(k + 1 < c.k1 ? k + 1 : k);
+    lds_barrier();
+    const bool up = k + 1 < nz;
+    const double* SD = ss[sl][0];
+    const double* Sr = ss[sl][1];
+    const double Dc = SD[ho], r23 = Sr[ho];
+    double sum = 0.0;
+    double diag = cP;
+    const double phc = phi_cell(G, ph, k);
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int q = coord(c, d), sd = d == 0 ? 1 : HX;
+      const double* SH = ss[sl][2 + d];
+      const double kd = G.S[d] / G.h[d];
+      const double Hc = SH[ho];
+      if (q + 1 < G.n[d]) {
+        sum += phit_val(Dc, SD[ho + sd], Hc, SH[ho + sd], r23, Sr[ho + sd], G.S[d], phc, G.inv_h[d]);
+        diag += 0.5 * (Dc + SD[ho + sd]) * kd;
+      }
+      if (q > 0) {
+        sum -= phit_val(SD[ho - sd], Dc, SH[ho - sd], Hc, Sr[ho - sd], r23, G.S[d], phc, G.inv_h[d]);
+        diag += 0.5 * (SD[ho - sd] + Dc) * kd;
+      }
+    }
+    double flux_hi = 0.0, diag_hi = 0.0;
+    if (up) {
+      flux_hi = phit_val(Dc, D_up, Hz, Hz_up, r23, r23_up, G.S[Z], phi_face<3>(G, ph, Z, k, k),
+                         G.inv_h[Z]);
+      diag_hi = 0.5 * (Dc + D_up) * kz_;
+      sum += flux_hi;
+      diag += diag_hi;
+    }
+    if (k > 0) {
+      sum -= flux_lo;
+      diag += diag_lo;
+    }
+    flux_lo = flux_hi;
+    diag_lo = diag_hi;
+    if (c.act) {
+      const int P = qo + pl * k;
+      b[P] = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
+      dinv[P] = 1.0 / diag;
+    }
   }
 }
 
@@ -626,6 +1228,155 @@ __global__ __launch_bounds__(kBlock) void k_correct(
     }
   }
   if (!last) return;
+  __shared__ double sh[3][kBlock / 64];
+  Reducer<0x2u, 3>::block(red, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partials[k * gridDim.x + blockIdx.x] = red[k];
+}
+
+// k_correct on a 3D mesh with the x/y neighbours of p' and rho23 (and, on the
+// last corrector, D, H_x and H_y) staged in LDS and the next plane's loads in
+// flight while a plane is computed.  Same formulas and order as k_correct.
+template <bool LAST>
+__global__ __launch_bounds__(kBlock) void k_correct3(
+    Geo G, Phys ph, int kc, const double* __restrict__ pp, const double* __restrict__ rho23,
+    const double* __restrict__ psi, Vec<3> H, const double* __restrict__ D,
+    const double* __restrict__ rho_star, Vec<3> u_out, const double* __restrict__ rho_old,
+    double* __restrict__ rho_new, double* __restrict__ p_new, double* partials) {
+  using St = Stage3<1>;
+  constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
+  constexpr int NF = LAST ? 5 : 2;
+  __shared__ double ss[2][NF][HP];  // p', rho23 (, D, H_x, H_y)
+  const Col c = col_of<3>(G, kc);
+  const St st = stage3<1>(G, c);
+  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
+  const double kz_ = G.S[Z] / G.h[Z];
+  // raw values of the plane in flight
+  double fs[NF][NU], frs, fpu, fru, fH[3], fDu = 0.0, fHzu = 0.0, fro = 0.0, fps = 0.0;
+  auto fetch = [&](int kk) {
+    const int o = pl * kk, P = qo + o;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int Q = st.q[m] + o;
+      fs[0][m] = pp[Q];
+      fs[1][m] = rho23[Q];
+      if (LAST) {
+        fs[2 % NF][m] = D[Q];
+        fs[3 % NF][m] = H.p[0][Q];
+        fs[4 % NF][m] = H.p[1][Q];
+      }
+    }
+    const int Pu = nb(kk + 1 < nz, P + pl, P);
+    frs = rho_star[P];
+    fpu = pp[Pu];
+    fru = rho23[Pu];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fH[d] = H.p[d][P];
+    if (LAST) {
+      fDu = D[Pu];
+      fHzu = H.p[Z][Pu];
+      fro = rho_old[P];
+      fps = psi[P];
+    }
+  };
+  double red[3] = {0.0, 0.0, 0.0};
+  double Flo = 0.0, flux_lo = 0.0;
+  if (c.k0 > 0) {
+    const int P = qo + pl * c.k0, Q = P - pl;
+    const double phf = phi_face<3>(G, ph, Z, c.k0 - 1, c.k0 - 1);
+    Flo = force_val(pp[Q], pp[P], rho23[Q], rho23[P], phf, G.inv_h[Z]);
+    if (LAST) {
+      const double w = 0.5 * (D[Q] + D[P]) * kz_;
+      flux_lo = phit_val(D[Q], D[P], H.p[Z][Q], H.p[Z][P], rho23[Q], rho23[P], G.S[Z], phf,
+                         G.inv_h[Z]) -
+                w * (pp[P] - pp[Q]);
+    }
+  }
+  fetch(c.k0);
+  for (int k = c.k0; k < c.k1; ++k) {
+    const int sl = k & 1;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int m = 0; m < NU; ++m)
+        if (st.has[m]) ss[sl][f][st.h[m]] = fs[f][m];
+    const double rs = frs, p_up = fpu, r_up = fru, D_up = fDu, Hz_up = fHzu, r_old = fro, psP = fps;
+    const double Hc[3] = {fH[0], fH[1], fH[2]};
+    fetch(k + 1 < c.k1 ? k + 1 : k);
+    lds_barrier();
+    const bool up = k + 1 < nz;
+    const double* Sp = ss[sl][0];
+    const double* Sr = ss[sl][1];
+    const double pc = Sp[ho], r23 = Sr[ho];
+    // velocity correction
+    const double inv_A = ph.dt / rs;
+    const double phc = phi_cell(G, ph, k);
+    const double Fhi = up ? force_val(pc, p_up, r23, r_up, phi_face<3>(G, ph, Z, k, k), G.inv_h[Z]) : 0.0;
+    bool finite = true;
+    double uo[3];
+#pragma unroll
+    for (int cmp = 0; cmp < 3; ++cmp) {
+      double RF;
+      if (cmp == Z) {
+        RF = 0.5 * (Flo + Fhi);
+      } else {
+        const int n = G.n[cmp], q = coord(c, cmp), sd = cmp == 0 ? 1 : HX;
+        const double hi = q + 1 < n ? force_val(pc, Sp[ho + sd], r23, Sr[ho + sd], phc, G.inv_h[cmp]) : 0.0;
+        const double lo = q > 0 ? force_val(Sp[ho - sd], pc, Sr[ho - sd], r23, phc, G.inv_h[cmp]) : 0.0;
+        RF = 0.5 * (lo + hi);
+      }
+      uo[cmp] = (Hc[cmp] - RF) * inv_A;
+      finite = finite && isfinite(uo[cmp]);
+    }
+    Flo = Fhi;
+    const int P = qo + pl * k;
+    if (c.act) {
+#pragma unroll
+      for (int cmp = 0; cmp < 3; ++cmp) u_out.p[cmp][P] = uo[cmp];
+    }
+    if (LAST) {
+      const double* SD = ss[sl][2 % NF];
+      const double Dc = SD[ho];
+      double sum = 0.0;
+#pragma unroll
+      for (int d = 0; d < Z; ++d) {
+        const int q = coord(c, d), sd = d == 0 ? 1 : HX;
+        const double* SH = ss[sl][(3 + d) % NF];
+        const double kd = G.S[d] / G.h[d];
+        if (q + 1 < G.n[d]) {
+          const double w = 0.5 * (Dc + SD[ho + sd]) * kd;
+          sum += phit_val(Dc, SD[ho + sd], Hc[d], SH[ho + sd], r23, Sr[ho + sd], G.S[d], phc, G.inv_h[d]) -
+                 w * (Sp[ho + sd] - pc);
+        }
+        if (q > 0) {
+          const double w = 0.5 * (SD[ho - sd] + Dc) * kd;
+          sum -= phit_val(SD[ho - sd], Dc, SH[ho - sd], Hc[d], Sr[ho - sd], r23, G.S[d], phc, G.inv_h[d]) -
+                 w * (pc - Sp[ho - sd]);
+        }
+      }
+      double flux_hi = 0.0;
+      if (up) {
+        const double w = 0.5 * (Dc + D_up) * kz_;
+        flux_hi = phit_val(Dc, D_up, Hc[Z], Hz_up, r23, r_up, G.S[Z], phi_face<3>(G, ph, Z, k, k),
+                           G.inv_h[Z]) -
+                  w * (p_up - pc);
+        sum += flux_hi;
+      }
+      if (k > 0) sum -= flux_lo;
+      flux_lo = flux_hi;
+      const double rn = r_old - ph.dt / G.V * sum;
+      const double pn = pc - r23 * phc;
+      if (c.act) {
+        rho_new[P] = rn;
+        p_new[P] = pn;
+        red[0] += rn * G.V;
+        red[1] = fmax(red[1], fabs(rn - psP * pn));
+      }
+      finite = finite && isfinite(rn) && isfinite(pn);
+    }
+    if (c.act) red[2] += finite ? 0.0 : 1.0;
+  }
+  if (!LAST) return;
   __shared__ double sh[3][kBlock / 64];
   Reducer<0x2u, 3>::block(red, sh);
   if (threadIdx.x == 0)
@@ -756,7 +1507,7 @@ void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double*
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
   else
-    hipLaunchKernelGGL(k_mass_flux<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), T, V3(phi), rho_star, e0);
+    hipLaunchKernelGGL(k_mass_flux3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), T, V3(phi), rho_star, e0);
 }
 
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
@@ -766,7 +1517,7 @@ void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const doubl
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star));
   else
-    hipLaunchKernelGGL(k_mom_predict<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star));
+    hipLaunchKernelGGL(k_mom_predict3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star));
 }
 
 void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
@@ -778,7 +1529,7 @@ void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const doub
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_energy_sweep<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
   else
-    hipLaunchKernelGGL(k_energy_sweep<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
+    hipLaunchKernelGGL(k_energy_sweep3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
 }
 
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,
@@ -787,7 +1538,7 @@ void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, do
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_H<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), V2(u_prev), V2(phi), V2(H));
   else
-    hipLaunchKernelGGL(k_H<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), V3(u_prev), V3(phi), V3(H));
+    hipLaunchKernelGGL(k_H3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), V3(u_prev), V3(phi), V3(H));
 }
 
 void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
@@ -797,7 +1548,7 @@ void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V2(H), b, dinv);
   else
-    hipLaunchKernelGGL(k_rhs<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V3(H), b, dinv);
+    hipLaunchKernelGGL(k_rhs3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V3(H), b, dinv);
 }
 
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
@@ -808,8 +1559,10 @@ void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* p
   const ZPlan zp = zplan(G);
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_correct<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V2(H), D, rho_star, V2(u_out), (int)last, rho_old, rho_new, p_new, partials);
+  else if (last)
+    hipLaunchKernelGGL(k_correct3<true>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, partials);
   else
-    hipLaunchKernelGGL(k_correct<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), (int)last, rho_old, rho_new, p_new, partials);
+    hipLaunchKernelGGL(k_correct3<false>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, partials);
   if (last)
     hipLaunchKernelGGL(k_finalize_reduce, dim3(1), dim3(kBlock), 0, s, (const double*)partials, zp.blocks, sc);
 }

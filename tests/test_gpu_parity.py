@@ -116,6 +116,7 @@ def test_pressure_system_and_solve_match_oracle(oracle_lib, gea_mod):
     ("nonsmooth2d_2048", (128, 128, None), 5),
     ("bubble3d_256x256x128", (24, 16, 20), 5),
     ("bubble3d_256x256x128", (13, 9, 11), 5),          # ragged 3D
+    ("bubble3d_256x256x128", (70, 9, 10), 3),          # 3D halos across x and y tiles
 ])
 def test_steps_match_oracle(oracle_lib, gea_mod, name, dims, steps):
     nx, nz, ny = dims

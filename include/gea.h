@@ -29,7 +29,9 @@
  *    ndim consecutive blocks of ncell values.
  *  - Memory: the caller owns every input and output array and the device
  *    workspace (size from gea_workspace_bytes, 256-byte aligned).  The
- *    library allocates no device memory; it owns only the opaque context.
+ *    library allocates no device memory; it owns only the opaque context
+ *    and, inside it, a 4 KB pinned host buffer through which it reads the
+ *    solver's convergence scalars.
  *  - Streams: all device work is enqueued on the stream given to
  *    gea_init_mesh.  gea_step, gea_pressure_solve and gea_init_bubble return
  *    after the work completed (convergence is decided from device values);

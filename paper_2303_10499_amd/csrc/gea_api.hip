@@ -189,9 +189,18 @@ struct gea_ctx {
   KernelTimer timer;
   int last_iters64 = 0;  // iterations of the previous solve: first batch length
   int last_iters32 = 0;
+  int last_iters_res = 0;  // iterations of the last Jacobi-PCG resumed after the network
   bool has_state = false;
   bool has_system = false;
+  bool sys32 = false;  // c32, D32, dinv32 hold the current operator
   std::string err;
+  // pinned host buffer the solver scalars are read through (device-to-host
+  // copies into it are asynchronous, so several go out with one wait)
+  char* pin = nullptr;
+  static constexpr size_t kPinBytes = 4096;
+  ~gea_ctx() {
+    if (pin) (void)hipHostFree(pin);
+  }
 };
 
 namespace {
@@ -349,19 +358,54 @@ void setup_geometry(gea_ctx* x) {
   x->ph = Phys{q.R, q.cp, q.cv, q.g, q.mu, q.Pr, q.dt, q.p0, q.theta0, 1.0 / q.dt, 1.0 / q.cv};
 }
 
-void read_scalars(gea_ctx* x, CgScalars* dev, CgScalars* host) {
-  HIPCHK(hipMemcpyAsync(host, dev, sizeof(CgScalars), hipMemcpyDeviceToHost, x->stream));
-  HIPCHK(hipStreamSynchronize(x->stream));
+// A device struct to read along with the solver scalars.
+struct Extra {
+  const void* dev = nullptr;
+  void* host = nullptr;
+  size_t bytes = 0;
+};
+
+// Wait for the stream by polling it: the host acts on the solver scalars
+// as soon as the copy lands, without a blocking wait's wake-up latency.
+void wait_stream(gea_ctx* x) {
+  hipError_t e;
+  while ((e = hipStreamQuery(x->stream)) == hipErrorNotReady) {
+  }
+  HIPCHK(e);
+}
+
+// Device structs to the host through the pinned buffer with one wait.
+void read_structs(gea_ctx* x, const Extra* parts, int n) {
+  size_t off = 0;
+  for (int k = 0; k < n; ++k) {
+    if (off + parts[k].bytes > gea_ctx::kPinBytes) throw HipError{hipErrorInvalidValue, "pinned read buffer too small"};
+    HIPCHK(hipMemcpyAsync(x->pin + off, parts[k].dev, parts[k].bytes, hipMemcpyDeviceToHost, x->stream));
+    off += (parts[k].bytes + 255) & ~(size_t)255;
+  }
+  wait_stream(x);
+  off = 0;
+  for (int k = 0; k < n; ++k) {
+    std::memcpy(parts[k].host, x->pin + off, parts[k].bytes);
+    off += (parts[k].bytes + 255) & ~(size_t)255;
+  }
   x->timer.flush();
+}
+
+// Device scalars (and an optional second struct) to the host with one wait.
+void read_scalars(gea_ctx* x, CgScalars* dev, CgScalars* host, const Extra& extra = Extra{}) {
+  const Extra parts[2] = {Extra{dev, host, sizeof(CgScalars)}, extra};
+  read_structs(x, parts, extra.bytes ? 2 : 1);
 }
 
 // Host loop of one CG solve: enqueue batches of iterations, read the device
 // scalars after each batch.  The batch length is predicted from the
 // residual's observed decay rate so that few launches follow convergence
-// (those find the done flag set and return at once).
+// (those find the done flag set and return at once).  A solve enqueued
+// behind kernels whose outcome the host has not read (hs.rr = 0 on entry)
+// takes its starting residual from the device scalars' rr0.
 template <typename LaunchIter>
 gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int first_batch,
-                  LaunchIter&& launch_iter) {
+                  LaunchIter&& launch_iter, const Extra& extra = Extra{}) {
   const int every = x->prm.check_every > 0 ? x->prm.check_every : 8;
   const long cap = (long)max_iter + 4L * every + 64;
   int batch = first_batch > 0 ? first_batch : every;
@@ -375,7 +419,11 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
     }
     for (int k = 0; k < batch; ++k, ++j) launch_iter((int)j);
     HIPCHK(hipGetLastError());
-    read_scalars(x, dsc, &hs);
+    read_scalars(x, dsc, &hs, extra);
+    if (prev_rr <= 0.0) {
+      prev_rr = hs.rr0;
+      prev_iter = 0;
+    }
     const int di = hs.iter - prev_iter;
     batch = every;
     if (!hs.done && di > 0 && hs.rr > 0 && prev_rr > 0 && hs.bb > 0) {
@@ -390,6 +438,24 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
     prev_rr = hs.rr;
   }
   return GEA_OK;
+}
+
+// Pressure right-hand side and 1/diag from H; the refined forms also get the
+// FP32 copies of the operator from the same pass.
+void build_system(gea_ctx* x, const State& S) {
+  const bool f32 = x->prm.solver != GEA_PCG_JACOBI_FP64;
+  launch_rhs(x->stream, x->G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H, x->b, x->dinv,
+             f32 ? x->c32 : nullptr, f32 ? x->D32 : nullptr, f32 ? x->dinv32 : nullptr);
+  x->sys32 = f32;
+}
+
+// FP32 copies of the operator unless the system build wrote them.
+void cast_system(gea_ctx* x) {
+  if (x->sys32) return;
+  x->timer.run(4, x->stream, [&] {
+    launch_cast_coeffs(x->stream, x->G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
+  });
+  x->sys32 = true;
 }
 
 // FP64 Jacobi-PCG on (c, D, dinv, b) from the initial guess in xv.
@@ -429,9 +495,7 @@ gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
 gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   const Geo& G = x->G;
   const CgWork& w = x->w32;
-  x->timer.run(4, x->stream, [&] {
-    launch_cast_coeffs(x->stream, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
-  });
+  cast_system(x);
   CgVectors<float> v{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
   int total = 0;
   int outer = 0;
@@ -445,11 +509,11 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
     }
     const int budget = x->prm.max_iter - total;
     x->timer.run(4, x->stream, [&] {
-      launch_residual64(x->stream, G, x->c, x->D, x->b, xv, x->r64, v, x->prm.tol,
+      launch_residual64(x->stream, G, x->c, x->D, x->b, xv, v, x->prm.tol,
                         x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
     });
     HIPCHK(hipGetLastError());
-    read_scalars(x, x->sc, &h64);
+    read_scalars(x, x->sc, &h64, Extra{x->sc32, &h32, sizeof h32});
     const double rel = h64.bb > 0 ? std::sqrt(h64.rr / h64.bb) : 0.0;
     if (out->rel_res0 < 0) out->rel_res0 = rel;
     out->rel_res = rel;
@@ -467,7 +531,6 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->status = GEA_ERR_NOCONV;
       break;
     }
-    read_scalars(x, x->sc32, &h32);
     const int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
     gea_status rc = run_cg(
         x, x->sc32, h32, budget, first,
@@ -491,11 +554,12 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
 }
 
 // Flexible CG with the network as preconditioner on the FP32 correction
-// system set up by the refinement residual (r32, c32, D32), at most `steps`
-// iterations.  Returns the iterations done; *stalled is set when the stall
-// test fired, *converged when the inner tolerance was reached.
-int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps, bool* stalled,
-                  bool* converged) {
+// system set up by the refinement residual (r32, c32, D32): enqueues at most
+// `steps` iterations and returns how many it enqueued.  The host reads the
+// flexible-CG scalars only between iterations, never after the last one:
+// the caller reads them with its next read of the solver scalars.  (After
+// the stop decision the iteration kernels return at once.)
+int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps) {
   const Geo& G = x->G;
   FcgVectors& v = x->fv;
   v.d = x->d32;
@@ -510,14 +574,15 @@ int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps
   x->timer.run(4, x->stream, [&] {
     fcg_start(x->stream, G, v, bb, inner_tol, budget, x->fsc);
   });
-  FcgScalars hf;
-  HIPCHK(hipMemcpyAsync(&hf, x->fsc, sizeof hf, hipMemcpyDeviceToHost, x->stream));
-  HIPCHK(hipStreamSynchronize(x->stream));
-  x->timer.flush();
-  *stalled = false;
-  int it = 0;
   const int cap = steps < budget ? steps : budget;
-  while (!hf.done && it < cap) {
+  int it = 0;
+  while (it < cap) {
+    if (it > 0) {
+      FcgScalars hf;
+      const Extra part{x->fsc, &hf, sizeof hf};
+      read_structs(x, &part, 1);
+      if (hf.done) break;
+    }
     x->timer.run(6, x->stream, [&] {
       cnn_input_from_residual(x->net, x->r32, &x->fsc->inv_s, x->c32, x->dinv32);
       cnn_forward(x->net);
@@ -526,12 +591,7 @@ int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps
     x->timer.run(2, x->stream, [&] { fcg_iteration_after_z(x->stream, G, v, it, x->fsc); });
     HIPCHK(hipGetLastError());
     ++it;
-    HIPCHK(hipMemcpyAsync(&hf, x->fsc, sizeof hf, hipMemcpyDeviceToHost, x->stream));
-    HIPCHK(hipStreamSynchronize(x->stream));
-    x->timer.flush();
   }
-  *stalled = hf.status == 1;
-  *converged = hf.done && hf.status == 0;
   return it;
 }
 
@@ -541,9 +601,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   if (!x->has_net) return solve_mixed(x, xv, out);
   const Geo& G = x->G;
   const CgWork& w = x->w32;
-  x->timer.run(4, x->stream, [&] {
-    launch_cast_coeffs(x->stream, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
-  });
+  cast_system(x);
   CgVectors<float> v{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
   int total = 0, outer = 0, fallbacks = 0;
   bool use_net = true;
@@ -557,11 +615,11 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
     }
     const int budget = x->prm.max_iter - total;
     x->timer.run(4, x->stream, [&] {
-      launch_residual64(x->stream, G, x->c, x->D, x->b, xv, x->r64, v, x->prm.tol,
+      launch_residual64(x->stream, G, x->c, x->D, x->b, xv, v, x->prm.tol,
                         x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
     });
     HIPCHK(hipGetLastError());
-    read_scalars(x, x->sc, &h64);
+    read_scalars(x, x->sc, &h64, Extra{x->sc32, &h32, sizeof h32});
     const double rel = h64.bb > 0 ? std::sqrt(h64.rr / h64.bb) : 0.0;
     if (out->rel_res0 < 0) out->rel_res0 = rel;
     out->rel_res = rel;
@@ -579,41 +637,45 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->status = GEA_ERR_NOCONV;
       break;
     }
-    read_scalars(x, x->sc32, &h32);
     int done_iters = 0;
-    bool pcg = true;  // the inner solve (still) needs Jacobi-PCG
+    FcgScalars hf{};
+    Extra fcg;  // the flexible-CG scalars, read along with the CG's
+    int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
     if (use_net) {
-      bool stalled = false, converged = false;
       // same adaptive inner tolerance as the refinement residual kernel sets
       const double need = 0.1 * std::sqrt(x->prm.tol * x->prm.tol * h64.bb / h64.rr);
       const double itol = std::max(x->prm.inner_tol, std::min(0.5, need));
-      done_iters = learned_inner(x, h32.bb, itol, budget > 0 ? budget : 1, x->prm.learned_steps,
-                                 &stalled, &converged);
-      // after learned_steps network iterations (or a stall) Jacobi-PCG continues
-      // the same inner solve from its current iterate and residual
+      const int launched = learned_inner(x, h32.bb, itol, budget > 0 ? budget : 1,
+                                         x->prm.learned_steps);
       use_net = false;
-      if (stalled) ++fallbacks;
-      pcg = !converged && done_iters < budget;
-      if (pcg) {
-        const int left = budget - done_iters;
-        x->timer.run(4, x->stream, [&] { cg_resume(x->stream, G, v, w, left); });
-        read_scalars(x, x->sc32, &h32);
-      }
+      // Jacobi-PCG continues the same inner solve from the flexible-CG
+      // iterate and residual, enqueued behind it unread: when the flexible
+      // CG has converged the resumed solve starts done, and its iteration
+      // kernels return at once.  Its first batch is the previous resumed
+      // solve's length and two more.
+      const int left = budget - launched;
+      x->timer.run(4, x->stream, [&] { cg_resume(x->stream, G, v, w, left > 0 ? left : 0); });
+      h32 = CgScalars{};
+      fcg = Extra{x->fsc, &hf, sizeof hf};
+      first = x->last_iters_res > 0 ? x->last_iters_res + 2 : 0;
     }
-    if (pcg) {
-      const int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
-      gea_status rc = run_cg(
-          x, x->sc32, h32, budget, first,
-          [&](int j) {
-            x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
-            x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
-          });
-      if (rc != GEA_OK) return rc;
-      done_iters += h32.iter;
-      if (h32.status == -5) {
-        out->status = GEA_ERR_NAN;
-        break;
-      }
+    gea_status rc = run_cg(
+        x, x->sc32, h32, budget, first,
+        [&](int j) {
+          x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
+          x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+        },
+        fcg);
+    if (rc != GEA_OK) return rc;
+    done_iters += h32.iter;
+    if (fcg.bytes) {
+      x->last_iters_res = h32.iter;
+      done_iters += hf.iter;
+      if (hf.status == 1) ++fallbacks;  // stalled: Jacobi-PCG took over
+    }
+    if (h32.status == -5) {
+      out->status = GEA_ERR_NAN;
+      break;
     }
     total += done_iters;
     ++outer;
@@ -653,6 +715,7 @@ void steps_1_2(gea_ctx* x, const State& S, double* T_out) {
     e_prev = e_next;
     T_prev = T_next;
   }
+  x->sys32 = false;  // c and D changed
 }
 
 gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
@@ -668,7 +731,7 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
   for (int k = 0; k < nc; ++k) {
     const bool last = k == nc - 1;
     x->timer.run(5, x->stream, [&] { launch_H(s, G, ph, S.rho, S.u, x->ustar, x->phi, x->H); });
-    x->timer.run(5, x->stream, [&] { launch_rhs(s, G, ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H, x->b, x->dinv); });
+    x->timer.run(5, x->stream, [&] { build_system(x, S); });
     HIPCHK(hipGetLastError());
     x->has_system = true;
     gea_solve_stats ss;
@@ -762,6 +825,13 @@ gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* h
   gea_ctx* x = new (std::nothrow) gea_ctx();
   if (!x) {
     g_init_error = "context allocation failed";
+    return GEA_ERR_ALLOC;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&x->pin), gea_ctx::kPinBytes, hipHostMallocDefault) !=
+      hipSuccess) {
+    x->pin = nullptr;
+    delete x;
+    g_init_error = "pinned host buffer allocation failed";
     return GEA_ERR_ALLOC;
   }
   x->mesh = *mesh;
@@ -878,7 +948,7 @@ gea_status gea_pressure_solve(gea_ctx* x, const double* b, double* xv, gea_ptr_k
     const State& N = x->st[1 - x->cur];
     steps_1_2(x, S, N.T);
     x->timer.run(5, x->stream, [&] { launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H); });
-    x->timer.run(5, x->stream, [&] { launch_rhs(s, G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H, x->b, x->dinv); });
+    x->timer.run(5, x->stream, [&] { build_system(x, S); });
     HIPCHK(hipGetLastError());
     const size_t n = sizeof(double) * G.nc;
     if (b) HIPCHK(hipMemcpyAsync(x->b, b, n, kind_in(kind), s));
@@ -981,7 +1051,7 @@ gea_status gea_time_solver_kernels(gea_ctx* x, int32_t reps, double* ms) {
     // FP32 inner kernels on the refinement's set-up (outer tol 0: not done)
     launch_cast_coeffs(s, G, x->c, x->D, x->dinv, x->c32, x->D32, x->dinv32);
     CgVectors<float> v32{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
-    launch_residual64(s, G, x->c, x->D, x->b, x->xs, x->r64, v32, 0.0, 1e-30, 1 << 30, x->o_part,
+    launch_residual64(s, G, x->c, x->D, x->b, x->xs, v32, 0.0, 1e-30, 1 << 30, x->o_part,
                       x->w32, x->sc);
     cg_iter_kernel<float>(s, G, v32, 0, x->w32);
     cg_scalars(s, G, 0, x->w32);
@@ -1069,7 +1139,7 @@ gea_status gea_make_pair(gea_ctx* x, double rel_tol, float* in_r, float* in_a, f
     const State& N = x->st[1 - x->cur];
     steps_1_2(x, S, N.T);
     launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H);
-    launch_rhs(s, G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H, x->b, x->dinv);
+    build_system(x, S);
     // r0 = b - A p'  (FP64), then the tight FP64 solve from x0 = p'
     launch_apply_A(s, G, x->c, x->D, S.pp, x->r64);
     const size_t n = sizeof(double) * G.nc;

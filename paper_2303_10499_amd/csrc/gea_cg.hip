@@ -561,7 +561,6 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
                                                        const double* __restrict__ D,
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ x,
-                                                       double* __restrict__ r64,
                                                        CgVectors<float> v32, int kc,
                                                        double* o_part, double* i_part) {
   double ro[2] = {0.0, 0.0};
@@ -578,7 +577,90 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
       const float di = v32.dinv[P];
       const double r = bp - A.at(G, K, col, P, k, c);
       A.next();
-      r64[P] = r;
+      const float rf = (float)r;
+      v32.r[P] = rf;
+      v32.x[P] = 0.0f;
+      v32.p0[P] = 0.0f;
+      ro[0] += r * r;
+      ro[1] += bp * bp;
+      ri[0] += (double)rf * (double)(rf * di);
+      ri[1] += (double)rf * (double)rf;
+    }
+  }
+  store_partials<2>(ro, o_part);
+  store_partials<2>(ri, i_part);
+}
+
+// k_residual64 on a 3D mesh with the x/y neighbours of x and D staged in LDS
+// and the next plane's loads in flight while a plane is computed.  Same
+// formulas and order as k_residual64.
+__global__ __launch_bounds__(kBlock) void k_residual64_3(Geo G, Stencil<3, double> K,
+                                                         const double* __restrict__ c,
+                                                         const double* __restrict__ D,
+                                                         const double* __restrict__ b,
+                                                         const double* __restrict__ x,
+                                                         CgVectors<float> v32, int kc,
+                                                         double* o_part, double* i_part) {
+  using St = Stage3<1>;
+  constexpr int HP = St::HP, HX = St::HX, NU = St::NU;
+  __shared__ double sx[2][HP], sd[2][HP];
+  const Col col = col_of<3>(G, kc);
+  const St st = stage3<1>(G, col);
+  const int nz = G.nz, pl = col.pl, qo = st.qo, ho = st.ho;
+  // raw values of the plane in flight
+  double fx[NU], fd[NU], fb, fc, fxu, fdu;
+  float fdi;
+  auto fetch = [&](int kk) {
+    const int o = pl * kk, P = qo + o;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      fx[m] = x[st.q[m] + o];
+      fd[m] = D[st.q[m] + o];
+    }
+    const int Pu = kk + 1 < nz ? P + pl : P;
+    fb = b[P];
+    fc = c[P];
+    fdi = v32.dinv[P];
+    fxu = x[Pu];
+    fdu = D[Pu];
+  };
+  double ro[2] = {0.0, 0.0};
+  double ri[2] = {0.0, 0.0};
+  double xm = 0.0, dm = 0.0;
+  if (col.k0 > 0) {
+    xm = x[qo + pl * (col.k0 - 1)];
+    dm = D[qo + pl * (col.k0 - 1)];
+  }
+  fetch(col.k0);
+  for (int k = col.k0; k < col.k1; ++k) {
+    const int sl = k & 1;
+#pragma unroll
+    for (int m = 0; m < NU; ++m)
+      if (st.has[m]) {
+        sx[sl][st.h[m]] = fx[m];
+        sd[sl][st.h[m]] = fd[m];
+      }
+    const double bp = fb, cP = fc, xu = fxu, du = fdu;
+    const float di = fdi;
+    fetch(k + 1 < col.k1 ? k + 1 : k);
+    lds_barrier();
+    const bool up = k + 1 < nz;
+    const double xc = sx[sl][ho], dc = sd[sl][ho];
+    const double xp = up ? xu : 0.0, dp = up ? du : 0.0;
+    double acc = cP * xc;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int q = coord(col, d), sd_ = d == 0 ? 1 : HX;
+      acc = q + 1 < G.n[d] ? acc + 0.5 * (dc + sd[sl][ho + sd_]) * K.k[d] * (xc - sx[sl][ho + sd_]) : acc;
+      acc = q > 0 ? acc + 0.5 * (sd[sl][ho - sd_] + dc) * K.k[d] * (xc - sx[sl][ho - sd_]) : acc;
+    }
+    if (up) acc += 0.5 * (dc + dp) * K.k[2] * (xc - xp);
+    if (k > 0) acc += 0.5 * (dm + dc) * K.k[2] * (xc - xm);
+    xm = xc;
+    dm = dc;
+    if (col.act) {
+      const int P = qo + pl * k;
+      const double r = bp - acc;
       const float rf = (float)r;
       v32.r[P] = rf;
       v32.x[P] = 0.0f;
@@ -660,6 +742,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resume_start(const double* part, 
   if (threadIdx.x != 0) return;
   sc->rz = s[0];
   sc->rr = s[1];
+  sc->rr0 = s[1];
   sc->alpha = 0.0;
   sc->beta = 0.0;
   sc->fin = 0;
@@ -761,16 +844,16 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 }
 
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
-                       const double* b, const double* x, double* r64,
-                       const CgVectors<float>& v32, double tol, double inner_tol, int inner_max,
-                       double* o_part, const CgWork& w32, CgScalars* sc64) {
+                       const double* b, const double* x, const CgVectors<float>& v32,
+                       double tol, double inner_tol, int inner_max, double* o_part,
+                       const CgWork& w32, CgScalars* sc64) {
   const ZPlan zp = zplan(G);
   const int gu = zp.blocks;
   const dim3 grid(gu), block(kBlock);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, r64, v32, zp.kc, o_part, w32.u[1]);
+    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1]);
   else
-    hipLaunchKernelGGL(k_residual64<3>, grid, block, 0, s, G, stencil<3, double>(G), c, D, b, x, r64, v32, zp.kc, o_part, w32.u[1]);
+    hipLaunchKernelGGL(k_residual64_3, grid, block, 0, s, G, stencil<3, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1]);
   hipLaunchKernelGGL(k_residual_check, dim3(1), block, 0, s, (const double*)o_part,
                      (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, inner_max,
                      sc64, w32.sc);

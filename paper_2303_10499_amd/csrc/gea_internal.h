@@ -46,6 +46,7 @@ struct CgScalars {
   double beta;      // its direction coefficient
   double tol2;      // tol^2
   double aux[6];    // reduction results of the step kernels
+  double rr0;       // ||r||^2 where a resumed solve started
   int iter;         // completed iterations
   int max_iter;
   int done;         // 1 once converged or failed
@@ -82,7 +83,8 @@ void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, do
               double* const* u_prev, double* const* phi, double* const* H);
 void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                 const double* rho23, const double* psi, const double* c, const double* D,
-                double* const* H, double* b, double* dinv);
+                double* const* H, double* b, double* dinv, float* c32, float* D32,
+                float* dinv32);  // FP32 copies of c, D, 1/diag written unless c32 is null
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
                     const double* rho23, const double* psi, double* const* H, const double* D,
                     const double* rho_star, double* const* u_out, bool last,
@@ -158,9 +160,9 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 // Mixed precision: FP64 residual r = b - A x and its FP32 copy as the inner
 // right-hand side, outer stop test and inner setup; x += dx.
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
-                       const double* b, const double* x, double* r64,
-                       const CgVectors<float>& v32, double tol, double inner_tol, int inner_max,
-                       double* o_part, const CgWork& w32, CgScalars* sc64);
+                       const double* b, const double* x, const CgVectors<float>& v32,
+                       double tol, double inner_tol, int inner_max, double* o_part,
+                       const CgWork& w32, CgScalars* sc64);
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,
                         const double* dinv, float* c32, float* D32, float* dinv32);
 void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx);

@@ -139,6 +139,70 @@ __device__ __forceinline__ Col col_of(const Geo& G, int kc) {
   return c;
 }
 
+// Plane staging of the 3D kernels: the workgroup's 64x4 column tile with a
+// halo of HW cells along x and y (HW = 2: 68x8 = 544 cells a plane, for the
+// fourth-order interpolation; HW = 1: 66x6 = 396).  Thread t stages its own
+// cell (slot 0) and halo cells t, 256 + t, ... (slots 1, 2, ...): the HW rows
+// below the tile, the HW rows above it, then the side columns.  Indices are
+// clamped into the mesh, so every staging load is unconditional and in
+// bounds; a staged value of a cell outside the mesh is only ever read into a
+// term that a wall test discards.
+template <int HW_>
+struct Stage3 {
+  static constexpr int TX = ZTile<3>::TX, TY = ZTile<3>::TY, HW = HW_;
+  static constexpr int HX = TX + 2 * HW, HY = TY + 2 * HW, HP = HX * HY;
+  static constexpr int NH = HP - TX * TY;                 // halo cells
+  static constexpr int NU = 1 + (NH + kBlock - 1) / kBlock;  // slots a thread
+  static_assert(TX * TY == kBlock, "one own cell a thread");
+  int q[NU];     // cell index in plane 0 (clamped into the mesh)
+  int h[NU];     // index in the staged plane
+  bool has[NU];  // the thread stages a cell in this slot
+  int qo;        // the thread's own column, clamped into the mesh
+  int ho;        // its cell in the staged plane
+};
+
+__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+template <int HW>
+__device__ __forceinline__ Stage3<HW> stage3(const Geo& G, const Col& c) {
+  using S = Stage3<HW>;
+  S st;
+  const int lx = (int)threadIdx.x % S::TX, ly = (int)threadIdx.x / S::TX;
+  const int i0 = c.i - lx, j0 = c.j - ly;
+  st.ho = (lx + HW) + S::HX * (ly + HW);
+  st.qo = clampi(c.i, G.nx) + G.nx * clampi(c.j, G.ny);
+  st.q[0] = st.qo;
+  st.h[0] = st.ho;
+  st.has[0] = true;
+#pragma unroll
+  for (int m = 1; m < S::NU; ++m) {
+    int e = (int)threadIdx.x + (m - 1) * kBlock;
+    st.has[m] = e < S::NH;
+    if (!st.has[m]) {  // no cell in this slot: load the own cell again, write nothing
+      st.q[m] = st.qo;
+      st.h[m] = st.ho;
+      continue;
+    }
+    int hx, hy;
+    if (e < HW * S::HX) {
+      hy = e / S::HX;
+      hx = e % S::HX;
+    } else if (e < 2 * HW * S::HX) {
+      e -= HW * S::HX;
+      hy = S::TY + HW + e / S::HX;
+      hx = e % S::HX;
+    } else {
+      e -= 2 * HW * S::HX;
+      hy = HW + e / (2 * HW);
+      const int s = e % (2 * HW);
+      hx = s < HW ? s : S::HX - 2 * HW + s;
+    }
+    st.h[m] = hx + S::HX * hy;
+    st.q[m] = clampi(i0 + hx - HW, G.nx) + G.nx * clampi(j0 + hy - HW, G.ny);
+  }
+  return st;
+}
+
 // coordinate of the column along an x/y direction
 __device__ __forceinline__ int coord(const Col& c, int d) { return d == 0 ? c.i : c.j; }
 

@@ -95,70 +95,6 @@ __device__ __forceinline__ double phit_val(double D_lo, double D_hi, double H_lo
   return Df * S * (Hf + phif * (r_hi - r_lo) * inv_h);
 }
 
-// Plane staging of the 3D kernels: the workgroup's 64x4 column tile with a
-// halo of HW cells along x and y (HW = 2: 68x8 = 544 cells a plane, for the
-// fourth-order interpolation; HW = 1: 66x6 = 396).  Thread t stages its own
-// cell (slot 0) and halo cells t, 256 + t, ... (slots 1, 2, ...): the HW rows
-// below the tile, the HW rows above it, then the side columns.  Indices are
-// clamped into the mesh, so every staging load is unconditional and in
-// bounds; a staged value of a cell outside the mesh is only ever read into a
-// term that a wall test discards.
-template <int HW_>
-struct Stage3 {
-  static constexpr int TX = ZTile<3>::TX, TY = ZTile<3>::TY, HW = HW_;
-  static constexpr int HX = TX + 2 * HW, HY = TY + 2 * HW, HP = HX * HY;
-  static constexpr int NH = HP - TX * TY;                 // halo cells
-  static constexpr int NU = 1 + (NH + kBlock - 1) / kBlock;  // slots a thread
-  static_assert(TX * TY == kBlock, "one own cell a thread");
-  int q[NU];     // cell index in plane 0 (clamped into the mesh)
-  int h[NU];     // index in the staged plane
-  bool has[NU];  // the thread stages a cell in this slot
-  int qo;        // the thread's own column, clamped into the mesh
-  int ho;        // its cell in the staged plane
-};
-
-__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
-
-template <int HW>
-__device__ __forceinline__ Stage3<HW> stage3(const Geo& G, const Col& c) {
-  using S = Stage3<HW>;
-  S st;
-  const int lx = (int)threadIdx.x % S::TX, ly = (int)threadIdx.x / S::TX;
-  const int i0 = c.i - lx, j0 = c.j - ly;
-  st.ho = (lx + HW) + S::HX * (ly + HW);
-  st.qo = clampi(c.i, G.nx) + G.nx * clampi(c.j, G.ny);
-  st.q[0] = st.qo;
-  st.h[0] = st.ho;
-  st.has[0] = true;
-#pragma unroll
-  for (int m = 1; m < S::NU; ++m) {
-    int e = (int)threadIdx.x + (m - 1) * kBlock;
-    st.has[m] = e < S::NH;
-    if (!st.has[m]) {  // no cell in this slot: load the own cell again, write nothing
-      st.q[m] = st.qo;
-      st.h[m] = st.ho;
-      continue;
-    }
-    int hx, hy;
-    if (e < HW * S::HX) {
-      hy = e / S::HX;
-      hx = e % S::HX;
-    } else if (e < 2 * HW * S::HX) {
-      e -= HW * S::HX;
-      hy = S::TY + HW + e / S::HX;
-      hx = e % S::HX;
-    } else {
-      e -= 2 * HW * S::HX;
-      hy = HW + e / (2 * HW);
-      const int s = e % (2 * HW);
-      hx = s < HW ? s : S::HX - 2 * HW + s;
-    }
-    st.h[m] = hx + S::HX * hy;
-    st.q[m] = clampi(i0 + hx - HW, G.nx) + G.nx * clampi(j0 + hy - HW, G.ny);
-  }
-  return st;
-}
-
 // the five staged values of a line through the own cell, stride 1 (x) or HX (y)
 __device__ __forceinline__ Line line_lds(const double* s, int h, int str) {
   return Line{s[h - 2 * str], s[h - str], s[h], s[h + str], s[h + 2 * str]};
@@ -938,7 +874,9 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
                                                 const double* __restrict__ psi,
                                                 const double* __restrict__ cc,
                                                 const double* __restrict__ D, Vec<NDIM> H,
-                                                double* __restrict__ b, double* __restrict__ dinv) {
+                                                double* __restrict__ b, double* __restrict__ dinv,
+                                                float* __restrict__ c32, float* __restrict__ D32,
+                                                float* __restrict__ dinv32) {
   constexpr int Z = NDIM - 1;
   const Col c = col_of<NDIM>(G, kc);
   if (!c.act) return;
@@ -1004,7 +942,13 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
     flux_lo = flux_hi;
     diag_lo = diag_hi;
     b[P] = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
-    dinv[P] = 1.0 / diag;
+    const double di = 1.0 / diag;
+    dinv[P] = di;
+    if (c32) {  // FP32 copies of the operator for the refined forms
+      c32[P] = (float)cP;
+      D32[P] = (float)Dc;
+      dinv32[P] = (float)di;
+    }
   }
 }
 
@@ -1017,7 +961,9 @@ __global__ __launch_bounds__(kBlock) void k_rhs3(Geo G, Phys ph, int kc,
                                                  const double* __restrict__ psi,
                                                  const double* __restrict__ cc,
                                                  const double* __restrict__ D, Vec<3> H,
-                                                 double* __restrict__ b, double* __restrict__ dinv) {
+                                                 double* __restrict__ b, double* __restrict__ dinv,
+                                                 float* __restrict__ c32, float* __restrict__ D32,
+                                                 float* __restrict__ dinv32) {
   using St = Stage3<1>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double ss[2][4][HP];  // D, rho23, H_x, H_y
@@ -1103,7 +1049,13 @@ __global__ __launch_bounds__(kBlock) void k_rhs3(Geo G, Phys ph, int kc,
     if (c.act) {
       const int P = qo + pl * k;
       b[P] = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
-      dinv[P] = 1.0 / diag;
+      const double di = 1.0 / diag;
+      dinv[P] = di;
+      if (c32) {  // FP32 copies of the operator for the refined forms
+        c32[P] = (float)cP;
+        D32[P] = (float)Dc;
+        dinv32[P] = (float)di;
+      }
     }
   }
 }
@@ -1543,12 +1495,13 @@ void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, do
 
 void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                 const double* rho23, const double* psi, const double* c, const double* D,
-                double* const* H, double* b, double* dinv) {
+                double* const* H, double* b, double* dinv, float* c32, float* D32,
+                float* dinv32) {
   const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V2(H), b, dinv);
+    hipLaunchKernelGGL(k_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V2(H), b, dinv, c32, D32, dinv32);
   else
-    hipLaunchKernelGGL(k_rhs3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V3(H), b, dinv);
+    hipLaunchKernelGGL(k_rhs3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V3(H), b, dinv, c32, D32, dinv32);
 }
 
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,

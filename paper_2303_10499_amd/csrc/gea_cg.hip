@@ -66,10 +66,10 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
 }
 
 // store this workgroup's N sums at part[k * gridDim.x + blockIdx.x]
-template <int N>
+template <int N, int NT = kBlock>
 __device__ __forceinline__ void store_partials(double (&v)[N], double* __restrict__ part) {
-  __shared__ double sh[N][kBlock / 64];
-  Reducer<0u, N>::block(v, sh);
+  __shared__ double sh[N][NT / 64];
+  Reducer<0u, N, NT>::block(v, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < N; ++k) part[k * gridDim.x + blockIdx.x] = v[k];
@@ -594,18 +594,19 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
 // k_residual64 on a 3D mesh with the x/y neighbours of x and D staged in LDS
 // and the next plane's loads in flight while a plane is computed.  Same
 // formulas and order as k_residual64.
-__global__ __launch_bounds__(kBlock) void k_residual64_3(Geo G, Stencil<3, double> K,
+template <int TY>
+__global__ __launch_bounds__(64 * TY) void k_residual64_3(Geo G, Stencil<3, double> K,
                                                          const double* __restrict__ c,
                                                          const double* __restrict__ D,
                                                          const double* __restrict__ b,
                                                          const double* __restrict__ x,
                                                          CgVectors<float> v32, int kc,
                                                          double* o_part, double* i_part) {
-  using St = Stage3<1>;
+  using St = Stage3<1, TY>;
   constexpr int HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double sx[2][HP], sd[2][HP];
-  const Col col = col_of<3>(G, kc);
-  const St st = stage3<1>(G, col);
+  const Col col = col_of3<TY>(G, kc);
+  const St st = stage3<1, TY>(G, col);
   const int nz = G.nz, pl = col.pl, qo = st.qo, ho = st.ho;
   // raw values of the plane in flight
   double fx[NU], fd[NU], fb, fc, fxu, fdu;
@@ -671,8 +672,8 @@ __global__ __launch_bounds__(kBlock) void k_residual64_3(Geo G, Stencil<3, doubl
       ri[1] += (double)rf * (double)rf;
     }
   }
-  store_partials<2>(ro, o_part);
-  store_partials<2>(ri, i_part);
+  store_partials<2, 64 * TY>(ro, o_part);
+  store_partials<2, 64 * TY>(ri, i_part);
 }
 
 // one workgroup: outer stop test and the inner solver's setup
@@ -847,13 +848,14 @@ void launch_residual64(hipStream_t s, const Geo& G, const double* c, const doubl
                        const double* b, const double* x, const CgVectors<float>& v32,
                        double tol, double inner_tol, int inner_max, double* o_part,
                        const CgWork& w32, CgScalars* sc64) {
-  const ZPlan zp = zplan(G);
+  constexpr int TY = 8;  // 64x8 column tiles in 3D
+  const ZPlan zp = G.ndim == 2 ? zplan(G) : zplan3(G, TY);
   const int gu = zp.blocks;
   const dim3 grid(gu), block(kBlock);
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1]);
   else
-    hipLaunchKernelGGL(k_residual64_3, grid, block, 0, s, G, stencil<3, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1]);
+    hipLaunchKernelGGL(k_residual64_3<TY>, grid, dim3(64 * TY), 0, s, G, stencil<3, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1]);
   hipLaunchKernelGGL(k_residual_check, dim3(1), block, 0, s, (const double*)o_part,
                      (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, inner_max,
                      sc64, w32.sc);

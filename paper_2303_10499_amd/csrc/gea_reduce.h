@@ -27,9 +27,9 @@ __device__ __forceinline__ double combine(double a, double b) {
   return ((MAXMASK >> K) & 1u) ? fmax(a, b) : a + b;
 }
 
-template <unsigned MAXMASK, int N>
+template <unsigned MAXMASK, int N, int NT = kBlock>
 struct Reducer {
-  static constexpr int kWaves = kBlock / 64;
+  static constexpr int kWaves = NT / 64;
 
   // Result in v[] of thread 0 (and, after the call, of every thread via sh).
   __device__ static void block(double (&v)[N], double (*sh)[kWaves]) {
@@ -139,21 +139,39 @@ __device__ __forceinline__ Col col_of(const Geo& G, int kc) {
   return c;
 }
 
-// Plane staging of the 3D kernels: the workgroup's 64x4 column tile with a
-// halo of HW cells along x and y (HW = 2: 68x8 = 544 cells a plane, for the
-// fourth-order interpolation; HW = 1: 66x6 = 396).  Thread t stages its own
-// cell (slot 0) and halo cells t, 256 + t, ... (slots 1, 2, ...): the HW rows
-// below the tile, the HW rows above it, then the side columns.  Indices are
-// clamped into the mesh, so every staging load is unconditional and in
-// bounds; a staged value of a cell outside the mesh is only ever read into a
-// term that a wall test discards.
-template <int HW_>
+// Column tiles of the LDS-staged 3D kernels: 64 x TY cells, one thread (of
+// 64 TY) a column, the same block order as col_of.
+template <int TY>
+__device__ __forceinline__ Col col_of3(const Geo& G, int kc) {
+  constexpr int TX = 64;
+  const int ntx = (G.nx + TX - 1) / TX, nty = (G.ny + TY - 1) / TY;
+  const int b = xcd_block();
+  const int bx = b % ntx, by = (b / ntx) % nty, bk = b / (ntx * nty);
+  Col c;
+  c.i = bx * TX + (int)threadIdx.x % TX;
+  c.j = by * TY + (int)threadIdx.x / TX;
+  c.k0 = bk * kc;
+  c.k1 = min(c.k0 + kc, G.nz);
+  c.pl = G.st[2];
+  c.base = c.i + G.nx * c.j;
+  c.act = c.i < G.nx && c.j < G.ny && c.k0 < G.nz;
+  return c;
+}
+
+// Plane staging of the 3D kernels: the workgroup's 64 x TY column tile with
+// a halo of HW cells along x and y (64x4, HW = 2: 68x8 = 544 cells a plane,
+// for the fourth-order interpolation; HW = 1: 66x6 = 396).  Thread t stages
+// its own cell (slot 0) and halo cells t, NT + t, ... (slots 1, 2, ...): the
+// HW rows below the tile, the HW rows above it, then the side columns.
+// Indices are clamped into the mesh, so every staging load is unconditional
+// and in bounds; a staged value of a cell outside the mesh is only ever read
+// into a term that a wall test discards.
+template <int HW_, int TY_>
 struct Stage3 {
-  static constexpr int TX = ZTile<3>::TX, TY = ZTile<3>::TY, HW = HW_;
+  static constexpr int TX = 64, TY = TY_, HW = HW_, NT = TX * TY;
   static constexpr int HX = TX + 2 * HW, HY = TY + 2 * HW, HP = HX * HY;
-  static constexpr int NH = HP - TX * TY;                 // halo cells
-  static constexpr int NU = 1 + (NH + kBlock - 1) / kBlock;  // slots a thread
-  static_assert(TX * TY == kBlock, "one own cell a thread");
+  static constexpr int NH = HP - TX * TY;            // halo cells
+  static constexpr int NU = 1 + (NH + NT - 1) / NT;  // slots a thread
   int q[NU];     // cell index in plane 0 (clamped into the mesh)
   int h[NU];     // index in the staged plane
   bool has[NU];  // the thread stages a cell in this slot
@@ -163,9 +181,9 @@ struct Stage3 {
 
 __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
 
-template <int HW>
-__device__ __forceinline__ Stage3<HW> stage3(const Geo& G, const Col& c) {
-  using S = Stage3<HW>;
+template <int HW, int TY>
+__device__ __forceinline__ Stage3<HW, TY> stage3(const Geo& G, const Col& c) {
+  using S = Stage3<HW, TY>;
   S st;
   const int lx = (int)threadIdx.x % S::TX, ly = (int)threadIdx.x / S::TX;
   const int i0 = c.i - lx, j0 = c.j - ly;
@@ -176,7 +194,7 @@ __device__ __forceinline__ Stage3<HW> stage3(const Geo& G, const Col& c) {
   st.has[0] = true;
 #pragma unroll
   for (int m = 1; m < S::NU; ++m) {
-    int e = (int)threadIdx.x + (m - 1) * kBlock;
+    int e = (int)threadIdx.x + (m - 1) * S::NT;
     st.has[m] = e < S::NH;
     if (!st.has[m]) {  // no cell in this slot: load the own cell again, write nothing
       st.q[m] = st.qo;

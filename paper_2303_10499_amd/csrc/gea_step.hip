@@ -163,16 +163,17 @@ __global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
 // k_mass_flux on a 3D mesh with the x/y neighbourhoods of rho u_x and rho u_y
 // staged in LDS and the next plane's loads in flight while a plane is
 // computed.  Same formulas and order as k_mass_flux.
-__global__ __launch_bounds__(kBlock) void k_mass_flux3(Geo G, Phys ph, int kc,
+template <int TY>
+__global__ __launch_bounds__(64 * TY) void k_mass_flux3(Geo G, Phys ph, int kc,
                                                        const double* __restrict__ rho, Vec<3> u,
                                                        const double* __restrict__ T, Vec<3> phi,
                                                        double* __restrict__ rho_star,
                                                        double* __restrict__ e0) {
-  using St = Stage3<2>;
+  using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double sm[2][2][HP];  // rho u_x, rho u_y
-  const Col c = col_of<3>(G, kc);
-  const St st = stage3<2>(G, c);
+  const Col c = col_of3<TY>(G, kc);
+  const St st = stage3<2, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
   const double* uz = u.p[Z];
   auto mz = [&](int Q) { return rho[Q] * uz[Q]; };
@@ -346,16 +347,17 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
 // k_mom_predict on a 3D mesh with the x/y neighbourhoods of u, p' and rho
 // staged in LDS and the next plane's loads in flight while a plane is
 // computed.  Same formulas and order as k_mom_predict.
-__global__ __launch_bounds__(kBlock) void k_mom_predict3(Geo G, Phys ph, int kc,
+template <int TY>
+__global__ __launch_bounds__(64 * TY) void k_mom_predict3(Geo G, Phys ph, int kc,
                                                          const double* __restrict__ rho, Vec<3> u,
                                                          const double* __restrict__ pp,
                                                          const double* __restrict__ rho_star,
                                                          Vec<3> phi, Vec<3> u_star) {
-  using St = Stage3<2>;
+  using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double su[2][5][HP];  // u (3 components), p', rho
-  const Col c = col_of<3>(G, kc);
-  const St st = stage3<2>(G, c);
+  const Col c = col_of3<TY>(G, kc);
+  const St st = stage3<2, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
@@ -566,18 +568,19 @@ __global__ __launch_bounds__(kBlock) void k_energy_sweep(
 // k_energy_sweep on a 3D mesh with the x/y neighbourhoods of e and T staged
 // in LDS and the next plane's loads in flight while a plane is computed.
 // Same formulas and order as k_energy_sweep.
-__global__ __launch_bounds__(kBlock) void k_energy_sweep3(
+template <int TY>
+__global__ __launch_bounds__(64 * TY) void k_energy_sweep3(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
     const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<3> phi,
     const double* __restrict__ rho_star, Vec<3> u_star, const double* __restrict__ Tbg,
     double* __restrict__ e_next, double* __restrict__ T_next, int last,
     const double* __restrict__ p, double* __restrict__ rho23, double* __restrict__ psi,
     double* __restrict__ cc, double* __restrict__ D) {
-  using St = Stage3<2>;
+  using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double su[2][2][HP];  // e, T
-  const Col c = col_of<3>(G, kc);
-  const St st = stage3<2>(G, c);
+  const Col c = col_of3<TY>(G, kc);
+  const St st = stage3<2, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
@@ -769,14 +772,15 @@ __global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
 // k_H on a 3D mesh with the x/y neighbourhoods of u_prev staged in LDS: the
 // next plane's loads are in flight while a plane is computed from LDS and
 // registers.  Same formulas and order as k_H.  (168 VGPRs: 3 waves a SIMD.)
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_H3(Geo G, Phys ph, int kc,
+template <int TY>
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(3))) void k_H3(Geo G, Phys ph, int kc,
                                                const double* __restrict__ rho, Vec<3> u,
                                                Vec<3> u_prev, Vec<3> phi, Vec<3> H) {
-  using St = Stage3<2>;
+  using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double su[2][3][HP];
-  const Col c = col_of<3>(G, kc);
-  const St st = stage3<2>(G, c);
+  const Col c = col_of3<TY>(G, kc);
+  const St st = stage3<2, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo;
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
@@ -955,7 +959,8 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
 // k_rhs on a 3D mesh with the x/y neighbours of D, rho23, H_x and H_y staged
 // in LDS and the next plane's loads in flight while a plane is computed.
 // Same formulas and order as k_rhs.
-__global__ __launch_bounds__(kBlock) void k_rhs3(Geo G, Phys ph, int kc,
+template <int TY>
+__global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
                                                  const double* __restrict__ rho,
                                                  const double* __restrict__ rho23,
                                                  const double* __restrict__ psi,
@@ -964,11 +969,11 @@ __global__ __launch_bounds__(kBlock) void k_rhs3(Geo G, Phys ph, int kc,
                                                  double* __restrict__ b, double* __restrict__ dinv,
                                                  float* __restrict__ c32, float* __restrict__ D32,
                                                  float* __restrict__ dinv32) {
-  using St = Stage3<1>;
+  using St = Stage3<1, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double ss[2][4][HP];  // D, rho23, H_x, H_y
-  const Col c = col_of<3>(G, kc);
-  const St st = stage3<1>(G, c);
+  const Col c = col_of3<TY>(G, kc);
+  const St st = stage3<1, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
   const double kz_ = G.S[Z] / G.h[Z];
   // raw values of the plane in flight
@@ -1189,18 +1194,18 @@ __global__ __launch_bounds__(kBlock) void k_correct(
 // k_correct on a 3D mesh with the x/y neighbours of p' and rho23 (and, on the
 // last corrector, D, H_x and H_y) staged in LDS and the next plane's loads in
 // flight while a plane is computed.  Same formulas and order as k_correct.
-template <bool LAST>
-__global__ __launch_bounds__(kBlock) void k_correct3(
+template <bool LAST, int TY>
+__global__ __launch_bounds__(64 * TY) void k_correct3(
     Geo G, Phys ph, int kc, const double* __restrict__ pp, const double* __restrict__ rho23,
     const double* __restrict__ psi, Vec<3> H, const double* __restrict__ D,
     const double* __restrict__ rho_star, Vec<3> u_out, const double* __restrict__ rho_old,
     double* __restrict__ rho_new, double* __restrict__ p_new, double* partials) {
-  using St = Stage3<1>;
+  using St = Stage3<1, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   constexpr int NF = LAST ? 5 : 2;
   __shared__ double ss[2][NF][HP];  // p', rho23 (, D, H_x, H_y)
-  const Col c = col_of<3>(G, kc);
-  const St st = stage3<1>(G, c);
+  const Col c = col_of3<TY>(G, kc);
+  const St st = stage3<1, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
   const double kz_ = G.S[Z] / G.h[Z];
   // raw values of the plane in flight
@@ -1329,8 +1334,8 @@ __global__ __launch_bounds__(kBlock) void k_correct3(
     if (c.act) red[2] += finite ? 0.0 : 1.0;
   }
   if (!LAST) return;
-  __shared__ double sh[3][kBlock / 64];
-  Reducer<0x2u, 3>::block(red, sh);
+  __shared__ double sh[3][TY];
+  Reducer<0x2u, 3, 64 * TY>::block(red, sh);
   if (threadIdx.x == 0)
     for (int k = 0; k < 3; ++k) partials[k * gridDim.x + blockIdx.x] = red[k];
 }
@@ -1449,27 +1454,48 @@ ZPlan zplan_t(const Geo& G) {
 
 ZPlan zplan(const Geo& G) { return G.ndim == 2 ? zplan_t<2>(G) : zplan_t<3>(G); }
 
+ZPlan zplan3(const Geo& G, int ty) {
+  const int cols = ((G.nx + 63) / 64) * ((G.ny + ty - 1) / ty), nz = G.nz;
+  int kc = ZTile<3>::KC < nz ? ZTile<3>::KC : nz;
+  int nk = (nz + kc - 1) / kc;
+  const int maxk = kMaxZBlocks / cols > 1 ? kMaxZBlocks / cols : 1;
+  if (nk > maxk) {
+    kc = (nz + maxk - 1) / maxk;
+    nk = (nz + kc - 1) / kc;
+  }
+  return ZPlan{kc, cols * nk};
+}
+
+namespace {
+
+// rows of the column tiles of the LDS-staged 3D step kernels (taller tiles
+// re-read fewer halo rows; the two kernels with the most registers keep
+// 64x4 for occupancy)
+constexpr int kTyMass = 8, kTyMom = 4, kTyEnergy = 8, kTyH = 4, kTyRhs = 8, kTyCorr = 8;
+
+}  // namespace
+
 #define V2(a) vec<2>(a)
 #define V3(a) vec<3>(a)
 
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                       double* const* u, const double* T, double* const* phi, double* rho_star,
                       double* e0) {
-  const ZPlan zp = zplan(G);
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMass) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
   else
-    hipLaunchKernelGGL(k_mass_flux3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), T, V3(phi), rho_star, e0);
+    hipLaunchKernelGGL(k_mass_flux3<kTyMass>, dim3(zp3.blocks), dim3(64 * kTyMass), 0, s, G, ph, zp3.kc, rho, V3(u), T, V3(phi), rho_star, e0);
 }
 
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                         double* const* u, const double* pp, const double* rho_star,
                         double* const* phi, double* const* u_star) {
-  const ZPlan zp = zplan(G);
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMom) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star));
   else
-    hipLaunchKernelGGL(k_mom_predict3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star));
+    hipLaunchKernelGGL(k_mom_predict3<kTyMom>, dim3(zp3.blocks), dim3(64 * kTyMom), 0, s, G, ph, zp3.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star));
 }
 
 void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
@@ -1477,31 +1503,31 @@ void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const doub
                          double* const* phi, const double* rho_star, double* const* u_star,
                          const double* Tbg, double* e_next, double* T_next, bool last,
                          const double* p, double* rho23, double* psi, double* c, double* D) {
-  const ZPlan zp = zplan(G);
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_energy_sweep<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
   else
-    hipLaunchKernelGGL(k_energy_sweep3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
+    hipLaunchKernelGGL(k_energy_sweep3<kTyEnergy>, dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
 }
 
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,
               double* const* u_prev, double* const* phi, double* const* H) {
-  const ZPlan zp = zplan(G);
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyH) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_H<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), V2(u_prev), V2(phi), V2(H));
   else
-    hipLaunchKernelGGL(k_H3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V3(u), V3(u_prev), V3(phi), V3(H));
+    hipLaunchKernelGGL(k_H3<kTyH>, dim3(zp3.blocks), dim3(64 * kTyH), 0, s, G, ph, zp3.kc, rho, V3(u), V3(u_prev), V3(phi), V3(H));
 }
 
 void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                 const double* rho23, const double* psi, const double* c, const double* D,
                 double* const* H, double* b, double* dinv, float* c32, float* D32,
                 float* dinv32) {
-  const ZPlan zp = zplan(G);
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyRhs) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V2(H), b, dinv, c32, D32, dinv32);
   else
-    hipLaunchKernelGGL(k_rhs3, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V3(H), b, dinv, c32, D32, dinv32);
+    hipLaunchKernelGGL(k_rhs3<kTyRhs>, dim3(zp3.blocks), dim3(64 * kTyRhs), 0, s, G, ph, zp3.kc, rho, rho23, psi, c, D, V3(H), b, dinv, c32, D32, dinv32);
 }
 
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
@@ -1509,15 +1535,15 @@ void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* p
                     const double* rho_star, double* const* u_out, bool last,
                     const double* rho_old, double* rho_new, double* p_new, double* partials,
                     CgScalars* sc) {
-  const ZPlan zp = zplan(G);
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyCorr) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_correct<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V2(H), D, rho_star, V2(u_out), (int)last, rho_old, rho_new, p_new, partials);
   else if (last)
-    hipLaunchKernelGGL(k_correct3<true>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, partials);
+    hipLaunchKernelGGL((k_correct3<true, kTyCorr>), dim3(zp3.blocks), dim3(64 * kTyCorr), 0, s, G, ph, zp3.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, partials);
   else
-    hipLaunchKernelGGL(k_correct3<false>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, partials);
+    hipLaunchKernelGGL((k_correct3<false, kTyCorr>), dim3(zp3.blocks), dim3(64 * kTyCorr), 0, s, G, ph, zp3.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, partials);
   if (last)
-    hipLaunchKernelGGL(k_finalize_reduce, dim3(1), dim3(kBlock), 0, s, (const double*)partials, zp.blocks, sc);
+    hipLaunchKernelGGL(k_finalize_reduce, dim3(1), dim3(kBlock), 0, s, (const double*)partials, zp3.blocks, sc);
 }
 
 void launch_init_column(hipStream_t s, const Geo& G, const Phys& ph, double* rho_a,

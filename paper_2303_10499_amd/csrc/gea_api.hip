@@ -302,7 +302,7 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->pair_s = cv.take<double>(2);
   x->fsc = cv.take<FcgScalars>(1);
   x->fv.part_d = cv.take<double>(2 * 2048);
-  x->fv.part_s = cv.take<double>(2048);
+  x->fv.part_s = cv.take<double>(2 * (size_t)std::max(2048, zplan(make_geo(m)).blocks));
   x->fv.part_u = cv.take<double>(2 * 2048);
   // the network (inference buffers) only for the learned form on a mesh whose
   // dimensions are multiples of 4
@@ -558,8 +558,10 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
 // `steps` iterations and returns how many it enqueued.  The host reads the
 // flexible-CG scalars only between iterations, never after the last one:
 // the caller reads them with its next read of the solver scalars.  (After
-// the stop decision the iteration kernels return at once.)
-int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps) {
+// the stop decision the iteration kernels return at once.)  When the last
+// iteration enqueued was the last allowed, it also formed the partials of
+// the resumed Jacobi-PCG's set-up: *res_parts is their count, else 0.
+int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps, int* res_parts) {
   const Geo& G = x->G;
   FcgVectors& v = x->fv;
   v.d = x->d32;
@@ -571,6 +573,9 @@ int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps
   v.q = x->q32;
   v.c = x->c32;
   v.D = x->D32;
+  v.dinv = x->dinv32;
+  v.p_cg = x->p032;
+  *res_parts = 0;
   x->timer.run(4, x->stream, [&] {
     fcg_start(x->stream, G, v, bb, inner_tol, budget, x->fsc);
   });
@@ -588,7 +593,11 @@ int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps
       cnn_forward(x->net);
       cnn_scale_output(x->net, &x->fsc->s, x->z32, 0);
     });
-    x->timer.run(2, x->stream, [&] { fcg_iteration_after_z(x->stream, G, v, it, x->fsc); });
+    const bool last = it + 1 == cap;
+    x->timer.run(2, x->stream, [&] {
+      const int n = fcg_iteration_after_z(x->stream, G, v, it, last, x->fsc);
+      if (last) *res_parts = n;
+    });
     HIPCHK(hipGetLastError());
     ++it;
   }
@@ -645,8 +654,9 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       // same adaptive inner tolerance as the refinement residual kernel sets
       const double need = 0.1 * std::sqrt(x->prm.tol * x->prm.tol * h64.bb / h64.rr);
       const double itol = std::max(x->prm.inner_tol, std::min(0.5, need));
+      int res_parts = 0;
       const int launched = learned_inner(x, h32.bb, itol, budget > 0 ? budget : 1,
-                                         x->prm.learned_steps);
+                                         x->prm.learned_steps, &res_parts);
       use_net = false;
       // Jacobi-PCG continues the same inner solve from the flexible-CG
       // iterate and residual, enqueued behind it unread: when the flexible
@@ -654,7 +664,12 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       // kernels return at once.  Its first batch is the previous resumed
       // solve's length and two more.
       const int left = budget - launched;
-      x->timer.run(4, x->stream, [&] { cg_resume(x->stream, G, v, w, left > 0 ? left : 0); });
+      x->timer.run(4, x->stream, [&] {
+        if (res_parts > 0)
+          cg_resume_scalars(x->stream, x->fv.part_d, res_parts, w, left > 0 ? left : 0);
+        else
+          cg_resume(x->stream, G, v, w, left > 0 ? left : 0);
+      });
       h32 = CgScalars{};
       fcg = Extra{x->fsc, &hf, sizeof hf};
       first = x->last_iters_res > 0 ? x->last_iters_res + 2 : 0;

@@ -869,6 +869,10 @@ void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgW
                      w.sc);
 }
 
+void cg_resume_scalars(hipStream_t s, const double* part, int n, const CgWork& w, int max_iter) {
+  hipLaunchKernelGGL(k_cg_resume_start, dim3(1), dim3(kBlock), 0, s, part, n, max_iter, w.sc);
+}
+
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,
                         const double* dinv, float* c32, float* D32, float* dinv32) {
   hipLaunchKernelGGL(k_cast_coeffs, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, c, D, dinv, c32, D32, dinv32);

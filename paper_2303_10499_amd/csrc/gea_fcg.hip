@@ -51,29 +51,35 @@ __device__ __forceinline__ double sum_part(const double* part, int n, int k) {
 }
 
 // beta from the dot partials; p = z + beta p_old; q = A p; partial <p, q>.
-// Cache-only stencil (the learned form's cost is dominated by the network).
-template <int NDIM>
+// Iteration 0 (ITER0): p = z (beta = 0, no previous direction), and the
+// partials also carry <z, r> (no dot kernel before it); p is stored only for
+// a later iteration (keep_p).  Cache-only stencil, used on 2D meshes.
+template <int NDIM, bool ITER0>
 __global__ __launch_bounds__(kBlock) void k_fcg_spmv(Geo G, int iter, const float* __restrict__ z,
                                                      const float* __restrict__ p_old,
                                                      float* __restrict__ p_new,
                                                      float* __restrict__ q,
                                                      const float* __restrict__ c,
                                                      const float* __restrict__ D,
+                                                     const float* __restrict__ r, int keep_p,
                                                      const double* dots, int nd, double* part,
                                                      FcgScalars* sc) {
   if (sc->done) return;
-  const double zr = sum_part(dots, nd, 0);
-  const double zro = sum_part(dots, nd, 1);
-  const double beta_d = iter == 0 ? 0.0 : (zr - zro) / sc->rz_prev[(iter + 1) & 1];
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->rz_prev[iter & 1] = zr;
-  const float beta = (float)beta_d;
+  float beta = 0.f;
+  if (!ITER0) {
+    const double zr = sum_part(dots, nd, 0);
+    const double zro = sum_part(dots, nd, 1);
+    const double beta_d = (zr - zro) / sc->rz_prev[(iter + 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->rz_prev[iter & 1] = zr;
+    beta = (float)beta_d;
+  }
   float kk[NDIM];
   for (int d = 0; d < NDIM; ++d) kk[d] = (float)(G.S[d] / G.h[d]);
-  double acc[1] = {0.0};
+  double acc[2] = {0.0, 0.0};
   GEA_FOR_CELLS(P, G) {
     int cc[NDIM];
     cell_coords<NDIM>(G, P, cc);
-    auto pn = [&](int Q) { return z[Q] + beta * p_old[Q]; };
+    auto pn = [&](int Q) { return ITER0 ? z[Q] : z[Q] + beta * p_old[Q]; };
     const float pp = pn(P), dp = D[P];
     float a = c[P] * pp;
 #pragma unroll
@@ -82,51 +88,191 @@ __global__ __launch_bounds__(kBlock) void k_fcg_spmv(Geo G, int iter, const floa
       if (cc[d] + 1 < G.n[d]) a += 0.5f * (dp + D[P + st]) * kk[d] * (pp - pn(P + st));
       if (cc[d] > 0) a += 0.5f * (D[P - st] + dp) * kk[d] * (pp - pn(P - st));
     }
-    p_new[P] = pp;
+    if (keep_p) p_new[P] = pp;
     q[P] = a;
     acc[0] += (double)pp * (double)a;
+    if (ITER0) acc[1] += (double)pp * (double)r[P];
   }
-  store_part<1>(acc, part);
+  if (ITER0) {
+    store_part<2>(acc, part);
+  } else {
+    double pq[1] = {acc[0]};
+    store_part<1>(pq, part);
+  }
+}
+
+// k_fcg_spmv on a 3D mesh: 64x4 column tiles marching in z with the new
+// direction formed on the tile and a one-cell halo in LDS, the next plane's
+// loads in flight while a plane is computed.  Same formulas and order.
+template <bool ITER0>
+__global__ __launch_bounds__(kBlock) void k_fcg_spmv3(Geo G, int kc, int iter,
+                                                      const float* __restrict__ z,
+                                                      const float* __restrict__ p_old,
+                                                      float* __restrict__ p_new,
+                                                      float* __restrict__ q,
+                                                      const float* __restrict__ c,
+                                                      const float* __restrict__ D,
+                                                      const float* __restrict__ r, int keep_p,
+                                                      const double* dots, int nd, double* part,
+                                                      FcgScalars* sc) {
+  using St = Stage3<1, 4>;
+  constexpr int HP = St::HP, HX = St::HX, NU = St::NU;
+  __shared__ float sp[2][HP], sd[2][HP];
+  if (sc->done) return;
+  float beta = 0.f;
+  if (!ITER0) {
+    const double zr = sum_part(dots, nd, 0);
+    const double zro = sum_part(dots, nd, 1);
+    const double beta_d = (zr - zro) / sc->rz_prev[(iter + 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->rz_prev[iter & 1] = zr;
+    beta = (float)beta_d;
+  }
+  const float kx = (float)(G.S[0] / G.h[0]), ky = (float)(G.S[1] / G.h[1]),
+              kz = (float)(G.S[2] / G.h[2]);
+  const Col col = col_of3<4>(G, kc);
+  const St st = stage3<1, 4>(G, col);
+  const int nz = G.nz, pl = col.pl, qo = st.qo, ho = st.ho;
+  // raw values of the plane in flight: staged z (and p_old), D; own c, r and
+  // the own column's direction and D one plane up
+  float fz[NU], fo[NU], fd[NU], fc, fr, fzu, fou, fdu;
+  auto fetch = [&](int kk) {
+    const int o = pl * kk, P = qo + o;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int Q = st.q[m] + o;
+      fz[m] = z[Q];
+      fo[m] = ITER0 ? 0.f : p_old[Q];
+      fd[m] = D[Q];
+    }
+    const int Pu = kk + 1 < nz ? P + pl : P;
+    fc = c[P];
+    fr = ITER0 ? r[P] : 0.f;
+    fzu = z[Pu];
+    fou = ITER0 ? 0.f : p_old[Pu];
+    fdu = D[Pu];
+  };
+  auto pn = [&](float zv, float ov) { return ITER0 ? zv : zv + beta * ov; };
+  double acc[2] = {0.0, 0.0};
+  float pm = 0.f, dm = 0.f;  // direction and D one plane down
+  if (col.k0 > 0) {
+    const int Q = qo + pl * (col.k0 - 1);
+    pm = pn(z[Q], ITER0 ? 0.f : p_old[Q]);
+    dm = D[Q];
+  }
+  fetch(col.k0);
+  for (int k = col.k0; k < col.k1; ++k) {
+    const int sl = k & 1;
+#pragma unroll
+    for (int m = 0; m < NU; ++m)
+      if (st.has[m]) {
+        sp[sl][st.h[m]] = pn(fz[m], fo[m]);
+        sd[sl][st.h[m]] = fd[m];
+      }
+    const float cP = fc, rP = fr, pu = pn(fzu, fou), du = fdu;
+    fetch(k + 1 < col.k1 ? k + 1 : k);
+    lds_barrier();
+    const float pp = sp[sl][ho], dp = sd[sl][ho];
+    float a = cP * pp;
+    const int i = col.i, j = col.j;
+    if (i + 1 < G.nx) a += 0.5f * (dp + sd[sl][ho + 1]) * kx * (pp - sp[sl][ho + 1]);
+    if (i > 0) a += 0.5f * (sd[sl][ho - 1] + dp) * kx * (pp - sp[sl][ho - 1]);
+    if (j + 1 < G.ny) a += 0.5f * (dp + sd[sl][ho + HX]) * ky * (pp - sp[sl][ho + HX]);
+    if (j > 0) a += 0.5f * (sd[sl][ho - HX] + dp) * ky * (pp - sp[sl][ho - HX]);
+    if (k + 1 < nz) a += 0.5f * (dp + du) * kz * (pp - pu);
+    if (k > 0) a += 0.5f * (dm + dp) * kz * (pp - pm);
+    pm = pp;
+    dm = dp;
+    if (col.act) {
+      const int P = qo + pl * k;
+      if (keep_p) p_new[P] = pp;
+      q[P] = a;
+      acc[0] += (double)pp * (double)a;
+      if (ITER0) acc[1] += (double)pp * (double)rP;
+    }
+  }
+  if (ITER0) {
+    store_part<2>(acc, part);
+  } else {
+    double pq[1] = {acc[0]};
+    store_part<1>(pq, part);
+  }
 }
 
 // alpha = <z, r>/<p, q>; d += alpha p, r_old = r, r -= alpha q;
-// partials ||r||^2 and max |r| (as a sum of per-workgroup maxima stored apart)
+// partials ||r||^2 and max |r| (as a sum of per-workgroup maxima stored apart).
+// Iteration 0 (ITER0): p = z, <z, r> from the direction kernel's partials,
+// and d = alpha p (d needs no clearing; it is cleared here when the solve has
+// already stopped).  The last iteration (LAST) keeps no r_old and also sets
+// up the Jacobi-PCG that resumes the solve: its first direction p_cg = 0 and
+// the partials <r, r/diag>, <r, r> of the residual it starts from (also when
+// the solve had stopped before this iteration).
+template <bool ITER0, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* __restrict__ d,
-                                                       const float* __restrict__ p,
+                                                       const float* p,
                                                        float* __restrict__ r,
                                                        float* __restrict__ r_old,
                                                        const float* __restrict__ q,
                                                        const double* pq_part, int np,
-                                                       double* part, FcgScalars* sc) {
-  if (sc->done) return;
-  const double pq = sum_part(pq_part, np, 0);
-  const double alpha_d = sc->rz_prev[iter & 1] / pq;
-  if (!isfinite(alpha_d) || alpha_d == 0.0) {
-    // no usable step (e.g. a network that outputs nothing): stop as stalled,
-    // leaving d and r untouched; every workgroup takes this same branch
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->status = 1;
-      sc->done = 1;
+                                                       double* part, FcgScalars* sc,
+                                                       const float* __restrict__ dinv,
+                                                       float* p_cg,  // may be p's buffer
+                                                       double* res_part) {
+  bool step = !sc->done;
+  float alpha = 0.f;
+  if (step) {
+    const double pq = sum_part(pq_part, np, 0);
+    double zr = sc->rz_prev[iter & 1];
+    if (ITER0) {
+      zr = sum_part(pq_part, np, 1);
+      if (blockIdx.x == 0 && threadIdx.x == 0) sc->rz_prev[0] = zr;
     }
-    return;
+    const double alpha_d = zr / pq;
+    if (!isfinite(alpha_d) || alpha_d == 0.0) {
+      // no usable step (e.g. a network that outputs nothing): stop as stalled,
+      // leaving d and r untouched; every workgroup takes this same branch
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->status = 1;
+        sc->done = 1;
+      }
+      step = false;
+    }
+    alpha = (float)alpha_d;
   }
-  const float alpha = (float)alpha_d;
+  if (!step && !ITER0 && !LAST) return;
   __shared__ double sh[2][kBlock / 64];
   double v[2] = {0.0, 0.0};
+  double w[2] = {0.0, 0.0};
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
-    d[P] += alpha * p[P];
-    const float ro = r[P];
-    r_old[P] = ro;
-    const float rn = ro - alpha * q[P];
-    r[P] = rn;
-    v[0] += (double)rn * (double)rn;
-    v[1] = fmax(v[1], fabs((double)rn));
+    float rn = r[P];
+    if (step) {
+      if (ITER0)
+        d[P] = alpha * p[P];
+      else
+        d[P] += alpha * p[P];
+      const float ro = rn;
+      if (!LAST) r_old[P] = ro;
+      rn = ro - alpha * q[P];
+      r[P] = rn;
+      v[0] += (double)rn * (double)rn;
+      v[1] = fmax(v[1], fabs((double)rn));
+    } else if (ITER0) {
+      d[P] = 0.f;
+    }
+    if (LAST) {
+      p_cg[P] = 0.f;
+      const double rd = (double)rn;
+      w[0] += rd * (double)(rn * dinv[P]);
+      w[1] += rd * rd;
+    }
   }
-  Reducer<0x2u, 2>::block(v, sh);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = v[0];
-    part[gridDim.x + blockIdx.x] = v[1];
+  if (step) {
+    Reducer<0x2u, 2>::block(v, sh);
+    if (threadIdx.x == 0) {
+      part[blockIdx.x] = v[0];
+      part[gridDim.x + blockIdx.x] = v[1];
+    }
   }
+  if (LAST) store_part<2>(w, res_part);
 }
 
 // One workgroup: ||r||^2 and max |r| from the update partials (or from the
@@ -173,18 +319,14 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
   sc->done = done;
 }
 
-// inner start: d = 0, p_old = 0, r_old = 0; r (= r32) already set by the
-// refinement residual; partials ||r||^2 and max |r|
-__global__ __launch_bounds__(kBlock) void k_fcg_start(int n, float* __restrict__ d,
-                                                      float* __restrict__ p0,
-                                                      float* __restrict__ r_old,
-                                                      const float* __restrict__ r, double* part) {
+// inner start: partials ||r||^2 and max |r| of r (= r32, set by the
+// refinement residual).  d, the direction and r_old need no clearing: the
+// first iteration writes d and reads neither of the others.
+__global__ __launch_bounds__(kBlock) void k_fcg_start(int n, const float* __restrict__ r,
+                                                      double* part) {
   __shared__ double sh[2][kBlock / 64];
   double v[2] = {0.0, 0.0};
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
-    d[P] = 0.f;
-    p0[P] = 0.f;
-    r_old[P] = 0.f;
     const double rv = r[P];
     v[0] += rv * rv;
     v[1] = fmax(v[1], fabs(rv));
@@ -240,30 +382,56 @@ __global__ __launch_bounds__(kBlock) void k_pair(int n, const double* __restrict
 void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, double bb, double tol,
                int max_iter, FcgScalars* sc) {
   const int gu = grid_for(G.nc);
-  hipLaunchKernelGGL(k_fcg_start, dim3(gu), dim3(kBlock), 0, s, G.nc, v.d, v.p0, v.r_old,
-                     (const float*)v.r, v.part_u);
+  hipLaunchKernelGGL(k_fcg_start, dim3(gu), dim3(kBlock), 0, s, G.nc, (const float*)v.r, v.part_u);
   hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(kBlock), 0, s, (const double*)v.part_u, gu, 0, 1,
                      bb, tol * tol, max_iter, sc);
 }
 
-void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter,
-                           FcgScalars* sc) {
+int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
+                          FcgScalars* sc) {
   const int gu = grid_for(G.nc);
   const dim3 gr(gu), bl(kBlock);
-  hipLaunchKernelGGL(k_fcg_dots, gr, bl, 0, s, G.nc, (const float*)v.z, (const float*)v.r,
-                     (const float*)v.r_old, v.part_d, (const FcgScalars*)sc);
+  const bool it0 = iter == 0;
+  if (!it0)
+    hipLaunchKernelGGL(k_fcg_dots, gr, bl, 0, s, G.nc, (const float*)v.z, (const float*)v.r,
+                       (const float*)v.r_old, v.part_d, (const FcgScalars*)sc);
   const float* p_old = (iter & 1) ? v.p1 : v.p0;
   float* p_new = (iter & 1) ? v.p0 : v.p1;
-  if (G.ndim == 2)
-    hipLaunchKernelGGL(k_fcg_spmv<2>, gr, bl, 0, s, G, iter, (const float*)v.z, p_old, p_new, v.q,
-                       v.c, v.D, (const double*)v.part_d, gu, v.part_s, sc);
-  else
-    hipLaunchKernelGGL(k_fcg_spmv<3>, gr, bl, 0, s, G, iter, (const float*)v.z, p_old, p_new, v.q,
-                       v.c, v.D, (const double*)v.part_d, gu, v.part_s, sc);
-  hipLaunchKernelGGL(k_fcg_update, gr, bl, 0, s, G.nc, iter, v.d, (const float*)p_new, v.r,
-                     v.r_old, (const float*)v.q, (const double*)v.part_s, gu, v.part_u, sc);
+  // iteration 0's direction is z itself: stored only for a later iteration
+  const int keep_p = !(it0 && last);
+  const float* p_upd = keep_p ? p_new : v.z;
+  int ns = gu;  // partials of the direction kernel
+  if (G.ndim == 2) {
+    if (it0)
+      hipLaunchKernelGGL((k_fcg_spmv<2, true>), gr, bl, 0, s, G, iter, (const float*)v.z, p_old, p_new, v.q,
+                         v.c, v.D, (const float*)v.r, keep_p, (const double*)v.part_d, gu, v.part_s, sc);
+    else
+      hipLaunchKernelGGL((k_fcg_spmv<2, false>), gr, bl, 0, s, G, iter, (const float*)v.z, p_old, p_new, v.q,
+                         v.c, v.D, (const float*)v.r, keep_p, (const double*)v.part_d, gu, v.part_s, sc);
+  } else {
+    const ZPlan zp = zplan3(G, 4);
+    ns = zp.blocks;
+    if (it0)
+      hipLaunchKernelGGL(k_fcg_spmv3<true>, dim3(zp.blocks), bl, 0, s, G, zp.kc, iter, (const float*)v.z, p_old,
+                         p_new, v.q, v.c, v.D, (const float*)v.r, keep_p, (const double*)v.part_d, gu,
+                         v.part_s, sc);
+    else
+      hipLaunchKernelGGL(k_fcg_spmv3<false>, dim3(zp.blocks), bl, 0, s, G, zp.kc, iter, (const float*)v.z, p_old,
+                         p_new, v.q, v.c, v.D, (const float*)v.r, keep_p, (const double*)v.part_d, gu,
+                         v.part_s, sc);
+  }
+#define GEA_UPD(I0, L)                                                                          \
+  hipLaunchKernelGGL((k_fcg_update<I0, L>), gr, bl, 0, s, G.nc, iter, v.d, p_upd, v.r, v.r_old, \
+                     (const float*)v.q, (const double*)v.part_s, ns, v.part_u, sc, v.dinv,       \
+                     v.p_cg, v.part_d)
+  if (it0 && last) GEA_UPD(true, true);
+  else if (it0) GEA_UPD(true, false);
+  else if (last) GEA_UPD(false, true);
+  else GEA_UPD(false, false);
+#undef GEA_UPD
   hipLaunchKernelGGL(k_fcg_check, dim3(1), bl, 0, s, (const double*)v.part_u, gu, iter + 1, 0, 0.0,
                      0.0, 0, sc);
+  return gu;
 }
 
 void pair_outputs(hipStream_t s, const Geo& G, const double* r0, const double* c,

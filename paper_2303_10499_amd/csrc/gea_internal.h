@@ -157,6 +157,8 @@ void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w);
 // residual (v.x, v.r), keeping the set-up's ||b||^2 and tolerance; then
 // cg_iter_kernel / cg_scalars from iteration 0
 void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter);
+// the resume's scalars from 2 x n partials <r, r/diag>, <r, r> already formed
+void cg_resume_scalars(hipStream_t s, const double* part, int n, const CgWork& w, int max_iter);
 void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,
                     const double* x, double* y);
 
@@ -186,14 +188,19 @@ struct FcgScalars {
 struct FcgVectors {
   float *d, *r, *r_old, *z, *p0, *p1, *q;
   const float *c, *D;
+  const float* dinv;  // 1/diag, for the resumed Jacobi-PCG's set-up
+  float* p_cg;        // the resumed Jacobi-PCG's first direction buffer
   double *part_d, *part_s, *part_u;
 };
 
 void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, double bb, double tol,
                int max_iter, FcgScalars* sc);
-// one iteration once z = M(r) is in v.z: dots, direction + operator, update, check
-void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter,
-                           FcgScalars* sc);
+// one iteration once z = M(r) is in v.z: dots, direction + operator, update,
+// check.  The last one (last) also sets up the Jacobi-PCG that resumes the
+// solve: p_cg = 0 and 2 x n partials <r, r/diag>, <r, r> in v.part_d, n the
+// returned count (then cg_resume_scalars finishes the set-up).
+int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
+                          FcgScalars* sc);
 // training pair: s = max |r0| (s_out[0], 1/s in s_out[1]); in_r = r0/s,
 // in_a = c/diag, out_d = (x - x0)/s
 void pair_outputs(hipStream_t s, const Geo& G, const double* r0, const double* c,

@@ -276,3 +276,41 @@ def test_trained_network_gain(learned, name):
     # while training crops were each scaled to their own maximum; the network
     # (with biases, so not scale-equivariant) predicts nothing useful there
     # and the solve relies on the Jacobi-PCG iterations (no gain, no loss)
+
+
+@pytest.mark.parametrize("name,dims,steps", [
+    ("bubble3d_256x256x128", (72, 24, 20), 1),
+    ("bubble3d_256x256x128", (72, 24, 20), 2),   # last flexible-CG iteration odd
+    ("bubble3d_256x256x128", (72, 24, 20), 3),
+    ("nonsmooth2d_2048", (160, 128, None), 2),
+])
+def test_learned_steps_converge_to_the_mixed_solution(learned, name, dims, steps):
+    """The learned form with 1-3 network-preconditioned flexible-CG
+    iterations before Jacobi-PCG resumes: every solve reaches the tolerance
+    (checked on the FP64 residual), and the state after two steps agrees with
+    the refinement's: both pressure solutions have relative residual <= 1e-10,
+    so they differ by at most cond(A) * 1e-10 relative, below 1e-6 for the
+    small meshes here (cond(A) < 1e4), and the other fields follow p'."""
+    from paper_2303_10499_amd import gea
+    nx, nz, ny = dims
+    states = {}
+    for form in ("mixed", "learned"):
+        cfg = configs.scaled(name, nx, nz, ny)
+        cfg["params"].update(tol=1e-10, inner_tol=1e-4, max_iter=100000, learned_steps=steps)
+        S = gea.Solver(cfg["mesh"], cfg["params"], solver=form)
+        if form == "learned":
+            S.load_weights()
+        S.init_bubble(**cfg["bubble"])
+        st = S.step(2)
+        for k in range(st.n_solves):
+            assert st.solve[k].status == 0
+            assert st.solve[k].rel_res <= 1e-10
+        states[form] = S.state()
+        S.close()
+    for f in ("rho", "T", "pp", "p"):
+        a, b = states["learned"][f], states["mixed"][f]
+        print(f, float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+        assert np.max(np.abs(a - b)) <= 1e-6 * np.max(np.abs(b)), f
+    u_a, u_b = states["learned"]["u"], states["mixed"]["u"]
+    print("u", float(np.max(np.abs(u_a - u_b)) / np.max(np.abs(u_b))))
+    assert np.max(np.abs(u_a - u_b)) <= 1e-5 * np.max(np.abs(u_b))

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -193,6 +194,22 @@ struct gea_ctx {
   bool has_state = false;
   bool has_system = false;
   bool sys32 = false;  // c32, D32, dinv32 hold the current operator
+  // Work that follows a converged solve (the corrector's correction),
+  // enqueued by the refined forms right behind an outer residual check that
+  // the previous step's same check found converged, before the host reads
+  // it; when that read says otherwise the tail is enqueued again after the
+  // solve (it reads nothing the solve writes).
+  const std::function<void()>* tail = nullptr;
+  bool tail_done = false;   // the tail ran behind the final residual check
+  CgScalars last_h64{};     // the FP64 scalars as the last outer residual check read them
+  int corr = 0;             // corrector of the solve in progress
+  bool conv_hist[8][4] = {};  // [corrector][outer step]: that check converged last time
+  bool predict_conv(int outer) const {
+    return tail && corr < 8 && conv_hist[corr][outer < 3 ? outer : 3];
+  }
+  void note_conv(int outer, bool c) {
+    if (corr < 8) conv_hist[corr][outer < 3 ? outer : 3] = c;
+  }
   std::string err;
   // pinned host buffer the solver scalars are read through (device-to-host
   // copies into it are asynchronous, so several go out with one wait)
@@ -282,8 +299,10 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
     x->partials = cv.take<double>(zb > kMaxPartials ? zb : kMaxPartials);
   }
   x->o_part = cv.take<double>(kMaxPartials);
+  // the solver scalars side by side, 256 bytes apart: a poll copies them in one piece
   x->sc = cv.take<CgScalars>(1);
   x->sc32 = cv.take<CgScalars>(1);
+  x->fsc = cv.take<FcgScalars>(1);
   // partials: 7 per workgroup of the iteration kernel's grid; 2 (and 1 for
   // ||b||^2) per workgroup of the set-up kernels' column-tile grid
   const int ns = iter_grid(make_geo(m));
@@ -300,7 +319,6 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->z32 = cv.take<float>(nc);
   x->pair_part = cv.take<double>(3 * 2048);
   x->pair_s = cv.take<double>(2);
-  x->fsc = cv.take<FcgScalars>(1);
   x->fv.part_d = cv.take<double>(2 * 2048);
   x->fv.part_s = cv.take<double>(2 * (size_t)std::max(2048, zplan(make_geo(m)).blocks));
   x->fv.part_u = cv.take<double>(2 * 2048);
@@ -374,13 +392,26 @@ void wait_stream(gea_ctx* x) {
   HIPCHK(e);
 }
 
-// Device structs to the host through the pinned buffer with one wait.
+// Device structs to the host through the pinned buffer with one wait.  Part
+// k lands at a 256-byte aligned offset; parts laid out the same way on the
+// device (the solver scalars are) go in one copy.
 void read_structs(gea_ctx* x, const Extra* parts, int n) {
   size_t off = 0;
+  bool one = true;
   for (int k = 0; k < n; ++k) {
     if (off + parts[k].bytes > gea_ctx::kPinBytes) throw HipError{hipErrorInvalidValue, "pinned read buffer too small"};
-    HIPCHK(hipMemcpyAsync(x->pin + off, parts[k].dev, parts[k].bytes, hipMemcpyDeviceToHost, x->stream));
+    one = one && static_cast<const char*>(parts[k].dev) == static_cast<const char*>(parts[0].dev) + off;
     off += (parts[k].bytes + 255) & ~(size_t)255;
+  }
+  if (one) {
+    const size_t span = off - ((parts[n - 1].bytes + 255) & ~(size_t)255) + parts[n - 1].bytes;
+    HIPCHK(hipMemcpyAsync(x->pin, parts[0].dev, span, hipMemcpyDeviceToHost, x->stream));
+  } else {
+    off = 0;
+    for (int k = 0; k < n; ++k) {
+      HIPCHK(hipMemcpyAsync(x->pin + off, parts[k].dev, parts[k].bytes, hipMemcpyDeviceToHost, x->stream));
+      off += (parts[k].bytes + 255) & ~(size_t)255;
+    }
   }
   wait_stream(x);
   off = 0;
@@ -513,7 +544,11 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
                         x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
     });
     HIPCHK(hipGetLastError());
+    const bool spec = x->predict_conv(outer);
+    if (spec) (*x->tail)();
     read_scalars(x, x->sc, &h64, Extra{x->sc32, &h32, sizeof h32});
+    x->note_conv(outer, h64.done != 0);
+    x->last_h64 = h64;
     const double rel = h64.bb > 0 ? std::sqrt(h64.rr / h64.bb) : 0.0;
     if (out->rel_res0 < 0) out->rel_res0 = rel;
     out->rel_res = rel;
@@ -526,7 +561,10 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->rel_res = 0.0;
       break;
     }
-    if (h64.done) break;
+    if (h64.done) {
+      x->tail_done = spec;
+      break;
+    }
     if (total >= x->prm.max_iter) {
       out->status = GEA_ERR_NOCONV;
       break;
@@ -628,7 +666,11 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
                         x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
     });
     HIPCHK(hipGetLastError());
+    const bool spec = x->predict_conv(outer);
+    if (spec) (*x->tail)();
     read_scalars(x, x->sc, &h64, Extra{x->sc32, &h32, sizeof h32});
+    x->note_conv(outer, h64.done != 0);
+    x->last_h64 = h64;
     const double rel = h64.bb > 0 ? std::sqrt(h64.rr / h64.bb) : 0.0;
     if (out->rel_res0 < 0) out->rel_res0 = rel;
     out->rel_res = rel;
@@ -641,7 +683,10 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->rel_res = 0.0;
       break;
     }
-    if (h64.done) break;
+    if (h64.done) {
+      x->tail_done = spec;
+      break;
+    }
     if (total >= x->prm.max_iter) {
       out->status = GEA_ERR_NOCONV;
       break;
@@ -662,7 +707,8 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       // iterate and residual, enqueued behind it unread: when the flexible
       // CG has converged the resumed solve starts done, and its iteration
       // kernels return at once.  Its first batch is the previous resumed
-      // solve's length and two more.
+      // solve's length and four more (launches after convergence return at
+      // once; a short batch costs a host round trip).
       const int left = budget - launched;
       x->timer.run(4, x->stream, [&] {
         if (res_parts > 0)
@@ -672,7 +718,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       });
       h32 = CgScalars{};
       fcg = Extra{x->fsc, &hf, sizeof hf};
-      first = x->last_iters_res > 0 ? x->last_iters_res + 2 : 0;
+      first = x->last_iters_res > 0 ? x->last_iters_res + 4 : 0;
     }
     gea_status rc = run_cg(
         x, x->sc32, h32, budget, first,
@@ -749,21 +795,33 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
     x->timer.run(5, x->stream, [&] { build_system(x, S); });
     HIPCHK(hipGetLastError());
     x->has_system = true;
+    double* uo[3] = {x->ustar[0], x->ustar[1], x->ustar[2]};
+    if (last)
+      for (int d = 0; d < 3; ++d) uo[d] = N.u[d];
+    const std::function<void()> correct = [&] {
+      x->timer.run(5, x->stream, [&] { launch_correct(s, G, ph, N.pp, x->rho23, x->psi, x->H, x->D, x->rho_star, uo, last, S.rho,
+                     N.rho, N.p, x->partials, x->sc); });
+    };
     gea_solve_stats ss;
+    x->tail = &correct;
+    x->tail_done = false;
+    x->corr = k;
     gea_status rc = solve(x, N.pp, &ss);
+    x->tail = nullptr;
     stats->solve[stats->n_solves++] = ss;
     stats->total_iters += ss.iters;
     stats->total_solves += 1;
     if (rc != GEA_OK) return rc;
-    double* uo[3] = {x->ustar[0], x->ustar[1], x->ustar[2]};
-    if (last)
-      for (int d = 0; d < 3; ++d) uo[d] = N.u[d];
-    x->timer.run(5, x->stream, [&] { launch_correct(s, G, ph, N.pp, x->rho23, x->psi, x->H, x->D, x->rho_star, uo, last, S.rho,
-                   N.rho, N.p, x->partials, x->sc); });
+    if (!x->tail_done) correct();
     HIPCHK(hipGetLastError());
   }
+  // the end-of-step reductions land in the FP64 scalars: already read when
+  // the last correction ran ahead of the last residual check's read
   CgScalars hs;
-  read_scalars(x, x->sc, &hs);
+  if (x->tail_done)
+    hs = x->last_h64;
+  else
+    read_scalars(x, x->sc, &hs);
   stats->mass = hs.aux[0];
   stats->eos_mismatch = hs.aux[1];
   if (hs.aux[2] != 0.0) return GEA_ERR_NAN;

@@ -475,17 +475,23 @@ __global__ __launch_bounds__(256) void k_conv5z(CnnDims d, const bf16_t* __restr
   const bool act = gx < d.nx && gy < d.ny;
   const size_t plane = (size_t)d.nx * d.ny;
   uint4 v[T::NL];
-  auto fetch = [&](int k) {  // plane k of d0 with its halo; zeros outside the grid
+  // plane k of d0 with its halo; zeros outside the grid.  Every load is made,
+  // from an index clamped into the grid, and the zero padding is a select:
+  // no branch separates the plane's loads.
+  auto fetch = [&](int k) {
+    const bool kin = k >= 0 && k < d.nz;
+    const size_t kp = (size_t)(k < 0 ? 0 : (k >= d.nz ? d.nz - 1 : k)) * plane;
 #pragma unroll
     for (int u = 0; u < T::NL; ++u) {
-      const int e = threadIdx.x + 256 * u, c = e >> 1, h = e & 1;
-      v[u] = make_uint4(0, 0, 0, 0);
-      if (c < T::HC && k >= 0 && k < d.nz) {
-        const int x = ox + c % T::HX - 1;
-        const int y = NDIM == 3 ? oy + c / T::HX - 1 : 0;
-        if (x >= 0 && x < d.nx && y >= 0 && y < d.ny)
-          v[u] = *reinterpret_cast<const uint4*>(X + ((size_t)k * plane + x + (size_t)d.nx * y) * 16 + 8 * h);
-      }
+      const int e = threadIdx.x + 256 * u, h = e & 1;
+      const int c = (e >> 1) < T::HC ? (e >> 1) : T::HC - 1;
+      const int x = ox + c % T::HX - 1;
+      const int y = NDIM == 3 ? oy + c / T::HX - 1 : 0;
+      const bool in = kin && (e >> 1) < T::HC && x >= 0 && x < d.nx && y >= 0 && y < d.ny;
+      const int xc = x < 0 ? 0 : (x >= d.nx ? d.nx - 1 : x);
+      const int yc = y < 0 ? 0 : (y >= d.ny ? d.ny - 1 : y);
+      const uint4 t = *reinterpret_cast<const uint4*>(X + (kp + xc + (size_t)d.nx * yc) * 16 + 8 * h);
+      v[u] = in ? t : make_uint4(0, 0, 0, 0);
     }
   };
   auto put = [&](int slot) {
@@ -499,7 +505,7 @@ __global__ __launch_bounds__(256) void k_conv5z(CnnDims d, const bf16_t* __restr
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;  // output planes k - 1, k, k + 1 of input plane k
   fetch(k0 - 1);
   put(0);
-  __syncthreads();
+  lds_barrier();
   int slot = 0;
   for (int k = k0 - 1; k <= k1; ++k) {
     if (k < k1) fetch(k + 1);
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(256) void k_conv5z(CnnDims d, const bf16_t* __restr
     a2 = 0.f;
     if (k < k1) {
       put(slot ^ 1);
-      __syncthreads();
+      lds_barrier();
       slot ^= 1;
     }
   }
@@ -1119,7 +1125,7 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
                                                 bf16_t* __restrict__ Y) {
   using T = Conv0Z;
   constexpr int RY = T::RY;
-  __shared__ uint32_t s2[T::HP];
+  __shared__ uint32_t s2[2][T::HP];  // two planes: the next one is staged while one is read
   __shared__ __attribute__((aligned(16))) unsigned char scr[4 * 1024];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
@@ -1132,36 +1138,41 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
   for (int i = 0; i < 3; ++i) bw[i] = load8(W0z + (size_t)(i * 64 + lane) * 8);
   const float bz = bias[m];
   uint32_t v[T::NL];
+  // plane z with its halo, zeros outside the grid: every load is made, from
+  // an index clamped into the grid, and the zero padding is a select
   auto fetch = [&](int z) {
     const bool zin = z >= 0 && z < d.nz;
+    const int zc = z < 0 ? 0 : (z >= d.nz ? d.nz - 1 : z);
 #pragma unroll
     for (int u = 0; u < T::NL; ++u) {
       const int e = threadIdx.x + 256 * u;
       const int x = x0 + e % T::HX - 1, y = y0 + e / T::HX - 1;
-      v[u] = 0u;
-      if (zin && e < T::HP && x >= 0 && x < d.nx && y >= 0 && y < d.ny)
-        v[u] = X2[((size_t)z * d.ny + y) * d.nx + x];
+      const bool in = zin && e < T::HP && x >= 0 && x < d.nx && y >= 0 && y < d.ny;
+      const int xc = x < 0 ? 0 : (x >= d.nx ? d.nx - 1 : x);
+      const int yc = y < 0 ? 0 : (y >= d.ny ? d.ny - 1 : y);
+      const uint32_t t = X2[((size_t)zc * d.ny + yc) * d.nx + xc];
+      v[u] = in ? t : 0u;
     }
   };
-  auto put = [&]() {
+  auto put = [&](int sl) {
 #pragma unroll
     for (int u = 0; u < T::NL; ++u) {
       const int e = threadIdx.x + 256 * u;
-      if (e < T::HP) s2[e] = v[u];
+      if (e < T::HP) s2[sl][e] = v[u];
     }
   };
   f32x4 aM[RY], a0[RY], aP[RY];
 #pragma unroll
   for (int j = 0; j < RY; ++j) aM[j] = a0[j] = aP[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  auto compute = [&]() {
+  auto compute = [&](int sl) {
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       uint4 a = make_uint4(0u, 0u, 0u, 0u);
       if (g < 3) {
         const int h = (RY * wave + j + g) * T::HX + m;  // input row y + g - 1, cells x - 1 ... x + 1
-        a.x = s2[h];
-        a.y = s2[h + 1];
-        a.z = s2[h + 2];
+        a.x = s2[sl][h];
+        a.y = s2[sl][h + 1];
+        a.z = s2[sl][h + 2];
       }
       const bf16x8 av = __builtin_bit_cast(bf16x8, a);
       aM[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[2], aM[j], 0, 0, 0);
@@ -1170,11 +1181,12 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
     }
   };
   fetch(k0 - 1);
-  put();
-  __syncthreads();
+  put(0);
+  lds_barrier();
+  int sl = 0;
   for (int z = k0 - 1; z <= k1; ++z) {
     if (z < k1) fetch(z + 1);
-    if (z >= 0 && z < d.nz) compute();
+    if (z >= 0 && z < d.nz) compute(sl);
     if (z - 1 >= k0) store_rows<RY, 16>(aM, bz, scr + wave * 1024, d, x0, y0 + RY * wave, z - 1, 0, Y);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
@@ -1183,9 +1195,10 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
       aP[j] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     if (z < k1) {
-      __syncthreads();
-      put();
-      __syncthreads();
+      // the other buffer was last read a plane ago, before the last barrier
+      put(sl ^ 1);
+      lds_barrier();
+      sl ^= 1;
     }
   }
 }

@@ -207,6 +207,9 @@ struct gea_ctx {
   bool predict_conv(int outer) const {
     return tail && corr < 8 && conv_hist[corr][outer < 3 ? outer : 3];
   }
+  bool predict_unconv(int outer) const {
+    return tail && corr < 8 && !conv_hist[corr][outer < 3 ? outer : 3];
+  }
   void note_conv(int outer, bool c) {
     if (corr < 8) conv_hist[corr][outer < 3 ? outer : 3] = c;
   }
@@ -215,6 +218,15 @@ struct gea_ctx {
   // copies into it are asynchronous, so several go out with one wait)
   char* pin = nullptr;
   static constexpr size_t kPinBytes = 4096;
+  // snapshots: device structs copied into the upper half of the pinned
+  // buffer where the stream reaches them, delivered at the next read
+  static constexpr size_t kSnapBase = 2048, kSnapSlot = 256;
+  struct Snap {
+    void* host;
+    size_t bytes;
+  };
+  Snap snaps[8];
+  int nsnap = 0;
   ~gea_ctx() {
     if (pin) (void)hipHostFree(pin);
   }
@@ -392,6 +404,16 @@ void wait_stream(gea_ctx* x) {
   HIPCHK(e);
 }
 
+// Copy a device struct into the pinned buffer at this point of the stream;
+// the host copy in *host is filled at the next read.
+void snapshot(gea_ctx* x, const void* dev, void* host, size_t bytes) {
+  if (x->nsnap >= 8 || bytes > gea_ctx::kSnapSlot)
+    throw HipError{hipErrorInvalidValue, "snapshot slots exhausted"};
+  char* slot = x->pin + gea_ctx::kSnapBase + gea_ctx::kSnapSlot * x->nsnap;
+  HIPCHK(hipMemcpyAsync(slot, dev, bytes, hipMemcpyDeviceToHost, x->stream));
+  x->snaps[x->nsnap++] = gea_ctx::Snap{host, bytes};
+}
+
 // Device structs to the host through the pinned buffer with one wait.  Part
 // k lands at a 256-byte aligned offset; parts laid out the same way on the
 // device (the solver scalars are) go in one copy.
@@ -399,7 +421,7 @@ void read_structs(gea_ctx* x, const Extra* parts, int n) {
   size_t off = 0;
   bool one = true;
   for (int k = 0; k < n; ++k) {
-    if (off + parts[k].bytes > gea_ctx::kPinBytes) throw HipError{hipErrorInvalidValue, "pinned read buffer too small"};
+    if (off + parts[k].bytes > gea_ctx::kSnapBase) throw HipError{hipErrorInvalidValue, "pinned read buffer too small"};
     one = one && static_cast<const char*>(parts[k].dev) == static_cast<const char*>(parts[0].dev) + off;
     off += (parts[k].bytes + 255) & ~(size_t)255;
   }
@@ -419,6 +441,10 @@ void read_structs(gea_ctx* x, const Extra* parts, int n) {
     std::memcpy(parts[k].host, x->pin + off, parts[k].bytes);
     off += (parts[k].bytes + 255) & ~(size_t)255;
   }
+  for (int k = 0; k < x->nsnap; ++k)
+    std::memcpy(x->snaps[k].host, x->pin + gea_ctx::kSnapBase + gea_ctx::kSnapSlot * k,
+                x->snaps[k].bytes);
+  x->nsnap = 0;
   x->timer.flush();
 }
 
@@ -599,7 +625,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
 // the stop decision the iteration kernels return at once.)  When the last
 // iteration enqueued was the last allowed, it also formed the partials of
 // the resumed Jacobi-PCG's set-up: *res_parts is their count, else 0.
-int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps, int* res_parts) {
+int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
   const Geo& G = x->G;
   FcgVectors& v = x->fv;
   v.d = x->d32;
@@ -614,9 +640,7 @@ int learned_inner(gea_ctx* x, double bb, double inner_tol, int budget, int steps
   v.dinv = x->dinv32;
   v.p_cg = x->p032;
   *res_parts = 0;
-  x->timer.run(4, x->stream, [&] {
-    fcg_start(x->stream, G, v, bb, inner_tol, budget, x->fsc);
-  });
+  x->timer.run(4, x->stream, [&] { fcg_start(x->stream, G, v, x->sc32, budget, x->fsc); });
   const int cap = steps < budget ? steps : budget;
   int it = 0;
   while (it < cap) {
@@ -653,6 +677,32 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   int total = 0, outer = 0, fallbacks = 0;
   bool use_net = true;
   CgScalars h64, h32;
+  // An inner solve enqueued without a host read: the scalars of the residual
+  // check before it (s_res) and of its flexible-CG and Jacobi-PCG parts
+  // (s_fcg, s_cg) arrive as snapshots with the next read.
+  bool unread = false;
+  int unread_bound = 0;  // iterations it may have taken
+  CgScalars s_res{}, s_cg{};
+  FcgScalars s_fcg{};
+  auto iterate = [&](int j) {
+    x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
+    x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+  };
+  // network step(s), then Jacobi-PCG resumed from their iterate and residual
+  // (when the flexible CG has converged the resumed solve starts done and its
+  // iteration kernels return at once); returns the network steps enqueued
+  auto learned_then_resume = [&](int budget) {
+    int res_parts = 0;
+    const int launched = learned_inner(x, budget, x->prm.learned_steps, &res_parts);
+    const int left = budget - launched;
+    x->timer.run(4, x->stream, [&] {
+      if (res_parts > 0)
+        cg_resume_scalars(x->stream, x->fv.part_d, res_parts, w, left > 0 ? left : 0);
+      else
+        cg_resume(x->stream, G, v, w, left > 0 ? left : 0);
+    });
+    return launched;
+  };
   out->rel_res0 = -1.0;
   out->status = GEA_OK;
   for (int guard = 0;; ++guard) {
@@ -660,15 +710,49 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->status = GEA_ERR_NOCONV;
       break;
     }
-    const int budget = x->prm.max_iter - total;
+    const int budget = x->prm.max_iter - total - unread_bound;
     x->timer.run(4, x->stream, [&] {
       launch_residual64(x->stream, G, x->c, x->D, x->b, xv, v, x->prm.tol,
                         x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
     });
     HIPCHK(hipGetLastError());
+    // The learned inner solve goes out unread behind this check when the
+    // same check did not converge last step and the resumed Jacobi-PCG's
+    // length is known: its first batch is that length and four more, then
+    // the correction, then (next pass) the following check; one read then
+    // covers all.  (Were this check converged, the inner system starts done
+    // and the correction adds zero.)
+    if (use_net && !unread && x->last_iters_res > 0 && x->predict_unconv(outer)) {
+      snapshot(x, x->sc, &s_res, sizeof s_res);
+      const int launched = learned_then_resume(budget > 0 ? budget : 1);
+      use_net = false;
+      const int first = x->last_iters_res + 4;
+      for (int j = 0; j < first; ++j) iterate(j);
+      HIPCHK(hipGetLastError());
+      snapshot(x, x->sc32, &s_cg, sizeof s_cg);
+      snapshot(x, x->fsc, &s_fcg, sizeof s_fcg);
+      x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+      unread = true;
+      unread_bound = launched + first;
+      ++outer;
+      continue;
+    }
     const bool spec = x->predict_conv(outer);
     if (spec) (*x->tail)();
     read_scalars(x, x->sc, &h64, Extra{x->sc32, &h32, sizeof h32});
+    if (unread) {  // the inner solve enqueued unread, and the check before it
+      unread = false;
+      unread_bound = 0;
+      x->note_conv(0, s_res.done != 0);
+      if (out->rel_res0 < 0) out->rel_res0 = s_res.bb > 0 ? std::sqrt(s_res.rr / s_res.bb) : 0.0;
+      total += s_cg.iter + s_fcg.iter;
+      x->last_iters_res = s_cg.iter;
+      if (s_fcg.status == 1) ++fallbacks;  // stalled: Jacobi-PCG took over
+      if (s_cg.status == -5) {
+        out->status = GEA_ERR_NAN;
+        break;
+      }
+    }
     x->note_conv(outer, h64.done != 0);
     x->last_h64 = h64;
     const double rel = h64.bb > 0 ? std::sqrt(h64.rr / h64.bb) : 0.0;
@@ -696,37 +780,13 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
     Extra fcg;  // the flexible-CG scalars, read along with the CG's
     int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
     if (use_net) {
-      // same adaptive inner tolerance as the refinement residual kernel sets
-      const double need = 0.1 * std::sqrt(x->prm.tol * x->prm.tol * h64.bb / h64.rr);
-      const double itol = std::max(x->prm.inner_tol, std::min(0.5, need));
-      int res_parts = 0;
-      const int launched = learned_inner(x, h32.bb, itol, budget > 0 ? budget : 1,
-                                         x->prm.learned_steps, &res_parts);
+      learned_then_resume(budget > 0 ? budget : 1);
       use_net = false;
-      // Jacobi-PCG continues the same inner solve from the flexible-CG
-      // iterate and residual, enqueued behind it unread: when the flexible
-      // CG has converged the resumed solve starts done, and its iteration
-      // kernels return at once.  Its first batch is the previous resumed
-      // solve's length and four more (launches after convergence return at
-      // once; a short batch costs a host round trip).
-      const int left = budget - launched;
-      x->timer.run(4, x->stream, [&] {
-        if (res_parts > 0)
-          cg_resume_scalars(x->stream, x->fv.part_d, res_parts, w, left > 0 ? left : 0);
-        else
-          cg_resume(x->stream, G, v, w, left > 0 ? left : 0);
-      });
       h32 = CgScalars{};
       fcg = Extra{x->fsc, &hf, sizeof hf};
       first = x->last_iters_res > 0 ? x->last_iters_res + 4 : 0;
     }
-    gea_status rc = run_cg(
-        x, x->sc32, h32, budget, first,
-        [&](int j) {
-          x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
-          x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
-        },
-        fcg);
+    gea_status rc = run_cg(x, x->sc32, h32, budget, first, iterate, fcg);
     if (rc != GEA_OK) return rc;
     done_iters += h32.iter;
     if (fcg.bytes) {

@@ -751,7 +751,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_resume_start(const double* part, 
   sc->max_iter = max_iter;
   const bool finite = isfinite(s[0]) && isfinite(s[1]);
   sc->status = finite ? 0 : -5;
-  const int done = (!finite || s[1] <= sc->tol2 * sc->bb || sc->max_iter <= 0) ? 1 : 0;
+  // (already done: the refinement's residual check found nothing left to solve)
+  const int done = (sc->done || !finite || s[1] <= sc->tol2 * sc->bb || sc->max_iter <= 0) ? 1 : 0;
   __hip_atomic_store(&sc->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

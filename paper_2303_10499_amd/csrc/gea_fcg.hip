@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
 // One workgroup: ||r||^2 and max |r| from the update partials (or from the
 // start kernel), stop / stall decision, next scale 1/s.
 __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n, int iter,
-                                                      int init, double bb, double tol2,
+                                                      int init, const CgScalars* sys,
                                                       int max_iter, FcgScalars* sc) {
   __shared__ double sh[2][kBlock / 64];
   if (!init && sc->done) return;
@@ -289,9 +289,9 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
   }
   Reducer<0x2u, 2>::block(a, sh);
   if (threadIdx.x != 0) return;
-  if (init) {
-    sc->bb = bb;
-    sc->tol2 = tol2;
+  if (init) {  // ||b||^2 and tolerance of the inner system as its set-up left them
+    sc->bb = sys->bb;
+    sc->tol2 = sys->tol2;
     sc->max_iter = max_iter;
     sc->status = 0;
     sc->rz_prev[0] = sc->rz_prev[1] = 1.0;
@@ -303,8 +303,9 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
   sc->inv_s = a[1] > 0 ? 1.0 / a[1] : 0.0;
   const double old = sc->hist[iter % 10];   // ||r||^2 ten iterations ago
   sc->hist[iter % 10] = a[0];
-  int done = 0;
-  if (!isfinite(a[0]) || !isfinite(a[1])) {
+  int done = init && sys->done ? 1 : 0;  // nothing to solve (the refinement has converged)
+  if (done) {
+  } else if (!isfinite(a[0]) || !isfinite(a[1])) {
     sc->status = 1;  // stall: fall back
     done = 1;
   } else if (a[0] <= sc->tol2 * sc->bb) {
@@ -379,12 +380,12 @@ __global__ __launch_bounds__(kBlock) void k_pair(int n, const double* __restrict
 
 }  // namespace
 
-void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, double bb, double tol,
+void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, const CgScalars* sys,
                int max_iter, FcgScalars* sc) {
   const int gu = grid_for(G.nc);
   hipLaunchKernelGGL(k_fcg_start, dim3(gu), dim3(kBlock), 0, s, G.nc, (const float*)v.r, v.part_u);
   hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(kBlock), 0, s, (const double*)v.part_u, gu, 0, 1,
-                     bb, tol * tol, max_iter, sc);
+                     sys, max_iter, sc);
 }
 
 int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
@@ -429,8 +430,8 @@ int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int 
   else if (last) GEA_UPD(false, true);
   else GEA_UPD(false, false);
 #undef GEA_UPD
-  hipLaunchKernelGGL(k_fcg_check, dim3(1), bl, 0, s, (const double*)v.part_u, gu, iter + 1, 0, 0.0,
-                     0.0, 0, sc);
+  hipLaunchKernelGGL(k_fcg_check, dim3(1), bl, 0, s, (const double*)v.part_u, gu, iter + 1, 0,
+                     (const CgScalars*)nullptr, 0, sc);
   return gu;
 }
 

@@ -193,7 +193,9 @@ struct FcgVectors {
   double *part_d, *part_s, *part_u;
 };
 
-void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, double bb, double tol,
+// flexible-CG set-up on the inner system whose ||b||^2, tolerance and done
+// flag the refinement's residual check left in sys
+void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, const CgScalars* sys,
                int max_iter, FcgScalars* sc);
 // one iteration once z = M(r) is in v.z: dots, direction + operator, update,
 // check.  The last one (last) also sets up the Jacobi-PCG that resumes the

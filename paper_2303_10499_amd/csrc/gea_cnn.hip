@@ -1119,10 +1119,14 @@ struct Conv0Z {
   static constexpr int NL = (HP + 255) / 256;
 };
 
+// With P0 given, the 2x average pooling of the output (what the next level
+// reads) is formed here too, from the same bf16 values in the same order as
+// the pooling kernel: each lane holds two x pairs of its channel in the rows
+// of its y pairs, and the planes of a z pair come one after the other.
 __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __restrict__ X2,
                                                 const bf16_t* __restrict__ W0z,
                                                 const float* __restrict__ bias,
-                                                bf16_t* __restrict__ Y) {
+                                                bf16_t* __restrict__ Y, bf16_t* __restrict__ P0) {
   using T = Conv0Z;
   constexpr int RY = T::RY;
   __shared__ uint32_t s2[2][T::HP];  // two planes: the next one is staged while one is read
@@ -1180,6 +1184,39 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
       aP[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[0], aP[j], 0, 0, 0);
     }
   };
+  static_assert(RY % 2 == 0 && T::KC % 2 == 0 && T::TX % 4 == 0, "pooling pairs inside a wave");
+  float ps[RY / 2][2];  // pooled sums of this lane: [y pair][x pair]
+  auto pool = [&](int zo) {
+    const bool first = ((zo - k0) & 1) == 0;
+#pragma unroll
+    for (int yp = 0; yp < RY / 2; ++yp)
+#pragma unroll
+      for (int xp = 0; xp < 2; ++xp) {
+        float sum = first ? 0.f : ps[yp][xp];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx)
+            sum += bf2f(f2bf(fmaxf(aM[2 * yp + dy][2 * xp + dx] + bz, 0.f)));
+        ps[yp][xp] = sum;
+      }
+    if (first) return;
+    // the wave's RY/2 x 8 coarse cells x 16 channels through its LDS scratch
+    // (after the rows of store_rows are out of it) to 16-byte stores
+    static_assert(RY / 2 * 8 * 32 <= 1024, "pooled tile fits the wave's scratch");
+    bf16_t* sw = reinterpret_cast<bf16_t*>(scr + wave * 1024);
+#pragma unroll
+    for (int yp = 0; yp < RY / 2; ++yp)
+#pragma unroll
+      for (int xp = 0; xp < 2; ++xp) sw[(yp * 8 + 2 * g + xp) * 16 + m] = f2bf(ps[yp][xp] * 0.125f);
+    if (lane < RY / 2 * 16) {
+      const int nx2 = d.nx / 2, ny2 = d.ny / 2;
+      const int cell = lane >> 1, yp = cell >> 3, cx = x0 / 2 + (cell & 7), cy = (y0 + RY * wave) / 2 + yp;
+      const uint4 val = *reinterpret_cast<const uint4*>(scr + wave * 1024 + lane * 16);
+      if (2 * cx < d.nx && 2 * cy < d.ny)
+        *reinterpret_cast<uint4*>(P0 + (((size_t)(zo / 2) * ny2 + cy) * nx2 + cx) * 16 + (lane & 1) * 8) = val;
+    }
+  };
   fetch(k0 - 1);
   put(0);
   lds_barrier();
@@ -1187,7 +1224,10 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
   for (int z = k0 - 1; z <= k1; ++z) {
     if (z < k1) fetch(z + 1);
     if (z >= 0 && z < d.nz) compute(sl);
-    if (z - 1 >= k0) store_rows<RY, 16>(aM, bz, scr + wave * 1024, d, x0, y0 + RY * wave, z - 1, 0, Y);
+    if (z - 1 >= k0) {
+      store_rows<RY, 16>(aM, bz, scr + wave * 1024, d, x0, y0 + RY * wave, z - 1, 0, Y);
+      if (P0) pool(z - 1);
+    }
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       aM[j] = a0[j];
@@ -1259,7 +1299,8 @@ int conv_blocks(int npix) { return (npix + 4 * 16 * kMT - 1) / (4 * 16 * kMT); }
 // forward convolution of a layer; layers 3 and 4 read the concatenation
 // [up(A), X] directly (A = e2 / d1 on the coarser grid, X = e1 / e0)
 template <int NDIM>
-void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y) {
+void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y,
+              bf16_t* pooled = nullptr) {
   const CnnLayer& L = n.L[layer];
   const CnnDims& d = n.d[L.level];
   const dim3 bl(256);
@@ -1271,7 +1312,7 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
     case 0:
       if constexpr (NDIM == 3)
         hipLaunchKernelGGL(k_conv0z, dim3(conv0z_tiles(d)), bl, 0, s, d, (const uint32_t*)n.x2, n.W0z,
-                           n.bias[0], (bf16_t*)Y);
+                           n.bias[0], (bf16_t*)Y, pooled);
       else
         hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d,
                            (const uint32_t*)n.x2, n.W0, n.bias[0], (bf16_t*)Y);
@@ -1369,8 +1410,12 @@ template <int NDIM>
 void forward_t(Cnn& n) {
   hipStream_t s = n.s;
   const dim3 bl(256);
-  conv_layer<NDIM>(n, 0);
-  hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[1].npix * 16)), bl, 0, s, n.d[1], 16, (const bf16_t*)n.e0, n.p0);
+  if constexpr (NDIM == 3) {
+    conv_fwd<NDIM>(n, 0, n.xin, nullptr, n.e0, n.p0);  // with the pooling of e0
+  } else {
+    conv_layer<NDIM>(n, 0);
+    hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[1].npix * 16)), bl, 0, s, n.d[1], 16, (const bf16_t*)n.e0, n.p0);
+  }
   conv_layer<NDIM>(n, 1);
   hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[2].npix * 32)), bl, 0, s, n.d[2], 32, (const bf16_t*)n.e1, n.p1);
   conv_layer<NDIM>(n, 2);

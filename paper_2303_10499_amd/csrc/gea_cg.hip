@@ -850,7 +850,7 @@ void launch_residual64(hipStream_t s, const Geo& G, const double* c, const doubl
                        double tol, double inner_tol, int inner_max, double* o_part,
                        const CgWork& w32, CgScalars* sc64) {
   constexpr int TY = 8;  // 64x8 column tiles in 3D
-  const ZPlan zp = G.ndim == 2 ? zplan(G) : zplan3(G, TY);
+  const ZPlan zp = G.ndim == 2 ? zplan(G) : zplan3(G, TY, ZTile<3>::KC);
   const int gu = zp.blocks;
   const dim3 grid(gu), block(kBlock);
   if (G.ndim == 2)

@@ -410,7 +410,7 @@ int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int 
       hipLaunchKernelGGL((k_fcg_spmv<2, false>), gr, bl, 0, s, G, iter, (const float*)v.z, p_old, p_new, v.q,
                          v.c, v.D, (const float*)v.r, keep_p, (const double*)v.part_d, gu, v.part_s, sc);
   } else {
-    const ZPlan zp = zplan3(G, 4);
+    const ZPlan zp = zplan3(G, 4, ZTile<3>::KC);
     ns = zp.blocks;
     if (it0)
       hipLaunchKernelGGL(k_fcg_spmv3<true>, dim3(zp.blocks), bl, 0, s, G, zp.kc, iter, (const float*)v.z, p_old,

@@ -66,9 +66,10 @@ struct ZPlan {
   int blocks;
 };
 ZPlan zplan(const Geo& G);
-// 3D column tiles of 64 x ty cells (64 ty threads a workgroup), chunks as zplan;
-// never more workgroups than zplan's for ty >= 4
-ZPlan zplan3(const Geo& G, int ty);
+// 3D column tiles of 64 x ty cells (64 ty threads a workgroup) marching
+// chunks of kc planes (fewer chunks where zplan would need them); never more
+// workgroups than zplan's for ty >= 4 and kc >= its chunk
+ZPlan zplan3(const Geo& G, int ty, int kc);
 
 // ---- explicit step kernels (gea_step.hip) ----------------------------------
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,

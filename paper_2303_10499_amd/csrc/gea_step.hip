@@ -1454,9 +1454,9 @@ ZPlan zplan_t(const Geo& G) {
 
 ZPlan zplan(const Geo& G) { return G.ndim == 2 ? zplan_t<2>(G) : zplan_t<3>(G); }
 
-ZPlan zplan3(const Geo& G, int ty) {
+ZPlan zplan3(const Geo& G, int ty, int kc0) {
   const int cols = ((G.nx + 63) / 64) * ((G.ny + ty - 1) / ty), nz = G.nz;
-  int kc = ZTile<3>::KC < nz ? ZTile<3>::KC : nz;
+  int kc = kc0 < nz ? kc0 : nz;
   int nk = (nz + kc - 1) / kc;
   const int maxk = kMaxZBlocks / cols > 1 ? kMaxZBlocks / cols : 1;
   if (nk > maxk) {
@@ -1472,6 +1472,9 @@ namespace {
 // re-read fewer halo rows; the two kernels with the most registers keep
 // 64x4 for occupancy)
 constexpr int kTyMass = 8, kTyMom = 4, kTyEnergy = 8, kTyH = 4, kTyRhs = 8, kTyCorr = 8;
+// planes of a chunk (measured per kernel: 16, 32 and 64 tried)
+constexpr int kKcMass = 32, kKcMom = 32, kKcEnergy = 64, kKcH = 16, kKcRhs = 32, kKcCorr = 32,
+              kKcCorrLast = 64;
 
 }  // namespace
 
@@ -1481,7 +1484,7 @@ constexpr int kTyMass = 8, kTyMom = 4, kTyEnergy = 8, kTyH = 4, kTyRhs = 8, kTyC
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                       double* const* u, const double* T, double* const* phi, double* rho_star,
                       double* e0) {
-  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMass) : zp;
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMass, kKcMass) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
   else
@@ -1491,7 +1494,7 @@ void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double*
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                         double* const* u, const double* pp, const double* rho_star,
                         double* const* phi, double* const* u_star) {
-  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMom) : zp;
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMom, kKcMom) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star));
   else
@@ -1503,7 +1506,7 @@ void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const doub
                          double* const* phi, const double* rho_star, double* const* u_star,
                          const double* Tbg, double* e_next, double* T_next, bool last,
                          const double* p, double* rho23, double* psi, double* c, double* D) {
-  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy) : zp;
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy, kKcEnergy) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_energy_sweep<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
   else
@@ -1512,7 +1515,7 @@ void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const doub
 
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,
               double* const* u_prev, double* const* phi, double* const* H) {
-  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyH) : zp;
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyH, kKcH) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_H<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), V2(u_prev), V2(phi), V2(H));
   else
@@ -1523,7 +1526,7 @@ void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                 const double* rho23, const double* psi, const double* c, const double* D,
                 double* const* H, double* b, double* dinv, float* c32, float* D32,
                 float* dinv32) {
-  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyRhs) : zp;
+  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyRhs, kKcRhs) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V2(H), b, dinv, c32, D32, dinv32);
   else
@@ -1535,7 +1538,8 @@ void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* p
                     const double* rho_star, double* const* u_out, bool last,
                     const double* rho_old, double* rho_new, double* p_new, double* partials,
                     CgScalars* sc) {
-  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyCorr) : zp;
+  const ZPlan zp = zplan(G),
+              zp3 = G.ndim == 3 ? zplan3(G, kTyCorr, last ? kKcCorrLast : kKcCorr) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_correct<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V2(H), D, rho_star, V2(u_out), (int)last, rho_old, rho_new, p_new, partials);
   else if (last)

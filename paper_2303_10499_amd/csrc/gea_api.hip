@@ -817,13 +817,14 @@ gea_status solve(gea_ctx* x, double* xv, gea_solve_stats* out) {
   return solve_mixed(x, xv, out);
 }
 
-// Steps 1 and 2 from state s; the last energy sweep writes T_out.
-void steps_1_2(gea_ctx* x, const State& S, double* T_out) {
+// Steps 1 and 2 from state s; the last energy sweep writes T_out; p' is
+// copied to pp_out when given (the pressure solve's initial guess).
+void steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out = nullptr) {
   const Geo& G = x->G;
   const Phys& ph = x->ph;
   hipStream_t s = x->stream;
   x->timer.run(5, x->stream, [&] { launch_mass_flux(s, G, ph, S.rho, S.u, S.T, x->phi, x->rho_star, x->e0); });
-  x->timer.run(5, x->stream, [&] { launch_mom_predict(s, G, ph, S.rho, S.u, S.pp, x->rho_star, x->phi, x->ustar); });
+  x->timer.run(5, x->stream, [&] { launch_mom_predict(s, G, ph, S.rho, S.u, S.pp, x->rho_star, x->phi, x->ustar, pp_out); });
   const double* e_prev = x->e0;
   const double* T_prev = S.T;
   const int ns = x->prm.n_energy_sweeps;
@@ -845,8 +846,7 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
   hipStream_t s = x->stream;
   const State& S = x->st[x->cur];
   const State& N = x->st[1 - x->cur];
-  steps_1_2(x, S, N.T);
-  HIPCHK(hipMemcpyAsync(N.pp, S.pp, sizeof(double) * G.nc, hipMemcpyDeviceToDevice, s));
+  steps_1_2(x, S, N.T, N.pp);
   const int nc = x->prm.n_corr;
   stats->n_solves = 0;
   for (int k = 0; k < nc; ++k) {

@@ -75,9 +75,10 @@ ZPlan zplan3(const Geo& G, int ty, int kc);
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                       double* const* u, const double* T, double* const* phi, double* rho_star,
                       double* e0);
+// (pp_copy: p' is also copied there, or null)
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                         double* const* u, const double* pp, const double* rho_star,
-                        double* const* phi, double* const* u_star);
+                        double* const* phi, double* const* u_star, double* pp_copy);
 void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                          const double* e0, const double* e_prev, const double* T_prev,
                          double* const* phi, const double* rho_star, double* const* u_star,

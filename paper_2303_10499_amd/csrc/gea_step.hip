@@ -249,7 +249,8 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
                                                         const double* __restrict__ rho, Vec<NDIM> u,
                                                         const double* __restrict__ pp,
                                                         const double* __restrict__ rho_star,
-                                                        Vec<NDIM> phi, Vec<NDIM> u_star) {
+                                                        Vec<NDIM> phi, Vec<NDIM> u_star,
+                                                        double* __restrict__ pp_copy) {
   constexpr int Z = NDIM - 1;
   const Col c = col_of<NDIM>(G, kc);
   if (!c.act) return;
@@ -340,6 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
       u_star.p[cc][P] = us[cc];
       z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
     }
+    if (pp_copy) pp_copy[P] = pc;
     Flo = Fhi;
   }
 }
@@ -352,7 +354,8 @@ __global__ __launch_bounds__(64 * TY) void k_mom_predict3(Geo G, Phys ph, int kc
                                                          const double* __restrict__ rho, Vec<3> u,
                                                          const double* __restrict__ pp,
                                                          const double* __restrict__ rho_star,
-                                                         Vec<3> phi, Vec<3> u_star) {
+                                                         Vec<3> phi, Vec<3> u_star,
+                                                         double* __restrict__ pp_copy) {
   using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double su[2][5][HP];  // u (3 components), p', rho
@@ -462,6 +465,7 @@ __global__ __launch_bounds__(64 * TY) void k_mom_predict3(Geo G, Phys ph, int kc
       const int P = qo + pl * k;
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) u_star.p[cc][P] = us[cc];
+      if (pp_copy) pp_copy[P] = pc;
     }
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
@@ -1493,12 +1497,12 @@ void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double*
 
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                         double* const* u, const double* pp, const double* rho_star,
-                        double* const* phi, double* const* u_star) {
+                        double* const* phi, double* const* u_star, double* pp_copy) {
   const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMom, kKcMom) : zp;
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star));
+    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star), pp_copy);
   else
-    hipLaunchKernelGGL(k_mom_predict3<kTyMom>, dim3(zp3.blocks), dim3(64 * kTyMom), 0, s, G, ph, zp3.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star));
+    hipLaunchKernelGGL(k_mom_predict3<kTyMom>, dim3(zp3.blocks), dim3(64 * kTyMom), 0, s, G, ph, zp3.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star), pp_copy);
 }
 
 void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,

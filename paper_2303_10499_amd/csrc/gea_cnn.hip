@@ -868,18 +868,22 @@ int blocks_for(long n) {
 // Bias, ReLU and bf16 of RY output rows (16 cells x one 16-channel tile each,
 // in MFMA D layout) through a wave's 1 KB LDS scratch: two rows per round,
 // then 16 bytes per lane to the channels-last output (COUT channels per cell).
+// (kept, when given, receives the lane's bf16 outputs: [row][x] of its channel)
 template <int RY, int COUT>
 __device__ __forceinline__ void store_rows(const f32x4 (&acc)[RY], float bz, unsigned char* scr,
                                            const CnnDims& d, int x0, int y, int zo, int nt,
-                                           bf16_t* __restrict__ Y) {
+                                           bf16_t* __restrict__ Y, bf16_t (*kept)[4] = nullptr) {
   const int lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int j0 = 0; j0 < RY; j0 += 2) {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        reinterpret_cast<bf16_t*>(scr)[(t * 16 + 4 * g + i) * 16 + m] = f2bf(fmaxf(acc[j0 + t][i] + bz, 0.f));
+      for (int i = 0; i < 4; ++i) {
+        const bf16_t v = f2bf(fmaxf(acc[j0 + t][i] + bz, 0.f));
+        reinterpret_cast<bf16_t*>(scr)[(t * 16 + 4 * g + i) * 16 + m] = v;
+        if (kept) kept[j0 + t][i] = v;
+      }
     const int t = lane >> 5, cell = (lane >> 1) & 15, c8 = nt * 16 + (lane & 1) * 8;
     const uint4 val = *reinterpret_cast<const uint4*>(scr + lane * 16);
     const int x = x0 + cell, yy = y + j0 + t;
@@ -1123,7 +1127,8 @@ struct Conv0Z {
 // reads) is formed here too, from the same bf16 values in the same order as
 // the pooling kernel: each lane holds two x pairs of its channel in the rows
 // of its y pairs, and the planes of a z pair come one after the other.
-__global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __restrict__ X2,
+template <bool POOL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_conv0z(CnnDims d, const uint32_t* __restrict__ X2,
                                                 const bf16_t* __restrict__ W0z,
                                                 const float* __restrict__ bias,
                                                 bf16_t* __restrict__ Y, bf16_t* __restrict__ P0) {
@@ -1186,6 +1191,7 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
   };
   static_assert(RY % 2 == 0 && T::KC % 2 == 0 && T::TX % 4 == 0, "pooling pairs inside a wave");
   float ps[RY / 2][2];  // pooled sums of this lane: [y pair][x pair]
+  bf16_t kept[RY][4];   // the lane's bf16 outputs of the plane
   auto pool = [&](int zo) {
     const bool first = ((zo - k0) & 1) == 0;
 #pragma unroll
@@ -1196,8 +1202,7 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-          for (int dx = 0; dx < 2; ++dx)
-            sum += bf2f(f2bf(fmaxf(aM[2 * yp + dy][2 * xp + dx] + bz, 0.f)));
+          for (int dx = 0; dx < 2; ++dx) sum += bf2f(kept[2 * yp + dy][2 * xp + dx]);
         ps[yp][xp] = sum;
       }
     if (first) return;
@@ -1225,8 +1230,12 @@ __global__ __launch_bounds__(256) void k_conv0z(CnnDims d, const uint32_t* __res
     if (z < k1) fetch(z + 1);
     if (z >= 0 && z < d.nz) compute(sl);
     if (z - 1 >= k0) {
-      store_rows<RY, 16>(aM, bz, scr + wave * 1024, d, x0, y0 + RY * wave, z - 1, 0, Y);
-      if (P0) pool(z - 1);
+      if constexpr (POOL) {
+        store_rows<RY, 16>(aM, bz, scr + wave * 1024, d, x0, y0 + RY * wave, z - 1, 0, Y, kept);
+        pool(z - 1);
+      } else {
+        store_rows<RY, 16>(aM, bz, scr + wave * 1024, d, x0, y0 + RY * wave, z - 1, 0, Y);
+      }
     }
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
@@ -1311,8 +1320,14 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
   switch (layer) {
     case 0:
       if constexpr (NDIM == 3)
-        hipLaunchKernelGGL(k_conv0z, dim3(conv0z_tiles(d)), bl, 0, s, d, (const uint32_t*)n.x2, n.W0z,
-                           n.bias[0], (bf16_t*)Y, pooled);
+      {
+        if (pooled)
+          hipLaunchKernelGGL(k_conv0z<true>, dim3(conv0z_tiles(d)), bl, 0, s, d, (const uint32_t*)n.x2,
+                             n.W0z, n.bias[0], (bf16_t*)Y, pooled);
+        else
+          hipLaunchKernelGGL(k_conv0z<false>, dim3(conv0z_tiles(d)), bl, 0, s, d, (const uint32_t*)n.x2,
+                             n.W0z, n.bias[0], (bf16_t*)Y, pooled);
+      }
       else
         hipLaunchKernelGGL((k_conv0<NDIM>), dim3(conv_tiles<NDIM, 8>(d)), bl, 0, s, d,
                            (const uint32_t*)n.x2, n.W0, n.bias[0], (bf16_t*)Y);
@@ -1397,7 +1412,9 @@ template <int NDIM>
 void conv_layer(Cnn& n, int layer) {
   const bf16_t* none = nullptr;
   switch (layer) {
-    case 0: conv_fwd<NDIM>(n, 0, n.xin, none, n.e0); break;
+    case 0:  // in 3D with the pooling of e0 it forms
+      conv_fwd<NDIM>(n, 0, n.xin, none, n.e0, NDIM == 3 ? n.p0 : nullptr);
+      break;
     case 1: conv_fwd<NDIM>(n, 1, n.p0, none, n.e1); break;
     case 2: conv_fwd<NDIM>(n, 2, n.p1, none, n.e2); break;
     case 3: conv_fwd<NDIM>(n, 3, n.e1, n.e2, n.d1); break;
@@ -1410,12 +1427,9 @@ template <int NDIM>
 void forward_t(Cnn& n) {
   hipStream_t s = n.s;
   const dim3 bl(256);
-  if constexpr (NDIM == 3) {
-    conv_fwd<NDIM>(n, 0, n.xin, nullptr, n.e0, n.p0);  // with the pooling of e0
-  } else {
-    conv_layer<NDIM>(n, 0);
+  conv_layer<NDIM>(n, 0);  // in 3D it also forms p0
+  if constexpr (NDIM == 2)
     hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[1].npix * 16)), bl, 0, s, n.d[1], 16, (const bf16_t*)n.e0, n.p0);
-  }
   conv_layer<NDIM>(n, 1);
   hipLaunchKernelGGL(k_pool<NDIM>, dim3(blocks_for((long)n.d[2].npix * 32)), bl, 0, s, n.d[2], 32, (const bf16_t*)n.e1, n.p1);
   conv_layer<NDIM>(n, 2);

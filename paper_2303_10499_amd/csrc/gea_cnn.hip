@@ -510,29 +510,25 @@ __global__ __launch_bounds__(256) void k_conv5z(CnnDims d, const bf16_t* __restr
   for (int k = k0 - 1; k <= k1; ++k) {
     if (k < k1) fetch(k + 1);
     if (k >= 0 && k < d.nz) {
-      // the thread's 3 x 3 (2D: 3) neighbours in this plane, then one tap
-      // group (9 or 3 taps x 8 channel pairs) per output plane
+      // the thread's 3 x 3 (2D: 3) neighbours in this plane, one at a time,
+      // each into the three tap groups (dz = +1 for output plane k - 1,
+      // dz = 0 for k, dz = -1 for k + 1): three independent chains, and
+      // only one neighbour's 16 channels live in registers
       constexpr int NC = NDIM == 3 ? 9 : 3;
       constexpr int TZ = NC;  // tap stride of dz
-      uint4 P[NC], Q[NC];
+      const bool g0 = k - 1 >= k0, g1 = k >= k0 && k < k1, g2 = k + 1 < k1;
+      float e0 = 0.f, e1 = 0.f, e2 = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int a = (NDIM == 3 ? (ly + c / 3) * T::HX : 0) + lx + c % 3;
-        P[c] = sx[slot][0][a];
-        Q[c] = sx[slot][1][a];
+        const uint4 P = sx[slot][0][a], Q = sx[slot][1][a];
+        if (g0) e0 = dot16(P, Q, W5 + 8 * (2 * TZ + c), e0);
+        if (g1) e1 = dot16(P, Q, W5 + 8 * (TZ + c), e1);
+        if (g2) e2 = dot16(P, Q, W5 + 8 * c, e2);
       }
-      auto group = [&](const uint32_t* __restrict__ w, float acc) {
-        float e = 0.f;  // two chains
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          if (c & 1) e = dot16(P[c], Q[c], w + 8 * c, e);
-          else acc = dot16(P[c], Q[c], w + 8 * c, acc);
-        }
-        return acc + e;
-      };
-      if (k - 1 >= k0) a0 = group(W5 + 8 * 2 * TZ, a0);     // dz = +1 for output k - 1
-      if (k >= k0 && k < k1) a1 = group(W5 + 8 * TZ, a1);  // dz = 0
-      if (k + 1 < k1) a2 = group(W5, a2);                   // dz = -1 for output k + 1
+      a0 += e0;
+      a1 += e1;
+      a2 += e2;
     }
     if (k - 1 >= k0 && act) Y[(size_t)(k - 1) * plane + gx + (size_t)d.nx * gy] = a0 + b0;
     a0 = a1;

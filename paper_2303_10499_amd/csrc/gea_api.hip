@@ -652,8 +652,7 @@ int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
     }
     x->timer.run(6, x->stream, [&] {
       cnn_input_from_residual(x->net, x->r32, &x->fsc->inv_s, x->c32, x->dinv32);
-      cnn_forward(x->net);
-      cnn_scale_output(x->net, &x->fsc->s, x->z32, 0);
+      cnn_forward_scaled(x->net, &x->fsc->s, x->z32);
     });
     const bool last = it + 1 == cap;
     x->timer.run(2, x->stream, [&] {

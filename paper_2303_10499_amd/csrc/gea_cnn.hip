@@ -456,11 +456,14 @@ __device__ __forceinline__ float dot16(const uint4& p, const uint4& q, const uin
   return a;
 }
 
+// With scale given, Y receives (float)*scale times the output (the solver's
+// scaled correction; the same product as the output scaling kernel).
 template <int NDIM>
 __global__ __launch_bounds__(256) void k_conv5z(CnnDims d, const bf16_t* __restrict__ X,
                                                 const uint32_t* __restrict__ W5,
                                                 const float* __restrict__ bias,
-                                                float* __restrict__ Y) {
+                                                float* __restrict__ Y,
+                                                const double* __restrict__ scale) {
   using T = Conv5Z<NDIM>;
   __shared__ uint4 sx[2][2][T::HC];  // [slot][channel half][cell]
   const int ntx = (d.nx + T::TX - 1) / T::TX;
@@ -502,6 +505,7 @@ __global__ __launch_bounds__(256) void k_conv5z(CnnDims d, const bf16_t* __restr
     }
   };
   const float b0 = bias[0];
+  const float sc = scale ? (float)*scale : 1.f;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;  // output planes k - 1, k, k + 1 of input plane k
   fetch(k0 - 1);
   put(0);
@@ -530,7 +534,10 @@ __global__ __launch_bounds__(256) void k_conv5z(CnnDims d, const bf16_t* __restr
       a1 += e1;
       a2 += e2;
     }
-    if (k - 1 >= k0 && act) Y[(size_t)(k - 1) * plane + gx + (size_t)d.nx * gy] = a0 + b0;
+    if (k - 1 >= k0 && act) {
+      const float y = a0 + b0;
+      Y[(size_t)(k - 1) * plane + gx + (size_t)d.nx * gy] = scale ? sc * y : y;
+    }
     a0 = a1;
     a1 = a2;
     a2 = 0.f;
@@ -1305,7 +1312,7 @@ int conv_blocks(int npix) { return (npix + 4 * 16 * kMT - 1) / (4 * 16 * kMT); }
 // [up(A), X] directly (A = e2 / d1 on the coarser grid, X = e1 / e0)
 template <int NDIM>
 void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y,
-              bf16_t* pooled = nullptr) {
+              bf16_t* pooled = nullptr, const double* scale = nullptr) {
   const CnnLayer& L = n.L[layer];
   const CnnDims& d = n.d[L.level];
   const dim3 bl(256);
@@ -1352,7 +1359,7 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
       break;
     case 5:
       hipLaunchKernelGGL((k_conv5z<NDIM>), dim3(conv5z_tiles<NDIM>(d)), bl, 0, s, d, X,
-                         (const uint32_t*)n.W5, n.bias[5], (float*)Y);
+                         (const uint32_t*)n.W5, n.bias[5], (float*)Y, scale);
       break;
   }
 #undef GEA_CONV
@@ -1419,8 +1426,9 @@ void conv_layer(Cnn& n, int layer) {
   }
 }
 
+// (with scale given, the output goes to out as (float)*scale times y; y is not stored)
 template <int NDIM>
-void forward_t(Cnn& n) {
+void forward_t(Cnn& n, const double* scale = nullptr, float* out = nullptr) {
   hipStream_t s = n.s;
   const dim3 bl(256);
   conv_layer<NDIM>(n, 0);  // in 3D it also forms p0
@@ -1431,7 +1439,10 @@ void forward_t(Cnn& n) {
   conv_layer<NDIM>(n, 2);
   conv_layer<NDIM>(n, 3);
   conv_layer<NDIM>(n, 4);
-  conv_layer<NDIM>(n, 5);
+  if (scale)
+    conv_fwd<NDIM>(n, 5, n.d0, nullptr, out, nullptr, scale);
+  else
+    conv_layer<NDIM>(n, 5);
   if (n.train) {
     // the concatenated inputs of layers 3 and 4, kept for the weight gradients
     hipLaunchKernelGGL(k_upcat<NDIM>, dim3(blocks_for((long)n.d[1].npix * 96)), bl, 0, s, n.d[1], 64, 32, (const bf16_t*)n.e2, (const bf16_t*)n.e1, n.c1);
@@ -1656,6 +1667,11 @@ void cnn_scale_output(Cnn& n, const double* s, float* out, int accumulate) {
 void cnn_forward(Cnn& n) {
   if (n.ndim == 2) forward_t<2>(n);
   else forward_t<3>(n);
+}
+
+void cnn_forward_scaled(Cnn& n, const double* s, float* out) {
+  if (n.ndim == 2) forward_t<2>(n, s, out);
+  else forward_t<3>(n, s, out);
 }
 
 void cnn_conv_layer(Cnn& n, int layer) {

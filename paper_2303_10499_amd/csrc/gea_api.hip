@@ -712,7 +712,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
     const int budget = x->prm.max_iter - total - unread_bound;
     x->timer.run(4, x->stream, [&] {
       launch_residual64(x->stream, G, x->c, x->D, x->b, xv, v, x->prm.tol,
-                        x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
+                        x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc, !use_net);
     });
     HIPCHK(hipGetLastError());
     // The learned inner solve goes out unread behind this check when the

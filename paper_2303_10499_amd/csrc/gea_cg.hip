@@ -562,7 +562,8 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ x,
                                                        CgVectors<float> v32, int kc,
-                                                       double* o_part, double* i_part) {
+                                                       double* o_part, double* i_part,
+                                                       int zero_inner) {
   double ro[2] = {0.0, 0.0};
   double ri[2] = {0.0, 0.0};
   const Col col = col_of<NDIM>(G, kc);
@@ -579,8 +580,10 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
       A.next();
       const float rf = (float)r;
       v32.r[P] = rf;
-      v32.x[P] = 0.0f;
-      v32.p0[P] = 0.0f;
+      if (zero_inner) {
+        v32.x[P] = 0.0f;
+        v32.p0[P] = 0.0f;
+      }
       ro[0] += r * r;
       ro[1] += bp * bp;
       ri[0] += (double)rf * (double)(rf * di);
@@ -601,7 +604,8 @@ __global__ __launch_bounds__(64 * TY) void k_residual64_3(Geo G, Stencil<3, doub
                                                          const double* __restrict__ b,
                                                          const double* __restrict__ x,
                                                          CgVectors<float> v32, int kc,
-                                                         double* o_part, double* i_part) {
+                                                         double* o_part, double* i_part,
+                                                         int zero_inner) {
   using St = Stage3<1, TY>;
   constexpr int HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double sx[2][HP], sd[2][HP];
@@ -664,8 +668,10 @@ __global__ __launch_bounds__(64 * TY) void k_residual64_3(Geo G, Stencil<3, doub
       const double r = bp - acc;
       const float rf = (float)r;
       v32.r[P] = rf;
-      v32.x[P] = 0.0f;
-      v32.p0[P] = 0.0f;
+      if (zero_inner) {
+        v32.x[P] = 0.0f;
+        v32.p0[P] = 0.0f;
+      }
       ro[0] += r * r;
       ro[1] += bp * bp;
       ri[0] += (double)rf * (double)(rf * di);
@@ -848,15 +854,15 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
                        const double* b, const double* x, const CgVectors<float>& v32,
                        double tol, double inner_tol, int inner_max, double* o_part,
-                       const CgWork& w32, CgScalars* sc64) {
+                       const CgWork& w32, CgScalars* sc64, bool zero_inner) {
   constexpr int TY = 8;  // 64x8 column tiles in 3D
   const ZPlan zp = G.ndim == 2 ? zplan(G) : zplan3(G, TY, ZTile<3>::KC);
   const int gu = zp.blocks;
   const dim3 grid(gu), block(kBlock);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1]);
+    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1], (int)zero_inner);
   else
-    hipLaunchKernelGGL(k_residual64_3<TY>, grid, dim3(64 * TY), 0, s, G, stencil<3, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1]);
+    hipLaunchKernelGGL(k_residual64_3<TY>, grid, dim3(64 * TY), 0, s, G, stencil<3, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1], (int)zero_inner);
   hipLaunchKernelGGL(k_residual_check, dim3(1), block, 0, s, (const double*)o_part,
                      (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, inner_max,
                      sc64, w32.sc);

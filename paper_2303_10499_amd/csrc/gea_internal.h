@@ -166,10 +166,12 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 
 // Mixed precision: FP64 residual r = b - A x and its FP32 copy as the inner
 // right-hand side, outer stop test and inner setup; x += dx.
+// (zero_inner: also clear the inner iterate and first direction, which a
+// Jacobi-PCG started on this set-up reads; the flexible CG needs neither)
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
                        const double* b, const double* x, const CgVectors<float>& v32,
                        double tol, double inner_tol, int inner_max, double* o_part,
-                       const CgWork& w32, CgScalars* sc64);
+                       const CgWork& w32, CgScalars* sc64, bool zero_inner = true);
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,
                         const double* dinv, float* c32, float* D32, float* dinv32);
 void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx);

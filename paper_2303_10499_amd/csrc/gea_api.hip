@@ -194,6 +194,7 @@ struct gea_ctx {
   bool has_state = false;
   bool has_system = false;
   bool sys32 = false;  // c32, D32, dinv32 hold the current operator
+  int res_parts = 0;   // partials of a first residual check the system build formed
   // Work that follows a converged solve (the corrector's correction),
   // enqueued by the refined forms right behind an outer residual check that
   // the previous step's same check found converged, before the host reads
@@ -499,11 +500,35 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
 
 // Pressure right-hand side and 1/diag from H; the refined forms also get the
 // FP32 copies of the operator from the same pass.
-void build_system(gea_ctx* x, const State& S) {
+// With xv given, a refined form's first residual check on xv (the solve's
+// initial guess) is formed in the same pass (3D); the solve then starts
+// from its one-workgroup check.
+void build_system(gea_ctx* x, const State& S, const double* xv = nullptr) {
   const bool f32 = x->prm.solver != GEA_PCG_JACOBI_FP64;
-  launch_rhs(x->stream, x->G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H, x->b, x->dinv,
-             f32 ? x->c32 : nullptr, f32 ? x->D32 : nullptr, f32 ? x->dinv32 : nullptr);
+  // the learned form's first inner solve is the flexible CG, which needs no
+  // cleared inner iterate or direction
+  const bool zero_inner = !(x->prm.solver == GEA_LEARNED_MIXED && x->has_net);
+  const RhsResidual res{xv, x->r32, x->d32, x->p032, (int)zero_inner, x->o_part, x->w32.u[1]};
+  x->res_parts = launch_rhs(x->stream, x->G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H,
+                            x->b, x->dinv, f32 ? x->c32 : nullptr, f32 ? x->D32 : nullptr,
+                            f32 ? x->dinv32 : nullptr, f32 && xv ? &res : nullptr);
   x->sys32 = f32;
+}
+
+// The refinement's residual check of xv: from the partials the system build
+// formed (first check of a solve), else a residual pass of its own.
+void residual_check(gea_ctx* x, const double* xv, const CgVectors<float>& v, int budget,
+                    bool zero_inner) {
+  const int n = x->res_parts;
+  x->res_parts = 0;
+  x->timer.run(4, x->stream, [&] {
+    if (n > 0)
+      launch_residual_check(x->stream, n, x->prm.tol, x->prm.inner_tol, budget > 0 ? budget : 1,
+                            x->o_part, x->w32, x->sc);
+    else
+      launch_residual64(x->stream, x->G, x->c, x->D, x->b, xv, v, x->prm.tol, x->prm.inner_tol,
+                        budget > 0 ? budget : 1, x->o_part, x->w32, x->sc, zero_inner);
+  });
 }
 
 // FP32 copies of the operator unless the system build wrote them.
@@ -565,10 +590,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
       break;
     }
     const int budget = x->prm.max_iter - total;
-    x->timer.run(4, x->stream, [&] {
-      launch_residual64(x->stream, G, x->c, x->D, x->b, xv, v, x->prm.tol,
-                        x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc);
-    });
+    residual_check(x, xv, v, budget, true);
     HIPCHK(hipGetLastError());
     const bool spec = x->predict_conv(outer);
     if (spec) (*x->tail)();
@@ -710,10 +732,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       break;
     }
     const int budget = x->prm.max_iter - total - unread_bound;
-    x->timer.run(4, x->stream, [&] {
-      launch_residual64(x->stream, G, x->c, x->D, x->b, xv, v, x->prm.tol,
-                        x->prm.inner_tol, budget > 0 ? budget : 1, x->o_part, w, x->sc, !use_net);
-    });
+    residual_check(x, xv, v, budget, !use_net);
     HIPCHK(hipGetLastError());
     // The learned inner solve goes out unread behind this check when the
     // same check did not converge last step and the resumed Jacobi-PCG's
@@ -851,7 +870,7 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
   for (int k = 0; k < nc; ++k) {
     const bool last = k == nc - 1;
     x->timer.run(5, x->stream, [&] { launch_H(s, G, ph, S.rho, S.u, x->ustar, x->phi, x->H); });
-    x->timer.run(5, x->stream, [&] { build_system(x, S); });
+    x->timer.run(5, x->stream, [&] { build_system(x, S, N.pp); });
     HIPCHK(hipGetLastError());
     x->has_system = true;
     double* uo[3] = {x->ustar[0], x->ustar[1], x->ustar[2]};

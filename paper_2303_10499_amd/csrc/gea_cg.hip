@@ -868,6 +868,12 @@ void launch_residual64(hipStream_t s, const Geo& G, const double* c, const doubl
                      sc64, w32.sc);
 }
 
+void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, int inner_max,
+                           const double* o_part, const CgWork& w32, CgScalars* sc64) {
+  hipLaunchKernelGGL(k_residual_check, dim3(1), dim3(kBlock), 0, s, o_part, (const double*)w32.u[1], n,
+                     tol * tol, inner_tol * inner_tol, inner_max, sc64, w32.sc);
+}
+
 void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter) {
   const int gu = zplan(G).blocks;  // the set-up partial buffer holds 2 values per block of this grid
   hipLaunchKernelGGL(k_cg_resume<float>, dim3(gu), dim3(kBlock), 0, s, G.nc, (const float*)v.r, v.dinv,

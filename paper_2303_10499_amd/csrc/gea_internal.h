@@ -75,6 +75,20 @@ ZPlan zplan3(const Geo& G, int ty, int kc);
 void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                       double* const* u, const double* T, double* const* phi, double* rho_star,
                       double* e0);
+// The refinement's first residual r = b - A x formed in the pass that forms
+// b (3D): the FP32 inner right-hand side, optionally the cleared inner
+// iterate and direction, and the 2 + 2 per-workgroup partials the residual
+// check reads (outer: ||r||^2, ||b||^2; inner: <r32, r32/diag>, ||r32||^2).
+struct RhsResidual {
+  const double* x;
+  float* r32;
+  float* x32;
+  float* p32;
+  int zero_inner;
+  double* o_part;
+  double* i_part;
+};
+
 // (pp_copy: p' is also copied there, or null)
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                         double* const* u, const double* pp, const double* rho_star,
@@ -86,10 +100,11 @@ void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const doub
                          const double* p, double* rho23, double* psi, double* c, double* D);
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,
               double* const* u_prev, double* const* phi, double* const* H);
-void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+int launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                 const double* rho23, const double* psi, const double* c, const double* D,
                 double* const* H, double* b, double* dinv, float* c32, float* D32,
-                float* dinv32);  // FP32 copies of c, D, 1/diag written unless c32 is null
+                float* dinv32,  // FP32 copies of c, D, 1/diag written unless c32 is null
+                const RhsResidual* res = nullptr);  // returns the residual partials' count, 0: not formed
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
                     const double* rho23, const double* psi, double* const* H, const double* D,
                     const double* rho_star, double* const* u_out, bool last,
@@ -166,6 +181,9 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 
 // Mixed precision: FP64 residual r = b - A x and its FP32 copy as the inner
 // right-hand side, outer stop test and inner setup; x += dx.
+// the residual check alone, on n partials a fused pass formed
+void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, int inner_max,
+                           const double* o_part, const CgWork& w32, CgScalars* sc64);
 // (zero_inner: also clear the inner iterate and first direction, which a
 // Jacobi-PCG started on this set-up reads; the flexible CG needs neither)
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,

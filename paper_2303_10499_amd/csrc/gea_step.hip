@@ -963,7 +963,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
 // k_rhs on a 3D mesh with the x/y neighbours of D, rho23, H_x and H_y staged
 // in LDS and the next plane's loads in flight while a plane is computed.
 // Same formulas and order as k_rhs.
-template <int TY>
+template <int TY, bool RES>
 __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
                                                  const double* __restrict__ rho,
                                                  const double* __restrict__ rho23,
@@ -972,16 +972,18 @@ __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
                                                  const double* __restrict__ D, Vec<3> H,
                                                  double* __restrict__ b, double* __restrict__ dinv,
                                                  float* __restrict__ c32, float* __restrict__ D32,
-                                                 float* __restrict__ dinv32) {
+                                                 float* __restrict__ dinv32, RhsResidual res) {
   using St = Stage3<1, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
-  __shared__ double ss[2][4][HP];  // D, rho23, H_x, H_y
+  constexpr int NF = RES ? 5 : 4;
+  __shared__ double ss[2][NF][HP];  // D, rho23, H_x, H_y (, x of the residual)
   const Col c = col_of3<TY>(G, kc);
   const St st = stage3<1, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
   const double kz_ = G.S[Z] / G.h[Z];
+  const double* __restrict__ xv = res.x;
   // raw values of the plane in flight
-  double fs[4][NU], fc, fr, fps, fDu, fHz, fHzu, fru;
+  double fs[NF][NU], fc, fr, fps, fDu, fHz, fHzu, fru, fxu = 0.0;
   auto fetch = [&](int kk) {
     const int o = pl * kk, P = qo + o;
 #pragma unroll
@@ -991,6 +993,7 @@ __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
       fs[1][m] = rho23[Q];
       fs[2][m] = H.p[0][Q];
       fs[3][m] = H.p[1][Q];
+      if (RES) fs[NF - 1][m] = xv[Q];
     }
     fc = cc[P];
     fr = rho[P];
@@ -1000,23 +1003,31 @@ __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
     fHz = H.p[Z][P];
     fHzu = H.p[Z][Pu];
     fru = rho23[Pu];
+    if (RES) fxu = xv[Pu];
   };
   double flux_lo = 0.0, diag_lo = 0.0;
+  double xm = 0.0, dm = 0.0;  // residual: x and D one plane down
   if (c.k0 > 0) {
     const int P = qo + pl * c.k0, Q = P - pl;
     flux_lo = phit_val(D[Q], D[P], H.p[Z][Q], H.p[Z][P], rho23[Q], rho23[P], G.S[Z],
                        phi_face<3>(G, ph, Z, c.k0 - 1, c.k0 - 1), G.inv_h[Z]);
     diag_lo = 0.5 * (D[Q] + D[P]) * kz_;
+    if (RES) {
+      xm = xv[Q];
+      dm = D[Q];
+    }
   }
+  double ro[2] = {0.0, 0.0}, ri[2] = {0.0, 0.0};
   fetch(c.k0);
   for (int k = c.k0; k < c.k1; ++k) {
     const int sl = k & 1;
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int m = 0; m < NU; ++m)
         if (st.has[m]) ss[sl][f][st.h[m]] = fs[f][m];
     const double cP = fc, rP = fr, psP = fps, D_up = fDu, Hz = fHz, Hz_up = fHzu, r23_up = fru;
+    const double x_up = fxu;
     fetch(k + 1 < c.k1 ? k + 1 : k);
     lds_barrier();
     const bool up = k + 1 < nz;
@@ -1055,9 +1066,30 @@ __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
     }
     flux_lo = flux_hi;
     diag_lo = diag_hi;
+    // residual of the solve's initial guess: the operator as the refinement
+    // residual kernel applies it, same order
+    double ax = 0.0;
+    if (RES) {
+      const double* Sx = ss[sl][NF - 1];
+      const double xc = Sx[ho];
+      const double xp = up ? x_up : 0.0, dp = up ? D_up : 0.0;
+      ax = cP * xc;
+#pragma unroll
+      for (int d = 0; d < Z; ++d) {
+        const int q = coord(c, d), sd = d == 0 ? 1 : HX;
+        const double kd = G.S[d] / G.h[d];
+        ax = q + 1 < G.n[d] ? ax + 0.5 * (Dc + SD[ho + sd]) * kd * (xc - Sx[ho + sd]) : ax;
+        ax = q > 0 ? ax + 0.5 * (SD[ho - sd] + Dc) * kd * (xc - Sx[ho - sd]) : ax;
+      }
+      if (up) ax += 0.5 * (Dc + dp) * kz_ * (xc - xp);
+      if (k > 0) ax += 0.5 * (dm + Dc) * kz_ * (xc - xm);
+      xm = xc;
+      dm = Dc;
+    }
     if (c.act) {
       const int P = qo + pl * k;
-      b[P] = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
+      const double bp = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
+      b[P] = bp;
       const double di = 1.0 / diag;
       dinv[P] = di;
       if (c32) {  // FP32 copies of the operator for the refined forms
@@ -1065,6 +1097,30 @@ __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
         D32[P] = (float)Dc;
         dinv32[P] = (float)di;
       }
+      if (RES) {
+        const double r = bp - ax;
+        const float rf = (float)r;
+        res.r32[P] = rf;
+        if (res.zero_inner) {
+          res.x32[P] = 0.0f;
+          res.p32[P] = 0.0f;
+        }
+        ro[0] += r * r;
+        ro[1] += bp * bp;
+        ri[0] += (double)rf * (double)(rf * (float)di);
+        ri[1] += (double)rf * (double)rf;
+      }
+    }
+  }
+  if (RES) {
+    double v[4] = {ro[0], ro[1], ri[0], ri[1]};
+    __shared__ double sh[4][TY];
+    Reducer<0u, 4, 64 * TY>::block(v, sh);
+    if (threadIdx.x == 0) {
+      res.o_part[blockIdx.x] = v[0];
+      res.o_part[gridDim.x + blockIdx.x] = v[1];
+      res.i_part[blockIdx.x] = v[2];
+      res.i_part[gridDim.x + blockIdx.x] = v[3];
     }
   }
 }
@@ -1526,15 +1582,21 @@ void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, do
     hipLaunchKernelGGL(k_H3<kTyH>, dim3(zp3.blocks), dim3(64 * kTyH), 0, s, G, ph, zp3.kc, rho, V3(u), V3(u_prev), V3(phi), V3(H));
 }
 
-void launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                const double* rho23, const double* psi, const double* c, const double* D,
-                double* const* H, double* b, double* dinv, float* c32, float* D32,
-                float* dinv32) {
+int launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+               const double* rho23, const double* psi, const double* c, const double* D,
+               double* const* H, double* b, double* dinv, float* c32, float* D32,
+               float* dinv32, const RhsResidual* res) {
   const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyRhs, kKcRhs) : zp;
-  if (G.ndim == 2)
+  if (G.ndim == 2) {
     hipLaunchKernelGGL(k_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, rho23, psi, c, D, V2(H), b, dinv, c32, D32, dinv32);
-  else
-    hipLaunchKernelGGL(k_rhs3<kTyRhs>, dim3(zp3.blocks), dim3(64 * kTyRhs), 0, s, G, ph, zp3.kc, rho, rho23, psi, c, D, V3(H), b, dinv, c32, D32, dinv32);
+    return 0;
+  }
+  if (res) {
+    hipLaunchKernelGGL((k_rhs3<kTyRhs, true>), dim3(zp3.blocks), dim3(64 * kTyRhs), 0, s, G, ph, zp3.kc, rho, rho23, psi, c, D, V3(H), b, dinv, c32, D32, dinv32, *res);
+    return zp3.blocks;
+  }
+  hipLaunchKernelGGL((k_rhs3<kTyRhs, false>), dim3(zp3.blocks), dim3(64 * kTyRhs), 0, s, G, ph, zp3.kc, rho, rho23, psi, c, D, V3(H), b, dinv, c32, D32, dinv32, RhsResidual{});
+  return 0;
 }
 
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,

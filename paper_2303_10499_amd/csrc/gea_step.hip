@@ -364,10 +364,10 @@ __global__ __launch_bounds__(64 * TY) void k_mom_predict3(Geo G, Phys ph, int kc
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
-  // raw values of the plane in flight
-  double fs[5][NU], frs, fz, fh[2], fl[2], fpu, fru, fzn[3];
+  // staged values of the plane in flight
+  double fs[5][NU];
   auto fetch = [&](int kk) {
-    const int o = pl * kk, P = qo + o;
+    const int o = pl * kk;
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
       const int Q = st.q[m] + o;
@@ -376,17 +376,6 @@ __global__ __launch_bounds__(64 * TY) void k_mom_predict3(Geo G, Phys ph, int kc
       fs[3][m] = pp[Q];
       fs[4][m] = rho[Q];
     }
-    frs = rho_star[P];
-    fz = phi.p[Z][P];
-    fh[0] = phi.p[0][P];
-    fh[1] = phi.p[1][P];
-    fl[0] = phi.p[0][Pxl + o];
-    fl[1] = phi.p[1][Pyl + o];
-    const int Pu = nb(kk + 1 < nz, P + pl, P), Pn = nb(kk + 3 < nz, P + 3 * pl, P);
-    fpu = pp[Pu];
-    fru = rho[Pu];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) fzn[cc] = u.p[cc][Pn];
   };
   Line z[3];
   double flo[3];
@@ -413,11 +402,16 @@ __global__ __launch_bounds__(64 * TY) void k_mom_predict3(Geo G, Phys ph, int kc
 #pragma unroll
       for (int m = 0; m < NU; ++m)
         if (st.has[m]) su[sl][f][st.h[m]] = fs[f][m];
-    const double rs = frs, phz = fz, p_up = fpu, r_up = fru;
-    const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
+    // the own cell's values of this plane, loaded before the next plane's
+    // staging loads (so waiting for them does not wait for those)
+    const int o = pl * k, P0 = qo + o;
+    const int Pu = nb(k + 1 < nz, P0 + pl, P0), Pn = nb(k + 3 < nz, P0 + 3 * pl, P0);
+    const double rs = rho_star[P0], phz = phi.p[Z][P0], p_up = pp[Pu], r_up = rho[Pu];
+    const double fhi[2] = {phi.p[0][P0], phi.p[1][P0]};
+    const double flod[2] = {phi.p[0][Pxl + o], phi.p[1][Pyl + o]};
     double zn[3];
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) zn[cc] = fzn[cc];
+    for (int cc = 0; cc < 3; ++cc) zn[cc] = u.p[cc][Pn];
     fetch(k + 1 < c.k1 ? k + 1 : k);
     lds_barrier();
     const bool up = k + 1 < nz;

@@ -841,8 +841,9 @@ void steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out = nullp
   const Geo& G = x->G;
   const Phys& ph = x->ph;
   hipStream_t s = x->stream;
-  x->timer.run(5, x->stream, [&] { launch_mass_flux(s, G, ph, S.rho, S.u, S.T, x->phi, x->rho_star, x->e0); });
-  x->timer.run(5, x->stream, [&] { launch_mom_predict(s, G, ph, S.rho, S.u, S.pp, x->rho_star, x->phi, x->ustar, pp_out); });
+  x->timer.run(5, x->stream, [&] {
+    launch_step1(s, G, ph, S.rho, S.u, S.T, S.pp, x->phi, x->rho_star, x->e0, x->ustar, pp_out);
+  });
   const double* e_prev = x->e0;
   const double* T_prev = S.T;
   const int ns = x->prm.n_energy_sweeps;

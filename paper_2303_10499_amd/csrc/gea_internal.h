@@ -89,6 +89,11 @@ struct RhsResidual {
   double* i_part;
 };
 
+// Step 1 (mass flux, rho*, e^n, momentum predictor): one pass in 3D, the two
+// kernels in 2D
+void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                  double* const* u, const double* T, const double* pp, double* const* phi,
+                  double* rho_star, double* e0, double* const* u_star, double* pp_copy);
 // (pp_copy: p' is also copied there, or null)
 void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                         double* const* u, const double* pp, const double* rho_star,

@@ -72,9 +72,6 @@ ZPlan zplan(const Geo& G);
 ZPlan zplan3(const Geo& G, int ty, int kc);
 
 // ---- explicit step kernels (gea_step.hip) ----------------------------------
-void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                      double* const* u, const double* T, double* const* phi, double* rho_star,
-                      double* e0);
 // The refinement's first residual r = b - A x formed in the pass that forms
 // b (3D): the FP32 inner right-hand side, optionally the cleared inner
 // iterate and direction, and the 2 + 2 per-workgroup partials the residual
@@ -90,14 +87,10 @@ struct RhsResidual {
 };
 
 // Step 1 (mass flux, rho*, e^n, momentum predictor): one pass in 3D, the two
-// kernels in 2D
+// kernels in 2D; pp_copy (or null) also receives p' (the solve's initial guess)
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
                   double* rho_star, double* e0, double* const* u_star, double* pp_copy);
-// (pp_copy: p' is also copied there, or null)
-void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                        double* const* u, const double* pp, const double* rho_star,
-                        double* const* phi, double* const* u_star, double* pp_copy);
 void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                          const double* e0, const double* e_prev, const double* T_prev,
                          double* const* phi, const double* rho_star, double* const* u_star,

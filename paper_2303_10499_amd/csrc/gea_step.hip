@@ -160,89 +160,6 @@ __global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
   }
 }
 
-// k_mass_flux on a 3D mesh with the x/y neighbourhoods of rho u_x and rho u_y
-// staged in LDS and the next plane's loads in flight while a plane is
-// computed.  Same formulas and order as k_mass_flux.
-template <int TY>
-__global__ __launch_bounds__(64 * TY) void k_mass_flux3(Geo G, Phys ph, int kc,
-                                                       const double* __restrict__ rho, Vec<3> u,
-                                                       const double* __restrict__ T, Vec<3> phi,
-                                                       double* __restrict__ rho_star,
-                                                       double* __restrict__ e0) {
-  using St = Stage3<2, TY>;
-  constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
-  __shared__ double sm[2][2][HP];  // rho u_x, rho u_y
-  const Col c = col_of3<TY>(G, kc);
-  const St st = stage3<2, TY>(G, c);
-  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
-  const double* uz = u.p[Z];
-  auto mz = [&](int Q) { return rho[Q] * uz[Q]; };
-  // raw values of the plane in flight
-  double fs[2][NU], fr, fT, fu[3], fzn;
-  auto fetch = [&](int kk) {
-    const int o = pl * kk, P = qo + o;
-#pragma unroll
-    for (int m = 0; m < NU; ++m) {
-      const int Q = st.q[m] + o;
-      const double rq = rho[Q];
-      fs[0][m] = rq * u.p[0][Q];
-      fs[1][m] = rq * u.p[1][Q];
-    }
-    fr = rho[P];
-    fT = T[P];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) fu[d] = u.p[d][P];
-    fzn = mz(nb(kk + 3 < nz, P + 3 * pl, P));
-  };
-  Line z;
-  double flo;
-  {
-    const int P = qo + pl * c.k0;
-    z = line_at(mz, P, pl, c.k0, nz);
-    flo = c.k0 > 0 ? i4_lo(z, c.k0, nz) * G.S[Z] : 0.0;
-  }
-  fetch(c.k0);
-  for (int k = c.k0; k < c.k1; ++k) {
-    const int sl = k & 1;
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-      for (int m = 0; m < NU; ++m)
-        if (st.has[m]) sm[sl][f][st.h[m]] = fs[f][m];
-    const double r = fr, Tc = fT, znext = fzn;
-    const double uc[3] = {fu[0], fu[1], fu[2]};
-    fetch(k + 1 < c.k1 ? k + 1 : k);
-    lds_barrier();
-    double sum = 0.0, hid[2];
-#pragma unroll
-    for (int d = 0; d < Z; ++d) {
-      const Line s = line_lds(sm[sl][d], ho, d == 0 ? 1 : HX);
-      const int n = G.n[d], q = coord(c, d);
-      const double hi = q + 1 < n ? i4_hi(s, q, n) * G.S[d] : 0.0;
-      const double lo = q > 0 ? i4_lo(s, q, n) * G.S[d] : 0.0;
-      hid[d] = hi;
-      sum += hi;
-      sum -= lo;
-    }
-    const double hi = k + 1 < nz ? i4_hi(z, k, nz) * G.S[Z] : 0.0;
-    sum += hi;
-    sum -= flo;
-    flo = hi;
-    double kin = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) kin += uc[d] * uc[d];
-    if (c.act) {
-      const int P = qo + pl * k;
-#pragma unroll
-      for (int d = 0; d < Z; ++d) phi.p[d][P] = hid[d];
-      phi.p[Z][P] = hi;
-      rho_star[P] = r - ph.dt / G.V * sum;
-      e0[P] = ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, k);
-    }
-    z = shift(z, k + 3 < nz ? znext : 0.0);
-  }
-}
-
 // rho* u* = rho u - dt/V [sum_out phi I4(u) - sum mu snGrad(u) S] - dt R(F)
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
@@ -346,133 +263,14 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
   }
 }
 
-// k_mom_predict on a 3D mesh with the x/y neighbourhoods of u, p' and rho
-// staged in LDS and the next plane's loads in flight while a plane is
-// computed.  Same formulas and order as k_mom_predict.
-template <int TY>
-__global__ __launch_bounds__(64 * TY) void k_mom_predict3(Geo G, Phys ph, int kc,
-                                                         const double* __restrict__ rho, Vec<3> u,
-                                                         const double* __restrict__ pp,
-                                                         const double* __restrict__ rho_star,
-                                                         Vec<3> phi, Vec<3> u_star,
-                                                         double* __restrict__ pp_copy) {
-  using St = Stage3<2, TY>;
-  constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
-  __shared__ double su[2][5][HP];  // u (3 components), p', rho
-  const Col c = col_of3<TY>(G, kc);
-  const St st = stage3<2, TY>(G, c);
-  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
-  const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
-  const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
-  // staged values of the plane in flight
-  double fs[5][NU];
-  auto fetch = [&](int kk) {
-    const int o = pl * kk;
-#pragma unroll
-    for (int m = 0; m < NU; ++m) {
-      const int Q = st.q[m] + o;
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) fs[cc][m] = u.p[cc][Q];
-      fs[3][m] = pp[Q];
-      fs[4][m] = rho[Q];
-    }
-  };
-  Line z[3];
-  double flo[3];
-  double Flo = 0.0;
-  {
-    const int P = qo + pl * c.k0;
-    const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      const double* uc = u.p[cc];
-      z[cc] = line_at([&](int Q) { return uc[Q]; }, P, pl, c.k0, nz);
-      flo[cc] = c.k0 > 0 ? phz_lo * i4_lo(z[cc], c.k0, nz) : 0.0;
-    }
-    if (c.k0 > 0)
-      Flo = force_val(pp[P - pl], pp[P], rho[P - pl], rho[P],
-                      phi_face<3>(G, ph, Z, c.k0 - 1, c.k0 - 1), G.inv_h[Z]);
-  }
-  fetch(c.k0);
-  const double kvz = ph.mu * G.S[Z] / G.h[Z];
-  for (int k = c.k0; k < c.k1; ++k) {
-    const int sl = k & 1;
-#pragma unroll
-    for (int f = 0; f < 5; ++f)
-#pragma unroll
-      for (int m = 0; m < NU; ++m)
-        if (st.has[m]) su[sl][f][st.h[m]] = fs[f][m];
-    // the own cell's values of this plane, loaded before the next plane's
-    // staging loads (so waiting for them does not wait for those)
-    const int o = pl * k, P0 = qo + o;
-    const int Pu = nb(k + 1 < nz, P0 + pl, P0), Pn = nb(k + 3 < nz, P0 + 3 * pl, P0);
-    const double rs = rho_star[P0], phz = phi.p[Z][P0], p_up = pp[Pu], r_up = rho[Pu];
-    const double fhi[2] = {phi.p[0][P0], phi.p[1][P0]};
-    const double flod[2] = {phi.p[0][Pxl + o], phi.p[1][Pyl + o]};
-    double zn[3];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) zn[cc] = u.p[cc][Pn];
-    fetch(k + 1 < c.k1 ? k + 1 : k);
-    lds_barrier();
-    const bool up = k + 1 < nz;
-    const double* Sp = su[sl][3];
-    const double* Sr = su[sl][4];
-    const double r = Sr[ho], pc = Sp[ho];
-    const double Fhi = up ? force_val(pc, p_up, r, r_up, phi_face<3>(G, ph, Z, k, k), G.inv_h[Z]) : 0.0;
-    const double inv_rs = 1.0 / rs;
-    double us[3];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      const Line s[2] = {line_lds(su[sl][cc], ho, 1), line_lds(su[sl][cc], ho, HX)};
-      double conv = 0.0, visc = 0.0;
-#pragma unroll
-      for (int d = 0; d < Z; ++d) {
-        const int n = G.n[d], q = coord(c, d);
-        conv = q + 1 < n ? conv + fhi[d] * i4_hi(s[d], q, n) : conv;
-        conv = q > 0 ? conv - flod[d] * i4_lo(s[d], q, n) : conv;
-      }
-      double fhz = 0.0;
-      if (up) {
-        fhz = phz * i4_hi(z[cc], k, nz);
-        conv += fhz;
-      }
-      if (k > 0) conv -= flo[cc];
-      flo[cc] = fhz;
-#pragma unroll
-      for (int d = 0; d < Z; ++d)
-        visc_add(visc, s[d], coord(c, d), G.n[d], ph.mu * G.S[d] / G.h[d], cc == d);
-      visc_add(visc, z[cc], k, nz, kvz, cc == Z);
-      double RF;
-      if (cc == Z) {
-        RF = 0.5 * (Flo + Fhi);
-      } else {
-        const int n = G.n[cc], q = coord(c, cc), sd = cc == 0 ? 1 : HX;
-        const double phf = phi_cell(G, ph, k);
-        const double hi = q + 1 < n ? force_val(pc, Sp[ho + sd], r, Sr[ho + sd], phf, G.inv_h[cc]) : 0.0;
-        const double lo = q > 0 ? force_val(Sp[ho - sd], pc, Sr[ho - sd], r, phf, G.inv_h[cc]) : 0.0;
-        RF = 0.5 * (lo + hi);
-      }
-      const double mom = r * z[cc].c - ph.dt / G.V * (conv - visc) - ph.dt * RF;
-      us[cc] = mom * inv_rs;
-    }
-    if (c.act) {
-      const int P = qo + pl * k;
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) u_star.p[cc][P] = us[cc];
-      if (pp_copy) pp_copy[P] = pc;
-    }
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
-    Flo = Fhi;
-  }
-}
-
-// Step 1 on a 3D mesh in one pass: k_mass_flux3's mass flux, rho* and e^n,
-// then k_mom_predict3's momentum predictor from them.  Every value the
-// predictor takes from the mass flux is the own cell's (its upper faces, the
-// lower faces of its own interpolation lines -- bitwise the neighbours' upper
-// faces -- and rho*), so nothing beyond the staged u, p' and rho is needed.
-// Same formulas and order as the two kernels.
+// Step 1 on a 3D mesh in one pass, with the x/y neighbourhoods of u, p' and
+// rho staged in LDS and the next plane's loads in flight while a plane is
+// computed: k_mass_flux's mass flux, rho* and e^n, then k_mom_predict's
+// momentum predictor from them.  Every value the predictor takes from the
+// mass flux is the own cell's (its upper faces, the lower faces of its own
+// interpolation lines -- bitwise the neighbours' upper faces -- and rho*), so
+// nothing beyond the staged u, p' and rho is needed.  Same formulas and order
+// as the two kernels.
 template <int TY>
 __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
                                                     const double* __restrict__ rho, Vec<3> u,
@@ -1684,46 +1482,26 @@ namespace {
 // rows of the column tiles of the LDS-staged 3D step kernels (taller tiles
 // re-read fewer halo rows; the two kernels with the most registers keep
 // 64x4 for occupancy)
-constexpr int kTyMass = 8, kTyMom = 4, kTyEnergy = 8, kTyH = 4, kTyRhs = 8, kTyCorr = 8;
+constexpr int kTyStep1 = 4, kTyEnergy = 8, kTyH = 4, kTyRhs = 8, kTyCorr = 8;
 // planes of a chunk (measured per kernel: 16, 32 and 64 tried)
-constexpr int kKcMass = 32, kKcMom = 32, kKcEnergy = 64, kKcH = 16, kKcRhs = 32, kKcCorr = 32,
-              kKcCorrLast = 64;
+constexpr int kKcStep1 = 64, kKcEnergy = 64, kKcH = 16, kKcRhs = 32, kKcCorr = 32, kKcCorrLast = 64;
 
 }  // namespace
 
 #define V2(a) vec<2>(a)
 #define V3(a) vec<3>(a)
 
-void launch_mass_flux(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                      double* const* u, const double* T, double* const* phi, double* rho_star,
-                      double* e0) {
-  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMass, kKcMass) : zp;
-  if (G.ndim == 2)
-    hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
-  else
-    hipLaunchKernelGGL(k_mass_flux3<kTyMass>, dim3(zp3.blocks), dim3(64 * kTyMass), 0, s, G, ph, zp3.kc, rho, V3(u), T, V3(phi), rho_star, e0);
-}
-
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
                   double* rho_star, double* e0, double* const* u_star, double* pp_copy) {
   if (G.ndim == 2) {
-    launch_mass_flux(s, G, ph, rho, u, T, phi, rho_star, e0);
-    launch_mom_predict(s, G, ph, rho, u, pp, rho_star, phi, u_star, pp_copy);
+    const ZPlan zp = zplan(G);
+    hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
+    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star), pp_copy);
     return;
   }
-  const ZPlan zp3 = zplan3(G, kTyMom, kKcMom);
-  hipLaunchKernelGGL(k_step1_3<kTyMom>, dim3(zp3.blocks), dim3(64 * kTyMom), 0, s, G, ph, zp3.kc, rho, V3(u), T, pp, V3(phi), rho_star, e0, V3(u_star), pp_copy);
-}
-
-void launch_mom_predict(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                        double* const* u, const double* pp, const double* rho_star,
-                        double* const* phi, double* const* u_star, double* pp_copy) {
-  const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyMom, kKcMom) : zp;
-  if (G.ndim == 2)
-    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star), pp_copy);
-  else
-    hipLaunchKernelGGL(k_mom_predict3<kTyMom>, dim3(zp3.blocks), dim3(64 * kTyMom), 0, s, G, ph, zp3.kc, rho, V3(u), pp, rho_star, V3(phi), V3(u_star), pp_copy);
+  const ZPlan zp3 = zplan3(G, kTyStep1, kKcStep1);
+  hipLaunchKernelGGL(k_step1_3<kTyStep1>, dim3(zp3.blocks), dim3(64 * kTyStep1), 0, s, G, ph, zp3.kc, rho, V3(u), T, pp, V3(phi), rho_star, e0, V3(u_star), pp_copy);
 }
 
 void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,

@@ -799,14 +799,6 @@ __global__ __launch_bounds__(256) void k_input_residual(int npix, const float* _
     put_input(p, r[p] * is, c[p] * dinv[p], x2, xin);
 }
 
-__global__ __launch_bounds__(256) void k_scale_output(int npix, const float* __restrict__ y,
-                                                      const double* __restrict__ s,
-                                                      float* __restrict__ out, int accumulate) {
-  const float sc = (float)*s;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x)
-    out[p] = accumulate ? out[p] + sc * y[p] : sc * y[p];
-}
-
 // master FP32 (W[co][t][ci], b) -> bf16 W[co_p][kpad] (k = t*cin_p + ci),
 // bf16 Wt[ci_p][kpad_t] (k' = flip(t)*cout_p + co), FP32 bias[co_p]
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ mW, const float* __restrict__ mb,
@@ -1659,10 +1651,6 @@ void cnn_input_from_residual(Cnn& n, const float* r, const double* inv_s, const 
                      n.d[0].npix, r, inv_s, c, dinv, n.x2, n.xin);
 }
 
-void cnn_scale_output(Cnn& n, const double* s, float* out, int accumulate) {
-  hipLaunchKernelGGL(k_scale_output, dim3(blocks_for(n.d[0].npix)), dim3(256), 0, n.s,
-                     n.d[0].npix, (const float*)n.y, s, out, accumulate);
-}
 
 void cnn_forward(Cnn& n) {
   if (n.ndim == 2) forward_t<2>(n);

@@ -79,7 +79,6 @@ int cnn_loss_partials(const Cnn& n);           // number of loss partials in lpa
 // from *inv_s on the device) and c/diag; out = s * y.
 void cnn_input_from_residual(Cnn& n, const float* r, const double* inv_s, const float* c,
                              const float* dinv);
-void cnn_scale_output(Cnn& n, const double* s, float* out, int accumulate);
 // inference only: the forward pass with the last layer writing out = (float)*s * y
 void cnn_forward_scaled(Cnn& n, const double* s, float* out);
 

@@ -318,7 +318,7 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->fsc = cv.take<FcgScalars>(1);
   // partials: 7 per workgroup of the iteration kernel's grid; 2 (and 1 for
   // ||b||^2) per workgroup of the set-up kernels' column-tile grid
-  const int ns = iter_grid(make_geo(m));
+  const int ns = std::max(iter_grid<double>(make_geo(m)), iter_grid<float>(make_geo(m)));
   const int nzb = zplan(make_geo(m)).blocks;
   for (CgWork* w : {&x->w64, &x->w32}) {
     w->s = cv.take<double>(7 * (size_t)ns);
@@ -328,6 +328,8 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   }
   x->w64.sc = x->sc;
   x->w32.sc = x->sc32;
+  x->w64.ns = iter_grid<double>(make_geo(m));
+  x->w32.ns = iter_grid<float>(make_geo(m));
   x->r_old32 = cv.take<float>(nc);
   x->z32 = cv.take<float>(nc);
   x->pair_part = cv.take<double>(3 * 2048);

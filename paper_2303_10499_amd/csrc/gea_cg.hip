@@ -39,7 +39,10 @@ namespace gea {
 
 namespace {
 
-constexpr int kTX3 = 64, kTY3 = 8, kKC3 = 16;  // 3D tile and z chunk
+constexpr int kTX3 = 64, kTY3 = 8;  // 3D tile
+// z chunk of the 3D iteration kernel
+template <typename T>
+constexpr int kKC3 = sizeof(T) == 8 ? 64 : 32;
 constexpr int kTX2 = 256, kKC2 = 16;           // 2D row segment and z chunk
 
 template <int NDIM, typename T>
@@ -265,10 +268,11 @@ __device__ __forceinline__ void iter_dots(double (&acc)[7], T p, T a, T r, T m) 
 }
 
 // 3D iteration kernel: a workgroup owns a 64 x 8 column tile and marches it
-// through a chunk of 16 planes.  Thread t stages its two own cells
-// (t % 64, t / 64) and (t % 64, t / 64 + 4) and, for t < 148, one halo cell of
-// the tile; each staged plane is loaded into registers one plane ahead (old
-// residual, old A p, old direction, D, 1/diag), turned into the new residual
+// through a chunk of planes (32 in FP32, 64 in FP64, whose loads carry twice
+// the bytes).  Thread t stages its two own cells (t % 64, t / 64) and
+// (t % 64, t / 64 + 4) and, for t < 148, one halo cell of the tile; each
+// staged plane is loaded into registers ahead (two planes in FP32, one in
+// FP64: old residual, old A p, old direction, D, 1/diag), turned into the new residual
 // and direction, and p and D are written to an LDS ring.  The own cells'
 // new residual and x update are stored there, and their residual and 1/diag
 // stay in the thread's registers for the dot products of the plane, which
@@ -276,7 +280,7 @@ __device__ __forceinline__ void iter_dots(double (&acc)[7], T p, T a, T r, T m) 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgIter<T> v,
                                                      double* part, CgScalars* sc) {
-  constexpr int TX = kTX3, TY = kTY3, KC = kKC3;
+  constexpr int TX = kTX3, TY = kTY3, KC = kKC3<T>;
   constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;
   constexpr int RPT = TX * TY / kBlock;  // own cells per thread
   constexpr int NH = HP - TX * TY;       // halo cells of a plane
@@ -349,32 +353,39 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
                      : qh[0];
   }
   const bool halo = threadIdx.x < NH;
-  T fr[NU], fq[NU], fp[NU], fd[NU], fm[NU], fx[RPT], fc[RPT];  // raw values of the plane in flight
-  auto fetch = [&](int kk) {
+  // raw values of a plane in flight: old residual, old A p, old direction,
+  // D, 1/diag of the staged cells, x and c of the own cells.  FP32 keeps two
+  // planes in flight (FP64 one, whose registers would cost occupancy): the
+  // set a plane is consumed from is refilled with the plane PF further on.
+  struct Raw {
+    T r[NU], q[NU], p[NU], d[NU], m[NU], x[RPT], c[RPT];
+  };
+  constexpr int PF = sizeof(T) == 8 ? 1 : 2;
+  auto fetch = [&](Raw& f, int kk) {
     const int o = plane * (kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk));
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int Q = qh[u] + o;
-      fr[u] = v.r_in[Q];
-      fq[u] = v.q_in[Q];
-      fp[u] = v.p_in[Q];
-      fd[u] = v.D[Q];
-      fm[u] = v.dinv[Q];
+      f.r[u] = v.r_in[Q];
+      f.q[u] = v.q_in[Q];
+      f.p[u] = v.p_in[Q];
+      f.d[u] = v.D[Q];
+      f.m[u] = v.dinv[Q];
       if (u < RPT) {  // own cell: x for its update, c for the operator
-        fx[u] = v.x[Q];
-        fc[u] = v.c[Q];
+        f.x[u] = v.x[Q];
+        f.c[u] = v.c[Q];
       }
     }
   };
-  fetch(k0 - 1);
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   // own cells' new residual, 1/diag and c of the last staged plane (the
   // compute step reads no global memory: a load issued after the next
-  // plane's loads would wait for all of them)
+  // planes' loads would wait for all of them)
   T r_own[RPT], m_own[RPT], c_own[RPT];
 #pragma unroll
   for (int m = 0; m < RPT; ++m) r_own[m] = m_own[m] = c_own[m] = T(0);
-  for (int kk = k0 - 1; kk <= k1; ++kk) {
+  // stage plane kk from f, refill f with plane kk + PF, compute plane kk - 1
+  auto plane_step = [&](Raw& f, int kk) {
     const int sl = (kk + NS) % NS;
     T r_prev[RPT], m_prev[RPT], c_prev[RPT];
 #pragma unroll
@@ -386,21 +397,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       if (u == RPT && !halo) break;
-      const T rn = fr[u] - alpha * fq[u];
-      sp[sl][hh[u]] = rn * fm[u] + beta * fp[u];
-      sd[sl][hh[u]] = fd[u];
+      const T rn = f.r[u] - alpha * f.q[u];
+      sp[sl][hh[u]] = rn * f.m[u] + beta * f.p[u];
+      sd[sl][hh[u]] = f.d[u];
       if (u < RPT) {
         r_own[u] = rn;
-        m_own[u] = fm[u];
-        c_own[u] = fc[u];
+        m_own[u] = f.m[u];
+        c_own[u] = f.c[u];
         if (kk >= k0 && kk < k1 && in[u]) {
           const int Q = qh[u] + plane * kk;
           v.r_out[Q] = rn;
-          v.x[Q] = fx[u] + alpha * fp[u];
+          v.x[Q] = f.x[u] + alpha * f.p[u];
         }
       }
     }
-    if (kk + 1 <= k1) fetch(kk + 1);
+    // FP32: refilled at every plane (the last two refills reload plane k1,
+    // an L2 hit), so that on every path the wait for one set leaves the
+    // other in flight
+    if (PF == 2 || kk + 1 <= k1) fetch(f, min(kk + PF, k1));
     lds_barrier();
     const int k = kk - 1;
     if (k >= k0 && k < k1) {
@@ -425,6 +439,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
       }
     }
     if (NS == 3) lds_barrier();
+  };
+  Raw f0, f1;
+  fetch(f0, k0 - 1);
+  if (PF == 2) {
+    // all of the first set's loads ahead of the second's, as in the loop
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(f1, k0);
+    int kk = k0 - 1;
+    for (; kk + 1 <= k1; kk += 2) {
+      plane_step(f0, kk);
+      plane_step(f1, kk + 1);
+    }
+    if (kk <= k1) plane_step(f0, kk);
+  } else {
+    for (int kk = k0 - 1; kk <= k1; ++kk) plane_step(f0, kk);
   }
   store_partials<7>(acc, part);
 }
@@ -791,11 +820,14 @@ Stencil<NDIM, T> stencil(const Geo& G) {
 
 }  // namespace
 
+template <typename T>
 int iter_grid(const Geo& G) {
   if (G.ndim == 3)
-    return ((G.nx + kTX3 - 1) / kTX3) * ((G.ny + kTY3 - 1) / kTY3) * ((G.nz + kKC3 - 1) / kKC3);
+    return ((G.nx + kTX3 - 1) / kTX3) * ((G.ny + kTY3 - 1) / kTY3) * ((G.nz + kKC3<T> - 1) / kKC3<T>);
   return ((G.nx + kTX2 - 1) / kTX2) * ((G.nz + kKC2 - 1) / kKC2);
 }
+template int iter_grid<double>(const Geo&);
+template int iter_grid<float>(const Geo&);
 
 template <typename T>
 void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w, double tol,
@@ -827,13 +859,13 @@ template <typename T>
 void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w) {
   const CgIter<T> it = iter_vectors(v, iter);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_cg_iter2<T>, dim3(iter_grid(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), it, w.s, w.sc);
+    hipLaunchKernelGGL(k_cg_iter2<T>, dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), it, w.s, w.sc);
   else
-    hipLaunchKernelGGL(k_cg_iter3<T>, dim3(iter_grid(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), it, w.s, w.sc);
+    hipLaunchKernelGGL(k_cg_iter3<T>, dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), it, w.s, w.sc);
 }
 
 void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w) {
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)w.s, iter_grid(G), iter, w.sc);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)w.s, w.ns, iter, w.sc);
 }
 
 template void cg_init<double>(hipStream_t, const Geo&, const CgVectors<double>&, const CgWork&, double, int);

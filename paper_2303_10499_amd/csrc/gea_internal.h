@@ -154,12 +154,14 @@ struct CgIter {
 // unused), b (||b||^2 at set-up).
 struct CgWork {
   double* s;
+  int ns;   // workgroups of the iteration kernel's grid (iter_grid of the precision)
   double* u[2];
   double* b;
   CgScalars* sc;
 };
 
-int iter_grid(const Geo& G);  // workgroups of the CG iteration kernel
+template <typename T>
+int iter_grid(const Geo& G);  // workgroups of the CG iteration kernel in precision T
 template <typename T>
 void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w, double tol,
              int max_iter);

@@ -117,6 +117,7 @@ def test_pressure_system_and_solve_match_oracle(oracle_lib, gea_mod):
     ("bubble3d_256x256x128", (24, 16, 20), 5),
     ("bubble3d_256x256x128", (13, 9, 11), 5),          # ragged 3D
     ("bubble3d_256x256x128", (70, 9, 10), 3),          # 3D halos across x and y tiles
+    ("bubble3d_256x256x128", (20, 150, 12), 2),        # several z chunks, ragged last chunk
 ])
 def test_steps_match_oracle(oracle_lib, gea_mod, name, dims, steps):
     nx, nz, ny = dims
@@ -196,7 +197,8 @@ def test_nonconvergence_rolls_back(oracle_lib, gea_mod):
 
 @pytest.mark.parametrize("name,dims", [("bubble2d_64x32", (64, 32, None)),
                                        ("nonsmooth2d_2048", (256, 256, None)),
-                                       ("bubble3d_256x256x128", (32, 16, 32))])
+                                       ("bubble3d_256x256x128", (32, 16, 32)),
+                                       ("bubble3d_256x256x128", (20, 150, 12))])
 def test_mixed_precision_reaches_fp64_residual(oracle_lib, gea_mod, name, dims):
     """FP32 inner CG with FP64 refinement: every solve's true FP64 residual
     meets tol, and each field is as close to the tightly solved oracle

@@ -522,13 +522,16 @@ __global__ __launch_bounds__(kBlock) void k_energy_sweep(
 
 // k_energy_sweep on a 3D mesh with the x/y neighbourhoods of e and T staged
 // in LDS and the next plane's loads in flight while a plane is computed.
-// Same formulas and order as k_energy_sweep.
-template <int TY>
-__global__ __launch_bounds__(64 * TY) void k_energy_sweep3(
+// Same formulas and order as k_energy_sweep.  LAST (the sweep that also
+// forms the pressure system's coefficients) is a template parameter, so the
+// other sweeps neither load p nor hold the registers of that part; those fit
+// in 128 VGPRs (two 512-thread workgroups per CU; the last sweep would spill).
+template <int TY, bool LAST>
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(LAST ? 1 : 4))) void k_energy_sweep3(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
     const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<3> phi,
     const double* __restrict__ rho_star, Vec<3> u_star, const double* __restrict__ Tbg,
-    double* __restrict__ e_next, double* __restrict__ T_next, int last,
+    double* __restrict__ e_next, double* __restrict__ T_next,
     const double* __restrict__ p, double* __restrict__ rho23, double* __restrict__ psi,
     double* __restrict__ cc, double* __restrict__ D) {
   using St = Stage3<2, TY>;
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_sweep3(
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
   // raw values of the plane in flight
-  double fs[2][NU], fh[2], fl[2], fz, frs, fr, fe0, fus[3], fen, fTn, fp;
+  double fs[2][NU], fh[2], fl[2], fz, frs, fr, fe0, fus[3], fen, fTn, fp = 0.0;
   auto fetch = [&](int kk) {
     const int o = pl * kk, P = qo + o;
 #pragma unroll
@@ -561,7 +564,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_sweep3(
     const int Pn = nb(kk + 3 < nz, P + 3 * pl, P);
     fen = e_prev[Pn];
     fTn = T_prev[Pn];
-    fp = p[P];  // read on every sweep (p is a valid field), used on the last
+    if (LAST) fp = p[P];
   };
   auto hhat = [&](const Line& e, const Line& T) {
     return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_sweep3(
       const int P = qo + pl * k;
       e_next[P] = e;
       T_next[P] = T;
-      if (last) {
+      if (LAST) {
         const double ps = 1.0 / (ph.R * T);
         const double r23 = pc * ps;
         rho23[P] = r23;
@@ -1512,8 +1515,10 @@ void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const doub
   const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy, kKcEnergy) : zp;
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_energy_sweep<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
+  else if (last)
+    hipLaunchKernelGGL((k_energy_sweep3<kTyEnergy, true>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, p, rho23, psi, c, D);
   else
-    hipLaunchKernelGGL(k_energy_sweep3<kTyEnergy>, dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
+    hipLaunchKernelGGL((k_energy_sweep3<kTyEnergy, false>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, p, rho23, psi, c, D);
 }
 
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,

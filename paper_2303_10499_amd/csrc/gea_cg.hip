@@ -43,7 +43,10 @@ constexpr int kTX3 = 64, kTY3 = 8;  // 3D tile
 // z chunk of the 3D iteration kernel
 template <typename T>
 constexpr int kKC3 = sizeof(T) == 8 ? 64 : 32;
-constexpr int kTX2 = 256, kKC2 = 16;           // 2D row segment and z chunk
+constexpr int kTX2 = 256;  // 2D row segment
+// z chunk of the 2D iteration kernel
+template <typename T>
+constexpr int kKC2 = sizeof(T) == 8 ? 16 : 32;
 
 template <int NDIM, typename T>
 struct Stencil {
@@ -459,14 +462,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
 }
 
 // 2D iteration kernel: a workgroup owns a 256-cell row segment and marches it
-// over 16 rows of z; each wave owns 64 consecutive cells.  The rows below and
+// over a chunk of rows of z (32 in FP32, 16 in FP64); each wave owns 64
+// consecutive cells.  The rows below and
 // above a cell stay in registers and x-neighbours come from the neighbouring
 // lanes (the first and last lane of a wave also load the cell just beyond the
 // wave), so the kernel needs neither LDS nor barriers.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgIter<T> v,
                                                      double* part, CgScalars* sc) {
-  constexpr int TX = kTX2, KC = kKC2;
+  constexpr int TX = kTX2, KC = kKC2<T>;
   static_assert(TX == kBlock, "one cell of the row segment per thread");
   if (load_done(sc)) return;
   const T alpha = (T)sc->alpha, beta = (T)sc->beta;
@@ -824,7 +828,7 @@ template <typename T>
 int iter_grid(const Geo& G) {
   if (G.ndim == 3)
     return ((G.nx + kTX3 - 1) / kTX3) * ((G.ny + kTY3 - 1) / kTY3) * ((G.nz + kKC3<T> - 1) / kKC3<T>);
-  return ((G.nx + kTX2 - 1) / kTX2) * ((G.nz + kKC2 - 1) / kKC2);
+  return ((G.nx + kTX2 - 1) / kTX2) * ((G.nz + kKC2<T> - 1) / kKC2<T>);
 }
 template int iter_grid<double>(const Geo&);
 template int iter_grid<float>(const Geo&);

@@ -1344,7 +1344,7 @@ void conv_fwd(const Cnn& n, int layer, const bf16_t* X, const bf16_t* A, void* Y
       break;
     case 4:
       if constexpr (NDIM == 3)
-        hipLaunchKernelGGL((k_conv_z<48, 32, 16, 32>), dim3(convz_tiles<48, 32, 16, 32>(d)), bl, 0, s, d,
+        hipLaunchKernelGGL((k_conv_z<48, 32, 16, 64>), dim3(convz_tiles<48, 32, 16, 64>(d)), bl, 0, s, d,
                            n.d[L.level + 1], X, A, n.Wz[4], n.bias[4], (bf16_t*)Y);
       else
         GEA_CONV(48, 16, 32);

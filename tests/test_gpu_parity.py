@@ -197,6 +197,7 @@ def test_nonconvergence_rolls_back(oracle_lib, gea_mod):
 
 @pytest.mark.parametrize("name,dims", [("bubble2d_64x32", (64, 32, None)),
                                        ("nonsmooth2d_2048", (256, 256, None)),
+                                       ("nonsmooth2d_2048", (96, 100, None)),  # ragged last z chunk
                                        ("bubble3d_256x256x128", (32, 16, 32)),
                                        ("bubble3d_256x256x128", (20, 150, 12))])
 def test_mixed_precision_reaches_fp64_residual(oracle_lib, gea_mod, name, dims):

@@ -129,7 +129,12 @@ enum {
 /* Bytes of device workspace needed for this mesh and parameter set. */
 gea_status gea_workspace_bytes(const gea_mesh* mesh, const gea_params* params, size_t* bytes);
 
-/* Create a context.  hip_stream is a hipStream_t (NULL = default stream);
+/* Create a context for a uniform hexahedral mesh of nx x ny x nz cells over
+ * lx x ly x lz metres, enclosed by impenetrable free-slip walls (the
+ * finite-volume setting of Sec. 3 and the closed box of Sec. 4; ny == 1 is
+ * the one-cell-thick xz-plane).  params holds the constants of Sec. 2 (R,
+ * c_p, c_v, g), the viscosity of Remark 1 and the time step of Sec. 3.
+ * hip_stream is a hipStream_t (NULL = default stream);
  * workspace is device memory of at least gea_workspace_bytes, owned by the
  * caller and kept alive until gea_destroy.  Returns GEA_ERR_ARG for
  * non-positive sizes or constants, more than 2^31 - 1 cells, or a short
@@ -147,7 +152,9 @@ gea_status gea_set_solver(gea_ctx* ctx, int32_t solver, double tol, int32_t max_
  * temperature perturbed by theta' at unchanged pressure, u = 0. */
 gea_status gea_init_bubble(gea_ctx* ctx, const gea_bubble* bubble);
 
-/* Copy a state in.  rho, T, p_prime, p: ncell values; u: ndim*ncell;
+/* Copy a state in: the given fields of the problem statement of Sec. 3
+ * (rho^n, u^n, T^n, p^n) and the split pressure p'^n = p^n + rho^n g z of
+ * eq. p_split.  rho, T, p_prime, p: ncell values; u: ndim*ncell;
  * T_bg: nz values (background temperature column that the energy diffusion
  * term subtracts).  All pointers of the given kind, none may be NULL. */
 gea_status gea_set_state(gea_ctx* ctx, const double* rho, const double* u, const double* T,
@@ -170,7 +177,13 @@ gea_status gea_pressure_solve(gea_ctx* ctx, const double* b, double* x, gea_ptr_
 gea_status gea_apply_pressure_operator(gea_ctx* ctx, const double* x, double* y,
                                        gea_ptr_kind kind);
 
-/* Copy the selected fields out, packed in bit order (see GEA_FIELD_*). */
+/* Copy the selected fields out, packed in bit order (see GEA_FIELD_*): the
+ * end-of-step state (rho, u, T, p', p)^{n+1} of the problem statement of
+ * Sec. 3, and the coefficients c, D and right-hand side b of the pressure
+ * system (eq. p_prime_sd, in the re-derived form stated at the top of this
+ * file) of the last assembly.  out: the caller's array of (number of
+ * selected fields, counting U as ndim) x ncell values, of the given kind;
+ * with GEA_DEVICE the copy is ordered on the context's stream. */
 gea_status gea_get_fields(gea_ctx* ctx, uint32_t field_mask, double* out, gea_ptr_kind kind);
 
 /* Measurement support.  With timing on, every kernel launch is bracketed by

@@ -163,6 +163,32 @@ def test_energy_e_to_T_round_trip_at_rest(oracle_lib):
     assert np.all(np.abs(Tn - s.T) <= 4 * np.finfo(float).eps * e / par["cv"])
 
 
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_energy_uses_old_density_and_kinetic_energy(oracle_lib, sweeps):
+    """eqs. step3_sd / step3_2sd with no face flux and no diffusion:
+    rho* e = rho^n e^n, e^n = c_v T^n + K^n + Phi, then T = (e - K* - Phi)/c_v.
+    rho* != rho^n and u* != u^n, so dividing by rho^n instead of rho*, or
+    forming e^n with K* (or T with K^n), changes the result."""
+    O, par = make(oracle_lib, mu=0.0, n_energy_sweeps=sweeps)
+    x, y, z, i, j, k = grid(O)
+    cv = par["cv"]
+    Phi = O.potential()
+    rho_n = 1.05 + 1e-4 * x - 2e-5 * z
+    rho_s = 0.93 + 3e-5 * z
+    u_n = np.zeros((2, O.nc))
+    u_n[0], u_n[1] = 12.0, -7.0 + 1e-3 * x
+    u_s = np.zeros((2, O.nc))
+    u_s[0], u_s[1] = -4.0 + 2e-3 * z, 9.0
+    T = 285.0 - 6e-3 * z + 1e-3 * x
+    Tbg = np.full(O.mesh.nz, 290.0)
+    phi0 = np.zeros((2, O.nc))
+    Tn = _energy(O, rho_n, u_n, T, u_s, rho_s, phi0, Tbg)
+    e_n = cv * T + 0.5 * (u_n ** 2).sum(0) + Phi
+    e = rho_n * e_n / rho_s
+    want = (e - 0.5 * (u_s ** 2).sum(0) - Phi) / cv
+    np.testing.assert_allclose(Tn, want, rtol=1e-13)
+
+
 def test_eos_coefficients(oracle_lib):
     O, par = make(oracle_lib)
     rng = np.random.default_rng(2)
@@ -209,6 +235,34 @@ def test_H_and_predicted_flux_closed_forms(oracle_lib):
     div_z = 0.9 * Sz * g * beta * m.lz / m.nz      # flux difference of the linear Phi_f
     want = V / dt * (rho + psi * r23 * g * z) - div_z
     np.testing.assert_allclose(b[inner], want[inner], rtol=1e-12)
+
+
+def test_H_takes_old_momentum_and_transports_previous_velocity(oracle_lib):
+    """H = rho^n u^n/dt - (1/V) sum_out phi I4(u^(k-1)) + (1/V) sum mu snGrad(u^(k-1)) S
+    (Step 3, corrector form of eq. step2_sd).  u^n and u^(k-1) differ: the
+    rho^n u^n/dt part must take u^n, the transport parts u^(k-1)."""
+    O, par = make(oracle_lib, mu=0.0)
+    x, y, z, i, j, k = grid(O)
+    m = O.mesh
+    dt = par["dt"]
+    rho = 1.0 + 1e-4 * z
+    u_n = np.zeros((2, O.nc))
+    u_n[0], u_n[1] = 3.0 - 1e-3 * x, 0.5 + 2e-4 * z
+    rng = np.random.default_rng(7)
+    u_prev = rng.uniform(-5.0, 5.0, (2, O.nc))
+    # no flux and no viscosity: H is the old momentum over dt, whatever u^(k-1) is
+    H = O.H(rho, u_n, u_prev, np.zeros((2, O.nc)))
+    np.testing.assert_allclose(H, rho * u_n / dt, rtol=1e-15)
+    # viscous part from u^(k-1) = 1 + a z^2 (Laplacian 2a), u^n linear in x
+    O2, par2 = make(oracle_lib, mu=3.0)
+    a = 2e-6
+    up = np.zeros((2, O.nc))
+    up[0] = 1.0 + a * z * z
+    phi, _ = O2.mass_predictor(np.ones(O.nc), up)
+    H2 = O2.H(np.ones(O.nc), u_n, up, phi)
+    sel = (i >= 1) & (i <= m.nx - 2) & (k >= 1) & (k <= m.nz - 2)
+    np.testing.assert_allclose(H2[0][sel], (u_n[0] / dt + 2 * a * par2["mu"])[sel], rtol=1e-12)
+    np.testing.assert_allclose(H2[1][sel], (u_n[1] / dt)[sel], rtol=1e-12)
 
 
 def test_corrector_closed_form(oracle_lib):

@@ -94,6 +94,21 @@ gea_status gea_load_weights(gea_ctx* ctx, const float* params, gea_ptr_kind kind
 gea_status gea_make_pair(gea_ctx* ctx, double rel_tol, float* in_r, float* in_a, float* out_d,
                          double* scale, gea_ptr_kind kind);
 
+/* Test support: the learned solver's network application exactly as its
+ * flexible CG makes it, on the pressure system of the context's last
+ * assembly (gea_pressure_solve or a step): r is an FP32 residual of npix
+ * values; the library forms s = max |r| (*scale, host) and
+ * z = s * net(r/s, c/diag) (npix FP32 values) with the loaded weights.
+ * GEA_ERR_STATE without weights or an assembled system.  Overwrites the
+ * solver's inner FP32 work vectors. */
+gea_status gea_learned_apply(gea_ctx* ctx, const float* r, float* z, double* scale,
+                             gea_ptr_kind kind);
+
+/* Test support: an activation of the context's network after its last
+ * application, as gea_cnn_activation (which = 1..9); which = 0 gives the two
+ * input channels (r/s, c/diag) per cell; the output y is not kept. */
+gea_status gea_learned_activation(gea_ctx* ctx, int32_t which, float* out, gea_ptr_kind kind);
+
 #ifdef __cplusplus
 }
 #endif

@@ -462,14 +462,16 @@ void read_scalars(gea_ctx* x, CgScalars* dev, CgScalars* host, const Extra& extr
 // residual's observed decay rate so that few launches follow convergence
 // (those find the done flag set and return at once).  A solve enqueued
 // behind kernels whose outcome the host has not read (hs.rr = 0 on entry)
-// takes its starting residual from the device scalars' rr0.
+// takes its starting residual from the device scalars' rr0.  A solve whose
+// first j0 iterations are already enqueued and read (hs) continues at
+// iteration j0.
 template <typename LaunchIter>
 gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int first_batch,
-                  LaunchIter&& launch_iter, const Extra& extra = Extra{}) {
+                  LaunchIter&& launch_iter, const Extra& extra = Extra{}, long j0 = 0) {
   const int every = x->prm.check_every > 0 ? x->prm.check_every : 8;
-  const long cap = (long)max_iter + 4L * every + 64;
+  const long cap = j0 + (long)max_iter + 4L * every + 64;
   int batch = first_batch > 0 ? first_batch : every;
-  long j = 0;
+  long j = j0;
   int prev_iter = hs.iter;
   double prev_rr = hs.rr;
   while (!hs.done) {
@@ -519,17 +521,19 @@ void build_system(gea_ctx* x, const State& S, const double* xv = nullptr) {
 
 // The refinement's residual check of xv: from the partials the system build
 // formed (first check of a solve), else a residual pass of its own.
+// With a gate the check acts only if the inner solve behind those scalars
+// is done.
 void residual_check(gea_ctx* x, const double* xv, const CgVectors<float>& v, int budget,
-                    bool zero_inner) {
+                    bool zero_inner, const CgScalars* gate = nullptr) {
   const int n = x->res_parts;
   x->res_parts = 0;
   x->timer.run(4, x->stream, [&] {
     if (n > 0)
       launch_residual_check(x->stream, n, x->prm.tol, x->prm.inner_tol, budget > 0 ? budget : 1,
-                            x->o_part, x->w32, x->sc);
+                            x->o_part, x->w32, x->sc, gate);
     else
       launch_residual64(x->stream, x->G, x->c, x->D, x->b, xv, v, x->prm.tol, x->prm.inner_tol,
-                        budget > 0 ? budget : 1, x->o_part, x->w32, x->sc, zero_inner);
+                        budget > 0 ? budget : 1, x->o_part, x->w32, x->sc, zero_inner, gate);
   });
 }
 
@@ -649,8 +653,8 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
 // the stop decision the iteration kernels return at once.)  When the last
 // iteration enqueued was the last allowed, it also formed the partials of
 // the resumed Jacobi-PCG's set-up: *res_parts is their count, else 0.
-int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
-  const Geo& G = x->G;
+// the flexible CG's vectors on the inner FP32 system
+FcgVectors& fcg_vectors(gea_ctx* x) {
   FcgVectors& v = x->fv;
   v.d = x->d32;
   v.r = x->r32;
@@ -663,6 +667,12 @@ int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
   v.D = x->D32;
   v.dinv = x->dinv32;
   v.p_cg = x->p032;
+  return v;
+}
+
+int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
+  const Geo& G = x->G;
+  FcgVectors& v = fcg_vectors(x);
   *res_parts = 0;
   x->timer.run(4, x->stream, [&] { fcg_start(x->stream, G, v, x->sc32, budget, x->fsc); });
   const int cap = steps < budget ? steps : budget;
@@ -705,6 +715,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   // (s_fcg, s_cg) arrive as snapshots with the next read.
   bool unread = false;
   int unread_bound = 0;  // iterations it may have taken
+  int unread_first = 0;  // Jacobi-PCG launches enqueued with it
   CgScalars s_res{}, s_cg{};
   FcgScalars s_fcg{};
   auto iterate = [&](int j) {
@@ -734,26 +745,29 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       break;
     }
     const int budget = x->prm.max_iter - total - unread_bound;
-    residual_check(x, xv, v, budget, !use_net);
+    // behind an unread inner solve the check acts only if that solve is done
+    residual_check(x, xv, v, budget, !use_net, unread ? x->sc32 : nullptr);
     HIPCHK(hipGetLastError());
     // The learned inner solve goes out unread behind this check when the
     // same check did not converge last step and the resumed Jacobi-PCG's
-    // length is known: its first batch is that length and four more, then
-    // the correction, then (next pass) the following check; one read then
-    // covers all.  (Were this check converged, the inner system starts done
-    // and the correction adds zero.)
+    // length is known: a first batch of that length and a margin, then the
+    // correction, then (next pass) the following check; one read then covers
+    // all.  (Were this check converged, the inner system starts done and the
+    // correction adds zero.)  The correction and the check are gated on the
+    // inner solve being done: when the batch fell short they do nothing, and
+    // after the read the same Jacobi-PCG continues where the batch ended.
     if (use_net && !unread && x->last_iters_res > 0 && x->predict_unconv(outer)) {
       snapshot(x, x->sc, &s_res, sizeof s_res);
       const int launched = learned_then_resume(budget > 0 ? budget : 1);
       use_net = false;
-      const int first = x->last_iters_res + 4;
-      for (int j = 0; j < first; ++j) iterate(j);
+      unread_first = x->last_iters_res + 4 + x->last_iters_res / 32;
+      for (int j = 0; j < unread_first; ++j) iterate(j);
       HIPCHK(hipGetLastError());
       snapshot(x, x->sc32, &s_cg, sizeof s_cg);
       snapshot(x, x->fsc, &s_fcg, sizeof s_fcg);
-      x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+      x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32); });
       unread = true;
-      unread_bound = launched + first;
+      unread_bound = launched + unread_first;
       ++outer;
       continue;
     }
@@ -771,6 +785,24 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       if (s_cg.status == -5) {
         out->status = GEA_ERR_NAN;
         break;
+      }
+      if (!s_cg.done) {
+        // The batch ended before the resumed Jacobi-PCG: the gated correction
+        // and check did nothing (h32 holds the solve's scalars as the batch
+        // left them).  Continue it at the next iteration, then correct.
+        const int before = h32.iter;
+        const int left = x->prm.max_iter - total;
+        gea_status rc = run_cg(x, x->sc32, h32, left > 0 ? left : 1, 0, iterate, Extra{},
+                               unread_first);
+        if (rc != GEA_OK) return rc;
+        total += h32.iter - before;
+        x->last_iters_res = h32.iter;
+        if (h32.status == -5) {
+          out->status = GEA_ERR_NAN;
+          break;
+        }
+        x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+        continue;
       }
     }
     x->note_conv(outer, h64.done != 0);
@@ -1329,6 +1361,38 @@ gea_status gea_make_pair(gea_ctx* x, double rel_tol, float* in_r, float* in_a, f
     x->has_system = true;
     return GEA_OK;
   });
+}
+
+gea_status gea_learned_apply(gea_ctx* x, const float* r, float* z, double* scale,
+                             gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!r || !z || !scale) return fail(x, GEA_ERR_ARG, "null argument");
+  if (!x->has_net) return fail(x, GEA_ERR_STATE, "no network weights loaded");
+  if (!x->has_system) return fail(x, GEA_ERR_STATE, "no assembled pressure system");
+  return guarded(x, [&]() {
+    const Geo& G = x->G;
+    hipStream_t s = x->stream;
+    cast_system(x);
+    HIPCHK(hipMemcpyAsync(x->r32, r, sizeof(float) * G.nc, kind_in(kind), s));
+    // the flexible CG's set-up forms s = max |r| and 1/s on the device
+    fcg_start(s, G, fcg_vectors(x), x->sc32, 1, x->fsc);
+    cnn_input_from_residual(x->net, x->r32, &x->fsc->inv_s, x->c32, x->dinv32);
+    cnn_forward_scaled(x->net, &x->fsc->s, x->z32);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(z, x->z32, sizeof(float) * G.nc, kind_out(kind), s));
+    FcgScalars hf;
+    const Extra part{x->fsc, &hf, sizeof hf};
+    read_structs(x, &part, 1);
+    *scale = hf.s;
+    return GEA_OK;
+  });
+}
+
+gea_status gea_learned_activation(gea_ctx* x, int32_t which, float* out, gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!out || which < 0 || which > 9) return fail(x, GEA_ERR_ARG, "bad activation");
+  if (!x->has_net) return fail(x, GEA_ERR_STATE, "no network weights loaded");
+  return cnn_copy_activation(x->net, which, out, kind, x->err);
 }
 
 void gea_destroy(gea_ctx* x) { delete x; }

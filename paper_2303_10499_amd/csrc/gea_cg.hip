@@ -86,6 +86,14 @@ __device__ __forceinline__ int load_done(CgScalars* sc) {
   return __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A kernel enqueued behind an inner solve whose outcome the host has not
+// read yet acts only once that solve is done (gate->done); with the gate
+// unset (null) it always acts.
+__device__ __forceinline__ bool gate_closed(const CgScalars* gate) {
+  return gate != nullptr &&
+         __hip_atomic_load(&gate->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
+
 template <int NDIM, typename T>
 __device__ __forceinline__ T apply_A_at(const Geo& G, const Stencil<NDIM, T>& K, const int* c,
                                         int P, const T* __restrict__ cc, const T* __restrict__ D,
@@ -596,7 +604,8 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
                                                        const double* __restrict__ x,
                                                        CgVectors<float> v32, int kc,
                                                        double* o_part, double* i_part,
-                                                       int zero_inner) {
+                                                       int zero_inner, const CgScalars* gate) {
+  if (gate_closed(gate)) return;
   double ro[2] = {0.0, 0.0};
   double ri[2] = {0.0, 0.0};
   const Col col = col_of<NDIM>(G, kc);
@@ -638,7 +647,8 @@ __global__ __launch_bounds__(64 * TY) void k_residual64_3(Geo G, Stencil<3, doub
                                                          const double* __restrict__ x,
                                                          CgVectors<float> v32, int kc,
                                                          double* o_part, double* i_part,
-                                                         int zero_inner) {
+                                                         int zero_inner, const CgScalars* gate) {
+  if (gate_closed(gate)) return;
   using St = Stage3<1, TY>;
   constexpr int HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double sx[2][HP], sd[2][HP];
@@ -720,7 +730,10 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
                                                            const double* i_part, int n,
                                                            double tol2, double inner_tol2,
                                                            int inner_max, CgScalars* sc64,
-                                                           CgScalars* sc32) {
+                                                           CgScalars* sc32, const CgScalars* gate) {
+  // (every thread reads the gate before sum_partials' barriers; thread 0
+  // writes sc32, which may be the gate, only after them)
+  if (gate_closed(gate)) return;
   double o[2], in[2];
   sum_partials<2>(o_part, n, o);
   sum_partials<2>(i_part, n, in);
@@ -810,7 +823,9 @@ __global__ __launch_bounds__(kBlock) void k_sub(int n, const double* b, double* 
     y[P] = b[P] - y[P];
 }
 
-__global__ __launch_bounds__(kBlock) void k_add_correction(int n, double* x, const float* dx) {
+__global__ __launch_bounds__(kBlock) void k_add_correction(int n, double* x, const float* dx,
+                                                           const CgScalars* gate) {
+  if (gate_closed(gate)) return;
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x)
     x[P] += (double)dx[P];
 }
@@ -890,24 +905,26 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
                        const double* b, const double* x, const CgVectors<float>& v32,
                        double tol, double inner_tol, int inner_max, double* o_part,
-                       const CgWork& w32, CgScalars* sc64, bool zero_inner) {
+                       const CgWork& w32, CgScalars* sc64, bool zero_inner,
+                       const CgScalars* gate) {
   constexpr int TY = 8;  // 64x8 column tiles in 3D
   const ZPlan zp = G.ndim == 2 ? zplan(G) : zplan3(G, TY, ZTile<3>::KC);
   const int gu = zp.blocks;
   const dim3 grid(gu), block(kBlock);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1], (int)zero_inner);
+    hipLaunchKernelGGL(k_residual64<2>, grid, block, 0, s, G, stencil<2, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1], (int)zero_inner, gate);
   else
-    hipLaunchKernelGGL(k_residual64_3<TY>, grid, dim3(64 * TY), 0, s, G, stencil<3, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1], (int)zero_inner);
+    hipLaunchKernelGGL(k_residual64_3<TY>, grid, dim3(64 * TY), 0, s, G, stencil<3, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1], (int)zero_inner, gate);
   hipLaunchKernelGGL(k_residual_check, dim3(1), block, 0, s, (const double*)o_part,
                      (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, inner_max,
-                     sc64, w32.sc);
+                     sc64, w32.sc, gate);
 }
 
 void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, int inner_max,
-                           const double* o_part, const CgWork& w32, CgScalars* sc64) {
+                           const double* o_part, const CgWork& w32, CgScalars* sc64,
+                           const CgScalars* gate) {
   hipLaunchKernelGGL(k_residual_check, dim3(1), dim3(kBlock), 0, s, o_part, (const double*)w32.u[1], n,
-                     tol * tol, inner_tol * inner_tol, inner_max, sc64, w32.sc);
+                     tol * tol, inner_tol * inner_tol, inner_max, sc64, w32.sc, gate);
 }
 
 void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter) {
@@ -927,8 +944,9 @@ void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const doub
   hipLaunchKernelGGL(k_cast_coeffs, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, c, D, dinv, c32, D32, dinv32);
 }
 
-void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx) {
-  hipLaunchKernelGGL(k_add_correction, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, x, dx);
+void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx,
+                           const CgScalars* gate) {
+  hipLaunchKernelGGL(k_add_correction, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, x, dx, gate);
 }
 
 void launch_sub(hipStream_t s, const Geo& G, const double* b, double* y) {

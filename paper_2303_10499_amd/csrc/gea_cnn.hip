@@ -1678,6 +1678,47 @@ void cnn_backward(Cnn& n, bool accumulate) {
   else backward_t<3>(n, accumulate);
 }
 
+// An activation of the last forward pass as FP32, channels last (see
+// gea_cnn_activation for `which`); which = 0 on an inference instance gives
+// the two input channels it keeps (r/s, c/diag per cell).
+gea_status cnn_copy_activation(Cnn& n, int which, float* out, gea_ptr_kind kind, std::string& err) {
+  auto ok = [&](hipError_t e) {
+    if (e == hipSuccess) return true;
+    err = std::string("HIP error in activation: ") + hipGetErrorString(e);
+    return false;
+  };
+  const hipMemcpyKind dir = kind == GEA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (which == 10) {
+    if (!ok(hipMemcpyAsync(out, n.y, sizeof(float) * n.d[0].npix, dir, n.s))) return GEA_ERR_HIP;
+    return ok(hipStreamSynchronize(n.s)) ? GEA_OK : GEA_ERR_HIP;
+  }
+  const bf16_t* src[10] = {n.xin, n.e0, n.p0, n.e1, n.p1, n.e2, n.c1, n.d1, n.c0, n.d0};
+  const int lev[10] = {0, 0, 1, 1, 2, 2, 1, 1, 0, 0};
+  int ch[10] = {8, 16, 16, 32, 32, 64, 96, 32, 48, 16};
+  if (which == 0 && !n.xin) {  // the 2-channel input: each x2 word holds (r/s, c/diag)
+    src[0] = reinterpret_cast<const bf16_t*>(n.x2);
+    ch[0] = 2;
+  }
+  if (!src[which]) {
+    err = "the concatenated inputs are kept by training instances only";
+    return GEA_ERR_STATE;
+  }
+  const long count = (long)n.d[lev[which]].npix * ch[which];
+  // host copies go through the FP32 input staging buffer (2 values a cell)
+  const long chunk = 2L * n.d[0].npix;
+  for (long off = 0; off < count; off += chunk) {
+    const long m = count - off < chunk ? count - off : chunk;
+    float* d = kind == GEA_HOST ? n.xf : out + off;
+    hipLaunchKernelGGL(k_bf16_to_f32, dim3(blocks_for(m)), dim3(256), 0, n.s, m, src[which] + off, d);
+    if (!ok(hipGetLastError())) return GEA_ERR_HIP;
+    if (kind == GEA_HOST) {
+      if (!ok(hipMemcpyAsync(out + off, n.xf, sizeof(float) * m, hipMemcpyDeviceToHost, n.s))) return GEA_ERR_HIP;
+      if (!ok(hipStreamSynchronize(n.s))) return GEA_ERR_HIP;
+    }
+  }
+  return ok(hipStreamSynchronize(n.s)) ? GEA_OK : GEA_ERR_HIP;
+}
+
 void cnn_adam(Cnn& n, float lr, float scale, int step) {
   const float bc1 = 1.f - powf(0.9f, (float)step), bc2 = 1.f - powf(0.999f, (float)step);
   hipLaunchKernelGGL(k_adam, dim3(blocks_for(n.nparams)), dim3(256), 0, n.s, n.nparams, n.master,
@@ -1822,37 +1863,7 @@ gea_status gea_cnn_adam(gea_cnn* x, float lr, float grad_scale, int32_t step) {
 
 gea_status gea_cnn_activation(gea_cnn* x, int32_t which, float* out, gea_ptr_kind kind) {
   if (!x || !out || which < 0 || which > 10) return GEA_ERR_ARG;
-  gea::Cnn& n = x->net;
-  const gea::bf16_t* src[10] = {n.xin, n.e0, n.p0, n.e1, n.p1, n.e2, n.c1, n.d1, n.c0, n.d0};
-  const int lev[10] = {0, 0, 1, 1, 2, 2, 1, 1, 0, 0};
-  const int ch[10] = {8, 16, 16, 32, 32, 64, 96, 32, 48, 16};
-  if (which == 10) {
-    gea_status st = hip_status(x, hipMemcpyAsync(out, n.y, sizeof(float) * n.d[0].npix, kout(kind), n.s), "activation");
-    if (st != GEA_OK) return st;
-    return hip_status(x, hipStreamSynchronize(n.s), "activation");
-  }
-  if (!src[which]) {
-    x->err = "the padded input and the concatenated inputs are kept by training instances only";
-    return GEA_ERR_STATE;
-  }
-  const long count = (long)n.d[lev[which]].npix * ch[which];
-  float* dst = out;
-  if (kind == GEA_HOST) {
-    dst = n.xf;  // staging: large enough only for the input; use a device copy per chunk
-  }
-  const long chunk = 2L * n.d[0].npix;
-  for (long off = 0; off < count; off += chunk) {
-    const long m = count - off < chunk ? count - off : chunk;
-    float* d = kind == GEA_HOST ? n.xf : out + off;
-    hipLaunchKernelGGL(gea::k_bf16_to_f32, dim3(gea::blocks_for_pub(m)), dim3(256), 0, n.s, m, src[which] + off, d);
-    if (kind == GEA_HOST) {
-      gea_status st = hip_status(x, hipMemcpyAsync(out + off, n.xf, sizeof(float) * m, hipMemcpyDeviceToHost, n.s), "activation");
-      if (st != GEA_OK) return st;
-      if ((st = hip_status(x, hipStreamSynchronize(n.s), "activation")) != GEA_OK) return st;
-    }
-  }
-  (void)dst;
-  return hip_status(x, hipStreamSynchronize(n.s), "activation");
+  return gea::cnn_copy_activation(x->net, which, out, kind, x->err);
 }
 
 void gea_cnn_destroy(gea_cnn* x) { delete x; }

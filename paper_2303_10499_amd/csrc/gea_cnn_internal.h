@@ -5,6 +5,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "gea.h"
 #include "gea_internal.h"
 
 namespace gea {
@@ -81,5 +84,7 @@ void cnn_input_from_residual(Cnn& n, const float* r, const double* inv_s, const 
                              const float* dinv);
 // inference only: the forward pass with the last layer writing out = (float)*s * y
 void cnn_forward_scaled(Cnn& n, const double* s, float* out);
+// an activation of the last forward pass as FP32 (test support)
+gea_status cnn_copy_activation(Cnn& n, int which, float* out, gea_ptr_kind kind, std::string& err);
 
 }  // namespace gea

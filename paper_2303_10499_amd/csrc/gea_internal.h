@@ -180,19 +180,25 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
                     const double* x, double* y);
 
 // Mixed precision: FP64 residual r = b - A x and its FP32 copy as the inner
-// right-hand side, outer stop test and inner setup; x += dx.
+// right-hand side, outer stop test and inner setup; x += dx.  With a gate
+// (the scalars of an inner solve enqueued ahead of the host's read) these
+// kernels do nothing unless that solve is done, so a solve cut short by its
+// batch can be continued on the same vectors.
 // the residual check alone, on n partials a fused pass formed
 void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, int inner_max,
-                           const double* o_part, const CgWork& w32, CgScalars* sc64);
+                           const double* o_part, const CgWork& w32, CgScalars* sc64,
+                           const CgScalars* gate = nullptr);
 // (zero_inner: also clear the inner iterate and first direction, which a
 // Jacobi-PCG started on this set-up reads; the flexible CG needs neither)
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
                        const double* b, const double* x, const CgVectors<float>& v32,
                        double tol, double inner_tol, int inner_max, double* o_part,
-                       const CgWork& w32, CgScalars* sc64, bool zero_inner = true);
+                       const CgWork& w32, CgScalars* sc64, bool zero_inner = true,
+                       const CgScalars* gate = nullptr);
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,
                         const double* dinv, float* c32, float* D32, float* dinv32);
-void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx);
+void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx,
+                           const CgScalars* gate = nullptr);
 // y = b - y
 void launch_sub(hipStream_t s, const Geo& G, const double* b, double* y);
 

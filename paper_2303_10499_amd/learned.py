@@ -30,10 +30,12 @@ def _lib():
         L.gea_cnn_destroy.restype = None
         L.gea_load_weights.argtypes = [vp, vp, C.c_int]
         L.gea_make_pair.argtypes = [vp, C.c_double, vp, vp, vp, P(C.c_double), C.c_int]
+        L.gea_learned_apply.argtypes = [vp, vp, vp, P(C.c_double), C.c_int]
+        L.gea_learned_activation.argtypes = [vp, C.c_int32, vp, C.c_int]
         for n in ("gea_cnn_param_count", "gea_cnn_workspace_bytes", "gea_cnn_create",
                   "gea_cnn_set_params", "gea_cnn_get_params", "gea_cnn_forward",
                   "gea_cnn_backward", "gea_cnn_get_grads", "gea_cnn_adam", "gea_load_weights",
-                  "gea_cnn_activation",
+                  "gea_cnn_activation", "gea_learned_apply", "gea_learned_activation",
                   "gea_make_pair"):
             getattr(L, n).restype = C.c_int
         L._learned_bound = True
@@ -164,3 +166,33 @@ class Net:
 
     def adam(self, lr, step, grad_scale=1.0):
         self._ok(self.L.gea_cnn_adam(self.h, float(lr), float(grad_scale), int(step)), "adam")
+
+
+def solver_apply(S, r):
+    """The learned solver's network application on the FP32 residual r (host
+    array of S.nc values) of solver S's last assembled system: (z, s) with
+    s = max |r| and z = s * net(r/s, c/diag)."""
+    r = np.ascontiguousarray(r, dtype=np.float32)
+    z = np.empty(S.nc, np.float32)
+    s = C.c_double(0.0)
+    rc = _lib().gea_learned_apply(S.ctx, C.c_void_p(r.ctypes.data), C.c_void_p(z.ctypes.data),
+                                  C.byref(s), gea.HOST)
+    if rc != gea.OK:
+        raise gea.GeaError(rc, S.L.gea_last_error(S.ctx).decode())
+    return z, s.value
+
+
+def solver_activation(S, name):
+    """an activation of solver S's network after solver_apply (FP32, grid
+    shape + channels); 'x2' gives the two input channels"""
+    if name == "x2":
+        which, level, ch = 0, 0, 2
+    else:
+        which, level, ch = Net.ACT[name]
+    m = S.mesh
+    sp = (m.nz >> level, m.nx >> level) if S.ndim == 2 else (m.nz >> level, m.ny >> level, m.nx >> level)
+    out = np.empty(int(np.prod(sp)) * ch, np.float32)
+    rc = _lib().gea_learned_activation(S.ctx, which, C.c_void_p(out.ctypes.data), gea.HOST)
+    if rc != gea.OK:
+        raise gea.GeaError(rc, S.L.gea_last_error(S.ctx).decode())
+    return out.reshape(sp + (ch,))

@@ -28,7 +28,8 @@ def L():
     ("gea.h", ("gea_init_mesh", "gea_set_state", "gea_step", "gea_pressure_solve",
                "gea_get_fields", "gea_time_network")),
     ("gea_learned.h", ("gea_cnn_forward", "gea_cnn_backward", "gea_cnn_adam",
-                       "gea_load_weights", "gea_make_pair")),
+                       "gea_load_weights", "gea_make_pair", "gea_learned_apply",
+                       "gea_learned_activation")),
 ])
 def test_every_declared_symbol_is_exported(L, header, must):
     names = declared(header)

@@ -65,7 +65,14 @@ def close_bf16(got, want, name, x=None, W=None, b=None):
     return frac
 
 
-@pytest.mark.parametrize("shape", [(16, 32), (8, 12, 16), (20, 36, 48)])
+# (36, 264): 2D, five 64-wide convolution tiles at full resolution, three at
+# half and two at quarter resolution, each with a ragged last tile; two
+# 256-wide layer-5 tiles, the second ragged; 16-row z chunks of layer 5.
+# (136, 12, 40): 3D, z chunks of layer 0 (32 planes: 5, ragged), layers 1
+# and 3 (16 planes of the 68 at half resolution: 5, ragged), layer 4 (64
+# planes: 3, ragged) and layer 5 (16 planes: 9, ragged); x rows of 16 cells
+# in 3 tiles at full resolution (ragged) and 2 at half.
+@pytest.mark.parametrize("shape", [(16, 32), (36, 264), (8, 12, 16), (20, 36, 48), (136, 12, 40)])
 def test_forward_layers_match_bf16_oracle(learned, shape):
     """each layer recomputed by the oracle from the GPU's own bf16 input of
     that layer (same bf16 products, only the FP32 summation order differs)"""
@@ -119,6 +126,107 @@ def test_gradients_match_oracle(learned, shape):
             assert e_gpu <= 1e-5, (k, j, e_gpu, e_bf)
             # and the gradient points the way the exact one does
             assert np.dot(a.ravel(), c.ravel()) > 0.9 * np.linalg.norm(a) * np.linalg.norm(c)
+
+
+def test_adam_matches_oracle(learned):
+    """three GPU Adam steps (FP32) on the GPU's own gradients against the
+    oracle's Adam step (Kingma & Ba, Algorithm 1) in FP64 from the same
+    parameters and gradients"""
+    shape = (8, 12, 16)
+    net, params, x = setup_net(learned, shape, seed=4)
+    rng = np.random.default_rng(11)
+    t = np.ascontiguousarray(rng.normal(size=int(np.prod(shape))), dtype=np.float32)
+    xf = np.ascontiguousarray(x.reshape(-1, 2), dtype=np.float32)
+    lr = 2e-3
+    p_or = learned.unpack(net.get_params().astype(np.float64), 3)
+    m = [[np.zeros_like(W), np.zeros_like(b)] for W, b in p_or]
+    v = [[np.zeros_like(W), np.zeros_like(b)] for W, b in p_or]
+    for step in (1, 2, 3):
+        net.forward(xf)
+        net.backward(t)
+        g = learned.unpack(net.get_grads().astype(np.float64), 3)
+        net.adam(lr, step)
+        p_or = cnn.adam_step(p_or, g, m, v, step, lr=lr)
+        p_gpu = learned.unpack(net.get_params().astype(np.float64), 3)
+        for k in range(6):
+            for j in range(2):
+                a, b = p_gpu[k][j], p_or[k][j]
+                # FP32 arithmetic of the update (a few ulps of it) and of the
+                # parameter (half an ulp a step)
+                tol = step * (1e-5 * lr + 2.0 ** -23 * np.abs(b))
+                assert np.all(np.abs(a - b) <= tol), (step, k, j, float(np.max(np.abs(a - b) / tol)))
+    # the steps moved the parameters by about lr each (Adam's normalised step)
+    moved = learned.unpack(net.get_params().astype(np.float64), 3)[4][0] - params[4][0]
+    assert 0.5 * lr < np.median(np.abs(moved)) <= 3 * lr * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("name,dims", [
+    ("nonsmooth2d_2048", (264, 36, None)),
+    ("bubble3d_256x256x128", (40, 136, 12)),
+])
+def test_solver_network_application_matches_oracle(learned, name, dims):
+    """The network application inside the learned solve (the flexible CG's
+    input kernel and scaled forward pass, with the shipped weights) on a
+    solver residual: s = max |r|, the input channels are bf16(r/s) and
+    bf16(c/diag), every layer equals the bf16 oracle recomputed from the
+    GPU's own input of that layer, and z = s y.  The shapes cross every
+    tile and z-chunk seam of the inference kernels."""
+    from paper_2303_10499_amd import gea
+    nx, nz, ny = dims
+    cfg = configs.scaled(name, nx, nz, ny)
+    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000)
+    S = gea.Solver(cfg["mesh"], cfg["params"], solver="learned")
+    S.load_weights()
+    S.init_bubble(**cfg["bubble"])
+    S.step(2)
+    pp = np.ascontiguousarray(S.state()["pp"])
+    x = pp.copy()
+    assert S.pressure_solve(x).status == 0      # assembles the next step's first system
+    b = S.get_fields(gea.FIELD_B)[0]
+    Ax = np.empty(S.nc)
+    S.apply_A(pp, Ax)
+    r = (b - Ax).astype(np.float32)
+    z, s = learned.solver_apply(S, r)
+    assert s == float(np.max(np.abs(r)))
+    params = learned.unpack(np.load(learned.weights_file(S.ndim), allow_pickle=False), S.ndim)
+    R = cnn.round_bf16
+    act = {k: learned.solver_activation(S, k) for k in ("x2", "e0", "p0", "e1", "p1", "e2", "d1", "d0")}
+    m = S.mesh
+    grid = (m.nz, m.nx) if S.ndim == 2 else (m.nz, m.ny, m.nx)
+    inv_s = np.float32(1.0 / s)
+    np.testing.assert_array_equal(act["x2"][..., 0], R(r.reshape(grid) * inv_s))
+    # c/diag, diag = c + sum_f w_f, from the FP32 copies of c and 1/diag:
+    # equal up to one bf16 rounding flip (1/diag may differ in its last bit)
+    c, D = S.get_fields(gea.FIELD_C | gea.FIELD_D)
+    cg, Dg = c.reshape(grid), D.reshape(grid)
+    h = [m.lz / m.nz, m.ly / m.ny, m.lx / m.nx] if S.ndim == 3 else [m.lz / m.nz, m.lx / m.nx]
+    V = float(np.prod(h)) if S.ndim == 3 else h[0] * h[1] * (m.ly / m.ny)
+    diag = cg.copy()
+    for ax in range(S.ndim):
+        w = 0.5 * (np.take(Dg, range(0, Dg.shape[ax] - 1), ax) + np.take(Dg, range(1, Dg.shape[ax]), ax)) \
+            * (V / h[ax]) / h[ax]
+        lo = [slice(None)] * S.ndim
+        hi = [slice(None)] * S.ndim
+        lo[ax], hi[ax] = slice(0, -1), slice(1, None)
+        diag[tuple(lo)] += w
+        diag[tuple(hi)] += w
+    want_a = R(cg.astype(np.float32) * (1.0 / diag).astype(np.float32))
+    close_bf16(act["x2"][..., 1], want_a, "c/diag")
+    (W0, b0), (W1, b1), (W2, b2), (W3, b3), (W4, b4), (W5, b5) = params
+    W0b = [R(W).astype(np.float64) for W, _ in params]
+    close_bf16(act["e0"], R(cnn.relu(cnn.conv(act["x2"], W0, b0, True))), "e0", act["x2"], W0b[0], b0)
+    np.testing.assert_array_equal(act["p0"], R(cnn.pool(act["e0"])))
+    close_bf16(act["e1"], R(cnn.relu(cnn.conv(act["p0"], W1, b1, True))), "e1", act["p0"], W0b[1], b1)
+    np.testing.assert_array_equal(act["p1"], R(cnn.pool(act["e1"])))
+    close_bf16(act["e2"], R(cnn.relu(cnn.conv(act["p1"], W2, b2, True))), "e2", act["p1"], W0b[2], b2)
+    c1 = np.concatenate([cnn.up(act["e2"]), act["e1"]], -1)
+    close_bf16(act["d1"], R(cnn.relu(cnn.conv(c1, W3, b3, True))), "d1", c1, W0b[3], b3)
+    c0 = np.concatenate([cnn.up(act["d1"]), act["e0"]], -1)
+    close_bf16(act["d0"], R(cnn.relu(cnn.conv(c0, W4, b4, True))), "d0", c0, W0b[4], b4)
+    y = cnn.conv(act["d0"], W5, b5, True).reshape(-1).astype(np.float64)
+    zs = np.float32(s) * y.astype(np.float32)
+    np.testing.assert_allclose(z, zs, rtol=0, atol=1e-5 * np.max(np.abs(zs)))
+    S.close()
 
 
 def test_training_reduces_loss(learned):
@@ -265,6 +373,8 @@ def test_trained_network_gain(learned, name):
     S.close()
     assert np.isfinite([e_net, rho_net, rho_jac, ea_net, ea_jac]).all()
     assert e_net <= 1.0 + 1e-6
+    # the network never costs the solve more than a few iterations
+    assert its["learned"][0] <= 1.02 * its["mixed"][0] + 10
     if S.ndim == 3:
         # the smooth 3D bubble: the network's correction is within a few per
         # cent of the exact one and one step along it beats a Jacobi step
@@ -354,3 +464,28 @@ def test_enqueue_ahead_survives_wrong_predictions(learned, form):
     u_a, u_b = states[form]["u"], states["pcg64"]["u"]
     print("u", float(np.max(np.abs(u_a - u_b)) / np.max(np.abs(u_b))))
     assert np.max(np.abs(u_a - u_b)) <= 1e-3 * np.max(np.abs(u_b))
+
+
+def test_learned_form_keeps_the_refinement_iteration_count_over_steps(learned):
+    """Over several steps the learned form sends each inner solve out ahead
+    of the host's read with a predicted first batch; a batch that falls short
+    must be continued, not restarted, so the learned form takes no more
+    inner iterations than the refinement alone (the 2D network gains little
+    here) beyond a small margin."""
+    from paper_2303_10499_amd import gea
+    its = {}
+    for form in ("mixed", "learned"):
+        cfg = configs.scaled("nonsmooth2d_2048", 512, 512)
+        cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=200000)
+        S = gea.Solver(cfg["mesh"], cfg["params"], solver=form)
+        if form == "learned":
+            S.load_weights()
+        S.init_bubble(**cfg["bubble"])
+        S.step(2)
+        st = S.step(8)
+        for k in range(st.n_solves):
+            assert st.solve[k].status == 0 and st.solve[k].rel_res <= 1e-8
+        its[form] = st.total_iters
+        S.close()
+    print("inner iterations over 8 steps", its)
+    assert its["learned"] <= 1.03 * its["mixed"] + 20

@@ -221,6 +221,27 @@ gea_status gea_time_solver_kernels(gea_ctx* ctx, int32_t reps, double* ms);
  * (GEA_ERR_STATE otherwise); overwrites only the network's activations. */
 gea_status gea_time_network(gea_ctx* ctx, int32_t reps, double* ms, double* gflop);
 
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the FP64
+ * Jacobi-PCG solve of gea_pressure_solve's FP64 form on a system the caller
+ * passes, with every work vector, partial sum and solver scalar in one
+ * static device array of the library (about 60 MB per GPU, held from the
+ * first call on a device until the process ends).  It allocates nothing
+ * and needs no context.
+ *   mesh: at most 2^20 cells (GEA_ERR_ARG beyond, see gea_last_error(NULL));
+ *   c, D, b: ncell device values of the system c_i x_i + sum_f w_f (x_i -
+ *     x_nb) = b_i, w_f = (D_P + D_N)/2 S_f/d_f (as gea_get_fields returns
+ *     them); x: ncell device values, in: initial guess, out: solution;
+ *   stops at ||b - A x||_2 <= tol ||b||_2 (recursive residual) or after
+ *   max_iter iterations (GEA_ERR_NOCONV); hip_stream: a stream of the
+ *   current device (NULL = default stream); stats: host, filled.
+ * Returns after the solve completed.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other threads, other streams) race
+ * and give wrong results. */
+gea_status gea_pressure_solve_static(const gea_mesh* mesh, const double* c, const double* D,
+                                     const double* b, double* x, double tol, int32_t max_iter,
+                                     void* hip_stream, gea_solve_stats* stats);
+
 /* Release the context (the workspace stays with its owner). */
 void gea_destroy(gea_ctx* ctx);
 

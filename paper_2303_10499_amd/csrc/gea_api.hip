@@ -260,6 +260,15 @@ Geo make_geo(const gea_mesh& m) {
   return G;
 }
 
+}  // namespace
+
+namespace gea {
+Geo mesh_geo(const gea_mesh& m) { return make_geo(m); }
+void set_call_error(const std::string& msg) { g_init_error = msg; }
+}  // namespace gea
+
+namespace {
+
 size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   const size_t nc = (size_t)m.nx * m.ny * m.nz;
   const int nd = m.ny == 1 ? 2 : 3;

@@ -87,6 +87,8 @@ def lib():
         L.gea_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_int64)]
         L.gea_time_solver_kernels.argtypes = [vp, C.c_int32, P(C.c_double)]
         L.gea_time_network.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_double)]
+        L.gea_pressure_solve_static.argtypes = [P(Mesh), dp, dp, dp, dp, C.c_double, C.c_int32,
+                                                vp, P(SolveStats)]
         L.gea_destroy.argtypes = [vp]
         L.gea_destroy.restype = None
         L.gea_last_error.argtypes = [vp]
@@ -94,7 +96,8 @@ def lib():
         for name in ("gea_workspace_bytes", "gea_init_mesh", "gea_set_solver", "gea_init_bubble",
                      "gea_set_state", "gea_step", "gea_pressure_solve",
                      "gea_apply_pressure_operator", "gea_get_fields", "gea_kernel_timing",
-                     "gea_kernel_times", "gea_time_solver_kernels", "gea_time_network"):
+                     "gea_kernel_times", "gea_time_solver_kernels", "gea_time_network",
+                     "gea_pressure_solve_static"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -259,3 +262,23 @@ class Solver:
         f = self.get_fields(FIELD_RHO | FIELD_U | FIELD_T | FIELD_PPRIME | FIELD_P)
         d = self.ndim
         return dict(rho=f[0], u=f[1:1 + d], T=f[1 + d], pp=f[2 + d], p=f[3 + d])
+
+
+def pressure_solve_static(mesh: dict, c, D, b, x, tol, max_iter=20000, stream=None):
+    """gea_pressure_solve_static: FP64 Jacobi-PCG of the system (c, D, b) from
+    the initial guess in x (solution written to x); c, D, b, x contiguous FP64
+    CUDA tensors of ncell values.  Allocates no device memory."""
+    import torch
+    for a in (c, D, b, x):
+        assert isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+    m = make_mesh(mesh)
+    st = SolveStats()
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    L = lib()
+    rc = L.gea_pressure_solve_static(C.byref(m), C.c_void_p(c.data_ptr()), C.c_void_p(D.data_ptr()),
+                                     C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
+                                     int(max_iter), C.c_void_p(stream.cuda_stream), C.byref(st))
+    if rc != OK:
+        raise GeaError(rc, L.gea_last_error(None).decode())
+    return st

@@ -89,3 +89,20 @@ def test_workspace_fits_the_largest_workload(L):
     n = C.c_size_t(0)
     assert L.gea_workspace_bytes(C.byref(m), C.byref(p), C.byref(n)) == gea.OK
     assert n.value < 64 * 2**30   # well inside one GPU's 288 GB
+
+
+def test_static_solve_argument_errors(L):
+    """the allocation-free solve rejects bad arguments and meshes beyond its
+    static work area before any device work"""
+    from paper_2303_10499_amd import gea
+    buf = (C.c_double * 4)()
+    p = C.cast(buf, C.c_void_p)
+    st = gea.SolveStats()
+    big = gea.Mesh(1024, 1, 1025, 1.0, 1.0, 1.0)
+    rc = L.gea_pressure_solve_static(C.byref(big), p, p, p, p, 1e-8, 100, None, C.byref(st))
+    assert rc == gea.ERR_ARG and b"static work area" in L.gea_last_error(None)
+    ok = gea.Mesh(64, 1, 32, 1.0, 1.0, 1.0)
+    assert L.gea_pressure_solve_static(C.byref(ok), None, p, p, p, 1e-8, 100, None, C.byref(st)) == gea.ERR_ARG
+    assert L.gea_pressure_solve_static(C.byref(ok), p, p, p, p, 0.0, 100, None, C.byref(st)) == gea.ERR_ARG
+    neg = gea.Mesh(0, 1, 32, 1.0, 1.0, 1.0)
+    assert L.gea_pressure_solve_static(C.byref(neg), p, p, p, p, 1e-8, 100, None, C.byref(st)) == gea.ERR_ARG

@@ -9,13 +9,22 @@ dataset).  Every solver form is timed on the same workload and tolerance:
 plain FP64 Jacobi-PCG, FP32/FP64 iterative refinement, and the learned
 initial guess/preconditioner when its weights are present.
 
-Prints one JSON line (see the design doc for the fields).
+Two measurements per form:
+  * the timed window: W warm-up steps, then exactly K steps between HIP
+    events on the solver's stream (`value`, `ms_per_step`);
+  * the full run: the whole evaluation run from the initial state (200
+    steps in 3D, 500 on the 2D 2048^2 mesh), timed as one piece, the median
+    of several repetitions in 3D (`full_run`).
+Every solve's exit residual is reported (`max_rel_res`), unrounded.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -24,13 +33,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-# algorithmic bytes per cell of one launch of each kernel class (each array
-# read or written once; halo re-reads are not counted)
-BYTES_PER_CELL = {
-    0: 88.0,   # FP64 CG iteration: read r, A p, p (old), x, 1/diag, c, D; write r, p, A p, x
-    2: 44.0,   # FP32 CG iteration (same arrays in FP32)
-}
+# Algorithmic bytes per cell of one Jacobi-PCG iteration: the operator
+# (read p, c, D; write A p: 32 B), the update (read x, p, r, A p, 1/diag;
+# write x, r: 56 B) and the new direction (read r, 1/diag, p; write p: 32 B)
+# with every array read or written once: 120 B in FP64, 60 B in FP32 (the
+# refined forms' inner iterations).
+ALG_BYTES_PER_CELL = {0: 120.0, 2: 60.0}
+# What the fused iteration kernel itself must move: 11 arrays (read r, A p,
+# p, x, 1/diag, c, D; write r, p, A p, x).
+FUSED_BYTES_PER_CELL = {0: 88.0, 2: 44.0}
 CLASS_NAMES = {0: "k_cg_iter<fp64>", 1: "k_cg_scalars<fp64>", 2: "k_cg_iter<fp32>",
                3: "k_cg_scalars<fp32>", 4: "solver set-up kernels",
                5: "explicit step kernels", 6: "learned network"}
@@ -41,67 +52,83 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 # vector bf16 pair dot products (layer 5): 256 CUs x 64 lanes x 2.4 GHz x 4 FLOP
 VALU_DOT2_PEAK_TFLOPS = 157.3
 
-
-def log(msg):
-    print(msg, file=sys.stderr, flush=True)
-
-
 # solver forms: (library solver, learned_steps)
 FORMS = {"pcg64": ("pcg64", 1), "mixed": ("mixed", 1), "learned": ("learned", 1),
          "learned_fcg": ("learned", 25)}
 
 
-def run_form(cfg, form, steps, warmup, kernel_steps):
-    import torch
-    from paper_2303_10499_amd import gea
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
+
+def sig(v, n=6):
+    """a float to n significant digits (small values keep their exponent)"""
+    return float(f"{v:.{n}g}") if isinstance(v, float) else v
+
+
+def clean(d):
+    return {k: (clean(v) if isinstance(v, dict) else sig(v)) for k, v in d.items()}
+
+
+def timed_steps(S, n):
+    """n steps between two events on the solver's stream: (ms, stats)"""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(S.stream)
+    st = S.step(n)
+    e1.record(S.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), st
+
+
+def make_solver(cfg, form):
+    from paper_2303_10499_amd import gea
     solver, lsteps = FORMS[form]
     params = dict(cfg["params"], learned_steps=lsteps)
     S = gea.Solver(cfg["mesh"], params, solver=solver)
     if solver == "learned":
         S.load_weights()
-    S.init_bubble(**cfg["bubble"])
-    stream = S.stream
+    return S
+
+
+def run_window(cfg, form, steps, warmup, kernel_steps):
+    """the timed window of a form, its kernel accounting and roofline candidates"""
+    solver, lsteps = FORMS[form]
+    S = make_solver(cfg, form)
     nc = S.nc
-    t0 = time.time()
+    S.init_bubble(**cfg["bubble"])
     if warmup:
         S.step(warmup)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    st = S.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    log(f"[bench] {cfg['name']} {form}: {steps} steps in {ms:.1f} ms "
-        f"({time.time() - t0:.1f} s wall incl. warmup)")
+    ms, st = timed_steps(S, steps)
+    log(f"[bench] {cfg['name']} {form}: {steps} steps in {ms:.1f} ms")
     out = dict(solver=solver, learned_steps=lsteps if solver == "learned" else None,
                ms_per_step=ms / steps, cell_steps_per_s=nc * steps / (ms * 1e-3),
                iters_per_solve=st.total_iters / max(st.total_solves, 1),
-               rel_res_last=max(st.solve[k].rel_res for k in range(st.n_solves)),
-               fallbacks_last_step=sum(st.solve[k].fallbacks for k in range(st.n_solves)),
+               max_rel_res=st.max_rel_res, fallbacks=st.total_fallbacks,
                eos_mismatch=st.eos_mismatch)
-    # launches per step of each kernel class, from a second window of steps
-    # with the per-launch event timer (events around every launch inflate
-    # short kernels, so its times are only used for the explicit kernels'
-    # share; kept out of the timed region above)
+    # A second window with the per-launch event timer (events around every
+    # launch inflate short kernels; kept out of the timed window above).
+    # Launches that find their solve already done return at once: the
+    # per-step device time of the CG iteration kernel counts only the
+    # launches that did an iteration.
     S.kernel_timing(True, reset=True)
-    S.step(kernel_steps)
+    st_k = S.step(kernel_steps)
     kms, kn = S.kernel_times()
     S.kernel_timing(False)
-    # accurate per-launch durations of the CG kernels: reps back-to-back
-    # launches between two events on the solver's stream
-    avg = S.time_solver_kernels(reps=50)
+    iters_per_step = st_k.total_iters / kernel_steps
+    avg = S.time_solver_kernels(reps=50)   # back-to-back launches between two events
     out["kernel_avg_us"] = {CLASS_NAMES[k]: round(avg[k] * 1e3, 2) for k in range(4)}
     out["launches_per_step"] = {CLASS_NAMES[k]: kn[k] / kernel_steps for k in range(7) if kn[k]}
+    out["iterations_per_step"] = iters_per_step
     out["explicit_ms_per_step_event_timed"] = kms[5] / kernel_steps
-    # candidates for the dominant kernel: device time per step = average
-    # launch duration x launches per step
     cands = {}
-    for k in BYTES_PER_CELL:
-        if kn[k]:
-            cands[CLASS_NAMES[k]] = dict(bound="hbm", avg_ms=avg[k], per_step_ms=avg[k] * kn[k] / kernel_steps,
-                                         work=BYTES_PER_CELL[k] * nc)
+    it_class = 0 if solver == "pcg64" else 2
+    cands[CLASS_NAMES[it_class]] = dict(bound="hbm", avg_ms=avg[it_class],
+                                        per_step_ms=avg[it_class] * iters_per_step,
+                                        bytes_alg=ALG_BYTES_PER_CELL[it_class] * nc,
+                                        bytes_fused=FUSED_BYTES_PER_CELL[it_class] * nc,
+                                        per_cell=(ALG_BYTES_PER_CELL[it_class], FUSED_BYTES_PER_CELL[it_class]))
     if solver == "learned":
         nms, ngf = S.time_network(reps=20)
         apps = kn[6] / kernel_steps
@@ -109,44 +136,87 @@ def run_form(cfg, form, steps, warmup, kernel_steps):
         out["network_layer_avg_us"] = {LAYER_NAMES[l]: round(nms[l] * 1e3, 2) for l in range(6)}
         for l in range(6):
             cands[LAYER_NAMES[l]] = dict(bound="alu" if l == 5 else "mfma", avg_ms=nms[l],
-                                         per_step_ms=nms[l] * apps,
-                                         work=ngf[l] * 1e9)
+                                         per_step_ms=nms[l] * apps, flop=ngf[l] * 1e9)
     out["kernel_ms_per_step"] = {k: round(v["per_step_ms"], 4) for k, v in cands.items()}
-    if cands:
-        dom = max(cands, key=lambda k: cands[k]["per_step_ms"])
-        out["roofline"] = dict(kernel=dom, **cands[dom])
+    dom = max(cands, key=lambda k: cands[k]["per_step_ms"])
+    out["_roofline"] = dict(kernel=dom, **cands[dom])
     S.close()
     return out
 
 
+def run_full(cfg, form, nsteps, reps):
+    """the whole evaluation run from the initial state, reps times"""
+    S = make_solver(cfg, form)
+    nc = S.nc
+    runs = []
+    for r in range(reps):
+        S.init_bubble(**cfg["bubble"])
+        ms, st = timed_steps(S, nsteps)
+        runs.append(dict(ms=ms, iters_per_solve=st.total_iters / max(st.total_solves, 1),
+                         max_rel_res=st.max_rel_res, fallbacks=st.total_fallbacks))
+        log(f"[bench] {cfg['name']} {form}: full run of {nsteps} steps #{r + 1}: {ms:.1f} ms, "
+            f"{runs[-1]['iters_per_solve']:.2f} iterations a solve, max rel_res {st.max_rel_res:.3e}")
+    S.close()
+    med = statistics.median(r["ms"] for r in runs)
+    return dict(steps=nsteps, reps=reps, cell_steps_per_s=nc * nsteps / (med * 1e-3),
+                ms_per_step=med / nsteps, runs_ms=[round(r["ms"], 2) for r in runs],
+                iters_per_solve=runs[0]["iters_per_solve"],
+                max_rel_res=max(r["max_rel_res"] for r in runs),
+                fallbacks=sum(r["fallbacks"] for r in runs))
+
+
 def roofline_entry(rr):
-    """the roofline object of a kernel candidate (see run_form)"""
+    """the roofline object of a kernel candidate (see run_window)"""
     t = rr["avg_ms"] * 1e-3
     if rr["bound"] == "hbm":
-        achieved, peak, unit = rr["work"] / t / 1e9, HBM_PEAK_GBS, "GB/s"
-        extra = dict(bytes_per_launch=rr["work"])
-    else:
-        peak = MFMA_BF16_PEAK_TFLOPS if rr["bound"] == "mfma" else VALU_DOT2_PEAK_TFLOPS
-        achieved, unit = rr["work"] / t / 1e12, "TFLOP/s"
-        extra = dict(flop_per_launch=rr["work"])
+        achieved = rr["bytes_alg"] / t / 1e9
+        fused = rr["bytes_fused"] / t / 1e9
+        return dict(bound="hbm", kernel=rr["kernel"], achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    avg_launch_us=round(rr["avg_ms"] * 1e3, 2),
+                    bytes_per_cell=rr["per_cell"][0], bytes_per_launch=rr["bytes_alg"],
+                    fused_bytes_per_cell=rr["per_cell"][1], achieved_fused=round(fused, 1),
+                    frac_fused=round(fused / HBM_PEAK_GBS, 4),
+                    traffic=read_traffic(rr["kernel"]))
+    peak = MFMA_BF16_PEAK_TFLOPS if rr["bound"] == "mfma" else VALU_DOT2_PEAK_TFLOPS
+    achieved = rr["flop"] / t / 1e12
     return dict(bound=rr["bound"], kernel=rr["kernel"], achieved=round(achieved, 1), peak=peak,
-                unit=unit, frac=round(achieved / peak, 4), avg_launch_us=round(rr["avg_ms"] * 1e3, 2),
-                **extra, traffic=read_traffic(rr["kernel"]))
+                unit="TFLOP/s", frac=round(achieved / peak, 4), avg_launch_us=round(rr["avg_ms"] * 1e3, 2),
+                flop_per_launch=rr["flop"], traffic=None)
 
 
-def cpu_baseline(cfg):
-    """The oracle as it stands, one step from the initial state, 1 thread."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(cfg, all_core_steps=3):
+    """The oracle as it stands on the host's cores: one step from the initial
+    state single-threaded, then the -fopenmp build of the same source (every
+    reduction serial, so the same bits, checked here) for a few steps on all
+    cores."""
+    import numpy as np
     from oracle import geao
-    geao.build(force=False)
-    O = geao.Oracle(cfg["mesh"], cfg["params"])
-    s = O.init_bubble(**cfg["bubble"])
+    one = geao.Oracle(cfg["mesh"], cfg["params"])
+    s1 = one.init_bubble(**cfg["bubble"])
     t = time.time()
-    O.step(s, 1)
-    dt = time.time() - t
-    return dict(value=O.nc / dt, unit="cell-steps/s", cores=1, kind="oracle",
-                sample=f"1 step of {cfg['name']} from the initial state, FP64 Jacobi-PCG at "
-                       f"tol {cfg['params']['tol']:g}, single-threaded C (-O2), {dt:.1f} s")
+    one.step(s1, 1)
+    dt1 = time.time() - t
+    many = geao.Oracle(cfg["mesh"], cfg["params"], omp=True)
+    threads = many.L.geao_threads()
+    s2 = many.init_bubble(**cfg["bubble"])
+    t = time.time()
+    many.step(s2, 1)
+    dts = [time.time() - t]
+    same = all(np.array_equal(getattr(s1, f), getattr(s2, f)) for f in ("rho", "u", "T", "pp", "p"))
+    for _ in range(all_core_steps - 1):
+        t = time.time()
+        many.step(s2, 1)
+        dts.append(time.time() - t)
+    nc = one.nc
+    return dict(value=nc * len(dts) / sum(dts), unit="cell-steps/s", cores=threads, kind="oracle",
+                sample=f"steps 1-{len(dts)} of {cfg['name']} from the initial state, FP64 Jacobi-PCG "
+                       f"at tol {cfg['params']['tol']:g}: the oracle's -fopenmp build on {threads} "
+                       f"threads ({sum(dts):.1f} s; step 1 bitwise equal to the single-threaded "
+                       f"build: {same})",
+                one_core=dict(value=nc / dt1, cores=1,
+                              sample=f"step 1 single-threaded (gcc -O2), {dt1:.1f} s"),
+                same_bits_as_one_core=same)
 
 
 def source_sha(name):
@@ -174,16 +244,28 @@ def read_traffic(kernel):
     return None
 
 
+def learned_available(cfg):
+    from paper_2303_10499_amd import learned
+    ndim = 2 if cfg["mesh"]["ny"] == 1 else 3
+    m = cfg["mesh"]
+    ok = all(n % 4 == 0 for n in (m["nx"], m["nz"])) and (ndim == 2 or m["ny"] % 4 == 0)
+    return ok and os.path.exists(learned.weights_file(ndim))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="bubble3d_256x256x128")
     ap.add_argument("--also", default="nonsmooth2d_2048_eval",
                     help="second evaluation mesh reported beside the first ('' for none)")
     ap.add_argument("--forms", default="pcg64,mixed,learned,learned_fcg")
     ap.add_argument("--kernel-steps", type=int, default=3)
+    ap.add_argument("--full-reps", type=int, default=3, help="full runs per form on the first mesh")
+    ap.add_argument("--full-reps-also", type=int, default=1, help="full runs per form on the second mesh")
+    ap.add_argument("--full-forms-also", default="pcg64,mixed,learned")
+    ap.add_argument("--no-full", action="store_true", help="skip the full evaluation runs")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -197,38 +279,61 @@ def main():
     gea.lib()
     forms = [f for f in args.forms.split(",") if f]
 
-    def run_workload(name):
+    def workload(name):
         cfg = configs.get(name)
         cfg["params"]["tol"] = 1e-8
         cfg["params"]["inner_tol"] = 1e-4
         cfg["params"]["max_iter"] = 200000
+        return cfg
+
+    def run_workload(cfg, full_reps, full_forms):
         res = {}
         for f in forms:
             if FORMS[f][0] == "learned" and not learned_available(cfg):
                 log(f"[bench] {f} skipped: no trained weights for this workload")
                 continue
-            res[f] = run_form(cfg, f, args.steps, args.warmup, args.kernel_steps)
-        return cfg, res
+            res[f] = run_window(cfg, f, args.steps, args.warmup, args.kernel_steps)
+        full = None
+        if not args.no_full:
+            full = {"workload": cfg["name"], "steps": cfg["steps"], "forms": {}}
+            for f in full_forms:
+                if f in res:
+                    full["forms"][f] = run_full(cfg, f, cfg["steps"], full_reps)
+            if "pcg64" in full["forms"]:
+                base = full["forms"]["pcg64"]["cell_steps_per_s"]
+                full["speedup_vs_pcg64"] = {k: round(v["cell_steps_per_s"] / base, 3)
+                                            for k, v in full["forms"].items()}
+            full["forms"] = {k: clean(v) for k, v in full["forms"].items()}
+        return res, full
 
-    cfg, results = run_workload(args.workload)
+    def speedups(res):
+        if "pcg64" not in res:
+            return None
+        base = res["pcg64"]["cell_steps_per_s"]
+        return {k: round(v["cell_steps_per_s"] / base, 3) for k, v in res.items()}
+
+    def public(res):
+        return {k: clean({kk: vv for kk, vv in v.items() if not kk.startswith("_")}) for k, v in res.items()}
+
+    cfg = workload(args.workload)
+    results, full = run_workload(cfg, args.full_reps, forms)
     also = None
     if args.also:
-        cfg2, res2 = run_workload(args.also)
+        cfg2 = workload(args.also)
+        res2, full2 = run_workload(cfg2, args.full_reps_also,
+                                   [f for f in args.full_forms_also.split(",") if f])
         also = {"workload": cfg2["name"],
                 "cells": cfg2["mesh"]["nx"] * cfg2["mesh"]["ny"] * cfg2["mesh"]["nz"],
-                "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv)
-                              for kk, vv in v.items() if kk != "roofline"} for k, v in res2.items()}}
-        if "pcg64" in res2:
-            also["speedup_vs_pcg64"] = {k: round(v["cell_steps_per_s"] / res2["pcg64"]["cell_steps_per_s"], 3)
-                                        for k, v in res2.items()}
+                "forms": public(res2), "speedup_vs_pcg64": speedups(res2),
+                "roofline": {k: roofline_entry(v["_roofline"]) for k, v in res2.items()},
+                "full_run": full2}
     primary = "learned" if "learned" in results else ("mixed" if "mixed" in results else forms[0])
     R = results[primary]
     nc = cfg["mesh"]["nx"] * cfg["mesh"]["ny"] * cfg["mesh"]["nz"]
-    roof = roofline_entry(R["roofline"]) if "roofline" in R else None
     cpu = None
     if not args.no_cpu:
-        log("[bench] timing the CPU oracle on a one-step sample ...")
-        cpu = cpu_baseline(cfg)
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        cpu = clean(cpu_baseline(cfg))
     line = {
         "metric": "cell-steps/s at pressure residual 1e-8: learned+mixed vs plain FP64 PCG",
         "value": round(R["cell_steps_per_s"], 1),
@@ -245,24 +350,15 @@ def main():
         "config": {"workload": cfg["name"], "cells": nc, "form": primary,
                    "dt": cfg["params"]["dt"], "n_corr": cfg["params"]["n_corr"],
                    "tol": cfg["params"]["tol"], "parallelism": "single GPU"},
-        "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv)
-                      for kk, vv in v.items() if kk != "roofline"} for k, v in results.items()},
-        "roofline": roof,
+        "forms": public(results),
+        "speedup_vs_pcg64": speedups(results),
+        "full_run": full,
+        "roofline": roofline_entry(R["_roofline"]),
+        "roofline_by_form": {k: roofline_entry(v["_roofline"]) for k, v in results.items()},
         "cpu_baseline": cpu,
+        "also": also,
     }
-    if "pcg64" in results:
-        line["speedup_vs_pcg64"] = {k: round(v["cell_steps_per_s"] / results["pcg64"]["cell_steps_per_s"], 3)
-                                    for k, v in results.items()}
-    line["also"] = also
     print(json.dumps(line), flush=True)
-
-
-def learned_available(cfg):
-    from paper_2303_10499_amd import learned
-    ndim = 2 if cfg["mesh"]["ny"] == 1 else 3
-    m = cfg["mesh"]
-    ok = all(n % 4 == 0 for n in (m["nx"], m["nz"])) and (ndim == 2 or m["ny"] % 4 == 0)
-    return ok and os.path.exists(learned.weights_file(ndim))
 
 
 if __name__ == "__main__":

@@ -112,6 +112,8 @@ typedef struct {
   int64_t total_solves;
   double eos_mismatch;         /* max |rho^{n+1} - p^{n+1}/(R T^{n+1})| of the last step */
   double mass;                 /* sum of rho^{n+1} V after the last step               */
+  double max_rel_res;          /* largest exit residual (rel_res) of all solves of this call */
+  int64_t total_fallbacks;     /* learned form: fallbacks of all solves of this call   */
 } gea_step_stats;
 
 /* field selectors for gea_get_fields (bit mask; output packed in bit order) */

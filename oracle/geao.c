@@ -52,6 +52,24 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* With -fopenmp (the all-core timing build) the loops below that write one
+ * cell per iteration are shared among threads; no reduction is: every sum
+ * and maximum keeps its serial order, so both builds give the same bits. */
+#ifdef _OPENMP
+#include <omp.h>
+#define PER_CELL _Pragma("omp parallel for schedule(static)")
+#else
+#define PER_CELL
+#endif
+
+int geao_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* mesh geometry                                                             */
 
@@ -124,11 +142,13 @@ static double interp4(const geom* G, const double* s, long P, int d) {
 
 void geao_face_interp4(const geao_mesh* m, const double* s, int dir, double* out) {
   geom G = make_geom(m);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) out[P] = has_hi(&G, P, dir) ? interp4(&G, s, P, dir) : 0.0;
 }
 
 void geao_face_sngrad(const geao_mesh* m, const double* s, int dir, double* out) {
   geom G = make_geom(m);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P)
     out[P] = has_hi(&G, P, dir) ? (s[P + G.st[dir]] - s[P]) / G.h[dir] : 0.0;
 }
@@ -143,6 +163,7 @@ static double reconstruct1(const geom* G, const double* Fd, long P, int d) {
 void geao_reconstruct(const geao_mesh* m, const double* faces, double* out) {
   geom G = make_geom(m);
   for (int d = 0; d < G.ndim; ++d)
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) out[d * G.nc + P] = reconstruct1(&G, faces + d * G.nc, P, d);
 }
 
@@ -159,6 +180,7 @@ static double sum_out(const geom* G, const double* faces, long P) {
 
 void geao_divergence(const geao_mesh* m, const double* faces, double* out) {
   geom G = make_geom(m);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) out[P] = sum_out(&G, faces, P) / G.V;
 }
 
@@ -176,6 +198,7 @@ static double convective1(const geom* G, const double* phi, const double* s, lon
 
 void geao_convective(const geao_mesh* m, const double* phi, const double* s, double* out) {
   geom G = make_geom(m);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) out[P] = convective1(&G, phi, s, P);
 }
 
@@ -197,11 +220,13 @@ static double viscous1(const geom* G, const double* uc, int comp, double mu, lon
 
 void geao_viscous(const geao_mesh* m, const double* uc, int comp, double mu, double* out) {
   geom G = make_geom(m);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) out[P] = viscous1(&G, uc, comp, mu, P);
 }
 
 void geao_potential(const geao_mesh* m, const geao_params* q, double* out) {
   geom G = make_geom(m);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) out[P] = phi_cell(&G, q, P);
 }
 
@@ -211,6 +236,7 @@ static void force_faces(const geom* G, const geao_params* q, const double* pp, c
                         double* F) {
   for (int d = 0; d < G->ndim; ++d) {
     long st = G->st[d];
+    PER_CELL
     for (long P = 0; P < G->nc; ++P) {
       double v = 0.0;
       if (has_hi(G, P, d))
@@ -252,6 +278,7 @@ int geao_init_bubble(const geao_mesh* m, const geao_params* q, const geao_bubble
     double pb = pp_a[k] - rho_a[k] * Phi;
     Tbg[k] = pb / (q->R * rho_a[k]);
   }
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) {
     int i = (int)(P % m->nx);
     int j = (int)((P / m->nx) % m->ny);
@@ -286,10 +313,13 @@ void geao_mass_predictor(const geao_mesh* m, const geao_params* q, const double*
   geom G = make_geom(m);
   double* mom = zalloc(G.nc);
   for (int d = 0; d < G.ndim; ++d) {
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) mom[P] = rho[P] * u[d * G.nc + P];
+    PER_CELL
     for (long P = 0; P < G.nc; ++P)
       phi[d * G.nc + P] = has_hi(&G, P, d) ? interp4(&G, mom, P, d) * G.S[d] : 0.0;
   }
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) rho_star[P] = rho[P] - q->dt / G.V * sum_out(&G, phi, P);
   free(mom);
 }
@@ -304,6 +334,7 @@ void geao_momentum_predictor(const geao_mesh* m, const geao_params* q, const dou
   force_faces(&G, q, pp, rho, F);
   for (int c = 0; c < G.ndim; ++c) {
     const double* uc = u + c * G.nc;
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       double conv = convective1(&G, phi, uc, P);
       double visc = viscous1(&G, uc, c, q->mu, P);
@@ -334,16 +365,19 @@ void geao_energy(const geao_mesh* m, const geao_params* q, const double* rho, co
   double* hhat = zalloc(G.nc);
   double* Tprime = zalloc(G.nc);
   double* e_next = zalloc(G.nc);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) {
     e_n[P] = q->cv * T[P] + kinetic(&G, u, P) + phi_cell(&G, q, P);  /* e = c_v T + K + g z */
     e[P] = e_n[P];
     Tk[P] = T[P];
   }
   for (int s = 0; s < q->n_energy_sweeps; ++s) {
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       hhat[P] = e[P] + q->R * Tk[P];          /* e + p/rho */
       Tprime[P] = Tk[P] - Tbg[coord(&G, P, G.zdir)];
     }
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       double conv = convective1(&G, phi, hhat, P);
       /* diffusion of h' = c_p (T - T_bg), adiabatic walls */
@@ -357,12 +391,14 @@ void geao_energy(const geao_mesh* m, const geao_params* q, const double* rho, co
       double rhoe = rho[P] * e_n[P] - q->dt / G.V * conv + q->dt / G.V * diff;
       e_next[P] = rhoe / rho_star[P];
     }
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       e[P] = e_next[P];
       /* e -> T: T = (e - K* - Phi) / c_v */
       Tk[P] = (e[P] - kinetic(&G, u_star, P) - phi_cell(&G, q, P)) / q->cv;
     }
   }
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) T_new[P] = Tk[P];
   free(e_n); free(e); free(Tk); free(hhat); free(Tprime); free(e_next);
 }
@@ -373,6 +409,7 @@ void geao_eos_coeffs(const geao_mesh* m, const geao_params* q, const double* p,
                      const double* T_new, const double* rho_star,
                      double* rho23, double* psi, double* c, double* D) {
   geom G = make_geom(m);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) {
     rho23[P] = p[P] / (q->R * T_new[P]);
     psi[P] = 1.0 / (q->R * T_new[P]);
@@ -390,6 +427,7 @@ void geao_H(const geao_mesh* m, const geao_params* q, const double* rho, const d
   geom G = make_geom(m);
   for (int c = 0; c < G.ndim; ++c) {
     const double* uc = u_prev + c * G.nc;
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       double conv = convective1(&G, phi, uc, P);
       double visc = viscous1(&G, uc, c, q->mu, P);
@@ -407,6 +445,7 @@ void geao_predicted_flux_rhs(const geao_mesh* m, const geao_params* q, const dou
   for (int d = 0; d < G.ndim; ++d) {
     long st = G.st[d];
     const double* Hd = H + d * G.nc;
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       double v = 0.0;
       if (has_hi(&G, P, d)) {
@@ -417,6 +456,7 @@ void geao_predicted_flux_rhs(const geao_mesh* m, const geao_params* q, const dou
       phi_tilde[d * G.nc + P] = v;
     }
   }
+  PER_CELL
   for (long P = 0; P < G.nc; ++P) {
     double Phi = phi_cell(&G, q, P);
     b[P] = G.V / q->dt * (rho[P] + psi[P] * rho23[P] * Phi) - sum_out(&G, phi_tilde, P);
@@ -425,6 +465,7 @@ void geao_predicted_flux_rhs(const geao_mesh* m, const geao_params* q, const dou
 
 /* y = A x, (A x)_i = c_i x_i + sum_f w_f (x_i - x_nb), w_f = (D_P + D_N)/2 S/d */
 static void apply_A(const geom* G, const double* c, const double* D, const double* x, double* y) {
+  PER_CELL
   for (long P = 0; P < G->nc; ++P) {
     double acc = c[P] * x[P];
     for (int d = 0; d < G->ndim; ++d) {
@@ -460,6 +501,7 @@ int geao_pcg(const geao_mesh* m, const double* c, const double* D, const double*
   double* pdir = zalloc(n);
   double* q = zalloc(n);
   double* diag = zalloc(n);
+  PER_CELL
   for (long P = 0; P < n; ++P) {
     double a = c[P];
     for (int d = 0; d < G.ndim; ++d) {
@@ -474,12 +516,16 @@ int geao_pcg(const geao_mesh* m, const double* c, const double* D, const double*
   int it = 0;
   double nr;
   if (nb == 0.0) {
+    PER_CELL
     for (long P = 0; P < n; ++P) x[P] = 0.0;
     nb = 1.0;
   }
   apply_A(&G, c, D, x, q);
+  PER_CELL
   for (long P = 0; P < n; ++P) r[P] = b[P] - q[P];
+  PER_CELL
   for (long P = 0; P < n; ++P) z[P] = r[P] / diag[P];
+  PER_CELL
   for (long P = 0; P < n; ++P) pdir[P] = z[P];
   double rz = dot(n, r, z);
   nr = sqrt(dot(n, r, r));
@@ -489,11 +535,15 @@ int geao_pcg(const geao_mesh* m, const double* c, const double* D, const double*
     if (it >= max_iter) { status = GEAO_ERR_NOCONV; break; }
     apply_A(&G, c, D, pdir, q);
     double alpha = rz / dot(n, pdir, q);
+    PER_CELL
     for (long P = 0; P < n; ++P) x[P] += alpha * pdir[P];
+    PER_CELL
     for (long P = 0; P < n; ++P) r[P] -= alpha * q[P];
+    PER_CELL
     for (long P = 0; P < n; ++P) z[P] = r[P] / diag[P];
     double rz_new = dot(n, r, z);
     double beta = rz_new / rz;
+    PER_CELL
     for (long P = 0; P < n; ++P) pdir[P] = z[P] + beta * pdir[P];
     rz = rz_new;
     nr = sqrt(dot(n, r, r));
@@ -504,6 +554,7 @@ int geao_pcg(const geao_mesh* m, const double* c, const double* D, const double*
   st->rel_res = nr / nb;
   st->converged = status == GEAO_OK;
   apply_A(&G, c, D, x, q);
+  PER_CELL
   for (long P = 0; P < n; ++P) r[P] = b[P] - q[P];
   st->true_rel_res = sqrt(dot(n, r, r)) / nb;
   free(r); free(z); free(pdir); free(q); free(diag);
@@ -519,6 +570,7 @@ void geao_correct(const geao_mesh* m, const geao_params* q, const double* pp,
   double* F = zalloc(G.ndim * G.nc);
   for (int d = 0; d < G.ndim; ++d) {
     long st = G.st[d];
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       double v = 0.0;
       if (has_hi(&G, P, d)) {
@@ -530,6 +582,7 @@ void geao_correct(const geao_mesh* m, const geao_params* q, const double* pp,
   }
   force_faces(&G, q, pp, rho23, F);
   for (int c = 0; c < G.ndim; ++c)
+    PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       double A = rho_star[P] / q->dt;
       u[c * G.nc + P] = (H[c * G.nc + P] - reconstruct1(&G, F + c * G.nc, P, c)) / A;
@@ -665,6 +718,7 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
 void geao_theta_prime(const geao_mesh* m, const geao_params* q, const double* T, const double* p,
                       double* out) {
   geom G = make_geom(m);
+  PER_CELL
   for (long P = 0; P < G.nc; ++P)
     out[P] = T[P] / pow(p[P] / q->p0, q->R / q->cp) - q->theta0;
 }

@@ -133,6 +133,10 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
 void geao_theta_prime(const geao_mesh* m, const geao_params* q, const double* T, const double* p,
                       double* out);
 
+/* threads the per-cell loops run on: 1, or the OpenMP team size of the
+ * -fopenmp build (timing only; both builds give the same results) */
+int geao_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

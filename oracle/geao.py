@@ -20,17 +20,22 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "geao.c")
 _LIB = os.path.join(_HERE, "libgeao.so")
+_LIB_OMP = os.path.join(_HERE, "libgeao_omp.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile ``libgeao.so`` with plain gcc -O2 (no fast-math, no OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, omp: bool = False) -> str:
+    """Compile ``libgeao.so`` with plain gcc -O2 (no fast-math, one thread);
+    with omp, ``libgeao_omp.so`` from the same source with -fopenmp (its
+    per-cell loops shared among threads, every reduction serial: the same
+    results bit for bit, used only to time the oracle on all host cores)."""
+    out = _LIB_OMP if omp else _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
         subprocess.run(
-            ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
-             "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+            ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared"]
+            + (["-fopenmp"] if omp else []) + ["-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, out)
+    return out
 
 
 class Mesh(C.Structure):
@@ -64,15 +69,13 @@ class StepStats(C.Structure):
 
 OK, ERR_ARG, ERR_NOCONV, ERR_NAN = 0, -1, -4, -5
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        L = C.CDLL(_LIB)
+def lib(omp: bool = False):
+    if omp not in _libs:
+        path = build(force=False, omp=omp)
+        L = C.CDLL(path)
         P = C.POINTER
         d = P(C.c_double)
         L.geao_ndim.argtypes = [P(Mesh)]
@@ -97,8 +100,10 @@ def lib():
         L.geao_pressure_system.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d]
         L.geao_step.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, P(StepStats)]
         L.geao_theta_prime.argtypes = [P(Mesh), P(Params), d, d, d]
-        _lib = L
-    return _lib
+        L.geao_threads.argtypes = []
+        L.geao_threads.restype = C.c_int
+        _libs[omp] = L
+    return _libs[omp]
 
 
 def _p(a: np.ndarray):
@@ -123,14 +128,14 @@ class State:
 class Oracle:
     """The oracle bound to one mesh and one parameter set (plain numbers)."""
 
-    def __init__(self, mesh: dict, params: dict):
+    def __init__(self, mesh: dict, params: dict, omp: bool = False):
         self.mesh = Mesh(int(mesh["nx"]), int(mesh["ny"]), int(mesh["nz"]),
                          float(mesh["lx"]), float(mesh["ly"]), float(mesh["lz"]))
         self.params = Params(*(float(params[k]) for k in ("R", "cp", "cv", "g", "p0",
                                                           "theta0", "mu", "Pr", "dt")),
                              int(params.get("n_corr", 2)), int(params.get("n_energy_sweeps", 2)),
                              float(params.get("tol", 1e-13)), int(params.get("max_iter", 100000)))
-        self.L = lib()
+        self.L = lib(omp)
         self.ndim = 2 if self.mesh.ny == 1 else 3
         self.nc = self.mesh.nx * self.mesh.ny * self.mesh.nz
 

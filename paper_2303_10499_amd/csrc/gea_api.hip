@@ -933,6 +933,8 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
     stats->solve[stats->n_solves++] = ss;
     stats->total_iters += ss.iters;
     stats->total_solves += 1;
+    stats->total_fallbacks += ss.fallbacks;
+    if (ss.rel_res > stats->max_rel_res) stats->max_rel_res = ss.rel_res;
     if (rc != GEA_OK) return rc;
     if (!x->tail_done) correct();
     HIPCHK(hipGetLastError());

@@ -456,3 +456,20 @@ def test_step_is_the_composition_of_the_pinned_substeps(oracle_lib):
     rn, pn, mm = O.finalize(s.rho, phik, ppk, r23, psi)
     for got, ref in ((rn, want.rho), (uk, want.u), (Tn, want.T), (ppk, want.pp), (pn, want.p)):
         np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name,dims", [("bubble2d_64x32", None), ("bubble3d_256x256x128", (16, 10, 12))])
+def test_all_core_oracle_build_gives_the_same_bits(oracle_lib, name, dims):
+    """The -fopenmp build of the same source (used only to time the oracle on
+    all host cores) shares the per-cell loops among threads and keeps every
+    reduction serial: its steps equal the single-threaded build's bit for bit."""
+    cfg = configs.get(name, tol=1e-13) if dims is None else configs.scaled(name, *dims)
+    cfg["params"]["tol"] = 1e-13
+    one = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+    many = oracle_lib.Oracle(cfg["mesh"], cfg["params"], omp=True)
+    s1 = one.init_bubble(**cfg["bubble"])
+    s2 = many.init_bubble(**cfg["bubble"])
+    one.step(s1, 4)
+    many.step(s2, 4)
+    for f in ("rho", "u", "T", "pp", "p"):
+        np.testing.assert_array_equal(getattr(s1, f), getattr(s2, f), err_msg=f)

@@ -353,8 +353,21 @@ static double kinetic(const geom* G, const double* u, long P) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Step 2 in total-energy form (eqs. ent, step3_sd, step3_2sd; R5, R7)       */
+/* Step 2 in total-energy form (eqs. ent, step3_sd, step3_2sd; R4, R5, R7)   */
 
+/* The diffusion term of Step 2 is taken at the new level, as eq. step3_sd
+ * writes it; the convective term by Picard sweeps with the frozen flux.
+ * Sweep s solves, with e = c_v T + K* + Phi and T' = T - T_bg,
+ *   rho* e^(s) = rho^n e^n - dt/V sum_out phi I4(e + R T)^(s-1)
+ *                + dt/V sum_f (mu/Pr) c_p snGrad(T'^(s))_f S_f,
+ * i.e. (times V/dt) the SPD system
+ *   c_i T_i + sum_f k_f (T_i - T_nb) = b_i,   c = rho* c_v V/dt,
+ *   k_f = (mu/Pr) c_p S_f/h_f (interior faces; adiabatic walls),
+ *   b = V/dt (rho^n e^n - rho* (K* + Phi)) - sum_out phi I4(e + R T)^(s-1)
+ *       + sum_f k_f (T_bg,i - T_bg,nb),
+ * by Jacobi-PCG from T^(s-1) to a relative residual of GEAO_ENERGY_TOL.
+ * (Explicit diffusion sweeps converge to this only while
+ * dt (mu/Pr) c_p/(rho c_v) sum_d 4/h_d^2 < 1.) */
 void geao_energy(const geao_mesh* m, const geao_params* q, const double* rho, const double* u,
                  const double* T, const double* u_star, const double* rho_star,
                  const double* phi, const double* Tbg, double* T_new) {
@@ -363,44 +376,44 @@ void geao_energy(const geao_mesh* m, const geao_params* q, const double* rho, co
   double* e = zalloc(G.nc);
   double* Tk = zalloc(G.nc);
   double* hhat = zalloc(G.nc);
-  double* Tprime = zalloc(G.nc);
-  double* e_next = zalloc(G.nc);
+  double* cT = zalloc(G.nc);
+  double* DT = zalloc(G.nc);
+  double* bT = zalloc(G.nc);
+  const double kcoef = q->mu / q->Pr * q->cp;  /* w_f = (D_P + D_N)/2 S/h with D = kcoef */
   PER_CELL
   for (long P = 0; P < G.nc; ++P) {
     e_n[P] = q->cv * T[P] + kinetic(&G, u, P) + phi_cell(&G, q, P);  /* e = c_v T + K + g z */
     e[P] = e_n[P];
     Tk[P] = T[P];
+    cT[P] = rho_star[P] * q->cv * G.V / q->dt;
+    DT[P] = kcoef;
   }
   for (int s = 0; s < q->n_energy_sweeps; ++s) {
     PER_CELL
-    for (long P = 0; P < G.nc; ++P) {
-      hhat[P] = e[P] + q->R * Tk[P];          /* e + p/rho */
-      Tprime[P] = Tk[P] - Tbg[coord(&G, P, G.zdir)];
-    }
+    for (long P = 0; P < G.nc; ++P) hhat[P] = e[P] + q->R * Tk[P];  /* e + p/rho */
     PER_CELL
     for (long P = 0; P < G.nc; ++P) {
       double conv = convective1(&G, phi, hhat, P);
-      /* diffusion of h' = c_p (T - T_bg), adiabatic walls */
-      double diff = 0.0;
+      /* the background part of the diffusion of h' = c_p (T - T_bg) */
+      double bg = 0.0;
+      int kz = coord(&G, P, G.zdir);
       for (int d = 0; d < G.ndim; ++d) {
+        double k = kcoef * G.S[d] / G.h[d];
         long st = G.st[d];
-        double k = q->mu / q->Pr * q->cp * G.S[d] / G.h[d];
-        if (has_hi(&G, P, d)) diff += k * (Tprime[P + st] - Tprime[P]);
-        if (has_lo(&G, P, d)) diff += k * (Tprime[P - st] - Tprime[P]);
+        if (has_hi(&G, P, d)) bg += k * (Tbg[kz] - Tbg[coord(&G, P + st, G.zdir)]);
+        if (has_lo(&G, P, d)) bg += k * (Tbg[kz] - Tbg[coord(&G, P - st, G.zdir)]);
       }
-      double rhoe = rho[P] * e_n[P] - q->dt / G.V * conv + q->dt / G.V * diff;
-      e_next[P] = rhoe / rho_star[P];
+      double rest = kinetic(&G, u_star, P) + phi_cell(&G, q, P);
+      bT[P] = G.V / q->dt * (rho[P] * e_n[P] - rho_star[P] * rest) - conv + bg;
     }
+    geao_solve_stats st;
+    geao_pcg(m, cT, DT, bT, Tk, GEAO_ENERGY_TOL, q->max_iter, &st);
     PER_CELL
-    for (long P = 0; P < G.nc; ++P) {
-      e[P] = e_next[P];
-      /* e -> T: T = (e - K* - Phi) / c_v */
-      Tk[P] = (e[P] - kinetic(&G, u_star, P) - phi_cell(&G, q, P)) / q->cv;
-    }
+    for (long P = 0; P < G.nc; ++P)
+      e[P] = q->cv * Tk[P] + kinetic(&G, u_star, P) + phi_cell(&G, q, P);
   }
-  PER_CELL
-  for (long P = 0; P < G.nc; ++P) T_new[P] = Tk[P];
-  free(e_n); free(e); free(Tk); free(hhat); free(Tprime); free(e_next);
+  memcpy(T_new, Tk, sizeof(double) * G.nc);
+  free(e_n); free(e); free(Tk); free(hhat); free(cT); free(DT); free(bT);
 }
 
 /* eq. step3_3sd: rho^{n+2/3} R T^{n+1} = p^n; and the pressure-equation

@@ -117,18 +117,28 @@ def _energy(O, rho, u, T, us, rs, phi, Tbg):
     return O.energy(rho, u, T, us, rs, phi, Tbg)
 
 
-def test_energy_diffusion_of_temperature_deviation(oracle_lib):
-    O, par = make(oracle_lib, mu=100.0, n_energy_sweeps=1)
+@pytest.mark.parametrize("mode", [1, 11])
+def test_energy_diffusion_is_implicit(oracle_lib, mode):
+    """eq. step3_sd takes the diffusion of h' = c_p (T - T_bg) at the new
+    level.  T' = A cos(pi m (i + 1/2)/nx) is an eigenvector of the discrete
+    Laplacian with adiabatic walls (eigenvalue (2/h^2)(1 - cos(pi m/nx))), so
+    one sweep with no flow scales it by exactly 1/(1 + lam),
+    lam = dt (mu/Pr) c_p/(rho c_v) (2/h^2)(1 - cos(pi m/nx)).  An explicit
+    sweep would scale it by 1 - lam (below -1 for m = 11 here)."""
+    O, par = make(oracle_lib, mu=2e4, n_energy_sweeps=1)
     x, y, z, i, j, k = grid(O)
-    a = 1e-5
+    nx = O.mesh.nx
+    h = O.mesh.lx / nx
     Tbg = 290.0 - 3e-3 * (np.arange(O.mesh.nz) + 0.5) * 100.0
-    T = Tbg[k] + a * x * x
-    rho = np.ones(O.nc)
+    Tp = 0.7 * np.cos(np.pi * mode * (i + 0.5) / nx)
+    T = Tbg[k] + Tp
+    ones = np.ones(O.nc)
     zero2 = np.zeros((2, O.nc))
-    Tn = _energy(O, rho, zero2, T, zero2, rho, zero2, Tbg)
-    sel = (i >= 1) & (i <= O.mesh.nx - 2)
-    want = par["dt"] * par["mu"] / par["Pr"] * par["cp"] * 2 * a / par["cv"]
-    np.testing.assert_allclose((Tn - T)[sel], want, rtol=1e-8)
+    Tn = _energy(O, ones, zero2, T, zero2, ones, zero2, Tbg)
+    lam = par["dt"] * par["mu"] / par["Pr"] * par["cp"] / par["cv"] * 2 / h ** 2 * (1 - np.cos(np.pi * mode / nx))
+    if mode == 11:
+        assert lam > 2.0
+    np.testing.assert_allclose(Tn - Tbg[k], Tp / (1 + lam), rtol=1e-9, atol=1e-9)
     # adiabatic walls: the heat content (rho c_v T summed) is conserved
     assert abs(np.sum(Tn - T)) < 1e-9 * np.abs(Tn - T).sum()
 

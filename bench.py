@@ -44,7 +44,7 @@ ALG_BYTES_PER_CELL = {0: 120.0, 2: 60.0}
 FUSED_BYTES_PER_CELL = {0: 88.0, 2: 44.0}
 CLASS_NAMES = {0: "k_cg_iter<fp64>", 1: "k_cg_scalars<fp64>", 2: "k_cg_iter<fp32>",
                3: "k_cg_scalars<fp32>", 4: "solver set-up kernels",
-               5: "explicit step kernels", 6: "learned network"}
+               5: "explicit step kernels", 6: "learned network", 7: "energy solve kernels"}
 # the six forward convolutions of the network (bf16 matrix-core kernels)
 LAYER_NAMES = ["k_conv0z L0 (2->16)", "k_conv_z L1 (16->32, 1/2)", "k_conv_t L2 (32->64, 1/4)",
                "k_conv_z L3 ([64,32]->32, 1/2)", "k_conv_z L4 ([32,16]->16)", "k_conv5z L5 (16->1)"]
@@ -119,7 +119,9 @@ def run_window(cfg, form, steps, warmup, kernel_steps):
     iters_per_step = st_k.total_iters / kernel_steps
     avg = S.time_solver_kernels(reps=50)   # back-to-back launches between two events
     out["kernel_avg_us"] = {CLASS_NAMES[k]: round(avg[k] * 1e3, 2) for k in range(4)}
-    out["launches_per_step"] = {CLASS_NAMES[k]: kn[k] / kernel_steps for k in range(7) if kn[k]}
+    out["launches_per_step"] = {CLASS_NAMES[k]: kn[k] / kernel_steps for k in range(8) if kn[k]}
+    out["energy_iters_per_step"] = st_k.energy_iters / kernel_steps
+    out["energy_ms_per_step_event_timed"] = kms[7] / kernel_steps
     out["iterations_per_step"] = iters_per_step
     out["explicit_ms_per_step_event_timed"] = kms[5] / kernel_steps
     cands = {}

@@ -9,8 +9,9 @@
  *   Step 1 (eqs. e1_d, step2_sd, step1_3sd)  mass flux, density and momentum
  *           predictors, kinetic energy;
  *   Step 2 (eqs. step3_sd, step3_2sd, step3_3sd) energy in total-energy form
- *           (eq. ent, e = c_v T + |u|^2/2 + g z), e -> T recovery and the EOS
- *           density rho^{n+2/3} = p^n/(R T^{n+1});
+ *           (eq. ent, e = c_v T + |u|^2/2 + g z) with its diffusion at the
+ *           new level (one SPD solve for T per sweep), e -> T recovery and
+ *           the EOS density rho^{n+2/3} = p^n/(R T^{n+1});
  *   Step 3 (eqs. step2_sd corrector, p_prime_sd, step4_4sd) PISO correctors:
  *           H operator, predicted face flux, pressure equation, flux and
  *           velocity correction, end-of-step p, K, rho.
@@ -114,6 +115,7 @@ typedef struct {
   double mass;                 /* sum of rho^{n+1} V after the last step               */
   double max_rel_res;          /* largest exit residual (rel_res) of all solves of this call */
   int64_t total_fallbacks;     /* learned form: fallbacks of all solves of this call   */
+  int64_t energy_iters;        /* CG iterations of the Step-2 energy solves of this call */
 } gea_step_stats;
 
 /* field selectors for gea_get_fields (bit mask; output packed in bit order) */
@@ -198,7 +200,8 @@ gea_status gea_get_fields(gea_ctx* ctx, uint32_t field_mask, double* out, gea_pt
  *   4 solver set-up kernels (initial residual and its scalars, refinement
  *     residual and correction, FP32 coefficient copy)
  *   5 explicit step kernels (Steps 1-3 outside the solve)
- *   6 learned network kernels         7 unused
+ *   6 learned network kernels
+ *   7 Step-2 energy solves (CG set-up, iteration and scalar kernels)
  * reset = 1 clears the sums.  Timing adds two event records per launch. */
 gea_status gea_kernel_timing(gea_ctx* ctx, int32_t on, int32_t reset);
 

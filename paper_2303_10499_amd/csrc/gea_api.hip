@@ -146,6 +146,7 @@ struct gea_ctx {
   double* psi;
   double* c;
   double* D;
+  double* DT;  // the energy system's D: (mu/Pr) c_p in every cell
   double* H[3];
   double* b;
   double* dinv;
@@ -189,6 +190,7 @@ struct gea_ctx {
   int fallbacks = 0;
   KernelTimer timer;
   int last_iters64 = 0;  // iterations of the previous solve: first batch length
+  int last_iters_energy[8] = {};  // of the previous step's energy solves, per sweep
   int last_iters32 = 0;
   int last_iters_res = 0;  // iterations of the last Jacobi-PCG resumed after the network
   bool has_state = false;
@@ -295,6 +297,7 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->psi = cv.take<double>(nc);
   x->c = cv.take<double>(nc);
   x->D = cv.take<double>(nc);
+  x->DT = cv.take<double>(nc);
   for (int d = 0; d < 3; ++d) x->H[d] = d < nd ? cv.take<double>(nc) : nullptr;
   x->b = cv.take<double>(nc);
   x->dinv = cv.take<double>(nc);
@@ -878,9 +881,42 @@ gea_status solve(gea_ctx* x, double* xv, gea_solve_stats* out) {
   return solve_mixed(x, xv, out);
 }
 
+// One energy sweep's system (Step 2), set up by the RHS pass: Jacobi-PCG in
+// FP64 on (c, DT, 1/diag, b) from the initial guess in T, to kEnergyTol.
+gea_status solve_energy(gea_ctx* x, double* T, int nparts, int sweep, int* iters) {
+  const Geo& G = x->G;
+  const CgWork& w = x->w64;
+  CgVectors<double> v{T, x->r, x->r1, x->p0, x->p1, x->q, x->q1, x->c, x->DT, x->dinv, x->b};
+  x->timer.run(7, x->stream, [&] {
+    cg_start_from(x->stream, w.u[1], nparts, w.b, kEnergyTol, x->prm.max_iter, w.sc);
+  });
+  CgScalars hs{};  // rr = 0: the first read supplies the starting residual
+  int& last = x->last_iters_energy[sweep < 8 ? sweep : 7];
+  gea_status rc = run_cg(
+      x, x->sc, hs, x->prm.max_iter, last > 0 ? last + 1 : 0,
+      [&](int j) {
+        x->timer.run(7, x->stream, [&] {
+          cg_iter_kernel<double>(x->stream, G, v, j, w);
+          cg_scalars(x->stream, G, j, w);
+        });
+      });
+  if (rc != GEA_OK) return rc;
+  last = hs.iter;
+  *iters = hs.iter;
+  if (hs.status == -4) {
+    x->err = "energy solve did not converge";
+    return GEA_ERR_NOCONV;
+  }
+  if (hs.status != 0) return GEA_ERR_NAN;
+  return GEA_OK;
+}
+
 // Steps 1 and 2 from state s; the last energy sweep writes T_out; p' is
-// copied to pp_out when given (the pressure solve's initial guess).
-void steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out = nullptr) {
+// copied to pp_out when given (the pressure solve's initial guess).  Each
+// energy sweep solves its implicit-diffusion system for T (pressure-solve
+// work vectors, which are free until Step 3).
+gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out = nullptr,
+                     int64_t* energy_iters = nullptr) {
   const Geo& G = x->G;
   const Phys& ph = x->ph;
   hipStream_t s = x->stream;
@@ -894,12 +930,26 @@ void steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out = nullp
     const bool last = sw == ns - 1;
     double* e_next = (sw & 1) ? x->eb : x->ea;
     double* T_next = last ? T_out : ((sw & 1) ? x->Tb : x->Ta);
-    x->timer.run(5, x->stream, [&] { launch_energy_sweep(s, G, ph, S.rho, x->e0, e_prev, T_prev, x->phi, x->rho_star, x->ustar,
-                        x->Tbg, e_next, T_next, last, S.p, x->rho23, x->psi, x->c, x->D); });
+    int nparts = 0;
+    x->timer.run(5, x->stream, [&] {
+      nparts = launch_energy_rhs(s, G, ph, S.rho, x->e0, e_prev, T_prev, x->phi, x->rho_star,
+                                 x->ustar, x->Tbg, x->b, x->c, x->dinv, T_next, x->r, x->p0,
+                                 x->w64.u[1], x->w64.b);
+    });
+    HIPCHK(hipGetLastError());
+    int its = 0;
+    gea_status rc = solve_energy(x, T_next, nparts, sw, &its);
+    if (energy_iters) *energy_iters += its;
+    if (rc != GEA_OK) return rc;
+    x->timer.run(5, x->stream, [&] {
+      launch_energy_post(s, G, ph, T_next, x->ustar, e_next, last, S.p, x->rho_star, x->rho23,
+                         x->psi, x->c, x->D);
+    });
     e_prev = e_next;
     T_prev = T_next;
   }
   x->sys32 = false;  // c and D changed
+  return GEA_OK;
 }
 
 gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
@@ -908,7 +958,10 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
   hipStream_t s = x->stream;
   const State& S = x->st[x->cur];
   const State& N = x->st[1 - x->cur];
-  steps_1_2(x, S, N.T, N.pp);
+  {
+    gea_status rc = steps_1_2(x, S, N.T, N.pp, &stats->energy_iters);
+    if (rc != GEA_OK) return rc;
+  }
   const int nc = x->prm.n_corr;
   stats->n_solves = 0;
   for (int k = 0; k < nc; ++k) {
@@ -1042,6 +1095,8 @@ gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* h
     // zero the solver scalars once
     HIPCHK(hipMemsetAsync(x->sc, 0, sizeof(CgScalars), x->stream));
     HIPCHK(hipMemsetAsync(x->sc32, 0, sizeof(CgScalars), x->stream));
+    launch_fill(x->stream, x->G, x->DT, x->prm.mu / x->prm.Pr * x->prm.cp);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(x->stream));
     return GEA_OK;
   });
@@ -1143,7 +1198,10 @@ gea_status gea_pressure_solve(gea_ctx* x, const double* b, double* xv, gea_ptr_k
     hipStream_t s = x->stream;
     const State& S = x->st[x->cur];
     const State& N = x->st[1 - x->cur];
-    steps_1_2(x, S, N.T);
+    {
+      gea_status rc = steps_1_2(x, S, N.T);
+      if (rc != GEA_OK) return fail(x, rc, "energy solve failed");
+    }
     x->timer.run(5, x->stream, [&] { launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H); });
     x->timer.run(5, x->stream, [&] { build_system(x, S); });
     HIPCHK(hipGetLastError());
@@ -1334,7 +1392,10 @@ gea_status gea_make_pair(gea_ctx* x, double rel_tol, float* in_r, float* in_a, f
     hipStream_t s = x->stream;
     const State& S = x->st[x->cur];
     const State& N = x->st[1 - x->cur];
-    steps_1_2(x, S, N.T);
+    {
+      gea_status rc = steps_1_2(x, S, N.T);
+      if (rc != GEA_OK) return fail(x, rc, "energy solve failed");
+    }
     launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H);
     build_system(x, S);
     // r0 = b - A p'  (FP64), then the tight FP64 solve from x0 = p'

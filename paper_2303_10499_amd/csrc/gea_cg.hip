@@ -213,6 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(const double* u_part, int n
   sc->fin = 0;
   sc->rz = s[0];
   sc->rr = s[1];
+  sc->rr0 = s[1];
   sc->iter = 0;
   int done = 0, status = 0;
   if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(bb)) {
@@ -818,6 +819,10 @@ __global__ __launch_bounds__(kBlock) void k_cast_coeffs(int n, const double* c, 
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill(int n, double* a, double v) {
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) a[P] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_sub(int n, const double* b, double* y) {
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x)
     y[P] = b[P] - y[P];
@@ -947,6 +952,16 @@ void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const doub
 void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx,
                            const CgScalars* gate) {
   hipLaunchKernelGGL(k_add_correction, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, x, dx, gate);
+}
+
+void cg_start_from(hipStream_t s, const double* u_part, int nu, const double* b_part, double tol,
+                   int max_iter, CgScalars* sc) {
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kBlock), 0, s, u_part, nu, b_part, tol * tol,
+                     max_iter, sc);
+}
+
+void launch_fill(hipStream_t s, const Geo& G, double* a, double v) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, a, v);
 }
 
 void launch_sub(hipStream_t s, const Geo& G, const double* b, double* y) {

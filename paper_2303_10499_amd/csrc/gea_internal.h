@@ -91,11 +91,23 @@ struct RhsResidual {
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
                   double* rho_star, double* e0, double* const* u_star, double* pp_copy);
-void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                         const double* e0, const double* e_prev, const double* T_prev,
-                         double* const* phi, const double* rho_star, double* const* u_star,
-                         const double* Tbg, double* e_next, double* T_next, bool last,
-                         const double* p, double* rho23, double* psi, double* c, double* D);
+// Step 2, one sweep: the right-hand side b, coefficient c and 1/diag of the
+// implicit-diffusion system for T, the initial guess x = T_prev, and the
+// solve's set-up (r = b - A x, p0 = 0, partials <r, r/diag>, ||r||^2 in
+// u_part and ||b||^2 in b_part, one per workgroup); returns the workgroup
+// count (k_cg_start's nu).  The system's D is (mu/Pr) c_p everywhere.
+int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                      const double* e0, const double* e_prev, const double* T_prev,
+                      double* const* phi, const double* rho_star, double* const* u_star,
+                      const double* Tbg, double* b, double* c, double* dinv, double* x, double* r,
+                      double* p0, double* u_part, double* b_part);
+// after a sweep's solve: e = c_v T + K* + Phi, or after the last sweep the
+// EOS density and pressure-equation coefficients rho23, psi, c, D
+void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
+                        double* const* u_star, double* e, bool last, const double* p,
+                        const double* rho_star, double* rho23, double* psi, double* c, double* D);
+// relative residual to which each energy sweep's system is solved
+constexpr double kEnergyTol = 1e-14;
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,
               double* const* u_prev, double* const* phi, double* const* H);
 int launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
@@ -201,6 +213,12 @@ void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* 
                            const CgScalars* gate = nullptr);
 // y = b - y
 void launch_sub(hipStream_t s, const Geo& G, const double* b, double* y);
+// a = v
+void launch_fill(hipStream_t s, const Geo& G, double* a, double v);
+// a solve's scalars from the set-up partials another kernel formed (nu
+// workgroups: <r, r/diag>, ||r||^2 in u_part, ||b||^2 in b_part)
+void cg_start_from(hipStream_t s, const double* u_part, int nu, const double* b_part, double tol,
+                   int max_iter, CgScalars* sc);
 
 // ---- learned form: flexible CG (gea_fcg.hip) ----------------------------------
 struct FcgScalars {

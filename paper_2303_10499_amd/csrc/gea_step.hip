@@ -426,114 +426,177 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
 
 // ---- Step 2 ----------------------------------------------------------------
 
-// One Picard sweep of the total-energy equation with frozen flux phi:
-//   rho* e = rho^n e^n - dt/V sum_out phi I4(e + R T) + dt/V sum (mu/Pr) c_p snGrad(T - T_bg) S
-//   T = (e - K* - Phi)/c_v
-// The last sweep also forms the EOS density and pressure-equation coefficients.
+// Step 2, sweep s: the right-hand side of the implicit-diffusion system
+//   c T + sum_f k_f (T_P - T_nb) = b,   c = rho* c_v V/dt,  k_f = (mu/Pr) c_p S_f/h_f,
+//   b = V/dt (rho^n e^n - rho* (K* + Phi)) - sum_out phi I4(e + R T)^(s-1)
+//       + sum_f k_f (T_bg,P - T_bg,nb)
+// (the total-energy balance times V/dt with e = c_v T + K* + Phi, the
+// diffusion of h' = c_p (T - T_bg) at the new level, the convective flux
+// from the previous sweep with the frozen Step-1 flux), its 1/diag, the
+// initial guess T^(s-1) and the solve's set-up as the CG set-up kernel forms
+// it: r = b - A T^(s-1), a zero first direction, and the partials <r, r/diag>,
+// ||r||^2 (u_part) and ||b||^2 (b_part) of each workgroup.
+struct EnergySys {
+  double* b;
+  double* c;
+  double* dinv;
+  double* x;      // the solve's initial guess (and later solution)
+  double* r;
+  double* p0;
+  double* u_part;
+  double* b_part;
+};
+
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_energy_sweep(
+__global__ __launch_bounds__(kBlock) void k_energy_rhs(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
     const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<NDIM> phi,
     const double* __restrict__ rho_star, Vec<NDIM> u_star, const double* __restrict__ Tbg,
-    double* __restrict__ e_next, double* __restrict__ T_next, int last,
-    const double* __restrict__ p, double* __restrict__ rho23, double* __restrict__ psi,
-    double* __restrict__ cc, double* __restrict__ D) {
+    EnergySys sy) {
   constexpr int Z = NDIM - 1;
   const Col c = col_of<NDIM>(G, kc);
-  if (!c.act) return;
-  const int nz = G.n[Z], pl = c.pl;
-  int P = c.base + pl * c.k0;
-  Line ze = line_at([&](int Q) { return e_prev[Q]; }, P, pl, c.k0, nz);
-  Line zT = line_at([&](int Q) { return T_prev[Q]; }, P, pl, c.k0, nz);
-  auto hhat = [&](const Line& e, const Line& T) {
-    return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
-                e.p2 + ph.R * T.p2};
-  };
-  double flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hhat(ze, zT), c.k0, nz) : 0.0;
-  const double kdz = ph.mu / ph.Pr * ph.cp * G.S[Z] / G.h[Z];
-  for (int k = c.k0; k < c.k1; ++k, P += pl) {
-    // loads of the plane
-    const int Pn = nb(k + 3 < nz, P + 3 * pl, P);
-    Line le[NDIM - 1], lT[NDIM - 1];
-    double fhi[NDIM - 1], flod[NDIM - 1];
+  double red[3] = {0.0, 0.0, 0.0};
+  if (c.act) {
+    const int nz = G.n[Z], pl = c.pl;
+    int P = c.base + pl * c.k0;
+    Line ze = line_at([&](int Q) { return e_prev[Q]; }, P, pl, c.k0, nz);
+    Line zT = line_at([&](int Q) { return T_prev[Q]; }, P, pl, c.k0, nz);
+    auto hhat = [&](const Line& e, const Line& T) {
+      return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
+                  e.p2 + ph.R * T.p2};
+    };
+    double flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hhat(ze, zT), c.k0, nz) : 0.0;
+    const double kcoef = ph.mu / ph.Pr * ph.cp;
+    const double kdz = kcoef * G.S[Z] / G.h[Z];      // background part of the flux
+    const double wz = kcoef * (G.S[Z] / G.h[Z]);    // operator weight (D = kcoef on both sides)
+    for (int k = c.k0; k < c.k1; ++k, P += pl) {
+      // loads of the plane
+      const int Pn = nb(k + 3 < nz, P + 3 * pl, P);
+      Line le[NDIM - 1], lT[NDIM - 1];
+      double fhi[NDIM - 1], flod[NDIM - 1];
 #pragma unroll
-    for (int d = 0; d < Z; ++d) {
-      const int st = G.st[d], n = G.n[d], q = coord(c, d);
-      le[d] = line_at([&](int Q) { return e_prev[Q]; }, P, st, q, n);
-      lT[d] = line_at([&](int Q) { return T_prev[Q]; }, P, st, q, n);
-      fhi[d] = phi.p[d][P];
-      flod[d] = phi.p[d][nb(q > 0, P - st, P)];
-    }
-    const double phz = phi.p[Z][P], rs = rho_star[P], r = rho[P], e0c = e0[P];
-    double us[NDIM];
+      for (int d = 0; d < Z; ++d) {
+        const int st = G.st[d], n = G.n[d], q = coord(c, d);
+        le[d] = line_at([&](int Q) { return e_prev[Q]; }, P, st, q, n);
+        lT[d] = line_at([&](int Q) { return T_prev[Q]; }, P, st, q, n);
+        fhi[d] = phi.p[d][P];
+        flod[d] = phi.p[d][nb(q > 0, P - st, P)];
+      }
+      const double phz = phi.p[Z][P], rs = rho_star[P], r = rho[P], e0c = e0[P];
+      double us[NDIM];
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) us[d] = u_star.p[d][P];
-    const double e_n = e_prev[Pn], T_n = T_prev[Pn];
-    const double tb = Tbg[k], tb_up = Tbg[k + 1 < nz ? k + 1 : k], tb_dn = Tbg[k > 0 ? k - 1 : k];
-    // update
-    double conv = 0.0;
+      for (int d = 0; d < NDIM; ++d) us[d] = u_star.p[d][P];
+      const double e_n = e_prev[Pn], T_n = T_prev[Pn];
+      const double tb = Tbg[k], tb_up = Tbg[k + 1 < nz ? k + 1 : k], tb_dn = Tbg[k > 0 ? k - 1 : k];
+      // convective flux of e + R T
+      double conv = 0.0;
 #pragma unroll
-    for (int d = 0; d < Z; ++d) {
-      const int n = G.n[d], q = coord(c, d);
-      const Line h = hhat(le[d], lT[d]);
-      conv = q + 1 < n ? conv + fhi[d] * i4_hi(h, q, n) : conv;
-      conv = q > 0 ? conv - flod[d] * i4_lo(h, q, n) : conv;
-    }
-    double fh = 0.0;
-    if (k + 1 < nz) {
-      fh = phz * i4_hi(hhat(ze, zT), k, nz);
-      conv += fh;
-    }
-    if (k > 0) conv -= flo;
-    flo = fh;
-    const double Tp = zT.c - tb;
-    double diff = 0.0;
+      for (int d = 0; d < Z; ++d) {
+        const int n = G.n[d], q = coord(c, d);
+        const Line h = hhat(le[d], lT[d]);
+        conv = q + 1 < n ? conv + fhi[d] * i4_hi(h, q, n) : conv;
+        conv = q > 0 ? conv - flod[d] * i4_lo(h, q, n) : conv;
+      }
+      double fh = 0.0;
+      if (k + 1 < nz) {
+        fh = phz * i4_hi(hhat(ze, zT), k, nz);
+        conv += fh;
+      }
+      if (k > 0) conv -= flo;
+      flo = fh;
+      // the background temperature's diffusion (z faces only: T_bg is a column)
+      double bg = 0.0;
+      if (k + 1 < nz) bg += kdz * (tb - tb_up);
+      if (k > 0) bg += kdz * (tb - tb_dn);
+      double kin = 0.0;
 #pragma unroll
-    for (int d = 0; d < Z; ++d) {
-      const int n = G.n[d], q = coord(c, d);
-      const double kd = ph.mu / ph.Pr * ph.cp * G.S[d] / G.h[d];
-      diff = q + 1 < n ? diff + kd * ((lT[d].p1 - tb) - Tp) : diff;
-      diff = q > 0 ? diff + kd * ((lT[d].m1 - tb) - Tp) : diff;
-    }
-    if (k + 1 < nz) diff += kdz * ((zT.p1 - tb_up) - Tp);
-    if (k > 0) diff += kdz * ((zT.m1 - tb_dn) - Tp);
-    const double inv_rs = 1.0 / rs;
-    const double rhoe = r * e0c - ph.dt * G.inv_V * conv + ph.dt * G.inv_V * diff;
-    const double e = rhoe * inv_rs;
-    double kin = 0.0;
+      for (int d = 0; d < NDIM; ++d) kin += us[d] * us[d];
+      const double rest = 0.5 * kin + phi_cell(G, ph, k);
+      const double bP = G.V / ph.dt * (r * e0c - rs * rest) - conv + bg;
+      const double cP = rs * ph.cv * G.V / ph.dt;
+      // operator on the initial guess and the diagonal
+      const double xc = zT.c;
+      double ax = cP * xc, diag = cP;
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) kin += us[d] * us[d];
-    const double T = (e - 0.5 * kin - phi_cell(G, ph, k)) * ph.inv_cv;
-    e_next[P] = e;
-    T_next[P] = T;
-    if (last) {
-      const double ps = 1.0 / (ph.R * T);
-      const double r23 = p[P] * ps;
-      rho23[P] = r23;
-      psi[P] = ps;
-      cc[P] = ps * G.V * ph.inv_dt;
-      D[P] = r23 * ph.dt * inv_rs;
+      for (int d = 0; d < Z; ++d) {
+        const int n = G.n[d], q = coord(c, d);
+        const double w = kcoef * (G.S[d] / G.h[d]);
+        if (q + 1 < n) {
+          ax += w * (xc - lT[d].p1);
+          diag += w;
+        }
+        if (q > 0) {
+          ax += w * (xc - lT[d].m1);
+          diag += w;
+        }
+      }
+      if (k + 1 < nz) {
+        ax += wz * (xc - zT.p1);
+        diag += wz;
+      }
+      if (k > 0) {
+        ax += wz * (xc - zT.m1);
+        diag += wz;
+      }
+      const double di = 1.0 / diag, rr = bP - ax;
+      sy.b[P] = bP;
+      sy.c[P] = cP;
+      sy.dinv[P] = di;
+      sy.x[P] = xc;
+      sy.r[P] = rr;
+      sy.p0[P] = 0.0;
+      red[0] += rr * (rr * di);
+      red[1] += rr * rr;
+      red[2] += bP * bP;
+      const bool more = k + 3 < nz;
+      ze = shift(ze, more ? e_n : 0.0);
+      zT = shift(zT, more ? T_n : 0.0);
     }
-    const bool more = k + 3 < nz;
-    ze = shift(ze, more ? e_n : 0.0);
-    zT = shift(zT, more ? T_n : 0.0);
+  }
+  __shared__ double sh[3][kBlock / 64];
+  Reducer<0u, 3>::block(red, sh);
+  if (threadIdx.x == 0) {
+    sy.u_part[blockIdx.x] = red[0];
+    sy.u_part[gridDim.x + blockIdx.x] = red[1];
+    sy.b_part[blockIdx.x] = red[2];
   }
 }
 
-// k_energy_sweep on a 3D mesh with the x/y neighbourhoods of e and T staged
-// in LDS and the next plane's loads in flight while a plane is computed.
-// Same formulas and order as k_energy_sweep.  LAST (the sweep that also
-// forms the pressure system's coefficients) is a template parameter, so the
-// other sweeps neither load p nor hold the registers of that part; those fit
-// in 128 VGPRs (two 512-thread workgroups per CU; the last sweep would spill).
-template <int TY, bool LAST>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(LAST ? 1 : 4))) void k_energy_sweep3(
+// After sweep s's solve: e = c_v T + K* + Phi for the next sweep, or (after
+// the last sweep) the EOS density of eq. step3_3sd and the pressure-equation
+// coefficients: rho^{n+2/3} = p^n/(R T^{n+1}), psi = 1/(R T), c = psi V/dt,
+// D = rho^{n+2/3} dt/rho*.
+template <int NDIM, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_energy_post(
+    Geo G, Phys ph, const double* __restrict__ T, Vec<NDIM> u_star, double* __restrict__ e,
+    const double* __restrict__ p, const double* __restrict__ rho_star, double* __restrict__ rho23,
+    double* __restrict__ psi, double* __restrict__ cc, double* __restrict__ D) {
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < G.nc; P += gridDim.x * blockDim.x) {
+    const double Tc = T[P];
+    if (LAST) {
+      const double r23 = p[P] / (ph.R * Tc), ps = 1.0 / (ph.R * Tc);
+      rho23[P] = r23;
+      psi[P] = ps;
+      cc[P] = ps * G.V / ph.dt;
+      D[P] = r23 / (rho_star[P] / ph.dt);
+    } else {
+      double kin = 0.0;
+#pragma unroll
+      for (int d = 0; d < NDIM; ++d) kin += u_star.p[d][P] * u_star.p[d][P];
+      e[P] = ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, P / G.st[NDIM - 1]);
+    }
+  }
+}
+
+// k_energy_rhs on a 3D mesh with the x/y neighbourhoods of e and T staged in
+// LDS and the next plane's loads in flight while a plane is computed.  Same
+// formulas and order as k_energy_rhs.
+template <int TY>
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) void k_energy_rhs3(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
     const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<3> phi,
     const double* __restrict__ rho_star, Vec<3> u_star, const double* __restrict__ Tbg,
-    double* __restrict__ e_next, double* __restrict__ T_next,
-    const double* __restrict__ p, double* __restrict__ rho23, double* __restrict__ psi,
-    double* __restrict__ cc, double* __restrict__ D) {
+    EnergySys sy) {
   using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double su[2][2][HP];  // e, T
@@ -543,7 +606,7 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(LAST ? 
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
   // raw values of the plane in flight
-  double fs[2][NU], fh[2], fl[2], fz, frs, fr, fe0, fus[3], fen, fTn, fp = 0.0;
+  double fs[2][NU], fh[2], fl[2], fz, frs, fr, fe0, fus[3], fen, fTn;
   auto fetch = [&](int kk) {
     const int o = pl * kk, P = qo + o;
 #pragma unroll
@@ -564,7 +627,6 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(LAST ? 
     const int Pn = nb(kk + 3 < nz, P + 3 * pl, P);
     fen = e_prev[Pn];
     fTn = T_prev[Pn];
-    if (LAST) fp = p[P];
   };
   auto hhat = [&](const Line& e, const Line& T) {
     return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
@@ -579,7 +641,10 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(LAST ? 
     flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hhat(ze, zT), c.k0, nz) : 0.0;
   }
   fetch(c.k0);
-  const double kdz = ph.mu / ph.Pr * ph.cp * G.S[Z] / G.h[Z];
+  const double kcoef = ph.mu / ph.Pr * ph.cp;
+  const double kdz = kcoef * G.S[Z] / G.h[Z];
+  const double wz = kcoef * (G.S[Z] / G.h[Z]);
+  double red[3] = {0.0, 0.0, 0.0};
   for (int k = c.k0; k < c.k1; ++k) {
     const int sl = k & 1;
 #pragma unroll
@@ -588,7 +653,7 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(LAST ? 
       for (int m = 0; m < NU; ++m)
         if (st.has[m]) su[sl][f][st.h[m]] = fs[f][m];
     const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
-    const double phz = fz, rs = frs, r = fr, e0c = fe0, e_n = fen, T_n = fTn, pc = fp;
+    const double phz = fz, rs = frs, r = fr, e0c = fe0, e_n = fen, T_n = fTn;
     const double us[3] = {fus[0], fus[1], fus[2]};
     const double tb = Tbg[k], tb_up = Tbg[k + 1 < nz ? k + 1 : k], tb_dn = Tbg[k > 0 ? k - 1 : k];
     fetch(k + 1 < c.k1 ? k + 1 : k);
@@ -614,40 +679,57 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(LAST ? 
     }
     if (k > 0) conv -= flo;
     flo = fhz;
-    const double Tp = zT.c - tb;
-    double diff = 0.0;
-#pragma unroll
-    for (int d = 0; d < Z; ++d) {
-      const int n = G.n[d], q = coord(c, d);
-      const double kd = ph.mu / ph.Pr * ph.cp * G.S[d] / G.h[d];
-      diff = q + 1 < n ? diff + kd * ((lT[d].p1 - tb) - Tp) : diff;
-      diff = q > 0 ? diff + kd * ((lT[d].m1 - tb) - Tp) : diff;
-    }
-    if (k + 1 < nz) diff += kdz * ((zT.p1 - tb_up) - Tp);
-    if (k > 0) diff += kdz * ((zT.m1 - tb_dn) - Tp);
-    const double inv_rs = 1.0 / rs;
-    const double rhoe = r * e0c - ph.dt * G.inv_V * conv + ph.dt * G.inv_V * diff;
-    const double e = rhoe * inv_rs;
+    double bg = 0.0;
+    if (k + 1 < nz) bg += kdz * (tb - tb_up);
+    if (k > 0) bg += kdz * (tb - tb_dn);
     double kin = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) kin += us[d] * us[d];
-    const double T = (e - 0.5 * kin - phi_cell(G, ph, k)) * ph.inv_cv;
+    const double rest = 0.5 * kin + phi_cell(G, ph, k);
+    const double bP = G.V / ph.dt * (r * e0c - rs * rest) - conv + bg;
+    const double cP = rs * ph.cv * G.V / ph.dt;
+    const double xc = zT.c;
+    double ax = cP * xc, diag = cP;
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int n = G.n[d], q = coord(c, d);
+      const double w = kcoef * (G.S[d] / G.h[d]);
+      ax = q + 1 < n ? ax + w * (xc - lT[d].p1) : ax;
+      diag = q + 1 < n ? diag + w : diag;
+      ax = q > 0 ? ax + w * (xc - lT[d].m1) : ax;
+      diag = q > 0 ? diag + w : diag;
+    }
+    if (k + 1 < nz) {
+      ax += wz * (xc - zT.p1);
+      diag += wz;
+    }
+    if (k > 0) {
+      ax += wz * (xc - zT.m1);
+      diag += wz;
+    }
     if (c.act) {
       const int P = qo + pl * k;
-      e_next[P] = e;
-      T_next[P] = T;
-      if (LAST) {
-        const double ps = 1.0 / (ph.R * T);
-        const double r23 = pc * ps;
-        rho23[P] = r23;
-        psi[P] = ps;
-        cc[P] = ps * G.V * ph.inv_dt;
-        D[P] = r23 * ph.dt * inv_rs;
-      }
+      const double di = 1.0 / diag, rr = bP - ax;
+      sy.b[P] = bP;
+      sy.c[P] = cP;
+      sy.dinv[P] = di;
+      sy.x[P] = xc;
+      sy.r[P] = rr;
+      sy.p0[P] = 0.0;
+      red[0] += rr * (rr * di);
+      red[1] += rr * rr;
+      red[2] += bP * bP;
     }
     const bool more = k + 3 < nz;
     ze = shift(ze, more ? e_n : 0.0);
     zT = shift(zT, more ? T_n : 0.0);
+  }
+  __shared__ double sh[3][TY];
+  Reducer<0u, 3, 64 * TY>::block(red, sh);
+  if (threadIdx.x == 0) {
+    sy.u_part[blockIdx.x] = red[0];
+    sy.u_part[gridDim.x + blockIdx.x] = red[1];
+    sy.b_part[blockIdx.x] = red[2];
   }
 }
 
@@ -1507,18 +1589,36 @@ void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho
   hipLaunchKernelGGL(k_step1_3<kTyStep1>, dim3(zp3.blocks), dim3(64 * kTyStep1), 0, s, G, ph, zp3.kc, rho, V3(u), T, pp, V3(phi), rho_star, e0, V3(u_star), pp_copy);
 }
 
-void launch_energy_sweep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
-                         const double* e0, const double* e_prev, const double* T_prev,
-                         double* const* phi, const double* rho_star, double* const* u_star,
-                         const double* Tbg, double* e_next, double* T_next, bool last,
-                         const double* p, double* rho23, double* psi, double* c, double* D) {
+int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                      const double* e0, const double* e_prev, const double* T_prev,
+                      double* const* phi, const double* rho_star, double* const* u_star,
+                      const double* Tbg, double* b, double* c, double* dinv, double* x, double* r,
+                      double* p0, double* u_part, double* b_part) {
   const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy, kKcEnergy) : zp;
-  if (G.ndim == 2)
-    hipLaunchKernelGGL(k_energy_sweep<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, e_next, T_next, (int)last, p, rho23, psi, c, D);
-  else if (last)
-    hipLaunchKernelGGL((k_energy_sweep3<kTyEnergy, true>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, p, rho23, psi, c, D);
-  else
-    hipLaunchKernelGGL((k_energy_sweep3<kTyEnergy, false>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, e_next, T_next, p, rho23, psi, c, D);
+  const EnergySys sy{b, c, dinv, x, r, p0, u_part, b_part};
+  if (G.ndim == 2) {
+    hipLaunchKernelGGL(k_energy_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, sy);
+    return zp.blocks;
+  }
+  hipLaunchKernelGGL(k_energy_rhs3<kTyEnergy>, dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, sy);
+  return zp3.blocks;
+}
+
+void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
+                        double* const* u_star, double* e, bool last, const double* p,
+                        const double* rho_star, double* rho23, double* psi, double* c, double* D) {
+  const dim3 grid(grid_for(G.nc)), block(kBlock);
+  if (G.ndim == 2) {
+    if (last)
+      hipLaunchKernelGGL((k_energy_post<2, true>), grid, block, 0, s, G, ph, T, V2(u_star), e, p, rho_star, rho23, psi, c, D);
+    else
+      hipLaunchKernelGGL((k_energy_post<2, false>), grid, block, 0, s, G, ph, T, V2(u_star), e, p, rho_star, rho23, psi, c, D);
+  } else {
+    if (last)
+      hipLaunchKernelGGL((k_energy_post<3, true>), grid, block, 0, s, G, ph, T, V3(u_star), e, p, rho_star, rho23, psi, c, D);
+    else
+      hipLaunchKernelGGL((k_energy_post<3, false>), grid, block, 0, s, G, ph, T, V3(u_star), e, p, rho_star, rho23, psi, c, D);
+  }
 }
 
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,

@@ -61,7 +61,8 @@ class StepStats(C.Structure):
     _fields_ = [("steps_done", C.c_int32), ("n_solves", C.c_int32), ("solve", SolveStats * 8),
                 ("total_iters", C.c_int64), ("total_solves", C.c_int64),
                 ("eos_mismatch", C.c_double), ("mass", C.c_double),
-                ("max_rel_res", C.c_double), ("total_fallbacks", C.c_int64)]
+                ("max_rel_res", C.c_double), ("total_fallbacks", C.c_int64),
+                ("energy_iters", C.c_int64)]
 
 
 _lib = None

@@ -89,6 +89,8 @@ typedef struct {
   int32_t learned_steps;           /* learned form: network-preconditioned flexible-CG iterations
                                       per solve before Jacobi-PCG continues (>= 1; 1 = the learned
                                       initial guess with an optimal step length)                    */
+  double inner_target;             /* refined forms: an inner solve aims at inner_target * tol ||b||
+                                      for the outer residual (in (0, 1]; 0 selects 0.8)            */
 } gea_params;
 
 /* initial perturbation of Sec. 4: kind 0 none; 1 cosine bubble

@@ -730,7 +730,8 @@ __global__ __launch_bounds__(64 * TY) void k_residual64_3(Geo G, Stencil<3, doub
 __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
                                                            const double* i_part, int n,
                                                            double tol2, double inner_tol2,
-                                                           int inner_max, CgScalars* sc64,
+                                                           double target, int inner_max,
+                                                           CgScalars* sc64,
                                                            CgScalars* sc32, const CgScalars* gate) {
   // (every thread reads the gate before sum_partials' barriers; thread 0
   // writes sc32, which may be the gate, only after them)
@@ -752,12 +753,12 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
   sc32->alpha = 0.0;
   sc32->beta = 0.0;
   sc32->fin = 0;
-  // inner tolerance: what the outer residual still needs (with a factor 0.1
-  // for the FP32 solve's own error), never looser than 0.5 nor tighter than
-  // the configured inner tolerance
+  // inner tolerance: what the outer residual still needs (times the target
+  // fraction, a margin for the FP32 solve's own error), never looser than
+  // 0.5 nor tighter than the configured inner tolerance
   double it2 = inner_tol2;
   if (o[0] > 0.0 && finite) {
-    const double need = 0.1 * sqrt(tol2 * o[1] / o[0]);
+    const double need = target * sqrt(tol2 * o[1] / o[0]);
     const double it = fmax(sqrt(inner_tol2), fmin(0.5, need));
     it2 = it * it;
   }
@@ -909,7 +910,7 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
                        const double* b, const double* x, const CgVectors<float>& v32,
-                       double tol, double inner_tol, int inner_max, double* o_part,
+                       double tol, double inner_tol, double target, int inner_max, double* o_part,
                        const CgWork& w32, CgScalars* sc64, bool zero_inner,
                        const CgScalars* gate) {
   constexpr int TY = 8;  // 64x8 column tiles in 3D
@@ -921,15 +922,15 @@ void launch_residual64(hipStream_t s, const Geo& G, const double* c, const doubl
   else
     hipLaunchKernelGGL(k_residual64_3<TY>, grid, dim3(64 * TY), 0, s, G, stencil<3, double>(G), c, D, b, x, v32, zp.kc, o_part, w32.u[1], (int)zero_inner, gate);
   hipLaunchKernelGGL(k_residual_check, dim3(1), block, 0, s, (const double*)o_part,
-                     (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, inner_max,
-                     sc64, w32.sc, gate);
+                     (const double*)w32.u[1], gu, tol * tol, inner_tol * inner_tol, target,
+                     inner_max, sc64, w32.sc, gate);
 }
 
-void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, int inner_max,
-                           const double* o_part, const CgWork& w32, CgScalars* sc64,
-                           const CgScalars* gate) {
+void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, double target,
+                           int inner_max, const double* o_part, const CgWork& w32,
+                           CgScalars* sc64, const CgScalars* gate) {
   hipLaunchKernelGGL(k_residual_check, dim3(1), dim3(kBlock), 0, s, o_part, (const double*)w32.u[1], n,
-                     tol * tol, inner_tol * inner_tol, inner_max, sc64, w32.sc, gate);
+                     tol * tol, inner_tol * inner_tol, target, inner_max, sc64, w32.sc, gate);
 }
 
 void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter) {

@@ -197,14 +197,14 @@ void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* 
 // kernels do nothing unless that solve is done, so a solve cut short by its
 // batch can be continued on the same vectors.
 // the residual check alone, on n partials a fused pass formed
-void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, int inner_max,
-                           const double* o_part, const CgWork& w32, CgScalars* sc64,
-                           const CgScalars* gate = nullptr);
+void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, double target,
+                           int inner_max, const double* o_part, const CgWork& w32,
+                           CgScalars* sc64, const CgScalars* gate = nullptr);
 // (zero_inner: also clear the inner iterate and first direction, which a
 // Jacobi-PCG started on this set-up reads; the flexible CG needs neither)
 void launch_residual64(hipStream_t s, const Geo& G, const double* c, const double* D,
                        const double* b, const double* x, const CgVectors<float>& v32,
-                       double tol, double inner_tol, int inner_max, double* o_part,
+                       double tol, double inner_tol, double target, int inner_max, double* o_part,
                        const CgWork& w32, CgScalars* sc64, bool zero_inner = true,
                        const CgScalars* gate = nullptr);
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,

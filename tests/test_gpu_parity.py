@@ -291,7 +291,14 @@ def test_full_size_2d_system_matches_oracle(oracle_lib, gea_mod):
     sysf = S.get_fields(gea_mod.FIELD_C | gea_mod.FIELD_D | gea_mod.FIELD_B)
     assert rel(sysf[0], c) <= 1e-14
     assert rel(sysf[1], D) <= 1e-14
-    assert rel(sysf[2], b) <= 1e-12
+    # T^{n+1} comes from Step 2's implicit-diffusion solve, done on each side
+    # by its own CG to 1e-14: c (~1/T) and D agree to ~1e-14, not to
+    # rounding.  b differences rho^{n+2/3} of neighbouring cells under the
+    # hydrostatic cancellation and amplifies T's relative difference ~55x on
+    # a 512^2 mesh (the oracle alone, energy tolerance 1e-14 vs 1e-16: c moves
+    # 2.0e-14, b 1.09e-12), growing as 1/dz: ~220x here.  So b may differ by
+    # up to ~220 x 2e-14 = 4.4e-12.
+    assert rel(sysf[2], b) <= 5e-12
     v = np.random.default_rng(1).normal(size=O.nc)
     y = np.empty_like(v)
     S.apply_A(v, y)

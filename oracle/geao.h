@@ -70,7 +70,7 @@ enum { GEAO_OK = 0, GEAO_ERR_ARG = -1, GEAO_ERR_NOCONV = -4, GEAO_ERR_NAN = -5 }
 
 /* relative residual to which each energy sweep's implicit-diffusion system
  * is solved (Step 2, see geao_energy) */
-#define GEAO_ENERGY_TOL 1e-14
+#define GEAO_ENERGY_TOL 1e-13
 
 int geao_ndim(const geao_mesh* m);
 

@@ -107,7 +107,7 @@ void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const doubl
                         double* const* u_star, double* e, bool last, const double* p,
                         const double* rho_star, double* rho23, double* psi, double* c, double* D);
 // relative residual to which each energy sweep's system is solved
-constexpr double kEnergyTol = 1e-14;
+constexpr double kEnergyTol = 1e-13;
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,
               double* const* u_prev, double* const* phi, double* const* H);
 int launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,

@@ -590,9 +590,12 @@ __global__ __launch_bounds__(kBlock) void k_energy_post(
 
 // k_energy_rhs on a 3D mesh with the x/y neighbourhoods of e and T staged in
 // LDS and the next plane's loads in flight while a plane is computed.  Same
-// formulas and order as k_energy_rhs.
+// formulas and order as k_energy_rhs.  (Held to 128 VGPRs for two 512-thread
+// workgroups a CU it spills 19 registers and ran at 301 us on the 3D
+// benchmark mesh; one workgroup a CU without the cap, 219 us; 64x4 tiles,
+// 410 us.)
 template <int TY>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) void k_energy_rhs3(
+__global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
     const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<3> phi,
     const double* __restrict__ rho_star, Vec<3> u_star, const double* __restrict__ Tbg,

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgea.so")
+# GEA_LIB_PATH overrides the library file (e.g. a build with other tuning)
+LIB_PATH = os.environ.get("GEA_LIB_PATH") or os.path.join(_HERE, "libgea.so")
 
 OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOCONV, ERR_NAN, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1

@@ -292,7 +292,7 @@ def test_full_size_2d_system_matches_oracle(oracle_lib, gea_mod):
     assert rel(sysf[0], c) <= 1e-14
     assert rel(sysf[1], D) <= 1e-14
     # T^{n+1} comes from Step 2's implicit-diffusion solve, done on each side
-    # by its own CG to 1e-14: c (~1/T) and D agree to ~1e-14, not to
+    # by its own CG to 1e-13: c (~1/T) and D agree to ~1e-14, not to
     # rounding.  b differences rho^{n+2/3} of neighbouring cells under the
     # hydrostatic cancellation and amplifies T's relative difference ~55x on
     # a 512^2 mesh (the oracle alone, energy tolerance 1e-14 vs 1e-16: c moves

@@ -52,9 +52,11 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 # vector bf16 pair dot products (layer 5): 256 CUs x 64 lanes x 2.4 GHz x 4 FLOP
 VALU_DOT2_PEAK_TFLOPS = 157.3
 
-# solver forms: (library solver, learned_steps)
-FORMS = {"pcg64": ("pcg64", 1), "mixed": ("mixed", 1), "learned": ("learned", 1),
-         "learned_fcg": ("learned", 25)}
+# solver forms: (library solver, learned_steps, learned_always).  "learned" is
+# the production form: its gate runs the network on a corrector only while
+# it pays for itself; "learned_always" applies it on every solve.
+FORMS = {"pcg64": ("pcg64", 1, 0), "mixed": ("mixed", 1, 0), "learned": ("learned", 1, 0),
+         "learned_always": ("learned", 1, 1), "learned_fcg": ("learned", 25, 1)}
 
 
 def log(msg):
@@ -84,8 +86,8 @@ def timed_steps(S, n):
 
 def make_solver(cfg, form):
     from paper_2303_10499_amd import gea
-    solver, lsteps = FORMS[form]
-    params = dict(cfg["params"], learned_steps=lsteps)
+    solver, lsteps, always = FORMS[form]
+    params = dict(cfg["params"], learned_steps=lsteps, learned_always=always)
     S = gea.Solver(cfg["mesh"], params, solver=solver)
     if solver == "learned":
         S.load_weights()
@@ -94,7 +96,7 @@ def make_solver(cfg, form):
 
 def run_window(cfg, form, steps, warmup, kernel_steps):
     """the timed window of a form, its kernel accounting and roofline candidates"""
-    solver, lsteps = FORMS[form]
+    solver, lsteps, _ = FORMS[form]
     S = make_solver(cfg, form)
     nc = S.nc
     S.init_bubble(**cfg["bubble"])
@@ -262,11 +264,11 @@ def main():
     ap.add_argument("--workload", default="bubble3d_256x256x128")
     ap.add_argument("--also", default="nonsmooth2d_2048_eval",
                     help="second evaluation mesh reported beside the first ('' for none)")
-    ap.add_argument("--forms", default="pcg64,mixed,learned,learned_fcg")
+    ap.add_argument("--forms", default="pcg64,mixed,learned,learned_always,learned_fcg")
     ap.add_argument("--kernel-steps", type=int, default=3)
     ap.add_argument("--full-reps", type=int, default=3, help="full runs per form on the first mesh")
     ap.add_argument("--full-reps-also", type=int, default=1, help="full runs per form on the second mesh")
-    ap.add_argument("--full-forms-also", default="pcg64,mixed,learned")
+    ap.add_argument("--full-forms-also", default="pcg64,mixed,learned,learned_always")
     ap.add_argument("--no-full", action="store_true", help="skip the full evaluation runs")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()

@@ -91,6 +91,11 @@ typedef struct {
                                       initial guess with an optimal step length)                    */
   double inner_target;             /* refined forms: an inner solve aims at inner_target * tol ||b||
                                       for the outer residual (in (0, 1]; 0 selects 0.8)            */
+  int32_t learned_always;          /* learned form: 0 = per corrector, run the network only while
+                                      the inner iterations it saves (running averages with and
+                                      without it, the other way re-tried every 16th solve) take
+                                      longer than one application (both timed on the device);
+                                      1 = on every solve                                          */
 } gea_params;
 
 /* initial perturbation of Sec. 4: kind 0 none; 1 cosine bubble

@@ -122,6 +122,28 @@ struct KernelTimer {
 
 }  // namespace
 
+// Whether the learned form runs its network on a corrector's solve: it runs
+// while the inner iterations it saves, in running averages of solves with
+// and without it, take longer than one application (network, flexible-CG
+// step and set-up); the other choice is re-tried every 16th solve.
+struct NetGate {
+  double it_net = -1.0, it_plain = -1.0;  // inner iterations a solve that needed any
+  int solves = 0;
+  bool use(double t_net, double t_iter) const {
+    if (it_net < 0) return true;    // first with the network,
+    if (it_plain < 0) return false;  // then once without
+    if (!(t_net > 0)) return true;    // (times still to be taken: the network's
+    if (!(t_iter > 0)) return false;  // in a solve with it, an iteration's without)
+    const bool pays = (it_plain - it_net) * t_iter > t_net;
+    return (solves % 16 == 15) ? !pays : pays;
+  }
+  void record(bool net, double its) {
+    double& e = net ? it_net : it_plain;
+    e = e < 0 ? its : 0.75 * e + 0.25 * its;
+    ++solves;
+  }
+};
+
 struct gea_ctx {
   gea_mesh mesh;
   gea_params prm;
@@ -188,6 +210,16 @@ struct gea_ctx {
   bool has_net_space = false;
   bool has_net = false;
   int fallbacks = 0;
+  // learned form: the gate per corrector, its decision for the solve being
+  // assembled, and the device times (ms) of one network application and
+  // one FP32 inner iteration, each taken once from events around real work
+  NetGate gate[8];
+  bool net_now = false;
+  double t_net_ms = -1.0, t_iter_ms = -1.0;
+  hipEvent_t ev_net[2] = {}, ev_it[2] = {};
+  int net_probe = 0;  // 1: ev_net recorded, not yet read
+  int it_probe = 0;   // batch length recorded between ev_it, 0: none
+  int it_probe_iter0 = 0;
   KernelTimer timer;
   int last_iters64 = 0;  // iterations of the previous solve: first batch length
   int last_iters_energy[8] = {};  // of the previous step's energy solves, per sweep
@@ -231,6 +263,8 @@ struct gea_ctx {
   Snap snaps[8];
   int nsnap = 0;
   ~gea_ctx() {
+    for (hipEvent_t e : {ev_net[0], ev_net[1], ev_it[0], ev_it[1]})
+      if (e) (void)hipEventDestroy(e);
     if (pin) (void)hipHostFree(pin);
   }
 };
@@ -483,7 +517,8 @@ void read_scalars(gea_ctx* x, CgScalars* dev, CgScalars* host, const Extra& extr
 // iteration j0.
 template <typename LaunchIter>
 gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int first_batch,
-                  LaunchIter&& launch_iter, const Extra& extra = Extra{}, long j0 = 0) {
+                  LaunchIter&& launch_iter, const Extra& extra = Extra{}, long j0 = 0,
+                  bool time_iter = false) {
   const int every = x->prm.check_every > 0 ? x->prm.check_every : 8;
   const long cap = j0 + (long)max_iter + 4L * every + 64;
   int batch = first_batch > 0 ? first_batch : every;
@@ -495,9 +530,20 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
       x->err = "solver flag never set";
       return GEA_ERR_HIP;
     }
+    // time_iter: events around a batch of at least two launches, kept as
+    // the time of one iteration if every launch of it did one
+    const bool timed = time_iter && x->t_iter_ms < 0 && batch >= 2 && hs.rr > 0;
+    if (timed) HIPCHK(hipEventRecord(x->ev_it[0], x->stream));
     for (int k = 0; k < batch; ++k, ++j) launch_iter((int)j);
+    if (timed) HIPCHK(hipEventRecord(x->ev_it[1], x->stream));
     HIPCHK(hipGetLastError());
+    const int iter_before = hs.iter;
     read_scalars(x, dsc, &hs, extra);
+    if (timed && hs.iter - iter_before == batch) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, x->ev_it[0], x->ev_it[1]));
+      x->t_iter_ms = (double)t / batch;
+    }
     if (prev_rr <= 0.0) {
       prev_rr = hs.rr0;
       prev_iter = 0;
@@ -518,6 +564,17 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
   return GEA_OK;
 }
 
+// The gate of the corrector in progress, with the timings of earlier
+// probes read in once their events have completed.
+NetGate& net_gate(gea_ctx* x) {
+  if (x->net_probe && hipEventQuery(x->ev_net[1]) == hipSuccess) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, x->ev_net[0], x->ev_net[1]) == hipSuccess) x->t_net_ms = t;
+    x->net_probe = 0;
+  }
+  return x->gate[x->corr < 8 ? x->corr : 7];
+}
+
 // Pressure right-hand side and 1/diag from H; the refined forms also get the
 // FP32 copies of the operator from the same pass.
 // With xv given, a refined form's first residual check on xv (the solve's
@@ -525,9 +582,11 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
 // from its one-workgroup check.
 void build_system(gea_ctx* x, const State& S, const double* xv = nullptr) {
   const bool f32 = x->prm.solver != GEA_PCG_JACOBI_FP64;
+  x->net_now = x->prm.solver == GEA_LEARNED_MIXED && x->has_net &&
+               (x->prm.learned_always || net_gate(x).use(x->t_net_ms, x->t_iter_ms));
   // the learned form's first inner solve is the flexible CG, which needs no
   // cleared inner iterate or direction
-  const bool zero_inner = !(x->prm.solver == GEA_LEARNED_MIXED && x->has_net);
+  const bool zero_inner = !x->net_now;
   const RhsResidual res{xv, x->r32, x->d32, x->p032, (int)zero_inner, x->o_part, x->w32.u[1]};
   x->res_parts = launch_rhs(x->stream, x->G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H,
                             x->b, x->dinv, f32 ? x->c32 : nullptr, f32 ? x->D32 : nullptr,
@@ -650,7 +709,8 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
         [&](int j) {
           x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
           x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
-        });
+        },
+        Extra{}, 0, x->prm.solver == GEA_LEARNED_MIXED);
     if (rc != GEA_OK) return rc;
     if (outer == 0) x->last_iters32 = h32.iter;
     total += h32.iter;
@@ -695,6 +755,9 @@ int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
   const Geo& G = x->G;
   FcgVectors& v = fcg_vectors(x);
   *res_parts = 0;
+  // the first application is timed (set-up, network and flexible-CG step)
+  const bool timed = x->t_net_ms < 0 && !x->net_probe;
+  if (timed) HIPCHK(hipEventRecord(x->ev_net[0], x->stream));
   x->timer.run(4, x->stream, [&] { fcg_start(x->stream, G, v, x->sc32, budget, x->fsc); });
   const int cap = steps < budget ? steps : budget;
   int it = 0;
@@ -716,6 +779,10 @@ int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
     });
     HIPCHK(hipGetLastError());
     ++it;
+    if (timed && it == 1) {
+      HIPCHK(hipEventRecord(x->ev_net[1], x->stream));
+      x->net_probe = 1;
+    }
   }
   return it;
 }
@@ -724,6 +791,11 @@ int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
 // an inner solve stalls the rest of this solve uses Jacobi-PCG (fallback).
 gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   if (!x->has_net) return solve_mixed(x, xv, out);
+  if (!x->net_now) {  // the gate chose the refinement alone for this solve
+    gea_status rc = solve_mixed(x, xv, out);
+    if (rc == GEA_OK && out->outer_iters > 0) net_gate(x).record(false, out->iters);
+    return rc;
+  }
   const Geo& G = x->G;
   const CgWork& w = x->w32;
   cast_system(x);
@@ -859,7 +931,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       fcg = Extra{x->fsc, &hf, sizeof hf};
       first = x->last_iters_res > 0 ? x->last_iters_res + 4 : 0;
     }
-    gea_status rc = run_cg(x, x->sc32, h32, budget, first, iterate, fcg);
+    gea_status rc = run_cg(x, x->sc32, h32, budget, first, iterate, fcg, 0, true);
     if (rc != GEA_OK) return rc;
     done_iters += h32.iter;
     if (fcg.bytes) {
@@ -880,6 +952,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   out->outer_iters = outer;
   out->fallbacks = fallbacks;
   x->fallbacks += fallbacks;
+  if (out->status == GEA_OK && outer > 0) net_gate(x).record(true, total);
   return (gea_status)out->status;
 }
 
@@ -975,6 +1048,7 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
   stats->n_solves = 0;
   for (int k = 0; k < nc; ++k) {
     const bool last = k == nc - 1;
+    x->corr = k;  // (the learned form's gate decides per corrector, before the assembly)
     x->timer.run(5, x->stream, [&] { launch_H(s, G, ph, S.rho, S.u, x->ustar, x->phi, x->H); });
     x->timer.run(5, x->stream, [&] { build_system(x, S, N.pp); });
     HIPCHK(hipGetLastError());
@@ -1106,6 +1180,8 @@ gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* h
     HIPCHK(hipMemsetAsync(x->sc32, 0, sizeof(CgScalars), x->stream));
     launch_fill(x->stream, x->G, x->DT, x->prm.mu / x->prm.Pr * x->prm.cp);
     HIPCHK(hipGetLastError());
+    for (hipEvent_t* e : {&x->ev_net[0], &x->ev_net[1], &x->ev_it[0], &x->ev_it[1]})
+      HIPCHK(hipEventCreate(e));
     HIPCHK(hipStreamSynchronize(x->stream));
     return GEA_OK;
   });
@@ -1211,6 +1287,7 @@ gea_status gea_pressure_solve(gea_ctx* x, const double* b, double* xv, gea_ptr_k
       gea_status rc = steps_1_2(x, S, N.T);
       if (rc != GEA_OK) return fail(x, rc, "energy solve failed");
     }
+    x->corr = 0;
     x->timer.run(5, x->stream, [&] { launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H); });
     x->timer.run(5, x->stream, [&] { build_system(x, S); });
     HIPCHK(hipGetLastError());

@@ -42,7 +42,8 @@ class Params(C.Structure):
                 ("Pr", C.c_double), ("dt", C.c_double), ("n_corr", C.c_int32),
                 ("n_energy_sweeps", C.c_int32), ("solver", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double),
-                ("learned_steps", C.c_int32), ("inner_target", C.c_double)]
+                ("learned_steps", C.c_int32), ("inner_target", C.c_double),
+                ("learned_always", C.c_int32)]
 
 
 class Bubble(C.Structure):
@@ -117,7 +118,8 @@ def make_params(p: dict, solver="pcg64") -> Params:
                   int(p.get("n_corr", 2)), int(p.get("n_energy_sweeps", 2)), s,
                   float(p.get("tol", 1e-10)), int(p.get("max_iter", 20000)),
                   int(p.get("check_every", 8)), float(p.get("inner_tol", 1e-4)),
-                  int(p.get("learned_steps", 1)), float(p.get("inner_target", 0.0)))
+                  int(p.get("learned_steps", 1)), float(p.get("inner_target", 0.0)),
+                  int(p.get("learned_always", 0)))
 
 
 def _ptr(a):

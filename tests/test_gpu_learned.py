@@ -282,7 +282,7 @@ def test_pairs_are_solver_corrections(learned):
 def test_learned_solver_falls_back_and_still_converges(learned, junk):
     from paper_2303_10499_amd import gea
     cfg = configs.scaled("nonsmooth2d_2048", 128, 128)
-    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000)
+    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000, learned_always=1)
     S = gea.Solver(cfg["mesh"], cfg["params"], solver="learned")
     S.init_bubble(**cfg["bubble"])
     npar = learned.param_count(2)
@@ -314,7 +314,7 @@ def test_trained_network_gain(learned, name):
     import ctypes as C
     from paper_2303_10499_amd import gea
     cfg = configs.get(name)
-    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=200000)
+    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=200000, learned_always=1)
     S = gea.Solver(cfg["mesh"], cfg["params"], solver="learned")
     S.load_weights()
     S.init_bubble(**cfg["bubble"])
@@ -406,7 +406,8 @@ def test_learned_steps_converge_to_the_mixed_solution(learned, name, dims, steps
     states = {}
     for form in ("mixed", "learned"):
         cfg = configs.scaled(name, nx, nz, ny)
-        cfg["params"].update(tol=1e-10, inner_tol=1e-4, max_iter=100000, learned_steps=steps)
+        cfg["params"].update(tol=1e-10, inner_tol=1e-4, max_iter=100000, learned_steps=steps,
+                             learned_always=1)
         S = gea.Solver(cfg["mesh"], cfg["params"], solver=form)
         if form == "learned":
             S.load_weights()
@@ -440,7 +441,7 @@ def test_enqueue_ahead_survives_wrong_predictions(learned, form):
     states = {}
     for f in (form, "pcg64"):
         cfg = configs.scaled("bubble3d_256x256x128", 72, 24, 20)
-        cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000)
+        cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000, learned_always=1)
         S = gea.Solver(cfg["mesh"], cfg["params"], solver=f)
         if f == "learned":
             S.load_weights()
@@ -489,3 +490,30 @@ def test_learned_form_keeps_the_refinement_iteration_count_over_steps(learned):
         S.close()
     print("inner iterations over 8 steps", its)
     assert its["learned"] <= 1.03 * its["mixed"] + 20
+
+
+def test_learned_gate_keeps_the_network_off_where_it_does_not_pay(learned):
+    """The gate runs the network on a corrector's solve while the inner
+    iterations it saves take longer than one application (both timed on the
+    device).  On the 3D bubble the network saves about one FP32 iteration a
+    solve and costs about eight, so after the first solve with it and one
+    without, it runs only on every 16th solve; the solves still end at their
+    tolerance, and the forced form (learned_always) applies it every time."""
+    from paper_2303_10499_amd import gea
+    apps = {}
+    for always in (0, 1):
+        cfg = configs.scaled("bubble3d_256x256x128", 128, 64, 128)
+        cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000, learned_always=always)
+        S = gea.Solver(cfg["mesh"], cfg["params"], solver="learned")
+        S.load_weights()
+        S.init_bubble(**cfg["bubble"])
+        S.kernel_timing(True, reset=True)
+        st = S.step(40)
+        ms, n = S.kernel_times()
+        S.kernel_timing(False)
+        assert st.max_rel_res <= 1e-8
+        apps[always] = n[6]   # network launches (class 6), input kernel included
+        S.close()
+    print("network kernel launches over 40 steps, gated / always:", apps)
+    assert apps[1] > 0
+    assert apps[0] <= 0.25 * apps[1]

@@ -36,6 +36,13 @@
  *  [R11] rho^{n+1} is the conservative update rho^n - dt/V sum_out phi; the
  *       EOS form of eq. step4_4sd differs from it by dt/V times the pressure
  *       residual, reported as eos_mismatch.
+ *  [R12] The flux phi^n of Steps 1-3 (eq. e1_d: the face value of rho^n u^n
+ *       times the face area) is part of the state: the last corrector's
+ *       corrected flux of the previous step, which satisfies that step's
+ *       discrete continuity.  Only a state given by cell fields alone (the
+ *       initial state) gets the cubic face interpolation of rho u.  (Forming
+ *       it from the cell momentum every step grows a grid-scale mode at a
+ *       rate ~|u|/h on the 5 m smooth bubble of Sec. 4.1.)
  *  [R13] The solve stops when ||b - A x||_2 <= tol ||b||_2 (recursive
  *       residual), starting from x0 = p' of the previous corrector.
  *  [R14] Initial state: eq. rho_wb read with the background theta0 in the
@@ -322,6 +329,28 @@ void geao_mass_predictor(const geao_mesh* m, const geao_params* q, const double*
   PER_CELL
   for (long P = 0; P < G.nc; ++P) rho_star[P] = rho[P] - q->dt / G.V * sum_out(&G, phi, P);
   free(mom);
+}
+
+/* phi_f = I4(rho u . n)_f S_f on interior faces (eq. e1_d from cell values) */
+void geao_face_mass_flux(const geao_mesh* m, const double* rho, const double* u, double* phi) {
+  geom G = make_geom(m);
+  double* mom = zalloc(G.nc);
+  for (int d = 0; d < G.ndim; ++d) {
+    PER_CELL
+    for (long P = 0; P < G.nc; ++P) mom[P] = rho[P] * u[d * G.nc + P];
+    PER_CELL
+    for (long P = 0; P < G.nc; ++P)
+      phi[d * G.nc + P] = has_hi(&G, P, d) ? interp4(&G, mom, P, d) * G.S[d] : 0.0;
+  }
+  free(mom);
+}
+
+/* rho* = rho^n - dt/V sum_out phi^n (eq. e1_d with the state's flux) */
+void geao_density_predictor(const geao_mesh* m, const geao_params* q, const double* rho,
+                            const double* phi, double* rho_star) {
+  geom G = make_geom(m);
+  PER_CELL
+  for (long P = 0; P < G.nc; ++P) rho_star[P] = rho[P] - q->dt / G.V * sum_out(&G, phi, P);
 }
 
 /* rho* u* = rho^n u^n - dt/V [sum_out phi I4(u^n) - sum_f mu snGrad(u^n) S]
@@ -657,11 +686,13 @@ static int check_args(const geao_mesh* m, const geao_params* q) {
   return 1;
 }
 
-/* Steps 1 and 2 of the step starting from the given state */
+/* Steps 1 and 2 of the step starting from the given state (phi: its flux) */
 static void steps_1_2(const geao_mesh* m, const geao_params* q, const double* rho,
                       const double* u, const double* T, const double* pp, const double* p,
-                      const double* Tbg, work_t* w) {
-  geao_mass_predictor(m, q, rho, u, w->phi, w->rho_star);
+                      const double* phi, const double* Tbg, work_t* w) {
+  geom G = make_geom(m);
+  memcpy(w->phi, phi, sizeof(double) * G.ndim * G.nc);
+  geao_density_predictor(m, q, rho, w->phi, w->rho_star);
   geao_momentum_predictor(m, q, rho, u, pp, w->rho_star, w->phi, w->u_star);
   geao_energy(m, q, rho, u, T, w->u_star, w->rho_star, w->phi, Tbg, w->T_new);
   geao_eos_coeffs(m, q, p, w->T_new, w->rho_star, w->rho23, w->psi, w->c, w->D);
@@ -669,11 +700,11 @@ static void steps_1_2(const geao_mesh* m, const geao_params* q, const double* rh
 
 int geao_pressure_system(const geao_mesh* m, const geao_params* q, const double* rho,
                          const double* u, const double* T, const double* pp, const double* p,
-                         const double* Tbg, double* c, double* D, double* b) {
+                         const double* phi, const double* Tbg, double* c, double* D, double* b) {
   if (!check_args(m, q)) return GEAO_ERR_ARG;
   geom G = make_geom(m);
   work_t w = work_alloc(&G);
-  steps_1_2(m, q, rho, u, T, pp, p, Tbg, &w);
+  steps_1_2(m, q, rho, u, T, pp, p, phi, Tbg, &w);
   geao_H(m, q, rho, u, w.u_star, w.phi, w.H);
   geao_predicted_flux_rhs(m, q, rho, w.rho23, w.psi, w.D, w.H, w.phi_tilde, w.b);
   memcpy(c, w.c, sizeof(double) * G.nc);
@@ -684,7 +715,7 @@ int geao_pressure_system(const geao_mesh* m, const geao_params* q, const double*
 }
 
 int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, double* T,
-              double* pp, double* p, const double* Tbg, geao_step_stats* st) {
+              double* pp, double* p, double* phi, const double* Tbg, geao_step_stats* st) {
   if (!check_args(m, q)) return GEAO_ERR_ARG;
   geom G = make_geom(m);
   work_t w = work_alloc(&G);
@@ -695,7 +726,7 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
   int status = GEAO_OK;
   st->n_solves = 0;
 
-  steps_1_2(m, q, rho, u, T, pp, p, Tbg, &w);
+  steps_1_2(m, q, rho, u, T, pp, p, phi, Tbg, &w);
 
   memcpy(u_k, w.u_star, sizeof(double) * G.ndim * G.nc);
   memcpy(pp_k, pp, sizeof(double) * G.nc);
@@ -722,6 +753,7 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
     memcpy(T, w.T_new, sizeof(double) * G.nc);
     memcpy(pp, pp_k, sizeof(double) * G.nc);
     memcpy(p, p_new, sizeof(double) * G.nc);
+    memcpy(phi, w.phi_corr, sizeof(double) * G.ndim * G.nc);  /* phi^{n+1} */
   }
   work_free(&w);
   free(u_k); free(pp_k); free(rho_new); free(p_new);

@@ -98,6 +98,12 @@ void geao_potential(const geao_mesh* m, const geao_params* q, double* out);
 /* ---- the sub-steps of one time step (Sec. 3) -------------------------- */
 void geao_mass_predictor(const geao_mesh* m, const geao_params* q, const double* rho,
                          const double* u, double* phi, double* rho_star);
+/* phi = I4(rho u . n) S on interior faces (ndim face arrays; 0 on walls):
+ * the flux of a state given by its cell fields alone */
+void geao_face_mass_flux(const geao_mesh* m, const double* rho, const double* u, double* phi);
+/* rho* = rho^n - dt/V sum_out phi^n with the state's flux */
+void geao_density_predictor(const geao_mesh* m, const geao_params* q, const double* rho,
+                            const double* phi, double* rho_star);
 void geao_momentum_predictor(const geao_mesh* m, const geao_params* q, const double* rho,
                              const double* u, const double* pp, const double* rho_star,
                              const double* phi, double* u_star);
@@ -127,11 +133,12 @@ void geao_finalize(const geao_mesh* m, const geao_params* q, const double* rho_o
  * from this state: returns the pressure system (c, D, b) it would solve. */
 int geao_pressure_system(const geao_mesh* m, const geao_params* q, const double* rho,
                          const double* u, const double* T, const double* pp, const double* p,
-                         const double* Tbg, double* c, double* D, double* b);
+                         const double* phi, const double* Tbg, double* c, double* D, double* b);
 
-/* One full step n -> n+1, in place. */
+/* One full step n -> n+1, in place; phi (ndim face arrays, the face flux of
+ * the state) in: phi^n, out: phi^{n+1} (the last corrector's flux). */
 int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, double* T,
-              double* pp, double* p, const double* Tbg, geao_step_stats* st);
+              double* pp, double* p, double* phi, const double* Tbg, geao_step_stats* st);
 
 /* potential temperature fluctuation theta' = T/(p/p0)^{R/cp} - theta0 (eqs. theta, theta_split) */
 void geao_theta_prime(const geao_mesh* m, const geao_params* q, const double* T, const double* p,

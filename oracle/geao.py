@@ -97,8 +97,10 @@ def lib(omp: bool = False):
         L.geao_pcg.argtypes = [P(Mesh), d, d, d, d, C.c_double, C.c_int, P(SolveStats)]
         L.geao_correct.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d]
         L.geao_finalize.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d]
-        L.geao_pressure_system.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d]
-        L.geao_step.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, P(StepStats)]
+        L.geao_pressure_system.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d, d]
+        L.geao_step.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, P(StepStats)]
+        L.geao_face_mass_flux.argtypes = [P(Mesh), d, d, d]
+        L.geao_density_predictor.argtypes = [P(Mesh), P(Params), d, d, d]
         L.geao_theta_prime.argtypes = [P(Mesh), P(Params), d, d, d]
         L.geao_threads.argtypes = []
         L.geao_threads.restype = C.c_int
@@ -119,10 +121,11 @@ class State:
     pp: np.ndarray     # p'
     p: np.ndarray
     Tbg: np.ndarray    # (nz,)
+    phi: np.ndarray = None  # (ndim, ncell) face mass flux; None: I4(rho u) S when first needed
 
     def copy(self) -> "State":
-        return State(*(np.array(a, copy=True) for a in
-                       (self.rho, self.u, self.T, self.pp, self.p, self.Tbg)))
+        return State(*(None if a is None else np.array(a, copy=True) for a in
+                       (self.rho, self.u, self.T, self.pp, self.p, self.Tbg, self.phi)))
 
 
 class Oracle:
@@ -158,14 +161,27 @@ class Oracle:
                                       _p(s.rho), _p(s.u), _p(s.T), _p(s.pp), _p(s.p), _p(s.Tbg))
         if rc_ != OK:
             raise ValueError(f"geao_init_bubble failed: {rc_}")
+        s.phi = self.face_mass_flux(s.rho, s.u)
         return s
+
+    def face_mass_flux(self, rho, u):
+        phi = self.zeros(self.ndim)
+        self.L.geao_face_mass_flux(C.byref(self.mesh), _p(np.ascontiguousarray(rho)),
+                                   _p(np.ascontiguousarray(u)), _p(phi))
+        return phi
+
+    def _flux(self, s: State):
+        if s.phi is None:
+            s.phi = self.face_mass_flux(s.rho, s.u)
+        return s.phi
 
     def step(self, s: State, nsteps: int = 1) -> list:
         stats = []
         for _ in range(nsteps):
             st = StepStats()
+            phi = self._flux(s)
             rc = self.L.geao_step(C.byref(self.mesh), C.byref(self.params), _p(s.rho), _p(s.u),
-                                  _p(s.T), _p(s.pp), _p(s.p), _p(s.Tbg), C.byref(st))
+                                  _p(s.T), _p(s.pp), _p(s.p), _p(phi), _p(s.Tbg), C.byref(st))
             stats.append(st)
             if rc != OK:
                 raise RuntimeError(f"geao_step failed with status {rc}")
@@ -174,8 +190,8 @@ class Oracle:
     def pressure_system(self, s: State):
         c, D, b = self.zeros(), self.zeros(), self.zeros()
         rc = self.L.geao_pressure_system(C.byref(self.mesh), C.byref(self.params), _p(s.rho),
-                                         _p(s.u), _p(s.T), _p(s.pp), _p(s.p), _p(s.Tbg),
-                                         _p(c), _p(D), _p(b))
+                                         _p(s.u), _p(s.T), _p(s.pp), _p(s.p), _p(self._flux(s)),
+                                         _p(s.Tbg), _p(c), _p(D), _p(b))
         if rc != OK:
             raise ValueError(f"geao_pressure_system failed: {rc}")
         return c, D, b
@@ -241,6 +257,12 @@ class Oracle:
         phi, rs = self.zeros(self.ndim), self.zeros()
         self.L.geao_mass_predictor(C.byref(self.mesh), C.byref(self.params), _p(rho), _p(u), _p(phi), _p(rs))
         return phi, rs
+
+    def density_predictor(self, rho, phi):
+        rs = self.zeros()
+        self.L.geao_density_predictor(C.byref(self.mesh), C.byref(self.params),
+                                      _p(np.ascontiguousarray(rho)), _p(np.ascontiguousarray(phi)), _p(rs))
+        return rs
 
     def momentum_predictor(self, rho, u, pp, rho_star, phi):
         us = self.zeros(self.ndim)

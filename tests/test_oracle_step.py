@@ -442,9 +442,10 @@ def test_unconverged_solve_leaves_state_untouched(oracle_lib):
 
 def test_step_is_the_composition_of_the_pinned_substeps(oracle_lib):
     """The step wires the sub-steps in the paper's order: Step 1, Step 2, then
-    n_corr correctors, each convecting with the frozen Step-1 flux phi^n
-    (eq. step2_sd of Step 3 and the H operator both carry phi^n_j), the
-    corrected flux of the last corrector feeding the end-of-step density."""
+    n_corr correctors, each convecting with the state's flux phi^n (eq. e1_d;
+    eq. step2_sd of Step 3 and the H operator both carry phi^n_j), the
+    corrected flux of the last corrector feeding the end-of-step density and
+    becoming the next state's flux."""
     cfg = configs.get("bubble2d_64x32", tol=1e-13)
     cfg["mesh"].update(nx=16, nz=12, ly=1250.0)
     O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
@@ -452,7 +453,8 @@ def test_step_is_the_composition_of_the_pinned_substeps(oracle_lib):
     O.step(s, 2)                      # a moving state
     want = s.copy()
     O.step(want, 1)
-    phi, rs = O.mass_predictor(s.rho, s.u)
+    phi = s.phi
+    rs = O.density_predictor(s.rho, phi)
     us = O.momentum_predictor(s.rho, s.u, s.pp, rs, phi)
     Tn = O.energy(s.rho, s.u, s.T, us, rs, phi, s.Tbg)
     r23, psi, c, D = O.eos_coeffs(s.p, Tn, rs)
@@ -464,8 +466,11 @@ def test_step_is_the_composition_of_the_pinned_substeps(oracle_lib):
         assert rc == 0
         phik, uk = O.correct(ppk, r23, H, D, rs, pt)
     rn, pn, mm = O.finalize(s.rho, phik, ppk, r23, psi)
-    for got, ref in ((rn, want.rho), (uk, want.u), (Tn, want.T), (ppk, want.pp), (pn, want.p)):
+    for got, ref in ((rn, want.rho), (uk, want.u), (Tn, want.T), (ppk, want.pp), (pn, want.p),
+                     (phik, want.phi)):
         np.testing.assert_array_equal(got, ref)
+    # the state's flux is not the face interpolation of its cell momentum
+    assert np.max(np.abs(want.phi - O.face_mass_flux(want.rho, want.u))) > 1e-6 * np.max(np.abs(want.phi))
 
 
 @pytest.mark.parametrize("name,dims", [("bubble2d_64x32", None), ("bubble3d_256x256x128", (16, 10, 12))])
@@ -481,5 +486,5 @@ def test_all_core_oracle_build_gives_the_same_bits(oracle_lib, name, dims):
     s2 = many.init_bubble(**cfg["bubble"])
     one.step(s1, 4)
     many.step(s2, 4)
-    for f in ("rho", "u", "T", "pp", "p"):
+    for f in ("rho", "u", "T", "pp", "p", "phi"):
         np.testing.assert_array_equal(getattr(s1, f), getattr(s2, f), err_msg=f)

@@ -134,7 +134,12 @@ enum {
   GEA_FIELD_P = 1u << 4,
   GEA_FIELD_C = 1u << 5,       /* pressure system of the last assembly: c    */
   GEA_FIELD_D = 1u << 6,       /*                                          D  */
-  GEA_FIELD_B = 1u << 7        /*                                          b  */
+  GEA_FIELD_B = 1u << 7,       /*                                          b  */
+  GEA_FIELD_PHI = 1u << 8      /* face mass flux of the state: ndim blocks,
+                                  block d, value P: the face between cell P
+                                  and cell P + stride_d (0 where P is at the
+                                  upper wall); strides 1, nx, nx*ny (3D) or
+                                  1, nx (2D) */
 };
 
 /* Bytes of device workspace needed for this mesh and parameter set. */
@@ -160,17 +165,30 @@ gea_status gea_set_solver(gea_ctx* ctx, int32_t solver, double tol, int32_t max_
 /* Build the initial state of Sec. 4 on the device (eqs. rho_wb, dcEqn1,
  * dcEqn2, e0): a neutral atmosphere with theta0, a discretely hydrostatic
  * background column (p'_{k+1} - p'_k = g z_{k+1/2} (rho_{k+1} - rho_k)), the
- * temperature perturbed by theta' at unchanged pressure, u = 0. */
+ * temperature perturbed by theta' at unchanged pressure, u = 0, and the
+ * face mass flux of those cell fields (0, since u = 0). */
 gea_status gea_init_bubble(gea_ctx* ctx, const gea_bubble* bubble);
 
 /* Copy a state in: the given fields of the problem statement of Sec. 3
  * (rho^n, u^n, T^n, p^n) and the split pressure p'^n = p^n + rho^n g z of
  * eq. p_split.  rho, T, p_prime, p: ncell values; u: ndim*ncell;
  * T_bg: nz values (background temperature column that the energy diffusion
- * term subtracts).  All pointers of the given kind, none may be NULL. */
+ * term subtracts).  All pointers of the given kind, none may be NULL.  The
+ * state's face mass flux, which Steps 1-3 transport with, becomes the
+ * fourth-order interpolation I4(rho u . n)_f S_f of these fields (eq. e1_d;
+ * 0 on the walls); gea_set_face_flux replaces it. */
 gea_status gea_set_state(gea_ctx* ctx, const double* rho, const double* u, const double* T,
                          const double* p_prime, const double* p, const double* T_bg,
                          gea_ptr_kind kind);
+
+/* Replace the current state's face mass flux (layout of GEA_FIELD_PHI,
+ * ndim*ncell values of the given kind; values on the upper walls are
+ * ignored and stored as 0).  A step transports with the flux of the state it
+ * starts from and leaves the last corrector's corrected flux for the next
+ * one (Sec. 3, Steps 1-3 and eq. e1_d), so a state copied out with
+ * gea_get_fields (all fields and GEA_FIELD_PHI) and copied back in with
+ * gea_set_state and this call continues bitwise as the original would. */
+gea_status gea_set_face_flux(gea_ctx* ctx, const double* phi, gea_ptr_kind kind);
 
 /* Advance nsteps time steps (Sec. 3, Steps 1-3).  stats may be NULL. */
 gea_status gea_step(gea_ctx* ctx, int32_t nsteps, gea_step_stats* stats);
@@ -187,6 +205,16 @@ gea_status gea_pressure_solve(gea_ctx* ctx, const double* b, double* x, gea_ptr_
  * last corrector of gea_step). */
 gea_status gea_apply_pressure_operator(gea_ctx* ctx, const double* x, double* y,
                                        gea_ptr_kind kind);
+
+/* Extrema of the current state, as the paper reports them for its validation
+ * runs (Sec. 4, Tables 1 and 3): the velocity components and the potential
+ * temperature perturbation theta' = T/pi - theta0, pi = (p/p0)^{R/c_p}
+ * (Sec. 2, eqs. theta, theta_split; p0 and theta0 from the parameters).
+ * v is 0 in 2D.  Computed on the device; returns after the copy. */
+typedef struct {
+  double u_min, u_max, v_min, v_max, w_min, w_max, theta_min, theta_max;
+} gea_extrema;
+gea_status gea_state_extrema(gea_ctx* ctx, gea_extrema* out);
 
 /* Copy the selected fields out, packed in bit order (see GEA_FIELD_*): the
  * end-of-step state (rho, u, T, p', p)^{n+1} of the problem statement of

@@ -50,6 +50,26 @@ CONFIGS = {
         steps=200, bubble=dict(kind=1, xc=10000.0, yc=10000.0, zc=2000.0, rc=2000.0, amp=2.0),
         solver="learned", tol=1e-8),
 }
+# The paper's own validation runs (Sec. 4): the 1000 m x 1000 m box, c_v = 715.5 and
+# c_p = R + c_v, dt 0.1 s, to 600 s; the smooth bubble (eq. dcEqn1: 0.5 K peak, r_c 250 m,
+# centre (500, 350) m, mu 0.15) on 5 m cells and the non-smooth one (eq. dcEqn2: 0.5 K,
+# centre (500, 260) m, mu 0.3) on 5 m and 10 m cells.
+AIR_PAPER = dict(AIR, cv=715.5, cp=287.0 + 715.5)
+
+
+def _paper(name, n, mu, bubble):
+    c = _cfg(name, n, 1, n, 1000.0, 1000.0 / n, 1000.0, dt=0.1, mu=mu, steps=6000, bubble=bubble,
+             solver="pcg64", tol=1e-10, max_iter=100000)
+    c["params"].update(cv=AIR_PAPER["cv"], cp=AIR_PAPER["cp"])
+    return c
+
+
+CONFIGS["paper_smooth_5m"] = _paper(
+    "paper_smooth_5m", 200, 0.15, dict(kind=1, xc=500.0, yc=0.0, zc=350.0, rc=250.0, amp=0.5))
+CONFIGS["paper_nonsmooth_5m"] = _paper(
+    "paper_nonsmooth_5m", 200, 0.3, dict(kind=2, xc=500.0, yc=0.0, zc=260.0, rc=250.0, amp=0.5))
+CONFIGS["paper_nonsmooth_10m"] = _paper(
+    "paper_nonsmooth_10m", 100, 0.3, dict(kind=2, xc=500.0, yc=0.0, zc=260.0, rc=250.0, amp=0.5))
 CONFIGS["nonsmooth2d_2048_eval"] = dict(copy.deepcopy(CONFIGS["nonsmooth2d_2048"]),
                                         name="nonsmooth2d_2048_eval", solver="learned")
 

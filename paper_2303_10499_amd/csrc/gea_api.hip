@@ -44,6 +44,7 @@ struct State {
   double* T;
   double* pp;
   double* p;
+  double* phi[3];  // face mass flux: face d of cell P lies between P and P + st[d]
 };
 
 constexpr int kMaxPartials = 2048 * 8;
@@ -156,7 +157,6 @@ struct gea_ctx {
   double* rho_a;
   double* pp_a;
   // step work arrays
-  double* phi[3];
   double* rho_star;
   double* ustar[3];
   double* e0;
@@ -194,6 +194,7 @@ struct gea_ctx {
   float* d32;
   // reductions
   double* partials;  // per-workgroup partials of the step kernels
+  double* ext;       // extrema of the state (8 values)
   double* o_part;    // partials of the refinement's outer residual
   CgScalars* sc;     // FP64 solver and step scalars
   CgScalars* sc32;   // inner FP32 solver scalars
@@ -315,11 +316,11 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
     S.T = cv.take<double>(nc);
     S.pp = cv.take<double>(nc);
     S.p = cv.take<double>(nc);
+    for (int d = 0; d < 3; ++d) S.phi[d] = d < nd ? cv.take<double>(nc) : nullptr;
   }
   x->Tbg = cv.take<double>(m.nz);
   x->rho_a = cv.take<double>(m.nz);
   x->pp_a = cv.take<double>(m.nz);
-  for (int d = 0; d < 3; ++d) x->phi[d] = d < nd ? cv.take<double>(nc) : nullptr;
   x->rho_star = cv.take<double>(nc);
   for (int d = 0; d < 3; ++d) x->ustar[d] = d < nd ? cv.take<double>(nc) : nullptr;
   x->e0 = cv.take<double>(nc);
@@ -358,6 +359,7 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
     x->partials = cv.take<double>(zb > kMaxPartials ? zb : kMaxPartials);
   }
   x->o_part = cv.take<double>(kMaxPartials);
+  x->ext = cv.take<double>(8);
   // the solver scalars side by side, 256 bytes apart: a poll copies them in one piece
   x->sc = cv.take<CgScalars>(1);
   x->sc32 = cv.take<CgScalars>(1);
@@ -1003,7 +1005,7 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
   const Phys& ph = x->ph;
   hipStream_t s = x->stream;
   x->timer.run(5, x->stream, [&] {
-    launch_step1(s, G, ph, S.rho, S.u, S.T, S.pp, x->phi, x->rho_star, x->e0, x->ustar, pp_out);
+    launch_step1(s, G, ph, S.rho, S.u, S.T, S.pp, S.phi, x->rho_star, x->e0, x->ustar, pp_out);
   });
   const double* e_prev = x->e0;
   const double* T_prev = S.T;
@@ -1014,7 +1016,7 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
     double* T_next = last ? T_out : ((sw & 1) ? x->Tb : x->Ta);
     int nparts = 0;
     x->timer.run(5, x->stream, [&] {
-      nparts = launch_energy_rhs(s, G, ph, S.rho, x->e0, e_prev, T_prev, x->phi, x->rho_star,
+      nparts = launch_energy_rhs(s, G, ph, S.rho, x->e0, e_prev, T_prev, S.phi, x->rho_star,
                                  x->ustar, x->Tbg, x->b, x->c, x->dinv, T_next, x->r, x->p0,
                                  x->w64.u[1], x->w64.b);
     });
@@ -1049,7 +1051,7 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
   for (int k = 0; k < nc; ++k) {
     const bool last = k == nc - 1;
     x->corr = k;  // (the learned form's gate decides per corrector, before the assembly)
-    x->timer.run(5, x->stream, [&] { launch_H(s, G, ph, S.rho, S.u, x->ustar, x->phi, x->H); });
+    x->timer.run(5, x->stream, [&] { launch_H(s, G, ph, S.rho, S.u, x->ustar, S.phi, x->H); });
     x->timer.run(5, x->stream, [&] { build_system(x, S, N.pp); });
     HIPCHK(hipGetLastError());
     x->has_system = true;
@@ -1058,7 +1060,7 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
       for (int d = 0; d < 3; ++d) uo[d] = N.u[d];
     const std::function<void()> correct = [&] {
       x->timer.run(5, x->stream, [&] { launch_correct(s, G, ph, N.pp, x->rho23, x->psi, x->H, x->D, x->rho_star, uo, last, S.rho,
-                     N.rho, N.p, x->partials, x->sc); });
+                     N.rho, N.p, N.phi, x->partials, x->sc); });
     };
     gea_solve_stats ss;
     x->tail = &correct;
@@ -1220,6 +1222,7 @@ gea_status gea_init_bubble(gea_ctx* x, const gea_bubble* b) {
     launch_init_column(x->stream, x->G, x->ph, x->rho_a, x->pp_a, x->Tbg);
     launch_init_fields(x->stream, x->G, x->ph, b->kind, b->xc, b->yc, b->zc, b->rc, b->amp,
                        x->rho_a, x->pp_a, x->Tbg, S.rho, S.u, S.T, S.pp, S.p);
+    launch_face_mass_flux(x->stream, x->G, S.rho, S.u, S.phi);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(x->stream));
     x->has_state = true;
@@ -1244,9 +1247,27 @@ gea_status gea_set_state(gea_ctx* x, const double* rho, const double* u, const d
     HIPCHK(hipMemcpyAsync(S.pp, p_prime, n, kind_in(kind), s));
     HIPCHK(hipMemcpyAsync(S.p, p, n, kind_in(kind), s));
     HIPCHK(hipMemcpyAsync(x->Tbg, T_bg, sizeof(double) * x->G.nz, kind_in(kind), s));
+    launch_face_mass_flux(s, x->G, S.rho, S.u, S.phi);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     x->has_state = true;
     x->has_system = false;
+    return GEA_OK;
+  });
+}
+
+gea_status gea_set_face_flux(gea_ctx* x, const double* phi, gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!phi) return fail(x, GEA_ERR_ARG, "null flux");
+  if (!x->has_state) return fail(x, GEA_ERR_STATE, "no state: call gea_init_bubble or gea_set_state");
+  return guarded(x, [&]() {
+    const State& S = x->st[x->cur];
+    const size_t n = sizeof(double) * x->G.nc;
+    for (int d = 0; d < x->G.ndim; ++d)
+      HIPCHK(hipMemcpyAsync(S.phi[d], phi + (size_t)d * x->G.nc, n, kind_in(kind), x->stream));
+    launch_clear_wall_faces(x->stream, x->G, S.phi);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(x->stream));
     return GEA_OK;
   });
 }
@@ -1288,7 +1309,7 @@ gea_status gea_pressure_solve(gea_ctx* x, const double* b, double* xv, gea_ptr_k
       if (rc != GEA_OK) return fail(x, rc, "energy solve failed");
     }
     x->corr = 0;
-    x->timer.run(5, x->stream, [&] { launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H); });
+    x->timer.run(5, x->stream, [&] { launch_H(s, G, x->ph, S.rho, S.u, x->ustar, S.phi, x->H); });
     x->timer.run(5, x->stream, [&] { build_system(x, S); });
     HIPCHK(hipGetLastError());
     const size_t n = sizeof(double) * G.nc;
@@ -1319,6 +1340,22 @@ gea_status gea_apply_pressure_operator(gea_ctx* x, const double* xin, double* y,
   });
 }
 
+gea_status gea_state_extrema(gea_ctx* x, gea_extrema* out) {
+  if (!x) return GEA_ERR_ARG;
+  if (!out) return fail(x, GEA_ERR_ARG, "null output");
+  if (!x->has_state) return fail(x, GEA_ERR_STATE, "no state");
+  return guarded(x, [&]() {
+    const State& S = x->st[x->cur];
+    launch_extrema(x->stream, x->G, x->ph, S.u, S.T, S.p, x->o_part, x->ext);
+    HIPCHK(hipGetLastError());
+    double v[8];
+    const Extra part{x->ext, v, sizeof v};
+    read_structs(x, &part, 1);
+    *out = gea_extrema{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+    return GEA_OK;
+  });
+}
+
 gea_status gea_get_fields(gea_ctx* x, uint32_t mask, double* out, gea_ptr_kind kind) {
   if (!x) return GEA_ERR_ARG;
   if (!out) return fail(x, GEA_ERR_ARG, "null output");
@@ -1342,6 +1379,8 @@ gea_status gea_get_fields(gea_ctx* x, uint32_t mask, double* out, gea_ptr_kind k
     if (mask & GEA_FIELD_C) put(x->c);
     if (mask & GEA_FIELD_D) put(x->D);
     if (mask & GEA_FIELD_B) put(x->b);
+    if (mask & GEA_FIELD_PHI)
+      for (int d = 0; d < x->G.ndim; ++d) put(S.phi[d]);
     HIPCHK(hipStreamSynchronize(x->stream));
     return GEA_OK;
   });
@@ -1482,7 +1521,7 @@ gea_status gea_make_pair(gea_ctx* x, double rel_tol, float* in_r, float* in_a, f
       gea_status rc = steps_1_2(x, S, N.T);
       if (rc != GEA_OK) return fail(x, rc, "energy solve failed");
     }
-    launch_H(s, G, x->ph, S.rho, S.u, x->ustar, x->phi, x->H);
+    launch_H(s, G, x->ph, S.rho, S.u, x->ustar, S.phi, x->H);
     build_system(x, S);
     // r0 = b - A p'  (FP64), then the tight FP64 solve from x0 = p'
     launch_apply_A(s, G, x->c, x->D, S.pp, x->r64);

@@ -86,8 +86,15 @@ struct RhsResidual {
   double* i_part;
 };
 
-// Step 1 (mass flux, rho*, e^n, momentum predictor): one pass in 3D, the two
-// kernels in 2D; pp_copy (or null) also receives p' (the solve's initial guess)
+// the face mass flux I4(rho u . n)_f S_f of a state given by its cell fields
+// (0 on walls): face d of cell P is the face between P and P + st[d]
+void launch_face_mass_flux(hipStream_t s, const Geo& G, const double* rho, double* const* u,
+                           double* const* phi);
+// sets the flux of the upper wall faces to 0
+void launch_clear_wall_faces(hipStream_t s, const Geo& G, double* const* phi);
+// Step 1 (rho* from the state's face flux phi, e^n, momentum predictor): one
+// pass in 3D, the two kernels in 2D; pp_copy (or null) also receives p' (the
+// solve's initial guess)
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
                   double* rho_star, double* e0, double* const* u_star, double* pp_copy);
@@ -118,8 +125,13 @@ int launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
                     const double* rho23, const double* psi, double* const* H, const double* D,
                     const double* rho_star, double* const* u_out, bool last,
-                    const double* rho_old, double* rho_new, double* p_new, double* partials,
-                    CgScalars* sc);
+                    const double* rho_old, double* rho_new, double* p_new,
+                    double* const* phi_out,  // last: the corrected face fluxes
+                    double* partials, CgScalars* sc);
+// extrema (min, max) of u, v (0 in 2D), w and theta' into out[8]; part holds
+// 8 values per workgroup of the grid-stride grid
+int launch_extrema(hipStream_t s, const Geo& G, const Phys& ph, double* const* u, const double* T,
+                   const double* p, double* part, double* out);
 void launch_init_column(hipStream_t s, const Geo& G, const Phys& ph, double* rho_a,
                         double* pp_a, double* Tbg);
 void launch_init_fields(hipStream_t s, const Geo& G, const Phys& ph, int kind, double xc,

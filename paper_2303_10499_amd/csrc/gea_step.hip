@@ -103,60 +103,83 @@ __device__ __forceinline__ Line line_lds(const double* s, int h, int str) {
 
 // ---- Step 1 ----------------------------------------------------------------
 
-// phi_f = I4(rho u . n) S on interior faces, rho* = rho - dt/V sum_out phi;
+// rho* = rho - dt/V sum_out phi with the state's face flux phi (eq. e1_d);
 // also e^n = c_v T + K + Phi, the total energy the Step 2 sweeps start from
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_mass_flux(Geo G, Phys ph, int kc,
-                                                      const double* __restrict__ rho,
-                                                      Vec<NDIM> u, const double* __restrict__ T,
-                                                      Vec<NDIM> phi, double* __restrict__ rho_star,
-                                                      double* __restrict__ e0) {
+__global__ __launch_bounds__(kBlock) void k_density_predictor(Geo G, Phys ph, int kc,
+                                                              const double* __restrict__ rho,
+                                                              Vec<NDIM> u, const double* __restrict__ T,
+                                                              Vec<NDIM> phi, double* __restrict__ rho_star,
+                                                              double* __restrict__ e0) {
   constexpr int Z = NDIM - 1;
   const Col c = col_of<NDIM>(G, kc);
   if (!c.act) return;
   const int nz = G.n[Z], pl = c.pl;
-  const double* uz = u.p[Z];
-  auto mz = [&](int Q) { return rho[Q] * uz[Q]; };
   int P = c.base + pl * c.k0;
-  Line z = line_at(mz, P, pl, c.k0, nz);
-  double flo = c.k0 > 0 ? i4_lo(z, c.k0, nz) * G.S[Z] : 0.0;
+  double flo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
   for (int k = c.k0; k < c.k1; ++k, P += pl) {
     // loads of the plane
-    Line s[NDIM - 1];
+    double fh[NDIM - 1], fl[NDIM - 1];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
-      const double* ud = u.p[d];
-      s[d] = line_at([&](int Q) { return rho[Q] * ud[Q]; }, P, G.st[d], coord(c, d), G.n[d]);
+      fh[d] = phi.p[d][P];
+      fl[d] = phi.p[d][nb(coord(c, d) > 0, P - G.st[d], P)];
     }
-    const double r = rho[P], Tc = T[P];
+    const double fz = phi.p[Z][P], r = rho[P], Tc = T[P];
     double uc[NDIM];
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) uc[d] = u.p[d][P];
-    const double znext = mz(nb(k + 3 < nz, P + 3 * pl, P));
-    // fluxes
-    double sum = 0.0, hid[NDIM - 1];
+    // net outward flux
+    double sum = 0.0;
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
       const int n = G.n[d], q = coord(c, d);
-      const double hi = q + 1 < n ? i4_hi(s[d], q, n) * G.S[d] : 0.0;
-      const double lo = q > 0 ? i4_lo(s[d], q, n) * G.S[d] : 0.0;
-      hid[d] = hi;
-      sum += hi;
-      sum -= lo;
+      sum += q + 1 < n ? fh[d] : 0.0;
+      sum -= q > 0 ? fl[d] : 0.0;
     }
-    const double hi = k + 1 < nz ? i4_hi(z, k, nz) * G.S[Z] : 0.0;
+    const double hi = k + 1 < nz ? fz : 0.0;
     sum += hi;
     sum -= flo;
     flo = hi;
-#pragma unroll
-    for (int d = 0; d < Z; ++d) phi.p[d][P] = hid[d];
-    phi.p[Z][P] = hi;
     rho_star[P] = r - ph.dt / G.V * sum;
     double kin = 0.0;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) kin += uc[d] * uc[d];
     e0[P] = ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, k);
-    z = shift(z, k + 3 < nz ? znext : 0.0);
+  }
+}
+
+// a given face flux: the upper wall faces hold 0
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_clear_wall_faces(Geo G, Vec<NDIM> phi) {
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < G.nc; P += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d)
+      if ((P / G.st[d]) % G.n[d] + 1 == G.n[d]) phi.p[d][P] = 0.0;
+  }
+}
+
+// phi_f = I4(rho u . n)_f S_f on interior faces, 0 on walls (eq. e1_d from
+// the cell fields): the flux of a state given by its cell fields alone
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_face_mass_flux(Geo G, const double* __restrict__ rho,
+                                                           Vec<NDIM> u, Vec<NDIM> phi) {
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < G.nc; P += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+      const int st = G.st[d], n = G.n[d], i = (P / st) % n;
+      const double* ud = u.p[d];
+      double v = 0.0;
+      if (i + 1 < n) {
+        const double mc = rho[P] * ud[P], mp = rho[P + st] * ud[P + st];
+        if (i >= 1 && i + 2 <= n - 1)
+          v = (-(rho[P - st] * ud[P - st]) + 9.0 * mc + 9.0 * mp - rho[P + 2 * st] * ud[P + 2 * st]) / 16.0;
+        else
+          v = 0.5 * (mc + mp);
+        v *= G.S[d];
+      }
+      phi.p[d][P] = v;
+    }
   }
 }
 
@@ -265,12 +288,10 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
 
 // Step 1 on a 3D mesh in one pass, with the x/y neighbourhoods of u, p' and
 // rho staged in LDS and the next plane's loads in flight while a plane is
-// computed: k_mass_flux's mass flux, rho* and e^n, then k_mom_predict's
-// momentum predictor from them.  Every value the predictor takes from the
-// mass flux is the own cell's (its upper faces, the lower faces of its own
-// interpolation lines -- bitwise the neighbours' upper faces -- and rho*), so
-// nothing beyond the staged u, p' and rho is needed.  Same formulas and order
-// as the two kernels.
+// computed: k_density_predictor's rho* and e^n from the state's face flux,
+// then k_mom_predict's momentum predictor.  The predictor takes the own
+// cell's six face fluxes and rho*.  Same formulas and order as the two
+// kernels.
 template <int TY>
 __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
                                                     const double* __restrict__ rho, Vec<3> u,
@@ -285,8 +306,8 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
   const Col c = col_of3<TY>(G, kc);
   const St st = stage3<2, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
-  const double* uz = u.p[Z];
-  auto mz = [&](int Q) { return rho[Q] * uz[Q]; };
+  const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
+  const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
   // staged values of the plane in flight
   double fs[5][NU];
   auto fetch = [&](int kk) {
@@ -301,14 +322,12 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
     }
   };
   Line z[3];       // u along z (momentum)
-  Line zm;         // rho u_z along z (mass flux)
   double flo[3];   // momentum flux through the face below
   double fmlo;     // mass flux through the face below
   double Flo = 0.0;
   {
     const int P = qo + pl * c.k0;
-    zm = line_at(mz, P, pl, c.k0, nz);
-    fmlo = c.k0 > 0 ? i4_lo(zm, c.k0, nz) * G.S[Z] : 0.0;
+    fmlo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       const double* uc = u.p[cc];
@@ -332,7 +351,9 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
     // staging loads (so waiting for them does not wait for those)
     const int P0 = qo + pl * k;
     const int Pu = nb(k + 1 < nz, P0 + pl, P0), Pn = nb(k + 3 < nz, P0 + 3 * pl, P0);
-    const double Tc = T[P0], p_up = pp[Pu], r_up = rho[Pu], r_n = rho[Pn];
+    const double Tc = T[P0], p_up = pp[Pu], r_up = rho[Pu];
+    const double fph[3] = {phi.p[0][P0], phi.p[1][P0], phi.p[Z][P0]};
+    const double fpl[2] = {phi.p[0][Pxl + pl * k], phi.p[1][Pyl + pl * k]};
     double zn[3];
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) zn[cc] = u.p[cc][Pn];
@@ -342,23 +363,17 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
     const double* Sp = su[sl][3];
     const double* Sr = su[sl][4];
     const double r = Sr[ho], pc = Sp[ho];
-    // mass flux through the faces of the cell, rho*, e^n
+    // the state's flux through the faces of the cell, rho*, e^n
     double sum = 0.0, fhi[2], flod[2];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
-      const double* Su = su[sl][d];
-      const int sd = d == 0 ? 1 : HX;
-      const Line sm{Sr[ho - 2 * sd] * Su[ho - 2 * sd], Sr[ho - sd] * Su[ho - sd], r * Su[ho],
-                    Sr[ho + sd] * Su[ho + sd], Sr[ho + 2 * sd] * Su[ho + 2 * sd]};
       const int n = G.n[d], q = coord(c, d);
-      const double hi = q + 1 < n ? i4_hi(sm, q, n) * G.S[d] : 0.0;
-      const double lo = q > 0 ? i4_lo(sm, q, n) * G.S[d] : 0.0;
-      fhi[d] = hi;
-      flod[d] = lo;
-      sum += hi;
-      sum -= lo;
+      fhi[d] = q + 1 < n ? fph[d] : 0.0;
+      flod[d] = q > 0 ? fpl[d] : 0.0;
+      sum += fhi[d];
+      sum -= flod[d];
     }
-    const double phz = up ? i4_hi(zm, k, nz) * G.S[Z] : 0.0;
+    const double phz = up ? fph[Z] : 0.0;
     sum += phz;
     sum -= fmlo;
     fmlo = phz;
@@ -407,9 +422,6 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
     }
     if (c.act) {
       const int P = qo + pl * k;
-#pragma unroll
-      for (int d = 0; d < Z; ++d) phi.p[d][P] = fhi[d];
-      phi.p[Z][P] = phz;
       rho_star[P] = rs;
       e0[P] = e0c;
 #pragma unroll
@@ -419,7 +431,6 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
     const bool more = k + 3 < nz;
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], more ? zn[cc] : 0.0);
-    zm = shift(zm, more ? r_n * zn[Z] : 0.0);
     Flo = Fhi;
   }
 }
@@ -1173,7 +1184,7 @@ __global__ __launch_bounds__(kBlock) void k_correct(
     const double* __restrict__ psi, Vec<NDIM> H, const double* __restrict__ D,
     const double* __restrict__ rho_star, Vec<NDIM> u_out, int last,
     const double* __restrict__ rho_old, double* __restrict__ rho_new, double* __restrict__ p_new,
-    double* partials) {
+    Vec<NDIM> phi_out, double* partials) {
   constexpr int Z = NDIM - 1;
   double red[3] = {0.0, 0.0, 0.0};
   const Col c = col_of<NDIM>(G, kc);
@@ -1251,11 +1262,14 @@ __global__ __launch_bounds__(kBlock) void k_correct(
         for (int d = 0; d < Z; ++d) {
           const int q = coord(c, d);
           const double kd = G.S[d] / G.h[d];
+          double fx = 0.0;
           if (q + 1 < G.n[d]) {
             const double w = 0.5 * (Dc + D_hi[d]) * kd;
-            sum += phit_val(Dc, D_hi[d], Hc[d], H_hi[d], r23, r_hi[d], G.S[d], phc, G.inv_h[d]) -
-                   w * (p_hi[d] - pc);
+            fx = phit_val(Dc, D_hi[d], Hc[d], H_hi[d], r23, r_hi[d], G.S[d], phc, G.inv_h[d]) -
+                 w * (p_hi[d] - pc);
+            sum += fx;
           }
+          phi_out.p[d][P] = fx;  // the next state's flux (0 on the wall)
           if (q > 0) {
             const double w = 0.5 * (D_lo[d] + Dc) * kd;
             sum -= phit_val(D_lo[d], Dc, H_lo[d], Hc[d], r_lo[d], r23, G.S[d], phc, G.inv_h[d]) -
@@ -1272,6 +1286,7 @@ __global__ __launch_bounds__(kBlock) void k_correct(
         }
         if (k > 0) sum -= flux_lo;
         flux_lo = flux_hi;
+        phi_out.p[Z][P] = flux_hi;
         const double rn = r_old - ph.dt / G.V * sum;
         const double pn = pc - r23 * phc;
         rho_new[P] = rn;
@@ -1298,7 +1313,7 @@ __global__ __launch_bounds__(64 * TY) void k_correct3(
     Geo G, Phys ph, int kc, const double* __restrict__ pp, const double* __restrict__ rho23,
     const double* __restrict__ psi, Vec<3> H, const double* __restrict__ D,
     const double* __restrict__ rho_star, Vec<3> u_out, const double* __restrict__ rho_old,
-    double* __restrict__ rho_new, double* __restrict__ p_new, double* partials) {
+    double* __restrict__ rho_new, double* __restrict__ p_new, Vec<3> phi_out, double* partials) {
   using St = Stage3<1, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   constexpr int NF = LAST ? 5 : 2;
@@ -1393,7 +1408,7 @@ __global__ __launch_bounds__(64 * TY) void k_correct3(
     if (LAST) {
       const double* SD = ss[sl][2 % NF];
       const double Dc = SD[ho];
-      double sum = 0.0;
+      double sum = 0.0, fxy[2] = {0.0, 0.0};
 #pragma unroll
       for (int d = 0; d < Z; ++d) {
         const int q = coord(c, d), sd = d == 0 ? 1 : HX;
@@ -1401,8 +1416,9 @@ __global__ __launch_bounds__(64 * TY) void k_correct3(
         const double kd = G.S[d] / G.h[d];
         if (q + 1 < G.n[d]) {
           const double w = 0.5 * (Dc + SD[ho + sd]) * kd;
-          sum += phit_val(Dc, SD[ho + sd], Hc[d], SH[ho + sd], r23, Sr[ho + sd], G.S[d], phc, G.inv_h[d]) -
-                 w * (Sp[ho + sd] - pc);
+          fxy[d] = phit_val(Dc, SD[ho + sd], Hc[d], SH[ho + sd], r23, Sr[ho + sd], G.S[d], phc, G.inv_h[d]) -
+                   w * (Sp[ho + sd] - pc);
+          sum += fxy[d];
         }
         if (q > 0) {
           const double w = 0.5 * (SD[ho - sd] + Dc) * kd;
@@ -1425,6 +1441,9 @@ __global__ __launch_bounds__(64 * TY) void k_correct3(
       if (c.act) {
         rho_new[P] = rn;
         p_new[P] = pn;
+        phi_out.p[0][P] = fxy[0];  // the next state's flux (0 on the walls)
+        phi_out.p[1][P] = fxy[1];
+        phi_out.p[Z][P] = flux_hi;
         red[0] += rn * G.V;
         red[1] = fmax(red[1], fabs(rn - psP * pn));
       }
@@ -1456,6 +1475,54 @@ __global__ __launch_bounds__(kBlock) void k_finalize_reduce(const double* partia
     sc->aux[1] = a[1];
     sc->aux[2] = a[2];
   }
+}
+
+// ---- diagnostics ----------------------------------------------------------------
+
+// Extrema of the velocity components and of the potential temperature
+// perturbation theta' = T/pi - theta0, pi = (p/p0)^{R/c_p} (Sec. 2,
+// eqs. theta, theta_split), as maxima of (-min, max) pairs: per workgroup
+// into part (8 values a workgroup, component-major), then one workgroup.
+__global__ __launch_bounds__(kBlock) void k_extrema(Geo G, Phys ph, const double* __restrict__ ux,
+                                                    const double* __restrict__ uy,
+                                                    const double* __restrict__ uz,
+                                                    const double* __restrict__ T,
+                                                    const double* __restrict__ p, double* part) {
+  __shared__ double sh[8][kBlock / 64];
+  double a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = -INFINITY;
+  const double kappa = ph.R / ph.cp;
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < G.nc; P += gridDim.x * blockDim.x) {
+    const double u = ux[P], v = uy ? uy[P] : 0.0, w = uz[P];
+    const double th = T[P] / pow(p[P] / ph.p0, kappa) - ph.theta0;
+    a[0] = fmax(a[0], -u);
+    a[1] = fmax(a[1], u);
+    a[2] = fmax(a[2], -v);
+    a[3] = fmax(a[3], v);
+    a[4] = fmax(a[4], -w);
+    a[5] = fmax(a[5], w);
+    a[6] = fmax(a[6], -th);
+    a[7] = fmax(a[7], th);
+  }
+  Reducer<0xFFu, 8>::block(a, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part[k * gridDim.x + blockIdx.x] = a[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_extrema_final(const double* part, int n, double* out) {
+  __shared__ double sh[8][kBlock / 64];
+  double a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = -INFINITY;
+  for (int b = threadIdx.x; b < n; b += kBlock)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = fmax(a[k], part[k * n + b]);
+  Reducer<0xFFu, 8>::block(a, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = (k & 1) ? a[k] : -a[k];
 }
 
 // ---- initial state (Sec. 4) --------------------------------------------------
@@ -1579,12 +1646,29 @@ constexpr int kKcStep1 = 64, kKcEnergy = 64, kKcH = 16, kKcRhs = 32, kKcCorr = 3
 #define V2(a) vec<2>(a)
 #define V3(a) vec<3>(a)
 
+void launch_face_mass_flux(hipStream_t s, const Geo& G, const double* rho, double* const* u,
+                           double* const* phi) {
+  const dim3 grid(grid_for(G.nc)), block(kBlock);
+  if (G.ndim == 2)
+    hipLaunchKernelGGL(k_face_mass_flux<2>, grid, block, 0, s, G, rho, V2(u), V2(phi));
+  else
+    hipLaunchKernelGGL(k_face_mass_flux<3>, grid, block, 0, s, G, rho, V3(u), V3(phi));
+}
+
+void launch_clear_wall_faces(hipStream_t s, const Geo& G, double* const* phi) {
+  const dim3 grid(grid_for(G.nc)), block(kBlock);
+  if (G.ndim == 2)
+    hipLaunchKernelGGL(k_clear_wall_faces<2>, grid, block, 0, s, G, V2(phi));
+  else
+    hipLaunchKernelGGL(k_clear_wall_faces<3>, grid, block, 0, s, G, V3(phi));
+}
+
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
                   double* rho_star, double* e0, double* const* u_star, double* pp_copy) {
   if (G.ndim == 2) {
     const ZPlan zp = zplan(G);
-    hipLaunchKernelGGL(k_mass_flux<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
+    hipLaunchKernelGGL(k_density_predictor<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
     hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star), pp_copy);
     return;
   }
@@ -1653,18 +1737,28 @@ int launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
                     const double* rho23, const double* psi, double* const* H, const double* D,
                     const double* rho_star, double* const* u_out, bool last,
-                    const double* rho_old, double* rho_new, double* p_new, double* partials,
-                    CgScalars* sc) {
+                    const double* rho_old, double* rho_new, double* p_new, double* const* phi_out,
+                    double* partials, CgScalars* sc) {
   const ZPlan zp = zplan(G),
               zp3 = G.ndim == 3 ? zplan3(G, kTyCorr, last ? kKcCorrLast : kKcCorr) : zp;
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_correct<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V2(H), D, rho_star, V2(u_out), (int)last, rho_old, rho_new, p_new, partials);
+    hipLaunchKernelGGL(k_correct<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, pp, rho23, psi, V2(H), D, rho_star, V2(u_out), (int)last, rho_old, rho_new, p_new, V2(phi_out), partials);
   else if (last)
-    hipLaunchKernelGGL((k_correct3<true, kTyCorr>), dim3(zp3.blocks), dim3(64 * kTyCorr), 0, s, G, ph, zp3.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, partials);
+    hipLaunchKernelGGL((k_correct3<true, kTyCorr>), dim3(zp3.blocks), dim3(64 * kTyCorr), 0, s, G, ph, zp3.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, V3(phi_out), partials);
   else
-    hipLaunchKernelGGL((k_correct3<false, kTyCorr>), dim3(zp3.blocks), dim3(64 * kTyCorr), 0, s, G, ph, zp3.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, partials);
+    hipLaunchKernelGGL((k_correct3<false, kTyCorr>), dim3(zp3.blocks), dim3(64 * kTyCorr), 0, s, G, ph, zp3.kc, pp, rho23, psi, V3(H), D, rho_star, V3(u_out), rho_old, rho_new, p_new, V3(phi_out), partials);
   if (last)
     hipLaunchKernelGGL(k_finalize_reduce, dim3(1), dim3(kBlock), 0, s, (const double*)partials, zp3.blocks, sc);
+}
+
+int launch_extrema(hipStream_t s, const Geo& G, const Phys& ph, double* const* u, const double* T,
+                   const double* p, double* part, double* out) {
+  const int gb = grid_for(G.nc);
+  hipLaunchKernelGGL(k_extrema, dim3(gb), dim3(kBlock), 0, s, G, ph, (const double*)u[0],
+                     (const double*)(G.ndim == 3 ? u[1] : nullptr), (const double*)u[G.ndim - 1], T,
+                     p, part);
+  hipLaunchKernelGGL(k_extrema_final, dim3(1), dim3(kBlock), 0, s, (const double*)part, gb, out);
+  return gb;
 }
 
 void launch_init_column(hipStream_t s, const Geo& G, const Phys& ph, double* rho_a,

@@ -21,8 +21,8 @@ HOST, DEVICE = 0, 1
 PCG_JACOBI_FP64, IR_FP32_FP64, LEARNED_MIXED = 0, 1, 2
 SOLVERS = {"pcg64": PCG_JACOBI_FP64, "mixed": IR_FP32_FP64, "learned": LEARNED_MIXED}
 
-FIELD_RHO, FIELD_U, FIELD_T, FIELD_PPRIME, FIELD_P, FIELD_C, FIELD_D, FIELD_B = (
-    1 << 0, 1 << 1, 1 << 2, 1 << 3, 1 << 4, 1 << 5, 1 << 6, 1 << 7)
+FIELD_RHO, FIELD_U, FIELD_T, FIELD_PPRIME, FIELD_P, FIELD_C, FIELD_D, FIELD_B, FIELD_PHI = (
+    1 << 0, 1 << 1, 1 << 2, 1 << 3, 1 << 4, 1 << 5, 1 << 6, 1 << 7, 1 << 8)
 
 
 class GeaError(RuntimeError):
@@ -67,6 +67,11 @@ class StepStats(C.Structure):
                 ("energy_iters", C.c_int64)]
 
 
+class Extrema(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("u_min", "u_max", "v_min", "v_max", "w_min", "w_max",
+                                           "theta_min", "theta_max")]
+
+
 _lib = None
 
 
@@ -83,6 +88,7 @@ def lib():
         L.gea_set_solver.argtypes = [vp, C.c_int32, C.c_double, C.c_int32, C.c_double]
         L.gea_init_bubble.argtypes = [vp, P(Bubble)]
         L.gea_set_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, C.c_int]
+        L.gea_set_face_flux.argtypes = [vp, dp, C.c_int]
         L.gea_step.argtypes = [vp, C.c_int32, P(StepStats)]
         L.gea_pressure_solve.argtypes = [vp, dp, dp, C.c_int, P(SolveStats)]
         L.gea_apply_pressure_operator.argtypes = [vp, dp, dp, C.c_int]
@@ -91,6 +97,7 @@ def lib():
         L.gea_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_int64)]
         L.gea_time_solver_kernels.argtypes = [vp, C.c_int32, P(C.c_double)]
         L.gea_time_network.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_double)]
+        L.gea_state_extrema.argtypes = [vp, P(Extrema)]
         L.gea_pressure_solve_static.argtypes = [P(Mesh), dp, dp, dp, dp, C.c_double, C.c_int32,
                                                 vp, P(SolveStats)]
         L.gea_destroy.argtypes = [vp]
@@ -101,7 +108,7 @@ def lib():
                      "gea_set_state", "gea_step", "gea_pressure_solve",
                      "gea_apply_pressure_operator", "gea_get_fields", "gea_kernel_timing",
                      "gea_kernel_times", "gea_time_solver_kernels", "gea_time_network",
-                     "gea_pressure_solve_static"):
+                     "gea_pressure_solve_static", "gea_state_extrema", "gea_set_face_flux"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -190,6 +197,11 @@ class Solver:
         self._check(self.L.gea_set_state(self.ctx, *[C.c_void_p(q) for q, _ in ptrs], kinds.pop()),
                     self.ctx)
 
+    def set_face_flux(self, phi):
+        """replace the state's face mass flux ((ndim, nc) values, GEA_FIELD_PHI layout)"""
+        q, kind = _ptr(phi)
+        self._check(self.L.gea_set_face_flux(self.ctx, C.c_void_p(q), kind), self.ctx)
+
     def step(self, nsteps=1) -> StepStats:
         st = StepStats()
         self._check(self.L.gea_step(self.ctx, int(nsteps), C.byref(st)), self.ctx)
@@ -216,11 +228,17 @@ class Solver:
         self._check(self.L.gea_apply_pressure_operator(self.ctx, C.c_void_p(xp), C.c_void_p(yp),
                                                        kind), self.ctx)
 
+    def extrema(self):
+        """extrema of u, v, w and theta' of the current state (a dict)"""
+        e = Extrema()
+        self._check(self.L.gea_state_extrema(self.ctx, C.byref(e)), self.ctx)
+        return {n: getattr(e, n) for n, _ in Extrema._fields_}
+
     def get_fields(self, mask, host=True):
         n = 0
-        for bit in range(8):
+        for bit in range(9):
             if mask & (1 << bit):
-                n += self.ndim if (1 << bit) == FIELD_U else 1
+                n += self.ndim if (1 << bit) in (FIELD_U, FIELD_PHI) else 1
         if host:
             out = np.empty((n, self.nc), dtype=np.float64)
         else:
@@ -263,10 +281,11 @@ class Solver:
         return list(ms), list(gf)
 
     def state(self):
-        """dict of host arrays: rho, u (ndim, nc), T, pp, p"""
-        f = self.get_fields(FIELD_RHO | FIELD_U | FIELD_T | FIELD_PPRIME | FIELD_P)
+        """dict of host arrays: rho, u (ndim, nc), T, pp, p, phi (ndim, nc)"""
+        f = self.get_fields(FIELD_RHO | FIELD_U | FIELD_T | FIELD_PPRIME | FIELD_P | FIELD_PHI)
         d = self.ndim
-        return dict(rho=f[0], u=f[1:1 + d], T=f[1 + d], pp=f[2 + d], p=f[3 + d])
+        return dict(rho=f[0], u=f[1:1 + d], T=f[1 + d], pp=f[2 + d], p=f[3 + d],
+                    phi=f[4 + d:4 + 2 * d])
 
 
 def pressure_solve_static(mesh: dict, c, D, b, x, tol, max_iter=20000, stream=None):

@@ -12,6 +12,7 @@ from paper_2303_10499_amd import configs
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("rho", "u", "T", "pp", "p")
+STATE = FIELDS + ("phi",)  # with the face mass flux the state carries
 
 
 @pytest.fixture(scope="module")
@@ -54,15 +55,28 @@ def u_floor(s, cfg, steps):
     return 16 * eps * np.max(np.abs(s.pp)) * par["dt"] * steps / (np.min(s.rho) * h)
 
 
+def flux_floor(s, cfg, steps):
+    """Absolute round-off floor of the face mass flux: the corrected flux's
+    pressure term w (p'_N - p'_P), w ~ dt S/h, moves by the same ulps of p'
+    as u does, times rho S (the flux is rho u S)."""
+    m = cfg["mesh"]
+    dx, dz = m["lx"] / m["nx"], m["lz"] / m["nz"]
+    dy = m["ly"] / m["ny"]
+    S_max = max(dy * dz, dx * dz, dx * dy)
+    return u_floor(s, cfg, steps) * np.max(s.rho) * S_max
+
+
 def compare(S, s, tol, cfg=None, steps=None):
-    """per-field relative error <= tol; for u, an absolute error below the
-    round-off floor u_floor() also passes (young flows, tiny |u|)"""
+    """per-field relative error <= tol; for u and the face flux, an absolute
+    error below the round-off floor (u_floor, flux_floor) also passes (young
+    flows, tiny |u|)"""
     g = S.state()
-    errs = {f: rel(g[f], getattr(s, f)) for f in FIELDS}
+    errs = {f: rel(g[f], getattr(s, f)) for f in STATE}
+    floors = {"u": u_floor, "phi": flux_floor}
     for f, e in errs.items():
-        if f == "u" and cfg is not None and e > tol:
-            absu = float(np.max(np.abs(g["u"] - s.u)))
-            assert absu <= u_floor(s, cfg, steps), f"u: {absu:.3e} m/s ({errs})"
+        if f in floors and cfg is not None and e > tol:
+            err = float(np.max(np.abs(g[f] - getattr(s, f))))
+            assert err <= floors[f](s, cfg, steps), f"{f}: {err:.3e} absolute ({errs})"
             continue
         assert e <= tol, f"{f}: {e:.3e} > {tol:.1e} ({errs})"
     return errs
@@ -83,6 +97,7 @@ def test_initial_state_matches_oracle(oracle_lib, gea_mod, name, dims):
     g = S.state()
     for f in FIELDS:
         assert rel(g[f], getattr(s, f)) <= 1e-13, f
+    assert np.max(np.abs(g["phi"])) == 0.0  # u = 0
 
 
 def test_pressure_system_and_solve_match_oracle(oracle_lib, gea_mod):
@@ -90,6 +105,9 @@ def test_pressure_system_and_solve_match_oracle(oracle_lib, gea_mod):
     O, s, S = pair(oracle_lib, gea_mod, cfg)
     O.step(s, 2)
     S.set_state(s.rho, np.ascontiguousarray(s.u), s.T, s.pp, s.p, s.Tbg)
+    assert rel(S.state()["phi"], O.face_mass_flux(s.rho, s.u)) <= 1e-13
+    S.set_face_flux(np.ascontiguousarray(s.phi))  # the flux the oracle's state carries
+    assert np.array_equal(S.state()["phi"], s.phi)
     c, D, b = O.pressure_system(s)
     x_ref, st_ref, rc = O.pcg(c, D, b, s.pp, tol=1e-13)
     assert rc == 0
@@ -158,8 +176,29 @@ def test_rest_state_and_determinism(oracle_lib, gea_mod):
         S.init_bubble(**cfg["bubble"])
         S.step(5)
         outs.append(S.state())
-    for f in FIELDS:
+    for f in STATE:
         assert np.array_equal(outs[0][f], outs[1][f]), f
+
+
+def test_state_round_trip_continues_bitwise(oracle_lib, gea_mod):
+    """a state copied out (cell fields and the face flux it carries) and into
+    a fresh context continues exactly as the original does; without the
+    flux (re-interpolated from the cell fields) it does not"""
+    cfg = cfg_mesh("bubble2d_64x32", 64, 32, tol=1e-13, max_iter=100000)
+    O, s, S = pair(oracle_lib, gea_mod, cfg)
+    S.step(3)
+    g = S.state()
+    T2 = gea_mod.Solver(cfg["mesh"], cfg["params"])
+    T2.set_state(g["rho"], np.ascontiguousarray(g["u"]), g["T"], g["pp"], g["p"], s.Tbg)
+    T3 = gea_mod.Solver(cfg["mesh"], cfg["params"])
+    T3.set_state(g["rho"], np.ascontiguousarray(g["u"]), g["T"], g["pp"], g["p"], s.Tbg)
+    T3.set_face_flux(np.ascontiguousarray(g["phi"]))
+    for X in (S, T2, T3):
+        X.step(2)
+    a, b, c = S.state(), T2.state(), T3.state()
+    for f in STATE:
+        assert np.array_equal(a[f], c[f]), f
+    assert not np.array_equal(a["rho"], b["rho"])
 
 
 def test_mass_and_symmetry_on_gpu(gea_mod):
@@ -185,7 +224,7 @@ def test_nonconvergence_rolls_back(oracle_lib, gea_mod):
     rc, st = S.step_status(1)
     assert rc == gea_mod.ERR_NOCONV
     after = S.state()
-    for f in FIELDS:
+    for f in STATE:
         assert np.array_equal(before[f], after[f]), f
     # the context still works after the failure
     S.set_solver("pcg64", 1e-13, 100000)
@@ -283,7 +322,7 @@ def test_full_size_2d_system_matches_oracle(oracle_lib, gea_mod):
     S.step(2)
     g = S.state()
     s2 = oracle_lib.State(*(np.ascontiguousarray(a) for a in
-                            (g["rho"], g["u"], g["T"], g["pp"], g["p"], s.Tbg)))
+                            (g["rho"], g["u"], g["T"], g["pp"], g["p"], s.Tbg, g["phi"])))
     c, D, b = O.pressure_system(s2)
     x = np.ascontiguousarray(g["pp"]).copy()
     st = S.pressure_solve(x)
@@ -305,3 +344,27 @@ def test_full_size_2d_system_matches_oracle(oracle_lib, gea_mod):
     assert rel(y, O.apply_A(c, D, v)) <= 1e-14
     r = b - O.apply_A(c, D, x)
     assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name,dims", [("bubble2d_64x32", (64, 32, None)),
+                                       ("bubble3d_256x256x128", (24, 16, 20))])
+def test_state_extrema_match_oracle(oracle_lib, gea_mod, name, dims):
+    """the device extrema of u, v, w and theta' (Sec. 4's diagnostics) against
+    the same extrema of the oracle's state after a few steps, theta' from
+    the oracle's potential-temperature routine (eqs. theta, theta_split)"""
+    nx, nz, ny = dims
+    cfg = cfg_mesh(name, nx, nz, ny, tol=1e-13, max_iter=100000)
+    O, s, S = pair(oracle_lib, gea_mod, cfg)
+    O.step(s, 3)
+    S.step(3)
+    e = S.extrema()
+    th = O.theta_prime(s)
+    nd = O.ndim
+    want = dict(u_min=s.u[0].min(), u_max=s.u[0].max(),
+                v_min=s.u[1].min() if nd == 3 else 0.0, v_max=s.u[1].max() if nd == 3 else 0.0,
+                w_min=s.u[nd - 1].min(), w_max=s.u[nd - 1].max(),
+                theta_min=th.min(), theta_max=th.max())
+    scale = {"u": np.abs(s.u).max(), "v": np.abs(s.u).max(), "w": np.abs(s.u).max(),
+             "theta": np.abs(th).max()}
+    for k, v in want.items():
+        assert abs(e[k] - v) <= 1e-9 * scale[k[:k.index("_")] if k[0] != "t" else "theta"], (k, e[k], v)

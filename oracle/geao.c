@@ -445,6 +445,73 @@ void geao_energy(const geao_mesh* m, const geao_params* q, const double* rho, co
   free(e_n); free(e); free(Tk); free(hhat); free(cT); free(DT); free(bT);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Step 2 in enthalpy form (eqs. over_ent, ent_LES, step3_sd, step3_2sd; R16) */
+
+/* The form the paper solves: with h = c_p T (eq. K_h) as the unknown,
+ *   rho* h/dt + (1/V) sum_out phi I4(h) - (1/V) sum_f (mu/Pr) snGrad(h') S
+ *     = b~_e - rho* K* / dt - (1/V) sum_out phi I4(K*) + p^n/dt - rho* g w*,
+ *   b~_e = (rho^n h^n + rho^n K^{n-1} - p^{n-1})/dt,
+ * where rho*, u* = (.., w*) and K* come from Step 1 and phi is the state's
+ * face flux.  As in the total-energy form, the convective term of h takes
+ * the previous sweep's h (sweep 1: h^n), the diffusion term the new one, and
+ * the diffusion acts on h' = c_p (T - T_bg) with adiabatic walls.  Sweep s
+ * solves (times V, for T) the SPD system
+ *   c_i T_i + sum_f k_f (T_i - T_nb) = b_i,   c = rho* c_p V/dt,
+ *   k_f = (mu/Pr) c_p S_f/h_f,
+ *   b = V [b~_e - rho* K* / dt + p^n/dt - rho* g w*] - sum_out phi I4(K*)
+ *       - sum_out phi I4(c_p T^(s-1)) + sum_f k_f (T_bg,i - T_bg,nb)
+ * by Jacobi-PCG from T^(s-1) to GEAO_ENERGY_TOL.  eq. step3_2sd then holds
+ * with h = c_p T at both levels. */
+void geao_energy_enthalpy(const geao_mesh* m, const geao_params* q, const double* rho,
+                          const double* T, const double* p, const double* p_old,
+                          const double* K_old, const double* u_star, const double* rho_star,
+                          const double* phi, const double* Tbg, double* T_new) {
+  geom G = make_geom(m);
+  double* Ks = zalloc(G.nc);
+  double* h = zalloc(G.nc);
+  double* Tk = zalloc(G.nc);
+  double* src = zalloc(G.nc);
+  double* cT = zalloc(G.nc);
+  double* DT = zalloc(G.nc);
+  double* bT = zalloc(G.nc);
+  const double kcoef = q->mu / q->Pr * q->cp;
+  const double* w_star = u_star + (long)G.zdir * G.nc;  /* vertical component of u* */
+  PER_CELL
+  for (long P = 0; P < G.nc; ++P) {
+    Ks[P] = kinetic(&G, u_star, P);
+    Tk[P] = T[P];
+    cT[P] = rho_star[P] * q->cp * G.V / q->dt;
+    DT[P] = kcoef;
+  }
+  /* the terms no sweep changes */
+  PER_CELL
+  for (long P = 0; P < G.nc; ++P) {
+    double b_e = (rho[P] * q->cp * T[P] + rho[P] * K_old[P] - p_old[P]) / q->dt;
+    double local = b_e - rho_star[P] * Ks[P] / q->dt + p[P] / q->dt - rho_star[P] * q->g * w_star[P];
+    double conv_K = convective1(&G, phi, Ks, P);
+    double bg = 0.0;
+    int kz = coord(&G, P, G.zdir);
+    for (int d = 0; d < G.ndim; ++d) {
+      double k = kcoef * G.S[d] / G.h[d];
+      long st = G.st[d];
+      if (has_hi(&G, P, d)) bg += k * (Tbg[kz] - Tbg[coord(&G, P + st, G.zdir)]);
+      if (has_lo(&G, P, d)) bg += k * (Tbg[kz] - Tbg[coord(&G, P - st, G.zdir)]);
+    }
+    src[P] = G.V * local - conv_K + bg;
+  }
+  for (int s = 0; s < q->n_energy_sweeps; ++s) {
+    PER_CELL
+    for (long P = 0; P < G.nc; ++P) h[P] = q->cp * Tk[P];
+    PER_CELL
+    for (long P = 0; P < G.nc; ++P) bT[P] = src[P] - convective1(&G, phi, h, P);
+    geao_solve_stats st;
+    geao_pcg(m, cT, DT, bT, Tk, GEAO_ENERGY_TOL, q->max_iter, &st);
+  }
+  memcpy(T_new, Tk, sizeof(double) * G.nc);
+  free(Ks); free(h); free(Tk); free(src); free(cT); free(DT); free(bT);
+}
+
 /* eq. step3_3sd: rho^{n+2/3} R T^{n+1} = p^n; and the pressure-equation
  * coefficients of reading R2: psi = 1/(R T), c = psi V/dt, D = rho23 dt / rho* */
 void geao_eos_coeffs(const geao_mesh* m, const geao_params* q, const double* p,
@@ -683,28 +750,35 @@ static int check_args(const geao_mesh* m, const geao_params* q) {
   if (!(m->lx > 0 && m->ly > 0 && m->lz > 0)) return 0;
   if (!(q->R > 0 && q->cp > 0 && q->cv > 0 && q->dt > 0 && q->Pr > 0)) return 0;
   if (q->n_corr < 1 || q->n_energy_sweeps < 1 || q->max_iter < 0) return 0;
+  if (q->energy_form != 0 && q->energy_form != 1) return 0;
   return 1;
 }
 
 /* Steps 1 and 2 of the step starting from the given state (phi: its flux) */
 static void steps_1_2(const geao_mesh* m, const geao_params* q, const double* rho,
                       const double* u, const double* T, const double* pp, const double* p,
-                      const double* phi, const double* Tbg, work_t* w) {
+                      const double* phi, const double* p_old, const double* K_old,
+                      const double* Tbg, work_t* w) {
   geom G = make_geom(m);
   memcpy(w->phi, phi, sizeof(double) * G.ndim * G.nc);
   geao_density_predictor(m, q, rho, w->phi, w->rho_star);
   geao_momentum_predictor(m, q, rho, u, pp, w->rho_star, w->phi, w->u_star);
-  geao_energy(m, q, rho, u, T, w->u_star, w->rho_star, w->phi, Tbg, w->T_new);
+  if (q->energy_form == 1)
+    geao_energy_enthalpy(m, q, rho, T, p, p_old, K_old, w->u_star, w->rho_star, w->phi, Tbg,
+                         w->T_new);
+  else
+    geao_energy(m, q, rho, u, T, w->u_star, w->rho_star, w->phi, Tbg, w->T_new);
   geao_eos_coeffs(m, q, p, w->T_new, w->rho_star, w->rho23, w->psi, w->c, w->D);
 }
 
 int geao_pressure_system(const geao_mesh* m, const geao_params* q, const double* rho,
                          const double* u, const double* T, const double* pp, const double* p,
-                         const double* phi, const double* Tbg, double* c, double* D, double* b) {
+                         const double* phi, const double* p_old, const double* K_old,
+                         const double* Tbg, double* c, double* D, double* b) {
   if (!check_args(m, q)) return GEAO_ERR_ARG;
   geom G = make_geom(m);
   work_t w = work_alloc(&G);
-  steps_1_2(m, q, rho, u, T, pp, p, phi, Tbg, &w);
+  steps_1_2(m, q, rho, u, T, pp, p, phi, p_old, K_old, Tbg, &w);
   geao_H(m, q, rho, u, w.u_star, w.phi, w.H);
   geao_predicted_flux_rhs(m, q, rho, w.rho23, w.psi, w.D, w.H, w.phi_tilde, w.b);
   memcpy(c, w.c, sizeof(double) * G.nc);
@@ -715,7 +789,8 @@ int geao_pressure_system(const geao_mesh* m, const geao_params* q, const double*
 }
 
 int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, double* T,
-              double* pp, double* p, double* phi, const double* Tbg, geao_step_stats* st) {
+              double* pp, double* p, double* phi, double* p_old, double* K_old,
+              const double* Tbg, geao_step_stats* st) {
   if (!check_args(m, q)) return GEAO_ERR_ARG;
   geom G = make_geom(m);
   work_t w = work_alloc(&G);
@@ -726,7 +801,7 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
   int status = GEAO_OK;
   st->n_solves = 0;
 
-  steps_1_2(m, q, rho, u, T, pp, p, phi, Tbg, &w);
+  steps_1_2(m, q, rho, u, T, pp, p, phi, p_old, K_old, Tbg, &w);
 
   memcpy(u_k, w.u_star, sizeof(double) * G.ndim * G.nc);
   memcpy(pp_k, pp, sizeof(double) * G.nc);
@@ -748,6 +823,9 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
       if (!isfinite(rho_new[P]) || !isfinite(p_new[P]) || !isfinite(w.T_new[P])) status = GEAO_ERR_NAN;
   }
   if (status == GEAO_OK) {
+    /* the lagged terms of the next step: p^n, K^n */
+    for (long P = 0; P < G.nc; ++P) K_old[P] = kinetic(&G, u, P);
+    memcpy(p_old, p, sizeof(double) * G.nc);
     memcpy(rho, rho_new, sizeof(double) * G.nc);
     memcpy(u, u_k, sizeof(double) * G.ndim * G.nc);
     memcpy(T, w.T_new, sizeof(double) * G.nc);

@@ -46,6 +46,8 @@ typedef struct {
   int32_t n_corr, n_energy_sweeps;
   double tol;
   int32_t max_iter;
+  int32_t energy_form;   /* Step 2: 0 total-energy form (geao_energy), 1 the
+                            enthalpy form of eq. step3_sd (geao_energy_enthalpy) */
 } geao_params;
 
 /* kind 0: no perturbation; 1: cosine theta' = amp/2 (1 + cos(pi r / rc)) for
@@ -110,6 +112,12 @@ void geao_momentum_predictor(const geao_mesh* m, const geao_params* q, const dou
 void geao_energy(const geao_mesh* m, const geao_params* q, const double* rho, const double* u,
                  const double* T, const double* u_star, const double* rho_star,
                  const double* phi, const double* Tbg, double* T_new);
+/* Step 2 in the enthalpy form of eq. step3_sd (see geao.c); p_old, K_old:
+ * p^{n-1} and K^{n-1} of the lagged terms of b~_e */
+void geao_energy_enthalpy(const geao_mesh* m, const geao_params* q, const double* rho,
+                          const double* T, const double* p, const double* p_old,
+                          const double* K_old, const double* u_star, const double* rho_star,
+                          const double* phi, const double* Tbg, double* T_new);
 void geao_eos_coeffs(const geao_mesh* m, const geao_params* q, const double* p,
                      const double* T_new, const double* rho_star,
                      double* rho23, double* psi, double* c, double* D);
@@ -130,15 +138,20 @@ void geao_finalize(const geao_mesh* m, const geao_params* q, const double* rho_o
                    double* rho_new, double* p_new, double* eos_mismatch);
 
 /* Steps 1-2 and the first corrector's Step 3a-b of the step that would start
- * from this state: returns the pressure system (c, D, b) it would solve. */
+ * from this state: returns the pressure system (c, D, b) it would solve.
+ * p_old, K_old: the state's p^{n-1}, K^{n-1} (read by the enthalpy form). */
 int geao_pressure_system(const geao_mesh* m, const geao_params* q, const double* rho,
                          const double* u, const double* T, const double* pp, const double* p,
-                         const double* phi, const double* Tbg, double* c, double* D, double* b);
+                         const double* phi, const double* p_old, const double* K_old,
+                         const double* Tbg, double* c, double* D, double* b);
 
 /* One full step n -> n+1, in place; phi (ndim face arrays, the face flux of
- * the state) in: phi^n, out: phi^{n+1} (the last corrector's flux). */
+ * the state) in: phi^n, out: phi^{n+1} (the last corrector's flux); p_old,
+ * K_old in: p^{n-1}, K^{n-1}, out: p^n, K^n (the enthalpy form's lagged
+ * terms; kept up to date in both forms). */
 int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, double* T,
-              double* pp, double* p, double* phi, const double* Tbg, geao_step_stats* st);
+              double* pp, double* p, double* phi, double* p_old, double* K_old,
+              const double* Tbg, geao_step_stats* st);
 
 /* potential temperature fluctuation theta' = T/(p/p0)^{R/cp} - theta0 (eqs. theta, theta_split) */
 void geao_theta_prime(const geao_mesh* m, const geao_params* q, const double* T, const double* p,

@@ -48,7 +48,7 @@ class Params(C.Structure):
                 ("g", C.c_double), ("p0", C.c_double), ("theta0", C.c_double),
                 ("mu", C.c_double), ("Pr", C.c_double), ("dt", C.c_double),
                 ("n_corr", C.c_int32), ("n_energy_sweeps", C.c_int32),
-                ("tol", C.c_double), ("max_iter", C.c_int32)]
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("energy_form", C.c_int32)]
 
 
 class Bubble(C.Structure):
@@ -90,6 +90,7 @@ def lib(omp: bool = False):
         L.geao_mass_predictor.argtypes = [P(Mesh), P(Params), d, d, d, d]
         L.geao_momentum_predictor.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d]
         L.geao_energy.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d]
+        L.geao_energy_enthalpy.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d, d]
         L.geao_eos_coeffs.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d]
         L.geao_H.argtypes = [P(Mesh), P(Params), d, d, d, d, d]
         L.geao_predicted_flux_rhs.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d]
@@ -97,8 +98,8 @@ def lib(omp: bool = False):
         L.geao_pcg.argtypes = [P(Mesh), d, d, d, d, C.c_double, C.c_int, P(SolveStats)]
         L.geao_correct.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d]
         L.geao_finalize.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d]
-        L.geao_pressure_system.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d, d]
-        L.geao_step.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, P(StepStats)]
+        L.geao_pressure_system.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d, d, d, d]
+        L.geao_step.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d, P(StepStats)]
         L.geao_face_mass_flux.argtypes = [P(Mesh), d, d, d]
         L.geao_density_predictor.argtypes = [P(Mesh), P(Params), d, d, d]
         L.geao_theta_prime.argtypes = [P(Mesh), P(Params), d, d, d]
@@ -122,10 +123,13 @@ class State:
     p: np.ndarray
     Tbg: np.ndarray    # (nz,)
     phi: np.ndarray = None  # (ndim, ncell) face mass flux; None: I4(rho u) S when first needed
+    p_old: np.ndarray = None  # p^{n-1}; None: p^n (a state without history)
+    K_old: np.ndarray = None  # K^{n-1}; None: K^n
 
     def copy(self) -> "State":
         return State(*(None if a is None else np.array(a, copy=True) for a in
-                       (self.rho, self.u, self.T, self.pp, self.p, self.Tbg, self.phi)))
+                       (self.rho, self.u, self.T, self.pp, self.p, self.Tbg, self.phi,
+                        self.p_old, self.K_old)))
 
 
 class Oracle:
@@ -137,7 +141,8 @@ class Oracle:
         self.params = Params(*(float(params[k]) for k in ("R", "cp", "cv", "g", "p0",
                                                           "theta0", "mu", "Pr", "dt")),
                              int(params.get("n_corr", 2)), int(params.get("n_energy_sweeps", 2)),
-                             float(params.get("tol", 1e-13)), int(params.get("max_iter", 100000)))
+                             float(params.get("tol", 1e-13)), int(params.get("max_iter", 100000)),
+                             int(params.get("energy_form", 0)))
         self.L = lib(omp)
         self.ndim = 2 if self.mesh.ny == 1 else 3
         self.nc = self.mesh.nx * self.mesh.ny * self.mesh.nz
@@ -175,13 +180,24 @@ class Oracle:
             s.phi = self.face_mass_flux(s.rho, s.u)
         return s.phi
 
+    def _history(self, s: State):
+        """p^{n-1}, K^{n-1} of the state; a state without history takes its own
+        p^n and K^n = |u^n|^2/2 (so the lagged terms vanish on its first step)"""
+        if s.p_old is None:
+            s.p_old = np.array(s.p, copy=True)
+        if s.K_old is None:
+            s.K_old = 0.5 * np.sum(s.u * s.u, axis=0)
+        return s.p_old, s.K_old
+
     def step(self, s: State, nsteps: int = 1) -> list:
         stats = []
         for _ in range(nsteps):
             st = StepStats()
             phi = self._flux(s)
+            p_old, K_old = self._history(s)
             rc = self.L.geao_step(C.byref(self.mesh), C.byref(self.params), _p(s.rho), _p(s.u),
-                                  _p(s.T), _p(s.pp), _p(s.p), _p(phi), _p(s.Tbg), C.byref(st))
+                                  _p(s.T), _p(s.pp), _p(s.p), _p(phi), _p(p_old), _p(K_old),
+                                  _p(s.Tbg), C.byref(st))
             stats.append(st)
             if rc != OK:
                 raise RuntimeError(f"geao_step failed with status {rc}")
@@ -189,9 +205,10 @@ class Oracle:
 
     def pressure_system(self, s: State):
         c, D, b = self.zeros(), self.zeros(), self.zeros()
+        p_old, K_old = self._history(s)
         rc = self.L.geao_pressure_system(C.byref(self.mesh), C.byref(self.params), _p(s.rho),
                                          _p(s.u), _p(s.T), _p(s.pp), _p(s.p), _p(self._flux(s)),
-                                         _p(s.Tbg), _p(c), _p(D), _p(b))
+                                         _p(p_old), _p(K_old), _p(s.Tbg), _p(c), _p(D), _p(b))
         if rc != OK:
             raise ValueError(f"geao_pressure_system failed: {rc}")
         return c, D, b
@@ -274,6 +291,14 @@ class Oracle:
         Tn = self.zeros()
         self.L.geao_energy(C.byref(self.mesh), C.byref(self.params), _p(rho), _p(u), _p(T), _p(u_star),
                            _p(rho_star), _p(phi), _p(Tbg), _p(Tn))
+        return Tn
+
+    def energy_enthalpy(self, rho, T, p, p_old, K_old, u_star, rho_star, phi, Tbg):
+        Tn = self.zeros()
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in
+             (rho, T, p, p_old, K_old, u_star, rho_star, phi, Tbg)]
+        self.L.geao_energy_enthalpy(C.byref(self.mesh), C.byref(self.params), *[_p(x) for x in a],
+                                    _p(Tn))
         return Tn
 
     def eos_coeffs(self, p, T_new, rho_star):

@@ -199,6 +199,149 @@ def test_energy_uses_old_density_and_kinetic_energy(oracle_lib, sweeps):
     np.testing.assert_allclose(Tn, want, rtol=1e-13)
 
 
+# ---- Step 2 in the enthalpy form the paper solves (eq. step3_sd)
+
+def _enthalpy(O, rho, T, p, p_old, K_old, us, rs, phi, Tbg):
+    return O.energy_enthalpy(rho, T, p, p_old, K_old, us, rs, phi, Tbg)
+
+
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_enthalpy_form_closed_form_with_lagged_terms(oracle_lib, sweeps):
+    """no face flux and no diffusion: eq. step3_sd is pointwise,
+    rho* h = rho^n h^n + rho^n K^{n-1} - p^{n-1} - rho* K* + p^n - dt rho* g w*
+    with h = c_p T.  rho* != rho^n, K^{n-1} != K*, p^{n-1} != p^n and w* != 0,
+    so a swapped density, kinetic energy or pressure level, or a wrong sign
+    or component of the gravity work, changes the result."""
+    O, par = make(oracle_lib, mu=0.0, n_energy_sweeps=sweeps, energy_form=1)
+    x, y, z, i, j, k = grid(O)
+    cp, dt, g = par["cp"], par["dt"], par["g"]
+    rho_n = 1.05 + 1e-4 * x - 2e-5 * z
+    rho_s = 0.93 + 3e-5 * z
+    T = 285.0 - 6e-3 * z + 1e-3 * x
+    p = 9.1e4 - 11.0 * z + 0.3 * x
+    p_old = p - 40.0 + 0.01 * z
+    K_old = 30.0 + 0.02 * x
+    u_s = np.zeros((2, O.nc))
+    u_s[0], u_s[1] = -4.0 + 2e-3 * z, 9.0 - 1e-3 * x
+    Tbg = np.full(O.mesh.nz, 290.0)
+    phi0 = np.zeros((2, O.nc))
+    Tn = _enthalpy(O, rho_n, T, p, p_old, K_old, u_s, rho_s, phi0, Tbg)
+    Ks = 0.5 * (u_s ** 2).sum(0)
+    h = (rho_n * cp * T + rho_n * K_old - p_old - rho_s * Ks + p - dt * rho_s * g * u_s[1]) / rho_s
+    np.testing.assert_allclose(Tn, h / cp, rtol=1e-13)
+
+
+@pytest.mark.parametrize("mode", [1, 11])
+def test_enthalpy_form_diffusion_is_implicit(oracle_lib, mode):
+    """the diffusion of h' at the new level: with no flow the eigenvector
+    T' = A cos(pi m (i + 1/2)/nx) scales by 1/(1 + lam),
+    lam = dt (mu/Pr)/rho (2/h^2)(1 - cos(pi m/nx)) (c_p cancels, since the
+    unknown's coefficient is rho* c_p/dt)"""
+    O, par = make(oracle_lib, mu=2e4, n_energy_sweeps=1, energy_form=1)
+    x, y, z, i, j, k = grid(O)
+    nx = O.mesh.nx
+    h = O.mesh.lx / nx
+    Tbg = 290.0 - 3e-3 * (np.arange(O.mesh.nz) + 0.5) * 100.0
+    Tp = 0.7 * np.cos(np.pi * mode * (i + 0.5) / nx)
+    T = Tbg[k] + Tp
+    ones = np.ones(O.nc)
+    zero2 = np.zeros((2, O.nc))
+    p = np.full(O.nc, 9e4)
+    Tn = _enthalpy(O, ones, T, p, p, np.zeros(O.nc), zero2, ones, zero2, Tbg)
+    lam = par["dt"] * par["mu"] / par["Pr"] * 2 / h ** 2 * (1 - np.cos(np.pi * mode / nx))
+    np.testing.assert_allclose(Tn - Tbg[k], Tp / (1 + lam), rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_enthalpy_form_transport_keeps_uniform_h(oracle_lib, sweeps):
+    """a uniform h stays uniform under any face flux whose divergence is the
+    density change of Step 1 (rho* = rho^n - dt/V sum_out phi): the
+    transport term enters with the sign that makes rho* h/dt + (1/V) sum phi h
+    = rho^n h/dt"""
+    O, par = make(oracle_lib, mu=0.4, n_energy_sweeps=sweeps, energy_form=1)
+    rng = np.random.default_rng(5)
+    m = O.mesh
+    x, y, z, i, j, k = grid(O)
+    rho = 1.1 + 0.05 * rng.standard_normal(O.nc)
+    phi = 40.0 * rng.standard_normal((2, O.nc))
+    phi[0][i == m.nx - 1] = 0.0
+    phi[1][k == m.nz - 1] = 0.0
+    rs = O.density_predictor(rho, phi)
+    T0 = 287.5
+    T = np.full(O.nc, T0)
+    p = 9e4 + 100.0 * rng.standard_normal(O.nc)
+    zero2 = np.zeros((2, O.nc))
+    Tn = _enthalpy(O, rho, T, p, p, np.zeros(O.nc), zero2, rs, phi, np.full(m.nz, T0))
+    np.testing.assert_allclose(Tn, T0, rtol=1e-13)
+
+
+@pytest.mark.parametrize("sweeps,margin", [(1, 1), (2, 3)])
+def test_enthalpy_form_flux_carries_kinetic_energy(oracle_lib, sweeps, margin):
+    """sum_out phi I4(K*) with K* linear in x under a uniform flux U S: the
+    interior temperature drops by dt U dK*/dx / c_p"""
+    O, par = make(oracle_lib, mu=0.0, n_energy_sweeps=sweeps, energy_form=1)
+    x, y, z, i, j, k = grid(O)
+    m = O.mesh
+    U, a, T0 = 15.0, 0.4, 300.0
+    u_s = np.zeros((2, O.nc))
+    u_s[0] = np.sqrt(2.0 * (5.0 + a * x))          # K* = 5 + a x
+    Ks = 0.5 * (u_s ** 2).sum(0)
+    S = m.ly * m.lz / m.nz
+    phi = np.zeros((2, O.nc))
+    phi[0] = np.where(i <= m.nx - 2, U * S, 0.0)
+    rho = np.ones(O.nc)
+    rs = O.density_predictor(rho, phi)
+    p = np.full(O.nc, 9e4)
+    Tn = _enthalpy(O, rho, np.full(O.nc, T0), p, p, Ks, u_s, rs, phi, np.full(m.nz, T0))
+    sel = (i >= margin) & (i <= m.nx - 1 - margin)
+    np.testing.assert_allclose((Tn - T0)[sel], -par["dt"] * U * a / par["cp"], rtol=1e-9)
+
+
+def test_enthalpy_form_conserves_the_budget(oracle_lib):
+    """summed over the closed box, transport and diffusion cancel: each sweep
+    gives sum rho* c_p T = sum [rho^n c_p T^n + rho^n K^{n-1} - p^{n-1}
+    - rho* K* + p^n - dt rho* g w*] for any fields"""
+    O, par = make(oracle_lib, mu=0.4, n_energy_sweeps=2, energy_form=1)
+    rng = np.random.default_rng(9)
+    m = O.mesh
+    x, y, z, i, j, k = grid(O)
+    cp, dt, g = par["cp"], par["dt"], par["g"]
+    rho = 1.1 + 0.05 * rng.standard_normal(O.nc)
+    rs = 1.1 + 0.05 * rng.standard_normal(O.nc)
+    phi = 40.0 * rng.standard_normal((2, O.nc))
+    phi[0][i == m.nx - 1] = 0.0
+    phi[1][k == m.nz - 1] = 0.0
+    T = 290.0 + rng.standard_normal(O.nc)
+    p = 9e4 + 100.0 * rng.standard_normal(O.nc)
+    p_old = p + 30.0 * rng.standard_normal(O.nc)
+    K_old = 20.0 + rng.standard_normal(O.nc)
+    u_s = 5.0 * rng.standard_normal((2, O.nc))
+    Tbg = 290.0 - 0.01 * np.arange(m.nz)
+    Tn = _enthalpy(O, rho, T, p, p_old, K_old, u_s, rs, phi, Tbg)
+    Ks = 0.5 * (u_s ** 2).sum(0)
+    want = np.sum(rho * cp * T + rho * K_old - p_old - rs * Ks + p - dt * rs * g * u_s[1])
+    assert abs(np.sum(rs * cp * Tn) - want) <= 1e-12 * np.sum(rs * cp * Tn)
+
+
+def test_step_hands_on_p_and_K_as_the_lagged_terms(oracle_lib):
+    """after a step the state carries p^n and K^n = |u^n|^2/2 for the next
+    step's b~_e; a state without history takes its own p and K"""
+    cfg = configs.get("bubble2d_64x32", tol=1e-13, energy_form=1)
+    cfg["mesh"].update(nx=16, nz=12, ly=1250.0)
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
+    s = O.init_bubble(**dict(cfg["bubble"], xc=9000.0))
+    O.step(s, 1)
+    p1, u1 = s.p.copy(), s.u.copy()
+    O.step(s, 1)
+    np.testing.assert_array_equal(s.p_old, p1)
+    np.testing.assert_array_equal(s.K_old, 0.5 * (u1 * u1).sum(0))
+    t = s.copy()
+    t.p_old = t.K_old = None
+    O._history(t)
+    np.testing.assert_array_equal(t.p_old, s.p)
+    np.testing.assert_array_equal(t.K_old, 0.5 * (s.u * s.u).sum(0))
+
+
 def test_eos_coefficients(oracle_lib):
     O, par = make(oracle_lib)
     rng = np.random.default_rng(2)
@@ -364,8 +507,9 @@ def test_initial_bubble_profiles(oracle_lib):
 
 # ---------------------------------------------------------------- whole step
 
-def test_rest_state_stays_at_rest(oracle_lib):
-    cfg = configs.get("bubble2d_64x32", tol=1e-14)
+@pytest.mark.parametrize("form", [0, 1])
+def test_rest_state_stays_at_rest(oracle_lib, form):
+    cfg = configs.get("bubble2d_64x32", tol=1e-14, energy_form=form)
     O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
     s = O.init_bubble(0)
     s0 = s.copy()
@@ -376,9 +520,10 @@ def test_rest_state_stays_at_rest(oracle_lib):
         assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), f
 
 
-def test_rest_state_3d(oracle_lib):
+@pytest.mark.parametrize("form", [0, 1])
+def test_rest_state_3d(oracle_lib, form):
     cfg = configs.scaled("bubble3d_256x256x128", 8, 6, ny=7)
-    cfg["params"]["tol"] = 1e-14
+    cfg["params"].update(tol=1e-14, energy_form=form)
     O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
     s = O.init_bubble(0)
     O.step(s, 10)
@@ -440,13 +585,14 @@ def test_unconverged_solve_leaves_state_untouched(oracle_lib):
         np.testing.assert_array_equal(getattr(s, f), getattr(s0, f))
 
 
-def test_step_is_the_composition_of_the_pinned_substeps(oracle_lib):
+@pytest.mark.parametrize("form", [0, 1])
+def test_step_is_the_composition_of_the_pinned_substeps(oracle_lib, form):
     """The step wires the sub-steps in the paper's order: Step 1, Step 2, then
     n_corr correctors, each convecting with the state's flux phi^n (eq. e1_d;
     eq. step2_sd of Step 3 and the H operator both carry phi^n_j), the
     corrected flux of the last corrector feeding the end-of-step density and
     becoming the next state's flux."""
-    cfg = configs.get("bubble2d_64x32", tol=1e-13)
+    cfg = configs.get("bubble2d_64x32", tol=1e-13, energy_form=form)
     cfg["mesh"].update(nx=16, nz=12, ly=1250.0)
     O = oracle_lib.Oracle(cfg["mesh"], cfg["params"])
     s = O.init_bubble(**dict(cfg["bubble"], xc=9000.0))
@@ -456,7 +602,10 @@ def test_step_is_the_composition_of_the_pinned_substeps(oracle_lib):
     phi = s.phi
     rs = O.density_predictor(s.rho, phi)
     us = O.momentum_predictor(s.rho, s.u, s.pp, rs, phi)
-    Tn = O.energy(s.rho, s.u, s.T, us, rs, phi, s.Tbg)
+    if form == 1:
+        Tn = O.energy_enthalpy(s.rho, s.T, s.p, s.p_old, s.K_old, us, rs, phi, s.Tbg)
+    else:
+        Tn = O.energy(s.rho, s.u, s.T, us, rs, phi, s.Tbg)
     r23, psi, c, D = O.eos_coeffs(s.p, Tn, rs)
     uk, ppk = us, s.pp.copy()
     for k in range(cfg["params"]["n_corr"]):

@@ -96,6 +96,9 @@ typedef struct {
                                       without it, the other way re-tried every 16th solve) take
                                       longer than one application (both timed on the device);
                                       1 = on every solve                                          */
+  int32_t energy_form;             /* Step 2: 0 = total-energy form (flux phi I4(e + R T)); 1 = the
+                                      enthalpy form of eq. step3_sd (h = c_p T, lagged p^{n-1} and
+                                      K^{n-1} in b~_e, gravity work rho* g w*)                      */
 } gea_params;
 
 /* initial perturbation of Sec. 4: kind 0 none; 1 cosine bubble
@@ -135,11 +138,14 @@ enum {
   GEA_FIELD_C = 1u << 5,       /* pressure system of the last assembly: c    */
   GEA_FIELD_D = 1u << 6,       /*                                          D  */
   GEA_FIELD_B = 1u << 7,       /*                                          b  */
-  GEA_FIELD_PHI = 1u << 8      /* face mass flux of the state: ndim blocks,
+  GEA_FIELD_PHI = 1u << 8,     /* face mass flux of the state: ndim blocks,
                                   block d, value P: the face between cell P
                                   and cell P + stride_d (0 where P is at the
                                   upper wall); strides 1, nx, nx*ny (3D) or
                                   1, nx (2D) */
+  GEA_FIELD_HISTORY = 1u << 9  /* 2 blocks: p^{n-1} and K^{n-1} of the
+                                  enthalpy form's lagged terms (a state
+                                  without history reports its own p and K) */
 };
 
 /* Bytes of device workspace needed for this mesh and parameter set. */
@@ -189,6 +195,15 @@ gea_status gea_set_state(gea_ctx* ctx, const double* rho, const double* u, const
  * gea_get_fields (all fields and GEA_FIELD_PHI) and copied back in with
  * gea_set_state and this call continues bitwise as the original would. */
 gea_status gea_set_face_flux(gea_ctx* ctx, const double* phi, gea_ptr_kind kind);
+
+/* Give the current state the lagged terms p^{n-1}, K^{n-1} (ncell values
+ * each, of the given kind) that the enthalpy form of Step 2 (energy_form 1;
+ * eq. step3_sd, b~_e) reads.  A step in that form hands p^n, K^n = |u^n|^2/2
+ * to the next state; a state without history (after gea_init_bubble,
+ * gea_set_state, or a step in the total-energy form) takes its own p and K,
+ * so that its first step has no lagged terms. */
+gea_status gea_set_history(gea_ctx* ctx, const double* p_prev, const double* K_prev,
+                           gea_ptr_kind kind);
 
 /* Advance nsteps time steps (Sec. 3, Steps 1-3).  stats may be NULL. */
 gea_status gea_step(gea_ctx* ctx, int32_t nsteps, gea_step_stats* stats);

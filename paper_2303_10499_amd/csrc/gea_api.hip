@@ -45,6 +45,8 @@ struct State {
   double* pp;
   double* p;
   double* phi[3];  // face mass flux: face d of cell P lies between P and P + st[d]
+  double* pm;      // p^{n-1} and K^{n-1} of the enthalpy form's lagged terms, valid
+  double* Km;      //   while the context's hist[] flag of this state is set
 };
 
 constexpr int kMaxPartials = 2048 * 8;
@@ -227,6 +229,7 @@ struct gea_ctx {
   int last_iters32 = 0;
   int last_iters_res = 0;  // iterations of the last Jacobi-PCG resumed after the network
   bool has_state = false;
+  bool hist[2] = {false, false};  // st[i].pm, st[i].Km hold the state's history
   bool has_system = false;
   bool sys32 = false;  // c32, D32, dinv32 hold the current operator
   int res_parts = 0;   // partials of a first residual check the system build formed
@@ -317,6 +320,8 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
     S.pp = cv.take<double>(nc);
     S.p = cv.take<double>(nc);
     for (int d = 0; d < 3; ++d) S.phi[d] = d < nd ? cv.take<double>(nc) : nullptr;
+    S.pm = cv.take<double>(nc);
+    S.Km = cv.take<double>(nc);
   }
   x->Tbg = cv.take<double>(m.nz);
   x->rho_a = cv.take<double>(m.nz);
@@ -432,6 +437,10 @@ gea_status check_params(const gea_mesh* m, const gea_params* q, std::string& err
   }
   if (q->solver == GEA_LEARNED_MIXED && q->learned_steps < 1) {
     err = "learned_steps must be >= 1";
+    return GEA_ERR_ARG;
+  }
+  if (q->energy_form != 0 && q->energy_form != 1) {
+    err = "energy_form must be 0 (total energy) or 1 (enthalpy)";
     return GEA_ERR_ARG;
   }
   return GEA_OK;
@@ -999,15 +1008,36 @@ gea_status solve_energy(gea_ctx* x, double* T, int nparts, int sweep, int* iters
 // copied to pp_out when given (the pressure solve's initial guess).  Each
 // energy sweep solves its implicit-diffusion system for T (pressure-solve
 // work vectors, which are free until Step 3).
+// the current state's p^{n-1}, K^{n-1}: its own p^n, K^n if it has none
+void ensure_history(gea_ctx* x) {
+  if (x->hist[x->cur]) return;
+  const State& S = x->st[x->cur];
+  launch_history_init(x->stream, x->G, S.p, S.u, S.pm, S.Km);
+  HIPCHK(hipGetLastError());
+  x->hist[x->cur] = true;
+}
+
 gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out = nullptr,
                      int64_t* energy_iters = nullptr) {
   const Geo& G = x->G;
   const Phys& ph = x->ph;
   hipStream_t s = x->stream;
+  const bool enth = x->prm.energy_form == 1;
   x->timer.run(5, x->stream, [&] {
     launch_step1(s, G, ph, S.rho, S.u, S.T, S.pp, S.phi, x->rho_star, x->e0, x->ustar, pp_out);
   });
   const double* e_prev = x->e0;
+  if (enth) {
+    // e0 becomes the sweep-independent balance, eb the first sweep's c_p T + K*;
+    // the next state's p^n, K^n go to the other state's history arrays
+    const State& N = x->st[1 - x->cur];
+    ensure_history(x);
+    x->timer.run(5, x->stream, [&] {
+      launch_enthalpy_prep(s, G, ph, S.rho, S.T, S.p, S.pm, S.Km, S.u, x->ustar, x->rho_star,
+                           x->e0, x->eb, N.pm, N.Km);
+    });
+    e_prev = x->eb;
+  }
   const double* T_prev = S.T;
   const int ns = x->prm.n_energy_sweeps;
   for (int sw = 0; sw < ns; ++sw) {
@@ -1016,7 +1046,7 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
     double* T_next = last ? T_out : ((sw & 1) ? x->Tb : x->Ta);
     int nparts = 0;
     x->timer.run(5, x->stream, [&] {
-      nparts = launch_energy_rhs(s, G, ph, S.rho, x->e0, e_prev, T_prev, S.phi, x->rho_star,
+      nparts = launch_energy_rhs(s, G, ph, enth, S.rho, x->e0, e_prev, T_prev, S.phi, x->rho_star,
                                  x->ustar, x->Tbg, x->b, x->c, x->dinv, T_next, x->r, x->p0,
                                  x->w64.u[1], x->w64.b);
     });
@@ -1026,7 +1056,7 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
     if (energy_iters) *energy_iters += its;
     if (rc != GEA_OK) return rc;
     x->timer.run(5, x->stream, [&] {
-      launch_energy_post(s, G, ph, T_next, x->ustar, e_next, last, S.p, x->rho_star, x->rho23,
+      launch_energy_post(s, G, ph, enth, T_next, x->ustar, e_next, last, S.p, x->rho_star, x->rho23,
                          x->psi, x->c, x->D);
     });
     e_prev = e_next;
@@ -1087,6 +1117,8 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
   stats->mass = hs.aux[0];
   stats->eos_mismatch = hs.aux[1];
   if (hs.aux[2] != 0.0) return GEA_ERR_NAN;
+  // the enthalpy form's Step 2 wrote the new state's p^{n-1}, K^{n-1}
+  x->hist[1 - x->cur] = x->prm.energy_form == 1;
   x->cur = 1 - x->cur;
   stats->steps_done += 1;
   return GEA_OK;
@@ -1226,6 +1258,7 @@ gea_status gea_init_bubble(gea_ctx* x, const gea_bubble* b) {
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(x->stream));
     x->has_state = true;
+    x->hist[x->cur] = false;
     x->has_system = false;
     return GEA_OK;
   });
@@ -1251,6 +1284,7 @@ gea_status gea_set_state(gea_ctx* x, const double* rho, const double* u, const d
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     x->has_state = true;
+    x->hist[x->cur] = false;
     x->has_system = false;
     return GEA_OK;
   });
@@ -1268,6 +1302,22 @@ gea_status gea_set_face_flux(gea_ctx* x, const double* phi, gea_ptr_kind kind) {
     launch_clear_wall_faces(x->stream, x->G, S.phi);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(x->stream));
+    return GEA_OK;
+  });
+}
+
+gea_status gea_set_history(gea_ctx* x, const double* p_prev, const double* K_prev,
+                           gea_ptr_kind kind) {
+  if (!x) return GEA_ERR_ARG;
+  if (!p_prev || !K_prev) return fail(x, GEA_ERR_ARG, "null field");
+  if (!x->has_state) return fail(x, GEA_ERR_STATE, "no state: call gea_init_bubble or gea_set_state");
+  return guarded(x, [&]() {
+    const State& S = x->st[x->cur];
+    const size_t n = sizeof(double) * x->G.nc;
+    HIPCHK(hipMemcpyAsync(S.pm, p_prev, n, kind_in(kind), x->stream));
+    HIPCHK(hipMemcpyAsync(S.Km, K_prev, n, kind_in(kind), x->stream));
+    HIPCHK(hipStreamSynchronize(x->stream));
+    x->hist[x->cur] = true;
     return GEA_OK;
   });
 }
@@ -1381,6 +1431,11 @@ gea_status gea_get_fields(gea_ctx* x, uint32_t mask, double* out, gea_ptr_kind k
     if (mask & GEA_FIELD_B) put(x->b);
     if (mask & GEA_FIELD_PHI)
       for (int d = 0; d < x->G.ndim; ++d) put(S.phi[d]);
+    if (mask & GEA_FIELD_HISTORY) {
+      ensure_history(x);
+      put(S.pm);
+      put(S.Km);
+    }
     HIPCHK(hipStreamSynchronize(x->stream));
     return GEA_OK;
   });

@@ -103,16 +103,25 @@ void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho
 // solve's set-up (r = b - A x, p0 = 0, partials <r, r/diag>, ||r||^2 in
 // u_part and ||b||^2 in b_part, one per workgroup); returns the workgroup
 // count (k_cg_start's nu).  The system's D is (mu/Pr) c_p everywhere.
-int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* rho,
                       const double* e0, const double* e_prev, const double* T_prev,
                       double* const* phi, const double* rho_star, double* const* u_star,
                       const double* Tbg, double* b, double* c, double* dinv, double* x, double* r,
                       double* p0, double* u_part, double* b_part);
 // after a sweep's solve: e = c_v T + K* + Phi, or after the last sweep the
 // EOS density and pressure-equation coefficients rho23, psi, c, D
-void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
+void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* T,
                         double* const* u_star, double* e, bool last, const double* p,
                         const double* rho_star, double* rho23, double* psi, double* c, double* D);
+// Step 2 in enthalpy form (enth = true above): p^{n-1} = p, K^{n-1} = |u|^2/2
+// for a state without history; and the sweep-independent balance q, the
+// first sweep's transported c_p T + K*, and the next state's p^n, K^n
+void launch_history_init(hipStream_t s, const Geo& G, const double* p, double* const* u,
+                         double* pm, double* Km);
+void launch_enthalpy_prep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                          const double* T, const double* p, const double* pm, const double* Km,
+                          double* const* u, double* const* u_star, const double* rho_star,
+                          double* q, double* h0, double* pm_next, double* Km_next);
 // relative residual to which each energy sweep's system is solved
 constexpr double kEnergyTol = 1e-13;
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,

@@ -458,7 +458,12 @@ struct EnergySys {
   double* b_part;
 };
 
-template <int NDIM>
+// ENTH: the enthalpy form (eq. step3_sd): e0 holds the sweep-independent
+// balance q = rho^n c_p T^n + rho^n K^{n-1} - p^{n-1} - rho* K* + p^n
+// - dt rho* g w*, e_prev the transported c_p T^(s-1) + K*, and the unknown's
+// coefficient is rho* c_p V/dt.  Otherwise (total energy) e0 = e^n, e_prev =
+// e^(s-1) and the transported quantity is e + R T.
+template <int NDIM, bool ENTH>
 __global__ __launch_bounds__(kBlock) void k_energy_rhs(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
     const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<NDIM> phi,
@@ -473,6 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_rhs(
     Line ze = line_at([&](int Q) { return e_prev[Q]; }, P, pl, c.k0, nz);
     Line zT = line_at([&](int Q) { return T_prev[Q]; }, P, pl, c.k0, nz);
     auto hhat = [&](const Line& e, const Line& T) {
+      if (ENTH) return e;
       return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
                   e.p2 + ph.R * T.p2};
     };
@@ -523,8 +529,8 @@ __global__ __launch_bounds__(kBlock) void k_energy_rhs(
 #pragma unroll
       for (int d = 0; d < NDIM; ++d) kin += us[d] * us[d];
       const double rest = 0.5 * kin + phi_cell(G, ph, k);
-      const double bP = G.V / ph.dt * (r * e0c - rs * rest) - conv + bg;
-      const double cP = rs * ph.cv * G.V / ph.dt;
+      const double bP = ENTH ? G.V / ph.dt * e0c - conv + bg : G.V / ph.dt * (r * e0c - rs * rest) - conv + bg;
+      const double cP = rs * (ENTH ? ph.cp : ph.cv) * G.V / ph.dt;
       // operator on the initial guess and the diagonal
       const double xc = zT.c;
       double ax = cP * xc, diag = cP;
@@ -573,11 +579,53 @@ __global__ __launch_bounds__(kBlock) void k_energy_rhs(
   }
 }
 
+// The lagged terms of a state without history: p^{n-1} = p^n, K^{n-1} = K^n.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_history_init(Geo G, const double* __restrict__ p,
+                                                         Vec<NDIM> u, double* __restrict__ pm,
+                                                         double* __restrict__ Km) {
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < G.nc; P += gridDim.x * blockDim.x) {
+    double kin = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) kin += u.p[d][P] * u.p[d][P];
+    Km[P] = 0.5 * kin;
+    pm[P] = p[P];
+  }
+}
+
+// Step 2 in enthalpy form (eq. step3_sd), the sweep-independent part: the
+// balance q = rho^n c_p T^n + rho^n K^{n-1} - p^{n-1} - rho* K* + p^n
+// - dt rho* g w* (times V/dt it is the right-hand side without the fluxes),
+// the first sweep's transported quantity c_p T^n + K*, and the next state's
+// lagged terms p^n, K^n.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_enthalpy_prep(
+    Geo G, Phys ph, const double* __restrict__ rho, const double* __restrict__ T,
+    const double* __restrict__ p, const double* __restrict__ pm, const double* __restrict__ Km,
+    Vec<NDIM> u, Vec<NDIM> u_star, const double* __restrict__ rho_star, double* __restrict__ q,
+    double* __restrict__ h0, double* __restrict__ pm_next, double* __restrict__ Km_next) {
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < G.nc; P += gridDim.x * blockDim.x) {
+    const double r = rho[P], Tc = T[P], pc = p[P], rs = rho_star[P];
+    double ks = 0.0, kn = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+      ks += u_star.p[d][P] * u_star.p[d][P];
+      kn += u.p[d][P] * u.p[d][P];
+    }
+    ks *= 0.5;
+    const double hn = ph.cp * Tc;
+    q[P] = r * hn + r * Km[P] - pm[P] - rs * ks + pc - ph.dt * rs * ph.g * u_star.p[NDIM - 1][P];
+    h0[P] = hn + ks;
+    pm_next[P] = pc;
+    Km_next[P] = 0.5 * kn;
+  }
+}
+
 // After sweep s's solve: e = c_v T + K* + Phi for the next sweep, or (after
 // the last sweep) the EOS density of eq. step3_3sd and the pressure-equation
 // coefficients: rho^{n+2/3} = p^n/(R T^{n+1}), psi = 1/(R T), c = psi V/dt,
 // D = rho^{n+2/3} dt/rho*.
-template <int NDIM, bool LAST>
+template <int NDIM, bool LAST, bool ENTH>
 __global__ __launch_bounds__(kBlock) void k_energy_post(
     Geo G, Phys ph, const double* __restrict__ T, Vec<NDIM> u_star, double* __restrict__ e,
     const double* __restrict__ p, const double* __restrict__ rho_star, double* __restrict__ rho23,
@@ -594,7 +642,9 @@ __global__ __launch_bounds__(kBlock) void k_energy_post(
       double kin = 0.0;
 #pragma unroll
       for (int d = 0; d < NDIM; ++d) kin += u_star.p[d][P] * u_star.p[d][P];
-      e[P] = ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, P / G.st[NDIM - 1]);
+      // the next sweep's transported quantity: c_p T + K* (enthalpy form) or
+      // e = c_v T + K* + Phi
+      e[P] = ENTH ? ph.cp * Tc + 0.5 * kin : ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, P / G.st[NDIM - 1]);
     }
   }
 }
@@ -605,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_post(
 // workgroups a CU it spills 19 registers and ran at 301 us on the 3D
 // benchmark mesh; one workgroup a CU without the cap, 219 us; 64x4 tiles,
 // 410 us.)
-template <int TY>
+template <int TY, bool ENTH>
 __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
     const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<3> phi,
@@ -643,6 +693,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     fTn = T_prev[Pn];
   };
   auto hhat = [&](const Line& e, const Line& T) {
+    if (ENTH) return e;
     return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
                 e.p2 + ph.R * T.p2};
   };
@@ -700,8 +751,8 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
 #pragma unroll
     for (int d = 0; d < 3; ++d) kin += us[d] * us[d];
     const double rest = 0.5 * kin + phi_cell(G, ph, k);
-    const double bP = G.V / ph.dt * (r * e0c - rs * rest) - conv + bg;
-    const double cP = rs * ph.cv * G.V / ph.dt;
+    const double bP = ENTH ? G.V / ph.dt * e0c - conv + bg : G.V / ph.dt * (r * e0c - rs * rest) - conv + bg;
+    const double cP = rs * (ENTH ? ph.cp : ph.cv) * G.V / ph.dt;
     const double xc = zT.c;
     double ax = cP * xc, diag = cP;
 #pragma unroll
@@ -1676,7 +1727,7 @@ void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho
   hipLaunchKernelGGL(k_step1_3<kTyStep1>, dim3(zp3.blocks), dim3(64 * kTyStep1), 0, s, G, ph, zp3.kc, rho, V3(u), T, pp, V3(phi), rho_star, e0, V3(u_star), pp_copy);
 }
 
-int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* rho,
                       const double* e0, const double* e_prev, const double* T_prev,
                       double* const* phi, const double* rho_star, double* const* u_star,
                       const double* Tbg, double* b, double* c, double* dinv, double* x, double* r,
@@ -1684,28 +1735,60 @@ int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double*
   const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy, kKcEnergy) : zp;
   const EnergySys sy{b, c, dinv, x, r, p0, u_part, b_part};
   if (G.ndim == 2) {
-    hipLaunchKernelGGL(k_energy_rhs<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, sy);
+    if (enth)
+      hipLaunchKernelGGL((k_energy_rhs<2, true>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, sy);
+    else
+      hipLaunchKernelGGL((k_energy_rhs<2, false>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, sy);
     return zp.blocks;
   }
-  hipLaunchKernelGGL(k_energy_rhs3<kTyEnergy>, dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, sy);
+  if (enth)
+    hipLaunchKernelGGL((k_energy_rhs3<kTyEnergy, true>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, sy);
+  else
+    hipLaunchKernelGGL((k_energy_rhs3<kTyEnergy, false>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, sy);
   return zp3.blocks;
 }
 
-void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
+template <int NDIM>
+static void energy_post_nd(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* T,
+                           double* const* u_star, double* e, bool last, const double* p,
+                           const double* rho_star, double* rho23, double* psi, double* c, double* D) {
+  const dim3 grid(grid_for(G.nc)), block(kBlock);
+  const Vec<NDIM> us = vec<NDIM>(u_star);
+  if (last)
+    hipLaunchKernelGGL((k_energy_post<NDIM, true, false>), grid, block, 0, s, G, ph, T, us, e, p, rho_star, rho23, psi, c, D);
+  else if (enth)
+    hipLaunchKernelGGL((k_energy_post<NDIM, false, true>), grid, block, 0, s, G, ph, T, us, e, p, rho_star, rho23, psi, c, D);
+  else
+    hipLaunchKernelGGL((k_energy_post<NDIM, false, false>), grid, block, 0, s, G, ph, T, us, e, p, rho_star, rho23, psi, c, D);
+}
+
+void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* T,
                         double* const* u_star, double* e, bool last, const double* p,
                         const double* rho_star, double* rho23, double* psi, double* c, double* D) {
+  if (G.ndim == 2)
+    energy_post_nd<2>(s, G, ph, enth, T, u_star, e, last, p, rho_star, rho23, psi, c, D);
+  else
+    energy_post_nd<3>(s, G, ph, enth, T, u_star, e, last, p, rho_star, rho23, psi, c, D);
+}
+
+void launch_history_init(hipStream_t s, const Geo& G, const double* p, double* const* u,
+                         double* pm, double* Km) {
   const dim3 grid(grid_for(G.nc)), block(kBlock);
-  if (G.ndim == 2) {
-    if (last)
-      hipLaunchKernelGGL((k_energy_post<2, true>), grid, block, 0, s, G, ph, T, V2(u_star), e, p, rho_star, rho23, psi, c, D);
-    else
-      hipLaunchKernelGGL((k_energy_post<2, false>), grid, block, 0, s, G, ph, T, V2(u_star), e, p, rho_star, rho23, psi, c, D);
-  } else {
-    if (last)
-      hipLaunchKernelGGL((k_energy_post<3, true>), grid, block, 0, s, G, ph, T, V3(u_star), e, p, rho_star, rho23, psi, c, D);
-    else
-      hipLaunchKernelGGL((k_energy_post<3, false>), grid, block, 0, s, G, ph, T, V3(u_star), e, p, rho_star, rho23, psi, c, D);
-  }
+  if (G.ndim == 2)
+    hipLaunchKernelGGL(k_history_init<2>, grid, block, 0, s, G, p, V2(u), pm, Km);
+  else
+    hipLaunchKernelGGL(k_history_init<3>, grid, block, 0, s, G, p, V3(u), pm, Km);
+}
+
+void launch_enthalpy_prep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
+                          const double* T, const double* p, const double* pm, const double* Km,
+                          double* const* u, double* const* u_star, const double* rho_star,
+                          double* q, double* h0, double* pm_next, double* Km_next) {
+  const dim3 grid(grid_for(G.nc)), block(kBlock);
+  if (G.ndim == 2)
+    hipLaunchKernelGGL(k_enthalpy_prep<2>, grid, block, 0, s, G, ph, rho, T, p, pm, Km, V2(u), V2(u_star), rho_star, q, h0, pm_next, Km_next);
+  else
+    hipLaunchKernelGGL(k_enthalpy_prep<3>, grid, block, 0, s, G, ph, rho, T, p, pm, Km, V3(u), V3(u_star), rho_star, q, h0, pm_next, Km_next);
 }
 
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,

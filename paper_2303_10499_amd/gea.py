@@ -23,6 +23,7 @@ SOLVERS = {"pcg64": PCG_JACOBI_FP64, "mixed": IR_FP32_FP64, "learned": LEARNED_M
 
 FIELD_RHO, FIELD_U, FIELD_T, FIELD_PPRIME, FIELD_P, FIELD_C, FIELD_D, FIELD_B, FIELD_PHI = (
     1 << 0, 1 << 1, 1 << 2, 1 << 3, 1 << 4, 1 << 5, 1 << 6, 1 << 7, 1 << 8)
+FIELD_HISTORY = 1 << 9
 
 
 class GeaError(RuntimeError):
@@ -43,7 +44,7 @@ class Params(C.Structure):
                 ("n_energy_sweeps", C.c_int32), ("solver", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double),
                 ("learned_steps", C.c_int32), ("inner_target", C.c_double),
-                ("learned_always", C.c_int32)]
+                ("learned_always", C.c_int32), ("energy_form", C.c_int32)]
 
 
 class Bubble(C.Structure):
@@ -89,6 +90,7 @@ def lib():
         L.gea_init_bubble.argtypes = [vp, P(Bubble)]
         L.gea_set_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, C.c_int]
         L.gea_set_face_flux.argtypes = [vp, dp, C.c_int]
+        L.gea_set_history.argtypes = [vp, dp, dp, C.c_int]
         L.gea_step.argtypes = [vp, C.c_int32, P(StepStats)]
         L.gea_pressure_solve.argtypes = [vp, dp, dp, C.c_int, P(SolveStats)]
         L.gea_apply_pressure_operator.argtypes = [vp, dp, dp, C.c_int]
@@ -108,7 +110,8 @@ def lib():
                      "gea_set_state", "gea_step", "gea_pressure_solve",
                      "gea_apply_pressure_operator", "gea_get_fields", "gea_kernel_timing",
                      "gea_kernel_times", "gea_time_solver_kernels", "gea_time_network",
-                     "gea_pressure_solve_static", "gea_state_extrema", "gea_set_face_flux"):
+                     "gea_pressure_solve_static", "gea_state_extrema", "gea_set_face_flux",
+                     "gea_set_history"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -126,7 +129,7 @@ def make_params(p: dict, solver="pcg64") -> Params:
                   float(p.get("tol", 1e-10)), int(p.get("max_iter", 20000)),
                   int(p.get("check_every", 8)), float(p.get("inner_tol", 1e-4)),
                   int(p.get("learned_steps", 1)), float(p.get("inner_target", 0.0)),
-                  int(p.get("learned_always", 0)))
+                  int(p.get("learned_always", 0)), int(p.get("energy_form", 0)))
 
 
 def _ptr(a):
@@ -197,6 +200,17 @@ class Solver:
         self._check(self.L.gea_set_state(self.ctx, *[C.c_void_p(q) for q, _ in ptrs], kinds.pop()),
                     self.ctx)
 
+    def set_history(self, p_old, K_old):
+        """the enthalpy form's lagged terms p^{n-1}, K^{n-1} of the current state"""
+        (q1, k1), (q2, k2) = _ptr(p_old), _ptr(K_old)
+        assert k1 == k2, "both arrays must live on the same side"
+        self._check(self.L.gea_set_history(self.ctx, C.c_void_p(q1), C.c_void_p(q2), k1), self.ctx)
+
+    def history(self):
+        """(p^{n-1}, K^{n-1}) of the current state (host arrays)"""
+        f = self.get_fields(FIELD_HISTORY)
+        return f[0], f[1]
+
     def set_face_flux(self, phi):
         """replace the state's face mass flux ((ndim, nc) values, GEA_FIELD_PHI layout)"""
         q, kind = _ptr(phi)
@@ -236,9 +250,10 @@ class Solver:
 
     def get_fields(self, mask, host=True):
         n = 0
-        for bit in range(9):
+        for bit in range(10):
             if mask & (1 << bit):
-                n += self.ndim if (1 << bit) in (FIELD_U, FIELD_PHI) else 1
+                n += self.ndim if (1 << bit) in (FIELD_U, FIELD_PHI) else \
+                    2 if (1 << bit) == FIELD_HISTORY else 1
         if host:
             out = np.empty((n, self.nc), dtype=np.float64)
         else:

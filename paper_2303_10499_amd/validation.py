@@ -4,10 +4,12 @@ reports beside its own numbers.
 Smooth rising thermal bubble (Sec. 4.1): u and w extrema at 600 s, against
 Table 1.  Non-smooth bubble (Sec. 4.2): theta' extrema at 420 s and 600 s on
 5 m and 10 m cells, against Table 3.  The paper's discretisation (OpenFOAM,
-implicit transport, enthalpy form) differs from this one, so its numbers are
-a plausibility band, not a parity target.
+implicit transport) differs from this one, so its numbers are a plausibility
+band, not a parity target.  --energy-form 1 takes Step 2 in the paper's
+enthalpy form (eq. step3_sd) instead of the total-energy form.
 
     python -m paper_2303_10499_amd.validation [--cases smooth5,nonsmooth5,nonsmooth10]
+                                              [--energy-form 0|1]
 """
 from __future__ import annotations
 
@@ -30,13 +32,13 @@ CASES = {"smooth5": "paper_smooth_5m", "nonsmooth5": "paper_nonsmooth_5m",
          "nonsmooth10": "paper_nonsmooth_10m"}
 
 
-def run(case: str, solver: str = "pcg64", tol: float = 1e-10, log=None) -> dict:
+def run(case: str, solver: str = "pcg64", tol: float = 1e-10, log=None, energy_form: int = 0) -> dict:
     """run one case to 600 s; the extrema at the paper's output times"""
     from . import configs, gea
     if log is None:
         def log(msg):
             print(msg, file=sys.stderr, flush=True)
-    cfg = configs.get(CASES[case], tol=tol)
+    cfg = configs.get(CASES[case], tol=tol, energy_form=energy_form)
     S = gea.Solver(cfg["mesh"], cfg["params"], solver=solver)
     if solver == "learned":
         S.load_weights()
@@ -70,10 +72,13 @@ def main(argv=None):
     ap.add_argument("--cases", default="smooth5,nonsmooth5,nonsmooth10")
     ap.add_argument("--solver", default="pcg64")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--energy-form", type=int, default=0,
+                    help="Step 2: 0 total energy, 1 the enthalpy form of eq. step3_sd")
     args = ap.parse_args(argv)
     res = {}
     for c in args.cases.split(","):
-        res[c] = dict(ours=run(c, args.solver, args.tol), paper=PAPER[c])
+        res[c] = dict(ours=run(c, args.solver, args.tol, energy_form=args.energy_form),
+                      paper=PAPER[c])
     print(json.dumps(res), flush=True)
     return res
 

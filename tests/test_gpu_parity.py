@@ -151,6 +151,63 @@ def test_steps_match_oracle(oracle_lib, gea_mod, name, dims, steps):
     assert abs(gst.eos_mismatch - ost[-1].eos_mismatch) <= 1e-12 + 1e-3 * ost[-1].eos_mismatch
 
 
+@pytest.mark.parametrize("name,dims,steps", [
+    ("bubble2d_64x32", (64, 32, None), 20),
+    ("bubble2d_64x32", (37, 23, None), 10),          # ragged
+    ("bubble3d_256x256x128", (13, 9, 11), 5),          # ragged 3D
+    ("bubble3d_256x256x128", (20, 150, 12), 2),        # several z chunks
+])
+def test_enthalpy_form_steps_match_oracle(oracle_lib, gea_mod, name, dims, steps):
+    """Step 2 in the enthalpy form (eq. step3_sd, energy_form 1): every field,
+    the face flux and the lagged p^{n-1}, K^{n-1} the state hands on"""
+    nx, nz, ny = dims
+    cfg = cfg_mesh(name, nx, nz, ny, tol=1e-13, max_iter=100000, energy_form=1)
+    O, s, S = pair(oracle_lib, gea_mod, cfg)
+    O.step(s, steps)
+    S.step(steps)
+    strict = name == "bubble2d_64x32" and dims[:2] == (64, 32)
+    compare(S, s, 1e-10, None if strict else cfg, steps)
+    p_old, K_old = S.history()
+    assert rel(p_old, s.p_old) <= 1e-10
+    # K = |u|^2/2 of the previous state: relative error about twice u's, or
+    # under u's round-off floor
+    K_err = float(np.max(np.abs(K_old - s.K_old)))
+    assert rel(K_old, s.K_old) <= 2e-10 or K_err <= 2 * np.max(np.abs(s.u)) * u_floor(s, cfg, steps)
+
+
+def test_enthalpy_form_history_round_trip(oracle_lib, gea_mod):
+    """a state copied out with its flux and its lagged terms, and into a fresh
+    context, continues bitwise; without the lagged terms its next step is
+    the oracle's step of a state without history"""
+    cfg = cfg_mesh("bubble2d_64x32", 64, 32, tol=1e-13, max_iter=100000, energy_form=1)
+    O, s, S = pair(oracle_lib, gea_mod, cfg)
+    S.step(3)
+    g = S.state()
+    p_old, K_old = S.history()
+    T2 = gea_mod.Solver(cfg["mesh"], cfg["params"])
+    T2.set_state(g["rho"], np.ascontiguousarray(g["u"]), g["T"], g["pp"], g["p"], s.Tbg)
+    T2.set_face_flux(np.ascontiguousarray(g["phi"]))
+    T2.set_history(p_old, K_old)
+    T3 = gea_mod.Solver(cfg["mesh"], cfg["params"])
+    T3.set_state(g["rho"], np.ascontiguousarray(g["u"]), g["T"], g["pp"], g["p"], s.Tbg)
+    T3.set_face_flux(np.ascontiguousarray(g["phi"]))
+    hp, hK = T3.history()                      # no history: its own p and K
+    assert np.array_equal(hp, g["p"])
+    assert rel(hK, 0.5 * (g["u"] * g["u"]).sum(0)) <= 4e-16  # (the device may fuse u*u + k)
+    for X in (S, T2, T3):
+        X.step(1)
+    a, b, c = S.state(), T2.state(), T3.state()
+    for f in STATE:
+        assert np.array_equal(a[f], b[f]), f
+    assert not np.array_equal(a["T"], c["T"])
+    # the oracle from the same state without history
+    t = oracle_lib.State(*(np.ascontiguousarray(v) for v in
+                           (g["rho"], g["u"], g["T"], g["pp"], g["p"], s.Tbg, g["phi"])))
+    O.step(t, 1)
+    for f in STATE:
+        assert rel(c[f], getattr(t, f)) <= 1e-10, f
+
+
 def test_many_workgroups_grid_stride(oracle_lib, gea_mod):
     """more cells than one pass of the fixed grid (2048 x 256 threads)"""
     cfg = cfg_mesh("bubble2d_1280x640", 1024, 640, tol=1e-13, max_iter=100000)

@@ -7,7 +7,8 @@ energy forms, so its numbers are a band, not a parity target: the smooth
 bubble's velocity extrema within 2% (measured: 0.1-0.8%); the non-smooth
 bubble's theta' maximum within 20% and its minimum a small undershoot
 (|theta'_min| < 0.2 K), as a central fourth-order interpolation of a 0.5 K
-jump gives.  Each case is 6000 steps on 200x200 or 100x100 cells (5-11 s)."""
+jump gives.  Each case is 6000 steps on 200x200 or 100x100 cells (5-11 s),
+with Step 2 in either energy form."""
 import json
 import os
 
@@ -28,9 +29,11 @@ def paper():
         return json.load(f)
 
 
-def test_smooth_bubble_velocity_extrema_table1(paper):
+@pytest.mark.parametrize("form", [0, 1])
+def test_smooth_bubble_velocity_extrema_table1(paper, form):
+    """form 0: Step 2 in total-energy form; 1: the paper's enthalpy form"""
     from paper_2303_10499_amd import validation
-    ours = validation.run("smooth5", log=print)["600"]
+    ours = validation.run("smooth5", log=print, energy_form=form)["600"]
     ref = paper["smooth5"]["600"]
     assert ours["max_rel_res"] <= 1.0001e-10
     assert abs(ours["u_min"] + ours["u_max"]) <= 1e-9  # mirror symmetry about x = 500 m
@@ -40,10 +43,11 @@ def test_smooth_bubble_velocity_extrema_table1(paper):
     assert abs(-ours["w_min"] - ref["w_min"]) <= 0.02 * ref["w_min"], (ours["w_min"], ref["w_min"])
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("case", ["nonsmooth5", "nonsmooth10"])
-def test_nonsmooth_bubble_theta_extrema_table3(paper, case):
+def test_nonsmooth_bubble_theta_extrema_table3(paper, case, form):
     from paper_2303_10499_amd import validation
-    res = validation.run(case, log=print)
+    res = validation.run(case, log=print, energy_form=form)
     for t in ("420", "600"):
         ours, ref = res[t], paper[case][t]
         assert ours["max_rel_res"] <= 1.0001e-10

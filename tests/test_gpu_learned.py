@@ -517,3 +517,28 @@ def test_learned_gate_keeps_the_network_off_where_it_does_not_pay(learned):
     print("network kernel launches over 40 steps, gated / always:", apps)
     assert apps[1] > 0
     assert apps[0] <= 0.25 * apps[1]
+
+
+def test_forms_per_field_error_over_20_steps(learned):
+    """Per-field error of every solver form over 20 steps of the non-smooth
+    bubble (Sec. 4.2 setup on 256^2 cells), each at relative residual 1e-8,
+    against FP64 Jacobi-PCG solved to 1e-12: the refined and learned forms
+    are within 10x of the error the FP64 form itself makes at 1e-8 (plus a
+    1e-12 floor)"""
+    from paper_2303_10499_amd import configs, field_error
+    wl = "nonsmooth2d_2048"
+    saved = configs.CONFIGS[wl]
+    cfg = configs.scaled(wl, 256, 256)
+    configs.CONFIGS["_field_error_256"] = cfg
+    try:
+        res = field_error.run("_field_error_256", 20, checkpoints=2, log=print)
+    finally:
+        del configs.CONFIGS["_field_error_256"]
+    assert configs.CONFIGS[wl] is saved
+    for m, errs in res["checkpoints"].items():
+        base = errs["pcg64"]
+        for form in ("mixed", "learned", "learned_always"):
+            for f, e in errs[form].items():
+                assert e <= 10 * base[f] + 1e-12, (m, form, f, e, base[f])
+    for form, s in res["solves"].items():
+        assert s["max_rel_res"] <= (1e-12 if form == "reference" else 1e-8), (form, s)

@@ -217,8 +217,17 @@ def test_many_workgroups_grid_stride(oracle_lib, gea_mod):
     compare(S, s, 1e-10, cfg, 1)
 
 
-def test_rest_state_and_determinism(oracle_lib, gea_mod):
-    cfg = cfg_mesh("bubble2d_64x32", 64, 32, tol=1e-14)
+@pytest.mark.parametrize("name,dims,form", [("bubble2d_64x32", (64, 32, None), 0),
+                                            ("bubble2d_64x32", (64, 32, None), 1),
+                                            ("bubble3d_256x256x128", (24, 16, 20), 0),
+                                            ("bubble3d_256x256x128", (70, 20, 10), 1)])
+def test_rest_state_and_determinism(oracle_lib, gea_mod, name, dims, form):
+    """the discretely hydrostatic atmosphere at rest stays at rest (Sec. 2, eq.
+    p_split), and two runs of a bubble from the same state are bitwise equal
+    (the 3D kernels stage tiles in LDS and reduce per workgroup: no atomic sums,
+    no order that depends on scheduling)"""
+    nx, nz, ny = dims
+    cfg = cfg_mesh(name, nx, nz, ny, tol=1e-14, energy_form=form)
     S = gea_mod.Solver(cfg["mesh"], cfg["params"])
     S.init_bubble(0)
     s0 = S.state()

@@ -51,6 +51,37 @@ def test_mass_predictor_closed_form(oracle_lib):
     assert abs(rs.sum() - rho.sum()) < 1e-13 * O.nc
 
 
+@pytest.mark.parametrize("mesh", [MESH, dict(nx=6, ny=5, nz=4, lx=600.0, ly=500.0, lz=400.0)])
+def test_density_predictor_with_a_given_flux(oracle_lib, mesh):
+    """eq. e1_d with the state's face flux: rho* = rho - dt/V (sum of the flux
+    out through the upper faces - the flux in through the lower faces), by
+    brute force over the cells of a tiny mesh; and the flux of a state given
+    by cell fields is the mass predictor's I4(rho u) S"""
+    O, par = make(oracle_lib, mesh=mesh)
+    rng = np.random.default_rng(3)
+    m, nd = O.mesh, O.ndim
+    n = [m.nx, m.ny, m.nz] if nd == 3 else [m.nx, m.nz]
+    st = [1, m.nx, m.nx * m.ny] if nd == 3 else [1, m.nx]
+    V = m.lx / m.nx * m.ly / m.ny * m.lz / m.nz
+    rho = 1.0 + 0.1 * rng.standard_normal(O.nc)
+    phi = rng.standard_normal((nd, O.nc))
+    for d in range(nd):
+        phi[d][(np.arange(O.nc) // st[d]) % n[d] == n[d] - 1] = 0.0   # upper walls
+    want = np.empty(O.nc)
+    for P in range(O.nc):
+        out = 0.0
+        for d in range(nd):
+            q = (P // st[d]) % n[d]
+            out += phi[d][P] if q + 1 < n[d] else 0.0
+            out -= phi[d][P - st[d]] if q > 0 else 0.0
+        want[P] = rho[P] - par["dt"] / V * out
+    np.testing.assert_allclose(O.density_predictor(rho, phi), want, rtol=1e-15, atol=1e-15)
+    u = rng.standard_normal((nd, O.nc))
+    phi_i, rs = O.mass_predictor(rho, u)
+    np.testing.assert_array_equal(O.face_mass_flux(rho, u), phi_i)
+    np.testing.assert_array_equal(O.density_predictor(rho, phi_i), rs)
+
+
 def test_momentum_predictor_pressure_gradient(oracle_lib):
     O, par = make(oracle_lib)
     x, y, z, i, j, k = grid(O)

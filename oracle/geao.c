@@ -670,6 +670,313 @@ int geao_pcg(const geao_mesh* m, const double* c, const double* D, const double*
   return status;
 }
 
+/* ------------------------------------------------------------------------ */
+/* implicit transport (eqs. step2_sd of Step 1 and step3_sd with the         */
+/* convective and diffusive terms at the new level, as written; R19)        */
+
+typedef void (*op_fn)(const geom* G, const void* ctx, const double* x, double* y);
+
+/* weight of cell P in the I4 value of its upper (hi = 1) or lower face along d */
+static double i4_self_weight(const geom* G, long P, int d, int hi) {
+  int q = hi ? coord(G, P, d) : coord(G, P, d) - 1;  /* the face's lower cell */
+  return (q >= 1 && q + 2 <= G->n[d] - 1) ? 9.0 / 16.0 : 0.5;
+}
+
+/* diagonal entry of x -> sum_out phi I4(x) */
+static double convective_diag(const geom* G, const double* phi, long P) {
+  double a = 0.0;
+  for (int d = 0; d < G->ndim; ++d) {
+    const double* f = phi + d * G->nc;
+    if (has_hi(G, P, d)) a += f[P] * i4_self_weight(G, P, d, 1);
+    if (has_lo(G, P, d)) a -= f[P - G->st[d]] * i4_self_weight(G, P, d, 0);
+  }
+  return a;
+}
+
+/* momentum component comp (times V):
+ *   (A u)_P = rho*_P V/dt u_P + sum_out phi I4(u) - sum_f mu snGrad(u)_f S_f */
+typedef struct {
+  const geao_params* q;
+  const double* rho_star;
+  const double* phi;
+  int comp;
+} mom_ctx;
+
+static void mom_op(const geom* G, const void* vc, const double* x, double* y) {
+  const mom_ctx* c = (const mom_ctx*)vc;
+  PER_CELL
+  for (long P = 0; P < G->nc; ++P)
+    y[P] = c->rho_star[P] * G->V / c->q->dt * x[P] + convective1(G, c->phi, x, P) -
+           viscous1(G, x, c->comp, c->q->mu, P);
+}
+
+static double mom_diag(const geom* G, const mom_ctx* c, long P) {
+  double a = c->rho_star[P] * G->V / c->q->dt + convective_diag(G, c->phi, P);
+  for (int d = 0; d < G->ndim; ++d) {
+    double k = c->q->mu * G->S[d] / G->h[d];
+    a += has_hi(G, P, d) ? k : (c->comp == d ? 2.0 * k : 0.0);
+    a += has_lo(G, P, d) ? k : (c->comp == d ? 2.0 * k : 0.0);
+  }
+  return a;
+}
+
+/* energy, unknown T (times V):
+ *   (A T)_P = cT_P T_P + c_p sum_out phi I4(T) + sum_f k_f (T_P - T_nb),
+ * k_f = (mu/Pr) c_p S_f/h_f on interior faces (adiabatic walls) */
+typedef struct {
+  const geao_params* q;
+  const double* cT;
+  const double* DT;
+  const double* phi;
+} energy_ctx;
+
+static void energy_op(const geom* G, const void* vc, const double* x, double* y) {
+  const energy_ctx* c = (const energy_ctx*)vc;
+  apply_A(G, c->cT, c->DT, x, y);
+  PER_CELL
+  for (long P = 0; P < G->nc; ++P) y[P] += c->q->cp * convective1(G, c->phi, x, P);
+}
+
+/* BiCGStab (van der Vorst 1992) with the Jacobi preconditioner on the right:
+ * each search direction is scaled by dinv = 1/diag(A) before the operator
+ * is applied.  Stops when the recursive residual (of s after the first half
+ * step, or of r) satisfies ||.|| <= tol ||b||; a zero denominator ends the
+ * solve as not converged. */
+static int bicgstab(const geom* G, op_fn A, const void* ctx, const double* b, double* x,
+                    const double* dinv, double tol, int max_iter, geao_solve_stats* st) {
+  long n = G->nc;
+  double* r = zalloc(n);
+  double* rh = zalloc(n);
+  double* p = zalloc(n);
+  double* v = zalloc(n);
+  double* y = zalloc(n);
+  double* sv = zalloc(n);
+  double* z = zalloc(n);
+  double* t = zalloc(n);
+  A(G, ctx, x, t);
+  PER_CELL
+  for (long P = 0; P < n; ++P) {
+    r[P] = b[P] - t[P];
+    rh[P] = r[P];
+  }
+  double bb = dot(n, b, b), rr = dot(n, r, r);
+  double tol2 = tol * tol;
+  st->rel_res0 = bb > 0 ? sqrt(rr / bb) : 0.0;
+  int status = GEAO_ERR_NOCONV, it = 0;
+  if (bb == 0.0) {
+    memset(x, 0, sizeof(double) * n);
+    rr = 0.0;
+    status = GEAO_OK;
+  } else if (rr <= tol2 * bb) {
+    status = GEAO_OK;
+  }
+  double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+  while (status == GEAO_ERR_NOCONV && it < max_iter) {
+    double rho = dot(n, rh, r);
+    if (rho == 0.0) break;
+    double beta = (rho / rho_old) * (alpha / omega);
+    PER_CELL
+    for (long P = 0; P < n; ++P) {
+      p[P] = r[P] + beta * (p[P] - omega * v[P]);
+      y[P] = dinv[P] * p[P];
+    }
+    A(G, ctx, y, v);
+    double rv = dot(n, rh, v);
+    if (rv == 0.0) break;
+    alpha = rho / rv;
+    PER_CELL
+    for (long P = 0; P < n; ++P) {
+      x[P] += alpha * y[P];
+      sv[P] = r[P] - alpha * v[P];
+    }
+    ++it;
+    double ss = dot(n, sv, sv);
+    if (!isfinite(ss)) { status = GEAO_ERR_NAN; break; }
+    if (ss <= tol2 * bb) {
+      memcpy(r, sv, sizeof(double) * n);
+      rr = ss;
+      status = GEAO_OK;
+      break;
+    }
+    PER_CELL
+    for (long P = 0; P < n; ++P) z[P] = dinv[P] * sv[P];
+    A(G, ctx, z, t);
+    double tt = dot(n, t, t);
+    if (tt == 0.0) break;
+    omega = dot(n, t, sv) / tt;
+    PER_CELL
+    for (long P = 0; P < n; ++P) {
+      x[P] += omega * z[P];
+      r[P] = sv[P] - omega * t[P];
+    }
+    rr = dot(n, r, r);
+    rho_old = rho;
+    if (!isfinite(rr)) { status = GEAO_ERR_NAN; break; }
+    if (rr <= tol2 * bb) status = GEAO_OK;
+    if (omega == 0.0) break;
+  }
+  st->iters = it;
+  st->converged = status == GEAO_OK;
+  st->rel_res = bb > 0 ? sqrt(rr / bb) : 0.0;
+  A(G, ctx, x, t);
+  PER_CELL
+  for (long P = 0; P < n; ++P) r[P] = b[P] - t[P];
+  st->true_rel_res = bb > 0 ? sqrt(dot(n, r, r) / bb) : 0.0;
+  free(r); free(rh); free(p); free(v); free(y); free(sv); free(z); free(t);
+  return status;
+}
+
+/* y = A x of the implicit predictor's operator for component comp */
+void geao_momentum_operator(const geao_mesh* m, const geao_params* q, const double* rho_star,
+                            const double* phi, int comp, const double* x, double* y) {
+  geom G = make_geom(m);
+  mom_ctx c = {q, rho_star, phi, comp};
+  mom_op(&G, &c, x, y);
+}
+
+/* y = A x of the implicit energy operator (cT: the unknown's coefficient) */
+void geao_energy_operator(const geao_mesh* m, const geao_params* q, const double* cT,
+                          const double* phi, const double* x, double* y) {
+  geom G = make_geom(m);
+  double* DT = zalloc(G.nc);
+  for (long P = 0; P < G.nc; ++P) DT[P] = q->mu / q->Pr * q->cp;
+  energy_ctx c = {q, cT, DT, phi};
+  energy_op(&G, &c, x, y);
+  free(DT);
+}
+
+/* the diagonal of the momentum operator (comp >= 0) or, with comp = -1, of
+ * the energy operator with coefficient cT (rho_star unused) */
+void geao_transport_diag(const geao_mesh* m, const geao_params* q, const double* rho_star,
+                         const double* cT, const double* phi, int comp, double* diag) {
+  geom G = make_geom(m);
+  const double kcoef = q->mu / q->Pr * q->cp;
+  mom_ctx mc = {q, rho_star, phi, comp};
+  PER_CELL
+  for (long P = 0; P < G.nc; ++P) {
+    if (comp >= 0) {
+      diag[P] = mom_diag(&G, &mc, P);
+    } else {
+      double a = cT[P] + q->cp * convective_diag(&G, phi, P);
+      for (int d = 0; d < G.ndim; ++d) {
+        double k = kcoef * G.S[d] / G.h[d];
+        if (has_hi(&G, P, d)) a += k;
+        if (has_lo(&G, P, d)) a += k;
+      }
+      diag[P] = a;
+    }
+  }
+}
+
+/* BiCGStab on the momentum operator of component comp (test access) */
+int geao_bicgstab_momentum(const geao_mesh* m, const geao_params* q, const double* rho_star,
+                           const double* phi, int comp, const double* b, double* x, double tol,
+                           int max_iter, geao_solve_stats* st) {
+  geom G = make_geom(m);
+  mom_ctx c = {q, rho_star, phi, comp};
+  double* dinv = zalloc(G.nc);
+  for (long P = 0; P < G.nc; ++P) dinv[P] = 1.0 / mom_diag(&G, &c, P);
+  int rc = bicgstab(&G, mom_op, &c, b, x, dinv, tol, max_iter, st);
+  free(dinv);
+  return rc;
+}
+
+/* eq. step2_sd of Step 1 implicit in u^{n+1/3}: for each component c
+ *   (rho* V/dt) u + sum_out phi I4(u) - sum_f mu snGrad(u) S = V (rho^n u^n/dt - R(F^n)),
+ * F^n from p'^n and rho^n as in the explicit predictor; solved by BiCGStab
+ * to GEAO_TRANSPORT_TOL from the value u_star holds on entry (the explicit
+ * predictor's).  Returns the first failing solve's status. */
+int geao_momentum_predictor_implicit(const geao_mesh* m, const geao_params* q, const double* rho,
+                                     const double* u, const double* pp, const double* rho_star,
+                                     const double* phi, double* u_star) {
+  geom G = make_geom(m);
+  double* F = zalloc(G.ndim * G.nc);
+  double* b = zalloc(G.nc);
+  double* dinv = zalloc(G.nc);
+  force_faces(&G, q, pp, rho, F);
+  int status = GEAO_OK;
+  for (int c = 0; c < G.ndim && status == GEAO_OK; ++c) {
+    const double* uc = u + c * G.nc;
+    mom_ctx ctx = {q, rho_star, phi, c};
+    PER_CELL
+    for (long P = 0; P < G.nc; ++P) {
+      b[P] = G.V * (rho[P] * uc[P] / q->dt - reconstruct1(&G, F + c * G.nc, P, c));
+      dinv[P] = 1.0 / mom_diag(&G, &ctx, P);
+    }
+    geao_solve_stats st;
+    status = bicgstab(&G, mom_op, &ctx, b, u_star + c * G.nc, dinv, GEAO_TRANSPORT_TOL,
+                      q->max_iter, &st);
+  }
+  free(F); free(b); free(dinv);
+  return status;
+}
+
+/* Step 2 with the transport of the energy implicit (either energy form):
+ * the unknown T, transported as c_p T, at the new level in both the
+ * convective and the diffusive term; the known part of the transported
+ * quantity (K* + Phi in the total-energy form, K* in the enthalpy form)
+ * explicit.  One BiCGStab solve from T^n to GEAO_TRANSPORT_TOL of
+ *   cT T + c_p sum_out phi I4(T) + sum_f k_f (T_P - T_nb) = b,
+ * total energy: cT = rho* c_v V/dt,
+ *   b = V/dt (rho^n e^n - rho* (K* + Phi)) - sum_out phi I4(K* + Phi) + bg;
+ * enthalpy:     cT = rho* c_p V/dt,
+ *   b = V [b~_e - rho* K* / dt + p^n/dt - rho* g w*] - sum_out phi I4(K*) + bg;
+ * bg the background column's diffusion as in the sweeps. */
+int geao_energy_implicit(const geao_mesh* m, const geao_params* q, const double* rho,
+                         const double* u, const double* T, const double* p, const double* p_old,
+                         const double* K_old, const double* u_star, const double* rho_star,
+                         const double* phi, const double* Tbg, double* T_new) {
+  geom G = make_geom(m);
+  const int enth = q->energy_form == 1;
+  double* w = zalloc(G.nc);
+  double* cT = zalloc(G.nc);
+  double* DT = zalloc(G.nc);
+  double* b = zalloc(G.nc);
+  double* dinv = zalloc(G.nc);
+  const double kcoef = q->mu / q->Pr * q->cp;
+  const double* w_star = u_star + (long)G.zdir * G.nc;
+  PER_CELL
+  for (long P = 0; P < G.nc; ++P) {
+    w[P] = kinetic(&G, u_star, P) + (enth ? 0.0 : phi_cell(&G, q, P));
+    cT[P] = rho_star[P] * (enth ? q->cp : q->cv) * G.V / q->dt;
+    DT[P] = kcoef;
+  }
+  PER_CELL
+  for (long P = 0; P < G.nc; ++P) {
+    double local;
+    if (enth) {
+      double b_e = (rho[P] * q->cp * T[P] + rho[P] * K_old[P] - p_old[P]) / q->dt;
+      local = G.V * (b_e - rho_star[P] * w[P] / q->dt + p[P] / q->dt -
+                     rho_star[P] * q->g * w_star[P]);
+    } else {
+      double e_n = q->cv * T[P] + kinetic(&G, u, P) + phi_cell(&G, q, P);
+      local = G.V / q->dt * (rho[P] * e_n - rho_star[P] * w[P]);
+    }
+    double bg = 0.0;
+    int kz = coord(&G, P, G.zdir);
+    for (int d = 0; d < G.ndim; ++d) {
+      double k = kcoef * G.S[d] / G.h[d];
+      long st = G.st[d];
+      if (has_hi(&G, P, d)) bg += k * (Tbg[kz] - Tbg[coord(&G, P + st, G.zdir)]);
+      if (has_lo(&G, P, d)) bg += k * (Tbg[kz] - Tbg[coord(&G, P - st, G.zdir)]);
+    }
+    b[P] = local - convective1(&G, phi, w, P) + bg;
+    double a = cT[P] + q->cp * convective_diag(&G, phi, P);
+    for (int d = 0; d < G.ndim; ++d) {
+      double k = kcoef * G.S[d] / G.h[d];
+      if (has_hi(&G, P, d)) a += k;
+      if (has_lo(&G, P, d)) a += k;
+    }
+    dinv[P] = 1.0 / a;
+  }
+  memcpy(T_new, T, sizeof(double) * G.nc);
+  energy_ctx ctx = {q, cT, DT, phi};
+  geao_solve_stats st;
+  int status = bicgstab(&G, energy_op, &ctx, b, T_new, dinv, GEAO_TRANSPORT_TOL, q->max_iter, &st);
+  free(w); free(cT); free(DT); free(b); free(dinv);
+  return status;
+}
+
 /* phi^(k) = phitilde - w (p'_N - p'_P);  u^(k) = (H - R(F^(k))) / A, A = rho* / dt,
  * F^(k) from p'^(k) and rho^{n+2/3} (eq. step2_sd corrector, R1) */
 void geao_correct(const geao_mesh* m, const geao_params* q, const double* pp,
@@ -751,24 +1058,33 @@ static int check_args(const geao_mesh* m, const geao_params* q) {
   if (!(q->R > 0 && q->cp > 0 && q->cv > 0 && q->dt > 0 && q->Pr > 0)) return 0;
   if (q->n_corr < 1 || q->n_energy_sweeps < 1 || q->max_iter < 0) return 0;
   if (q->energy_form != 0 && q->energy_form != 1) return 0;
+  if (q->transport != 0 && q->transport != 1) return 0;
   return 1;
 }
 
 /* Steps 1 and 2 of the step starting from the given state (phi: its flux) */
-static void steps_1_2(const geao_mesh* m, const geao_params* q, const double* rho,
-                      const double* u, const double* T, const double* pp, const double* p,
-                      const double* phi, const double* p_old, const double* K_old,
-                      const double* Tbg, work_t* w) {
+static int steps_1_2(const geao_mesh* m, const geao_params* q, const double* rho,
+                     const double* u, const double* T, const double* pp, const double* p,
+                     const double* phi, const double* p_old, const double* K_old,
+                     const double* Tbg, work_t* w) {
   geom G = make_geom(m);
   memcpy(w->phi, phi, sizeof(double) * G.ndim * G.nc);
   geao_density_predictor(m, q, rho, w->phi, w->rho_star);
   geao_momentum_predictor(m, q, rho, u, pp, w->rho_star, w->phi, w->u_star);
-  if (q->energy_form == 1)
+  if (q->transport == 1) {
+    /* the explicit predictor's u* is the implicit solve's initial guess */
+    int rc = geao_momentum_predictor_implicit(m, q, rho, u, pp, w->rho_star, w->phi, w->u_star);
+    if (rc == GEAO_OK)
+      rc = geao_energy_implicit(m, q, rho, u, T, p, p_old, K_old, w->u_star, w->rho_star, w->phi,
+                                Tbg, w->T_new);
+    if (rc != GEAO_OK) return rc;
+  } else if (q->energy_form == 1)
     geao_energy_enthalpy(m, q, rho, T, p, p_old, K_old, w->u_star, w->rho_star, w->phi, Tbg,
                          w->T_new);
   else
     geao_energy(m, q, rho, u, T, w->u_star, w->rho_star, w->phi, Tbg, w->T_new);
   geao_eos_coeffs(m, q, p, w->T_new, w->rho_star, w->rho23, w->psi, w->c, w->D);
+  return GEAO_OK;
 }
 
 int geao_pressure_system(const geao_mesh* m, const geao_params* q, const double* rho,
@@ -778,7 +1094,11 @@ int geao_pressure_system(const geao_mesh* m, const geao_params* q, const double*
   if (!check_args(m, q)) return GEAO_ERR_ARG;
   geom G = make_geom(m);
   work_t w = work_alloc(&G);
-  steps_1_2(m, q, rho, u, T, pp, p, phi, p_old, K_old, Tbg, &w);
+  int rc = steps_1_2(m, q, rho, u, T, pp, p, phi, p_old, K_old, Tbg, &w);
+  if (rc != GEAO_OK) {
+    work_free(&w);
+    return rc;
+  }
   geao_H(m, q, rho, u, w.u_star, w.phi, w.H);
   geao_predicted_flux_rhs(m, q, rho, w.rho23, w.psi, w.D, w.H, w.phi_tilde, w.b);
   memcpy(c, w.c, sizeof(double) * G.nc);
@@ -801,14 +1121,14 @@ int geao_step(const geao_mesh* m, const geao_params* q, double* rho, double* u, 
   int status = GEAO_OK;
   st->n_solves = 0;
 
-  steps_1_2(m, q, rho, u, T, pp, p, phi, p_old, K_old, Tbg, &w);
+  status = steps_1_2(m, q, rho, u, T, pp, p, phi, p_old, K_old, Tbg, &w);
 
   memcpy(u_k, w.u_star, sizeof(double) * G.ndim * G.nc);
   memcpy(pp_k, pp, sizeof(double) * G.nc);
   /* every corrector convects with the frozen Step-1 flux phi^n (eq. step2_sd
    * of Step 3 and the H operator); the corrected flux only feeds the
    * end-of-step density */
-  for (int k = 0; k < q->n_corr; ++k) {
+  for (int k = 0; k < q->n_corr && status == GEAO_OK; ++k) {
     geao_H(m, q, rho, u, u_k, w.phi, w.H);
     geao_predicted_flux_rhs(m, q, rho, w.rho23, w.psi, w.D, w.H, w.phi_tilde, w.b);
     geao_solve_stats ss;

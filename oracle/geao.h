@@ -48,6 +48,10 @@ typedef struct {
   int32_t max_iter;
   int32_t energy_form;   /* Step 2: 0 total-energy form (geao_energy), 1 the
                             enthalpy form of eq. step3_sd (geao_energy_enthalpy) */
+  int32_t transport;     /* 0: explicit Picard sweeps of the transport terms;
+                            1: Steps 1-2 implicit in the transported quantity,
+                            BiCGStab solves (geao_momentum_predictor_implicit,
+                            geao_energy_implicit) */
 } geao_params;
 
 /* kind 0: no perturbation; 1: cosine theta' = amp/2 (1 + cos(pi r / rc)) for
@@ -73,6 +77,8 @@ enum { GEAO_OK = 0, GEAO_ERR_ARG = -1, GEAO_ERR_NOCONV = -4, GEAO_ERR_NAN = -5 }
 /* relative residual to which each energy sweep's implicit-diffusion system
  * is solved (Step 2, see geao_energy) */
 #define GEAO_ENERGY_TOL 1e-13
+/* relative residual of the implicit-transport solves (transport = 1) */
+#define GEAO_TRANSPORT_TOL 1e-13
 
 int geao_ndim(const geao_mesh* m);
 
@@ -112,6 +118,26 @@ void geao_momentum_predictor(const geao_mesh* m, const geao_params* q, const dou
 void geao_energy(const geao_mesh* m, const geao_params* q, const double* rho, const double* u,
                  const double* T, const double* u_star, const double* rho_star,
                  const double* phi, const double* Tbg, double* T_new);
+/* Implicit transport (transport = 1; see geao.c): operators, their
+ * diagonals (comp >= 0: momentum component; comp = -1: energy with
+ * coefficient cT), the BiCGStab solve of a momentum system, and the two
+ * implicit predictors (u_star: in the initial guess, out the solution). */
+void geao_momentum_operator(const geao_mesh* m, const geao_params* q, const double* rho_star,
+                            const double* phi, int comp, const double* x, double* y);
+void geao_energy_operator(const geao_mesh* m, const geao_params* q, const double* cT,
+                          const double* phi, const double* x, double* y);
+void geao_transport_diag(const geao_mesh* m, const geao_params* q, const double* rho_star,
+                         const double* cT, const double* phi, int comp, double* diag);
+int geao_bicgstab_momentum(const geao_mesh* m, const geao_params* q, const double* rho_star,
+                           const double* phi, int comp, const double* b, double* x, double tol,
+                           int max_iter, geao_solve_stats* st);
+int geao_momentum_predictor_implicit(const geao_mesh* m, const geao_params* q, const double* rho,
+                                     const double* u, const double* pp, const double* rho_star,
+                                     const double* phi, double* u_star);
+int geao_energy_implicit(const geao_mesh* m, const geao_params* q, const double* rho,
+                         const double* u, const double* T, const double* p, const double* p_old,
+                         const double* K_old, const double* u_star, const double* rho_star,
+                         const double* phi, const double* Tbg, double* T_new);
 /* Step 2 in the enthalpy form of eq. step3_sd (see geao.c); p_old, K_old:
  * p^{n-1} and K^{n-1} of the lagged terms of b~_e */
 void geao_energy_enthalpy(const geao_mesh* m, const geao_params* q, const double* rho,

@@ -48,7 +48,8 @@ class Params(C.Structure):
                 ("g", C.c_double), ("p0", C.c_double), ("theta0", C.c_double),
                 ("mu", C.c_double), ("Pr", C.c_double), ("dt", C.c_double),
                 ("n_corr", C.c_int32), ("n_energy_sweeps", C.c_int32),
-                ("tol", C.c_double), ("max_iter", C.c_int32), ("energy_form", C.c_int32)]
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("energy_form", C.c_int32),
+                ("transport", C.c_int32)]
 
 
 class Bubble(C.Structure):
@@ -91,6 +92,13 @@ def lib(omp: bool = False):
         L.geao_momentum_predictor.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d]
         L.geao_energy.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d]
         L.geao_energy_enthalpy.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d, d]
+        L.geao_momentum_operator.argtypes = [P(Mesh), P(Params), d, d, C.c_int, d, d]
+        L.geao_energy_operator.argtypes = [P(Mesh), P(Params), d, d, d, d]
+        L.geao_transport_diag.argtypes = [P(Mesh), P(Params), d, d, d, C.c_int, d]
+        L.geao_bicgstab_momentum.argtypes = [P(Mesh), P(Params), d, d, C.c_int, d, d, C.c_double,
+                                             C.c_int, P(SolveStats)]
+        L.geao_momentum_predictor_implicit.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d]
+        L.geao_energy_implicit.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d, d, d, d, d]
         L.geao_eos_coeffs.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d]
         L.geao_H.argtypes = [P(Mesh), P(Params), d, d, d, d, d]
         L.geao_predicted_flux_rhs.argtypes = [P(Mesh), P(Params), d, d, d, d, d, d, d]
@@ -142,7 +150,7 @@ class Oracle:
                                                           "theta0", "mu", "Pr", "dt")),
                              int(params.get("n_corr", 2)), int(params.get("n_energy_sweeps", 2)),
                              float(params.get("tol", 1e-13)), int(params.get("max_iter", 100000)),
-                             int(params.get("energy_form", 0)))
+                             int(params.get("energy_form", 0)), int(params.get("transport", 0)))
         self.L = lib(omp)
         self.ndim = 2 if self.mesh.ny == 1 else 3
         self.nc = self.mesh.nx * self.mesh.ny * self.mesh.nz
@@ -299,6 +307,61 @@ class Oracle:
              (rho, T, p, p_old, K_old, u_star, rho_star, phi, Tbg)]
         self.L.geao_energy_enthalpy(C.byref(self.mesh), C.byref(self.params), *[_p(x) for x in a],
                                     _p(Tn))
+        return Tn
+
+    # ---- implicit transport ------------------------------------------------
+    def momentum_operator(self, rho_star, phi, comp, x):
+        y = self.zeros()
+        self.L.geao_momentum_operator(C.byref(self.mesh), C.byref(self.params),
+                                      _p(np.ascontiguousarray(rho_star, dtype=np.float64)),
+                                      _p(np.ascontiguousarray(phi, dtype=np.float64)), int(comp),
+                                      _p(np.ascontiguousarray(x, dtype=np.float64)), _p(y))
+        return y
+
+    def energy_operator(self, cT, phi, x):
+        y = self.zeros()
+        self.L.geao_energy_operator(C.byref(self.mesh), C.byref(self.params),
+                                    _p(np.ascontiguousarray(cT, dtype=np.float64)),
+                                    _p(np.ascontiguousarray(phi, dtype=np.float64)),
+                                    _p(np.ascontiguousarray(x, dtype=np.float64)), _p(y))
+        return y
+
+    def transport_diag(self, phi, comp, rho_star=None, cT=None):
+        out = self.zeros()
+        z = self.zeros()
+        self.L.geao_transport_diag(C.byref(self.mesh), C.byref(self.params),
+                                   _p(np.ascontiguousarray(z if rho_star is None else rho_star, dtype=np.float64)),
+                                   _p(np.ascontiguousarray(z if cT is None else cT, dtype=np.float64)),
+                                   _p(np.ascontiguousarray(phi, dtype=np.float64)), int(comp), _p(out))
+        return out
+
+    def bicgstab_momentum(self, rho_star, phi, comp, b, x0, tol, max_iter=1000):
+        x = np.array(x0, dtype=np.float64, copy=True)
+        st = SolveStats()
+        rc = self.L.geao_bicgstab_momentum(C.byref(self.mesh), C.byref(self.params),
+                                           _p(np.ascontiguousarray(rho_star, dtype=np.float64)),
+                                           _p(np.ascontiguousarray(phi, dtype=np.float64)), int(comp),
+                                           _p(np.ascontiguousarray(b, dtype=np.float64)), _p(x),
+                                           float(tol), int(max_iter), C.byref(st))
+        return x, st, rc
+
+    def momentum_predictor_implicit(self, rho, u, pp, rho_star, phi, u_guess):
+        us = np.array(u_guess, dtype=np.float64, copy=True)
+        rc = self.L.geao_momentum_predictor_implicit(
+            C.byref(self.mesh), C.byref(self.params), *[_p(np.ascontiguousarray(a, dtype=np.float64))
+                                                        for a in (rho, u, pp, rho_star, phi)], _p(us))
+        if rc != OK:
+            raise RuntimeError(f"geao_momentum_predictor_implicit failed: {rc}")
+        return us
+
+    def energy_implicit(self, rho, u, T, p, p_old, K_old, u_star, rho_star, phi, Tbg):
+        Tn = self.zeros()
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in
+             (rho, u, T, p, p_old, K_old, u_star, rho_star, phi, Tbg)]
+        rc = self.L.geao_energy_implicit(C.byref(self.mesh), C.byref(self.params), *[_p(x) for x in a],
+                                         _p(Tn))
+        if rc != OK:
+            raise RuntimeError(f"geao_energy_implicit failed: {rc}")
         return Tn
 
     def eos_coeffs(self, p, T_new, rho_star):

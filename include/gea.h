@@ -99,6 +99,11 @@ typedef struct {
   int32_t energy_form;             /* Step 2: 0 = total-energy form (flux phi I4(e + R T)); 1 = the
                                       enthalpy form of eq. step3_sd (h = c_p T, lagged p^{n-1} and
                                       K^{n-1} in b~_e, gravity work rho* g w*)                      */
+  int32_t transport;               /* Steps 1-2: 0 = explicit transport (Picard sweeps, implicit
+                                      diffusion of the energy); 1 = implicit transport as eqs.
+                                      step2_sd (Step 1) and step3_sd write it: per velocity
+                                      component and once for T a non-symmetric system, solved by
+                                      Jacobi-preconditioned BiCGStab to 1e-13                      */
 } gea_params;
 
 /* initial perturbation of Sec. 4: kind 0 none; 1 cosine bubble
@@ -126,6 +131,7 @@ typedef struct {
   double max_rel_res;          /* largest exit residual (rel_res) of all solves of this call */
   int64_t total_fallbacks;     /* learned form: fallbacks of all solves of this call   */
   int64_t energy_iters;        /* CG iterations of the Step-2 energy solves of this call */
+  int64_t transport_iters;     /* implicit transport: BiCGStab iterations of this call   */
 } gea_step_stats;
 
 /* field selectors for gea_get_fields (bit mask; output packed in bit order) */
@@ -251,7 +257,8 @@ gea_status gea_get_fields(gea_ctx* ctx, uint32_t field_mask, double* out, gea_pt
  *     residual and correction, FP32 coefficient copy)
  *   5 explicit step kernels (Steps 1-3 outside the solve)
  *   6 learned network kernels
- *   7 Step-2 energy solves (CG set-up, iteration and scalar kernels)
+ *   7 Step-2 energy solves (CG set-up, iteration and scalar kernels), and
+ *     with transport = 1 the BiCGStab solves of Steps 1 and 2
  * reset = 1 clears the sums.  Timing adds two event records per launch. */
 gea_status gea_kernel_timing(gea_ctx* ctx, int32_t on, int32_t reset);
 

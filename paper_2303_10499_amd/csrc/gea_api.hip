@@ -209,6 +209,9 @@ struct gea_ctx {
   double* pair_s;      // max |r0| and its inverse (training pairs)
   FcgScalars* fsc;
   FcgVectors fv;
+  // implicit transport (transport = 1): BiCGStab vectors and scalars
+  TrVecs trv{};
+  TrScalars* tsc = nullptr;
   Cnn net;             // network at the mesh resolution (learned form only)
   bool has_net_space = false;
   bool has_net = false;
@@ -309,7 +312,7 @@ void set_call_error(const std::string& msg) { g_init_error = msg; }
 
 namespace {
 
-size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
+size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned, bool transport) {
   const size_t nc = (size_t)m.nx * m.ny * m.nz;
   const int nd = m.ny == 1 ? 2 : 3;
   for (int s = 0; s < 2; ++s) {
@@ -369,6 +372,11 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned) {
   x->sc = cv.take<CgScalars>(1);
   x->sc32 = cv.take<CgScalars>(1);
   x->fsc = cv.take<FcgScalars>(1);
+  x->tsc = cv.take<TrScalars>(1);
+  if (transport)
+    for (double** a : {&x->trv.b, &x->trv.dinv, &x->trv.r, &x->trv.rh, &x->trv.p, &x->trv.v,
+                       &x->trv.y, &x->trv.z, &x->trv.t})
+      *a = cv.take<double>(nc);
   // partials: 7 per workgroup of the iteration kernel's grid; 2 (and 1 for
   // ||b||^2) per workgroup of the set-up kernels' column-tile grid
   const int ns = std::max(iter_grid<double>(make_geo(m)), iter_grid<float>(make_geo(m)));
@@ -441,6 +449,10 @@ gea_status check_params(const gea_mesh* m, const gea_params* q, std::string& err
   }
   if (q->energy_form != 0 && q->energy_form != 1) {
     err = "energy_form must be 0 (total energy) or 1 (enthalpy)";
+    return GEA_ERR_ARG;
+  }
+  if (q->transport != 0 && q->transport != 1) {
+    err = "transport must be 0 (explicit sweeps) or 1 (implicit, BiCGStab)";
     return GEA_ERR_ARG;
   }
   return GEA_OK;
@@ -1008,6 +1020,71 @@ gea_status solve_energy(gea_ctx* x, double* T, int nparts, int sweep, int* iters
 // copied to pp_out when given (the pressure solve's initial guess).  Each
 // energy sweep solves its implicit-diffusion system for T (pressure-solve
 // work vectors, which are free until Step 3).
+// Implicit transport (transport = 1): the momentum operator of component
+// comp and the energy operator (unknown T) of Steps 1 and 2, with the
+// state's face flux
+TrOp momentum_op(const gea_ctx* x, const State& S, int comp) {
+  const Geo& G = x->G;
+  TrOp op{};
+  op.rho_star = x->rho_star;
+  op.tcoef = G.V / x->ph.dt;
+  op.gamma = 1.0;
+  op.wall_comp = comp;
+  for (int d = 0; d < G.ndim; ++d) {
+    op.phi[d] = S.phi[d];
+    op.k[d] = x->ph.mu * G.S[d] / G.h[d];
+  }
+  return op;
+}
+
+TrOp energy_op(const gea_ctx* x, const State& S, bool enth) {
+  const Geo& G = x->G;
+  TrOp op{};
+  op.rho_star = x->rho_star;
+  op.tcoef = (enth ? x->ph.cp : x->ph.cv) * G.V / x->ph.dt;
+  op.gamma = x->ph.cp;
+  op.wall_comp = -1;
+  for (int d = 0; d < G.ndim; ++d) {
+    op.phi[d] = S.phi[d];
+    op.k[d] = x->ph.mu / x->ph.Pr * x->ph.cp * G.S[d] / G.h[d];
+  }
+  return op;
+}
+
+// One BiCGStab solve behind its enqueued set-up: iterations in batches
+// (doubling up to 16), the scalars read once a batch.
+gea_status bicg_run(gea_ctx* x, const TrOp& op, double* xv, int* iters) {
+  const Geo& G = x->G;
+  x->timer.run(7, x->stream, [&] {
+    launch_tr_start(x->stream, G, x->partials, kTransportTol, x->prm.max_iter, x->tsc);
+  });
+  TrScalars hs{};
+  int batch = 2;
+  long launched = 0;
+  for (;;) {
+    for (int k = 0; k < batch; ++k)
+      x->timer.run(7, x->stream, [&] {
+        launch_tr_iteration(x->stream, G, op, xv, x->trv, x->partials, x->tsc);
+      });
+    HIPCHK(hipGetLastError());
+    launched += batch;
+    const Extra part{x->tsc, &hs, sizeof hs};
+    read_structs(x, &part, 1);
+    if (hs.done) break;
+    if (launched > (long)x->prm.max_iter + 32) {
+      x->err = "implicit transport solve: the solver never finished";
+      return GEA_ERR_NOCONV;
+    }
+    batch = batch < 16 ? 2 * batch : 16;
+  }
+  if (hs.bb == 0.0) launch_fill(x->stream, G, xv, 0.0);  // b = 0: x = 0
+  *iters = hs.iter;
+  if (hs.status == 0) return GEA_OK;
+  x->err = hs.status == -5 ? "non-finite value in an implicit transport solve"
+                           : "implicit transport solve did not converge";
+  return hs.status == -5 ? GEA_ERR_NAN : GEA_ERR_NOCONV;
+}
+
 // the current state's p^{n-1}, K^{n-1}: its own p^n, K^n if it has none
 void ensure_history(gea_ctx* x) {
   if (x->hist[x->cur]) return;
@@ -1018,7 +1095,7 @@ void ensure_history(gea_ctx* x) {
 }
 
 gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out = nullptr,
-                     int64_t* energy_iters = nullptr) {
+                     int64_t* energy_iters = nullptr, int64_t* transport_iters = nullptr) {
   const Geo& G = x->G;
   const Phys& ph = x->ph;
   hipStream_t s = x->stream;
@@ -1026,6 +1103,44 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
   x->timer.run(5, x->stream, [&] {
     launch_step1(s, G, ph, S.rho, S.u, S.T, S.pp, S.phi, x->rho_star, x->e0, x->ustar, pp_out);
   });
+  if (x->prm.transport == 1) {
+    // Step 1's momentum predictor implicit: per component from the explicit
+    // predictor's u*
+    for (int d = 0; d < G.ndim; ++d) {
+      const TrOp op = momentum_op(x, S, d);
+      x->timer.run(7, x->stream, [&] {
+        launch_tr_setup_mom(s, G, op, S.u[d], x->ustar[d], x->trv, x->partials);
+      });
+      int its = 0;
+      gea_status rc = bicg_run(x, op, x->ustar[d], &its);
+      if (transport_iters) *transport_iters += its;
+      if (rc != GEA_OK) return rc;
+    }
+    if (enth) {
+      const State& N = x->st[1 - x->cur];
+      ensure_history(x);
+      x->timer.run(5, x->stream, [&] {
+        launch_enthalpy_prep(s, G, ph, S.rho, S.T, S.p, S.pm, S.Km, S.u, x->ustar, x->rho_star,
+                             x->e0, x->eb, N.pm, N.Km);
+      });
+    }
+    // Step 2 in one implicit solve for T
+    const TrOp op = energy_op(x, S, enth);
+    x->timer.run(7, x->stream, [&] {
+      launch_tr_setup_energy(s, G, ph, enth, op, S.rho, x->e0, x->ustar, x->ea, S.T, x->Tbg, T_out,
+                             x->trv, x->partials);
+    });
+    int its = 0;
+    gea_status rc = bicg_run(x, op, T_out, &its);
+    if (transport_iters) *transport_iters += its;
+    if (rc != GEA_OK) return rc;
+    x->timer.run(5, x->stream, [&] {
+      launch_energy_post(s, G, ph, enth, T_out, x->ustar, x->ea, true, S.p, x->rho_star, x->rho23,
+                         x->psi, x->c, x->D);
+    });
+    x->sys32 = false;
+    return GEA_OK;
+  }
   const double* e_prev = x->e0;
   if (enth) {
     // e0 becomes the sweep-independent balance, eb the first sweep's c_p T + K*;
@@ -1073,7 +1188,7 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
   const State& S = x->st[x->cur];
   const State& N = x->st[1 - x->cur];
   {
-    gea_status rc = steps_1_2(x, S, N.T, N.pp, &stats->energy_iters);
+    gea_status rc = steps_1_2(x, S, N.T, N.pp, &stats->energy_iters, &stats->transport_iters);
     if (rc != GEA_OK) return rc;
   }
   const int nc = x->prm.n_corr;
@@ -1166,7 +1281,7 @@ gea_status gea_workspace_bytes(const gea_mesh* mesh, const gea_params* params, s
   if (!bytes) return GEA_ERR_ARG;
   gea_ctx tmp;
   Carver cv(nullptr);
-  *bytes = carve(cv, &tmp, *mesh, params->solver == GEA_LEARNED_MIXED);
+  *bytes = carve(cv, &tmp, *mesh, params->solver == GEA_LEARNED_MIXED, params->transport == 1);
   return GEA_OK;
 }
 
@@ -1207,7 +1322,7 @@ gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* h
   x->net.s = x->stream;
   setup_geometry(x);
   Carver cv(workspace);
-  carve(cv, x, *mesh, params->solver == GEA_LEARNED_MIXED);
+  carve(cv, x, *mesh, params->solver == GEA_LEARNED_MIXED, params->transport == 1);
   gea_status rc = guarded(x, [&]() {
     // zero the solver scalars once
     HIPCHK(hipMemsetAsync(x->sc, 0, sizeof(CgScalars), x->stream));

@@ -236,6 +236,43 @@ void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* 
 void launch_sub(hipStream_t s, const Geo& G, const double* b, double* y);
 // a = v
 void launch_fill(hipStream_t s, const Geo& G, double* a, double v);
+
+// ---- implicit transport (gea_bicg.hip) --------------------------------------
+// Operator (times V): (A x)_P = rho*_P tcoef x_P + gamma sum_out phi I4(x)
+//   + sum_f k_d (x_P - x_nb) + 2 k_d x_P on the walls normal to d = wall_comp.
+struct TrOp {
+  const double* rho_star;
+  double tcoef;
+  const double* phi[3];
+  double gamma;
+  double k[3];
+  int wall_comp;  // -1: no wall term
+};
+// BiCGStab work vectors (ncell each); r also holds s between the half steps
+struct TrVecs {
+  double *b, *dinv, *r, *rh, *p, *v, *y, *z, *t;
+};
+struct TrScalars {
+  double bb, rr, rr0, rho, rho_old, alpha, omega, beta, tol2;
+  int iter, max_iter, status, done;  // status 0 ok, -4 no convergence or breakdown, -5 non-finite
+};
+// set-up of a momentum component (x0: the initial guess, u^n: the old
+// component; b = A u^n + c (x0 - u^n)) or of the energy solve (writes the
+// known transported part into w and T^n into x); each stores 2 partials a
+// workgroup (grid_for(nc) workgroups) for launch_tr_start
+void launch_tr_setup_mom(hipStream_t s, const Geo& G, const TrOp& op, const double* un,
+                         const double* x0, const TrVecs& v, double* part);
+void launch_tr_setup_energy(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const TrOp& op,
+                            const double* rho, const double* e0, double* const* u_star,
+                            double* w, const double* Tn, const double* Tbg, double* x,
+                            const TrVecs& v, double* part);
+void launch_tr_start(hipStream_t s, const Geo& G, const double* part, double tol, int max_iter,
+                     TrScalars* sc);
+// one BiCGStab iteration (nine launches; all return at once once sc->done)
+void launch_tr_iteration(hipStream_t s, const Geo& G, const TrOp& op, double* x, const TrVecs& v,
+                         double* part, TrScalars* sc);
+// relative residual of the implicit-transport solves
+constexpr double kTransportTol = 1e-13;
 // a solve's scalars from the set-up partials another kernel formed (nu
 // workgroups: <r, r/diag>, ||r||^2 in u_part, ||b||^2 in b_part)
 void cg_start_from(hipStream_t s, const double* u_part, int nu, const double* b_part, double tol,

@@ -44,7 +44,8 @@ class Params(C.Structure):
                 ("n_energy_sweeps", C.c_int32), ("solver", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("check_every", C.c_int32), ("inner_tol", C.c_double),
                 ("learned_steps", C.c_int32), ("inner_target", C.c_double),
-                ("learned_always", C.c_int32), ("energy_form", C.c_int32)]
+                ("learned_always", C.c_int32), ("energy_form", C.c_int32),
+                ("transport", C.c_int32)]
 
 
 class Bubble(C.Structure):
@@ -65,7 +66,7 @@ class StepStats(C.Structure):
                 ("total_iters", C.c_int64), ("total_solves", C.c_int64),
                 ("eos_mismatch", C.c_double), ("mass", C.c_double),
                 ("max_rel_res", C.c_double), ("total_fallbacks", C.c_int64),
-                ("energy_iters", C.c_int64)]
+                ("energy_iters", C.c_int64), ("transport_iters", C.c_int64)]
 
 
 class Extrema(C.Structure):
@@ -129,7 +130,8 @@ def make_params(p: dict, solver="pcg64") -> Params:
                   float(p.get("tol", 1e-10)), int(p.get("max_iter", 20000)),
                   int(p.get("check_every", 8)), float(p.get("inner_tol", 1e-4)),
                   int(p.get("learned_steps", 1)), float(p.get("inner_target", 0.0)),
-                  int(p.get("learned_always", 0)), int(p.get("energy_form", 0)))
+                  int(p.get("learned_always", 0)), int(p.get("energy_form", 0)),
+                  int(p.get("transport", 0)))
 
 
 def _ptr(a):

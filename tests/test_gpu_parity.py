@@ -175,6 +175,28 @@ def test_enthalpy_form_steps_match_oracle(oracle_lib, gea_mod, name, dims, steps
     assert rel(K_old, s.K_old) <= 2e-10 or K_err <= 2 * np.max(np.abs(s.u)) * u_floor(s, cfg, steps)
 
 
+@pytest.mark.parametrize("name,dims,steps,form", [
+    ("bubble2d_64x32", (64, 32, None), 10, 0),
+    ("bubble2d_64x32", (37, 23, None), 5, 1),          # ragged, enthalpy form
+    ("nonsmooth2d_2048", (96, 100, None), 3, 0),       # CFL ~ 0.1 on 10 m cells
+    ("bubble3d_256x256x128", (13, 9, 11), 3, 0),       # ragged 3D
+    ("bubble3d_256x256x128", (20, 150, 12), 2, 1),     # tall 3D, enthalpy form
+])
+def test_implicit_transport_steps_match_oracle(oracle_lib, gea_mod, name, dims, steps, form):
+    """Steps 1-2 with implicit transport (transport 1: BiCGStab per velocity
+    component and for T, Sec. 3 eqs. step2_sd and step3_sd at the new
+    level): every field and the face flux against the oracle"""
+    nx, nz, ny = dims
+    cfg = cfg_mesh(name, nx, nz, ny, tol=1e-13, max_iter=100000, energy_form=form, transport=1)
+    O, s, S = pair(oracle_lib, gea_mod, cfg)
+    O.step(s, steps)
+    st = S.step(steps)
+    assert st.steps_done == steps
+    assert st.transport_iters >= steps * (1 + O.ndim)   # every solve iterated
+    strict = name == "bubble2d_64x32" and dims[:2] == (64, 32)
+    compare(S, s, 1e-10, None if strict else cfg, steps)
+
+
 def test_enthalpy_form_history_round_trip(oracle_lib, gea_mod):
     """a state copied out with its flux and its lagged terms, and into a fresh
     context, continues bitwise; without the lagged terms its next step is
@@ -217,17 +239,20 @@ def test_many_workgroups_grid_stride(oracle_lib, gea_mod):
     compare(S, s, 1e-10, cfg, 1)
 
 
-@pytest.mark.parametrize("name,dims,form", [("bubble2d_64x32", (64, 32, None), 0),
-                                            ("bubble2d_64x32", (64, 32, None), 1),
-                                            ("bubble3d_256x256x128", (24, 16, 20), 0),
-                                            ("bubble3d_256x256x128", (70, 20, 10), 1)])
-def test_rest_state_and_determinism(oracle_lib, gea_mod, name, dims, form):
+@pytest.mark.parametrize("name,dims,form,transport", [
+    ("bubble2d_64x32", (64, 32, None), 0, 0),
+    ("bubble2d_64x32", (64, 32, None), 1, 0),
+    ("bubble2d_64x32", (64, 32, None), 1, 1),
+    ("bubble3d_256x256x128", (24, 16, 20), 0, 0),
+    ("bubble3d_256x256x128", (70, 20, 10), 1, 0),
+    ("bubble3d_256x256x128", (24, 16, 20), 0, 1)])
+def test_rest_state_and_determinism(oracle_lib, gea_mod, name, dims, form, transport):
     """the discretely hydrostatic atmosphere at rest stays at rest (Sec. 2, eq.
     p_split), and two runs of a bubble from the same state are bitwise equal
     (the 3D kernels stage tiles in LDS and reduce per workgroup: no atomic sums,
     no order that depends on scheduling)"""
     nx, nz, ny = dims
-    cfg = cfg_mesh(name, nx, nz, ny, tol=1e-14, energy_form=form)
+    cfg = cfg_mesh(name, nx, nz, ny, tol=1e-14, energy_form=form, transport=transport)
     S = gea_mod.Solver(cfg["mesh"], cfg["params"])
     S.init_bubble(0)
     s0 = S.state()

@@ -16,6 +16,9 @@ Two measurements per form:
     steps in 3D, 500 on the 2D 2048^2 mesh), timed as one piece, the median
     of several repetitions in 3D (`full_run`).
 Every solve's exit residual is reported (`max_rel_res`), unrounded.
+`implicit_transport`: the same meshes with Steps 1-2 solved implicitly
+(transport = 1, BiCGStab; the refinement form for the pressure), in both
+energy forms: the timed window only.
 
 Prints one JSON line.
 """
@@ -148,6 +151,28 @@ def run_window(cfg, form, steps, warmup, kernel_steps):
     return out
 
 
+def run_transport(cfg, steps, warmup, solver="mixed"):
+    """the implicit-transport variant of the step (Steps 1-2 solved by BiCGStab,
+    transport = 1) in both energy forms: the timed window of one solver form"""
+    from paper_2303_10499_amd import gea
+    out = {}
+    for name, form in (("total_energy", 0), ("enthalpy", 1)):
+        params = dict(cfg["params"], transport=1, energy_form=form)
+        S = gea.Solver(cfg["mesh"], params, solver=solver)
+        S.init_bubble(**cfg["bubble"])
+        if warmup:
+            S.step(warmup)
+        ms, st = timed_steps(S, steps)
+        log(f"[bench] {cfg['name']} {solver}, implicit transport, {name}: {steps} steps in {ms:.1f} ms")
+        out[name] = dict(solver=solver, ms_per_step=ms / steps,
+                         cell_steps_per_s=S.nc * steps / (ms * 1e-3),
+                         transport_iters_per_step=st.transport_iters / steps,
+                         iters_per_solve=st.total_iters / max(st.total_solves, 1),
+                         max_rel_res=st.max_rel_res)
+        S.close()
+    return {k: clean(v) for k, v in out.items()}
+
+
 def run_full(cfg, form, nsteps, reps):
     """the whole evaluation run from the initial state, reps times"""
     S = make_solver(cfg, form)
@@ -270,6 +295,8 @@ def main():
     ap.add_argument("--full-reps-also", type=int, default=1, help="full runs per form on the second mesh")
     ap.add_argument("--full-forms-also", default="pcg64,mixed,learned,learned_always")
     ap.add_argument("--no-full", action="store_true", help="skip the full evaluation runs")
+    ap.add_argument("--no-transport", action="store_true",
+                    help="skip the implicit-transport variant (Steps 1-2 by BiCGStab)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -330,7 +357,9 @@ def main():
                 "cells": cfg2["mesh"]["nx"] * cfg2["mesh"]["ny"] * cfg2["mesh"]["nz"],
                 "forms": public(res2), "speedup_vs_pcg64": speedups(res2),
                 "roofline": {k: roofline_entry(v["_roofline"]) for k, v in res2.items()},
-                "full_run": full2}
+                "full_run": full2,
+                "implicit_transport": None if args.no_transport else
+                run_transport(cfg2, args.steps, args.warmup)}
     primary = "learned" if "learned" in results else ("mixed" if "mixed" in results else forms[0])
     R = results[primary]
     nc = cfg["mesh"]["nx"] * cfg["mesh"]["ny"] * cfg["mesh"]["nz"]
@@ -359,6 +388,7 @@ def main():
         "full_run": full,
         "roofline": roofline_entry(R["_roofline"]),
         "roofline_by_form": {k: roofline_entry(v["_roofline"]) for k, v in results.items()},
+        "implicit_transport": None if args.no_transport else run_transport(cfg, args.steps, args.warmup),
         "cpu_baseline": cpu,
         "also": also,
     }

@@ -50,6 +50,12 @@ CONFIGS = {
         steps=200, bubble=dict(kind=1, xc=10000.0, yc=10000.0, zc=2000.0, rc=2000.0, amp=2.0),
         solver="learned", tol=1e-8),
 }
+# small 3D runs for the 3D network's training pairs: the evaluation mesh's
+# 78 m cells and time step on a 5 km x 5 km x 2.5 km box
+CONFIGS["bubble3d_64x64x32_train"] = _cfg(
+    "bubble3d_64x64x32_train", 64, 64, 32, 5000.0, 5000.0, 2500.0, dt=0.5, mu=0.15, steps=100,
+    bubble=dict(kind=1, xc=2500.0, yc=2500.0, zc=800.0, rc=500.0, amp=2.0),
+    solver="mixed", tol=1e-8)
 # The paper's own validation runs (Sec. 4): the 1000 m x 1000 m box, c_v = 715.5 and
 # c_p = R + c_v, dt 0.1 s, to 600 s; the smooth bubble (eq. dcEqn1: 0.5 K peak, r_c 250 m,
 # centre (500, 350) m, mu 0.15) on 5 m cells and the non-smooth one (eq. dcEqn2: 0.5 K,

@@ -17,7 +17,17 @@ network's output scale irrelevant to the solve).  Training runs the library's
 bfloat16 forward and backward kernels with Adam (FP32 master weights).  The
 held-out error is reported on crops and on whole fields.
 
-Usage: python -m paper_2303_10499_amd.train --workload nonsmooth2d_2048 --out w2d.npy
+Data (--data sources, the default): 20000 pairs dumped from whole runs of
+the 2D workloads bubble2d_64x32, bubble2d_1280x640 and nonsmooth2d_2048 (one
+pair a step, each from a fresh random bubble every 100 steps; 10000, 8500
+and 1500 pairs) for the 2D network, and 20000 pairs from runs on a small 3D
+mesh with the evaluation mesh's cells and time step (bubble3d_64x64x32_train)
+for the 3D network; one 32^2 or 32^3 crop a pair.  --data workload cuts
+the crops from runs on the evaluation workload itself instead.  Held-out
+pairs come from the same sources with seed 1, and whole fields of the
+evaluation workload measure the error the solver sees.
+
+Usage: python -m paper_2303_10499_amd.train --ndim 2 [--data sources|workload] [--out w2d.npy]
 """
 from __future__ import annotations
 
@@ -125,6 +135,76 @@ def make_pairs(workload: str, runs: int, crops_per_run: int, seed: int, device="
     return torch.stack(Xs), torch.stack(Ts), ndim, cs
 
 
+# pair sources of the default training set: (workload, pairs a seed-0 set of
+# 20000 holds; a run gives one pair a step)
+SOURCES = {2: [("bubble2d_64x32", 10000), ("bubble2d_1280x640", 8500), ("nonsmooth2d_2048", 1500)],
+           3: [("bubble3d_64x64x32_train", 20000)]}
+EVAL_WORKLOAD = {2: "nonsmooth2d_2048", 3: "bubble3d_256x256x128"}
+
+
+def make_source_pairs(ndim: int, total: int, seed: int, device="cuda:0", cs: int = 32,
+                      steps_per_run: int = 100):
+    """one cs^ndim crop (rescaled by its own max |r0|, at least 5 % of the
+    field's maximum) from each of `total` pairs dumped step by step from
+    runs of the source workloads (shares as in SOURCES)"""
+    import torch
+    L = learned._lib()
+    rng = np.random.default_rng(seed)
+    ref = sum(n for _, n in SOURCES[ndim])
+    Xs, Ts = [], []
+    t0 = time.time()
+    for wl, share in SOURCES[ndim]:
+        want = max(1, round(total * share / ref))
+        cfg = configs.get(wl)
+        m = cfg["mesh"]
+        cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=200000)
+        S = gea.Solver(m, cfg["params"], solver="mixed", device=device)
+        nc = S.nc
+        r = torch.empty(nc, dtype=torch.float32, device=device)
+        a = torch.empty_like(r)
+        d = torch.empty_like(r)
+        shape = (m["nz"], m["nx"]) if ndim == 2 else (m["nz"], m["ny"], m["nx"])
+        R, A, D = (v.view(shape) for v in (r, a, d))
+        got = 0
+        n_step = steps_per_run
+        t_log = time.time()
+        while got < want:
+            if n_step >= steps_per_run:
+                S.init_bubble(**draw_bubble(rng, cfg))
+                n_step = 0
+            rc, st = S.step_status(1)
+            n_step += 1
+            if rc != gea.OK:       # a bubble the mesh cannot carry: draw another
+                n_step = steps_per_run
+                continue
+            sc = C.c_double(0.0)
+            rc = L.gea_make_pair(S.ctx, 1e-12, C.c_void_p(r.data_ptr()), C.c_void_p(a.data_ptr()),
+                                 C.c_void_p(d.data_ptr()), C.byref(sc), gea.DEVICE)
+            if rc != gea.OK:
+                raise gea.GeaError(rc, "gea_make_pair")
+            for _ in range(20):
+                o = [int(rng.integers(0, n - cs + 1)) for n in shape]
+                sl = tuple(slice(oi, oi + cs) for oi in o)
+                s = float(R[sl].abs().max())
+                if s >= 0.05:
+                    Xs.append(torch.stack([R[sl] / s, A[sl]], dim=-1).reshape(-1, 2).clone())
+                    Ts.append((D[sl] / s).reshape(-1).clone())
+                    got += 1
+                    break
+            if time.time() - t_log > 10.0 or got == want:
+                t_log = time.time()
+                log(f"[pairs] {wl} seed {seed}: {got}/{want} pairs ({time.time() - t0:.1f} s)")
+        S.close()
+    return torch.stack(Xs), torch.stack(Ts), cs
+
+
+def eval_fields(ndim: int, runs: int, seed: int, device="cuda:0"):
+    """whole-field pairs (x, t) of the evaluation workload (held out)"""
+    fields = []
+    make_pairs(EVAL_WORKLOAD[ndim], runs, 1, seed=seed, device=device, fields=fields)
+    return fields
+
+
 def rel_error(net, X, T) -> float:
     """||y - t|| / ||t|| over held-out crops"""
     num = den = 0.0
@@ -192,7 +272,11 @@ def evaluate(net, X, T) -> float:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="nonsmooth2d_2048")
+    ap.add_argument("--ndim", type=int, default=2)
+    ap.add_argument("--data", choices=("sources", "workload"), default="sources")
+    ap.add_argument("--pairs", type=int, default=20000, help="--data sources: training pairs")
+    ap.add_argument("--heldout-pairs", type=int, default=400)
+    ap.add_argument("--workload", default=None, help="--data workload: default the evaluation mesh")
     ap.add_argument("--runs", type=int, default=40)
     ap.add_argument("--crops", type=int, default=50)
     ap.add_argument("--eval-runs", type=int, default=4)
@@ -202,11 +286,19 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--crop-scale", choices=("local", "global"), default="local")
     args = ap.parse_args()
-    X, T, ndim, cs = make_pairs(args.workload, args.runs, args.crops, seed=0,
-                                crop_scale=args.crop_scale)
-    fields = []
-    Xv, Tv, _, _ = make_pairs(args.workload, args.eval_runs, 16, seed=1,
-                              crop_scale=args.crop_scale, fields=fields)
+    ndim = args.ndim
+    if args.data == "sources":
+        X, T, cs = make_source_pairs(ndim, args.pairs, seed=0)
+        Xv, Tv, _ = make_source_pairs(ndim, args.heldout_pairs, seed=1)
+        fields = eval_fields(ndim, args.eval_runs, seed=1)
+        workload = "+".join(w for w, _ in SOURCES[ndim])
+    else:
+        workload = args.workload or EVAL_WORKLOAD[ndim]
+        X, T, ndim, cs = make_pairs(workload, args.runs, args.crops, seed=0,
+                                    crop_scale=args.crop_scale)
+        fields = []
+        Xv, Tv, _, _ = make_pairs(workload, args.eval_runs, 16, seed=1,
+                                  crop_scale=args.crop_scale, fields=fields)
     sigma = float(T.pow(2).mean().sqrt())
     T /= sigma
     Tv /= sigma
@@ -220,10 +312,10 @@ def main():
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     params = net.get_params()
     np.save(out, params)
-    m = configs.get(args.workload)["mesh"]
+    m = configs.get(EVAL_WORKLOAD[ndim] if args.data == "sources" else workload)["mesh"]
     shape = (m["nz"], m["nx"]) if ndim == 2 else (m["nz"], m["ny"], m["nx"])
     ferr = field_error(ndim, shape, params, fields)
-    summary = dict(workload=args.workload, ndim=ndim, crop=cs, crop_scale=args.crop_scale,
+    summary = dict(data=args.data, workload=workload, ndim=ndim, crop=cs, crop_scale=args.crop_scale,
                    heldout_field_rel_error=ferr, train_crops=int(X.shape[0]),
                    heldout_crops=int(Xv.shape[0]), steps=args.steps, batch=args.batch,
                    first_loss=float(np.mean(losses[:20])), last_loss=float(np.mean(losses[-200:])),

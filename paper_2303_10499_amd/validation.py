@@ -6,10 +6,11 @@ Table 1.  Non-smooth bubble (Sec. 4.2): theta' extrema at 420 s and 600 s on
 5 m and 10 m cells, against Table 3.  The paper's discretisation (OpenFOAM,
 implicit transport) differs from this one, so its numbers are a plausibility
 band, not a parity target.  --energy-form 1 takes Step 2 in the paper's
-enthalpy form (eq. step3_sd) instead of the total-energy form.
+enthalpy form (eq. step3_sd) instead of the total-energy form; --transport 1
+solves Steps 1-2 with the transport implicit, as the paper writes them.
 
     python -m paper_2303_10499_amd.validation [--cases smooth5,nonsmooth5,nonsmooth10]
-                                              [--energy-form 0|1]
+                                              [--energy-form 0|1] [--transport 0|1]
 """
 from __future__ import annotations
 
@@ -32,13 +33,14 @@ CASES = {"smooth5": "paper_smooth_5m", "nonsmooth5": "paper_nonsmooth_5m",
          "nonsmooth10": "paper_nonsmooth_10m"}
 
 
-def run(case: str, solver: str = "pcg64", tol: float = 1e-10, log=None, energy_form: int = 0) -> dict:
+def run(case: str, solver: str = "pcg64", tol: float = 1e-10, log=None, energy_form: int = 0,
+        transport: int = 0) -> dict:
     """run one case to 600 s; the extrema at the paper's output times"""
     from . import configs, gea
     if log is None:
         def log(msg):
             print(msg, file=sys.stderr, flush=True)
-    cfg = configs.get(CASES[case], tol=tol, energy_form=energy_form)
+    cfg = configs.get(CASES[case], tol=tol, energy_form=energy_form, transport=transport)
     S = gea.Solver(cfg["mesh"], cfg["params"], solver=solver)
     if solver == "learned":
         S.load_weights()
@@ -74,11 +76,13 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--energy-form", type=int, default=0,
                     help="Step 2: 0 total energy, 1 the enthalpy form of eq. step3_sd")
+    ap.add_argument("--transport", type=int, default=0,
+                    help="Steps 1-2: 0 explicit transport, 1 implicit (BiCGStab)")
     args = ap.parse_args(argv)
     res = {}
     for c in args.cases.split(","):
-        res[c] = dict(ours=run(c, args.solver, args.tol, energy_form=args.energy_form),
-                      paper=PAPER[c])
+        res[c] = dict(ours=run(c, args.solver, args.tol, energy_form=args.energy_form,
+                               transport=args.transport), paper=PAPER[c])
     print(json.dumps(res), flush=True)
     return res
 

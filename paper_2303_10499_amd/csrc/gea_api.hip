@@ -211,6 +211,7 @@ struct gea_ctx {
   FcgVectors fv;
   // implicit transport (transport = 1): BiCGStab vectors and scalars
   TrVecs trv{};
+  double* trb[3] = {nullptr, nullptr, nullptr};  // the predictor systems' right-hand sides
   TrScalars* tsc = nullptr;
   Cnn net;             // network at the mesh resolution (learned form only)
   bool has_net_space = false;
@@ -377,6 +378,8 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned, bool trans
     for (double** a : {&x->trv.b, &x->trv.dinv, &x->trv.r, &x->trv.rh, &x->trv.p, &x->trv.v,
                        &x->trv.y, &x->trv.z, &x->trv.t})
       *a = cv.take<double>(nc);
+  if (transport)
+    for (int d = 0; d < nd; ++d) x->trb[d] = cv.take<double>(nc);
   // partials: 7 per workgroup of the iteration kernel's grid; 2 (and 1 for
   // ||b||^2) per workgroup of the set-up kernels' column-tile grid
   const int ns = std::max(iter_grid<double>(make_geo(m)), iter_grid<float>(make_geo(m)));
@@ -1100,17 +1103,19 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
   const Phys& ph = x->ph;
   hipStream_t s = x->stream;
   const bool enth = x->prm.energy_form == 1;
+  const bool implicit = x->prm.transport == 1;
   x->timer.run(5, x->stream, [&] {
-    launch_step1(s, G, ph, S.rho, S.u, S.T, S.pp, S.phi, x->rho_star, x->e0, x->ustar, pp_out);
+    launch_step1(s, G, ph, S.rho, S.u, S.T, S.pp, S.phi, x->rho_star, x->e0, x->ustar, pp_out,
+                 implicit ? x->trb : nullptr);
   });
-  if (x->prm.transport == 1) {
+  if (implicit) {
     // Step 1's momentum predictor implicit: per component from the explicit
-    // predictor's u*
+    // predictor's u*, with the right-hand side Step 1's pass wrote
     for (int d = 0; d < G.ndim; ++d) {
       const TrOp op = momentum_op(x, S, d);
-      x->timer.run(7, x->stream, [&] {
-        launch_tr_setup_mom(s, G, op, S.u[d], x->ustar[d], x->trv, x->partials);
-      });
+      TrVecs v = x->trv;
+      v.b = x->trb[d];
+      x->timer.run(7, x->stream, [&] { launch_tr_setup_mom(s, G, op, x->ustar[d], v, x->partials); });
       int its = 0;
       gea_status rc = bicg_run(x, op, x->ustar[d], &its);
       if (transport_iters) *transport_iters += its;

@@ -13,16 +13,20 @@
 // the cubic face interpolation (-1, 9, 9, -1)/16 with two cells on each
 // side, else the linear mean; there is no convective flux through a wall.
 //
-// Every kernel of an iteration is a grid-stride pass (8.4 M cells: about
-// 2048 workgroups); each stores one partial a workgroup for every dot
-// product it forms, and a one-workgroup kernel sums them in workgroup order
-// (bitwise reproducible) and updates the solver scalars.  All kernels of an
-// iteration return at once when the scalars say the solve is done, so the
-// host enqueues iterations in batches and reads the scalars once a batch.
+// The operator kernels march column tiles through z like the explicit step
+// kernels (the line along z in registers, the x/y neighbours from the
+// caches, the flux of the face below carried from the plane below); the
+// vector updates are grid-stride passes.  Each kernel stores one partial a
+// workgroup for every dot product it forms, and a one-workgroup kernel sums
+// them in workgroup order (bitwise reproducible) and updates the solver
+// scalars.  All kernels of an iteration return at once when the scalars say
+// the solve is done, so the host enqueues iterations in batches and reads
+// the scalars once a batch.
 #include <hip/hip_runtime.h>
 
 #include "gea_internal.h"
 #include "gea_reduce.h"
+#include "gea_stencil.h"
 
 namespace gea {
 namespace {
@@ -62,53 +66,9 @@ __device__ __forceinline__ bool tr_done(const TrScalars* sc) {
   return __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// face value of x between cell P (coordinate q along d, n cells) and P + st
-__device__ __forceinline__ double i4_face(const double* __restrict__ x, int P, int st, int q, int n) {
-  if (q >= 1 && q + 2 <= n - 1)
-    return (-x[P - st] + 9.0 * x[P] + 9.0 * x[P + st] - x[P + 2 * st]) / 16.0;
-  return 0.5 * (x[P] + x[P + st]);
-}
-
 // weight of the face's lower cell (q) or upper cell in its I4 value
 __device__ __forceinline__ double i4_weight(int q, int n) {
   return (q >= 1 && q + 2 <= n - 1) ? 9.0 / 16.0 : 0.5;
-}
-
-// (A x)_P and, when diag is given, the diagonal entry
-template <int NDIM>
-__device__ __forceinline__ double tr_apply(const Geo& G, const TrOpD<NDIM>& op,
-                                           const double* __restrict__ x, int P,
-                                           double* diag = nullptr) {
-  const double xc = x[P];
-  const double c = op.rho_star[P] * op.tcoef;
-  double conv = 0.0, cdiag = 0.0, lap = 0.0, ldiag = 0.0;
-#pragma unroll
-  for (int d = 0; d < NDIM; ++d) {
-    const int st = G.st[d], n = G.n[d], q = (P / st) % n;
-    const double* f = op.phi[d];
-    if (q + 1 < n) {
-      const double fh = f[P];
-      conv += fh * i4_face(x, P, st, q, n);
-      cdiag += fh * i4_weight(q, n);
-      lap += op.k[d] * (xc - x[P + st]);
-      ldiag += op.k[d];
-    } else if (op.wall_comp == d) {
-      lap += 2.0 * op.k[d] * xc;
-      ldiag += 2.0 * op.k[d];
-    }
-    if (q > 0) {
-      const double fl = f[P - st];
-      conv -= fl * i4_face(x, P - st, st, q - 1, n);
-      cdiag -= fl * i4_weight(q - 1, n);
-      lap += op.k[d] * (xc - x[P - st]);
-      ldiag += op.k[d];
-    } else if (op.wall_comp == d) {
-      lap += 2.0 * op.k[d] * xc;
-      ldiag += 2.0 * op.k[d];
-    }
-  }
-  if (diag) *diag = c + op.gamma * cdiag + ldiag;
-  return c * xc + op.gamma * conv + lap;
 }
 
 template <int N>
@@ -121,32 +81,105 @@ __device__ __forceinline__ void store_partials(double (&v)[N], double* part) {
   }
 }
 
+// The operator at cell P of a column (plane k): (A x)_P and its diagonal.
+// zx holds x along the column (k-2..k+2); the x/y lines are loaded here;
+// fz_lo, fz_hi are the fluxes of the faces below and above (0 on a wall).
+template <int NDIM>
+__device__ __forceinline__ double tr_plane(const Geo& G, const TrOpD<NDIM>& op, const Col& c,
+                                           int P, int k, const double* __restrict__ x,
+                                           const Line& zx, double fz_lo, double fz_hi,
+                                           double* diag) {
+  constexpr int Z = NDIM - 1;
+  const int nz = G.n[Z];
+  const double xc = zx.c;
+  const double cP = op.rho_star[P] * op.tcoef;
+  double conv = 0.0, cdiag = 0.0, lap = 0.0, ldiag = 0.0;
+  auto faces = [&](const Line& l, int q, int n, double fh, double fl, double kd, bool wall) {
+    const double wallk = wall ? 2.0 * kd : 0.0;
+    if (q + 1 < n) {
+      conv += fh * i4_hi(l, q, n);
+      cdiag += fh * i4_weight(q, n);
+      lap += kd * (xc - l.p1);
+      ldiag += kd;
+    } else {
+      lap += wallk * xc;
+      ldiag += wallk;
+    }
+    if (q > 0) {
+      conv -= fl * i4_lo(l, q, n);
+      cdiag -= fl * i4_weight(q - 1, n);
+      lap += kd * (xc - l.m1);
+      ldiag += kd;
+    } else {
+      lap += wallk * xc;
+      ldiag += wallk;
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < Z; ++d) {
+    const int st = G.st[d], n = G.n[d], q = coord(c, d);
+    const Line l = line_at([&](int Q) { return x[Q]; }, P, st, q, n);
+    const double fh = op.phi[d][P], fl = op.phi[d][nb(q > 0, P - st, P)];
+    faces(l, q, n, fh, fl, op.k[d], op.wall_comp == d);
+  }
+  faces(zx, k, nz, fz_hi, fz_lo, op.k[Z], op.wall_comp == Z);
+  *diag = cP + op.gamma * cdiag + ldiag;
+  return cP * xc + op.gamma * conv + lap;
+}
+
+// sum_out phi I4(w) at cell P (the explicit part of Step 2's transport)
+template <int NDIM>
+__device__ __forceinline__ double tr_conv(const Geo& G, const TrOpD<NDIM>& op, const Col& c, int P,
+                                          int k, const double* __restrict__ w, const Line& zw,
+                                          double fz_lo, double fz_hi) {
+  constexpr int Z = NDIM - 1;
+  double conv = 0.0;
+#pragma unroll
+  for (int d = 0; d < Z; ++d) {
+    const int st = G.st[d], n = G.n[d], q = coord(c, d);
+    const Line l = line_at([&](int Q) { return w[Q]; }, P, st, q, n);
+    if (q + 1 < n) conv += op.phi[d][P] * i4_hi(l, q, n);
+    if (q > 0) conv -= op.phi[d][P - st] * i4_lo(l, q, n);
+  }
+  const int nz = G.n[Z];
+  if (k + 1 < nz) conv += fz_hi * i4_hi(zw, k, nz);
+  if (k > 0) conv -= fz_lo * i4_lo(zw, k, nz);
+  return conv;
+}
+
 // ---- set-up ------------------------------------------------------------------
 
-// momentum component: b = A u^n + c (x0 - u^n) (= V (rho^n u^n/dt - R(F^n))
-// when x0 is the explicit predictor's u*), r = b - A x0, rh = r, p = v = 0;
-// partials ||b||^2, ||r||^2
+// momentum component: b = V (rho^n u^n/dt - R(F^n)) from the explicit
+// predictor's pass, r = b - A x0, rh = r, p = v = 0, 1/diag; partials
+// ||b||^2, ||r||^2
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_tr_setup_mom(Geo G, TrOpD<NDIM> op,
-                                                         const double* __restrict__ un,
+__global__ __launch_bounds__(kBlock) void k_tr_setup_mom(Geo G, int kc, TrOpD<NDIM> op,
                                                          const double* __restrict__ x0, TrVecs v,
                                                          double* part) {
+  constexpr int Z = NDIM - 1;
+  const Col c = col_of<NDIM>(G, kc);
   double red[2] = {0.0, 0.0};
-  GEA_FOR_CELLS(P, G) {
-    double diag;
-    const double aun = tr_apply<NDIM>(G, op, un, P);
-    const double ax0 = tr_apply<NDIM>(G, op, x0, P, &diag);
-    const double c = op.rho_star[P] * op.tcoef;
-    const double b = aun + c * (x0[P] - un[P]);
-    const double r = b - ax0;
-    v.b[P] = b;
-    v.dinv[P] = 1.0 / diag;
-    v.r[P] = r;
-    v.rh[P] = r;
-    v.p[P] = 0.0;
-    v.v[P] = 0.0;
-    red[0] += b * b;
-    red[1] += r * r;
+  if (c.act) {
+    const int nz = G.n[Z], pl = c.pl;
+    int P = c.base + pl * c.k0;
+    Line zx = line_at([&](int Q) { return x0[Q]; }, P, pl, c.k0, nz);
+    double flo = c.k0 > 0 ? op.phi[Z][P - pl] : 0.0;
+    for (int k = c.k0; k < c.k1; ++k, P += pl) {
+      const double fhi = op.phi[Z][P];
+      const double xn = x0[nb(k + 3 < nz, P + 3 * pl, P)];
+      double diag;
+      const double ax = tr_plane<NDIM>(G, op, c, P, k, x0, zx, flo, fhi, &diag);
+      const double b = v.b[P], r = b - ax;
+      v.dinv[P] = 1.0 / diag;
+      v.r[P] = r;
+      v.rh[P] = r;
+      v.p[P] = 0.0;
+      v.v[P] = 0.0;
+      red[0] += b * b;
+      red[1] += r * r;
+      flo = fhi;
+      zx = shift(zx, k + 3 < nz ? xn : 0.0);
+    }
   }
   store_partials<2>(red, part);
 }
@@ -171,40 +204,47 @@ __global__ __launch_bounds__(kBlock) void k_tr_known(Geo G, Phys ph, Vec<NDIM> u
 // p = v = 0; partials ||b||^2, ||r||^2
 template <int NDIM, bool ENTH>
 __global__ __launch_bounds__(kBlock) void k_tr_setup_energy(
-    Geo G, Phys ph, TrOpD<NDIM> op, const double* __restrict__ rho, const double* __restrict__ e0,
-    const double* __restrict__ w, const double* __restrict__ Tn, const double* __restrict__ Tbg,
-    double* __restrict__ x, TrVecs v, double* part) {
+    Geo G, Phys ph, int kc, TrOpD<NDIM> op, const double* __restrict__ rho,
+    const double* __restrict__ e0, const double* __restrict__ w, const double* __restrict__ Tn,
+    const double* __restrict__ Tbg, double* __restrict__ x, TrVecs v, double* part) {
   constexpr int Z = NDIM - 1;
+  const Col c = col_of<NDIM>(G, kc);
   double red[2] = {0.0, 0.0};
-  const double kcoef = ph.mu / ph.Pr * ph.cp;
-  const double kdz = kcoef * G.S[Z] / G.h[Z];
-  GEA_FOR_CELLS(P, G) {
-    const double rs = op.rho_star[P];
-    const double local = ENTH ? G.V / ph.dt * e0[P] : G.V / ph.dt * (rho[P] * e0[P] - rs * w[P]);
-    double convw = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-      const int st = G.st[d], n = G.n[d], q = (P / st) % n;
-      if (q + 1 < n) convw += op.phi[d][P] * i4_face(w, P, st, q, n);
-      if (q > 0) convw -= op.phi[d][P - st] * i4_face(w, P - st, st, q - 1, n);
+  if (c.act) {
+    const int nz = G.n[Z], pl = c.pl;
+    const double kdz = op.k[Z];   // (mu/Pr) c_p S_z/h_z
+    int P = c.base + pl * c.k0;
+    Line zT = line_at([&](int Q) { return Tn[Q]; }, P, pl, c.k0, nz);
+    Line zw = line_at([&](int Q) { return w[Q]; }, P, pl, c.k0, nz);
+    double flo = c.k0 > 0 ? op.phi[Z][P - pl] : 0.0;
+    for (int k = c.k0; k < c.k1; ++k, P += pl) {
+      const double fhi = op.phi[Z][P];
+      const int Pn = nb(k + 3 < nz, P + 3 * pl, P);
+      const double Tnext = Tn[Pn], wnext = w[Pn];
+      const double rs = op.rho_star[P];
+      const double local = ENTH ? G.V / ph.dt * e0[P] : G.V / ph.dt * (rho[P] * e0[P] - rs * zw.c);
+      const double convw = tr_conv<NDIM>(G, op, c, P, k, w, zw, flo, fhi);
+      double bg = 0.0;
+      if (k + 1 < nz) bg += kdz * (Tbg[k] - Tbg[k + 1]);
+      if (k > 0) bg += kdz * (Tbg[k] - Tbg[k - 1]);
+      const double b = local - convw + bg;
+      double diag;
+      const double ax = tr_plane<NDIM>(G, op, c, P, k, Tn, zT, flo, fhi, &diag);
+      const double r = b - ax;
+      x[P] = zT.c;
+      v.b[P] = b;
+      v.dinv[P] = 1.0 / diag;
+      v.r[P] = r;
+      v.rh[P] = r;
+      v.p[P] = 0.0;
+      v.v[P] = 0.0;
+      red[0] += b * b;
+      red[1] += r * r;
+      flo = fhi;
+      const bool more = k + 3 < nz;
+      zT = shift(zT, more ? Tnext : 0.0);
+      zw = shift(zw, more ? wnext : 0.0);
     }
-    const int k = P / G.st[Z], nz = G.n[Z];
-    double bg = 0.0;
-    if (k + 1 < nz) bg += kdz * (Tbg[k] - Tbg[k + 1]);
-    if (k > 0) bg += kdz * (Tbg[k] - Tbg[k - 1]);
-    const double b = local - convw + bg;
-    double diag;
-    const double ax = tr_apply<NDIM>(G, op, Tn, P, &diag);
-    const double r = b - ax;
-    x[P] = Tn[P];
-    v.b[P] = b;
-    v.dinv[P] = 1.0 / diag;
-    v.r[P] = r;
-    v.rh[P] = r;
-    v.p[P] = 0.0;
-    v.v[P] = 0.0;
-    red[0] += b * b;
-    red[1] += r * r;
   }
   store_partials<2>(red, part);
 }
@@ -222,18 +262,46 @@ __global__ __launch_bounds__(kBlock) void k_tr_dir(int nc, TrVecs v, const TrSca
   }
 }
 
-// v = A y; partial <rh, v>
-template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_tr_matvec_v(Geo G, TrOpD<NDIM> op, TrVecs v,
-                                                        const TrScalars* sc, double* part) {
+// out = A in (TWO = 0: v = A y, partial <rh, v>; TWO = 1: t = A z, partials
+// <t, s>, <t, t> with s in r)
+template <int NDIM, int TWO>
+__global__ __launch_bounds__(kBlock) void k_tr_matvec(Geo G, int kc, TrOpD<NDIM> op,
+                                                      const double* __restrict__ in,
+                                                      double* __restrict__ out,
+                                                      const double* __restrict__ dv,
+                                                      const TrScalars* sc, double* part) {
   if (tr_done(sc)) return;
-  double red[1] = {0.0};
-  GEA_FOR_CELLS(P, G) {
-    const double av = tr_apply<NDIM>(G, op, v.y, P);
-    v.v[P] = av;
-    red[0] += v.rh[P] * av;
+  constexpr int Z = NDIM - 1;
+  const Col c = col_of<NDIM>(G, kc);
+  double red[2] = {0.0, 0.0};
+  if (c.act) {
+    const int nz = G.n[Z], pl = c.pl;
+    int P = c.base + pl * c.k0;
+    Line zx = line_at([&](int Q) { return in[Q]; }, P, pl, c.k0, nz);
+    double flo = c.k0 > 0 ? op.phi[Z][P - pl] : 0.0;
+    for (int k = c.k0; k < c.k1; ++k, P += pl) {
+      const double fhi = op.phi[Z][P];
+      const double xn = in[nb(k + 3 < nz, P + 3 * pl, P)];
+      const double d = dv[P];
+      double diag;
+      const double a = tr_plane<NDIM>(G, op, c, P, k, in, zx, flo, fhi, &diag);
+      out[P] = a;
+      if (TWO) {
+        red[0] += a * d;
+        red[1] += a * a;
+      } else {
+        red[0] += d * a;
+      }
+      flo = fhi;
+      zx = shift(zx, k + 3 < nz ? xn : 0.0);
+    }
   }
-  store_partials<1>(red, part);
+  if (TWO) {
+    store_partials<2>(red, part);
+  } else {
+    double one[1] = {red[0]};
+    store_partials<1>(one, part);
+  }
 }
 
 // x += alpha y, s = r - alpha v (into r), z = dinv s; partial ||s||^2
@@ -250,21 +318,6 @@ __global__ __launch_bounds__(kBlock) void k_tr_half(int nc, double* __restrict__
     red[0] += s * s;
   }
   store_partials<1>(red, part);
-}
-
-// t = A z; partials <t, s>, <t, t>
-template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_tr_matvec_t(Geo G, TrOpD<NDIM> op, TrVecs v,
-                                                        const TrScalars* sc, double* part) {
-  if (tr_done(sc)) return;
-  double red[2] = {0.0, 0.0};
-  GEA_FOR_CELLS(P, G) {
-    const double t = tr_apply<NDIM>(G, op, v.z, P);
-    v.t[P] = t;
-    red[0] += t * v.r[P];
-    red[1] += t * t;
-  }
-  store_partials<2>(red, part);
 }
 
 // x += omega z, r = s - omega t; partials <rh, r>, ||r||^2
@@ -399,13 +452,13 @@ __global__ __launch_bounds__(kBlock) void k_tr_end(const double* part, int nb, T
 
 // ---- launchers ---------------------------------------------------------------
 
-void launch_tr_setup_mom(hipStream_t s, const Geo& G, const TrOp& op, const double* un,
-                         const double* x0, const TrVecs& v, double* part) {
-  const int gb = grid_for(G.nc);
+void launch_tr_setup_mom(hipStream_t s, const Geo& G, const TrOp& op, const double* x0,
+                         const TrVecs& v, double* part) {
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_tr_setup_mom<2>, dim3(gb), dim3(kBlock), 0, s, G, dev_op<2>(op), un, x0, v, part);
+    hipLaunchKernelGGL(k_tr_setup_mom<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, zp.kc, dev_op<2>(op), x0, v, part);
   else
-    hipLaunchKernelGGL(k_tr_setup_mom<3>, dim3(gb), dim3(kBlock), 0, s, G, dev_op<3>(op), un, x0, v, part);
+    hipLaunchKernelGGL(k_tr_setup_mom<3>, dim3(zp.blocks), dim3(kBlock), 0, s, G, zp.kc, dev_op<3>(op), x0, v, part);
 }
 
 void launch_tr_setup_energy(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const TrOp& op,
@@ -413,44 +466,47 @@ void launch_tr_setup_energy(hipStream_t s, const Geo& G, const Phys& ph, bool en
                             double* w, const double* Tn, const double* Tbg, double* x,
                             const TrVecs& v, double* part) {
   const int gb = grid_for(G.nc);
+  const ZPlan zp = zplan(G);
   if (G.ndim == 2) {
     hipLaunchKernelGGL(k_tr_known<2>, dim3(gb), dim3(kBlock), 0, s, G, ph, uvec<2>(u_star), (int)enth, w);
     if (enth)
-      hipLaunchKernelGGL((k_tr_setup_energy<2, true>), dim3(gb), dim3(kBlock), 0, s, G, ph, dev_op<2>(op), rho, e0, (const double*)w, Tn, Tbg, x, v, part);
+      hipLaunchKernelGGL((k_tr_setup_energy<2, true>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, dev_op<2>(op), rho, e0, (const double*)w, Tn, Tbg, x, v, part);
     else
-      hipLaunchKernelGGL((k_tr_setup_energy<2, false>), dim3(gb), dim3(kBlock), 0, s, G, ph, dev_op<2>(op), rho, e0, (const double*)w, Tn, Tbg, x, v, part);
+      hipLaunchKernelGGL((k_tr_setup_energy<2, false>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, dev_op<2>(op), rho, e0, (const double*)w, Tn, Tbg, x, v, part);
   } else {
     hipLaunchKernelGGL(k_tr_known<3>, dim3(gb), dim3(kBlock), 0, s, G, ph, uvec<3>(u_star), (int)enth, w);
     if (enth)
-      hipLaunchKernelGGL((k_tr_setup_energy<3, true>), dim3(gb), dim3(kBlock), 0, s, G, ph, dev_op<3>(op), rho, e0, (const double*)w, Tn, Tbg, x, v, part);
+      hipLaunchKernelGGL((k_tr_setup_energy<3, true>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, dev_op<3>(op), rho, e0, (const double*)w, Tn, Tbg, x, v, part);
     else
-      hipLaunchKernelGGL((k_tr_setup_energy<3, false>), dim3(gb), dim3(kBlock), 0, s, G, ph, dev_op<3>(op), rho, e0, (const double*)w, Tn, Tbg, x, v, part);
+      hipLaunchKernelGGL((k_tr_setup_energy<3, false>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, dev_op<3>(op), rho, e0, (const double*)w, Tn, Tbg, x, v, part);
   }
 }
 
 void launch_tr_start(hipStream_t s, const Geo& G, const double* part, double tol, int max_iter,
                      TrScalars* sc) {
-  hipLaunchKernelGGL(k_tr_start, dim3(1), dim3(kBlock), 0, s, part, grid_for(G.nc), tol, max_iter, sc);
+  hipLaunchKernelGGL(k_tr_start, dim3(1), dim3(kBlock), 0, s, part, zplan(G).blocks, tol, max_iter, sc);
 }
 
 void launch_tr_iteration(hipStream_t s, const Geo& G, const TrOp& op, double* x, const TrVecs& v,
                          double* part, TrScalars* sc) {
   const int gb = grid_for(G.nc);
-  const dim3 grid(gb), block(kBlock);
-  hipLaunchKernelGGL(k_tr_dir, grid, block, 0, s, G.nc, v, (const TrScalars*)sc);
+  const ZPlan zp = zplan(G);
+  const dim3 grid(gb), block(kBlock), zgrid(zp.blocks);
+  const TrScalars* csc = sc;
+  hipLaunchKernelGGL(k_tr_dir, grid, block, 0, s, G.nc, v, csc);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_tr_matvec_v<2>, grid, block, 0, s, G, dev_op<2>(op), v, (const TrScalars*)sc, part);
+    hipLaunchKernelGGL((k_tr_matvec<2, 0>), zgrid, block, 0, s, G, zp.kc, dev_op<2>(op), (const double*)v.y, v.v, (const double*)v.rh, csc, part);
   else
-    hipLaunchKernelGGL(k_tr_matvec_v<3>, grid, block, 0, s, G, dev_op<3>(op), v, (const TrScalars*)sc, part);
-  hipLaunchKernelGGL(k_tr_alpha, dim3(1), block, 0, s, (const double*)part, gb, sc);
-  hipLaunchKernelGGL(k_tr_half, grid, block, 0, s, G.nc, x, v, (const TrScalars*)sc, part);
+    hipLaunchKernelGGL((k_tr_matvec<3, 0>), zgrid, block, 0, s, G, zp.kc, dev_op<3>(op), (const double*)v.y, v.v, (const double*)v.rh, csc, part);
+  hipLaunchKernelGGL(k_tr_alpha, dim3(1), block, 0, s, (const double*)part, zp.blocks, sc);
+  hipLaunchKernelGGL(k_tr_half, grid, block, 0, s, G.nc, x, v, csc, part);
   hipLaunchKernelGGL(k_tr_half_check, dim3(1), block, 0, s, (const double*)part, gb, sc);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_tr_matvec_t<2>, grid, block, 0, s, G, dev_op<2>(op), v, (const TrScalars*)sc, part);
+    hipLaunchKernelGGL((k_tr_matvec<2, 1>), zgrid, block, 0, s, G, zp.kc, dev_op<2>(op), (const double*)v.z, v.t, (const double*)v.r, csc, part);
   else
-    hipLaunchKernelGGL(k_tr_matvec_t<3>, grid, block, 0, s, G, dev_op<3>(op), v, (const TrScalars*)sc, part);
-  hipLaunchKernelGGL(k_tr_omega, dim3(1), block, 0, s, (const double*)part, gb, sc);
-  hipLaunchKernelGGL(k_tr_update, grid, block, 0, s, G.nc, x, v, (const TrScalars*)sc, part);
+    hipLaunchKernelGGL((k_tr_matvec<3, 1>), zgrid, block, 0, s, G, zp.kc, dev_op<3>(op), (const double*)v.z, v.t, (const double*)v.r, csc, part);
+  hipLaunchKernelGGL(k_tr_omega, dim3(1), block, 0, s, (const double*)part, zp.blocks, sc);
+  hipLaunchKernelGGL(k_tr_update, grid, block, 0, s, G.nc, x, v, csc, part);
   hipLaunchKernelGGL(k_tr_end, dim3(1), block, 0, s, (const double*)part, gb, sc);
 }
 

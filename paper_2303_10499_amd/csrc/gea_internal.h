@@ -97,7 +97,8 @@ void launch_clear_wall_faces(hipStream_t s, const Geo& G, double* const* phi);
 // solve's initial guess)
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
-                  double* rho_star, double* e0, double* const* u_star, double* pp_copy);
+                  double* rho_star, double* e0, double* const* u_star, double* pp_copy,
+                  double* const* b_out = nullptr);  // b_out: implicit transport's V (rho u/dt - R(F))
 // Step 2, one sweep: the right-hand side b, coefficient c and 1/diag of the
 // implicit-diffusion system for T, the initial guess x = T_prev, and the
 // solve's set-up (r = b - A x, p0 = 0, partials <r, r/diag>, ||r||^2 in
@@ -256,12 +257,12 @@ struct TrScalars {
   double bb, rr, rr0, rho, rho_old, alpha, omega, beta, tol2;
   int iter, max_iter, status, done;  // status 0 ok, -4 no convergence or breakdown, -5 non-finite
 };
-// set-up of a momentum component (x0: the initial guess, u^n: the old
-// component; b = A u^n + c (x0 - u^n)) or of the energy solve (writes the
-// known transported part into w and T^n into x); each stores 2 partials a
-// workgroup (grid_for(nc) workgroups) for launch_tr_start
-void launch_tr_setup_mom(hipStream_t s, const Geo& G, const TrOp& op, const double* un,
-                         const double* x0, const TrVecs& v, double* part);
+// set-up of a momentum component (x0: the initial guess; v.b the right-hand
+// side V (rho^n u^n/dt - R(F^n)) from Step 1's pass) or of the energy solve
+// (writes the known transported part into w and T^n into x); each stores 2
+// partials a workgroup (zplan(G).blocks workgroups) for launch_tr_start
+void launch_tr_setup_mom(hipStream_t s, const Geo& G, const TrOp& op, const double* x0,
+                         const TrVecs& v, double* part);  // v.b: the component's right-hand side
 void launch_tr_setup_energy(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const TrOp& op,
                             const double* rho, const double* e0, double* const* u_star,
                             double* w, const double* Tn, const double* Tbg, double* x,

@@ -10,6 +10,7 @@
 // computed once and carried to the cell above, so the flux leaving one cell
 // is bitwise the flux entering the other and the divergence telescopes.
 #include "gea_reduce.h"
+#include "gea_stencil.h"
 
 namespace gea {
 
@@ -26,48 +27,6 @@ __device__ __forceinline__ double phi_face(const Geo& G, const Phys& ph, int d, 
   return d == NDIM - 1 ? ph.g * (cq + 1.0) * G.dz : phi_cell(G, ph, kz);
 }
 
-
-// Five consecutive values of a cell field along one direction, centred on
-// the cell.  Positions outside the mesh hold the centre value (their load is
-// clamped to the cell itself) and are never used.
-struct Line {
-  double m2, m1, c, p1, p2;
-};
-
-// Index of a neighbour if it exists, else of the cell itself.  Every load of
-// a plane is then made unconditionally from inside the mesh and each wall
-// test is a select on loaded values: no branch separates a plane's loads, so
-// they are all in flight together.
-__device__ __forceinline__ int nb(bool ok, int Q, int P) { return ok ? Q : P; }
-
-template <typename F>
-__device__ __forceinline__ Line line_at(F s, int P, int st, int q, int n) {
-  Line L;
-  L.m2 = s(nb(q >= 2, P - 2 * st, P));
-  L.m1 = s(nb(q >= 1, P - st, P));
-  L.c = s(P);
-  L.p1 = s(nb(q + 1 < n, P + st, P));
-  L.p2 = s(nb(q + 2 < n, P + 2 * st, P));
-  return L;
-}
-
-// next plane: drop the lowest value, append the one two planes above
-__device__ __forceinline__ Line shift(const Line& L, double next) {
-  return Line{L.m1, L.c, L.p1, L.p2, next};
-}
-
-// interp4 on the face above (q + 1/2) and below (q - 1/2) the centre of a
-// line; linear next to a wall
-__device__ __forceinline__ double i4_hi(const Line& s, int q, int n) {
-  const double f4 = (-s.m1 + 9.0 * s.c + 9.0 * s.p1 - s.p2) / 16.0;
-  const double f2 = 0.5 * (s.c + s.p1);
-  return (q >= 1 && q + 2 <= n - 1) ? f4 : f2;
-}
-__device__ __forceinline__ double i4_lo(const Line& s, int q, int n) {
-  const double f4 = (-s.m2 + 9.0 * s.m1 + 9.0 * s.c - s.p1) / 16.0;
-  const double f2 = 0.5 * (s.m1 + s.c);
-  return (q >= 2 && q + 1 <= n - 1) ? f4 : f2;
-}
 
 // mu snGrad(u_comp) S on the two faces of a line; walls normal to the line
 // hold the normal component at 0 and leave the tangential ones free
@@ -190,7 +149,8 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
                                                         const double* __restrict__ pp,
                                                         const double* __restrict__ rho_star,
                                                         Vec<NDIM> phi, Vec<NDIM> u_star,
-                                                        double* __restrict__ pp_copy) {
+                                                        double* __restrict__ pp_copy,
+                                                        Vec<NDIM> b_out) {
   constexpr int Z = NDIM - 1;
   const Col c = col_of<NDIM>(G, kc);
   if (!c.act) return;
@@ -275,6 +235,8 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
       }
       const double mom = r * z[cc].c - ph.dt / G.V * (conv - visc) - ph.dt * RF;
       us[cc] = mom * inv_rs;
+      // implicit transport: the predictor system's right-hand side V (rho u/dt - R(F))
+      if (b_out.p[0]) b_out.p[cc][P] = G.V * (r * z[cc].c / ph.dt - RF);
     }
 #pragma unroll
     for (int cc = 0; cc < NDIM; ++cc) {
@@ -299,7 +261,7 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
                                                     const double* __restrict__ pp, Vec<3> phi,
                                                     double* __restrict__ rho_star,
                                                     double* __restrict__ e0, Vec<3> u_star,
-                                                    double* __restrict__ pp_copy) {
+                                                    double* __restrict__ pp_copy, Vec<3> b_out) {
   using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   __shared__ double su[2][5][HP];  // u (3 components), p', rho
@@ -419,6 +381,8 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
       }
       const double mom = r * z[cc].c - ph.dt / G.V * (conv - visc) - ph.dt * RF;
       us[cc] = mom * inv_rs;
+      // implicit transport: the predictor system's right-hand side V (rho u/dt - R(F))
+      if (b_out.p[0] && c.act) b_out.p[cc][qo + pl * k] = G.V * (r * z[cc].c / ph.dt - RF);
     }
     if (c.act) {
       const int P = qo + pl * k;
@@ -1716,15 +1680,18 @@ void launch_clear_wall_faces(hipStream_t s, const Geo& G, double* const* phi) {
 
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
-                  double* rho_star, double* e0, double* const* u_star, double* pp_copy) {
+                  double* rho_star, double* e0, double* const* u_star, double* pp_copy,
+                  double* const* b_out) {
+  double* const nob[3] = {nullptr, nullptr, nullptr};
+  double* const* bo = b_out ? b_out : nob;
   if (G.ndim == 2) {
     const ZPlan zp = zplan(G);
     hipLaunchKernelGGL(k_density_predictor<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
-    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star), pp_copy);
+    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star), pp_copy, V2(bo));
     return;
   }
   const ZPlan zp3 = zplan3(G, kTyStep1, kKcStep1);
-  hipLaunchKernelGGL(k_step1_3<kTyStep1>, dim3(zp3.blocks), dim3(64 * kTyStep1), 0, s, G, ph, zp3.kc, rho, V3(u), T, pp, V3(phi), rho_star, e0, V3(u_star), pp_copy);
+  hipLaunchKernelGGL(k_step1_3<kTyStep1>, dim3(zp3.blocks), dim3(64 * kTyStep1), 0, s, G, ph, zp3.kc, rho, V3(u), T, pp, V3(phi), rho_star, e0, V3(u_star), pp_copy, V3(bo));
 }
 
 int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* rho,

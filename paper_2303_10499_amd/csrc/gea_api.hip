@@ -228,9 +228,11 @@ struct gea_ctx {
   int it_probe = 0;   // batch length recorded between ev_it, 0: none
   int it_probe_iter0 = 0;
   KernelTimer timer;
-  int last_iters64 = 0;  // iterations of the previous solve: first batch length
+  // iterations of the previous step's solve of the same corrector (and
+  // refinement step): the first batch's length
+  int last_iters64[8] = {};
   int last_iters_energy[8] = {};  // of the previous step's energy solves, per sweep
-  int last_iters32 = 0;
+  int last_iters32[8][4] = {};
   int last_iters_res = 0;  // iterations of the last Jacobi-PCG resumed after the network
   bool has_state = false;
   bool hist[2] = {false, false};  // st[i].pm, st[i].Km hold the state's history
@@ -669,7 +671,8 @@ gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
     out->status = GEA_OK;
     return GEA_OK;
   }
-  const int first = x->last_iters64 > 0 ? (int)(0.9 * x->last_iters64) : 0;
+  int& last64 = x->last_iters64[x->corr < 8 ? x->corr : 7];
+  const int first = last64 > 0 ? (int)(0.9 * last64) : 0;
   gea_status rc = run_cg(
       x, x->sc, hs, x->prm.max_iter, first,
       [&](int j) {
@@ -677,7 +680,7 @@ gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
         x->timer.run(1, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
       });
   if (rc != GEA_OK) return rc;
-  x->last_iters64 = hs.iter;
+  last64 = hs.iter;
   out->iters = hs.iter;
   out->outer_iters = 0;
   out->rel_res = std::sqrt(hs.rr / hs.bb);
@@ -729,7 +732,8 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->status = GEA_ERR_NOCONV;
       break;
     }
-    const int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
+    int& last32 = x->last_iters32[x->corr < 8 ? x->corr : 7][outer < 3 ? outer : 3];
+    const int first = last32 > 0 ? (int)(0.9 * last32) : 0;
     gea_status rc = run_cg(
         x, x->sc32, h32, budget, first,
         [&](int j) {
@@ -738,7 +742,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
         },
         Extra{}, 0, x->prm.solver == GEA_LEARNED_MIXED);
     if (rc != GEA_OK) return rc;
-    if (outer == 0) x->last_iters32 = h32.iter;
+    last32 = h32.iter;
     total += h32.iter;
     ++outer;
     if (h32.status == -5) {
@@ -949,7 +953,8 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
     int done_iters = 0;
     FcgScalars hf{};
     Extra fcg;  // the flexible-CG scalars, read along with the CG's
-    int first = x->last_iters32 > 0 ? (int)(0.9 * x->last_iters32) : 0;
+    const int last32 = x->last_iters32[x->corr < 8 ? x->corr : 7][outer < 3 ? outer : 3];
+    int first = last32 > 0 ? (int)(0.9 * last32) : 0;
     if (use_net) {
       learned_then_resume(budget > 0 ? budget : 1);
       use_net = false;

@@ -372,6 +372,25 @@ def test_full_size_3d_step_matches_oracle(oracle_lib, gea_mod):
     print("full-size 3D step, per-field relative error:", errs)
 
 
+def test_full_size_3d_paper_scheme_step_matches_oracle(oracle_lib, gea_mod):
+    """bubble3d_256x256x128 at full size with the paper's scheme for Steps 1-2:
+    the enthalpy form (eq. step3_sd) and implicit transport solved by
+    BiCGStab; one step against the oracle (its all-core build: the same bits
+    as the single-threaded one) with FP64 Jacobi-PCG"""
+    cfg = configs.get("bubble3d_256x256x128", tol=1e-13, max_iter=100000, energy_form=1, transport=1)
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"], omp=True)
+    s = O.init_bubble(**cfg["bubble"])
+    S = gea_mod.Solver(cfg["mesh"], cfg["params"])
+    S.init_bubble(**cfg["bubble"])
+    O.step(s, 1)
+    st = S.step(1)
+    assert st.steps_done == 1 and st.transport_iters >= 4
+    errs = compare(S, s, 1e-10, cfg, 1)
+    p_old, K_old = S.history()
+    assert rel(p_old, s.p_old) <= 1e-13
+    print("full-size 3D step, enthalpy form + implicit transport, per-field error:", errs)
+
+
 def test_full_size_3d_mixed_error_per_field(oracle_lib, gea_mod):
     """the refinement form on the full 3D mesh at the benchmark's tolerance
     (1e-8): its error against the tightly solved FP64 oracle, per field, is

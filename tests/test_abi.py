@@ -106,3 +106,28 @@ def test_static_solve_argument_errors(L):
     assert L.gea_pressure_solve_static(C.byref(ok), p, p, p, p, 0.0, 100, None, C.byref(st)) == gea.ERR_ARG
     neg = gea.Mesh(0, 1, 32, 1.0, 1.0, 1.0)
     assert L.gea_pressure_solve_static(C.byref(neg), p, p, p, p, 1e-8, 100, None, C.byref(st)) == gea.ERR_ARG
+
+
+def test_scheme_variants_and_state_entry_points_without_a_gpu(L):
+    """energy_form and transport take 0 or 1; implicit transport adds its
+    BiCGStab vectors (9) and the predictors' right-hand sides (ndim) to the
+    workspace; the state entry points reject a null context or pointer"""
+    from paper_2303_10499_amd import configs, gea
+    cfg = configs.get("bubble3d_256x256x128")
+    m = gea.make_mesh(cfg["mesh"])
+    n0, n1 = C.c_size_t(0), C.c_size_t(0)
+    p0 = gea.make_params(dict(cfg["params"], transport=0))
+    p1 = gea.make_params(dict(cfg["params"], transport=1))
+    assert L.gea_workspace_bytes(C.byref(m), C.byref(p0), C.byref(n0)) == gea.OK
+    assert L.gea_workspace_bytes(C.byref(m), C.byref(p1), C.byref(n1)) == gea.OK
+    nc = 256 * 256 * 128
+    assert n1.value - n0.value >= (9 + 3) * 8 * nc
+    for bad in (dict(energy_form=2), dict(transport=-1)):
+        pb = gea.make_params(dict(cfg["params"], **bad))
+        assert L.gea_workspace_bytes(C.byref(m), C.byref(pb), C.byref(n0)) == gea.ERR_ARG
+        assert re.search(rb"energy_form|transport", L.gea_last_error(None))
+    buf = (C.c_double * 4)()
+    p = C.cast(buf, C.c_void_p)
+    assert L.gea_set_face_flux(None, p, gea.HOST) == gea.ERR_ARG
+    assert L.gea_set_history(None, p, p, gea.HOST) == gea.ERR_ARG
+    assert L.gea_state_extrema(None, None) == gea.ERR_ARG

@@ -248,9 +248,9 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
   }
 }
 
-// Step 1 on a 3D mesh in one pass, with the x/y neighbourhoods of u, p' and
-// rho staged in LDS and the next plane's loads in flight while a plane is
-// computed: k_density_predictor's rho* and e^n from the state's face flux,
+// Step 1 on a 3D mesh in one pass, with the x/y neighbourhoods of u (two
+// cells, for I4) and of p' and rho (one cell, for the force) staged in LDS
+// and the next plane's loads in flight while a plane is computed: k_density_predictor's rho* and e^n from the state's face flux,
 // then k_mom_predict's momentum predictor.  The predictor takes the own
 // cell's six face fluxes and rho*.  Same formulas and order as the two
 // kernels.
@@ -263,15 +263,19 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
                                                     double* __restrict__ e0, Vec<3> u_star,
                                                     double* __restrict__ pp_copy, Vec<3> b_out) {
   using St = Stage3<2, TY>;
+  using St1 = Stage3<1, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
-  __shared__ double su[2][5][HP];  // u (3 components), p', rho
+  constexpr int HP1 = St1::HP, HX1 = St1::HX, NU1 = St1::NU;
+  __shared__ double su[2][3][HP];   // u (3 components): two-cell halo (I4)
+  __shared__ double sq[2][2][HP1];  // p', rho: one-cell halo (the force)
   const Col c = col_of3<TY>(G, kc);
   const St st = stage3<2, TY>(G, c);
-  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
+  const St1 st1 = stage3<1, TY>(G, c);
+  const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho, ho1 = st1.ho;
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
   // staged values of the plane in flight
-  double fs[5][NU];
+  double fs[3][NU], fq[2][NU1];
   auto fetch = [&](int kk) {
     const int o = pl * kk;
 #pragma unroll
@@ -279,8 +283,12 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
       const int Q = st.q[m] + o;
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) fs[cc][m] = u.p[cc][Q];
-      fs[3][m] = pp[Q];
-      fs[4][m] = rho[Q];
+    }
+#pragma unroll
+    for (int m = 0; m < NU1; ++m) {
+      const int Q = st1.q[m] + o;
+      fq[0][m] = pp[Q];
+      fq[1][m] = rho[Q];
     }
   };
   Line z[3];       // u along z (momentum)
@@ -305,10 +313,15 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
   for (int k = c.k0; k < c.k1; ++k) {
     const int sl = k & 1;
 #pragma unroll
-    for (int f = 0; f < 5; ++f)
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
       for (int m = 0; m < NU; ++m)
         if (st.has[m]) su[sl][f][st.h[m]] = fs[f][m];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int m = 0; m < NU1; ++m)
+        if (st1.has[m]) sq[sl][f][st1.h[m]] = fq[f][m];
     // the own cell's values of this plane, loaded before the next plane's
     // staging loads (so waiting for them does not wait for those)
     const int P0 = qo + pl * k;
@@ -322,9 +335,9 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
     fetch(k + 1 < c.k1 ? k + 1 : k);
     lds_barrier();
     const bool up = k + 1 < nz;
-    const double* Sp = su[sl][3];
-    const double* Sr = su[sl][4];
-    const double r = Sr[ho], pc = Sp[ho];
+    const double* Sp = sq[sl][0];
+    const double* Sr = sq[sl][1];
+    const double r = Sr[ho1], pc = Sp[ho1];
     // the state's flux through the faces of the cell, rho*, e^n
     double sum = 0.0, fhi[2], flod[2];
 #pragma unroll
@@ -373,10 +386,10 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
       if (cc == Z) {
         RF = 0.5 * (Flo + Fhi);
       } else {
-        const int n = G.n[cc], q = coord(c, cc), sd = cc == 0 ? 1 : HX;
+        const int n = G.n[cc], q = coord(c, cc), sd = cc == 0 ? 1 : HX1;
         const double phf = phi_cell(G, ph, k);
-        const double hi = q + 1 < n ? force_val(pc, Sp[ho + sd], r, Sr[ho + sd], phf, G.inv_h[cc]) : 0.0;
-        const double lo = q > 0 ? force_val(Sp[ho - sd], pc, Sr[ho - sd], r, phf, G.inv_h[cc]) : 0.0;
+        const double hi = q + 1 < n ? force_val(pc, Sp[ho1 + sd], r, Sr[ho1 + sd], phf, G.inv_h[cc]) : 0.0;
+        const double lo = q > 0 ? force_val(Sp[ho1 - sd], pc, Sr[ho1 - sd], r, phf, G.inv_h[cc]) : 0.0;
         RF = 0.5 * (lo + hi);
       }
       const double mom = r * z[cc].c - ph.dt / G.V * (conv - visc) - ph.dt * RF;

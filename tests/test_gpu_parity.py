@@ -372,6 +372,22 @@ def test_full_size_3d_step_matches_oracle(oracle_lib, gea_mod):
     print("full-size 3D step, per-field relative error:", errs)
 
 
+def test_full_size_384x384x192_step_matches_oracle(oracle_lib, gea_mod):
+    """bubble3d_384x384x192 (28.3 M cells, the largest 3D workload): one step
+    with FP64 Jacobi-PCG against the oracle's all-core build (the same bits
+    as the single-threaded one), every field and the face flux"""
+    cfg = configs.get("bubble3d_384x384x192", tol=1e-13, max_iter=100000)
+    O = oracle_lib.Oracle(cfg["mesh"], cfg["params"], omp=True)
+    s = O.init_bubble(**cfg["bubble"])
+    S = gea_mod.Solver(cfg["mesh"], cfg["params"])
+    S.init_bubble(**cfg["bubble"])
+    O.step(s, 1)
+    st = S.step(1)
+    assert st.steps_done == 1
+    errs = compare(S, s, 1e-10, cfg, 1)
+    print("full-size 384x384x192 step, per-field relative error:", errs)
+
+
 def test_full_size_3d_paper_scheme_step_matches_oracle(oracle_lib, gea_mod):
     """bubble3d_256x256x128 at full size with the paper's scheme for Steps 1-2:
     the enthalpy form (eq. step3_sd) and implicit transport solved by

@@ -248,12 +248,15 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
   }
 }
 
-// Step 1 on a 3D mesh in one pass, with the x/y neighbourhoods of u (two
-// cells, for I4) and of p' and rho (one cell, for the force) staged in LDS
-// and the next plane's loads in flight while a plane is computed: k_density_predictor's rho* and e^n from the state's face flux,
-// then k_mom_predict's momentum predictor.  The predictor takes the own
-// cell's six face fluxes and rho*.  Same formulas and order as the two
-// kernels.
+// Step 1 on a 3D mesh in one pass: k_density_predictor's rho* and e^n from
+// the state's face flux, then k_mom_predict's momentum predictor, which
+// takes the own cell's six face fluxes and rho*.  Same formulas and order as
+// the two kernels.  The x/y neighbourhoods of u (two cells, for I4) and of p'
+// and rho (one cell, for the force) are staged in rings of three LDS planes
+// filled three planes ahead of the plane computed; the staged own values of
+// plane k + 2 feed the register lines of u along z, and those of plane k + 1
+// the force on the face above, so each value is loaded from HBM once a chunk
+// (as in k_H3).
 template <int TY>
 __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
                                                     const double* __restrict__ rho, Vec<3> u,
@@ -266,32 +269,60 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
   using St1 = Stage3<1, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
   constexpr int HP1 = St1::HP, HX1 = St1::HX, NU1 = St1::NU;
-  __shared__ double su[2][3][HP];   // u (3 components): two-cell halo (I4)
-  __shared__ double sq[2][2][HP1];  // p', rho: one-cell halo (the force)
+  __shared__ double su[3][3][HP];   // u (3 components): two-cell halo (I4)
+  __shared__ double sq[3][2][HP1];  // p', rho: one-cell halo (the force)
   const Col c = col_of3<TY>(G, kc);
   const St st = stage3<2, TY>(G, c);
   const St1 st1 = stage3<1, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho, ho1 = st1.ho;
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
-  // staged values of the plane in flight
-  double fs[3][NU], fq[2][NU1];
-  auto fetch = [&](int kk) {
-    const int o = pl * kk;
+  // highest plane the chunk reads; planes above the chunk are loaded for the
+  // own column only (the halo slots load it again)
+  const int ktop = min(c.k1 + 1, nz - 1);
+  struct Planes {
+    double u[3][NU], q[2][NU1];  // u; p' and rho
+  };
+  Planes fs;                     // staged plane in flight
+  double fT, fph[3], fpl[2];     // own cell's values of the next plane
+  auto fetch = [&](int kk, Planes& dst) {
+    const int kq = min(kk, ktop), o = pl * kq;
+    const bool halo = kq < c.k1;
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
-      const int Q = st.q[m] + o;
+      const int Q = (halo ? st.q[m] : qo) + o;
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) fs[cc][m] = u.p[cc][Q];
+      for (int cc = 0; cc < 3; ++cc) dst.u[cc][m] = u.p[cc][Q];
     }
 #pragma unroll
     for (int m = 0; m < NU1; ++m) {
-      const int Q = st1.q[m] + o;
-      fq[0][m] = pp[Q];
-      fq[1][m] = rho[Q];
+      const int Q = (halo ? st1.q[m] : qo) + o;
+      dst.q[0][m] = pp[Q];
+      dst.q[1][m] = rho[Q];
     }
   };
-  Line z[3];       // u along z (momentum)
+  auto own = [&](int kk) {
+    const int o = pl * min(kk, c.k1 - 1), P = qo + o;
+    fT = T[P];
+    fph[0] = phi.p[0][P];
+    fph[1] = phi.p[1][P];
+    fph[2] = phi.p[Z][P];
+    fpl[0] = phi.p[0][Pxl + o];
+    fpl[1] = phi.p[1][Pyl + o];
+  };
+  auto stage = [&](int sl, const Planes& src) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int m = 0; m < NU; ++m)
+        if (st.has[m]) su[sl][f][st.h[m]] = src.u[f][m];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int m = 0; m < NU1; ++m)
+        if (st1.has[m]) sq[sl][f][st1.h[m]] = src.q[f][m];
+  };
+  Line z[3];       // u along z (momentum); planes k0-3 .. k0+1 before the loop
   double flo[3];   // momentum flux through the face below
   double fmlo;     // mass flux through the face below
   double Flo = 0.0;
@@ -301,54 +332,57 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       const double* uc = u.p[cc];
-      z[cc] = line_at([&](int Q) { return uc[Q]; }, P, pl, c.k0, nz);
-      flo[cc] = c.k0 > 0 ? fmlo * i4_lo(z[cc], c.k0, nz) : 0.0;
+      z[cc].m2 = 0.0;
+      z[cc].m1 = uc[nb(c.k0 >= 2, P - 2 * pl, P)];
+      z[cc].c = uc[nb(c.k0 >= 1, P - pl, P)];
     }
     if (c.k0 > 0)
       Flo = force_val(pp[P - pl], pp[P], rho[P - pl], rho[P],
                       phi_face<3>(G, ph, Z, c.k0 - 1, c.k0 - 1), G.inv_h[Z]);
+    Planes f1;  // the chunk's first two planes are loaded together
+    fetch(c.k0, fs);
+    fetch(c.k0 + 1, f1);
+    stage(0, fs);
+    stage(1, f1);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      z[cc].p1 = fs.u[cc][0];
+      z[cc].p2 = f1.u[cc][0];
+      const Line L{z[cc].m1, z[cc].c, z[cc].p1, z[cc].p2, 0.0};  // centred on k0
+      flo[cc] = c.k0 > 0 ? fmlo * i4_lo(L, c.k0, nz) : 0.0;
+    }
   }
-  fetch(c.k0);
+  own(c.k0);
+  fetch(c.k0 + 2, fs);
   const double kvz = ph.mu * G.S[Z] / G.h[Z];
+  int sl = 0;  // slot of plane k
   for (int k = c.k0; k < c.k1; ++k) {
-    const int sl = k & 1;
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-      for (int m = 0; m < NU; ++m)
-        if (st.has[m]) su[sl][f][st.h[m]] = fs[f][m];
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-      for (int m = 0; m < NU1; ++m)
-        if (st1.has[m]) sq[sl][f][st1.h[m]] = fq[f][m];
-    // the own cell's values of this plane, loaded before the next plane's
-    // staging loads (so waiting for them does not wait for those)
-    const int P0 = qo + pl * k;
-    const int Pu = nb(k + 1 < nz, P0 + pl, P0), Pn = nb(k + 3 < nz, P0 + 3 * pl, P0);
-    const double Tc = T[P0], p_up = pp[Pu], r_up = rho[Pu];
-    const double fph[3] = {phi.p[0][P0], phi.p[1][P0], phi.p[Z][P0]};
-    const double fpl[2] = {phi.p[0][Pxl + pl * k], phi.p[1][Pyl + pl * k]};
-    double zn[3];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) zn[cc] = u.p[cc][Pn];
-    fetch(k + 1 < c.k1 ? k + 1 : k);
+    // every thread is done with plane k-1, whose slot takes plane k+2
     lds_barrier();
+    stage(sl == 0 ? 2 : sl - 1, fs);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], fs.u[cc][0]);
+    const double Tc = fT;
+    const double fh3[3] = {fph[0], fph[1], fph[2]}, fl2[2] = {fpl[0], fpl[1]};
+    own(k + 1);
+    fetch(k + 3, fs);
     const bool up = k + 1 < nz;
     const double* Sp = sq[sl][0];
     const double* Sr = sq[sl][1];
+    const int su1 = sl == 2 ? 0 : sl + 1;  // slot of plane k+1
     const double r = Sr[ho1], pc = Sp[ho1];
+    const double p_up = sq[su1][0][ho1], r_up = sq[su1][1][ho1];
     // the state's flux through the faces of the cell, rho*, e^n
     double sum = 0.0, fhi[2], flod[2];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
       const int n = G.n[d], q = coord(c, d);
-      fhi[d] = q + 1 < n ? fph[d] : 0.0;
-      flod[d] = q > 0 ? fpl[d] : 0.0;
+      fhi[d] = q + 1 < n ? fh3[d] : 0.0;
+      flod[d] = q > 0 ? fl2[d] : 0.0;
       sum += fhi[d];
       sum -= flod[d];
     }
-    const double phz = up ? fph[Z] : 0.0;
+    const double phz = up ? fh3[Z] : 0.0;
     sum += phz;
     sum -= fmlo;
     fmlo = phz;
@@ -405,10 +439,8 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
       for (int cc = 0; cc < 3; ++cc) u_star.p[cc][P] = us[cc];
       if (pp_copy) pp_copy[P] = pc;
     }
-    const bool more = k + 3 < nz;
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], more ? zn[cc] : 0.0);
     Flo = Fhi;
+    sl = su1;
   }
 }
 
@@ -627,11 +659,14 @@ __global__ __launch_bounds__(kBlock) void k_energy_post(
 }
 
 // k_energy_rhs on a 3D mesh with the x/y neighbourhoods of e and T staged in
-// LDS and the next plane's loads in flight while a plane is computed.  Same
-// formulas and order as k_energy_rhs.  (Held to 128 VGPRs for two 512-thread
-// workgroups a CU it spills 19 registers and ran at 301 us on the 3D
-// benchmark mesh; one workgroup a CU without the cap, 219 us; 64x4 tiles,
-// 410 us.)
+// a ring of three LDS planes filled three planes ahead of the plane computed
+// (the staged own values of plane k + 2 feed the register lines along z, as
+// in k_H3) and the next plane's own-cell loads in flight.  Same formulas and
+// order as k_energy_rhs.  On the 3D benchmark mesh: 213 us and 1162 MB of
+// HBM traffic a launch, against 212 us and 1259 MB with a two-plane ring and
+// separate loads of the column three planes up; held to 128 VGPRs (two
+// workgroups a CU, 9 registers spilled) 223 us; 64x4 tiles in 43-plane
+// chunks 222 us; 32-plane chunks 225 us.
 template <int TY, bool ENTH>
 __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
@@ -640,21 +675,29 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     EnergySys sy) {
   using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
-  __shared__ double su[2][2][HP];  // e, T
+  __shared__ double su[3][2][HP];  // e, T; plane k in slot (k - k0) % 3
   const Col c = col_of3<TY>(G, kc);
   const St st = stage3<2, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
-  // raw values of the plane in flight
-  double fs[2][NU], fh[2], fl[2], fz, frs, fr, fe0, fus[3], fen, fTn;
-  auto fetch = [&](int kk) {
-    const int o = pl * kk, P = qo + o;
+  // highest plane the chunk's z lines read; planes above the chunk are
+  // loaded for the own column only (the halo slots load it again)
+  const int ktop = min(c.k1 + 1, nz - 1);
+  double fs[2][NU];                                    // staged plane in flight
+  double fh[2], fl[2], fz, frs, fr, fe0, fus[3];       // own cell's values of the next plane
+  auto fetch = [&](int kk, double (&dst)[2][NU]) {
+    const int kq = min(kk, ktop), o = pl * kq;
+    const bool halo = kq < c.k1;
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
-      fs[0][m] = e_prev[st.q[m] + o];
-      fs[1][m] = T_prev[st.q[m] + o];
+      const int Q = (halo ? st.q[m] : qo) + o;
+      dst[0][m] = e_prev[Q];
+      dst[1][m] = T_prev[Q];
     }
+  };
+  auto own = [&](int kk) {
+    const int o = pl * min(kk, c.k1 - 1), P = qo + o;
     fh[0] = phi.p[0][P];
     fh[1] = phi.p[1][P];
     fl[0] = phi.p[0][Pxl + o];
@@ -665,41 +708,63 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     fe0 = e0[P];
 #pragma unroll
     for (int d = 0; d < 3; ++d) fus[d] = u_star.p[d][P];
-    const int Pn = nb(kk + 3 < nz, P + 3 * pl, P);
-    fen = e_prev[Pn];
-    fTn = T_prev[Pn];
+  };
+  auto stage = [&](int sl, const double (&src)[2][NU]) {
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int m = 0; m < NU; ++m)
+        if (st.has[m]) su[sl][f][st.h[m]] = src[f][m];
   };
   auto hhat = [&](const Line& e, const Line& T) {
     if (ENTH) return e;
     return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
                 e.p2 + ph.R * T.p2};
   };
+  // the z lines hold planes k0-3 .. k0+1 before the loop (k0-3 is never read)
   Line ze, zT;
   double flo;
   {
     const int P = qo + pl * c.k0;
-    ze = line_at([&](int Q) { return e_prev[Q]; }, P, pl, c.k0, nz);
-    zT = line_at([&](int Q) { return T_prev[Q]; }, P, pl, c.k0, nz);
-    flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hhat(ze, zT), c.k0, nz) : 0.0;
+    const int Q2 = nb(c.k0 >= 2, P - 2 * pl, P), Q1 = nb(c.k0 >= 1, P - pl, P);
+    ze.m2 = 0.0;
+    zT.m2 = 0.0;
+    ze.m1 = e_prev[Q2];
+    zT.m1 = T_prev[Q2];
+    ze.c = e_prev[Q1];
+    zT.c = T_prev[Q1];
+    const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
+    double f1[2][NU];  // the chunk's first two planes are loaded together
+    fetch(c.k0, fs);
+    fetch(c.k0 + 1, f1);
+    stage(0, fs);
+    stage(1, f1);
+    ze.p1 = fs[0][0];
+    zT.p1 = fs[1][0];
+    ze.p2 = f1[0][0];
+    zT.p2 = f1[1][0];
+    const Line Le{ze.m1, ze.c, ze.p1, ze.p2, 0.0}, LT{zT.m1, zT.c, zT.p1, zT.p2, 0.0};  // centred on k0
+    flo = c.k0 > 0 ? phz_lo * i4_lo(hhat(Le, LT), c.k0, nz) : 0.0;
   }
-  fetch(c.k0);
+  own(c.k0);
+  fetch(c.k0 + 2, fs);
   const double kcoef = ph.mu / ph.Pr * ph.cp;
   const double kdz = kcoef * G.S[Z] / G.h[Z];
   const double wz = kcoef * (G.S[Z] / G.h[Z]);
   double red[3] = {0.0, 0.0, 0.0};
+  int sl = 0;  // slot of plane k
   for (int k = c.k0; k < c.k1; ++k) {
-    const int sl = k & 1;
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-      for (int m = 0; m < NU; ++m)
-        if (st.has[m]) su[sl][f][st.h[m]] = fs[f][m];
+    // every thread is done with plane k-1, whose slot takes plane k+2
+    lds_barrier();
+    stage(sl == 0 ? 2 : sl - 1, fs);
+    ze = shift(ze, fs[0][0]);
+    zT = shift(zT, fs[1][0]);
     const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
-    const double phz = fz, rs = frs, r = fr, e0c = fe0, e_n = fen, T_n = fTn;
+    const double phz = fz, rs = frs, r = fr, e0c = fe0;
     const double us[3] = {fus[0], fus[1], fus[2]};
     const double tb = Tbg[k], tb_up = Tbg[k + 1 < nz ? k + 1 : k], tb_dn = Tbg[k > 0 ? k - 1 : k];
-    fetch(k + 1 < c.k1 ? k + 1 : k);
-    lds_barrier();
+    own(k + 1);
+    fetch(k + 3, fs);
     Line le[2], lT[2];
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
@@ -762,9 +827,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
       red[1] += rr * rr;
       red[2] += bP * bP;
     }
-    const bool more = k + 3 < nz;
-    ze = shift(ze, more ? e_n : 0.0);
-    zT = shift(zT, more ? T_n : 0.0);
+    sl = sl == 2 ? 0 : sl + 1;
   }
   __shared__ double sh[3][TY];
   Reducer<0u, 3, 64 * TY>::block(red, sh);
@@ -851,73 +914,103 @@ __global__ __launch_bounds__(kBlock) void k_H(Geo G, Phys ph, int kc,
   }
 }
 
-// k_H on a 3D mesh with the x/y neighbourhoods of u_prev staged in LDS: the
-// next plane's loads are in flight while a plane is computed from LDS and
-// registers.  Same formulas and order as k_H.  (168 VGPRs: 3 waves a SIMD.)
+// k_H on a 3D mesh.  The x/y neighbourhoods of u_prev (two cells, for I4)
+// are staged in a ring of three LDS planes that is filled three planes ahead
+// of the plane computed, and the staged own value of plane k + 2 is the one
+// the register line along z takes in: each value of u_prev comes from HBM once
+// a chunk.  (A separate load of the column three planes up, as the explicit
+// kernels with a two-plane ring make, came back from HBM: between it and the
+// plane's staging load, more data passes through an XCD's L2 than it holds.)
+// Same formulas and order as k_H.
 template <int TY>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(3))) void k_H3(Geo G, Phys ph, int kc,
+__global__ __launch_bounds__(64 * TY) void k_H3(Geo G, Phys ph, int kc,
                                                const double* __restrict__ rho, Vec<3> u,
                                                Vec<3> u_prev, Vec<3> phi, Vec<3> H) {
   using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
-  __shared__ double su[2][3][HP];
+  __shared__ double su[3][3][HP];  // plane k in slot (k - k0) % 3
   const Col c = col_of3<TY>(G, kc);
   const St st = stage3<2, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo;
   const int Pxl = nb(clampi(c.i, G.nx) > 0, qo - 1, qo);
   const int Pyl = nb(clampi(c.j, G.ny) > 0, qo - G.nx, qo);
-  // raw values of the plane in flight
-  double fu[3][NU], fr, fz, fh[2], fl[2], fun[3], fzn[3];
-  auto fetch = [&](int kk) {
-    const int o = pl * kk, P = qo + o;
+  // highest plane the chunk's z lines read; planes above the chunk are
+  // loaded for the own column only (the halo slots load it again)
+  const int ktop = min(c.k1 + 1, nz - 1);
+  double fu[3][NU];                       // staged plane in flight
+  double fr, fz, fh[2], fl[2], fun[3];    // own cell's values of the next plane
+  auto fetch = [&](int kk, double (&dst)[3][NU]) {
+    const int kq = min(kk, ktop), o = pl * kq;
+    const bool halo = kq < c.k1;
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc)
+    for (int m = 0; m < NU; ++m) {
+      const int Q = (halo ? st.q[m] : qo) + o;
 #pragma unroll
-      for (int m = 0; m < NU; ++m) fu[cc][m] = u_prev.p[cc][st.q[m] + o];
+      for (int cc = 0; cc < 3; ++cc) dst[cc][m] = u_prev.p[cc][Q];
+    }
+  };
+  auto own = [&](int kk) {
+    const int o = pl * min(kk, c.k1 - 1), P = qo + o;
     fr = rho[P];
     fz = phi.p[Z][P];
     fh[0] = phi.p[0][P];
     fh[1] = phi.p[1][P];
     fl[0] = phi.p[0][Pxl + o];
     fl[1] = phi.p[1][Pyl + o];
-    const int Pn = nb(kk + 3 < nz, P + 3 * pl, P);
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      fun[cc] = u.p[cc][P];
-      fzn[cc] = u_prev.p[cc][Pn];
-    }
+    for (int cc = 0; cc < 3; ++cc) fun[cc] = u.p[cc][P];
   };
-  Line z[3];
-  double flo[3];
-  {
-    const int P = qo + pl * c.k0;
-    const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      const double* uc = u_prev.p[cc];
-      z[cc] = line_at([&](int Q) { return uc[Q]; }, P, pl, c.k0, nz);
-      flo[cc] = c.k0 > 0 ? phz_lo * i4_lo(z[cc], c.k0, nz) : 0.0;
-    }
-  }
-  fetch(c.k0);
-  const double kvz = ph.mu * G.S[Z] / G.h[Z];
-  for (int k = c.k0; k < c.k1; ++k) {
-    const int sl = k & 1;
+  auto stage = [&](int sl, const double (&src)[3][NU]) {
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
       for (int m = 0; m < NU; ++m)
-        if (st.has[m]) su[sl][cc][st.h[m]] = fu[cc][m];
-    const double r = fr, phz = fz;
-    const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
-    double un[3], zn[3];
+        if (st.has[m]) su[sl][cc][st.h[m]] = src[cc][m];
+  };
+  // the z lines hold planes k0-3 .. k0+1 before the loop (k0-3 is never
+  // read); the chunk's first two planes are loaded together
+  Line z[3];
+  double flo[3];
+  {
+    const int P = qo + pl * c.k0;
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
-      un[cc] = fun[cc];
-      zn[cc] = fzn[cc];
+      const double* uc = u_prev.p[cc];
+      z[cc].m2 = 0.0;
+      z[cc].m1 = uc[nb(c.k0 >= 2, P - 2 * pl, P)];
+      z[cc].c = uc[nb(c.k0 >= 1, P - pl, P)];
     }
-    fetch(k + 1 < c.k1 ? k + 1 : k);
+    const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
+    double f1[3][NU];
+    fetch(c.k0, fu);
+    fetch(c.k0 + 1, f1);
+    stage(0, fu);
+    stage(1, f1);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      z[cc].p1 = fu[cc][0];
+      z[cc].p2 = f1[cc][0];
+      const Line L{z[cc].m1, z[cc].c, z[cc].p1, z[cc].p2, 0.0};  // centred on k0
+      flo[cc] = c.k0 > 0 ? phz_lo * i4_lo(L, c.k0, nz) : 0.0;
+    }
+  }
+  own(c.k0);
+  fetch(c.k0 + 2, fu);
+  const double kvz = ph.mu * G.S[Z] / G.h[Z];
+  int sl = 0;  // slot of plane k
+  for (int k = c.k0; k < c.k1; ++k) {
+    // every thread is done with plane k-1, whose slot takes plane k+2
     lds_barrier();
+    stage(sl == 0 ? 2 : sl - 1, fu);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], fu[cc][0]);
+    const double r = fr, phz = fz;
+    const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
+    double un[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) un[cc] = fun[cc];
+    own(k + 1);
+    fetch(k + 3, fu);
     double h[3];
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
@@ -947,8 +1040,7 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(3))) vo
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) H.p[cc][P] = h[cc];
     }
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
+    sl = sl == 2 ? 0 : sl + 1;
   }
 }
 
@@ -1663,11 +1755,15 @@ ZPlan zplan3(const Geo& G, int ty, int kc0) {
 namespace {
 
 // rows of the column tiles of the LDS-staged 3D step kernels (taller tiles
-// re-read fewer halo rows; the two kernels with the most registers keep
-// 64x4 for occupancy)
-constexpr int kTyStep1 = 4, kTyEnergy = 8, kTyH = 4, kTyRhs = 8, kTyCorr = 8;
-// planes of a chunk (measured per kernel: 16, 32 and 64 tried)
-constexpr int kKcStep1 = 64, kKcEnergy = 64, kKcH = 16, kKcRhs = 32, kKcCorr = 32, kKcCorrLast = 64;
+// re-read fewer halo rows) and planes of a chunk, measured per kernel on the
+// 256 x 256 x 128 mesh.  The kernels with three-plane rings hold one
+// 512-thread workgroup a CU (registers or LDS), and 64 x 8 tiles in 64-plane
+// chunks give 256 workgroups, one for each CU, which all run at once: k_H3
+// took 185 us so against 205 us in 64 x 4 tiles of 16 planes (2048
+// workgroups, three a CU, the last of three rounds a third empty) and 207 us
+// in 43-plane chunks (one round).
+constexpr int kTyStep1 = 8, kTyEnergy = 8, kTyH = 8, kTyRhs = 8, kTyCorr = 8;
+constexpr int kKcStep1 = 64, kKcEnergy = 64, kKcH = 64, kKcRhs = 32, kKcCorr = 32, kKcCorrLast = 64;
 
 }  // namespace
 

@@ -128,22 +128,39 @@ struct KernelTimer {
 // Whether the learned form runs its network on a corrector's solve: it runs
 // while the inner iterations it saves, in running averages of solves with
 // and without it, take longer than one application (network, flexible-CG
-// step and set-up); the other choice is re-tried every 16th solve.
+// step and set-up).  The other choice is re-tried after a period of solves
+// that starts at 16 and doubles, up to 256, each time a re-try leaves the
+// choice as it was (a re-try that changes it sets the period back to 16):
+// where the network keeps not paying, re-tries stop costing the solver.
 struct NetGate {
+  static constexpr int kFirst = 16, kMost = 256;
   double it_net = -1.0, it_plain = -1.0;  // inner iterations a solve that needed any
-  int solves = 0;
+  int since = 0;       // solves since the last re-try
+  int every = kFirst;  // re-try period
+  // the choice the averages make, -1 while one of them or a time is missing
+  static int choice(double it_net, double it_plain, double t_net, double t_iter) {
+    if (it_net < 0 || it_plain < 0 || !(t_net > 0) || !(t_iter > 0)) return -1;
+    return (it_plain - it_net) * t_iter > t_net ? 1 : 0;
+  }
   bool use(double t_net, double t_iter) const {
     if (it_net < 0) return true;    // first with the network,
     if (it_plain < 0) return false;  // then once without
     if (!(t_net > 0)) return true;    // (times still to be taken: the network's
     if (!(t_iter > 0)) return false;  // in a solve with it, an iteration's without)
-    const bool pays = (it_plain - it_net) * t_iter > t_net;
-    return (solves % 16 == 15) ? !pays : pays;
+    const bool pays = choice(it_net, it_plain, t_net, t_iter) == 1;
+    return since + 1 >= every ? !pays : pays;
   }
-  void record(bool net, double its) {
+  void record(bool net, double its, double t_net, double t_iter) {
+    const int before = choice(it_net, it_plain, t_net, t_iter);
     double& e = net ? it_net : it_plain;
     e = e < 0 ? its : 0.75 * e + 0.25 * its;
-    ++solves;
+    if (before >= 0 && (net ? 1 : 0) != before) {  // a re-try
+      const int after = choice(it_net, it_plain, t_net, t_iter);
+      every = after == before ? (2 * every < kMost ? 2 * every : kMost) : kFirst;
+      since = 0;
+    } else {
+      ++since;
+    }
   }
 };
 
@@ -823,7 +840,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   if (!x->has_net) return solve_mixed(x, xv, out);
   if (!x->net_now) {  // the gate chose the refinement alone for this solve
     gea_status rc = solve_mixed(x, xv, out);
-    if (rc == GEA_OK && out->outer_iters > 0) net_gate(x).record(false, out->iters);
+    if (rc == GEA_OK && out->outer_iters > 0) net_gate(x).record(false, out->iters, x->t_net_ms, x->t_iter_ms);
     return rc;
   }
   const Geo& G = x->G;
@@ -983,7 +1000,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   out->outer_iters = outer;
   out->fallbacks = fallbacks;
   x->fallbacks += fallbacks;
-  if (out->status == GEA_OK && outer > 0) net_gate(x).record(true, total);
+  if (out->status == GEA_OK && outer > 0) net_gate(x).record(true, total, x->t_net_ms, x->t_iter_ms);
   return (gea_status)out->status;
 }
 

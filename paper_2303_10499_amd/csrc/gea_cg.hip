@@ -707,11 +707,10 @@ __global__ __launch_bounds__(64 * TY) void k_residual64_3(Geo G, Stencil<3, doub
   for (int k = col.k0; k < col.k1; ++k) {
     const int sl = k & 1;
 #pragma unroll
-    for (int m = 0; m < NU; ++m)
-      if (st.has[m]) {
-        sx[sl][st.h[m]] = fx[m];
-        sd[sl][st.h[m]] = fd[m];
-      }
+    for (int m = 0; m < NU; ++m) {
+      sx[sl][st.h[m]] = fx[m];
+      sd[sl][st.h[m]] = fd[m];
+    }
     const double bp = fb, cP = fc, xu = fxu, du = fdu;
     const float di = fdi;
     fetch(k + 1 < col.k1 ? k + 1 : k);

@@ -163,11 +163,10 @@ __global__ __launch_bounds__(kBlock) void k_fcg_spmv3(Geo G, int kc, int iter,
   for (int k = col.k0; k < col.k1; ++k) {
     const int sl = k & 1;
 #pragma unroll
-    for (int m = 0; m < NU; ++m)
-      if (st.has[m]) {
-        sp[sl][st.h[m]] = pn(fz[m], fo[m]);
-        sd[sl][st.h[m]] = fd[m];
-      }
+    for (int m = 0; m < NU; ++m) {
+      sp[sl][st.h[m]] = pn(fz[m], fo[m]);
+      sd[sl][st.h[m]] = fd[m];
+    }
     const float cP = fc, rP = fr, pu = pn(fzu, fou), du = fdu;
     fetch(k + 1 < col.k1 ? k + 1 : k);
     lds_barrier();

@@ -196,7 +196,8 @@ __device__ __forceinline__ Stage3<HW, TY> stage3(const Geo& G, const Col& c) {
   for (int m = 1; m < S::NU; ++m) {
     int e = (int)threadIdx.x + (m - 1) * S::NT;
     st.has[m] = e < S::NH;
-    if (!st.has[m]) {  // no cell in this slot: load the own cell again, write nothing
+    if (!st.has[m]) {  // no cell in this slot: the own cell again (the step kernels store
+                       // it unconditionally, to its own place: the same value as slot 0)
       st.q[m] = st.qo;
       st.h[m] = st.ho;
       continue;

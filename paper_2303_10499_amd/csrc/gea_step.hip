@@ -315,12 +315,12 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
     for (int f = 0; f < 3; ++f)
 #pragma unroll
       for (int m = 0; m < NU; ++m)
-        if (st.has[m]) su[sl][f][st.h[m]] = src.u[f][m];
+        su[sl][f][st.h[m]] = src.u[f][m];
 #pragma unroll
     for (int f = 0; f < 2; ++f)
 #pragma unroll
       for (int m = 0; m < NU1; ++m)
-        if (st1.has[m]) sq[sl][f][st1.h[m]] = src.q[f][m];
+        sq[sl][f][st1.h[m]] = src.q[f][m];
   };
   Line z[3];       // u along z (momentum); planes k0-3 .. k0+1 before the loop
   double flo[3];   // momentum flux through the face below
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     for (int f = 0; f < 2; ++f)
 #pragma unroll
       for (int m = 0; m < NU; ++m)
-        if (st.has[m]) su[sl][f][st.h[m]] = src[f][m];
+        su[sl][f][st.h[m]] = src[f][m];
   };
   auto hhat = [&](const Line& e, const Line& T) {
     if (ENTH) return e;
@@ -965,7 +965,7 @@ __global__ __launch_bounds__(64 * TY) void k_H3(Geo G, Phys ph, int kc,
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
       for (int m = 0; m < NU; ++m)
-        if (st.has[m]) su[sl][cc][st.h[m]] = src[cc][m];
+        su[sl][cc][st.h[m]] = src[cc][m];
   };
   // the z lines hold planes k0-3 .. k0+1 before the loop (k0-3 is never
   // read); the chunk's first two planes are loaded together
@@ -1195,7 +1195,7 @@ __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int m = 0; m < NU; ++m)
-        if (st.has[m]) ss[sl][f][st.h[m]] = fs[f][m];
+        ss[sl][f][st.h[m]] = fs[f][m];
     const double cP = fc, rP = fr, psP = fps, D_up = fDu, Hz = fHz, Hz_up = fHzu, r23_up = fru;
     const double x_up = fxu;
     fetch(k + 1 < c.k1 ? k + 1 : k);
@@ -1490,7 +1490,7 @@ __global__ __launch_bounds__(64 * TY) void k_correct3(
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int m = 0; m < NU; ++m)
-        if (st.has[m]) ss[sl][f][st.h[m]] = fs[f][m];
+        ss[sl][f][st.h[m]] = fs[f][m];
     const double rs = frs, p_up = fpu, r_up = fru, D_up = fDu, Hz_up = fHzu, r_old = fro, psP = fps;
     const double Hc[3] = {fH[0], fH[1], fH[2]};
     fetch(k + 1 < c.k1 ? k + 1 : k);

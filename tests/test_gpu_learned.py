@@ -497,8 +497,10 @@ def test_learned_gate_keeps_the_network_off_where_it_does_not_pay(learned):
     iterations it saves take longer than one application (both timed on the
     device).  On the 3D bubble the network saves about one FP32 iteration a
     solve and costs about eight, so after the first solve with it and one
-    without, it runs only on every 16th solve; the solves still end at their
-    tolerance, and the forced form (learned_always) applies it every time."""
+    without, it runs only on re-tries, after 16 solves and then after
+    periods that double while the re-tries confirm the choice; the solves
+    still end at their tolerance, and the forced form (learned_always)
+    applies it every time."""
     from paper_2303_10499_amd import gea
     apps = {}
     for always in (0, 1):

@@ -249,9 +249,12 @@ gea_status gea_get_fields(gea_ctx* ctx, uint32_t field_mask, double* out, gea_pt
 /* Measurement support.  With timing on, every kernel launch is bracketed by
  * two events on the context's stream and its device time is summed per
  * kernel class:
- *   0 FP64 CG iteration kernel (the previous update of r and x, the new
- *     direction p, q = A p, the iteration's partial dot products)
- *   1 FP64 CG scalar kernel (one workgroup: alpha, beta, stop test)
+ *   0 FP64 CG iteration kernel (the scalars of the iteration before it from
+ *     that iteration's partials, except at the start of a batch of
+ *     iterations; the previous update of r and x, the new direction p,
+ *     q = A p, the iteration's partial dot products)
+ *   1 FP64 CG scalar kernel (one workgroup, at the end of each batch:
+ *     alpha, beta, stop test)
  *   2 FP32 inner CG iteration kernel  3 FP32 inner CG scalar kernel
  *   4 solver set-up kernels (initial residual and its scalars, refinement
  *     residual and correction, FP32 coefficient copy)
@@ -269,8 +272,8 @@ gea_status gea_kernel_times(gea_ctx* ctx, double* ms, int64_t* launches);
  * pressure system of the last assembly, each launched reps times back to
  * back between two events on the context's stream: ms[0] FP64 iteration
  * kernel, ms[1] FP64 scalar kernel, ms[2] FP32 iteration kernel, ms[3] FP32
- * scalar kernel (iteration 1 of a fresh solve, so that the previous
- * iteration's update is applied as in every later one).  Uses scratch
+ * scalar kernel (iteration 1 of a fresh solve inside a batch: it forms
+ * iteration 0's scalars and applies its update, as every later one does).  Uses scratch
  * vectors only; the state is not changed. */
 gea_status gea_time_solver_kernels(gea_ctx* ctx, int32_t reps, double* ms);
 

@@ -399,12 +399,13 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned, bool trans
       *a = cv.take<double>(nc);
   if (transport)
     for (int d = 0; d < nd; ++d) x->trb[d] = cv.take<double>(nc);
-  // partials: 7 per workgroup of the iteration kernel's grid; 2 (and 1 for
-  // ||b||^2) per workgroup of the set-up kernels' column-tile grid
+  // partials: 7 per workgroup of the iteration kernel's grid, in two sets
+  // (by iteration parity); 2 (and 1 for ||b||^2) per workgroup of the set-up
+  // kernels' column-tile grid
   const int ns = std::max(iter_grid<double>(make_geo(m)), iter_grid<float>(make_geo(m)));
   const int nzb = zplan(make_geo(m)).blocks;
   for (CgWork* w : {&x->w64, &x->w32}) {
-    w->s = cv.take<double>(7 * (size_t)ns);
+    w->s = cv.take<double>(14 * (size_t)ns);
     w->u[0] = nullptr;
     w->u[1] = cv.take<double>(2 * (size_t)nzb);
     w->b = cv.take<double>(nzb);
@@ -579,7 +580,7 @@ gea_status run_cg(gea_ctx* x, CgScalars* dsc, CgScalars& hs, int max_iter, int f
     // the time of one iteration if every launch of it did one
     const bool timed = time_iter && x->t_iter_ms < 0 && batch >= 2 && hs.rr > 0;
     if (timed) HIPCHK(hipEventRecord(x->ev_it[0], x->stream));
-    for (int k = 0; k < batch; ++k, ++j) launch_iter((int)j);
+    for (int k = 0; k < batch; ++k, ++j) launch_iter((int)j, k > 0, k == batch - 1);
     if (timed) HIPCHK(hipEventRecord(x->ev_it[1], x->stream));
     HIPCHK(hipGetLastError());
     const int iter_before = hs.iter;
@@ -692,9 +693,9 @@ gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
   const int first = last64 > 0 ? (int)(0.9 * last64) : 0;
   gea_status rc = run_cg(
       x, x->sc, hs, x->prm.max_iter, first,
-      [&](int j) {
-        x->timer.run(0, x->stream, [&] { cg_iter_kernel<double>(x->stream, G, v, j, w); });
-        x->timer.run(1, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+      [&](int j, bool fold, bool last) {
+        x->timer.run(0, x->stream, [&] { cg_iter_kernel<double>(x->stream, G, v, j, w, fold); });
+        if (last || !cg_folds(w)) x->timer.run(1, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
       });
   if (rc != GEA_OK) return rc;
   last64 = hs.iter;
@@ -753,9 +754,9 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
     const int first = last32 > 0 ? (int)(0.9 * last32) : 0;
     gea_status rc = run_cg(
         x, x->sc32, h32, budget, first,
-        [&](int j) {
-          x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
-          x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+        [&](int j, bool fold, bool last) {
+          x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w, fold); });
+          if (last || !cg_folds(w)) x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
         },
         Extra{}, 0, x->prm.solver == GEA_LEARNED_MIXED);
     if (rc != GEA_OK) return rc;
@@ -858,9 +859,9 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   int unread_first = 0;  // Jacobi-PCG launches enqueued with it
   CgScalars s_res{}, s_cg{};
   FcgScalars s_fcg{};
-  auto iterate = [&](int j) {
-    x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w); });
-    x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+  auto iterate = [&](int j, bool fold, bool last) {
+    x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w, fold); });
+    if (last || !cg_folds(w)) x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
   };
   // network step(s), then Jacobi-PCG resumed from their iterate and residual
   // (when the flexible CG has converged the resumed solve starts done and its
@@ -901,7 +902,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       const int launched = learned_then_resume(budget > 0 ? budget : 1);
       use_net = false;
       unread_first = x->last_iters_res + 4 + x->last_iters_res / 32;
-      for (int j = 0; j < unread_first; ++j) iterate(j);
+      for (int j = 0; j < unread_first; ++j) iterate(j, j > 0, j == unread_first - 1);
       HIPCHK(hipGetLastError());
       snapshot(x, x->sc32, &s_cg, sizeof s_cg);
       snapshot(x, x->fsc, &s_fcg, sizeof s_fcg);
@@ -1024,10 +1025,10 @@ gea_status solve_energy(gea_ctx* x, double* T, int nparts, int sweep, int* iters
   int& last = x->last_iters_energy[sweep < 8 ? sweep : 7];
   gea_status rc = run_cg(
       x, x->sc, hs, x->prm.max_iter, last > 0 ? last + 1 : 0,
-      [&](int j) {
+      [&](int j, bool fold, bool last) {
         x->timer.run(7, x->stream, [&] {
-          cg_iter_kernel<double>(x->stream, G, v, j, w);
-          cg_scalars(x->stream, G, j, w);
+          cg_iter_kernel<double>(x->stream, G, v, j, w, fold);
+          if (last || !cg_folds(w)) cg_scalars(x->stream, G, j, w);
         });
       });
   if (rc != GEA_OK) return rc;
@@ -1614,11 +1615,11 @@ gea_status gea_time_solver_kernels(gea_ctx* x, int32_t reps, double* ms) {
     HIPCHK(hipMemcpyAsync(x->xs, S.pp, sizeof(double) * G.nc, hipMemcpyDeviceToDevice, s));
     CgVectors<double> v{x->xs, x->r, x->r1, x->p0, x->p1, x->q, x->q1, x->c, x->D, x->dinv, x->b};
     cg_init<double>(s, G, v, x->w64, 0.0, 1 << 30);
-    cg_iter_kernel<double>(s, G, v, 0, x->w64);
+    cg_iter_kernel<double>(s, G, v, 0, x->w64, false);
     cg_scalars(s, G, 0, x->w64);
-    cg_iter_kernel<double>(s, G, v, 1, x->w64);  // warm-up
+    cg_iter_kernel<double>(s, G, v, 1, x->w64, true);  // warm-up
     HIPCHK(hipEventRecord(ev[0], s));
-    for (int k = 0; k < reps; ++k) cg_iter_kernel<double>(s, G, v, 1, x->w64);
+    for (int k = 0; k < reps; ++k) cg_iter_kernel<double>(s, G, v, 1, x->w64, true);
     HIPCHK(hipEventRecord(ev[1], s));
     for (int k = 0; k < reps; ++k) cg_scalars(s, G, 1, x->w64);
     HIPCHK(hipEventRecord(ev[2], s));
@@ -1630,11 +1631,11 @@ gea_status gea_time_solver_kernels(gea_ctx* x, int32_t reps, double* ms) {
     CgVectors<float> v32{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
     launch_residual64(s, G, x->c, x->D, x->b, x->xs, v32, 0.0, 1e-30, 0.1, 1 << 30, x->o_part,
                       x->w32, x->sc);
-    cg_iter_kernel<float>(s, G, v32, 0, x->w32);
+    cg_iter_kernel<float>(s, G, v32, 0, x->w32, false);
     cg_scalars(s, G, 0, x->w32);
-    cg_iter_kernel<float>(s, G, v32, 1, x->w32);
+    cg_iter_kernel<float>(s, G, v32, 1, x->w32, true);
     HIPCHK(hipEventRecord(ev[0], s));
-    for (int k = 0; k < reps; ++k) cg_iter_kernel<float>(s, G, v32, 1, x->w32);
+    for (int k = 0; k < reps; ++k) cg_iter_kernel<float>(s, G, v32, 1, x->w32, true);
     HIPCHK(hipEventRecord(ev[1], s));
     for (int k = 0; k < reps; ++k) cg_scalars(s, G, 1, x->w32);
     HIPCHK(hipEventRecord(ev[2], s));

@@ -4,7 +4,7 @@
 // homogeneous Neumann on walls; face weights are formed on the fly from the
 // cell coefficient D.
 //
-// One iteration is one stencil kernel and one one-workgroup scalar kernel:
+// One iteration is one stencil kernel:
 //   iteration j:  r_j = r_{j-1} - alpha q_{j-1} and p_j = r_j/diag + beta p_{j-1}
 //                 on the tile and its halo, x += alpha p_{j-1} on the own cells,
 //                 q_j = A p_j, and partials <p,q>, <q,z>, <q,q/diag>, <r,r>,
@@ -18,14 +18,27 @@
 // This is Jacobi-PCG with the same iterates; it reads and writes 11 arrays
 // per iteration instead of 14 (separate operator and update kernels) and
 // needs no grid-wide reduction inside the stencil kernel.  The residual,
-// direction and A p are double buffered by iteration parity (the stencil
-// kernel reads the old values with halo while writing the new ones).  When
-// the scalar kernel finds the solve converged it raises a finish flag: the
-// next iteration kernel only applies the last x update, and the scalar
-// kernel after it sets the done flag, on which later launches return at once.
-// Dot products: every workgroup reduces its values (wave xor-shuffles, then
-// LDS) and stores one partial; the scalar kernel sums them in workgroup
-// order, so results are bitwise reproducible.
+// direction, A p and the partials are double buffered by iteration parity
+// (the stencil kernel reads the old values with halo while writing the new
+// ones).  The scalars of iteration j are formed at the start of iteration
+// j+1's kernel by every workgroup, each summing j's partials in workgroup
+// order (so all take bitwise the same values; workgroup 0 publishes them);
+// the host enqueues iterations in batches and ends each with a
+// one-workgroup scalar kernel that forms the last iteration's scalars for it
+// to read, and the batch's next iteration kernel takes them from there.
+// When the scalars show the solve converged, that iteration kernel only
+// applies the last x update and marks its launch as the last (later launches
+// of the batch return at once); the scalar kernel at the batch's end then
+// sets the done flag, on which later launches return at once.  (One scalar
+// kernel an iteration cost 3.5 us on the 30 us FP32 iteration of the 2D
+// benchmark mesh.)  Every workgroup reads all 7 ns partials, so the fold
+// costs L2 traffic that grows as ns^2: it is used up to 512 workgroups (the
+// 2D mesh's FP32 and both 3D grids: 14.7 MB a launch at 512, +2.7 us on the
+// 79 us 3D FP32 iteration); larger grids (the 2D FP64 one, 1024) keep one
+// scalar kernel an iteration (folded there the iteration took 73-77 us
+// instead of 68).  Dot products: every workgroup reduces its values (wave
+// xor-shuffles, then LDS) and stores one partial; the sums over partials
+// run in workgroup order, so results are bitwise reproducible.
 //
 // The 3D stencil kernel stages, per workgroup, a 64 x 4 column tile of p, D,
 // r and 1/diag with a one-cell halo in an LDS ring of planes and marches
@@ -40,6 +53,7 @@ namespace gea {
 namespace {
 
 constexpr int kTX3 = 64, kTY3 = 8;  // 3D tile
+constexpr int kFoldMaxParts = 512;   // largest iteration grid that folds its scalars
 // z chunk of the 3D iteration kernel
 template <typename T>
 constexpr int kKC3 = sizeof(T) == 8 ? 64 : 32;
@@ -53,20 +67,25 @@ struct Stencil {
   T k[NDIM];  // S_d / h_d in the working precision
 };
 
-// sum of n partials, identical in every workgroup; result in all threads
-template <int N>
+// sum of n partials, identical in every workgroup; result in all threads.
+// (Unrolling keeps each thread's order of additions: U only trades
+// registers for loads in flight.  LDSB: barriers that order LDS only.)
+template <int N, int U = 8, bool LDSB = false>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int n,
                                              double (&out)[N]) {
   __shared__ double sh[N][kBlock / 64];
   double a[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) a[k] = 0.0;
-#pragma unroll 8
+#pragma unroll U
   for (int b = threadIdx.x; b < n; b += kBlock) {
 #pragma unroll
     for (int k = 0; k < N; ++k) a[k] += part[k * n + b];
   }
-  Reducer<0u, N>::block(a, sh);
+  if constexpr (LDSB)
+    Reducer<0u, N>::block_lds(a, sh);
+  else
+    Reducer<0u, N>::block(a, sh);
 #pragma unroll
   for (int k = 0; k < N; ++k) out[k] = a[k];
 }
@@ -92,6 +111,108 @@ __device__ __forceinline__ int load_done(CgScalars* sc) {
 __device__ __forceinline__ bool gate_closed(const CgScalars* gate) {
   return gate != nullptr &&
          __hip_atomic_load(&gate->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
+
+// the partials of iteration `iter` within the parity-buffered set
+__device__ __forceinline__ double* iter_part(double* part, int ns, int iter) {
+  return part + (iter & 1) * 7L * ns;
+}
+
+// alpha, the residual after the update, beta and the stop test of iteration
+// `iter` from its ns partials (see the file header); every thread of every
+// workgroup that forms them gets the same values
+struct StepScalars {
+  double alpha, beta, rz, rr;
+  int fin, status;
+  bool bad;
+};
+__device__ __forceinline__ StepScalars step_scalars(const double* part, int ns, int iter,
+                                                    const CgScalars* sc) {
+  double s[7];
+  // (few registers, and the iteration kernels' first loads stay in flight)
+  sum_partials<7, 2, true>(part, ns, s);
+  const double pq = s[0], qz = s[1], qmq = s[2], rr0 = s[3], qr = s[4], qq = s[5], rz0 = s[6];
+  StepScalars o;
+  o.alpha = rz0 / pq;
+  o.rz = rz0 - 2.0 * o.alpha * qz + o.alpha * o.alpha * qmq;
+  o.rr = fmax(rr0 - 2.0 * o.alpha * qr + o.alpha * o.alpha * qq, 0.0);
+  o.beta = o.rz / rz0;
+  o.bad = !isfinite(o.alpha) || !isfinite(o.rz) || !isfinite(o.rr) || !isfinite(o.beta);
+  o.fin = 0;
+  o.status = 0;
+  if (o.bad) {
+    o.status = -5;
+  } else if (o.rr <= sc->tol2 * sc->bb) {
+    o.fin = 1;
+  } else if (iter + 1 >= sc->max_iter) {
+    o.fin = 1;
+    o.status = -4;
+  }
+  return o;
+}
+
+// (one thread) the scalars of iteration `iter` for the host and the next
+// kernels
+__device__ __forceinline__ void publish(const StepScalars& o, int iter, CgScalars* sc) {
+  sc->iter = iter + 1;
+  sc->alpha = o.alpha;
+  sc->beta = o.beta;
+  sc->rz = o.rz;
+  sc->rr = o.rr;
+  sc->status = o.status;
+  sc->fin = o.fin;
+}
+
+// Where an iteration kernel stands in its batch: the partial sets, this
+// launch's iteration index and whether it forms the previous iteration's
+// scalars itself
+struct CgStep {
+  double* part;
+  int ns;
+  int iter;
+  int fold;
+};
+
+// Whether an iteration kernel has work: false once the solve is done or an
+// earlier launch of its batch ended it.  Within a launch only done_iter
+// changes (workgroup 0 sets it to this launch's index), so every workgroup
+// takes the same branch here and in step_take; the done flag is set by the
+// scalar kernel at the end of the batch.
+__device__ __forceinline__ bool step_live(const CgStep& st, CgScalars* sc) {
+  if (load_done(sc)) return false;
+  const int di = __hip_atomic_load(&sc->done_iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return !(di >= 0 && di < st.iter);
+}
+
+// The update an iteration kernel applies (alpha, beta of the iteration
+// before it) and whether it is the solve's last; false: return at once.
+// The kernels call it after issuing their first loads.
+template <typename T>
+__device__ __forceinline__ bool step_take(const CgStep& st, CgScalars* sc, T& alpha, T& beta,
+                                          int& fin) {
+  if (st.fold) {
+    const StepScalars o = step_scalars(iter_part(st.part, st.ns, st.iter - 1), st.ns, st.iter - 1, sc);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      publish(o, st.iter - 1, sc);
+      if (o.bad)  // a non-finite value ends the solve without this update
+        __hip_atomic_store(&sc->done_iter, st.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (o.bad) return false;
+    alpha = (T)o.alpha;
+    beta = (T)o.beta;
+    fin = o.fin;
+  } else {
+    alpha = (T)sc->alpha;
+    beta = (T)sc->beta;
+    fin = sc->fin;
+  }
+  return true;
+}
+
+// (after the last x update) later launches of the batch return at once
+__device__ __forceinline__ void step_last(const CgStep& st, CgScalars* sc) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&sc->done_iter, st.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int NDIM, typename T>
@@ -211,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(const double* u_part, int n
   sc->alpha = 0.0;
   sc->beta = 0.0;
   sc->fin = 0;
+  sc->done_iter = -1;
   sc->rz = s[0];
   sc->rr = s[1];
   sc->rr0 = s[1];
@@ -231,38 +353,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(const double* u_part, int n
 
 // one workgroup after iteration `iter`: alpha, the residual after the
 // update, beta and the stop test (see the file header)
-__global__ __launch_bounds__(kBlock) void k_cg_scalars(const double* part, int n, int iter,
+__global__ __launch_bounds__(kBlock) void k_cg_scalars(double* part, int ns, int iter,
                                                        CgScalars* sc) {
   if (load_done(sc)) return;
-  if (sc->fin) {  // the iteration kernel just applied the last update
+  if (sc->done_iter >= 0) {  // a launch of the batch ended the solve
     if (threadIdx.x == 0) __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
-  double s[7];
-  sum_partials<7>(part, n, s);
+  const StepScalars o = step_scalars(iter_part(part, ns, iter), ns, iter, sc);
   if (threadIdx.x != 0) return;
-  const double pq = s[0], qz = s[1], qmq = s[2], rr0 = s[3], qr = s[4], qq = s[5], rz0 = s[6];
-  const double alpha = rz0 / pq;
-  const double rz = rz0 - 2.0 * alpha * qz + alpha * alpha * qmq;
-  const double rr = fmax(rr0 - 2.0 * alpha * qr + alpha * alpha * qq, 0.0);
-  sc->iter = iter + 1;
-  sc->alpha = alpha;
-  sc->beta = rz / rz0;
-  sc->rz = rz;
-  sc->rr = rr;
-  int done = 0, fin = 0, status = 0;
-  if (!isfinite(alpha) || !isfinite(rz) || !isfinite(rr) || !isfinite(sc->beta)) {
-    done = 1;
-    status = -5;
-  } else if (rr <= sc->tol2 * sc->bb) {
-    fin = 1;
-  } else if (iter + 1 >= sc->max_iter) {
-    fin = 1;
-    status = -4;
-  }
-  sc->status = status;
-  sc->fin = fin;
-  if (done) __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  publish(o, iter, sc);
+  if (o.bad) __hip_atomic_store(&sc->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // the seven partials of an iteration: <p,q>, <q,z>, <q,q/diag>, <r,r>, <q,r>,
@@ -312,7 +413,7 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 // is computed one step later.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgIter<T> v,
-                                                     double* part, CgScalars* sc) {
+                                                     CgStep stp, CgScalars* sc) {
   constexpr int TX = kTX3, TY = kTY3, KC = kKC3<T>;
   constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;
   constexpr int RPT = TX * TY / kBlock;  // own cells per thread
@@ -325,9 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
   constexpr int NS = sizeof(T) == 8 ? 3 : 4;
   __shared__ T sp[NS][HP];  // direction
   __shared__ T sd[NS][HP];  // D
-  if (load_done(sc)) return;
-  const T alpha = (T)sc->alpha, beta = (T)sc->beta;
-  const int fin = sc->fin;
+  if (!step_live(stp, sc)) return;
   const int nx = G.nx, ny = G.ny, nz = G.nz;
   const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
   const int b = xcd_block();
@@ -343,16 +442,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
   for (int m = 0; m < RPT; ++m) {
     jo[m] = j0 + ly0 + m * (kBlock / TX);
     in[m] = i < nx && jo[m] < ny;
-  }
-  if (fin) {  // the solve ended at the last scalar kernel: its x update only
-#pragma unroll
-    for (int m = 0; m < RPT; ++m)
-      if (in[m])
-        for (int k = k0; k < k1; ++k) {
-          const int P = i + nx * (jo[m] + ny * k);
-          v.x[P] += alpha * v.p_in[P];
-        }
-    return;
   }
   const T kx = K.k[0], ky = K.k[1], kz = K.k[2];
   // staged cells of this thread: [0, RPT) its own cells, [RPT] halo cell e = t
@@ -394,6 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
     T r[NU], q[NU], p[NU], d[NU], m[NU], x[RPT], c[RPT];
   };
   constexpr int PF = sizeof(T) == 8 ? 1 : 2;
+  T alpha = T(0), beta = T(0);  // (from step_take, after the first loads)
   auto fetch = [&](Raw& f, int kk) {
     const int o = plane * (kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk));
 #pragma unroll
@@ -479,6 +569,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
     // all of the first set's loads ahead of the second's, as in the loop
     __builtin_amdgcn_sched_barrier(0);
     fetch(f1, k0);
+  }
+  // the scalars, while the first planes' loads are in flight
+  int fin;
+  if (!step_take(stp, sc, alpha, beta, fin)) return;
+  if (fin) {  // the solve has converged: its last x update only
+#pragma unroll
+    for (int m = 0; m < RPT; ++m)
+      if (in[m])
+        for (int k = k0; k < k1; ++k) {
+          const int P = i + nx * (jo[m] + ny * k);
+          v.x[P] += alpha * v.p_in[P];
+        }
+    step_last(stp, sc);
+    return;
+  }
+  if (PF == 2) {
     int kk = k0 - 1;
     for (; kk + 1 <= k1; kk += 2) {
       plane_step(f0, kk);
@@ -488,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
   } else {
     for (int kk = k0 - 1; kk <= k1; ++kk) plane_step(f0, kk);
   }
-  store_partials<7>(acc, part);
+  store_partials<7>(acc, iter_part(stp.part, stp.ns, stp.iter));
 }
 
 // 2D iteration kernel: a workgroup owns a 256-cell row segment and marches it
@@ -499,13 +605,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
 // wave), so the kernel needs neither LDS nor barriers.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgIter<T> v,
-                                                     double* part, CgScalars* sc) {
+                                                     CgStep stp, CgScalars* sc) {
   constexpr int TX = kTX2, KC = kKC2<T>;
   constexpr bool NT2 = sizeof(T) == 8;  // (see ld_stream)
   static_assert(TX == kBlock, "one cell of the row segment per thread");
-  if (load_done(sc)) return;
-  const T alpha = (T)sc->alpha, beta = (T)sc->beta;
-  const int fin = sc->fin;
+  if (!step_live(stp, sc)) return;
   const int nx = G.nx, nz = G.nz;
   const int ntx = (nx + TX - 1) / TX;
   const int b = xcd_block();
@@ -514,14 +618,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
   const int i = tx * TX + threadIdx.x;
   const int k0 = tz * KC, k1 = min(k0 + KC, nz);
   const bool in = i < nx;
-  if (fin) {  // the solve ended at the last scalar kernel: its x update only
-    if (in)
-      for (int k = k0; k < k1; ++k) {
-        const int P = i + nx * k;
-        v.x[P] += alpha * v.p_in[P];
-      }
-    return;
-  }
   const T kx = K.k[0], kz = K.k[1];
   // the cell beyond the wave that an edge lane supplies (lane 0: left, lane 63: right)
   const int ie = lane == 0 ? i - 1 : (lane == 63 ? i + 1 : -1);
@@ -542,16 +638,28 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
                ld_stream<NT2>(&v.c[Q]),
                v.r_in[Qe], v.q_in[Qe], v.p_in[Qe], v.D[Qe], v.dinv[Qe]};
   };
-  // new residual and direction from raw values
-  auto rnew = [&](T r, T q) { return r - alpha * q; };
-  auto pnew = [&](T rn, T m, T po) { return rn * m + beta * po; };
-  // rows k0-1 .. k0+PD in flight while the scalars are read; afterwards row
-  // k+PD+1 is requested while row k is computed
+  // rows k0-1 .. k0+PD in flight while the scalars are formed or read;
+  // afterwards row k+PD+1 is requested while row k is computed
   constexpr int PD = sizeof(T) == 8 ? 2 : 3;
   Raw ring[PD + 1];
   const Raw wm = fetch(k0 - 1);
 #pragma unroll
   for (int w = 0; w <= PD; ++w) ring[w] = fetch(k0 + w);
+  T alpha, beta;
+  int fin;
+  if (!step_take(stp, sc, alpha, beta, fin)) return;
+  if (fin) {  // the solve has converged: its last x update only
+    if (in)
+      for (int k = k0; k < k1; ++k) {
+        const int P = i + nx * k;
+        v.x[P] += alpha * v.p_in[P];
+      }
+    step_last(stp, sc);
+    return;
+  }
+  // new residual and direction from raw values
+  auto rnew = [&](T r, T q) { return r - alpha * q; };
+  auto pnew = [&](T rn, T m, T po) { return rn * m + beta * po; };
   T pm = pnew(rnew(wm.r, wm.q), wm.m, wm.p), dm = wm.d;
   Raw cur = ring[0];
   T rc = rnew(cur.r, cur.q);
@@ -600,7 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
     rc = rn;
     cur = wn;
   }
-  store_partials<7>(acc, part);
+  store_partials<7>(acc, iter_part(stp.part, stp.ns, stp.iter));
 }
 
 template <int NDIM>
@@ -775,6 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
   sc32->alpha = 0.0;
   sc32->beta = 0.0;
   sc32->fin = 0;
+  sc32->done_iter = -1;
   // inner tolerance: what the outer residual still needs (times the target
   // fraction, a margin for the FP32 solve's own error), never looser than
   // 0.5 nor tighter than the configured inner tolerance
@@ -823,6 +932,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resume_start(const double* part, 
   sc->alpha = 0.0;
   sc->beta = 0.0;
   sc->fin = 0;
+  sc->done_iter = -1;
   sc->iter = 0;
   sc->max_iter = max_iter;
   const bool finite = isfinite(s[0]) && isfinite(s[1]);
@@ -902,23 +1012,27 @@ CgIter<T> iter_vectors(const CgVectors<T>& v, int iter) {
                    v.c, v.D, v.dinv};
 }
 
+bool cg_folds(const CgWork& w) { return w.ns <= kFoldMaxParts; }
+
 template <typename T>
-void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w) {
+void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w,
+                    bool fold) {
   const CgIter<T> it = iter_vectors(v, iter);
+  const CgStep stp{w.s, w.ns, iter, fold && iter > 0 && cg_folds(w) ? 1 : 0};
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_cg_iter2<T>, dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), it, w.s, w.sc);
+    hipLaunchKernelGGL(k_cg_iter2<T>, dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), it, stp, w.sc);
   else
-    hipLaunchKernelGGL(k_cg_iter3<T>, dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), it, w.s, w.sc);
+    hipLaunchKernelGGL(k_cg_iter3<T>, dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), it, stp, w.sc);
 }
 
 void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w) {
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)w.s, w.ns, iter, w.sc);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, w.s, w.ns, iter, w.sc);
 }
 
 template void cg_init<double>(hipStream_t, const Geo&, const CgVectors<double>&, const CgWork&, double, int);
 template void cg_init<float>(hipStream_t, const Geo&, const CgVectors<float>&, const CgWork&, double, int);
-template void cg_iter_kernel<double>(hipStream_t, const Geo&, const CgVectors<double>&, int, const CgWork&);
-template void cg_iter_kernel<float>(hipStream_t, const Geo&, const CgVectors<float>&, int, const CgWork&);
+template void cg_iter_kernel<double>(hipStream_t, const Geo&, const CgVectors<double>&, int, const CgWork&, bool);
+template void cg_iter_kernel<float>(hipStream_t, const Geo&, const CgVectors<float>&, int, const CgWork&, bool);
 
 
 void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,

@@ -52,6 +52,8 @@ struct CgScalars {
   int done;         // 1 once converged or failed
   int status;       // 0 ok, -4 no convergence, -5 non-finite
   int fin;          // 1: the next iteration kernel applies the last x update only
+  int done_iter;    // the launch that applied the last update (later launches of its
+                    // batch return at once); -1 while the solve runs
 };
 
 // Number of workgroups of the grid-stride kernels: a fixed multiple of the
@@ -184,8 +186,9 @@ struct CgIter {
 };
 
 // Per-workgroup partial sums of one CG instance: s (iteration kernel, 7
-// values per workgroup), u[1] (the set-up kernel's <r, z>, ||r||^2; u[0] is
-// unused), b (||b||^2 at set-up).
+// values per workgroup, in two sets by iteration parity: 14 ns doubles),
+// u[1] (the set-up kernel's <r, z>, ||r||^2; u[0] is unused), b (||b||^2 at
+// set-up).
 struct CgWork {
   double* s;
   int ns;   // workgroups of the iteration kernel's grid (iter_grid of the precision)
@@ -199,11 +202,18 @@ int iter_grid(const Geo& G);  // workgroups of the CG iteration kernel in precis
 template <typename T>
 void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w, double tol,
              int max_iter);
-// iteration `iter` of a solve set up by cg_init / launch_residual64: the
-// stencil kernel, then the one-workgroup scalar kernel
+// iteration `iter` of a solve set up by cg_init / launch_residual64.  The
+// host enqueues batches of iterations and ends each with cg_scalars: the
+// first iteration kernel of a batch takes the scalars the kernel before it
+// left (fold = false); each later one (fold = true) forms the scalars of the
+// iteration before it from that iteration's partials, in every workgroup.
+// A grid above 512 workgroups does not fold (cg_folds false): the host then
+// follows every iteration kernel with cg_scalars.
 template <typename T>
-void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w);
+void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter, const CgWork& w,
+                    bool fold);
 void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w);
+bool cg_folds(const CgWork& w);
 // Jacobi-PCG resumed on the FP32 inner system from its current iterate and
 // residual (v.x, v.r), keeping the set-up's ||b||^2 and tolerance; then
 // cg_iter_kernel / cg_scalars from iteration 0

@@ -51,6 +51,9 @@ struct Reducer {
     __syncthreads();
   }
 
+  // The same with barriers that order LDS only (sh is all they exchange), so
+  // that global loads issued before the call stay in flight across them.
+  __device__ static void block_lds(double (&v)[N], double (*sh)[kWaves]);
 };
 
 // Workgroup barrier that orders LDS accesses only.  __syncthreads() is also a
@@ -62,6 +65,26 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <unsigned MAXMASK, int N, int NT>
+__device__ void Reducer<MAXMASK, N, NT>::block_lds(double (&v)[N], double (*sh)[kWaves]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    v[k] = ((MAXMASK >> k) & 1u) ? wave_max(v[k]) : wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[k][w] = v[k];
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double a = sh[k][0];
+    for (int i = 1; i < kWaves; ++i) a = ((MAXMASK >> k) & 1u) ? fmax(a, sh[k][i]) : a + sh[k][i];
+    v[k] = a;
+  }
+  lds_barrier();
 }
 
 // 2D/3D cell coordinates: c[0] = i, then (j,) k.

@@ -25,7 +25,7 @@ namespace {
 // Capacity of the static work area: meshes of up to 2^20 cells.
 constexpr long kStaticMaxCells = 1L << 20;
 constexpr int kStaticVectors = 7;             // r, r1, p0, p1, q, q1, 1/diag
-constexpr long kStaticIterParts = 7L * 65536;  // 7 partials per iteration-kernel workgroup
+constexpr long kStaticIterParts = 7L * 65536;  // 7 partials per iteration-kernel workgroup, two parity sets
 constexpr long kStaticSetupParts = 3L * kMaxZBlocks;  // set-up: 2 + 1 per workgroup
 constexpr long kStaticScalarDoubles = 32;     // one CgScalars (256 bytes)
 constexpr long kStaticDoubles =
@@ -130,7 +130,7 @@ gea_status gea_pressure_solve_static(const gea_mesh* mesh, const double* c, cons
   const Geo G = mesh_geo(*mesh);
   const int ns = iter_grid<double>(G);
   const int nzb = zplan(G).blocks;
-  if ((long)7 * ns > kStaticIterParts || nzb > kMaxZBlocks)
+  if ((long)14 * ns > kStaticIterParts || nzb > kMaxZBlocks)
     return fail(GEA_ERR_ARG, "gea_pressure_solve_static: mesh shape needs more partial sums "
                              "than its static work area holds");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -189,8 +189,8 @@ gea_status gea_pressure_solve_static(const gea_mesh* mesh, const double* c, cons
   while (!hs.done) {
     if (j > cap) return fail(GEA_ERR_HIP, "gea_pressure_solve_static: solver flag never set");
     for (int k = 0; k < batch; ++k, ++j) {
-      cg_iter_kernel<double>(s, G, v, (int)j, w);
-      cg_scalars(s, G, (int)j, w);
+      cg_iter_kernel<double>(s, G, v, (int)j, w, k > 0);
+      if (k == batch - 1 || !cg_folds(w)) cg_scalars(s, G, (int)j, w);
     }
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "CG iteration launch");
     if ((e = read()) != hipSuccess) return hip_fail(e, "reading the solver scalars");

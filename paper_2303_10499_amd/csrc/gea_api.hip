@@ -707,6 +707,13 @@ gea_status solve_pcg64(gea_ctx* x, double* xv, gea_solve_stats* out) {
 }
 
 // FP64 outer residual + FP32 inner Jacobi-PCG on the correction.
+// An inner solve goes out unread behind its residual check when the same
+// check did not converge last step and the solve's length is known: a batch
+// of that length and a margin, then the correction and (next pass) the
+// following check, both gated on the inner solve being done, so that one
+// read covers all three (as the learned form's inner solves do).  When the
+// batch fell short, the gated kernels did nothing and the same solve
+// continues after the read.
 gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   const Geo& G = x->G;
   const CgWork& w = x->w32;
@@ -715,6 +722,17 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   int total = 0;
   int outer = 0;
   CgScalars h64, h32;
+  bool unread = false;
+  int unread_n = 0;      // launches of the unread solve's batch
+  int unread_outer = 0;  // the check it follows
+  CgScalars s_res{}, s_cg{};
+  auto iterate = [&](int j, bool fold, bool last) {
+    x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w, fold); });
+    if (last || !cg_folds(w)) x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
+  };
+  auto last32_of = [&](int o) -> int& {
+    return x->last_iters32[x->corr < 8 ? x->corr : 7][o < 3 ? o : 3];
+  };
   out->rel_res0 = -1.0;
   out->status = GEA_OK;
   for (int guard = 0;; ++guard) {
@@ -722,12 +740,55 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->status = GEA_ERR_NOCONV;
       break;
     }
-    const int budget = x->prm.max_iter - total;
-    residual_check(x, xv, v, budget, true);
+    const int budget = x->prm.max_iter - total - (unread ? unread_n : 0);
+    // behind an unread inner solve the check acts only if that solve is done
+    residual_check(x, xv, v, budget, true, unread ? x->sc32 : nullptr);
     HIPCHK(hipGetLastError());
+    if (!unread && last32_of(outer) > 0 && x->predict_unconv(outer)) {
+      // (were this check converged after all, the inner system starts done,
+      // its iterate zero, and the correction adds zero)
+      snapshot(x, x->sc, &s_res, sizeof s_res);
+      const int n = last32_of(outer);
+      unread_n = n + 4 + n / 32;
+      for (int j = 0; j < unread_n; ++j) iterate(j, j > 0, j == unread_n - 1);
+      HIPCHK(hipGetLastError());
+      snapshot(x, x->sc32, &s_cg, sizeof s_cg);
+      x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32); });
+      unread = true;
+      unread_outer = outer;
+      ++outer;
+      continue;
+    }
     const bool spec = x->predict_conv(outer);
     if (spec) (*x->tail)();
     read_scalars(x, x->sc, &h64, Extra{x->sc32, &h32, sizeof h32});
+    if (unread) {  // the inner solve enqueued unread, and the check before it
+      unread = false;
+      x->note_conv(unread_outer, s_res.done != 0);
+      if (out->rel_res0 < 0) out->rel_res0 = s_res.bb > 0 ? std::sqrt(s_res.rr / s_res.bb) : 0.0;
+      total += s_cg.iter;
+      if (s_cg.status == -5) {
+        out->status = GEA_ERR_NAN;
+        break;
+      }
+      if (!s_cg.done) {
+        // The batch ended before the solve did (h32 holds its scalars as the
+        // batch left them): continue it at the next iteration, then correct.
+        const int before = h32.iter;
+        const int left = x->prm.max_iter - total;
+        gea_status rc = run_cg(x, x->sc32, h32, left > 0 ? left : 1, 0, iterate, Extra{}, unread_n);
+        if (rc != GEA_OK) return rc;
+        total += h32.iter - before;
+        last32_of(unread_outer) = h32.iter;
+        if (h32.status == -5) {
+          out->status = GEA_ERR_NAN;
+          break;
+        }
+        x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+        continue;
+      }
+      last32_of(unread_outer) = s_cg.iter;
+    }
     x->note_conv(outer, h64.done != 0);
     x->last_h64 = h64;
     const double rel = h64.bb > 0 ? std::sqrt(h64.rr / h64.bb) : 0.0;
@@ -750,14 +811,11 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->status = GEA_ERR_NOCONV;
       break;
     }
-    int& last32 = x->last_iters32[x->corr < 8 ? x->corr : 7][outer < 3 ? outer : 3];
+    int& last32 = last32_of(outer);
     const int first = last32 > 0 ? (int)(0.9 * last32) : 0;
     gea_status rc = run_cg(
         x, x->sc32, h32, budget, first,
-        [&](int j, bool fold, bool last) {
-          x->timer.run(2, x->stream, [&] { cg_iter_kernel<float>(x->stream, G, v, j, w, fold); });
-          if (last || !cg_folds(w)) x->timer.run(3, x->stream, [&] { cg_scalars(x->stream, G, j, w); });
-        },
+        [&](int j, bool fold, bool last) { iterate(j, fold, last); },
         Extra{}, 0, x->prm.solver == GEA_LEARNED_MIXED);
     if (rc != GEA_OK) return rc;
     last32 = h32.iter;

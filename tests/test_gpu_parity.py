@@ -136,6 +136,8 @@ def test_pressure_system_and_solve_match_oracle(oracle_lib, gea_mod):
     ("bubble3d_256x256x128", (13, 9, 11), 5),          # ragged 3D
     ("bubble3d_256x256x128", (70, 9, 10), 3),          # 3D halos across x and y tiles
     ("bubble3d_256x256x128", (20, 150, 12), 2),        # several z chunks, ragged last chunk
+    ("bubble3d_256x256x128", (20, 65, 12), 2),         # a last chunk of one plane (64 + 1)
+    ("bubble3d_256x256x128", (20, 130, 12), 2),        # a last chunk of two planes (64 + 64 + 2)
 ])
 def test_steps_match_oracle(oracle_lib, gea_mod, name, dims, steps):
     nx, nz, ny = dims

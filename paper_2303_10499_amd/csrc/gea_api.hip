@@ -1186,8 +1186,9 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
   const bool enth = x->prm.energy_form == 1;
   const bool implicit = x->prm.transport == 1;
   x->timer.run(5, x->stream, [&] {
+    // (explicit transport: K* into ea for the energy sweeps)
     launch_step1(s, G, ph, S.rho, S.u, S.T, S.pp, S.phi, x->rho_star, x->e0, x->ustar, pp_out,
-                 implicit ? x->trb : nullptr);
+                 implicit ? x->trb : nullptr, implicit ? nullptr : x->ea);
   });
   if (implicit) {
     // Step 1's momentum predictor implicit: per component from the explicit
@@ -1221,34 +1222,34 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
     if (transport_iters) *transport_iters += its;
     if (rc != GEA_OK) return rc;
     x->timer.run(5, x->stream, [&] {
-      launch_energy_post(s, G, ph, enth, T_out, x->ustar, x->ea, true, S.p, x->rho_star, x->rho23,
-                         x->psi, x->c, x->D);
+      launch_energy_post(s, G, ph, T_out, S.p, x->rho_star, x->rho23, x->psi, x->c, x->D);
     });
     x->sys32 = false;
     return GEA_OK;
   }
-  const double* e_prev = x->e0;
+  const double* Ks = x->ea;  // K*, from Step 1
   if (enth) {
-    // e0 becomes the sweep-independent balance, eb the first sweep's c_p T + K*;
-    // the next state's p^n, K^n go to the other state's history arrays
+    // e0 becomes the sweep-independent balance; the next state's p^n, K^n go
+    // to the other state's history arrays
     const State& N = x->st[1 - x->cur];
     ensure_history(x);
     x->timer.run(5, x->stream, [&] {
       launch_enthalpy_prep(s, G, ph, S.rho, S.T, S.p, S.pm, S.Km, S.u, x->ustar, x->rho_star,
                            x->e0, x->eb, N.pm, N.Km);
     });
-    e_prev = x->eb;
   }
   const double* T_prev = S.T;
   const int ns = x->prm.n_energy_sweeps;
   for (int sw = 0; sw < ns; ++sw) {
     const bool last = sw == ns - 1;
-    double* e_next = (sw & 1) ? x->eb : x->ea;
+    // the first total-energy sweep transports e^n + R T^n; every other sweep
+    // forms its transported quantity from T^(s-1) and K*
+    const bool ks = enth || sw > 0;
     double* T_next = last ? T_out : ((sw & 1) ? x->Tb : x->Ta);
     int nparts = 0;
     x->timer.run(5, x->stream, [&] {
-      nparts = launch_energy_rhs(s, G, ph, enth, S.rho, x->e0, e_prev, T_prev, S.phi, x->rho_star,
-                                 x->ustar, x->Tbg, x->b, x->c, x->dinv, T_next, x->r, x->p0,
+      nparts = launch_energy_rhs(s, G, ph, enth, ks, S.rho, x->e0, ks ? Ks : x->e0, T_prev, S.phi,
+                                 x->rho_star, Ks, x->Tbg, x->b, x->c, x->dinv, T_next, x->r, x->p0,
                                  x->w64.u[1], x->w64.b);
     });
     HIPCHK(hipGetLastError());
@@ -1256,11 +1257,10 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
     gea_status rc = solve_energy(x, T_next, nparts, sw, &its);
     if (energy_iters) *energy_iters += its;
     if (rc != GEA_OK) return rc;
-    x->timer.run(5, x->stream, [&] {
-      launch_energy_post(s, G, ph, enth, T_next, x->ustar, e_next, last, S.p, x->rho_star, x->rho23,
-                         x->psi, x->c, x->D);
-    });
-    e_prev = e_next;
+    if (last)
+      x->timer.run(5, x->stream, [&] {
+        launch_energy_post(s, G, ph, T_next, S.p, x->rho_star, x->rho23, x->psi, x->c, x->D);
+      });
     T_prev = T_next;
   }
   x->sys32 = false;  // c and D changed

@@ -96,26 +96,30 @@ void launch_face_mass_flux(hipStream_t s, const Geo& G, const double* rho, doubl
 void launch_clear_wall_faces(hipStream_t s, const Geo& G, double* const* phi);
 // Step 1 (rho* from the state's face flux phi, e^n, momentum predictor): one
 // pass in 3D, the two kernels in 2D; pp_copy (or null) also receives p' (the
-// solve's initial guess)
+// solve's initial guess), Ks (or null) K* = |u*|^2/2 for the energy sweeps
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
                   double* rho_star, double* e0, double* const* u_star, double* pp_copy,
-                  double* const* b_out = nullptr);  // b_out: implicit transport's V (rho u/dt - R(F))
+                  double* const* b_out = nullptr,  // b_out: implicit transport's V (rho u/dt - R(F))
+                  double* Ks = nullptr);
 // Step 2, one sweep: the right-hand side b, coefficient c and 1/diag of the
 // implicit-diffusion system for T, the initial guess x = T_prev, and the
 // solve's set-up (r = b - A x, p0 = 0, partials <r, r/diag>, ||r||^2 in
 // u_part and ||b||^2 in b_part, one per workgroup); returns the workgroup
-// count (k_cg_start's nu).  The system's D is (mu/Pr) c_p everywhere.
-int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* rho,
-                      const double* e0, const double* e_prev, const double* T_prev,
-                      double* const* phi, const double* rho_star, double* const* u_star,
-                      const double* Tbg, double* b, double* c, double* dinv, double* x, double* r,
-                      double* p0, double* u_part, double* b_part);
-// after a sweep's solve: e = c_v T + K* + Phi, or after the last sweep the
-// EOS density and pressure-equation coefficients rho23, psi, c, D
-void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* T,
-                        double* const* u_star, double* e, bool last, const double* p,
-                        const double* rho_star, double* rho23, double* psi, double* c, double* D);
+// count (k_cg_start's nu).  The system's D is (mu/Pr) c_p everywhere.  The
+// sweep stages a_prev and T_prev: with ks (and always in the enthalpy form)
+// a_prev = Ks (K*, from Step 1) and the transported quantity is formed from
+// T and K*; else (the first total-energy sweep) a_prev = e^n.
+int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, bool ks,
+                      const double* rho, const double* e0, const double* a_prev,
+                      const double* T_prev, double* const* phi, const double* rho_star,
+                      const double* Ks, const double* Tbg, double* b, double* c, double* dinv,
+                      double* x, double* r, double* p0, double* u_part, double* b_part);
+// after the last sweep's solve: the EOS density and pressure-equation
+// coefficients rho23, psi, c, D
+void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
+                        const double* p, const double* rho_star, double* rho23, double* psi,
+                        double* c, double* D);
 // Step 2 in enthalpy form (enth = true above): p^{n-1} = p, K^{n-1} = |u|^2/2
 // for a state without history; and the sweep-independent balance q, the
 // first sweep's transported c_p T + K*, and the next state's p^n, K^n

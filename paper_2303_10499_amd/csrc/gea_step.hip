@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
                                                         const double* __restrict__ rho_star,
                                                         Vec<NDIM> phi, Vec<NDIM> u_star,
                                                         double* __restrict__ pp_copy,
-                                                        Vec<NDIM> b_out) {
+                                                        Vec<NDIM> b_out, double* __restrict__ Ks) {
   constexpr int Z = NDIM - 1;
   const Col c = col_of<NDIM>(G, kc);
   if (!c.act) return;
@@ -238,11 +238,14 @@ __global__ __launch_bounds__(kBlock) void k_mom_predict(Geo G, Phys ph, int kc,
       // implicit transport: the predictor system's right-hand side V (rho u/dt - R(F))
       if (b_out.p[0]) b_out.p[cc][P] = G.V * (r * z[cc].c / ph.dt - RF);
     }
+    double ks = 0.0;
 #pragma unroll
     for (int cc = 0; cc < NDIM; ++cc) {
       u_star.p[cc][P] = us[cc];
+      ks += us[cc] * us[cc];
       z[cc] = shift(z[cc], k + 3 < nz ? zn[cc] : 0.0);
     }
+    if (Ks) Ks[P] = 0.5 * ks;  // K* for the energy sweeps
     if (pp_copy) pp_copy[P] = pc;
     Flo = Fhi;
   }
@@ -264,7 +267,8 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
                                                     const double* __restrict__ pp, Vec<3> phi,
                                                     double* __restrict__ rho_star,
                                                     double* __restrict__ e0, Vec<3> u_star,
-                                                    double* __restrict__ pp_copy, Vec<3> b_out) {
+                                                    double* __restrict__ pp_copy, Vec<3> b_out,
+                                                    double* __restrict__ Ks) {
   using St = Stage3<2, TY>;
   using St1 = Stage3<1, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
@@ -435,8 +439,13 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
       const int P = qo + pl * k;
       rho_star[P] = rs;
       e0[P] = e0c;
+      double ks = 0.0;
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) u_star.p[cc][P] = us[cc];
+      for (int cc = 0; cc < 3; ++cc) {
+        u_star.p[cc][P] = us[cc];
+        ks += us[cc] * us[cc];
+      }
+      if (Ks) Ks[P] = 0.5 * ks;  // K* for the energy sweeps
       if (pp_copy) pp_copy[P] = pc;
     }
     Flo = Fhi;
@@ -467,31 +476,50 @@ struct EnergySys {
   double* b_part;
 };
 
+// The quantity a sweep transports, on a line of cells, from the two fields
+// the sweep stages (a, T): KS false (the first sweep of the total-energy
+// form): a = e^n and the quantity is e + R T; KS true: a = K* (written by
+// Step 1) and the quantity is (c_v + R) T + K* + Phi (total energy: e + R T
+// with e = c_v T + K* + Phi, so no pass forms e between sweeps) or c_p T + K*
+// (enthalpy form).  kz: the line's centre plane; along z (zl) Phi changes
+// from cell to cell, across a plane it does not.
+template <bool ENTH, bool KS>
+__device__ __forceinline__ Line transported(const Geo& G, const Phys& ph, const Line& a,
+                                            const Line& T, int kz, bool zl) {
+  auto one = [&](double av, double Tv, int kk) {
+    if (!KS) return ENTH ? av : av + ph.R * Tv;
+    return ENTH ? ph.cp * Tv + av : (ph.cv + ph.R) * Tv + av + phi_cell(G, ph, kk);
+  };
+  const int d = zl ? 1 : 0;
+  return Line{one(a.m2, T.m2, kz - 2 * d), one(a.m1, T.m1, kz - d), one(a.c, T.c, kz),
+              one(a.p1, T.p1, kz + d), one(a.p2, T.p2, kz + 2 * d)};
+}
+
 // ENTH: the enthalpy form (eq. step3_sd): e0 holds the sweep-independent
 // balance q = rho^n c_p T^n + rho^n K^{n-1} - p^{n-1} - rho* K* + p^n
-// - dt rho* g w*, e_prev the transported c_p T^(s-1) + K*, and the unknown's
-// coefficient is rho* c_p V/dt.  Otherwise (total energy) e0 = e^n, e_prev =
-// e^(s-1) and the transported quantity is e + R T.
-template <int NDIM, bool ENTH>
+// - dt rho* g w*, the transported quantity is c_p T^(s-1) + K*, and the
+// unknown's coefficient is rho* c_p V/dt.  Otherwise (total energy) e0 = e^n
+// and the transported quantity is e + R T of the previous sweep.  KS: the
+// sweep stages T^(s-1) and K* (a_prev = K*), else e^n and T^n (a_prev = e^n,
+// the first sweep of the total-energy form); see transported().
+template <int NDIM, bool ENTH, bool KS>
 __global__ __launch_bounds__(kBlock) void k_energy_rhs(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
-    const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<NDIM> phi,
-    const double* __restrict__ rho_star, Vec<NDIM> u_star, const double* __restrict__ Tbg,
-    EnergySys sy) {
+    const double* __restrict__ a_prev, const double* __restrict__ T_prev, Vec<NDIM> phi,
+    const double* __restrict__ rho_star, const double* __restrict__ Ks,
+    const double* __restrict__ Tbg, EnergySys sy) {
   constexpr int Z = NDIM - 1;
   const Col c = col_of<NDIM>(G, kc);
   double red[3] = {0.0, 0.0, 0.0};
   if (c.act) {
     const int nz = G.n[Z], pl = c.pl;
     int P = c.base + pl * c.k0;
-    Line ze = line_at([&](int Q) { return e_prev[Q]; }, P, pl, c.k0, nz);
+    Line ze = line_at([&](int Q) { return a_prev[Q]; }, P, pl, c.k0, nz);
     Line zT = line_at([&](int Q) { return T_prev[Q]; }, P, pl, c.k0, nz);
-    auto hhat = [&](const Line& e, const Line& T) {
-      if (ENTH) return e;
-      return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
-                  e.p2 + ph.R * T.p2};
+    auto hhat = [&](const Line& a, const Line& T, int kz, bool zl) {
+      return transported<ENTH, KS>(G, ph, a, T, kz, zl);
     };
-    double flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hhat(ze, zT), c.k0, nz) : 0.0;
+    double flo = c.k0 > 0 ? phi.p[Z][P - pl] * i4_lo(hhat(ze, zT, c.k0, true), c.k0, nz) : 0.0;
     const double kcoef = ph.mu / ph.Pr * ph.cp;
     const double kdz = kcoef * G.S[Z] / G.h[Z];      // background part of the flux
     const double wz = kcoef * (G.S[Z] / G.h[Z]);    // operator weight (D = kcoef on both sides)
@@ -503,29 +531,27 @@ __global__ __launch_bounds__(kBlock) void k_energy_rhs(
 #pragma unroll
       for (int d = 0; d < Z; ++d) {
         const int st = G.st[d], n = G.n[d], q = coord(c, d);
-        le[d] = line_at([&](int Q) { return e_prev[Q]; }, P, st, q, n);
+        le[d] = line_at([&](int Q) { return a_prev[Q]; }, P, st, q, n);
         lT[d] = line_at([&](int Q) { return T_prev[Q]; }, P, st, q, n);
         fhi[d] = phi.p[d][P];
         flod[d] = phi.p[d][nb(q > 0, P - st, P)];
       }
       const double phz = phi.p[Z][P], rs = rho_star[P], r = rho[P], e0c = e0[P];
-      double us[NDIM];
-#pragma unroll
-      for (int d = 0; d < NDIM; ++d) us[d] = u_star.p[d][P];
-      const double e_n = e_prev[Pn], T_n = T_prev[Pn];
+      const double ks = KS ? ze.c : Ks[P];  // K* of the cell
+      const double e_n = a_prev[Pn], T_n = T_prev[Pn];
       const double tb = Tbg[k], tb_up = Tbg[k + 1 < nz ? k + 1 : k], tb_dn = Tbg[k > 0 ? k - 1 : k];
       // convective flux of e + R T
       double conv = 0.0;
 #pragma unroll
       for (int d = 0; d < Z; ++d) {
         const int n = G.n[d], q = coord(c, d);
-        const Line h = hhat(le[d], lT[d]);
+        const Line h = hhat(le[d], lT[d], k, false);
         conv = q + 1 < n ? conv + fhi[d] * i4_hi(h, q, n) : conv;
         conv = q > 0 ? conv - flod[d] * i4_lo(h, q, n) : conv;
       }
       double fh = 0.0;
       if (k + 1 < nz) {
-        fh = phz * i4_hi(hhat(ze, zT), k, nz);
+        fh = phz * i4_hi(hhat(ze, zT, k, true), k, nz);
         conv += fh;
       }
       if (k > 0) conv -= flo;
@@ -534,10 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_rhs(
       double bg = 0.0;
       if (k + 1 < nz) bg += kdz * (tb - tb_up);
       if (k > 0) bg += kdz * (tb - tb_dn);
-      double kin = 0.0;
-#pragma unroll
-      for (int d = 0; d < NDIM; ++d) kin += us[d] * us[d];
-      const double rest = 0.5 * kin + phi_cell(G, ph, k);
+      const double rest = ks + phi_cell(G, ph, k);
       const double bP = ENTH ? G.V / ph.dt * e0c - conv + bg : G.V / ph.dt * (r * e0c - rs * rest) - conv + bg;
       const double cP = rs * (ENTH ? ph.cp : ph.cv) * G.V / ph.dt;
       // operator on the initial guess and the diagonal
@@ -630,31 +653,22 @@ __global__ __launch_bounds__(kBlock) void k_enthalpy_prep(
   }
 }
 
-// After sweep s's solve: e = c_v T + K* + Phi for the next sweep, or (after
-// the last sweep) the EOS density of eq. step3_3sd and the pressure-equation
-// coefficients: rho^{n+2/3} = p^n/(R T^{n+1}), psi = 1/(R T), c = psi V/dt,
-// D = rho^{n+2/3} dt/rho*.
-template <int NDIM, bool LAST, bool ENTH>
+// After the last sweep's solve: the EOS density of eq. step3_3sd and the
+// pressure-equation coefficients: rho^{n+2/3} = p^n/(R T^{n+1}),
+// psi = 1/(R T), c = psi V/dt, D = rho^{n+2/3} dt/rho*.  (Between sweeps no
+// pass is needed: the next sweep forms its transported quantity from T and
+// K*, see transported().)
 __global__ __launch_bounds__(kBlock) void k_energy_post(
-    Geo G, Phys ph, const double* __restrict__ T, Vec<NDIM> u_star, double* __restrict__ e,
-    const double* __restrict__ p, const double* __restrict__ rho_star, double* __restrict__ rho23,
-    double* __restrict__ psi, double* __restrict__ cc, double* __restrict__ D) {
+    Geo G, Phys ph, const double* __restrict__ T, const double* __restrict__ p,
+    const double* __restrict__ rho_star, double* __restrict__ rho23, double* __restrict__ psi,
+    double* __restrict__ cc, double* __restrict__ D) {
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < G.nc; P += gridDim.x * blockDim.x) {
     const double Tc = T[P];
-    if (LAST) {
-      const double r23 = p[P] / (ph.R * Tc), ps = 1.0 / (ph.R * Tc);
-      rho23[P] = r23;
-      psi[P] = ps;
-      cc[P] = ps * G.V / ph.dt;
-      D[P] = r23 / (rho_star[P] / ph.dt);
-    } else {
-      double kin = 0.0;
-#pragma unroll
-      for (int d = 0; d < NDIM; ++d) kin += u_star.p[d][P] * u_star.p[d][P];
-      // the next sweep's transported quantity: c_p T + K* (enthalpy form) or
-      // e = c_v T + K* + Phi
-      e[P] = ENTH ? ph.cp * Tc + 0.5 * kin : ph.cv * Tc + 0.5 * kin + phi_cell(G, ph, P / G.st[NDIM - 1]);
-    }
+    const double r23 = p[P] / (ph.R * Tc), ps = 1.0 / (ph.R * Tc);
+    rho23[P] = r23;
+    psi[P] = ps;
+    cc[P] = ps * G.V / ph.dt;
+    D[P] = r23 / (rho_star[P] / ph.dt);
   }
 }
 
@@ -667,15 +681,15 @@ __global__ __launch_bounds__(kBlock) void k_energy_post(
 // separate loads of the column three planes up; held to 128 VGPRs (two
 // workgroups a CU, 9 registers spilled) 223 us; 64x4 tiles in 43-plane
 // chunks 222 us; 32-plane chunks 225 us.
-template <int TY, bool ENTH>
+template <int TY, bool ENTH, bool KS>
 __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     Geo G, Phys ph, int kc, const double* __restrict__ rho, const double* __restrict__ e0,
-    const double* __restrict__ e_prev, const double* __restrict__ T_prev, Vec<3> phi,
-    const double* __restrict__ rho_star, Vec<3> u_star, const double* __restrict__ Tbg,
-    EnergySys sy) {
+    const double* __restrict__ a_prev, const double* __restrict__ T_prev, Vec<3> phi,
+    const double* __restrict__ rho_star, const double* __restrict__ Ks,
+    const double* __restrict__ Tbg, EnergySys sy) {
   using St = Stage3<2, TY>;
   constexpr int Z = 2, HP = St::HP, HX = St::HX, NU = St::NU;
-  __shared__ double su[3][2][HP];  // e, T; plane k in slot (k - k0) % 3
+  __shared__ double su[3][2][HP];  // a (e^n or K*), T; plane k in slot (k - k0) % 3
   const Col c = col_of3<TY>(G, kc);
   const St st = stage3<2, TY>(G, c);
   const int nz = G.n[Z], pl = c.pl, qo = st.qo, ho = st.ho;
@@ -684,15 +698,15 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
   // highest plane the chunk's z lines read; planes above the chunk are
   // loaded for the own column only (the halo slots load it again)
   const int ktop = min(c.k1 + 1, nz - 1);
-  double fs[2][NU];                                    // staged plane in flight
-  double fh[2], fl[2], fz, frs, fr, fe0, fus[3];       // own cell's values of the next plane
+  double fs[2][NU];                             // staged plane in flight
+  double fh[2], fl[2], fz, frs, fr, fe0, fks;   // own cell's values of the next plane
   auto fetch = [&](int kk, double (&dst)[2][NU]) {
     const int kq = min(kk, ktop), o = pl * kq;
     const bool halo = kq < c.k1;
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
       const int Q = (halo ? st.q[m] : qo) + o;
-      dst[0][m] = e_prev[Q];
+      dst[0][m] = a_prev[Q];
       dst[1][m] = T_prev[Q];
     }
   };
@@ -706,8 +720,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     frs = rho_star[P];
     fr = rho[P];
     fe0 = e0[P];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) fus[d] = u_star.p[d][P];
+    if (!KS) fks = Ks[P];  // (KS: the staged own value)
   };
   auto stage = [&](int sl, const double (&src)[2][NU]) {
 #pragma unroll
@@ -716,10 +729,8 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
       for (int m = 0; m < NU; ++m)
         su[sl][f][st.h[m]] = src[f][m];
   };
-  auto hhat = [&](const Line& e, const Line& T) {
-    if (ENTH) return e;
-    return Line{e.m2 + ph.R * T.m2, e.m1 + ph.R * T.m1, e.c + ph.R * T.c, e.p1 + ph.R * T.p1,
-                e.p2 + ph.R * T.p2};
+  auto hhat = [&](const Line& a, const Line& T, int kz, bool zl) {
+    return transported<ENTH, KS>(G, ph, a, T, kz, zl);
   };
   // the z lines hold planes k0-3 .. k0+1 before the loop (k0-3 is never read)
   Line ze, zT;
@@ -729,9 +740,9 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     const int Q2 = nb(c.k0 >= 2, P - 2 * pl, P), Q1 = nb(c.k0 >= 1, P - pl, P);
     ze.m2 = 0.0;
     zT.m2 = 0.0;
-    ze.m1 = e_prev[Q2];
+    ze.m1 = a_prev[Q2];
     zT.m1 = T_prev[Q2];
-    ze.c = e_prev[Q1];
+    ze.c = a_prev[Q1];
     zT.c = T_prev[Q1];
     const double phz_lo = c.k0 > 0 ? phi.p[Z][P - pl] : 0.0;
     double f1[2][NU];  // the chunk's first two planes are loaded together
@@ -744,7 +755,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     ze.p2 = f1[0][0];
     zT.p2 = f1[1][0];
     const Line Le{ze.m1, ze.c, ze.p1, ze.p2, 0.0}, LT{zT.m1, zT.c, zT.p1, zT.p2, 0.0};  // centred on k0
-    flo = c.k0 > 0 ? phz_lo * i4_lo(hhat(Le, LT), c.k0, nz) : 0.0;
+    flo = c.k0 > 0 ? phz_lo * i4_lo(hhat(Le, LT, c.k0, true), c.k0, nz) : 0.0;
   }
   own(c.k0);
   fetch(c.k0 + 2, fs);
@@ -761,7 +772,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     zT = shift(zT, fs[1][0]);
     const double fhi[2] = {fh[0], fh[1]}, flod[2] = {fl[0], fl[1]};
     const double phz = fz, rs = frs, r = fr, e0c = fe0;
-    const double us[3] = {fus[0], fus[1], fus[2]};
+    const double ks = KS ? ze.c : fks;  // K* of the cell
     const double tb = Tbg[k], tb_up = Tbg[k + 1 < nz ? k + 1 : k], tb_dn = Tbg[k > 0 ? k - 1 : k];
     own(k + 1);
     fetch(k + 3, fs);
@@ -775,13 +786,13 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
 #pragma unroll
     for (int d = 0; d < Z; ++d) {
       const int n = G.n[d], q = coord(c, d);
-      const Line h = hhat(le[d], lT[d]);
+      const Line h = hhat(le[d], lT[d], k, false);
       conv = q + 1 < n ? conv + fhi[d] * i4_hi(h, q, n) : conv;
       conv = q > 0 ? conv - flod[d] * i4_lo(h, q, n) : conv;
     }
     double fhz = 0.0;
     if (k + 1 < nz) {
-      fhz = phz * i4_hi(hhat(ze, zT), k, nz);
+      fhz = phz * i4_hi(hhat(ze, zT, k, true), k, nz);
       conv += fhz;
     }
     if (k > 0) conv -= flo;
@@ -789,10 +800,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     double bg = 0.0;
     if (k + 1 < nz) bg += kdz * (tb - tb_up);
     if (k > 0) bg += kdz * (tb - tb_dn);
-    double kin = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) kin += us[d] * us[d];
-    const double rest = 0.5 * kin + phi_cell(G, ph, k);
+    const double rest = ks + phi_cell(G, ph, k);
     const double bP = ENTH ? G.V / ph.dt * e0c - conv + bg : G.V / ph.dt * (r * e0c - rs * rest) - conv + bg;
     const double cP = rs * (ENTH ? ph.cp : ph.cv) * G.V / ph.dt;
     const double xc = zT.c;
@@ -1790,61 +1798,50 @@ void launch_clear_wall_faces(hipStream_t s, const Geo& G, double* const* phi) {
 void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                   double* const* u, const double* T, const double* pp, double* const* phi,
                   double* rho_star, double* e0, double* const* u_star, double* pp_copy,
-                  double* const* b_out) {
+                  double* const* b_out, double* Ks) {
   double* const nob[3] = {nullptr, nullptr, nullptr};
   double* const* bo = b_out ? b_out : nob;
   if (G.ndim == 2) {
     const ZPlan zp = zplan(G);
     hipLaunchKernelGGL(k_density_predictor<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), T, V2(phi), rho_star, e0);
-    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star), pp_copy, V2(bo));
+    hipLaunchKernelGGL(k_mom_predict<2>, dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, V2(u), pp, rho_star, V2(phi), V2(u_star), pp_copy, V2(bo), Ks);
     return;
   }
   const ZPlan zp3 = zplan3(G, kTyStep1, kKcStep1);
-  hipLaunchKernelGGL(k_step1_3<kTyStep1>, dim3(zp3.blocks), dim3(64 * kTyStep1), 0, s, G, ph, zp3.kc, rho, V3(u), T, pp, V3(phi), rho_star, e0, V3(u_star), pp_copy, V3(bo));
+  hipLaunchKernelGGL(k_step1_3<kTyStep1>, dim3(zp3.blocks), dim3(64 * kTyStep1), 0, s, G, ph, zp3.kc, rho, V3(u), T, pp, V3(phi), rho_star, e0, V3(u_star), pp_copy, V3(bo), Ks);
 }
 
-int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* rho,
-                      const double* e0, const double* e_prev, const double* T_prev,
-                      double* const* phi, const double* rho_star, double* const* u_star,
-                      const double* Tbg, double* b, double* c, double* dinv, double* x, double* r,
-                      double* p0, double* u_part, double* b_part) {
+int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, bool ks,
+                      const double* rho, const double* e0, const double* a_prev,
+                      const double* T_prev, double* const* phi, const double* rho_star,
+                      const double* Ks, const double* Tbg, double* b, double* c, double* dinv,
+                      double* x, double* r, double* p0, double* u_part, double* b_part) {
   const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy, kKcEnergy) : zp;
   const EnergySys sy{b, c, dinv, x, r, p0, u_part, b_part};
+  // (the enthalpy form always stages T and K*)
   if (G.ndim == 2) {
     if (enth)
-      hipLaunchKernelGGL((k_energy_rhs<2, true>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, sy);
+      hipLaunchKernelGGL((k_energy_rhs<2, true, true>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, a_prev, T_prev, V2(phi), rho_star, Ks, Tbg, sy);
+    else if (ks)
+      hipLaunchKernelGGL((k_energy_rhs<2, false, true>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, a_prev, T_prev, V2(phi), rho_star, Ks, Tbg, sy);
     else
-      hipLaunchKernelGGL((k_energy_rhs<2, false>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, e_prev, T_prev, V2(phi), rho_star, V2(u_star), Tbg, sy);
+      hipLaunchKernelGGL((k_energy_rhs<2, false, false>), dim3(zp.blocks), dim3(kBlock), 0, s, G, ph, zp.kc, rho, e0, a_prev, T_prev, V2(phi), rho_star, Ks, Tbg, sy);
     return zp.blocks;
   }
   if (enth)
-    hipLaunchKernelGGL((k_energy_rhs3<kTyEnergy, true>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, sy);
+    hipLaunchKernelGGL((k_energy_rhs3<kTyEnergy, true, true>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, a_prev, T_prev, V3(phi), rho_star, Ks, Tbg, sy);
+  else if (ks)
+    hipLaunchKernelGGL((k_energy_rhs3<kTyEnergy, false, true>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, a_prev, T_prev, V3(phi), rho_star, Ks, Tbg, sy);
   else
-    hipLaunchKernelGGL((k_energy_rhs3<kTyEnergy, false>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, e_prev, T_prev, V3(phi), rho_star, V3(u_star), Tbg, sy);
+    hipLaunchKernelGGL((k_energy_rhs3<kTyEnergy, false, false>), dim3(zp3.blocks), dim3(64 * kTyEnergy), 0, s, G, ph, zp3.kc, rho, e0, a_prev, T_prev, V3(phi), rho_star, Ks, Tbg, sy);
   return zp3.blocks;
 }
 
-template <int NDIM>
-static void energy_post_nd(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* T,
-                           double* const* u_star, double* e, bool last, const double* p,
-                           const double* rho_star, double* rho23, double* psi, double* c, double* D) {
-  const dim3 grid(grid_for(G.nc)), block(kBlock);
-  const Vec<NDIM> us = vec<NDIM>(u_star);
-  if (last)
-    hipLaunchKernelGGL((k_energy_post<NDIM, true, false>), grid, block, 0, s, G, ph, T, us, e, p, rho_star, rho23, psi, c, D);
-  else if (enth)
-    hipLaunchKernelGGL((k_energy_post<NDIM, false, true>), grid, block, 0, s, G, ph, T, us, e, p, rho_star, rho23, psi, c, D);
-  else
-    hipLaunchKernelGGL((k_energy_post<NDIM, false, false>), grid, block, 0, s, G, ph, T, us, e, p, rho_star, rho23, psi, c, D);
-}
-
-void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, bool enth, const double* T,
-                        double* const* u_star, double* e, bool last, const double* p,
-                        const double* rho_star, double* rho23, double* psi, double* c, double* D) {
-  if (G.ndim == 2)
-    energy_post_nd<2>(s, G, ph, enth, T, u_star, e, last, p, rho_star, rho23, psi, c, D);
-  else
-    energy_post_nd<3>(s, G, ph, enth, T, u_star, e, last, p, rho_star, rho23, psi, c, D);
+void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const double* T,
+                        const double* p, const double* rho_star, double* rho23, double* psi,
+                        double* c, double* D) {
+  hipLaunchKernelGGL(k_energy_post, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G, ph, T, p, rho_star,
+                     rho23, psi, c, D);
 }
 
 void launch_history_init(hipStream_t s, const Geo& G, const double* p, double* const* u,

@@ -625,8 +625,10 @@ NetGate& net_gate(gea_ctx* x) {
 // FP32 copies of the operator from the same pass.
 // With xv given, a refined form's first residual check on xv (the solve's
 // initial guess) is formed in the same pass (3D); the solve then starts
-// from its one-workgroup check.
-void build_system(gea_ctx* x, const State& S, const double* xv = nullptr) {
+// from its one-workgroup check.  coeffs = false: 1/diag and the FP32 copies
+// of c, D, 1/diag are those an earlier corrector of the step wrote (c and D
+// change only in Step 2), and only b (and the residual) are formed.
+void build_system(gea_ctx* x, const State& S, const double* xv = nullptr, bool coeffs = true) {
   const bool f32 = x->prm.solver != GEA_PCG_JACOBI_FP64;
   x->net_now = x->prm.solver == GEA_LEARNED_MIXED && x->has_net &&
                (x->prm.learned_always || net_gate(x).use(x->t_net_ms, x->t_iter_ms));
@@ -634,9 +636,11 @@ void build_system(gea_ctx* x, const State& S, const double* xv = nullptr) {
   // cleared inner iterate or direction
   const bool zero_inner = !x->net_now;
   const RhsResidual res{xv, x->r32, x->d32, x->p032, (int)zero_inner, x->o_part, x->w32.u[1]};
+  const bool c32 = f32 && (coeffs || !x->sys32);
   x->res_parts = launch_rhs(x->stream, x->G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H,
-                            x->b, x->dinv, f32 ? x->c32 : nullptr, f32 ? x->D32 : nullptr,
-                            f32 ? x->dinv32 : nullptr, f32 && xv ? &res : nullptr);
+                            x->b, coeffs ? x->dinv : nullptr, c32 ? x->c32 : nullptr,
+                            c32 ? x->D32 : nullptr, c32 ? x->dinv32 : nullptr,
+                            f32 && xv ? &res : nullptr);
   x->sys32 = f32;
 }
 
@@ -1283,7 +1287,8 @@ gea_status one_step(gea_ctx* x, gea_step_stats* stats) {
     const bool last = k == nc - 1;
     x->corr = k;  // (the learned form's gate decides per corrector, before the assembly)
     x->timer.run(5, x->stream, [&] { launch_H(s, G, ph, S.rho, S.u, x->ustar, S.phi, x->H); });
-    x->timer.run(5, x->stream, [&] { build_system(x, S, N.pp); });
+    // (c, D and 1/diag change only in Step 2: later correctors form b only)
+    x->timer.run(5, x->stream, [&] { build_system(x, S, N.pp, k == 0); });
     HIPCHK(hipGetLastError());
     x->has_system = true;
     double* uo[3] = {x->ustar[0], x->ustar[1], x->ustar[2]};

@@ -136,7 +136,8 @@ void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, do
 int launch_rhs(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                 const double* rho23, const double* psi, const double* c, const double* D,
                 double* const* H, double* b, double* dinv, float* c32, float* D32,
-                float* dinv32,  // FP32 copies of c, D, 1/diag written unless c32 is null
+                float* dinv32,  // FP32 copies of c, D, 1/diag written unless c32 is null;
+                                // 1/diag written unless dinv is null
                 const RhsResidual* res = nullptr);  // returns the residual partials' count, 0: not formed
 void launch_correct(hipStream_t s, const Geo& G, const Phys& ph, const double* pp,
                     const double* rho23, const double* psi, double* const* H, const double* D,

@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo G, Phys ph, int kc,
     diag_lo = diag_hi;
     b[P] = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
     const double di = 1.0 / diag;
-    dinv[P] = di;
+    if (dinv) dinv[P] = di;  // (null: the coefficients of an earlier corrector stand)
     if (c32) {  // FP32 copies of the operator for the refined forms
       c32[P] = (float)cP;
       D32[P] = (float)Dc;
@@ -1269,7 +1269,7 @@ __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
       const double bp = G.V / ph.dt * (rP + psP * r23 * phc) - sum;
       b[P] = bp;
       const double di = 1.0 / diag;
-      dinv[P] = di;
+      if (dinv) dinv[P] = di;  // (null: the coefficients of an earlier corrector stand)
       if (c32) {  // FP32 copies of the operator for the refined forms
         c32[P] = (float)cP;
         D32[P] = (float)Dc;

@@ -635,7 +635,7 @@ void build_system(gea_ctx* x, const State& S, const double* xv = nullptr, bool c
   // the learned form's first inner solve is the flexible CG, which needs no
   // cleared inner iterate or direction
   const bool zero_inner = !x->net_now;
-  const RhsResidual res{xv, x->r32, x->d32, x->p032, (int)zero_inner, x->o_part, x->w32.u[1]};
+  const RhsResidual res{xv, x->r32, x->d32, (int)zero_inner, x->o_part, x->w32.u[1]};
   const bool c32 = f32 && (coeffs || !x->sys32);
   x->res_parts = launch_rhs(x->stream, x->G, x->ph, S.rho, x->rho23, x->psi, x->c, x->D, x->H,
                             x->b, coeffs ? x->dinv : nullptr, c32 ? x->c32 : nullptr,
@@ -1253,7 +1253,7 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
     int nparts = 0;
     x->timer.run(5, x->stream, [&] {
       nparts = launch_energy_rhs(s, G, ph, enth, ks, S.rho, x->e0, ks ? Ks : x->e0, T_prev, S.phi,
-                                 x->rho_star, Ks, x->Tbg, x->b, x->c, x->dinv, T_next, x->r, x->p0,
+                                 x->rho_star, Ks, x->Tbg, x->b, x->c, x->dinv, T_next, x->r,
                                  x->w64.u[1], x->w64.b);
     });
     HIPCHK(hipGetLastError());

@@ -305,7 +305,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geo G, Stencil<NDIM, T> K, C
       const T r = bp - A.at(G, K, c, P, k, v.c);
       A.next();
       v.r[P] = r;
-      v.p0[P] = T(0);
       const double rd = (double)r;
       red[0] += rd * (double)(r * di);
       red[1] += rd * rd;
@@ -754,10 +753,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(Geo G, Stencil<NDIM, doub
       A.next();
       const float rf = (float)r;
       v32.r[P] = rf;
-      if (zero_inner) {
-        v32.x[P] = 0.0f;
-        v32.p0[P] = 0.0f;
-      }
+      if (zero_inner) v32.x[P] = 0.0f;
       ro[0] += r * r;
       ro[1] += bp * bp;
       ri[0] += (double)rf * (double)(rf * di);
@@ -842,10 +838,7 @@ __global__ __launch_bounds__(64 * TY) void k_residual64_3(Geo G, Stencil<3, doub
       const double r = bp - acc;
       const float rf = (float)r;
       v32.r[P] = rf;
-      if (zero_inner) {
-        v32.x[P] = 0.0f;
-        v32.p0[P] = 0.0f;
-      }
+      if (zero_inner) v32.x[P] = 0.0f;
       ro[0] += r * r;
       ro[1] += bp * bp;
       ri[0] += (double)rf * (double)(rf * di);
@@ -902,16 +895,14 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
 }
 
 // Jacobi-PCG resumed on an inner system from its current iterate (after the
-// learned form's flexible-CG steps): zero direction, and partials
-// <r, r/diag>, ||r||^2 of the current residual
+// learned form's flexible-CG steps): partials <r, r/diag>, ||r||^2 of the
+// current residual (the resumed iteration 0 takes no previous direction)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_resume(int n, const T* __restrict__ r,
-                                                      const T* __restrict__ dinv,
-                                                      T* __restrict__ p0, double* part) {
+                                                      const T* __restrict__ dinv, double* part) {
   double v[2] = {0.0, 0.0};
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
     const T rv = r[P];
-    p0[P] = T(0);
     const double rd = (double)rv;
     v[0] += rd * (double)(rv * dinv[P]);
     v[1] += rd * rd;
@@ -999,16 +990,17 @@ void cg_init(hipStream_t s, const Geo& G, const CgVectors<T>& v, const CgWork& w
 }
 
 // the vectors iteration `iter` reads and writes (by parity; the set-up
-// kernels leave the residual in r and a zero direction in p0).  Iteration 0
-// has no update to apply (alpha = 0, beta = 0): it reads r in place of the
-// old A p, so that only finite values enter r - 0 q and x + 0 p.
+// kernels leave the residual in r).  Iteration 0 has no update to apply and
+// no previous direction (alpha = 0, beta = 0): it reads r in place of the
+// old A p and of the old direction, so that only finite values enter
+// r - 0 q, x + 0 p and r/diag + 0 p, and no set-up pass clears a direction.
 template <typename T>
 CgIter<T> iter_vectors(const CgVectors<T>& v, int iter) {
   const bool odd = iter & 1;
   return CgIter<T>{v.x,
                    odd ? v.r1 : v.r, odd ? v.r : v.r1,
                    iter == 0 ? v.r : (odd ? v.q : v.q1), odd ? v.q1 : v.q,
-                   odd ? v.p1 : v.p0, odd ? v.p0 : v.p1,
+                   iter == 0 ? v.r : (odd ? v.p1 : v.p0), odd ? v.p0 : v.p1,
                    v.c, v.D, v.dinv};
 }
 
@@ -1072,7 +1064,7 @@ void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, d
 void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter) {
   const int gu = zplan(G).blocks;  // the set-up partial buffer holds 2 values per block of this grid
   hipLaunchKernelGGL(k_cg_resume<float>, dim3(gu), dim3(kBlock), 0, s, G.nc, (const float*)v.r, v.dinv,
-                     v.p0, w.u[1]);
+                     w.u[1]);
   hipLaunchKernelGGL(k_cg_resume_start, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[1], gu, max_iter,
                      w.sc);
 }

@@ -82,7 +82,6 @@ struct RhsResidual {
   const double* x;
   float* r32;
   float* x32;
-  float* p32;
   int zero_inner;
   double* o_part;
   double* i_part;
@@ -104,7 +103,7 @@ void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho
                   double* Ks = nullptr);
 // Step 2, one sweep: the right-hand side b, coefficient c and 1/diag of the
 // implicit-diffusion system for T, the initial guess x = T_prev, and the
-// solve's set-up (r = b - A x, p0 = 0, partials <r, r/diag>, ||r||^2 in
+// solve's set-up (r = b - A x, partials <r, r/diag>, ||r||^2 in
 // u_part and ||b||^2 in b_part, one per workgroup); returns the workgroup
 // count (k_cg_start's nu).  The system's D is (mu/Pr) c_p everywhere.  The
 // sweep stages a_prev and T_prev: with ks (and always in the enthalpy form)
@@ -114,7 +113,7 @@ int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, bo
                       const double* rho, const double* e0, const double* a_prev,
                       const double* T_prev, double* const* phi, const double* rho_star,
                       const double* Ks, const double* Tbg, double* b, double* c, double* dinv,
-                      double* x, double* r, double* p0, double* u_part, double* b_part);
+                      double* x, double* r, double* u_part, double* b_part);
 // after the last sweep's solve: the EOS density and pressure-equation
 // coefficients rho23, psi, c, D
 void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const double* T,

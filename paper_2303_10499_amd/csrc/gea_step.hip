@@ -463,7 +463,7 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
 // diffusion of h' = c_p (T - T_bg) at the new level, the convective flux
 // from the previous sweep with the frozen Step-1 flux), its 1/diag, the
 // initial guess T^(s-1) and the solve's set-up as the CG set-up kernel forms
-// it: r = b - A T^(s-1), a zero first direction, and the partials <r, r/diag>,
+// it: r = b - A T^(s-1) and the partials <r, r/diag>,
 // ||r||^2 (u_part) and ||b||^2 (b_part) of each workgroup.
 struct EnergySys {
   double* b;
@@ -471,7 +471,6 @@ struct EnergySys {
   double* dinv;
   double* x;      // the solve's initial guess (and later solution)
   double* r;
-  double* p0;
   double* u_part;
   double* b_part;
 };
@@ -593,7 +592,6 @@ __global__ __launch_bounds__(kBlock) void k_energy_rhs(
       sy.dinv[P] = di;
       sy.x[P] = xc;
       sy.r[P] = rr;
-      sy.p0[P] = 0.0;
       red[0] += rr * (rr * di);
       red[1] += rr * rr;
       red[2] += bP * bP;
@@ -830,7 +828,6 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
       sy.dinv[P] = di;
       sy.x[P] = xc;
       sy.r[P] = rr;
-      sy.p0[P] = 0.0;
       red[0] += rr * (rr * di);
       red[1] += rr * rr;
       red[2] += bP * bP;
@@ -1279,10 +1276,7 @@ __global__ __launch_bounds__(64 * TY) void k_rhs3(Geo G, Phys ph, int kc,
         const double r = bp - ax;
         const float rf = (float)r;
         res.r32[P] = rf;
-        if (res.zero_inner) {
-          res.x32[P] = 0.0f;
-          res.p32[P] = 0.0f;
-        }
+        if (res.zero_inner) res.x32[P] = 0.0f;
         ro[0] += r * r;
         ro[1] += bp * bp;
         ri[0] += (double)rf * (double)(rf * (float)di);
@@ -1815,9 +1809,9 @@ int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, bo
                       const double* rho, const double* e0, const double* a_prev,
                       const double* T_prev, double* const* phi, const double* rho_star,
                       const double* Ks, const double* Tbg, double* b, double* c, double* dinv,
-                      double* x, double* r, double* p0, double* u_part, double* b_part) {
+                      double* x, double* r, double* u_part, double* b_part) {
   const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy, kKcEnergy) : zp;
-  const EnergySys sy{b, c, dinv, x, r, p0, u_part, b_part};
+  const EnergySys sy{b, c, dinv, x, r, u_part, b_part};
   // (the enthalpy form always stages T and K*)
   if (G.ndim == 2) {
     if (enth)

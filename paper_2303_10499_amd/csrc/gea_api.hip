@@ -857,7 +857,6 @@ FcgVectors& fcg_vectors(gea_ctx* x) {
   v.c = x->c32;
   v.D = x->D32;
   v.dinv = x->dinv32;
-  v.p_cg = x->p032;
   return v;
 }
 

@@ -201,10 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_fcg_spmv3(Geo G, int kc, int iter,
 // partials ||r||^2 and max |r| (as a sum of per-workgroup maxima stored apart).
 // Iteration 0 (ITER0): p = z, <z, r> from the direction kernel's partials,
 // and d = alpha p (d needs no clearing; it is cleared here when the solve has
-// already stopped).  The last iteration (LAST) keeps no r_old and also sets
-// up the Jacobi-PCG that resumes the solve: its first direction p_cg = 0 and
-// the partials <r, r/diag>, <r, r> of the residual it starts from (also when
-// the solve had stopped before this iteration).
+// already stopped).  The last iteration (LAST) keeps no r_old and also forms
+// the partials <r, r/diag>, <r, r> of the residual the resumed Jacobi-PCG
+// starts from (also when the solve had stopped before this iteration).
 template <bool ITER0, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* __restrict__ d,
                                                        const float* p,
@@ -214,7 +213,6 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
                                                        const double* pq_part, int np,
                                                        double* part, FcgScalars* sc,
                                                        const float* __restrict__ dinv,
-                                                       float* p_cg,  // may be p's buffer
                                                        double* res_part) {
   bool step = !sc->done;
   float alpha = 0.f;
@@ -258,7 +256,6 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
       d[P] = 0.f;
     }
     if (LAST) {
-      p_cg[P] = 0.f;
       const double rd = (double)rn;
       w[0] += rd * (double)(rn * dinv[P]);
       w[1] += rd * rd;
@@ -423,7 +420,7 @@ int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int 
 #define GEA_UPD(I0, L)                                                                          \
   hipLaunchKernelGGL((k_fcg_update<I0, L>), gr, bl, 0, s, G.nc, iter, v.d, p_upd, v.r, v.r_old, \
                      (const float*)v.q, (const double*)v.part_s, ns, v.part_u, sc, v.dinv,       \
-                     v.p_cg, v.part_d)
+                     v.part_d)
   if (it0 && last) GEA_UPD(true, true);
   else if (it0) GEA_UPD(true, false);
   else if (last) GEA_UPD(false, true);

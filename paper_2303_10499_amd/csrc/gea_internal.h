@@ -308,7 +308,6 @@ struct FcgVectors {
   float *d, *r, *r_old, *z, *p0, *p1, *q;
   const float *c, *D;
   const float* dinv;  // 1/diag, for the resumed Jacobi-PCG's set-up
-  float* p_cg;        // the resumed Jacobi-PCG's first direction buffer
   double *part_d, *part_s, *part_u;
 };
 
@@ -318,7 +317,7 @@ void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, const CgScalars
                int max_iter, FcgScalars* sc);
 // one iteration once z = M(r) is in v.z: dots, direction + operator, update,
 // check.  The last one (last) also sets up the Jacobi-PCG that resumes the
-// solve: p_cg = 0 and 2 x n partials <r, r/diag>, <r, r> in v.part_d, n the
+// solve: 2 x n partials <r, r/diag>, <r, r> in v.part_d, n the
 // returned count (then cg_resume_scalars finishes the set-up).
 int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
                           FcgScalars* sc);

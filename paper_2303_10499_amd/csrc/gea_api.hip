@@ -179,10 +179,7 @@ struct gea_ctx {
   double* rho_star;
   double* ustar[3];
   double* e0;
-  double* ea;
-  double* eb;
-  double* Ta;
-  double* Tb;
+  double* ea;  // K* (explicit transport) or the implicit energy system's known part
   double* rho23;
   double* psi;
   double* c;
@@ -353,9 +350,6 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned, bool trans
   for (int d = 0; d < 3; ++d) x->ustar[d] = d < nd ? cv.take<double>(nc) : nullptr;
   x->e0 = cv.take<double>(nc);
   x->ea = cv.take<double>(nc);
-  x->eb = cv.take<double>(nc);
-  x->Ta = cv.take<double>(nc);
-  x->Tb = cv.take<double>(nc);
   x->rho23 = cv.take<double>(nc);
   x->psi = cv.take<double>(nc);
   x->c = cv.take<double>(nc);
@@ -1211,7 +1205,7 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
       ensure_history(x);
       x->timer.run(5, x->stream, [&] {
         launch_enthalpy_prep(s, G, ph, S.rho, S.T, S.p, S.pm, S.Km, S.u, x->ustar, x->rho_star,
-                             x->e0, x->eb, N.pm, N.Km);
+                             x->e0, N.pm, N.Km);
       });
     }
     // Step 2 in one implicit solve for T
@@ -1238,7 +1232,7 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
     ensure_history(x);
     x->timer.run(5, x->stream, [&] {
       launch_enthalpy_prep(s, G, ph, S.rho, S.T, S.p, S.pm, S.Km, S.u, x->ustar, x->rho_star,
-                           x->e0, x->eb, N.pm, N.Km);
+                           x->e0, N.pm, N.Km);
     });
   }
   const double* T_prev = S.T;
@@ -1246,14 +1240,15 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
   for (int sw = 0; sw < ns; ++sw) {
     const bool last = sw == ns - 1;
     // the first total-energy sweep transports e^n + R T^n; every other sweep
-    // forms its transported quantity from T^(s-1) and K*
+    // forms its transported quantity from T^(s-1) and K*.  Every sweep solves
+    // into T_out: after the first, the initial guess is already there.
     const bool ks = enth || sw > 0;
-    double* T_next = last ? T_out : ((sw & 1) ? x->Tb : x->Ta);
+    double* T_next = T_out;
     int nparts = 0;
     x->timer.run(5, x->stream, [&] {
       nparts = launch_energy_rhs(s, G, ph, enth, ks, S.rho, x->e0, ks ? Ks : x->e0, T_prev, S.phi,
-                                 x->rho_star, Ks, x->Tbg, x->b, x->c, x->dinv, T_next, x->r,
-                                 x->w64.u[1], x->w64.b);
+                                 x->rho_star, Ks, x->Tbg, x->b, x->c, x->dinv,
+                                 T_next == T_prev ? nullptr : T_next, x->r, x->w64.u[1], x->w64.b);
     });
     HIPCHK(hipGetLastError());
     int its = 0;

@@ -120,14 +120,14 @@ void launch_energy_post(hipStream_t s, const Geo& G, const Phys& ph, const doubl
                         const double* p, const double* rho_star, double* rho23, double* psi,
                         double* c, double* D);
 // Step 2 in enthalpy form (enth = true above): p^{n-1} = p, K^{n-1} = |u|^2/2
-// for a state without history; and the sweep-independent balance q, the
-// first sweep's transported c_p T + K*, and the next state's p^n, K^n
+// for a state without history; and the sweep-independent balance q and the
+// next state's p^n, K^n
 void launch_history_init(hipStream_t s, const Geo& G, const double* p, double* const* u,
                          double* pm, double* Km);
 void launch_enthalpy_prep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                           const double* T, const double* p, const double* pm, const double* Km,
                           double* const* u, double* const* u_star, const double* rho_star,
-                          double* q, double* h0, double* pm_next, double* Km_next);
+                          double* q, double* pm_next, double* Km_next);
 // relative residual to which each energy sweep's system is solved
 constexpr double kEnergyTol = 1e-13;
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,

@@ -469,7 +469,7 @@ struct EnergySys {
   double* b;
   double* c;
   double* dinv;
-  double* x;      // the solve's initial guess (and later solution)
+  double* x;      // the solve's initial guess (and later solution); null: T_prev itself
   double* r;
   double* u_part;
   double* b_part;
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_rhs(
       sy.b[P] = bP;
       sy.c[P] = cP;
       sy.dinv[P] = di;
-      sy.x[P] = xc;
+      if (sy.x) sy.x[P] = xc;  // (null: the solve runs in place on T_prev)
       sy.r[P] = rr;
       red[0] += rr * (rr * di);
       red[1] += rr * rr;
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(kBlock) void k_enthalpy_prep(
     Geo G, Phys ph, const double* __restrict__ rho, const double* __restrict__ T,
     const double* __restrict__ p, const double* __restrict__ pm, const double* __restrict__ Km,
     Vec<NDIM> u, Vec<NDIM> u_star, const double* __restrict__ rho_star, double* __restrict__ q,
-    double* __restrict__ h0, double* __restrict__ pm_next, double* __restrict__ Km_next) {
+    double* __restrict__ pm_next, double* __restrict__ Km_next) {
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < G.nc; P += gridDim.x * blockDim.x) {
     const double r = rho[P], Tc = T[P], pc = p[P], rs = rho_star[P];
     double ks = 0.0, kn = 0.0;
@@ -645,7 +645,6 @@ __global__ __launch_bounds__(kBlock) void k_enthalpy_prep(
     ks *= 0.5;
     const double hn = ph.cp * Tc;
     q[P] = r * hn + r * Km[P] - pm[P] - rs * ks + pc - ph.dt * rs * ph.g * u_star.p[NDIM - 1][P];
-    h0[P] = hn + ks;
     pm_next[P] = pc;
     Km_next[P] = 0.5 * kn;
   }
@@ -826,7 +825,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
       sy.b[P] = bP;
       sy.c[P] = cP;
       sy.dinv[P] = di;
-      sy.x[P] = xc;
+      if (sy.x) sy.x[P] = xc;  // (null: the solve runs in place on T_prev)
       sy.r[P] = rr;
       red[0] += rr * (rr * di);
       red[1] += rr * rr;
@@ -1850,12 +1849,12 @@ void launch_history_init(hipStream_t s, const Geo& G, const double* p, double* c
 void launch_enthalpy_prep(hipStream_t s, const Geo& G, const Phys& ph, const double* rho,
                           const double* T, const double* p, const double* pm, const double* Km,
                           double* const* u, double* const* u_star, const double* rho_star,
-                          double* q, double* h0, double* pm_next, double* Km_next) {
+                          double* q, double* pm_next, double* Km_next) {
   const dim3 grid(grid_for(G.nc)), block(kBlock);
   if (G.ndim == 2)
-    hipLaunchKernelGGL(k_enthalpy_prep<2>, grid, block, 0, s, G, ph, rho, T, p, pm, Km, V2(u), V2(u_star), rho_star, q, h0, pm_next, Km_next);
+    hipLaunchKernelGGL(k_enthalpy_prep<2>, grid, block, 0, s, G, ph, rho, T, p, pm, Km, V2(u), V2(u_star), rho_star, q, pm_next, Km_next);
   else
-    hipLaunchKernelGGL(k_enthalpy_prep<3>, grid, block, 0, s, G, ph, rho, T, p, pm, Km, V3(u), V3(u_star), rho_star, q, h0, pm_next, Km_next);
+    hipLaunchKernelGGL(k_enthalpy_prep<3>, grid, block, 0, s, G, ph, rho, T, p, pm, Km, V3(u), V3(u_star), rho_star, q, pm_next, Km_next);
 }
 
 void launch_H(hipStream_t s, const Geo& G, const Phys& ph, const double* rho, double* const* u,

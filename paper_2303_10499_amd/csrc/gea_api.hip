@@ -184,7 +184,6 @@ struct gea_ctx {
   double* psi;
   double* c;
   double* D;
-  double* DT;  // the energy system's D: (mu/Pr) c_p in every cell
   double* H[3];
   double* b;
   double* dinv;
@@ -354,7 +353,6 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned, bool trans
   x->psi = cv.take<double>(nc);
   x->c = cv.take<double>(nc);
   x->D = cv.take<double>(nc);
-  x->DT = cv.take<double>(nc);
   for (int d = 0; d < 3; ++d) x->H[d] = d < nd ? cv.take<double>(nc) : nullptr;
   x->b = cv.take<double>(nc);
   x->dinv = cv.take<double>(nc);
@@ -1068,11 +1066,13 @@ gea_status solve(gea_ctx* x, double* xv, gea_solve_stats* out) {
 }
 
 // One energy sweep's system (Step 2), set up by the RHS pass: Jacobi-PCG in
-// FP64 on (c, DT, 1/diag, b) from the initial guess in T, to kEnergyTol.
+// FP64 on (c, D = (mu/Pr) c_p, 1/diag, b) from the initial guess in T, to kEnergyTol.
 gea_status solve_energy(gea_ctx* x, double* T, int nparts, int sweep, int* iters) {
   const Geo& G = x->G;
   const CgWork& w = x->w64;
-  CgVectors<double> v{T, x->r, x->r1, x->p0, x->p1, x->q, x->q1, x->c, x->DT, x->dinv, x->b};
+  // D = (mu/Pr) c_p in every cell: the iteration kernels take it as a value
+  CgVectors<double> v{T, x->r, x->r1, x->p0, x->p1, x->q, x->q1, x->c, nullptr, x->dinv, x->b,
+                      x->prm.mu / x->prm.Pr * x->prm.cp};
   x->timer.run(7, x->stream, [&] {
     cg_start_from(x->stream, w.u[1], nparts, w.b, kEnergyTol, x->prm.max_iter, w.sc);
   });
@@ -1412,7 +1412,6 @@ gea_status gea_init_mesh(const gea_mesh* mesh, const gea_params* params, void* h
     // zero the solver scalars once
     HIPCHK(hipMemsetAsync(x->sc, 0, sizeof(CgScalars), x->stream));
     HIPCHK(hipMemsetAsync(x->sc32, 0, sizeof(CgScalars), x->stream));
-    launch_fill(x->stream, x->G, x->DT, x->prm.mu / x->prm.Pr * x->prm.cp);
     HIPCHK(hipGetLastError());
     for (hipEvent_t* e : {&x->ev_net[0], &x->ev_net[1], &x->ev_it[0], &x->ev_it[1]})
       HIPCHK(hipEventCreate(e));

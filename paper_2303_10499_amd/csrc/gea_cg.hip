@@ -410,7 +410,8 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 // new residual and x update are stored there, and their residual and 1/diag
 // stay in the thread's registers for the dot products of the plane, which
 // is computed one step later.
-template <typename T>
+// CD: D is v.Dc in every cell (no D array is read)
+template <typename T, bool CD>
 __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgIter<T> v,
                                                      CgStep stp, CgScalars* sc) {
   constexpr int TX = kTX3, TY = kTY3, KC = kKC3<T>;
@@ -491,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
       f.r[u] = v.r_in[Q];
       f.q[u] = v.q_in[Q];
       f.p[u] = v.p_in[Q];
-      f.d[u] = v.D[Q];
+      f.d[u] = CD ? v.Dc : v.D[Q];
       f.m[u] = v.dinv[Q];
       if (u < RPT) {  // own cell: x for its update, c for the operator
         f.x[u] = ld_stream<true>(&v.x[Q]);
@@ -602,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
 // above a cell stay in registers and x-neighbours come from the neighbouring
 // lanes (the first and last lane of a wave also load the cell just beyond the
 // wave), so the kernel needs neither LDS nor barriers.
-template <typename T>
+template <typename T, bool CD>
 __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgIter<T> v,
                                                      CgStep stp, CgScalars* sc) {
   constexpr int TX = kTX2, KC = kKC2<T>;
@@ -633,9 +634,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
   auto fetch = [&](int kk) {
     const int kc = kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk);
     const int Q = ic + nx * kc, Qe = iec + nx * kc;
-    return Raw{v.r_in[Q], v.q_in[Q], v.p_in[Q], v.D[Q], v.dinv[Q], ld_stream<NT2>(&v.x[Q]),
+    return Raw{v.r_in[Q], v.q_in[Q], v.p_in[Q], CD ? v.Dc : v.D[Q], v.dinv[Q], ld_stream<NT2>(&v.x[Q]),
                ld_stream<NT2>(&v.c[Q]),
-               v.r_in[Qe], v.q_in[Qe], v.p_in[Qe], v.D[Qe], v.dinv[Qe]};
+               v.r_in[Qe], v.q_in[Qe], v.p_in[Qe], CD ? v.Dc : v.D[Qe], v.dinv[Qe]};
   };
   // rows k0-1 .. k0+PD in flight while the scalars are formed or read;
   // afterwards row k+PD+1 is requested while row k is computed
@@ -1001,7 +1002,7 @@ CgIter<T> iter_vectors(const CgVectors<T>& v, int iter) {
                    odd ? v.r1 : v.r, odd ? v.r : v.r1,
                    iter == 0 ? v.r : (odd ? v.q : v.q1), odd ? v.q1 : v.q,
                    iter == 0 ? v.r : (odd ? v.p1 : v.p0), odd ? v.p0 : v.p1,
-                   v.c, v.D, v.dinv};
+                   v.c, v.D, v.dinv, v.Dc};
 }
 
 bool cg_folds(const CgWork& w) { return w.ns <= kFoldMaxParts; }
@@ -1011,10 +1012,18 @@ void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter
                     bool fold) {
   const CgIter<T> it = iter_vectors(v, iter);
   const CgStep stp{w.s, w.ns, iter, fold && iter > 0 && cg_folds(w) ? 1 : 0};
-  if (G.ndim == 2)
-    hipLaunchKernelGGL(k_cg_iter2<T>, dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), it, stp, w.sc);
-  else
-    hipLaunchKernelGGL(k_cg_iter3<T>, dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), it, stp, w.sc);
+  const bool cd = v.D == nullptr;
+  if (G.ndim == 2) {
+    if (cd)
+      hipLaunchKernelGGL((k_cg_iter2<T, true>), dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), it, stp, w.sc);
+    else
+      hipLaunchKernelGGL((k_cg_iter2<T, false>), dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<2, T>(G), it, stp, w.sc);
+  } else {
+    if (cd)
+      hipLaunchKernelGGL((k_cg_iter3<T, true>), dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), it, stp, w.sc);
+    else
+      hipLaunchKernelGGL((k_cg_iter3<T, false>), dim3(iter_grid<T>(G)), dim3(kBlock), 0, s, G, stencil<3, T>(G), it, stp, w.sc);
+  }
 }
 
 void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w) {

@@ -169,9 +169,10 @@ struct CgVectors {
   T* q;
   T* q1;
   const T* c;
-  const T* D;
+  const T* D;     // null: D is Dc in every cell (the energy sweeps' system)
   const T* dinv;
   const T* b;
+  T Dc = T(0);
 };
 
 // The vectors one iteration kernel reads (_in) and writes (_out).
@@ -187,6 +188,7 @@ struct CgIter {
   const T* c;
   const T* D;
   const T* dinv;
+  T Dc;  // D in every cell when the kernel's CD flag is set (D unused)
 };
 
 // Per-workgroup partial sums of one CG instance: s (iteration kernel, 7

@@ -153,6 +153,23 @@ def test_steps_match_oracle(oracle_lib, gea_mod, name, dims, steps):
     assert abs(gst.eos_mismatch - ost[-1].eos_mismatch) <= 1e-12 + 1e-3 * ost[-1].eos_mismatch
 
 
+@pytest.mark.parametrize("name,dims", [("bubble2d_64x32", (37, 23, None)),
+                                       ("bubble3d_256x256x128", (13, 9, 11))])
+@pytest.mark.parametrize("sweeps,form", [(1, 0), (3, 0), (1, 1), (3, 1)])
+def test_energy_sweep_counts_match_oracle(oracle_lib, gea_mod, name, dims, sweeps, form):
+    """Step 2 with one and with three sweeps, in both energy forms: a single
+    sweep solves straight into the new state's T, and every sweep after the
+    first forms the transported quantity from T and K* and solves in place
+    on the previous sweep's T"""
+    nx, nz, ny = dims
+    cfg = cfg_mesh(name, nx, nz, ny, tol=1e-13, max_iter=100000, n_energy_sweeps=sweeps,
+                   energy_form=form)
+    O, s, S = pair(oracle_lib, gea_mod, cfg)
+    O.step(s, 3)
+    S.step(3)
+    compare(S, s, 1e-10, cfg, 3)
+
+
 @pytest.mark.parametrize("name,dims,steps", [
     ("bubble2d_64x32", (64, 32, None), 20),
     ("bubble2d_64x32", (37, 23, None), 10),          # ragged

@@ -895,22 +895,6 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Jacobi-PCG resumed on an inner system from its current iterate (after the
-// learned form's flexible-CG steps): partials <r, r/diag>, ||r||^2 of the
-// current residual (the resumed iteration 0 takes no previous direction)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_resume(int n, const T* __restrict__ r,
-                                                      const T* __restrict__ dinv, double* part) {
-  double v[2] = {0.0, 0.0};
-  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
-    const T rv = r[P];
-    const double rd = (double)rv;
-    v[0] += rd * (double)(rv * dinv[P]);
-    v[1] += rd * rd;
-  }
-  store_partials<2>(v, part);
-}
-
 // one workgroup: scalars of the resumed solve (its ||b||^2 and tolerance are
 // those the set-up kernel gave the inner system; max_iter iterations remain)
 __global__ __launch_bounds__(kBlock) void k_cg_resume_start(const double* part, int n, int max_iter,
@@ -1068,14 +1052,6 @@ void launch_residual_check(hipStream_t s, int n, double tol, double inner_tol, d
                            CgScalars* sc64, const CgScalars* gate) {
   hipLaunchKernelGGL(k_residual_check, dim3(1), dim3(kBlock), 0, s, o_part, (const double*)w32.u[1], n,
                      tol * tol, inner_tol * inner_tol, target, inner_max, sc64, w32.sc, gate);
-}
-
-void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter) {
-  const int gu = zplan(G).blocks;  // the set-up partial buffer holds 2 values per block of this grid
-  hipLaunchKernelGGL(k_cg_resume<float>, dim3(gu), dim3(kBlock), 0, s, G.nc, (const float*)v.r, v.dinv,
-                     w.u[1]);
-  hipLaunchKernelGGL(k_cg_resume_start, dim3(1), dim3(kBlock), 0, s, (const double*)w.u[1], gu, max_iter,
-                     w.sc);
 }
 
 void cg_resume_scalars(hipStream_t s, const double* part, int n, const CgWork& w, int max_iter) {

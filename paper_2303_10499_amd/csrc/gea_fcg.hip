@@ -201,9 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_spmv3(Geo G, int kc, int iter,
 // partials ||r||^2 and max |r| (as a sum of per-workgroup maxima stored apart).
 // Iteration 0 (ITER0): p = z, <z, r> from the direction kernel's partials,
 // and d = alpha p (d needs no clearing; it is cleared here when the solve has
-// already stopped).  The last iteration (LAST) keeps no r_old and also forms
-// the partials <r, r/diag>, <r, r> of the residual the resumed Jacobi-PCG
-// starts from (also when the solve had stopped before this iteration).
+// already stopped).  The last iteration (LAST) keeps no r_old.
 template <bool ITER0, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* __restrict__ d,
                                                        const float* p,
@@ -211,9 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
                                                        float* __restrict__ r_old,
                                                        const float* __restrict__ q,
                                                        const double* pq_part, int np,
-                                                       double* part, FcgScalars* sc,
-                                                       const float* __restrict__ dinv,
-                                                       double* res_part) {
+                                                       double* part, FcgScalars* sc) {
   bool step = !sc->done;
   float alpha = 0.f;
   if (step) {
@@ -235,30 +231,23 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
     }
     alpha = (float)alpha_d;
   }
-  if (!step && !ITER0 && !LAST) return;
+  if (!step && !ITER0) return;
   __shared__ double sh[2][kBlock / 64];
   double v[2] = {0.0, 0.0};
-  double w[2] = {0.0, 0.0};
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
-    float rn = r[P];
     if (step) {
       if (ITER0)
         d[P] = alpha * p[P];
       else
         d[P] += alpha * p[P];
-      const float ro = rn;
+      const float ro = r[P];
       if (!LAST) r_old[P] = ro;
-      rn = ro - alpha * q[P];
+      const float rn = ro - alpha * q[P];
       r[P] = rn;
       v[0] += (double)rn * (double)rn;
       v[1] = fmax(v[1], fabs((double)rn));
-    } else if (ITER0) {
-      d[P] = 0.f;
-    }
-    if (LAST) {
-      const double rd = (double)rn;
-      w[0] += rd * (double)(rn * dinv[P]);
-      w[1] += rd * rd;
+    } else {
+      d[P] = 0.f;  // (ITER0 only: the other iterations returned above)
     }
   }
   if (step) {
@@ -268,7 +257,43 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
       part[gridDim.x + blockIdx.x] = v[1];
     }
   }
-  if (LAST) store_part<2>(w, res_part);
+}
+
+// Hand-over to Jacobi-PCG: the residual of the flexible CG's correction
+// taken afresh, r = r0 - A d with the inner system's FP32 operator, in place
+// of the recurrence residual, and the resumed solve's set-up partials
+// <r, r/diag>, <r, r>.  A few flexible steps with poor directions (long steps
+// that mostly cancel) leave a recurrence residual that has drifted far from
+// the true one at FP32 rounding of d; resumed from it, the Jacobi-PCG would
+// converge on the drift and leave it to the next refinement step.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_fcg_handover(Geo G, const float* __restrict__ d,
+                                                         const float* __restrict__ r0,
+                                                         const float* __restrict__ c,
+                                                         const float* __restrict__ D,
+                                                         const float* __restrict__ dinv,
+                                                         float* __restrict__ r, double* part) {
+  float kk[NDIM];
+  for (int k = 0; k < NDIM; ++k) kk[k] = (float)(G.S[k] / G.h[k]);
+  double w[2] = {0.0, 0.0};
+  GEA_FOR_CELLS(P, G) {
+    int cc[NDIM];
+    cell_coords<NDIM>(G, P, cc);
+    const float dp = d[P], Dp = D[P];
+    float a = c[P] * dp;
+#pragma unroll
+    for (int k = 0; k < NDIM; ++k) {
+      const int st = G.st[k];
+      if (cc[k] + 1 < G.n[k]) a += 0.5f * (Dp + D[P + st]) * kk[k] * (dp - d[P + st]);
+      if (cc[k] > 0) a += 0.5f * (D[P - st] + Dp) * kk[k] * (dp - d[P - st]);
+    }
+    const float rn = r0[P] - a;
+    r[P] = rn;
+    const double rd = (double)rn;
+    w[0] += rd * (double)(rn * dinv[P]);
+    w[1] += rd * rd;
+  }
+  store_part<2>(w, part);
 }
 
 // One workgroup: ||r||^2 and max |r| from the update partials (or from the
@@ -317,14 +342,17 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
 }
 
 // inner start: partials ||r||^2 and max |r| of r (= r32, set by the
-// refinement residual).  d, the direction and r_old need no clearing: the
-// first iteration writes d and reads neither of the others.
+// refinement residual), and its copy r0 for the hand-over.  d, the direction
+// and r_old need no clearing: the first iteration writes d and reads neither
+// of the others.
 __global__ __launch_bounds__(kBlock) void k_fcg_start(int n, const float* __restrict__ r,
-                                                      double* part) {
+                                                      float* __restrict__ r0, double* part) {
   __shared__ double sh[2][kBlock / 64];
   double v[2] = {0.0, 0.0};
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
-    const double rv = r[P];
+    const float rf = r[P];
+    r0[P] = rf;
+    const double rv = rf;
     v[0] += rv * rv;
     v[1] = fmax(v[1], fabs(rv));
   }
@@ -379,13 +407,13 @@ __global__ __launch_bounds__(kBlock) void k_pair(int n, const double* __restrict
 void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, const CgScalars* sys,
                int max_iter, FcgScalars* sc) {
   const int gu = grid_for(G.nc);
-  hipLaunchKernelGGL(k_fcg_start, dim3(gu), dim3(kBlock), 0, s, G.nc, (const float*)v.r, v.part_u);
+  hipLaunchKernelGGL(k_fcg_start, dim3(gu), dim3(kBlock), 0, s, G.nc, (const float*)v.r, v.r0, v.part_u);
   hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(kBlock), 0, s, (const double*)v.part_u, gu, 0, 1,
                      sys, max_iter, sc);
 }
 
-int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
-                          FcgScalars* sc) {
+void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
+                           FcgScalars* sc) {
   const int gu = grid_for(G.nc);
   const dim3 gr(gu), bl(kBlock);
   const bool it0 = iter == 0;
@@ -419,8 +447,7 @@ int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int 
   }
 #define GEA_UPD(I0, L)                                                                          \
   hipLaunchKernelGGL((k_fcg_update<I0, L>), gr, bl, 0, s, G.nc, iter, v.d, p_upd, v.r, v.r_old, \
-                     (const float*)v.q, (const double*)v.part_s, ns, v.part_u, sc, v.dinv,       \
-                     v.part_d)
+                     (const float*)v.q, (const double*)v.part_s, ns, v.part_u, sc)
   if (it0 && last) GEA_UPD(true, true);
   else if (it0) GEA_UPD(true, false);
   else if (last) GEA_UPD(false, true);
@@ -428,7 +455,17 @@ int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int 
 #undef GEA_UPD
   hipLaunchKernelGGL(k_fcg_check, dim3(1), bl, 0, s, (const double*)v.part_u, gu, iter + 1, 0,
                      (const CgScalars*)nullptr, 0, sc);
-  return gu;
+}
+
+void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter) {
+  const int gu = grid_for(G.nc);
+  if (G.ndim == 2)
+    hipLaunchKernelGGL(k_fcg_handover<2>, dim3(gu), dim3(kBlock), 0, s, G, (const float*)v.d,
+                       (const float*)v.r0, v.c, v.D, v.dinv, v.r, v.part_d);
+  else
+    hipLaunchKernelGGL(k_fcg_handover<3>, dim3(gu), dim3(kBlock), 0, s, G, (const float*)v.d,
+                       (const float*)v.r0, v.c, v.D, v.dinv, v.r, v.part_d);
+  cg_resume_scalars(s, v.part_d, gu, w, max_iter);
 }
 
 void pair_outputs(hipStream_t s, const Geo& G, const double* r0, const double* c,

@@ -221,10 +221,9 @@ void cg_iter_kernel(hipStream_t s, const Geo& G, const CgVectors<T>& v, int iter
 void cg_scalars(hipStream_t s, const Geo& G, int iter, const CgWork& w);
 bool cg_folds(const CgWork& w);
 // Jacobi-PCG resumed on the FP32 inner system from its current iterate and
-// residual (v.x, v.r), keeping the set-up's ||b||^2 and tolerance; then
-// cg_iter_kernel / cg_scalars from iteration 0
-void cg_resume(hipStream_t s, const Geo& G, const CgVectors<float>& v, const CgWork& w, int max_iter);
-// the resume's scalars from 2 x n partials <r, r/diag>, <r, r> already formed
+// residual, keeping the set-up's ||b||^2 and tolerance: its scalars from
+// 2 x n partials <r, r/diag>, <r, r> of that residual (fcg_handover forms
+// them); then cg_iter_kernel / cg_scalars from iteration 0
 void cg_resume_scalars(hipStream_t s, const double* part, int n, const CgWork& w, int max_iter);
 void launch_apply_A(hipStream_t s, const Geo& G, const double* c, const double* D,
                     const double* x, double* y);
@@ -308,6 +307,7 @@ struct FcgScalars {
 
 struct FcgVectors {
   float *d, *r, *r_old, *z, *p0, *p1, *q;
+  float* r0;          // the starting residual, kept for the hand-over
   const float *c, *D;
   const float* dinv;  // 1/diag, for the resumed Jacobi-PCG's set-up
   double *part_d, *part_s, *part_u;
@@ -318,11 +318,13 @@ struct FcgVectors {
 void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, const CgScalars* sys,
                int max_iter, FcgScalars* sc);
 // one iteration once z = M(r) is in v.z: dots, direction + operator, update,
-// check.  The last one (last) also sets up the Jacobi-PCG that resumes the
-// solve: 2 x n partials <r, r/diag>, <r, r> in v.part_d, n the
-// returned count (then cg_resume_scalars finishes the set-up).
-int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
-                          FcgScalars* sc);
+// check (last: the last one enqueued, which keeps no r_old)
+void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
+                           FcgScalars* sc);
+// hand-over to the Jacobi-PCG that resumes the inner solve from the flexible
+// CG's iterate d: v.r = r0 - A d afresh, then the resumed solve's scalars in
+// w.sc (max_iter iterations remain)
+void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter);
 // training pair: s = max |r0| (s_out[0], 1/s in s_out[1]); in_r = r0/s,
 // in_a = c/diag, out_d = (x - x0)/s
 void pair_outputs(hipStream_t s, const Geo& G, const double* r0, const double* c,

@@ -348,7 +348,9 @@ def test_nonconvergence_rolls_back(oracle_lib, gea_mod):
                                        ("nonsmooth2d_2048", (256, 256, None)),
                                        ("nonsmooth2d_2048", (96, 100, None)),  # ragged last z chunk
                                        ("bubble3d_256x256x128", (32, 16, 32)),
-                                       ("bubble3d_256x256x128", (20, 150, 12))])
+                                       ("bubble3d_256x256x128", (20, 150, 12)),
+                                       # odd nx: the FP32 iteration kernel without x-pairs
+                                       ("bubble3d_256x256x128", (33, 17, 9))])
 def test_mixed_precision_reaches_fp64_residual(oracle_lib, gea_mod, name, dims):
     """FP32 inner CG with FP64 refinement: every solve's true FP64 residual
     meets tol, and each field is as close to the tightly solved oracle

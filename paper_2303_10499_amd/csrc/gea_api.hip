@@ -828,9 +828,8 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   return (gea_status)out->status;
 }
 
-// the flexible CG's vectors on the inner FP32 system (the starting residual
-// is kept in q132, which the resumed Jacobi-PCG first writes at its
-// iteration 1)
+// the flexible CG's vectors on the inner FP32 system (no copy of the
+// starting residual: see learned_inner)
 FcgVectors& fcg_vectors(gea_ctx* x) {
   FcgVectors& v = x->fv;
   v.d = x->d32;
@@ -840,7 +839,7 @@ FcgVectors& fcg_vectors(gea_ctx* x) {
   v.p0 = x->p032;
   v.p1 = x->p132;
   v.q = x->q32;
-  v.r0 = x->q132;
+  v.r0 = nullptr;
   v.c = x->c32;
   v.D = x->D32;
   v.dinv = x->dinv32;
@@ -852,10 +851,15 @@ FcgVectors& fcg_vectors(gea_ctx* x) {
 // `steps` iterations and returns how many it enqueued.  The host reads the
 // flexible-CG scalars only between iterations, never after the last one:
 // the caller reads them with its next read of the solver scalars.  (After
-// the stop decision the iteration kernels return at once.)
-int learned_inner(gea_ctx* x, int budget, int steps) {
+// the stop decision the iteration kernels return at once.)  With several
+// steps the set-up keeps the starting residual in q132 (the resumed
+// Jacobi-PCG first writes it at its iteration 1) for fcg_handover; a single
+// step forms the resume's partials itself: *res_parts is their count.
+int learned_inner(gea_ctx* x, int budget, int steps, int* res_parts) {
   const Geo& G = x->G;
   FcgVectors& v = fcg_vectors(x);
+  if (steps > 1) v.r0 = x->q132;
+  *res_parts = 0;
   // the first application is timed (set-up, network and flexible-CG step)
   const bool timed = x->t_net_ms < 0 && !x->net_probe;
   if (timed) HIPCHK(hipEventRecord(x->ev_net[0], x->stream));
@@ -874,7 +878,10 @@ int learned_inner(gea_ctx* x, int budget, int steps) {
       cnn_forward_scaled(x->net, &x->fsc->s, x->z32);
     });
     const bool last = it + 1 == cap;
-    x->timer.run(2, x->stream, [&] { fcg_iteration_after_z(x->stream, G, v, it, last, x->fsc); });
+    x->timer.run(2, x->stream, [&] {
+      const int n = fcg_iteration_after_z(x->stream, G, v, it, last, x->fsc);
+      if (last) *res_parts = n;
+    });
     HIPCHK(hipGetLastError());
     ++it;
     if (timed && it == 1) {
@@ -917,9 +924,17 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   // (when the flexible CG has converged the resumed solve starts done and its
   // iteration kernels return at once); returns the network steps enqueued
   auto learned_then_resume = [&](int budget) {
-    const int launched = learned_inner(x, budget, x->prm.learned_steps);
+    int res_parts = 0;
+    const int launched = learned_inner(x, budget, x->prm.learned_steps, &res_parts);
     const int left = budget - launched;
-    x->timer.run(4, x->stream, [&] { fcg_handover(x->stream, G, x->fv, w, left > 0 ? left : 0); });
+    // (one step: its one iteration was the last, so res_parts > 0; several:
+    // the starting residual was kept)
+    x->timer.run(4, x->stream, [&] {
+      if (res_parts > 0)
+        cg_resume_scalars(x->stream, x->fv.part_d, res_parts, w, left > 0 ? left : 0);
+      else
+        fcg_handover(x->stream, G, x->fv, w, left > 0 ? left : 0);
+    });
     return launched;
   };
   out->rel_res0 = -1.0;

@@ -201,7 +201,10 @@ __global__ __launch_bounds__(kBlock) void k_fcg_spmv3(Geo G, int kc, int iter,
 // partials ||r||^2 and max |r| (as a sum of per-workgroup maxima stored apart).
 // Iteration 0 (ITER0): p = z, <z, r> from the direction kernel's partials,
 // and d = alpha p (d needs no clearing; it is cleared here when the solve has
-// already stopped).  The last iteration (LAST) keeps no r_old.
+// already stopped).  The last iteration (LAST) keeps no r_old and, when
+// res_part is set, also forms the partials <r, r/diag>, <r, r> of the
+// residual the resumed Jacobi-PCG starts from (also when the solve had
+// stopped before this iteration).
 template <bool ITER0, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* __restrict__ d,
                                                        const float* p,
@@ -209,7 +212,9 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
                                                        float* __restrict__ r_old,
                                                        const float* __restrict__ q,
                                                        const double* pq_part, int np,
-                                                       double* part, FcgScalars* sc) {
+                                                       double* part, FcgScalars* sc,
+                                                       const float* __restrict__ dinv,
+                                                       double* res_part) {
   bool step = !sc->done;
   float alpha = 0.f;
   if (step) {
@@ -231,23 +236,31 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
     }
     alpha = (float)alpha_d;
   }
-  if (!step && !ITER0) return;
+  if (!step && !ITER0 && !(LAST && res_part)) return;
   __shared__ double sh[2][kBlock / 64];
   double v[2] = {0.0, 0.0};
+  double w[2] = {0.0, 0.0};
+  const bool res = LAST && res_part;
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
+    float rn = r[P];
     if (step) {
       if (ITER0)
         d[P] = alpha * p[P];
       else
         d[P] += alpha * p[P];
-      const float ro = r[P];
+      const float ro = rn;
       if (!LAST) r_old[P] = ro;
-      const float rn = ro - alpha * q[P];
+      rn = ro - alpha * q[P];
       r[P] = rn;
       v[0] += (double)rn * (double)rn;
       v[1] = fmax(v[1], fabs((double)rn));
-    } else {
-      d[P] = 0.f;  // (ITER0 only: the other iterations returned above)
+    } else if (ITER0) {
+      d[P] = 0.f;
+    }
+    if (res) {
+      const double rd = (double)rn;
+      w[0] += rd * (double)(rn * dinv[P]);
+      w[1] += rd * rd;
     }
   }
   if (step) {
@@ -257,15 +270,19 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
       part[gridDim.x + blockIdx.x] = v[1];
     }
   }
+  if (res) store_part<2>(w, res_part);
 }
 
-// Hand-over to Jacobi-PCG: the residual of the flexible CG's correction
-// taken afresh, r = r0 - A d with the inner system's FP32 operator, in place
-// of the recurrence residual, and the resumed solve's set-up partials
-// <r, r/diag>, <r, r>.  A few flexible steps with poor directions (long steps
-// that mostly cancel) leave a recurrence residual that has drifted far from
-// the true one at FP32 rounding of d; resumed from it, the Jacobi-PCG would
-// converge on the drift and leave it to the next refinement step.
+// Hand-over to Jacobi-PCG after several flexible steps: the residual of the
+// flexible CG's correction taken afresh, r = r0 - A d with the inner
+// system's FP32 operator, in place of the recurrence residual, and the
+// resumed solve's set-up partials <r, r/diag>, <r, r>.  Flexible steps with
+// poor directions (long steps that mostly cancel) leave a recurrence
+// residual that has drifted far from the true one at FP32 rounding of d;
+// resumed from it, the Jacobi-PCG would converge on the drift and leave it to
+// the next refinement step.  (After a single step, r0 - alpha A z differs
+// from r0 - A (alpha z) by rounding of terms no larger than r0 itself, and
+// the last update's partials serve.)
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_fcg_handover(Geo G, const float* __restrict__ d,
                                                          const float* __restrict__ r0,
@@ -342,16 +359,16 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
 }
 
 // inner start: partials ||r||^2 and max |r| of r (= r32, set by the
-// refinement residual), and its copy r0 for the hand-over.  d, the direction
-// and r_old need no clearing: the first iteration writes d and reads neither
-// of the others.
+// refinement residual), and (when r0 is set) its copy for the hand-over.
+// d, the direction and r_old need no clearing: the first iteration writes d
+// and reads neither of the others.
 __global__ __launch_bounds__(kBlock) void k_fcg_start(int n, const float* __restrict__ r,
                                                       float* __restrict__ r0, double* part) {
   __shared__ double sh[2][kBlock / 64];
   double v[2] = {0.0, 0.0};
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
     const float rf = r[P];
-    r0[P] = rf;
+    if (r0) r0[P] = rf;
     const double rv = rf;
     v[0] += rv * rv;
     v[1] = fmax(v[1], fabs(rv));
@@ -412,8 +429,8 @@ void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, const CgScalars
                      sys, max_iter, sc);
 }
 
-void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
-                           FcgScalars* sc) {
+int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
+                          FcgScalars* sc) {
   const int gu = grid_for(G.nc);
   const dim3 gr(gu), bl(kBlock);
   const bool it0 = iter == 0;
@@ -447,7 +464,8 @@ void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int
   }
 #define GEA_UPD(I0, L)                                                                          \
   hipLaunchKernelGGL((k_fcg_update<I0, L>), gr, bl, 0, s, G.nc, iter, v.d, p_upd, v.r, v.r_old, \
-                     (const float*)v.q, (const double*)v.part_s, ns, v.part_u, sc)
+                     (const float*)v.q, (const double*)v.part_s, ns, v.part_u, sc, v.dinv,       \
+                     v.r0 ? nullptr : v.part_d)
   if (it0 && last) GEA_UPD(true, true);
   else if (it0) GEA_UPD(true, false);
   else if (last) GEA_UPD(false, true);
@@ -455,6 +473,7 @@ void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int
 #undef GEA_UPD
   hipLaunchKernelGGL(k_fcg_check, dim3(1), bl, 0, s, (const double*)v.part_u, gu, iter + 1, 0,
                      (const CgScalars*)nullptr, 0, sc);
+  return last && !v.r0 ? gu : 0;
 }
 
 void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter) {

@@ -307,7 +307,7 @@ struct FcgScalars {
 
 struct FcgVectors {
   float *d, *r, *r_old, *z, *p0, *p1, *q;
-  float* r0;          // the starting residual, kept for the hand-over
+  float* r0;          // the starting residual, kept for the hand-over (or null)
   const float *c, *D;
   const float* dinv;  // 1/diag, for the resumed Jacobi-PCG's set-up
   double *part_d, *part_s, *part_u;
@@ -318,11 +318,14 @@ struct FcgVectors {
 void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, const CgScalars* sys,
                int max_iter, FcgScalars* sc);
 // one iteration once z = M(r) is in v.z: dots, direction + operator, update,
-// check (last: the last one enqueued, which keeps no r_old)
-void fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
-                           FcgScalars* sc);
-// hand-over to the Jacobi-PCG that resumes the inner solve from the flexible
-// CG's iterate d: v.r = r0 - A d afresh, then the resumed solve's scalars in
+// check (last: the last one enqueued, which keeps no r_old).  Without r0
+// (a single flexible step) the last one also sets up the Jacobi-PCG that
+// resumes the solve: 2 x n partials <r, r/diag>, <r, r> in v.part_d, n the
+// returned count, else 0 (then cg_resume_scalars finishes the set-up).
+int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
+                          FcgScalars* sc);
+// hand-over after several flexible steps (v.r0 kept): v.r = r0 - A d afresh
+// from the flexible CG's iterate d, then the resumed Jacobi-PCG's scalars in
 // w.sc (max_iter iterations remain)
 void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter);
 // training pair: s = max |r0| (s_out[0], 1/s in s_out[1]); in_r = r0/s,

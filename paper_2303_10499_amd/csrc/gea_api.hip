@@ -715,6 +715,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
   const CgWork& w = x->w32;
   cast_system(x);
   CgVectors<float> v{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
+  v.xo = xv;  // the last inner update corrects xv (launch_add_correction then does nothing)
   int total = 0;
   int outer = 0;
   CgScalars h64, h32;
@@ -749,7 +750,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
       for (int j = 0; j < unread_n; ++j) iterate(j, j > 0, j == unread_n - 1);
       HIPCHK(hipGetLastError());
       snapshot(x, x->sc32, &s_cg, sizeof s_cg);
-      x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32); });
+      x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32, x->sc32); });
       unread = true;
       unread_outer = outer;
       ++outer;
@@ -780,7 +781,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
           out->status = GEA_ERR_NAN;
           break;
         }
-        x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+        x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32); });
         continue;
       }
       last32_of(unread_outer) = s_cg.iter;
@@ -821,7 +822,7 @@ gea_status solve_mixed(gea_ctx* x, double* xv, gea_solve_stats* out) {
       out->status = GEA_ERR_NAN;
       break;
     }
-    x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+    x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32); });
   }
   out->iters = total;
   out->outer_iters = outer;
@@ -905,6 +906,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
   const CgWork& w = x->w32;
   cast_system(x);
   CgVectors<float> v{x->d32, x->r32, x->r132, x->p032, x->p132, x->q32, x->q132, x->c32, x->D32, x->dinv32, x->r32};
+  v.xo = xv;  // (as in solve_mixed)
   int total = 0, outer = 0, fallbacks = 0;
   bool use_net = true;
   CgScalars h64, h32;
@@ -965,7 +967,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       HIPCHK(hipGetLastError());
       snapshot(x, x->sc32, &s_cg, sizeof s_cg);
       snapshot(x, x->fsc, &s_fcg, sizeof s_fcg);
-      x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32); });
+      x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32, x->sc32); });
       unread = true;
       unread_bound = launched + unread_first;
       ++outer;
@@ -1001,7 +1003,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
           out->status = GEA_ERR_NAN;
           break;
         }
-        x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+        x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32); });
         continue;
       }
     }
@@ -1054,7 +1056,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
     total += done_iters;
     ++outer;
     // a stalled learned correction is still a descent step: keep it
-    x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32); });
+    x->timer.run(4, x->stream, [&] { launch_add_correction(x->stream, G, xv, x->d32, x->sc32); });
   }
   out->iters = total;
   out->outer_iters = outer;

@@ -209,10 +209,26 @@ __device__ __forceinline__ bool step_take(const CgStep& st, CgScalars* sc, T& al
   return true;
 }
 
-// (after the last x update) later launches of the batch return at once
-__device__ __forceinline__ void step_last(const CgStep& st, CgScalars* sc) {
-  if (blockIdx.x == 0 && threadIdx.x == 0)
+// (after the last x update) later launches of the batch return at once;
+// corrected: that update also corrected the outer iterate
+__device__ __forceinline__ void step_last(const CgStep& st, CgScalars* sc, bool corrected) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (corrected) sc->corrected = 1;
     __hip_atomic_store(&sc->done_iter, st.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// The last x update at cell P: x += alpha p, or, for an inner solve of the
+// refinement, the outer iterate takes the updated inner one (rounded to T as
+// a stored x would be) and x is left as it was (the next refinement
+// residual clears it).
+template <typename T>
+__device__ __forceinline__ void last_update(const CgIter<T>& v, int P, T alpha) {
+  const T xn = v.x[P] + alpha * v.p_in[P];
+  if (v.xo)
+    v.xo[P] += (double)xn;
+  else
+    v.x[P] = xn;
 }
 
 template <int NDIM, typename T>
@@ -332,6 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(const double* u_part, int n
   sc->beta = 0.0;
   sc->fin = 0;
   sc->done_iter = -1;
+  sc->corrected = 0;
   sc->rz = s[0];
   sc->rr = s[1];
   sc->rr0 = s[1];
@@ -579,9 +596,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
       if (in[m])
         for (int k = k0; k < k1; ++k) {
           const int P = i + nx * (jo[m] + ny * k);
-          v.x[P] += alpha * v.p_in[P];
+          last_update(v, P, alpha);
         }
-    step_last(stp, sc);
+    step_last(stp, sc, v.xo != nullptr);
     return;
   }
   if (PF == 2) {
@@ -650,11 +667,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
   if (!step_take(stp, sc, alpha, beta, fin)) return;
   if (fin) {  // the solve has converged: its last x update only
     if (in)
-      for (int k = k0; k < k1; ++k) {
-        const int P = i + nx * k;
-        v.x[P] += alpha * v.p_in[P];
-      }
-    step_last(stp, sc);
+      for (int k = k0; k < k1; ++k) last_update(v, i + nx * k, alpha);
+    step_last(stp, sc, v.xo != nullptr);
     return;
   }
   // new residual and direction from raw values
@@ -878,6 +892,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_check(const double* o_part,
   sc32->beta = 0.0;
   sc32->fin = 0;
   sc32->done_iter = -1;
+  sc32->corrected = 0;
   // inner tolerance: what the outer residual still needs (times the target
   // fraction, a margin for the FP32 solve's own error), never looser than
   // 0.5 nor tighter than the configured inner tolerance
@@ -909,6 +924,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_resume_start(const double* part, 
   sc->beta = 0.0;
   sc->fin = 0;
   sc->done_iter = -1;
+  sc->corrected = 0;
   sc->iter = 0;
   sc->max_iter = max_iter;
   const bool finite = isfinite(s[0]) && isfinite(s[1]);
@@ -938,8 +954,9 @@ __global__ __launch_bounds__(kBlock) void k_sub(int n, const double* b, double* 
 }
 
 __global__ __launch_bounds__(kBlock) void k_add_correction(int n, double* x, const float* dx,
+                                                           const CgScalars* own,
                                                            const CgScalars* gate) {
-  if (gate_closed(gate)) return;
+  if (gate_closed(gate) || own->corrected) return;
   for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x)
     x[P] += (double)dx[P];
 }
@@ -986,7 +1003,7 @@ CgIter<T> iter_vectors(const CgVectors<T>& v, int iter) {
                    odd ? v.r1 : v.r, odd ? v.r : v.r1,
                    iter == 0 ? v.r : (odd ? v.q : v.q1), odd ? v.q1 : v.q,
                    iter == 0 ? v.r : (odd ? v.p1 : v.p0), odd ? v.p0 : v.p1,
-                   v.c, v.D, v.dinv, v.Dc};
+                   v.c, v.D, v.dinv, v.Dc, v.xo};
 }
 
 bool cg_folds(const CgWork& w) { return w.ns <= kFoldMaxParts; }
@@ -1064,8 +1081,9 @@ void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const doub
 }
 
 void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx,
-                           const CgScalars* gate) {
-  hipLaunchKernelGGL(k_add_correction, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, x, dx, gate);
+                           const CgScalars* own, const CgScalars* gate) {
+  hipLaunchKernelGGL(k_add_correction, dim3(grid_for(G.nc)), dim3(kBlock), 0, s, G.nc, x, dx, own,
+                     gate);
 }
 
 void cg_start_from(hipStream_t s, const double* u_part, int nu, const double* b_part, double tol,

@@ -54,6 +54,8 @@ struct CgScalars {
   int fin;          // 1: the next iteration kernel applies the last x update only
   int done_iter;    // the launch that applied the last update (later launches of its
                     // batch return at once); -1 while the solve runs
+  int corrected;    // 1: that last update also added the iterate to the outer one
+                    // (an inner solve of the refinement, CgVectors::xo)
 };
 
 // Number of workgroups of the grid-stride kernels: a fixed multiple of the
@@ -173,6 +175,10 @@ struct CgVectors {
   const T* dinv;
   const T* b;
   T Dc = T(0);
+  // FP32 inner solve of the refinement: its outer FP64 iterate, to which the
+  // last update adds the inner one (x + alpha p, not stored back to x); null
+  // otherwise
+  double* xo = nullptr;
 };
 
 // The vectors one iteration kernel reads (_in) and writes (_out).
@@ -189,6 +195,7 @@ struct CgIter {
   const T* D;
   const T* dinv;
   T Dc;  // D in every cell when the kernel's CD flag is set (D unused)
+  double* xo;  // (CgVectors::xo)
 };
 
 // Per-workgroup partial sums of one CG instance: s (iteration kernel, 7
@@ -246,8 +253,10 @@ void launch_residual64(hipStream_t s, const Geo& G, const double* c, const doubl
                        const CgScalars* gate = nullptr);
 void launch_cast_coeffs(hipStream_t s, const Geo& G, const double* c, const double* D,
                         const double* dinv, float* c32, float* D32, float* dinv32);
+// x += dx unless the inner solve's last update added it already (own: that
+// solve's scalars) or, with a gate, that solve is not done
 void launch_add_correction(hipStream_t s, const Geo& G, double* x, const float* dx,
-                           const CgScalars* gate = nullptr);
+                           const CgScalars* own, const CgScalars* gate = nullptr);
 // y = b - y
 void launch_sub(hipStream_t s, const Geo& G, const double* b, double* y);
 // a = v

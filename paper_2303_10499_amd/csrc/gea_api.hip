@@ -410,7 +410,7 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned, bool trans
   x->z32 = cv.take<float>(nc);
   x->pair_part = cv.take<double>(3 * 2048);
   x->pair_s = cv.take<double>(2);
-  x->fv.part_d = cv.take<double>(2 * 2048);
+  x->fv.part_d = cv.take<double>(4 * 2048);  // (4 sums a workgroup at the hand-over)
   x->fv.part_s = cv.take<double>(2 * (size_t)std::max(2048, zplan(make_geo(m)).blocks));
   x->fv.part_u = cv.take<double>(2 * 2048);
   // the network (inference buffers) only for the learned form on a mesh whose
@@ -935,7 +935,7 @@ gea_status solve_learned(gea_ctx* x, double* xv, gea_solve_stats* out) {
       if (res_parts > 0)
         cg_resume_scalars(x->stream, x->fv.part_d, res_parts, w, left > 0 ? left : 0);
       else
-        fcg_handover(x->stream, G, x->fv, w, left > 0 ? left : 0);
+        fcg_handover(x->stream, G, x->fv, w, left > 0 ? left : 0, x->fsc);
     });
     return launched;
   };

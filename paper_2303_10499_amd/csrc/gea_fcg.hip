@@ -10,8 +10,13 @@
 // network's correction itself, so the first step is the learned initial
 // guess with an optimal step length.  A one-workgroup kernel per iteration
 // publishes ||r||, max |r| (the next scale) and the stop / stall decision:
-// converged, non-finite, or ||r|| not reduced by 10 % over 10 iterations
-// (then the caller falls back to Jacobi-PCG).
+// converged, non-finite, ||r|| grown past twice its start, or ||r|| not
+// reduced by 10 % over 10 iterations (then the caller falls back to
+// Jacobi-PCG).  A network that does not fit the system (far outside what it
+// was trained on) can make the flexible iteration diverge within a few
+// steps, its residual growing by tens of orders of magnitude before the
+// ten-iteration test would see it: hence the growth test, and the hand-over
+// that drops a correction leaving the true residual above the start.
 #include "gea_reduce.h"
 
 namespace gea {
@@ -292,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_handover(Geo G, const float* __r
                                                          float* __restrict__ r, double* part) {
   float kk[NDIM];
   for (int k = 0; k < NDIM; ++k) kk[k] = (float)(G.S[k] / G.h[k]);
-  double w[2] = {0.0, 0.0};
+  double w[4] = {0.0, 0.0, 0.0, 0.0};
   GEA_FOR_CELLS(P, G) {
     int cc[NDIM];
     cell_coords<NDIM>(G, P, cc);
@@ -304,13 +309,46 @@ __global__ __launch_bounds__(kBlock) void k_fcg_handover(Geo G, const float* __r
       if (cc[k] + 1 < G.n[k]) a += 0.5f * (Dp + D[P + st]) * kk[k] * (dp - d[P + st]);
       if (cc[k] > 0) a += 0.5f * (D[P - st] + Dp) * kk[k] * (dp - d[P - st]);
     }
-    const float rn = r0[P] - a;
+    const float r0p = r0[P], mp = dinv[P];
+    const float rn = r0p - a;
     r[P] = rn;
-    const double rd = (double)rn;
-    w[0] += rd * (double)(rn * dinv[P]);
+    const double rd = (double)rn, r0d = (double)r0p;
+    w[0] += rd * (double)(rn * mp);
     w[1] += rd * rd;
+    w[2] += r0d * (double)(r0p * mp);
+    w[3] += r0d * r0d;
   }
-  store_part<2>(w, part);
+  store_part<4>(w, part);
+}
+
+// One workgroup after the hand-over pass: keep the flexible CG's correction
+// (<r, r/diag>, <r, r> of r = r0 - A d) or, when that residual is not finite
+// or larger than r0, drop it (restart: d = 0, r = r0, and r0's sums); the
+// chosen pair goes to pick[0], pick[1] for the resumed solve's set-up.
+__global__ __launch_bounds__(kBlock) void k_fcg_pick(const double* part, int n, double* pick,
+                                                     FcgScalars* sc) {
+  __shared__ double sh[4][kBlock / 64];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < n; b += kBlock)
+    for (int k = 0; k < 4; ++k) a[k] += part[k * n + b];
+  Reducer<0u, 4>::block(a, sh);
+  if (threadIdx.x != 0) return;
+  const bool keep = isfinite(a[0]) && isfinite(a[1]) && a[1] <= a[3];
+  sc->restart = keep ? 0 : 1;
+  pick[0] = keep ? a[0] : a[2];
+  pick[1] = keep ? a[1] : a[3];
+}
+
+// d = 0, r = r0 where the pick dropped the flexible CG's correction
+__global__ __launch_bounds__(kBlock) void k_fcg_restart(int n, float* __restrict__ d,
+                                                        float* __restrict__ r,
+                                                        const float* __restrict__ r0,
+                                                        const FcgScalars* sc) {
+  if (!sc->restart) return;
+  for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < n; P += gridDim.x * blockDim.x) {
+    d[P] = 0.f;
+    r[P] = r0[P];
+  }
 }
 
 // One workgroup: ||r||^2 and max |r| from the update partials (or from the
@@ -343,8 +381,8 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
   sc->hist[iter % 10] = a[0];
   int done = init && sys->done ? 1 : 0;  // nothing to solve (the refinement has converged)
   if (done) {
-  } else if (!isfinite(a[0]) || !isfinite(a[1])) {
-    sc->status = 1;  // stall: fall back
+  } else if (!isfinite(a[0]) || !isfinite(a[1]) || a[0] > 4.0 * sc->bb) {
+    sc->status = 1;  // stall (or divergence): fall back
     done = 1;
   } else if (a[0] <= sc->tol2 * sc->bb) {
     done = 1;
@@ -476,7 +514,8 @@ int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int 
   return last && !v.r0 ? gu : 0;
 }
 
-void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter) {
+void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter,
+                  FcgScalars* sc) {
   const int gu = grid_for(G.nc);
   if (G.ndim == 2)
     hipLaunchKernelGGL(k_fcg_handover<2>, dim3(gu), dim3(kBlock), 0, s, G, (const float*)v.d,
@@ -484,7 +523,11 @@ void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork
   else
     hipLaunchKernelGGL(k_fcg_handover<3>, dim3(gu), dim3(kBlock), 0, s, G, (const float*)v.d,
                        (const float*)v.r0, v.c, v.D, v.dinv, v.r, v.part_d);
-  cg_resume_scalars(s, v.part_d, gu, w, max_iter);
+  // (part_u is free once the last check has run)
+  hipLaunchKernelGGL(k_fcg_pick, dim3(1), dim3(kBlock), 0, s, (const double*)v.part_d, gu, v.part_u, sc);
+  hipLaunchKernelGGL(k_fcg_restart, dim3(gu), dim3(kBlock), 0, s, G.nc, v.d, v.r, (const float*)v.r0,
+                     (const FcgScalars*)sc);
+  cg_resume_scalars(s, v.part_u, 1, w, max_iter);
 }
 
 void pair_outputs(hipStream_t s, const Geo& G, const double* r0, const double* c,

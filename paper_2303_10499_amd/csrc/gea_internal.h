@@ -311,7 +311,8 @@ struct FcgScalars {
   double hist[10];      // ||r||^2 of the last ten iterations (stall test)
   int iter, max_iter;
   int done;
-  int status;           // 0 ok, 1 stalled or non-finite (fall back), 2 iteration cap
+  int status;           // 0 ok, 1 stalled, diverging or non-finite (fall back), 2 iteration cap
+  int restart;          // the hand-over dropped the correction (the resumed solve starts at 0)
 };
 
 struct FcgVectors {
@@ -334,9 +335,11 @@ void fcg_start(hipStream_t s, const Geo& G, const FcgVectors& v, const CgScalars
 int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int iter, bool last,
                           FcgScalars* sc);
 // hand-over after several flexible steps (v.r0 kept): v.r = r0 - A d afresh
-// from the flexible CG's iterate d, then the resumed Jacobi-PCG's scalars in
-// w.sc (max_iter iterations remain)
-void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter);
+// from the flexible CG's iterate d (or, when that is not finite or larger
+// than r0, d = 0 and r = r0: sc->restart), then the resumed Jacobi-PCG's
+// scalars in w.sc (max_iter iterations remain)
+void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter,
+                  FcgScalars* sc);
 // training pair: s = max |r0| (s_out[0], 1/s in s_out[1]); in_r = r0/s,
 // in_a = c/diag, out_d = (x - x0)/s
 void pair_outputs(hipStream_t s, const Geo& G, const double* r0, const double* c,

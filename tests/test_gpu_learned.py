@@ -505,6 +505,40 @@ def test_learned_form_keeps_the_refinement_iteration_count_over_steps(learned):
     assert its["learned"] <= 1.03 * its["mixed"] + 20
 
 
+@pytest.mark.parametrize("dims,steps", [((512, 512), 8), ((1024, 1024), 3)])
+def test_diverging_flexible_cg_falls_back(learned, dims, steps):
+    """The 2D network on meshes it was not trained for, as a preconditioner
+    of up to 25 flexible-CG steps a solve: its iteration diverges (the
+    recurrence residual grew from ||r0||^2 ~ 9 to 1e43 within ten steps and
+    overflowed FP32, the step failing as non-finite).  The growth stop
+    (||r|| past twice its start) and the hand-over that drops a correction
+    leaving the true residual above r0 make every step succeed, every solve
+    reach the tolerance in the refinement's outer-step count, and the
+    inner iterations stay within 10 % of the refinement alone's."""
+    from paper_2303_10499_amd import gea
+    per = {}
+    for form, ls in (("mixed", 1), ("learned", 25)):
+        cfg = configs.scaled("nonsmooth2d_2048", dims[0], dims[1])
+        cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=200000, learned_steps=ls,
+                             learned_always=1)
+        S = gea.Solver(cfg["mesh"], cfg["params"], solver=form)
+        if form == "learned":
+            S.load_weights()
+        S.init_bubble(**cfg["bubble"])
+        per[form] = []
+        for n in range(steps):
+            st = S.step(1)
+            for k in range(st.n_solves):
+                assert st.solve[k].status == 0 and st.solve[k].rel_res <= 1e-8, (form, n, k)
+                per[form].append((st.solve[k].iters, st.solve[k].outer_iters))
+        S.close()
+    its = {f: sum(i for i, _ in v) for f, v in per.items()}
+    print("inner iterations", its, "outer steps", {f: [o for _, o in v] for f, v in per.items()})
+    for (_, o_l), (_, o_m) in zip(per["learned"], per["mixed"]):
+        assert o_l <= o_m + 1
+    assert its["learned"] <= 1.10 * its["mixed"] + 20
+
+
 def test_learned_gate_keeps_the_network_off_where_it_does_not_pay(learned):
     """The gate runs the network on a corrector's solve while the inner
     iterations it saves take longer than one application (both timed on the

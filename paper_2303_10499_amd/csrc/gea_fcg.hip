@@ -11,12 +11,14 @@
 // guess with an optimal step length.  A one-workgroup kernel per iteration
 // publishes ||r||, max |r| (the next scale) and the stop / stall decision:
 // converged, non-finite, ||r|| grown past twice its start, or ||r|| not
-// reduced by 10 % over 10 iterations (then the caller falls back to
-// Jacobi-PCG).  A network that does not fit the system (far outside what it
-// was trained on) can make the flexible iteration diverge within a few
-// steps, its residual growing by tens of orders of magnitude before the
-// ten-iteration test would see it: hence the growth test, and the hand-over
-// that drops a correction leaving the true residual above the start.
+// reduced by 10 % over the last 3 iterations (then the caller falls back to
+// Jacobi-PCG, whose iterations cost a small fraction of a network
+// application: the 3D network's first step cuts ||r||^2 about a hundredfold
+// and the next ones leave it flat).  A network that does not fit the system
+// (far outside what it was trained on) can make the flexible iteration
+// diverge within a few steps, its residual growing by tens of orders of
+// magnitude: hence the growth test, and the hand-over that drops a
+// correction leaving the true residual above the start.
 #include "gea_reduce.h"
 
 namespace gea {
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
   sc->iter = iter;
   sc->s = a[1];
   sc->inv_s = a[1] > 0 ? 1.0 / a[1] : 0.0;
-  const double old = sc->hist[iter % 10];   // ||r||^2 ten iterations ago
+  const double old = sc->hist[(iter + 7) % 10];  // ||r||^2 three iterations ago
   sc->hist[iter % 10] = a[0];
   int done = init && sys->done ? 1 : 0;  // nothing to solve (the refinement has converged)
   if (done) {
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
     done = 1;
   } else if (a[0] <= sc->tol2 * sc->bb) {
     done = 1;
-  } else if (iter >= 10 && a[0] > 0.81 * old) {
+  } else if (iter >= 3 && a[0] > 0.81 * old) {
     sc->status = 1;
     done = 1;
   } else if (iter >= sc->max_iter) {

@@ -88,12 +88,17 @@ typedef struct {
   double inner_tol;                /* relative tolerance of each inner solve (refined forms)         */
   int32_t learned_steps;           /* learned form: network-preconditioned flexible-CG iterations
                                       per solve before Jacobi-PCG continues (>= 1; 1 = the learned
-                                      initial guess with an optimal step length)                    */
+                                      initial guess with an optimal step length).  At most: the
+                                      iteration stops (a fallback) once ||r|| falls less than 10 %
+                                      over 3 iterations or grows past twice its start, and a
+                                      correction leaving the true residual above its start is
+                                      dropped                                                        */
   double inner_target;             /* refined forms: an inner solve aims at inner_target * tol ||b||
                                       for the outer residual (in (0, 1]; 0 selects 0.8)            */
   int32_t learned_always;          /* learned form: 0 = per corrector, run the network only while
                                       the inner iterations it saves (running averages with and
-                                      without it, the other way re-tried every 16th solve) take
+                                      without it, the other way re-tried after 16 solves, the
+                                      period doubling up to 256 while the choice holds) take
                                       longer than one application (both timed on the device);
                                       1 = on every solve                                          */
   int32_t energy_form;             /* Step 2: 0 = total-energy form (flux phi I4(e + R T)); 1 = the

@@ -90,7 +90,7 @@ typedef struct {
                                       per solve before Jacobi-PCG continues (>= 1; 1 = the learned
                                       initial guess with an optimal step length).  At most: the
                                       iteration stops (a fallback) once ||r|| falls less than 10 %
-                                      over 3 iterations or grows past twice its start, and a
+                                      over 2 iterations or grows past twice its start, and a
                                       correction leaving the true residual above its start is
                                       dropped                                                        */
   double inner_target;             /* refined forms: an inner solve aims at inner_target * tol ||b||

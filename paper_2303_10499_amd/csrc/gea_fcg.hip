@@ -11,10 +11,11 @@
 // guess with an optimal step length.  A one-workgroup kernel per iteration
 // publishes ||r||, max |r| (the next scale) and the stop / stall decision:
 // converged, non-finite, ||r|| grown past twice its start, or ||r|| not
-// reduced by 10 % over the last 3 iterations (then the caller falls back to
+// reduced by 10 % over the last 2 iterations (then the caller falls back to
 // Jacobi-PCG, whose iterations cost a small fraction of a network
 // application: the 3D network's first step cuts ||r||^2 about a hundredfold
-// and the next ones leave it flat).  A network that does not fit the system
+// and the next ones leave it flat; one flat step is tolerated, as a
+// Polak-Ribiere direction can recover on the next).  A network that does not fit the system
 // (far outside what it was trained on) can make the flexible iteration
 // diverge within a few steps, its residual growing by tens of orders of
 // magnitude: hence the growth test, and the hand-over that drops a
@@ -379,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
   sc->iter = iter;
   sc->s = a[1];
   sc->inv_s = a[1] > 0 ? 1.0 / a[1] : 0.0;
-  const double old = sc->hist[(iter + 7) % 10];  // ||r||^2 three iterations ago
+  const double old = sc->hist[(iter + 8) % 10];  // ||r||^2 two iterations ago
   sc->hist[iter % 10] = a[0];
   int done = init && sys->done ? 1 : 0;  // nothing to solve (the refinement has converged)
   if (done) {
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double* part, int n,
     done = 1;
   } else if (a[0] <= sc->tol2 * sc->bb) {
     done = 1;
-  } else if (iter >= 3 && a[0] > 0.81 * old) {
+  } else if (iter >= 2 && a[0] > 0.81 * old) {
     sc->status = 1;
     done = 1;
   } else if (iter >= sc->max_iter) {

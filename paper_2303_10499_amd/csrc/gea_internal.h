@@ -308,7 +308,7 @@ struct FcgScalars {
   double rr, bb, tol2;
   double s, inv_s;      // max |r| and its inverse (scale of the network input)
   double rz_prev[2];    // <z, r> of iterations of even / odd index
-  double hist[10];      // ||r||^2 of the last ten iterations (the stall test reads 3 back)
+  double hist[10];      // ||r||^2 of the last ten iterations (the stall test reads 2 back)
   int iter, max_iter;
   int done;
   int status;           // 0 ok, 1 stalled, diverging or non-finite (fall back), 2 iteration cap

@@ -427,7 +427,10 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 // new residual and x update are stored there, and their residual and 1/diag
 // stay in the thread's registers for the dot products of the plane, which
 // is computed one step later.
-// CD: D is v.Dc in every cell (no D array is read)
+// CD: D is v.Dc in every cell (no D array is read), and 1/diag is formed
+// from c (the diagonal is c plus Dc S/h for each face inside the mesh, summed
+// in the order the energy system's set-up sums it), so c is staged in place
+// of 1/diag and no 1/diag array is read
 template <typename T, bool CD>
 __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgIter<T> v,
                                                      CgStep stp, CgScalars* sc) {
@@ -461,16 +464,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
     in[m] = i < nx && jo[m] < ny;
   }
   const T kx = K.k[0], ky = K.k[1], kz = K.k[2];
+  const T wx = v.Dc * kx, wy = v.Dc * ky, wz = v.Dc * kz;  // (CD) face weights
   // staged cells of this thread: [0, RPT) its own cells, [RPT] halo cell e = t
   // (row 0, row TY+1, then the two side columns); global index in plane 0,
   // clamped into the mesh (values staged for cells outside it are never read,
   // and unconditional loads are not waited for where branches would merge)
   constexpr int NU = RPT + 1;
   int qh[NU], hh[NU];
+  // faces inside the mesh of each staged cell (CD): x+, x-, y+, y- in bits 0-3
+  int fm[NU];
+  auto faces = [&](int gi, int gj) {
+    return (gi + 1 < nx ? 1 : 0) | (gi > 0 ? 2 : 0) | (gj + 1 < ny ? 4 : 0) | (gj > 0 ? 8 : 0);
+  };
 #pragma unroll
   for (int m = 0; m < RPT; ++m) {
     hh[m] = (lx + 1) + HX * (jo[m] - j0 + 1);
     qh[m] = (i < nx ? i : nx - 1) + nx * (jo[m] < ny ? jo[m] : ny - 1);
+    fm[m] = faces(i, jo[m]);
   }
   {
     const int e = threadIdx.x;
@@ -487,6 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
     }
     const int gi = i0 + hx - 1, gj = j0 + hy - 1;
     hh[RPT] = hx + HX * hy;
+    fm[RPT] = faces(gi, gj);
     // threads without a halo cell load their own cell again (a cache hit)
     qh[RPT] = e < NH ? (gi < 0 ? 0 : (gi >= nx ? nx - 1 : gi)) + nx * (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj))
                      : qh[0];
@@ -510,10 +521,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
       f.q[u] = v.q_in[Q];
       f.p[u] = v.p_in[Q];
       f.d[u] = CD ? v.Dc : v.D[Q];
-      f.m[u] = v.dinv[Q];
+      f.m[u] = CD ? v.c[Q] : v.dinv[Q];  // (CD: c, turned into 1/diag when staged)
       if (u < RPT) {  // own cell: x for its update, c for the operator
         f.x[u] = ld_stream<true>(&v.x[Q]);
-        f.c[u] = ld_stream<true>(&v.c[Q]);
+        if (!CD) f.c[u] = ld_stream<true>(&v.c[Q]);
       }
     }
   };
@@ -538,12 +549,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter3(Geo G, Stencil<3, T> K, CgI
     for (int u = 0; u < NU; ++u) {
       if (u == RPT && !halo) break;
       const T rn = f.r[u] - alpha * f.q[u];
-      sp[sl][hh[u]] = rn * f.m[u] + beta * f.p[u];
+      T mv = f.m[u];
+      if constexpr (CD) {
+        T dg = f.m[u];
+        dg += (fm[u] & 1) ? wx : T(0);
+        dg += (fm[u] & 2) ? wx : T(0);
+        dg += (fm[u] & 4) ? wy : T(0);
+        dg += (fm[u] & 8) ? wy : T(0);
+        dg += kk + 1 < nz ? wz : T(0);
+        dg += kk > 0 ? wz : T(0);
+        mv = T(1) / dg;
+      }
+      sp[sl][hh[u]] = rn * mv + beta * f.p[u];
       sd[sl][hh[u]] = f.d[u];
       if (u < RPT) {
         r_own[u] = rn;
-        m_own[u] = f.m[u];
-        c_own[u] = f.c[u];
+        m_own[u] = mv;
+        c_own[u] = CD ? f.m[u] : f.c[u];
         if (kk >= k0 && kk < k1 && in[u]) {
           const int Q = qh[u] + plane * kk;
           st_stream<true>(rn, &v.r_out[Q]);

@@ -468,7 +468,7 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
 struct EnergySys {
   double* b;
   double* c;
-  double* dinv;
+  double* dinv;   // (2D; the 3D iteration kernel forms 1/diag from c)
   double* x;      // the solve's initial guess (and later solution); null: T_prev itself
   double* r;
   double* u_part;
@@ -825,10 +825,10 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     }
     if (c.act) {
       const int P = qo + pl * k;
+      // (1/diag is not stored: the 3D iteration kernel forms it from c)
       const double di = 1.0 / diag, rr = bP - ax;
       sy.b[P] = bP;
       sy.c[P] = cP;
-      sy.dinv[P] = di;
       if (sy.x) sy.x[P] = xc;  // (null: the solve runs in place on T_prev)
       sy.r[P] = rr;
       red[0] += rr * (rr * di);

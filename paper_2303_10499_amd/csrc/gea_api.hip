@@ -1079,7 +1079,8 @@ gea_status solve_energy(gea_ctx* x, double* T, int nparts, int sweep, int* iters
   const Geo& G = x->G;
   const CgWork& w = x->w64;
   // D = (mu/Pr) c_p in every cell: the iteration kernels take it as a value
-  CgVectors<double> v{T, x->r, x->r1, x->p0, x->p1, x->q, x->q1, x->c, nullptr, x->dinv, x->b,
+  // and form 1/diag from c (no 1/diag array)
+  CgVectors<double> v{T, x->r, x->r1, x->p0, x->p1, x->q, x->q1, x->c, nullptr, nullptr, x->b,
                       x->prm.mu / x->prm.Pr * x->prm.cp};
   x->timer.run(7, x->stream, [&] {
     cg_start_from(x->stream, w.u[1], nparts, w.b, kEnergyTol, x->prm.max_iter, w.sc);
@@ -1255,7 +1256,7 @@ gea_status steps_1_2(gea_ctx* x, const State& S, double* T_out, double* pp_out =
     int nparts = 0;
     x->timer.run(5, x->stream, [&] {
       nparts = launch_energy_rhs(s, G, ph, enth, ks, S.rho, x->e0, ks ? Ks : x->e0, T_prev, S.phi,
-                                 x->rho_star, Ks, x->Tbg, x->b, x->c, x->dinv,
+                                 x->rho_star, Ks, x->Tbg, x->b, x->c,
                                  T_next == T_prev ? nullptr : T_next, x->r, x->w64.u[1], x->w64.b);
     });
     HIPCHK(hipGetLastError());

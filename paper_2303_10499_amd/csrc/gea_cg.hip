@@ -662,10 +662,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
   const int ie = lane == 0 ? i - 1 : (lane == 63 ? i + 1 : -1);
   const bool edge = ie >= 0 && ie < nx;
   // raw values of row kk (old residual, old A p, old direction, D, 1/diag),
-  // own cell and edge cell
+  // own cell and edge cell (CD: me holds the edge cell's c, and 1/diag is
+  // formed from c where it is used, as in k_cg_iter3)
   struct Raw {
     T r, q, p, d, m, x, c, re, qe, pe, de, me;
   };
+  const T wx = v.Dc * kx, wz = v.Dc * kz;  // (CD) face weights
+  auto diag_inv = [&](T c, int ci, int kk) {
+    T dg = c;
+    dg += ci + 1 < nx ? wx : T(0);
+    dg += ci > 0 ? wx : T(0);
+    dg += kk + 1 < nz ? wz : T(0);
+    dg += kk > 0 ? wz : T(0);
+    return T(1) / dg;
+  };
+  auto m_own = [&](const Raw& w, int kk) { return CD ? diag_inv(w.c, i, kk) : w.m; };
+  auto m_edge = [&](const Raw& w, int kk) { return CD ? diag_inv(w.me, ie, kk) : w.me; };
   // unconditional loads from indices clamped into the mesh (values of cells
   // or rows outside it are never used; a load under a branch would be
   // waited for where the branches merge)
@@ -673,9 +685,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
   auto fetch = [&](int kk) {
     const int kc = kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk);
     const int Q = ic + nx * kc, Qe = iec + nx * kc;
-    return Raw{v.r_in[Q], v.q_in[Q], v.p_in[Q], CD ? v.Dc : v.D[Q], v.dinv[Q], ld_stream<NT2>(&v.x[Q]),
-               ld_stream<NT2>(&v.c[Q]),
-               v.r_in[Qe], v.q_in[Qe], v.p_in[Qe], CD ? v.Dc : v.D[Qe], v.dinv[Qe]};
+    return Raw{v.r_in[Q], v.q_in[Q], v.p_in[Q], CD ? v.Dc : v.D[Q], CD ? T(0) : v.dinv[Q],
+               ld_stream<NT2>(&v.x[Q]), ld_stream<NT2>(&v.c[Q]),
+               v.r_in[Qe], v.q_in[Qe], v.p_in[Qe], CD ? v.Dc : v.D[Qe], CD ? v.c[Qe] : v.dinv[Qe]};
   };
   // rows k0-1 .. k0+PD in flight while the scalars are formed or read;
   // afterwards row k+PD+1 is requested while row k is computed
@@ -696,20 +708,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
   // new residual and direction from raw values
   auto rnew = [&](T r, T q) { return r - alpha * q; };
   auto pnew = [&](T rn, T m, T po) { return rn * m + beta * po; };
-  T pm = pnew(rnew(wm.r, wm.q), wm.m, wm.p), dm = wm.d;
+  T pm = pnew(rnew(wm.r, wm.q), m_own(wm, k0 - 1), wm.p), dm = wm.d;
   Raw cur = ring[0];
-  T rc = rnew(cur.r, cur.q);
-  T pc = pnew(rc, cur.m, cur.p), dc = cur.d;
-  T pec = pnew(rnew(cur.re, cur.qe), cur.me, cur.pe), dec = cur.de;
+  T rc = rnew(cur.r, cur.q), mc = m_own(cur, k0);
+  T pc = pnew(rc, mc, cur.p), dc = cur.d;
+  T pec = pnew(rnew(cur.re, cur.qe), m_edge(cur, k0), cur.pe), dec = cur.de;
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int it = 0; it < KC; ++it) {
     const int k = k0 + it;
     if (k >= k1) break;
     const Raw wn = ring[(it + 1) % (PD + 1)];
-    const T rn = rnew(wn.r, wn.q);
-    const T pn = pnew(rn, wn.m, wn.p), dn = wn.d;
-    const T pen = pnew(rnew(wn.re, wn.qe), wn.me, wn.pe), den = wn.de;
+    const T rn = rnew(wn.r, wn.q), mn = m_own(wn, k + 1);
+    const T pn = pnew(rn, mn, wn.p), dn = wn.d;
+    const T pen = pnew(rnew(wn.re, wn.qe), m_edge(wn, k + 1), wn.pe), den = wn.de;
     // slot of row k is free now: request row k+PD+1 into it
     if (k + PD + 1 <= k1) ring[it % (PD + 1)] = fetch(k + PD + 1);
     T pl = __shfl_up(pc, 1, 64), pr = __shfl_down(pc, 1, 64);
@@ -733,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
       st_stream<NT2>(a, &v.q_out[P]);
       st_stream<NT2>(rc, &v.r_out[P]);
       st_stream<NT2>(cur.x + alpha * cur.p, &v.x[P]);
-      iter_dots(acc, pc, a, rc, cur.m);
+      iter_dots(acc, pc, a, rc, mc);
     }
     pm = pc;
     dm = dc;
@@ -742,6 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter2(Geo G, Stencil<2, T> K, CgI
     pec = pen;
     dec = den;
     rc = rn;
+    mc = mn;
     cur = wn;
   }
   store_partials<7>(acc, iter_part(stp.part, stp.ns, stp.iter));

@@ -114,7 +114,7 @@ void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho
 int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, bool ks,
                       const double* rho, const double* e0, const double* a_prev,
                       const double* T_prev, double* const* phi, const double* rho_star,
-                      const double* Ks, const double* Tbg, double* b, double* c, double* dinv,
+                      const double* Ks, const double* Tbg, double* b, double* c,
                       double* x, double* r, double* u_part, double* b_part);
 // after the last sweep's solve: the EOS density and pressure-equation
 // coefficients rho23, psi, c, D
@@ -172,7 +172,8 @@ struct CgVectors {
   T* q1;
   const T* c;
   const T* D;     // null: D is Dc in every cell (the energy sweeps' system)
-  const T* dinv;
+  const T* dinv;  // (with D null: unused, the iteration kernels form 1/diag from c;
+                  // such a system starts with cg_start_from, not cg_init)
   const T* b;
   T Dc = T(0);
   // FP32 inner solve of the refinement: its outer FP64 iterate, to which the

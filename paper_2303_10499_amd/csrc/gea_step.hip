@@ -467,8 +467,7 @@ __global__ __launch_bounds__(64 * TY) void k_step1_3(Geo G, Phys ph, int kc,
 // ||r||^2 (u_part) and ||b||^2 (b_part) of each workgroup.
 struct EnergySys {
   double* b;
-  double* c;
-  double* dinv;   // (2D; the 3D iteration kernel forms 1/diag from c)
+  double* c;      // (the iteration kernels form 1/diag from c: D is a constant)
   double* x;      // the solve's initial guess (and later solution); null: T_prev itself
   double* r;
   double* u_part;
@@ -587,10 +586,10 @@ __global__ __launch_bounds__(kBlock) void k_energy_rhs(
         ax += wz * (xc - zT.m1);
         diag += wz;
       }
+      // (1/diag is not stored: the iteration kernels form it from c)
       const double di = 1.0 / diag, rr = bP - ax;
       sy.b[P] = bP;
       sy.c[P] = cP;
-      sy.dinv[P] = di;
       if (sy.x) sy.x[P] = xc;  // (null: the solve runs in place on T_prev)
       sy.r[P] = rr;
       red[0] += rr * (rr * di);
@@ -825,7 +824,7 @@ __global__ __launch_bounds__(64 * TY) void k_energy_rhs3(
     }
     if (c.act) {
       const int P = qo + pl * k;
-      // (1/diag is not stored: the 3D iteration kernel forms it from c)
+      // (1/diag is not stored: the iteration kernel forms it from c)
       const double di = 1.0 / diag, rr = bP - ax;
       sy.b[P] = bP;
       sy.c[P] = cP;
@@ -1836,10 +1835,10 @@ void launch_step1(hipStream_t s, const Geo& G, const Phys& ph, const double* rho
 int launch_energy_rhs(hipStream_t s, const Geo& G, const Phys& ph, bool enth, bool ks,
                       const double* rho, const double* e0, const double* a_prev,
                       const double* T_prev, double* const* phi, const double* rho_star,
-                      const double* Ks, const double* Tbg, double* b, double* c, double* dinv,
+                      const double* Ks, const double* Tbg, double* b, double* c,
                       double* x, double* r, double* u_part, double* b_part) {
   const ZPlan zp = zplan(G), zp3 = G.ndim == 3 ? zplan3(G, kTyEnergy, kKcEnergy) : zp;
-  const EnergySys sy{b, c, dinv, x, r, u_part, b_part};
+  const EnergySys sy{b, c, x, r, u_part, b_part};
   // (the enthalpy form always stages T and K*)
   if (G.ndim == 2) {
     if (enth)

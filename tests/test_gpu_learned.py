@@ -278,11 +278,16 @@ def test_pairs_are_solver_corrections(learned):
     assert np.linalg.norm(b - Ax) <= 1e-6 * np.linalg.norm(b - Ax0) + 1e-12 * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("junk", ["zeros", "random"])
-def test_learned_solver_falls_back_and_still_converges(learned, junk):
+@pytest.mark.parametrize("junk,steps", [("zeros", 1), ("random", 1), ("zeros", 25), ("random", 25)])
+def test_learned_solver_falls_back_and_still_converges(learned, junk, steps):
+    """A network that cannot help (all-zero or random weights), as a one-step
+    initial guess or as the preconditioner of up to 25 flexible steps: every
+    solve reaches the tolerance (the stall / divergence stop and the
+    hand-over's restart keep a useless or harmful correction out)."""
     from paper_2303_10499_amd import gea
     cfg = configs.scaled("nonsmooth2d_2048", 128, 128)
-    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000, learned_always=1)
+    cfg["params"].update(tol=1e-8, inner_tol=1e-4, max_iter=100000, learned_always=1,
+                         learned_steps=steps)
     S = gea.Solver(cfg["mesh"], cfg["params"], solver="learned")
     S.init_bubble(**cfg["bubble"])
     npar = learned.param_count(2)

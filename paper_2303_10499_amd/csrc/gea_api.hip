@@ -410,7 +410,7 @@ size_t carve(Carver& cv, gea_ctx* x, const gea_mesh& m, bool learned, bool trans
   x->z32 = cv.take<float>(nc);
   x->pair_part = cv.take<double>(3 * 2048);
   x->pair_s = cv.take<double>(2);
-  x->fv.part_d = cv.take<double>(4 * 2048);  // (4 sums a workgroup at the hand-over)
+  x->fv.part_d = cv.take<double>(4 * (size_t)std::max(2048, zplan(make_geo(m)).blocks));  // (4 sums a workgroup at the hand-over)
   x->fv.part_s = cv.take<double>(2 * (size_t)std::max(2048, zplan(make_geo(m)).blocks));
   x->fv.part_u = cv.take<double>(2 * 2048);
   // the network (inference buffers) only for the learned form on a mesh whose

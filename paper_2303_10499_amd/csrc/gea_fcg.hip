@@ -292,34 +292,32 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(int n, int iter, float* _
 // from r0 - A (alpha z) by rounding of terms no larger than r0 itself, and
 // the last update's partials serve.)
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_fcg_handover(Geo G, const float* __restrict__ d,
+__global__ __launch_bounds__(kBlock) void k_fcg_handover(Geo G, Stencil<NDIM, float> K, int kc,
+                                                         const float* __restrict__ d,
                                                          const float* __restrict__ r0,
                                                          const float* __restrict__ c,
                                                          const float* __restrict__ D,
                                                          const float* __restrict__ dinv,
                                                          float* __restrict__ r, double* part) {
-  float kk[NDIM];
-  for (int k = 0; k < NDIM; ++k) kk[k] = (float)(G.S[k] / G.h[k]);
   double w[4] = {0.0, 0.0, 0.0, 0.0};
-  GEA_FOR_CELLS(P, G) {
-    int cc[NDIM];
-    cell_coords<NDIM>(G, P, cc);
-    const float dp = d[P], Dp = D[P];
-    float a = c[P] * dp;
-#pragma unroll
-    for (int k = 0; k < NDIM; ++k) {
-      const int st = G.st[k];
-      if (cc[k] + 1 < G.n[k]) a += 0.5f * (Dp + D[P + st]) * kk[k] * (dp - d[P + st]);
-      if (cc[k] > 0) a += 0.5f * (D[P - st] + Dp) * kk[k] * (dp - d[P - st]);
+  const Col col = col_of<NDIM>(G, kc);
+  if (col.act) {  // a column walking up through z (A d as the refinement residual forms A x)
+    ColumnA<NDIM, float> A{d, D};
+    A.nz = G.n[NDIM - 1];
+    A.pl = col.pl;
+    int P = col.base + col.pl * col.k0;
+    A.start(col, P);
+    for (int k = col.k0; k < col.k1; ++k, P += col.pl) {
+      const float r0p = r0[P], mp = dinv[P];
+      const float rn = r0p - A.at(G, K, col, P, k, c);
+      A.next();
+      r[P] = rn;
+      const double rd = (double)rn, r0d = (double)r0p;
+      w[0] += rd * (double)(rn * mp);
+      w[1] += rd * rd;
+      w[2] += r0d * (double)(r0p * mp);
+      w[3] += r0d * r0d;
     }
-    const float r0p = r0[P], mp = dinv[P];
-    const float rn = r0p - a;
-    r[P] = rn;
-    const double rd = (double)rn, r0d = (double)r0p;
-    w[0] += rd * (double)(rn * mp);
-    w[1] += rd * rd;
-    w[2] += r0d * (double)(r0p * mp);
-    w[3] += r0d * r0d;
   }
   store_part<4>(w, part);
 }
@@ -519,16 +517,20 @@ int fcg_iteration_after_z(hipStream_t s, const Geo& G, const FcgVectors& v, int 
 
 void fcg_handover(hipStream_t s, const Geo& G, const FcgVectors& v, const CgWork& w, int max_iter,
                   FcgScalars* sc) {
-  const int gu = grid_for(G.nc);
-  if (G.ndim == 2)
-    hipLaunchKernelGGL(k_fcg_handover<2>, dim3(gu), dim3(kBlock), 0, s, G, (const float*)v.d,
+  const ZPlan zp = zplan(G);
+  const int gu = zp.blocks, gc = grid_for(G.nc);
+  if (G.ndim == 2) {
+    const Stencil<2, float> K{{(float)(G.S[0] / G.h[0]), (float)(G.S[1] / G.h[1])}};
+    hipLaunchKernelGGL(k_fcg_handover<2>, dim3(gu), dim3(kBlock), 0, s, G, K, zp.kc, (const float*)v.d,
                        (const float*)v.r0, v.c, v.D, v.dinv, v.r, v.part_d);
-  else
-    hipLaunchKernelGGL(k_fcg_handover<3>, dim3(gu), dim3(kBlock), 0, s, G, (const float*)v.d,
+  } else {
+    const Stencil<3, float> K{{(float)(G.S[0] / G.h[0]), (float)(G.S[1] / G.h[1]), (float)(G.S[2] / G.h[2])}};
+    hipLaunchKernelGGL(k_fcg_handover<3>, dim3(gu), dim3(kBlock), 0, s, G, K, zp.kc, (const float*)v.d,
                        (const float*)v.r0, v.c, v.D, v.dinv, v.r, v.part_d);
+  }
   // (part_u is free once the last check has run)
   hipLaunchKernelGGL(k_fcg_pick, dim3(1), dim3(kBlock), 0, s, (const double*)v.part_d, gu, v.part_u, sc);
-  hipLaunchKernelGGL(k_fcg_restart, dim3(gu), dim3(kBlock), 0, s, G.nc, v.d, v.r, (const float*)v.r0,
+  hipLaunchKernelGGL(k_fcg_restart, dim3(gc), dim3(kBlock), 0, s, G.nc, v.d, v.r, (const float*)v.r0,
                      (const FcgScalars*)sc);
   cg_resume_scalars(s, v.part_u, 1, w, max_iter);
 }

@@ -248,4 +248,65 @@ __device__ __forceinline__ Stage3<HW, TY> stage3(const Geo& G, const Col& c) {
 // coordinate of the column along an x/y direction
 __device__ __forceinline__ int coord(const Col& c, int d) { return d == 0 ? c.i : c.j; }
 
+template <int NDIM, typename T>
+struct Stencil {
+  T k[NDIM];  // S_d / h_d in the working precision
+};
+
+// A x at the cells of a column walking up through z: x and D of the planes
+// below, at and above the current one stay in registers, x/y neighbours
+// come from the caches.  The terms are summed in the order x+, x-, y+, y-,
+// z+, z- (the order of the CG kernels' operator).
+template <int NDIM, typename T>
+struct ColumnA {
+  const T* x;
+  const T* D;
+  T xm, xc, xp, dm, dc, dp;
+  int nz, pl;
+  __device__ void start(const Col& c, int P) {
+    xm = c.k0 > 0 ? x[P - pl] : T(0);
+    dm = c.k0 > 0 ? D[P - pl] : T(0);
+    xc = x[P];
+    dc = D[P];
+  }
+  // A x at cell P of plane k (loads the plane above first).  Neighbour loads
+  // are clamped to the cell itself where the neighbour does not exist, and
+  // the wall tests are selects, so no branch separates the plane's loads.
+  __device__ T at(const Geo& G, const Stencil<NDIM, T>& K, const Col& c, int P, int k,
+                  const T* __restrict__ cc) {
+    constexpr int Z = NDIM - 1;
+    const bool up = k + 1 < nz;
+    const int Pu = up ? P + pl : P;
+    const T xu = x[Pu], du = D[Pu], cP = cc[P];
+    T x_hi[Z > 0 ? Z : 1], x_lo[Z > 0 ? Z : 1], d_hi[Z > 0 ? Z : 1], d_lo[Z > 0 ? Z : 1];
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int st = G.st[d], q = coord(c, d);
+      const int Ph = q + 1 < G.n[d] ? P + st : P, Pl = q > 0 ? P - st : P;
+      x_hi[d] = x[Ph];
+      d_hi[d] = D[Ph];
+      x_lo[d] = x[Pl];
+      d_lo[d] = D[Pl];
+    }
+    xp = up ? xu : T(0);
+    dp = up ? du : T(0);
+    T acc = cP * xc;
+#pragma unroll
+    for (int d = 0; d < Z; ++d) {
+      const int q = coord(c, d);
+      acc = q + 1 < G.n[d] ? acc + T(0.5) * (dc + d_hi[d]) * K.k[d] * (xc - x_hi[d]) : acc;
+      acc = q > 0 ? acc + T(0.5) * (d_lo[d] + dc) * K.k[d] * (xc - x_lo[d]) : acc;
+    }
+    if (up) acc += T(0.5) * (dc + dp) * K.k[Z] * (xc - xp);
+    if (k > 0) acc += T(0.5) * (dm + dc) * K.k[Z] * (xc - xm);
+    return acc;
+  }
+  __device__ void next() {
+    xm = xc;
+    dm = dc;
+    xc = xp;
+    dc = dp;
+  }
+};
+
 }  // namespace gea

@@ -90,9 +90,9 @@ typedef struct {
                                       per solve before Jacobi-PCG continues (>= 1; 1 = the learned
                                       initial guess with an optimal step length).  At most: the
                                       iteration stops (a fallback) once ||r|| falls less than 10 %
-                                      over 2 iterations or grows past twice its start, and a
-                                      correction leaving the true residual above its start is
-                                      dropped                                                        */
+                                      over 2 iterations or grows past twice its start, and
+                                      (with more than one step) a correction leaving the true
+                                      residual above its start is dropped                            */
   double inner_target;             /* refined forms: an inner solve aims at inner_target * tol ||b||
                                       for the outer residual (in (0, 1]; 0 selects 0.8)            */
   int32_t learned_always;          /* learned form: 0 = per corrector, run the network only while
